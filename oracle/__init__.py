@@ -1,0 +1,23 @@
+"""FP64 CPU oracle (TEST INFRASTRUCTURE ONLY).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library neither imports nor
+links it, and the two share no code.
+"""
+
+from .oracle import (  # noqa: F401
+    OracleTree,
+    build_library,
+    eigh3,
+    octant_init,
+    em_partition,
+    build_tree,
+    build_root,
+    build_level,
+    estep,
+    normal_equations,
+    solve_update,
+    register,
+    level_offset,
+    level_nodes,
+)
