@@ -1,0 +1,186 @@
+"""Throughput of GMM-Tree registration on one MI355X.
+
+One step = the whole hot path for one cloud pair: build the GMM tree of the
+source cloud (root statistics, per-level EM, partition) and register the
+target cloud against it (adaptive descent, moments, normal equations, solve),
+inputs already resident in HBM.  The default workload is the spinning-scanner
+pair (64 rings x 1875 azimuths, 4 levels).
+
+Prints one JSON line: pairs/s, ms/step, the dominant kernel's achieved rate
+against the MI355X roofline (from HIP events bracketing its launches inside
+the timed region), the E-step rate in Mpts/s, the registration error of the
+timed runs, and the FP64 CPU oracle timed on a bounded sample of the same
+workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+
+# Algorithmic work per unit (derivation in the design doc):
+#  construction EM, per point-iteration: 8 children x (score 19 + softmax 4 + moments 21) FLOP
+EM_FLOP_PER_POINT_ITER = 8 * 44
+EM_BYTES_PER_POINT_ITER = 12
+#  registration descent, per point: transform 18 + per visited level 8 x 19 + stop level 35 FLOP
+DESC_FLOP_FIXED = 18 + 35
+DESC_FLOP_PER_LEVEL = 8 * 19
+DESC_BYTES_PER_POINT = 12
+
+
+def _workload(name):
+    from paper_1807_02587_amd.presets import PRESETS
+    from synth import depth_pair, lidar_pair, small_pair
+    if name == "lidar":
+        p = lidar_pair(1000)
+        desc = "lidar 64 rings x 1875 azimuths, ground + 50 boxes + 30 cylinders, 1 m / <=2 deg motion"
+    elif name == "small":
+        p = small_pair(0)
+        desc = "planes+spheres unit cube, 10k points, <=30 deg / 0.1 motion"
+    elif name == "depth":
+        p = depth_pair(2000)
+        desc = "depth camera 640x480 in a furnished room, <=10 deg / 0.2 m motion"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return p, PRESETS[name], desc
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="lidar", choices=["lidar", "small", "depth"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
+              "described in DESIGN.md and not run here.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1807_02587_amd as hg
+    from synth import rotation_angle_deg
+
+    p, pr, desc = _workload(args.workload)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    src = torch.from_numpy(p.src).to(dev)
+    tgt = torch.from_numpy(p.tgt).to(dev)
+    n1, n2 = p.src.shape[1], p.tgt.shape[1]
+    ws_b, ws_r = hg.Workspace(dev), hg.Workspace(dev)
+    tree = None
+
+    def step():
+        nonlocal tree
+        tree = hg.hgmm_build(src, levels=pr["levels"], reg_eps=pr["reg_eps"], min_mass=pr["min_mass"], ws=ws_b,
+                             tree=tree)
+        return hg.hgmm_register(tree, tgt, lambda_c=pr["lambda_c"], ws=ws_r, raise_singular=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    hg.hgmm_profile_reset()
+    hg.hgmm_profile(True)
+    errs, iters = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = step()
+        errs.append(rotation_angle_deg(r["R"], p.R_true))
+        iters.append(r["iters"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hg.hgmm_profile(False)
+    prof = {k: hg.hgmm_profile_read(k) for k in hg.PROFILE_KINDS}
+    sec = t1 - t0
+
+    # mean number of levels a point visits at the final pose (for the descent FLOP count)
+    e = hg.hgmm_estep(tree, tgt, r["R"], r["t"], lambda_c=pr["lambda_c"])
+    off = np.array([hg.hgmm_level_offset(l) for l in range(pr["levels"] + 1)])
+    stop = e["stop_node"].cpu().numpy()
+    depth = float(np.mean(np.searchsorted(off, stop, side="right")))
+
+    # dominant kernel and its roofline
+    em_ms = prof["em_tile"]["ms"] + prof["em_fused"]["ms"]
+    em_units = prof["em_tile"]["units"] + prof["em_fused"]["units"]
+    ds = prof["descend"]
+    cand = {"em": em_ms, "descend": ds["ms"]}
+    dom = max(cand, key=cand.get)
+    if dom == "em":
+        flop = em_units * EM_FLOP_PER_POINT_ITER
+        byts = em_units * EM_BYTES_PER_POINT_ITER
+        ms = em_ms
+        launches = prof["em_tile"]["launches"] + prof["em_fused"]["launches"]
+        kname = "em_tile_kernel+em_fused_kernel (construction E/M-step)"
+    else:
+        flop = ds["units"] * (DESC_FLOP_FIXED + DESC_FLOP_PER_LEVEL * depth)
+        byts = ds["units"] * DESC_BYTES_PER_POINT
+        ms = ds["ms"]
+        launches = ds["launches"]
+        kname = "descend_kernel (registration E-step)"
+    achieved = flop / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None, "kernel": kname,
+                "launches": launches, "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
+                "achieved_hbm_GBs": round(byts / (ms * 1e-3) / 1e9, 1) if ms > 0 else 0.0}
+    estep_mpts = ds["units"] / (ds["ms"] * 1e-3) / 1e6 if ds["ms"] > 0 else 0.0
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t_c = 0.0
+        reps = 0
+        while t_c < args.cpu_seconds and reps < 8:
+            c0 = time.perf_counter()
+            ot, _ = oracle.build_tree(p.src, pr["levels"], eps=pr["reg_eps"], min_mass=pr["min_mass"])
+            oracle.register(ot, p.tgt, lambda_c=pr["lambda_c"])
+            t_c += time.perf_counter() - c0
+            reps += 1
+        cpu = {"value": round(reps / t_c, 4), "unit": "pairs/s", "cores": 1, "kind": "oracle",
+               "sample": f"{reps} full pair(s) of the same workload (build {n1} + register {n2} points), "
+                         f"single-threaded FP64, {t_c:.1f} s"}
+
+    out = {
+        "metric": "cloud pairs registered/s (build + register)",
+        "value": round(args.steps / sec, 3),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32 (E-step, moments) + fp64 (transform, eigen, solves)",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "points_src": n1, "points_tgt": n2,
+                   "levels": pr["levels"], "lambda_c": pr["lambda_c"], "reg_eps": pr["reg_eps"],
+                   "min_mass": pr["min_mass"], "build_iters": 30, "max_iters": 30, "init": "identity"},
+        "estep_mpts_s": round(estep_mpts, 1),
+        "rot_err_deg_median": round(float(np.median(errs)), 4),
+        "iters_mean": round(float(np.mean(iters)), 2),
+        "mean_levels_visited": round(depth, 3),
+        "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in prof.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,214 @@
+/*
+ * hgmm -- GMM-Tree point cloud registration on AMD Instinct MI355X (gfx950).
+ *
+ * The method is Eckart, Kim, Kautz, "Fast and Accurate Point Cloud Registration
+ * using Trees of Gaussian Mixtures" (2018).  Given a model cloud Z1 and a cloud
+ * Z2, find the rigid T = (R, t) that maximises the likelihood of T(Z2) under a
+ * mixture model of Z1 (Sec. 3, Eq. 1-2).  Two entry points carry the method:
+ *
+ *   hgmm_build     builds the tree of 8-component Gaussian mixtures of Z1
+ *                  (Sec. 3 end, Sec. 4.1: every component owns an 8-component
+ *                  child mixture; construction = per-parent EM, Eq. 2-3, run for
+ *                  all parents of a level at once);
+ *   hgmm_register  runs the registration EM on that tree: the adaptive
+ *                  max-likelihood descent with the complexity stop
+ *                  (Sec. 4.1, Algorithm 1), moment accumulation (Eq. 9) and the
+ *                  PCA-form Mahalanobis least squares (Sec. 4.2, Eq. 10-16).
+ *
+ * Every computation runs in HIP kernels on the device.  The library never
+ * falls back to the host.
+ *
+ * Conventions shared by every entry point
+ *   - Points are FP32 SoA in device memory: x[n], y[n], z[n] back to back
+ *     (one allocation of 3n floats).  The caller owns them; the library never
+ *     keeps a pointer past the call.
+ *   - A rigid transform maps a point p of Z2 to R p + t; R is row-major 3x3
+ *     (9 doubles), t is 3 doubles, both in host memory.
+ *   - Tree levels are numbered from 0; level l holds 8^(l+1) nodes and node k
+ *     of level l has children 8k..8k+7 at level l+1.  (The paper numbers
+ *     recursion levels from 1: its "level 2" with J = 64 is level index 1.)
+ *     Nodes are stored level-major; level l of a tree starts at
+ *     hgmm_level_offset(l).
+ *   - A covariance is packed as [xx, xy, xz, yy, yz, zz] and includes the
+ *     regularisation reg_eps * I.
+ *   - "stream" is a hipStream_t (NULL = the default stream).  All work is
+ *     enqueued on it.  hgmm_build synchronises it once per tree level (to plan
+ *     the next level's tiles); hgmm_register synchronises it once at the end
+ *     to return the pose.
+ *   - Workspaces are caller-owned device memory of at least the size the
+ *     matching *_workspace_bytes() call returns; their contents need not be
+ *     initialised.  One workspace must not be used by two calls at once.
+ *   - Every int-returning function returns HGMM_OK (0) or a negative
+ *     hgmm_status; hgmm_last_error() then describes the failure (thread-local).
+ *     No C++ exception crosses the boundary.
+ */
+#ifndef HGMM_H
+#define HGMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HGMM_MAX_LEVELS 6
+
+typedef enum {
+  HGMM_OK = 0,
+  HGMM_EINVAL = -1,     /* bad argument: null pointer, levels outside [1, 6], workspace too small */
+  HGMM_ETOOFEW = -2,    /* fewer than 8 model points, or an empty cloud to register */
+  HGMM_ENONFINITE = -3, /* a non-finite coordinate in the model cloud */
+  HGMM_ENOMEM = -4,     /* device or pinned-host allocation failed */
+  HGMM_EHIP = -5,       /* a HIP runtime call failed */
+  HGMM_ESINGULAR = -6   /* the 6x6 normal equations were not positive definite, even damped */
+} hgmm_status;
+
+/* Opaque handle to one or more device-resident trees (a forest; a single
+ * build makes a forest of one tree).  It owns its node arrays, per-point
+ * labels and a small pinned staging area; free it with hgmm_tree_destroy. */
+typedef struct hgmm_forest_s *hgmm_tree;
+
+/* Tree construction parameters.  The paper delegates construction to its
+ * reference [33]; these are the knobs of this library's reading of it:
+ * PCA-octant initialisation of each parent's 8 children, build_iters EM
+ * iterations per parent, hard partition of the points by their most likely
+ * child, covariance regularisation reg_eps * I, and children whose soft mass
+ * falls below min_mass dropped for the rest of the build. */
+typedef struct {
+  int32_t levels;      /* 1..6 */
+  int32_t build_iters; /* EM iterations per level, default 30 */
+  double reg_eps;      /* default 1e-6 (squared length units) */
+  double min_mass;     /* default 1.0 */
+} hgmm_build_params;
+
+/* Registration parameters (Sec. 4.1-4.2).  lambda_c is the complexity
+ * threshold of Algorithm 1 (the paper uses 0.01; 0 gives the "GMM-Tree Ln"
+ * variant of Sec. 5).  The loop stops after max_iters E/M iterations or once
+ * the angle of the rotation increment is below tol_rot (radians) and the norm
+ * of the translation increment is below tol_trans_rel times the model's
+ * bounding-box diagonal. */
+typedef struct {
+  int32_t max_iters;   /* default 30 */
+  int32_t pad_;
+  double lambda_c;     /* default 0.01 */
+  double tol_rot;      /* default 1e-6 */
+  double tol_trans_rel;/* default 1e-6 */
+} hgmm_reg_params;
+
+/* Host copy of one tree in FP64.  The caller allocates every array with
+ * hgmm_tree_nodes(levels) entries (times the per-node width) before calling
+ * hgmm_tree_export, or fills them before calling hgmm_tree_import. */
+typedef struct {
+  int32_t levels;
+  int32_t pad_;
+  int64_t n_points;     /* model cloud size */
+  double origin[3];     /* model mean: centre of the rotation increments */
+  double extent;        /* model bounding-box diagonal */
+  int32_t *live;        /* 1 if the node exists */
+  int32_t *has_children;/* 1 if at least one child is live */
+  int64_t *count;       /* size of the node's hard partition of Z1 */
+  double *pi;           /* weight inside its sibling group */
+  double *pig;          /* product of weights from the root */
+  double *mu;           /* 3 per node */
+  double *cov;          /* 6 per node */
+  double *lam;          /* 3 per node, lam1 >= lam2 >= lam3 */
+  double *evec;         /* 9 per node, row a is the eigenvector of lam_a (largest-|.| entry positive) */
+  double *kappa;        /* lam3 / (lam1 + lam2 + lam3), the complexity of Sec. 4.1 */
+} hgmm_tree_host;
+
+/* Defaults: levels 2, build_iters 30, reg_eps 1e-6, min_mass 1; max_iters 30,
+ * lambda_c 0.01, tol_rot 1e-6, tol_trans_rel 1e-6.  Either pointer may be NULL. */
+int hgmm_params_default(hgmm_build_params *bp, hgmm_reg_params *rp);
+
+/* Nodes of a tree with `levels` levels: (8^(levels+1) - 8) / 7.  Returns -1 for
+ * levels outside [1, 6]. */
+int64_t hgmm_tree_nodes(int levels);
+/* First node of level `level` inside a tree: (8^(level+1) - 8) / 7. */
+int64_t hgmm_level_offset(int level);
+
+/* Workspace sizes in bytes for a cloud of n points and a tree of `levels`. */
+size_t hgmm_build_workspace_bytes(int64_t n, int levels);
+size_t hgmm_register_workspace_bytes(int64_t n, int levels);
+
+/* Builds the tree of d_xyz (n points, SoA FP32, device).  If *tree is NULL a
+ * new handle is allocated; otherwise the handle is reused (and grown if it is
+ * too small) so that repeated builds do not allocate.  Errors: HGMM_EINVAL,
+ * HGMM_ETOOFEW (n < 8), HGMM_ENONFINITE, HGMM_ENOMEM, HGMM_EHIP. */
+int hgmm_build(const float *d_xyz, int64_t n, const hgmm_build_params *p, void *d_ws, size_t ws_bytes,
+               void *stream, hgmm_tree *tree);
+
+/* Registers d_xyz (n points, SoA FP32, device) onto tree (tree index 0).
+ * R0/t0 (host, nullable = identity / zero) is the initial transform.  On
+ * return R, t hold the estimate, *iters the number of E/M iterations run
+ * (== max_iters when the tolerance was not reached, which is not an error),
+ * *loglik (nullable) the mean log-likelihood of the points under the nodes
+ * they stopped at, from the last E-step.  HGMM_ESINGULAR leaves R, t at the
+ * last good value.  Synchronises `stream` once. */
+int hgmm_register(hgmm_tree tree, const float *d_xyz, int64_t n, const hgmm_reg_params *p, const double *R0,
+                  const double *t0, void *d_ws, size_t ws_bytes, void *stream, double R[9], double t[3],
+                  int *iters, double *loglik);
+
+/* One registration E-step at a fixed transform (Algorithm 1): for each point
+ * the stop node (global node id inside the tree, device int32, nullable) and
+ * its weight gamma (device float, nullable); per node the moments
+ * d_bins[node * 6 + {0..5}] = {M0 = sum gamma, D = sum gamma (T(p) - mu_node)
+ * (3 values), number of points, sum of squared Mahalanobis distances}
+ * (device double, nullable), and the mean log-likelihood (host, nullable).
+ * Synchronises `stream` when loglik is requested. */
+int hgmm_estep(hgmm_tree tree, const float *d_xyz, int64_t n, const double R[9], const double t[3],
+               double lambda_c, void *d_ws, size_t ws_bytes, void *stream, int32_t *d_stop_node,
+               float *d_gamma, double *d_bins, double *loglik);
+
+/* The PCA-form normal equations (Eq. 11-16) of one M-step from per-node
+ * moments in the hgmm_estep layout (device): H (6x6 row-major, host) and g
+ * (6, host) with H x = g for the increment x = (omega, tau) of
+ * T(p) -> p + omega x (p - origin) + tau.  Synchronises `stream`. */
+int hgmm_normal_equations(hgmm_tree tree, const double *d_bins, int64_t n, void *d_ws, size_t ws_bytes,
+                          void *stream, double H[36], double g[6]);
+
+/* FP64 host copy of tree `index` of the forest (all arrays caller-allocated). */
+int hgmm_tree_export(hgmm_tree tree, int index, hgmm_tree_host *out);
+/* Per-point node labels of tree `index`: d_labels[l * n_points + i] is the
+ * index inside level l of the node that point i of the model cloud belongs to
+ * (-1 if its path ended above level l).  Device int32, caller-allocated. */
+int hgmm_tree_labels(hgmm_tree tree, int index, int32_t *d_labels, void *stream);
+/* Builds a single-tree handle from a host tree (every field is used as
+ * given, origin and extent included).  Node arrays are copied; the handle has
+ * no per-point labels. */
+int hgmm_tree_import(const hgmm_tree_host *in, void *stream, hgmm_tree *out);
+/* levels, total nodes, origin and extent of tree `index`. */
+int hgmm_tree_info(hgmm_tree tree, int index, int *levels, int64_t *n_nodes, double origin[3], double *extent);
+void hgmm_tree_destroy(hgmm_tree tree);
+
+/* Launch-shape knobs of the construction and registration kernels (process
+ * wide; a negative value keeps the current setting).  fused_max: parents with
+ * at most this many points run all their EM iterations inside one wavefront;
+ * min_tile / max_tile / target_tiles: points per construction tile are
+ * level_points / target_tiles rounded up to a multiple of 64 and clamped to
+ * [min_tile, max_tile]; reg_tile: points per registration block (multiple of
+ * 256).  Defaults 512, 256, 1024, 4096, 256.  Not thread-safe against
+ * concurrent builds. */
+int hgmm_set_tuning(int fused_max, int min_tile, int target_tiles, int max_tile, int reg_tile);
+
+/* Benchmark instrumentation.  hgmm_profile(1) brackets every kernel launch
+ * of hgmm_build / hgmm_register with HIP events on the caller's stream;
+ * hgmm_profile_read returns, per kernel kind, the summed event time (ms), the
+ * number of timed launches and the work units they processed (points, or
+ * point-iterations for the fused construction kernel, or nodes for the
+ * normal equations).  Registration launches after convergence (which exit at
+ * once) are not counted.  Kinds: 0 construction EM tile iteration,
+ * 1 fused construction EM, 2 partition, 3 stable split, 4 registration
+ * descent, 5 normal equations + solve, 6 root statistics.  Process-wide, not
+ * thread-safe. */
+int hgmm_profile(int enable);
+void hgmm_profile_reset(void);
+int hgmm_profile_read(int kind, double *total_ms, int64_t *launches, double *units);
+
+/* Thread-local description of the last failure on this thread. */
+const char *hgmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,24 @@
+"""GMM-Tree point cloud registration on MI355X (gfx950).
+
+Thin Python binding over the C ABI of ``libhgmm.so`` (see include/hgmm.h).
+PyTorch provides device memory and streams; every step of construction and
+registration runs in the library's HIP kernels.
+"""
+
+from .api import (  # noqa: F401
+    Tree,
+    Workspace,
+    hgmm_build,
+    hgmm_register,
+    hgmm_estep,
+    hgmm_normal_equations,
+    hgmm_tree_import,
+    hgmm_tree_nodes,
+    hgmm_level_offset,
+    hgmm_set_tuning,
+    library_path,
+    hgmm_profile,
+    hgmm_profile_reset,
+    hgmm_profile_read,
+    PROFILE_KINDS,
+)

@@ -1,0 +1,669 @@
+// GMM-Tree construction kernels (gfx950).
+//
+// A level of the tree is fitted for every parent at once.  Points are kept
+// sorted by their parent, so each parent owns a contiguous range of the point
+// arrays; that range is cut into tiles of one wavefront each.  Per EM
+// iteration a tile evaluates the 8 child scores of each of its points
+// (Sec. 3, Eq. 2-3), turns them into responsibilities and accumulates the
+// responsibility-weighted zeroth, first and second moments of every child
+// about the child's current mean (80 FP32 sums per lane).  The sums are
+// reduced across the wave with DPP, written as FP64 tile partials, and the
+// last tile of a parent to finish combines them in a fixed order and runs the
+// FP64 M-step for the 8 children.  Parents with few points run all their EM
+// iterations inside one wave instead (em_fused_kernel).
+#include "hgmm_dev.h"
+#include "hgmm_host.h"
+
+#include <algorithm>
+
+namespace hgmm {
+
+// ---------------------------------------------------------------------------
+// small utilities
+// ---------------------------------------------------------------------------
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+void launch_fill_u32(void* p, uint32_t v, int64_t n_words, hipStream_t s) {
+  if (n_words <= 0) return;
+  int64_t blocks = (n_words + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, v, n_words);
+}
+
+__device__ __forceinline__ unsigned ticket_add(unsigned* c) {
+  return __hip_atomic_fetch_add(c, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void copy_nodef(NodeF& dst, const NodeF& src) {
+  const float4* s = reinterpret_cast<const float4*>(&src);
+  float4* d = reinterpret_cast<float4*>(&dst);
+  d[0] = s[0]; d[1] = s[1]; d[2] = s[2]; d[3] = s[3];
+}
+
+// ---------------------------------------------------------------------------
+// root statistics (the tile list of level 0 has one job per tree root)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(64) void root_mean_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
+                                                       const float* __restrict__ zs, const Tile* __restrict__ tiles,
+                                                       const Job* __restrict__ jobs, TreeDev* trees,
+                                                       double* partials, size_t pstride, unsigned* counters) {
+  const Tile tl = tiles[blockIdx.x];
+  const int lane = threadIdx.x;
+  double s0 = 0, s1 = 0, s2 = 0;
+  float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY, hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
+  int bad = 0;
+  for (int i = tl.start + lane; i < tl.end; i += 64) {
+    float x = xs[i], y = ys[i], z = zs[i];
+    bad |= !(isfinite(x) && isfinite(y) && isfinite(z));
+    s0 += x; s1 += y; s2 += z;
+    lo0 = fminf(lo0, x); lo1 = fminf(lo1, y); lo2 = fminf(lo2, z);
+    hi0 = fmaxf(hi0, x); hi1 = fmaxf(hi1, y); hi2 = fmaxf(hi2, z);
+  }
+  s0 = wave_sum_d(s0); s1 = wave_sum_d(s1); s2 = wave_sum_d(s2);
+  for (int m = 32; m >= 1; m >>= 1) {
+    lo0 = fminf(lo0, __shfl_xor(lo0, m, 64)); lo1 = fminf(lo1, __shfl_xor(lo1, m, 64));
+    lo2 = fminf(lo2, __shfl_xor(lo2, m, 64)); hi0 = fmaxf(hi0, __shfl_xor(hi0, m, 64));
+    hi1 = fmaxf(hi1, __shfl_xor(hi1, m, 64)); hi2 = fmaxf(hi2, __shfl_xor(hi2, m, 64));
+  }
+  bad = __any(bad);
+  if (lane == 0) {
+    const double vals[10] = {s0, s1, s2, (double)lo0, (double)lo1, (double)lo2, (double)hi0, (double)hi1,
+                             (double)hi2, (double)bad};
+    for (int v = 0; v < 10; ++v) partials[(size_t)v * pstride + blockIdx.x] = vals[v];
+  }
+  __threadfence();
+  __shared__ unsigned tk;
+  const Job jb = jobs[tl.job];
+  if (lane == 0) tk = ticket_add(&counters[tl.job]);
+  __syncthreads();
+  if (tk != (unsigned)jb.ntiles - 1) return;
+  __threadfence();
+  // the last tile of the tree folds all tile partials (lanes stride over tiles)
+  const double a0 = wave_sum_range(partials + 0 * pstride + jb.tile_first, jb.ntiles, lane);
+  const double a1 = wave_sum_range(partials + 1 * pstride + jb.tile_first, jb.ntiles, lane);
+  const double a2 = wave_sum_range(partials + 2 * pstride + jb.tile_first, jb.ntiles, lane);
+  const double b = wave_sum_range(partials + 9 * pstride + jb.tile_first, jb.ntiles, lane);
+  double l0 = INFINITY, l1 = INFINITY, l2 = INFINITY, h0 = -INFINITY, h1 = -INFINITY, h2 = -INFINITY;
+  for (int t = lane; t < jb.ntiles; t += 64) {
+    const size_t c = (size_t)jb.tile_first + t;
+    l0 = fmin(l0, partials[3 * pstride + c]); l1 = fmin(l1, partials[4 * pstride + c]);
+    l2 = fmin(l2, partials[5 * pstride + c]); h0 = fmax(h0, partials[6 * pstride + c]);
+    h1 = fmax(h1, partials[7 * pstride + c]); h2 = fmax(h2, partials[8 * pstride + c]);
+  }
+  for (int m = 32; m >= 1; m >>= 1) {
+    l0 = fmin(l0, __shfl_xor(l0, m, 64)); l1 = fmin(l1, __shfl_xor(l1, m, 64));
+    l2 = fmin(l2, __shfl_xor(l2, m, 64)); h0 = fmax(h0, __shfl_xor(h0, m, 64));
+    h1 = fmax(h1, __shfl_xor(h1, m, 64)); h2 = fmax(h2, __shfl_xor(h2, m, 64));
+  }
+  if (lane == 0) {
+    TreeDev& T = trees[jb.tree];
+    double n = (double)jb.count;
+    T.origin[0] = a0 / n; T.origin[1] = a1 / n; T.origin[2] = a2 / n;
+    T.extent = sqrt((h0 - l0) * (h0 - l0) + (h1 - l1) * (h1 - l1) + (h2 - l2) * (h2 - l2));
+    if (b > 0) T.status = -3;
+    counters[tl.job] = 0;
+  }
+}
+
+__global__ __launch_bounds__(64) void root_cov_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
+                                                      const float* __restrict__ zs, const Tile* __restrict__ tiles,
+                                                      const Job* __restrict__ jobs, TreeDev* trees, double* partials,
+                                                      size_t pstride, unsigned* counters, double eps) {
+  const Tile tl = tiles[blockIdx.x];
+  const Job jb = jobs[tl.job];
+  const int lane = threadIdx.x;
+  const double o0 = trees[jb.tree].origin[0], o1 = trees[jb.tree].origin[1], o2 = trees[jb.tree].origin[2];
+  double c[6] = {0, 0, 0, 0, 0, 0};
+  for (int i = tl.start + lane; i < tl.end; i += 64) {
+    double d0 = (double)xs[i] - o0, d1 = (double)ys[i] - o1, d2 = (double)zs[i] - o2;
+    c[0] += d0 * d0; c[1] += d0 * d1; c[2] += d0 * d2; c[3] += d1 * d1; c[4] += d1 * d2; c[5] += d2 * d2;
+  }
+  for (int k = 0; k < 6; ++k) c[k] = wave_sum_d(c[k]);
+  if (lane < 6) {
+    double v = c[0];
+    for (int k = 1; k < 6; ++k) v = (lane == k) ? c[k] : v;
+    partials[(size_t)lane * pstride + blockIdx.x] = v;
+  }
+  __threadfence();
+  __shared__ unsigned tk;
+  if (lane == 0) tk = ticket_add(&counters[tl.job]);
+  __syncthreads();
+  if (tk != (unsigned)jb.ntiles - 1) return;
+  __threadfence();
+  double a[6];
+  for (int k = 0; k < 6; ++k) a[k] = wave_sum_range(partials + k * pstride + jb.tile_first, jb.ntiles, lane);
+  if (lane == 0) {
+    TreeDev& T = trees[jb.tree];
+    double n = (double)jb.count;
+    for (int k = 0; k < 6; ++k) T.root_cov[k] = a[k] / n;
+    T.root_cov[0] += eps; T.root_cov[3] += eps; T.root_cov[5] += eps;
+    eig_sym3(T.root_cov, T.root_lam, T.root_evec);
+    counters[tl.job] = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// PCA-octant initialisation of the children of every job's parent
+// ---------------------------------------------------------------------------
+
+__global__ void init_children_kernel(const Job* __restrict__ jobs, int njobs, const TreeDev* __restrict__ trees,
+                                     NodeD* nodes, NodeF* tab, double eps) {
+  int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = gid >> 3, k = gid & 7;
+  if (j >= njobs) return;
+  const Job jb = jobs[j];
+  double pmu[3], plam[3], pev[9];
+  if (jb.parent < 0) {
+    const TreeDev& T = trees[jb.tree];
+    for (int i = 0; i < 3; ++i) { pmu[i] = T.origin[i]; plam[i] = T.root_lam[i]; }
+    for (int i = 0; i < 9; ++i) pev[i] = T.root_evec[i];
+  } else {
+    const NodeD& P = nodes[jb.parent];
+    for (int i = 0; i < 3; ++i) { pmu[i] = P.mu[i]; plam[i] = P.lam[i]; }
+    for (int i = 0; i < 9; ++i) pev[i] = P.evec[i];
+  }
+  // child k covers the eigen-octant with sign + on axis a when bit a of k is 0;
+  // mean and covariance of a Gaussian restricted to it (half-normal moments)
+  const double hn_mean = 0.79788456080286535588;   // sqrt(2/pi)
+  const double hn_var = 0.36338022763241865692;    // 1 - 2/pi
+  double mu[3] = {pmu[0], pmu[1], pmu[2]};
+  double cov[6] = {eps, 0, 0, eps, 0, eps};
+  for (int a = 0; a < 3; ++a) {
+    double lr = fmax(plam[a] - eps, 0.0);
+    double sg = ((k >> a) & 1) ? -1.0 : 1.0;
+    double off = sg * hn_mean * sqrt(lr);
+    const double* e = pev + 3 * a;
+    mu[0] += off * e[0]; mu[1] += off * e[1]; mu[2] += off * e[2];
+    double v = hn_var * lr;
+    cov[0] += v * e[0] * e[0]; cov[1] += v * e[0] * e[1]; cov[2] += v * e[0] * e[2];
+    cov[3] += v * e[1] * e[1]; cov[4] += v * e[1] * e[2]; cov[5] += v * e[2] * e[2];
+  }
+  const int g = jb.child_base + k;
+  NodeD nd;
+  NodeF nf;
+  NodeD& out = nodes[g];
+  if (make_node(mu, cov, 0.125, nd, nf)) {
+    for (int i = 0; i < 3; ++i) out.mu[i] = nd.mu[i];
+    for (int i = 0; i < 6; ++i) { out.cov[i] = nd.cov[i]; out.winv[i] = nd.winv[i]; }
+    out.pi = nd.pi; out.c = nd.c; out.logdet = nd.logdet; out.live = 1;
+    copy_nodef(tab[g], nf);
+  } else {
+    out.live = 0; out.pi = 0.0;
+    tab[g].flags = 0u;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// EM: responsibilities and moments of one point against the 8 children
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void em_point(const NodeF* ch, uint32_t live, double p0, double p1, double p2,
+                                         float (&a)[8][10]) {
+  float s[8];
+  float smax = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (live & (1u << k)) {
+      float q, m;
+      s[k] = score32(ch[k], p0, p1, p2, q, m);
+      smax = fmaxf(smax, s[k]);
+    } else {
+      s[k] = -INFINITY;
+    }
+  }
+  float e[8], sum = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    e[k] = (live & (1u << k)) ? __builtin_amdgcn_exp2f(s[k] - smax) : 0.f;
+    sum += e[k];
+  }
+  const float inv = 1.0f / sum;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (live & (1u << k)) {
+      const float r = e[k] * inv;
+      const float d0 = (float)(p0 - ch[k].mu[0]);
+      const float d1 = (float)(p1 - ch[k].mu[1]);
+      const float d2 = (float)(p2 - ch[k].mu[2]);
+      const float r0 = r * d0, r1 = r * d1, r2 = r * d2;
+      a[k][0] += r;
+      a[k][1] += r0; a[k][2] += r1; a[k][3] += r2;
+      a[k][4] = fmaf(r0, d0, a[k][4]);
+      a[k][5] = fmaf(r0, d1, a[k][5]);
+      a[k][6] = fmaf(r0, d2, a[k][6]);
+      a[k][7] = fmaf(r1, d1, a[k][7]);
+      a[k][8] = fmaf(r1, d2, a[k][8]);
+      a[k][9] = fmaf(r2, d2, a[k][9]);
+    }
+  }
+}
+
+template <typename FP>
+__device__ __forceinline__ void em_range(FP xs, FP ys, FP zs, int start, int end, int lane,
+                                         const NodeF* ch, uint32_t live, float (&a)[8][10]) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int v = 0; v < 10; ++v) a[k][v] = 0.f;
+  for (int i = start + lane; i < end; i += 64) em_point(ch, live, (double)xs[i], (double)ys[i], (double)zs[i], a);
+}
+
+// Sum the 80 per-lane accumulators over the wave; out[v] (v < 80) is valid in
+// every lane as a wave-uniform value written to the LDS array red (80 floats).
+__device__ __forceinline__ void wave_reduce80(float (&a)[8][10], float* red, int lane) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int v = 0; v < 10; ++v) {
+      float t = wave_sum(a[k][v]);
+      if (lane == 0) red[k * 10 + v] = t;
+    }
+}
+
+// FP64 M-step of the 8 children of one parent from the 80 combined sums
+// (moments about the means the E-step used).  Runs on one full wave; lanes 0..7
+// own one child each.  Updates the LDS copy of the children, the FP32 table
+// and the FP64 node records.
+__device__ __forceinline__ void mstep_children(const double* tot, NodeF* ch, NodeF* tab, NodeD* nodes,
+                                               int child_base, double eps, double min_mass, int lane) {
+  bool live = false;
+  double N = 0.0;
+  if (lane < 8) {
+    live = (ch[lane].flags & F_LIVE) != 0;
+    N = tot[lane * 10];
+    if (live && !(N >= min_mass)) live = false;
+  }
+  double total = live ? N : 0.0;
+  total += __shfl_xor(total, 1, 64);
+  total += __shfl_xor(total, 2, 64);
+  total += __shfl_xor(total, 4, 64);
+  if (lane < 8) {
+    const int g = child_base + lane;
+    NodeD nd;
+    NodeF nf;
+    if (live) {
+      const double* A = tot + lane * 10;
+      const double inv = 1.0 / N;
+      const double dl0 = A[1] * inv, dl1 = A[2] * inv, dl2 = A[3] * inv;
+      double mu[3] = {ch[lane].mu[0] + dl0, ch[lane].mu[1] + dl1, ch[lane].mu[2] + dl2};
+      double cov[6] = {A[4] * inv - dl0 * dl0 + eps, A[5] * inv - dl0 * dl1, A[6] * inv - dl0 * dl2,
+                       A[7] * inv - dl1 * dl1 + eps, A[8] * inv - dl1 * dl2, A[9] * inv - dl2 * dl2 + eps};
+      live = make_node(mu, cov, N / total, nd, nf);
+    }
+    NodeD& out = nodes[g];
+    if (live) {
+      for (int i = 0; i < 3; ++i) out.mu[i] = nd.mu[i];
+      for (int i = 0; i < 6; ++i) { out.cov[i] = nd.cov[i]; out.winv[i] = nd.winv[i]; }
+      out.pi = nd.pi; out.c = nd.c; out.logdet = nd.logdet; out.live = 1;
+      copy_nodef(tab[g], nf);
+      copy_nodef(ch[lane], nf);
+    } else {
+      out.live = 0; out.pi = 0.0;
+      tab[g].flags = 0u;
+      ch[lane].flags = 0u;
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t live_mask(const NodeF* ch) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) m |= (ch[k].flags & F_LIVE) ? (1u << k) : 0u;
+  return m;
+}
+
+// One EM iteration for the tiles of the large jobs; the last tile of each job
+// performs the M-step.
+__global__ __launch_bounds__(64) void em_tile_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
+                                                     const float* __restrict__ zs, const Tile* __restrict__ tiles,
+                                                     const int* __restrict__ tile_ids, const Job* __restrict__ jobs,
+                                                     NodeF* tab, NodeD* nodes, double* partials, size_t pstride,
+                                                     unsigned* counters, double eps, double min_mass) {
+  const int tid = tile_ids[blockIdx.x];
+  const Tile tl = tiles[tid];
+  const Job jb = jobs[tl.job];
+  const int lane = threadIdx.x;
+  __shared__ NodeF ch[8];
+  __shared__ float red[80];
+  __shared__ double tot[80];
+  __shared__ unsigned tk;
+  if (lane < 8) copy_nodef(ch[lane], tab[jb.child_base + lane]);
+  __syncthreads();
+  const uint32_t live = live_mask(ch);
+  float a[8][10];
+  em_range(xs, ys, zs, tl.start, tl.end, lane, ch, live, a);
+  wave_reduce80(a, red, lane);
+  __syncthreads();
+  // tile partials are stored value-major: partials[v * pstride + tile]
+  partials[(size_t)lane * pstride + tid] = red[lane];
+  if (lane < 16) partials[(size_t)(64 + lane) * pstride + tid] = red[64 + lane];
+  __threadfence();
+  if (lane == 0) tk = ticket_add(&counters[tl.job]);
+  __syncthreads();
+  if (tk != (unsigned)jb.ntiles - 1) return;
+  __threadfence();
+  // last tile of the job: fixed-order FP64 combination of the tile partials,
+  // the lanes striding over the job's tiles
+  if (jb.ntiles <= 64) {
+    for (int v = 0; v < 80; ++v) {
+      const double x = lane < jb.ntiles ? partials[(size_t)v * pstride + jb.tile_first + lane] : 0.0;
+      const double t = wave_sum_dd(x);
+      if (lane == 0) tot[v] = t;
+    }
+  } else {
+    for (int v = 0; v < 80; ++v) {
+      const double t = wave_sum_range(partials + (size_t)v * pstride + jb.tile_first, jb.ntiles, lane);
+      if (lane == 0) tot[v] = t;
+    }
+  }
+  __syncthreads();
+  mstep_children(tot, ch, tab, nodes, jb.child_base, eps, min_mass, lane);
+  if (lane == 0) counters[tl.job] = 0;
+}
+
+// All EM iterations of one small job inside one wave; the job's points are
+// staged once in LDS (cap points, dynamic shared memory) when they fit.
+__global__ __launch_bounds__(64) void em_fused_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
+                                                      const float* __restrict__ zs, const int* __restrict__ job_ids,
+                                                      const Job* __restrict__ jobs, NodeF* tab, NodeD* nodes,
+                                                      int iters, double eps, double min_mass, int cap) {
+  const Job jb = jobs[job_ids[blockIdx.x]];
+  const int lane = threadIdx.x;
+  extern __shared__ float spts[];
+  __shared__ NodeF ch[8];
+  __shared__ float red[80];
+  __shared__ double tot[80];
+  if (lane < 8) copy_nodef(ch[lane], tab[jb.child_base + lane]);
+  const bool staged = jb.count <= cap;
+  if (staged)
+    for (int i = lane; i < jb.count; i += 64) {
+      spts[i] = xs[jb.start + i];
+      spts[cap + i] = ys[jb.start + i];
+      spts[2 * cap + i] = zs[jb.start + i];
+    }
+  __syncthreads();
+  for (int it = 0; it < iters; ++it) {
+    const uint32_t live = live_mask(ch);
+    if (live == 0u) break;
+    float a[8][10];
+    if (staged) em_range(spts, spts + cap, spts + 2 * cap, 0, jb.count, lane, ch, live, a);
+    else em_range(xs, ys, zs, jb.start, jb.start + jb.count, lane, ch, live, a);
+    wave_reduce80(a, red, lane);
+    __syncthreads();
+    tot[lane] = (double)red[lane];
+    if (lane < 16) tot[64 + lane] = (double)red[64 + lane];
+    __syncthreads();
+    mstep_children(tot, ch, tab, nodes, jb.child_base, eps, min_mass, lane);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// hard partition: most likely live child of every point, with an FP64 re-check
+// whenever the FP32 top-2 gap is inside the rounding bound
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(64) void partition_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
+                                                       const float* __restrict__ zs, const Tile* __restrict__ tiles,
+                                                       const Job* __restrict__ jobs, const NodeF* __restrict__ tab,
+                                                       const NodeD* __restrict__ nodes, uint8_t* child_out,
+                                                       int* tile_counts) {
+  const Tile tl = tiles[blockIdx.x];
+  const Job jb = jobs[tl.job];
+  const int lane = threadIdx.x;
+  __shared__ NodeF ch[8];
+  if (lane < 8) copy_nodef(ch[lane], tab[jb.child_base + lane]);
+  __syncthreads();
+  const uint32_t live = live_mask(ch);
+  int cnt[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int base = tl.start; base < tl.end; base += 64) {
+    const int i = base + lane;
+    const bool valid = i < tl.end;
+    int bucket = 8;
+    if (valid && live) {
+      const double p0 = xs[i], p1 = ys[i], p2 = zs[i];
+      float s[8], q[8], m[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (live & (1u << k)) s[k] = score32(ch[k], p0, p1, p2, q[k], m[k]);
+        else { s[k] = -INFINITY; q[k] = 0.f; m[k] = 0.f; }
+      }
+      int k1 = -1;
+      float s1 = -INFINITY;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if ((live & (1u << k)) && (k1 < 0 || s[k] > s1)) { s1 = s[k]; k1 = k; }
+      int k2 = -1;
+      float s2 = -INFINITY;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if ((live & (1u << k)) && k != k1 && (k2 < 0 || s[k] > s2)) { s2 = s[k]; k2 = k; }
+      bucket = k1;
+      if (k2 >= 0) {
+        float e1 = 0.f, e2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (k == k1) e1 = score_err(ch[k], q[k], m[k]);
+          if (k == k2) e2 = score_err(ch[k], q[k], m[k]);
+        }
+        if (s1 - s2 <= 2.f * (e1 + e2)) {
+          double best = -INFINITY;
+          int kb = -1;
+          for (int k = 0; k < 8; ++k) {
+            if (!(live & (1u << k))) continue;
+            double v = score64(nodes[jb.child_base + k], p0, p1, p2);
+            if (kb < 0 || v > best) { best = v; kb = k; }
+          }
+          bucket = kb;
+        }
+      }
+    }
+    if (valid) child_out[i] = (uint8_t)bucket;
+#pragma unroll
+    for (int b = 0; b < 9; ++b) cnt[b] += __popcll(__ballot(valid && bucket == b));
+  }
+  if (lane < 9) {
+    int v = cnt[0];
+#pragma unroll
+    for (int b = 1; b < 9; ++b) v = (lane == b) ? cnt[b] : v;
+    tile_counts[(size_t)blockIdx.x * 9 + lane] = v;
+  }
+}
+
+// Per job: exclusive prefix of the bucket counts over its tiles, the start and
+// size of every child's range, and the child partition sizes.
+__global__ __launch_bounds__(64) void prefix_kernel(const Job* __restrict__ jobs, const int* __restrict__ tile_counts,
+                                                    int* tile_base, NodeD* nodes, int2* lvl_info) {
+  const Job jb = jobs[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int chunk = (jb.ntiles + 63) / 64;
+  const int t0 = jb.tile_first + lane * chunk;
+  const int t1 = min(jb.tile_first + jb.ntiles, t0 + chunk);
+  int own[9], excl[9], tot[9];
+#pragma unroll
+  for (int b = 0; b < 9; ++b) own[b] = 0;
+  for (int t = t0; t < t1; ++t)
+#pragma unroll
+    for (int b = 0; b < 9; ++b) own[b] += tile_counts[(size_t)t * 9 + b];
+#pragma unroll
+  for (int b = 0; b < 9; ++b) {
+    int v = own[b];
+    for (int d = 1; d < 64; d <<= 1) {
+      int u = __shfl_up(v, d, 64);
+      if (lane >= d) v += u;
+    }
+    excl[b] = v - own[b];
+    tot[b] = __shfl(v, 63, 64);
+  }
+  int boff[9];
+  boff[0] = 0;
+#pragma unroll
+  for (int b = 1; b < 9; ++b) boff[b] = boff[b - 1] + tot[b - 1];
+  int run[9];
+#pragma unroll
+  for (int b = 0; b < 9; ++b) run[b] = jb.start + boff[b] + excl[b];
+  for (int t = t0; t < t1; ++t)
+#pragma unroll
+    for (int b = 0; b < 9; ++b) {
+      tile_base[(size_t)t * 9 + b] = run[b];
+      run[b] += tile_counts[(size_t)t * 9 + b];
+    }
+  if (lane < 8) {
+    int st = boff[0], ct = tot[0];
+#pragma unroll
+    for (int b = 1; b < 8; ++b) {
+      st = (lane == b) ? boff[b] : st;
+      ct = (lane == b) ? tot[b] : ct;
+    }
+    nodes[jb.child_base + lane].count = ct;
+    lvl_info[jb.child_lvl + lane] = make_int2(jb.start + st, ct);
+  }
+}
+
+// Stable 9-way split of each job's range by child (8 = no live child): moves
+// the points, the original indices and writes the level's labels.
+__global__ __launch_bounds__(64) void scatter_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
+                                                     const float* __restrict__ zs, const int* __restrict__ perm,
+                                                     const Tile* __restrict__ tiles, const Job* __restrict__ jobs,
+                                                     const TreeDev* __restrict__ trees, const uint8_t* __restrict__ child,
+                                                     const int* __restrict__ tile_base, float* xo, float* yo, float* zo,
+                                                     int* perm_out, int32_t* labels, int level, int64_t level_off) {
+  const Tile tl = tiles[blockIdx.x];
+  const Job jb = jobs[tl.job];
+  const TreeDev& T = trees[jb.tree];
+  const int lane = threadIdx.x;
+  __shared__ int base[9];
+  if (lane < 9) base[lane] = tile_base[(size_t)blockIdx.x * 9 + lane];
+  __syncthreads();
+  const int local_child0 = (int)(jb.child_base - T.node_base - level_off);
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int b0 = tl.start; b0 < tl.end; b0 += 64) {
+    const int i = b0 + lane;
+    const bool valid = i < tl.end;
+    const int b = valid ? (int)child[i] : 15;
+    int rank = 0, dst = 0;
+    int add[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+      unsigned long long msk = __ballot(b == v);
+      if (b == v) rank = __popcll(msk & lt);
+      add[v] = __popcll(msk);
+    }
+    if (valid) dst = base[b] + rank;
+    __syncthreads();
+    if (lane < 9) {
+      int v = add[0];
+#pragma unroll
+      for (int u = 1; u < 9; ++u) v = (lane == u) ? add[u] : v;
+      base[lane] += v;
+    }
+    if (valid) {
+      const int src = perm ? perm[i] : i;
+      xo[dst] = xs[i]; yo[dst] = ys[i]; zo[dst] = zs[i];
+      perm_out[dst] = src;
+      if (b < 8) labels[T.label_base + (int64_t)level * T.n_points + (src - T.point_off)] = local_child0 + b;
+    }
+    __syncthreads();
+  }
+}
+
+// Eigen-decomposition, complexity and global weight of the new level's nodes;
+// the parent learns whether it has live children.
+__global__ __launch_bounds__(64) void finalize_level_kernel(const Job* __restrict__ jobs, int njobs, NodeD* nodes,
+                                                            NodeF* tab) {
+  const int gid = blockIdx.x * 64 + threadIdx.x;
+  const int j = gid >> 3, k = gid & 7;
+  const bool valid = j < njobs;
+  bool live = false;
+  Job jb;
+  if (valid) {
+    jb = jobs[j];
+    live = nodes[jb.child_base + k].live != 0;
+  }
+  const unsigned long long bal = __ballot(live);
+  if (!valid) return;
+  const int lane = threadIdx.x;
+  const bool any = ((bal >> (lane & ~7)) & 0xFFull) != 0ull;
+  if (k == 0 && jb.parent >= 0) {
+    nodes[jb.parent].has_children = any ? 1 : 0;
+    if (any) tab[jb.parent].flags |= F_HASCH;
+  }
+  NodeD& nd = nodes[jb.child_base + k];
+  nd.has_children = 0;
+  if (!live) {
+    nd.count = 0;
+    return;
+  }
+  double lam[3], ev[9];
+  eig_sym3(nd.cov, lam, ev);
+  for (int i = 0; i < 3; ++i) nd.lam[i] = lam[i];
+  for (int i = 0; i < 9; ++i) nd.evec[i] = ev[i];
+  nd.kappa = lam[2] / (lam[0] + lam[1] + lam[2]);
+  nd.pig = nd.pi * (jb.parent >= 0 ? nodes[jb.parent].pig : 1.0);
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+
+void launch_root(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles, const Job* jobs,
+                 TreeDev* trees, double* partials, size_t pstride, unsigned* counters, double eps, hipStream_t s) {
+  hipLaunchKernelGGL(root_mean_kernel, dim3(ntiles), dim3(64), 0, s, xs, ys, zs, tiles, jobs, trees, partials, pstride,
+                     counters);
+  hipLaunchKernelGGL(root_cov_kernel, dim3(ntiles), dim3(64), 0, s, xs, ys, zs, tiles, jobs, trees, partials, pstride,
+                     counters, eps);
+}
+
+void launch_init_children(const Job* jobs, int njobs, const TreeDev* trees, NodeD* nodes, NodeF* tab, double eps,
+                          hipStream_t s) {
+  int threads = njobs * 8;
+  hipLaunchKernelGGL(init_children_kernel, dim3((threads + 63) / 64), dim3(64), 0, s, jobs, njobs, trees, nodes, tab,
+                     eps);
+}
+
+void launch_em_tiles(const float* xs, const float* ys, const float* zs, const Tile* tiles, const int* tile_ids,
+                     int n, const Job* jobs, NodeF* tab, NodeD* nodes, double* partials, size_t pstride,
+                     unsigned* counters, double eps, double min_mass, hipStream_t s) {
+  hipLaunchKernelGGL(em_tile_kernel, dim3(n), dim3(64), 0, s, xs, ys, zs, tiles, tile_ids, jobs, tab, nodes, partials,
+                     pstride, counters, eps, min_mass);
+}
+
+void launch_em_fused(const float* xs, const float* ys, const float* zs, const int* job_ids, int n, const Job* jobs,
+                     NodeF* tab, NodeD* nodes, int iters, double eps, double min_mass, int cap, hipStream_t s) {
+  cap = std::min(cap, 4096);
+  hipLaunchKernelGGL(em_fused_kernel, dim3(n), dim3(64), (size_t)cap * 12, s, xs, ys, zs, job_ids, jobs, tab, nodes,
+                     iters, eps, min_mass, cap);
+}
+
+void launch_partition(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
+                      const Job* jobs, const NodeF* tab, const NodeD* nodes, uint8_t* child, int* tile_counts,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(partition_kernel, dim3(ntiles), dim3(64), 0, s, xs, ys, zs, tiles, jobs, tab, nodes, child,
+                     tile_counts);
+}
+
+void launch_prefix(const Job* jobs, int njobs, const int* tile_counts, int* tile_base, NodeD* nodes, int2* lvl_info,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(prefix_kernel, dim3(njobs), dim3(64), 0, s, jobs, tile_counts, tile_base, nodes, lvl_info);
+}
+
+void launch_scatter(const float* xs, const float* ys, const float* zs, const int* perm, const Tile* tiles, int ntiles,
+                    const Job* jobs, const TreeDev* trees, const uint8_t* child, const int* tile_base, float* xo,
+                    float* yo, float* zo, int* perm_out, int32_t* labels, int level, int64_t level_off,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(scatter_kernel, dim3(ntiles), dim3(64), 0, s, xs, ys, zs, perm, tiles, jobs, trees, child,
+                     tile_base, xo, yo, zo, perm_out, labels, level, level_off);
+}
+
+void launch_finalize_level(const Job* jobs, int njobs, NodeD* nodes, NodeF* tab, hipStream_t s) {
+  int threads = njobs * 8;
+  hipLaunchKernelGGL(finalize_level_kernel, dim3((threads + 63) / 64), dim3(64), 0, s, jobs, njobs, nodes, tab);
+}
+
+}  // namespace hgmm

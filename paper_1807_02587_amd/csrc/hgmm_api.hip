@@ -1,0 +1,918 @@
+// C ABI of the GMM-Tree library: handles, workspace layout, level planning
+// and the launch sequence of tree construction and registration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hgmm.h"
+#include "hgmm_dev.h"
+#include "hgmm_host.h"
+
+using namespace hgmm;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                              \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess) return fail(HGMM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define HIP_LAUNCHED()                                                                                 \
+  do {                                                                                                 \
+    hipError_t e_ = hipGetLastError();                                                                 \
+    if (e_ != hipSuccess) return fail(HGMM_EHIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
+  } while (0)
+
+static int64_t level_off(int l) { return (((int64_t)1 << (3 * (l + 1))) - 8) / 7; }
+static int64_t level_nodes(int l) { return (int64_t)1 << (3 * (l + 1)); }
+static int64_t tree_nodes(int L) { return level_off(L); }
+
+// ---------------------------------------------------------------------------
+// forest handle
+// ---------------------------------------------------------------------------
+
+struct TreeHost {
+  int levels;
+  int64_t n_points;
+  int64_t node_base;
+  int64_t point_off;
+  int64_t label_base;
+};
+
+struct hgmm_forest_s {
+  int device = 0;
+  std::vector<TreeHost> trees;
+  TreeDev* d_trees = nullptr;
+  size_t cap_trees = 0;
+  NodeD* d_nodes = nullptr;
+  NodeF* d_tab = nullptr;
+  int64_t cap_nodes = 0;
+  int64_t cap_tab = 0;
+  int32_t* d_labels = nullptr;
+  int64_t cap_labels = 0;
+  bool has_labels = false;
+  char* h_stage = nullptr;
+  size_t cap_stage = 0;
+  int64_t total_nodes() const {
+    int64_t s = 0;
+    for (auto& t : trees) s += tree_nodes(t.levels);
+    return s;
+  }
+};
+
+static void free_forest(hgmm_forest_s* f) {
+  if (!f) return;
+  if (f->d_trees) (void)hipFree(f->d_trees);
+  if (f->d_nodes) (void)hipFree(f->d_nodes);
+  if (f->d_tab) (void)hipFree(f->d_tab);
+  if (f->d_labels) (void)hipFree(f->d_labels);
+  if (f->h_stage) (void)hipHostFree(f->h_stage);
+  delete f;
+}
+
+template <typename T>
+static int grow_dev(T*& p, int64_t& cap, int64_t need) {
+  if (need <= cap && p) return HGMM_OK;
+  if (p) { (void)hipFree(p); p = nullptr; }
+  cap = 0;
+  if (hipMalloc((void**)&p, sizeof(T) * (size_t)std::max<int64_t>(need, 1)) != hipSuccess)
+    return fail(HGMM_ENOMEM, "device allocation of %lld bytes failed", (long long)(sizeof(T) * need));
+  cap = need;
+  return HGMM_OK;
+}
+
+static int grow_stage(hgmm_forest_s* f, size_t need) {
+  if (need <= f->cap_stage && f->h_stage) return HGMM_OK;
+  if (f->h_stage) { (void)hipHostFree(f->h_stage); f->h_stage = nullptr; }
+  f->cap_stage = 0;
+  size_t sz = std::max<size_t>(need, 1 << 16);
+  if (hipHostMalloc((void**)&f->h_stage, sz, hipHostMallocDefault) != hipSuccess)
+    return fail(HGMM_ENOMEM, "pinned host allocation of %zu bytes failed", sz);
+  f->cap_stage = sz;
+  return HGMM_OK;
+}
+
+// Lays out `trees` (levels and point counts already set) and sizes the device
+// arrays of the forest.
+static int setup_forest(hgmm_forest_s* f) {
+  int64_t nb = 0, lb = 0, pb = 0;
+  for (auto& t : f->trees) {
+    t.node_base = nb;
+    t.label_base = lb;
+    t.point_off = pb;
+    nb += tree_nodes(t.levels);
+    lb += (int64_t)t.levels * t.n_points;
+    pb += t.n_points;
+  }
+  int64_t ct = (int64_t)f->cap_trees;
+  int st = grow_dev(f->d_trees, ct, (int64_t)f->trees.size());
+  f->cap_trees = (size_t)ct;
+  if (st) return st;
+  if ((st = grow_dev(f->d_nodes, f->cap_nodes, nb))) return st;
+  if ((st = grow_dev(f->d_tab, f->cap_tab, nb))) return st;
+  if ((st = grow_dev(f->d_labels, f->cap_labels, std::max<int64_t>(lb, 1)))) return st;
+  return HGMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layouts
+// ---------------------------------------------------------------------------
+
+static size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+struct BuildLayout {
+  size_t pts[2], perm[2], child, tiles, tile_ids, job_ids, jobs, partials, tile_counts, tile_base, counters,
+      lvl_info, total;
+  int64_t max_tiles, max_jobs, max_lvl;
+};
+
+static BuildLayout build_layout(int64_t n_total, int64_t max_jobs, int64_t max_lvl) {
+  BuildLayout L;
+  L.max_jobs = std::max<int64_t>(max_jobs, 1);
+  L.max_tiles = n_total / 64 + L.max_jobs + 1;
+  L.max_lvl = std::max<int64_t>(max_lvl, 8);
+  size_t o = 0;
+  for (int k = 0; k < 2; ++k) { L.pts[k] = o; o = align_up(o + sizeof(float) * 3 * (size_t)n_total); }
+  for (int k = 0; k < 2; ++k) { L.perm[k] = o; o = align_up(o + sizeof(int) * (size_t)n_total); }
+  L.child = o; o = align_up(o + (size_t)n_total);
+  L.tiles = o; o = align_up(o + sizeof(Tile) * (size_t)L.max_tiles);
+  L.tile_ids = o; o = align_up(o + sizeof(int) * (size_t)L.max_tiles);
+  L.job_ids = o; o = align_up(o + sizeof(int) * (size_t)L.max_jobs);
+  L.jobs = o; o = align_up(o + sizeof(Job) * (size_t)L.max_jobs);
+  L.partials = o; o = align_up(o + sizeof(double) * 80 * (size_t)L.max_tiles);
+  L.tile_counts = o; o = align_up(o + sizeof(int) * 9 * (size_t)L.max_tiles);
+  L.tile_base = o; o = align_up(o + sizeof(int) * 9 * (size_t)L.max_tiles);
+  L.counters = o; o = align_up(o + sizeof(unsigned) * (size_t)L.max_jobs);
+  L.lvl_info = o; o = align_up(o + sizeof(int2) * (size_t)L.max_lvl);
+  L.total = o;
+  return L;
+}
+
+struct RegLayout {
+  size_t bins, partials, counters, state, nmov, tiles, out, dpart, dcount, ptiles, total;
+  int64_t max_tiles;
+};
+
+static RegLayout reg_layout(int64_t n_total, int64_t nodes, int npairs) {
+  RegLayout L;
+  L.max_tiles = n_total / 256 + npairs + 1;
+  size_t o = 0;
+  L.bins = o; o = align_up(o + sizeof(double) * 6 * (size_t)std::max<int64_t>(nodes, 1));
+  L.partials = o; o = align_up(o + sizeof(double) * 28 * (size_t)normal_blocks_per_pair() * npairs);
+  L.counters = o; o = align_up(o + sizeof(unsigned) * (size_t)npairs);
+  L.dpart = o; o = align_up(o + sizeof(double) * 72 * 6 * (size_t)L.max_tiles);
+  L.dcount = o; o = align_up(o + sizeof(unsigned) * (size_t)npairs);
+  L.ptiles = o; o = align_up(o + sizeof(int2) * (size_t)npairs);
+  L.state = o; o = align_up(o + sizeof(PoseState) * (size_t)npairs);
+  L.nmov = o; o = align_up(o + sizeof(int64_t) * (size_t)npairs);
+  L.tiles = o; o = align_up(o + sizeof(Tile) * (size_t)L.max_tiles);
+  L.out = o; o = align_up(o + sizeof(double) * 28 * (size_t)npairs + sizeof(double) * 12 * npairs);
+  L.total = o;
+  return L;
+}
+
+static int64_t max_jobs_for(const std::vector<TreeHost>& trees) {
+  int64_t m = 0;
+  int Lmax = 0;
+  for (auto& t : trees) Lmax = std::max(Lmax, t.levels);
+  for (int l = 0; l < Lmax; ++l) {
+    int64_t s = 0;
+    for (auto& t : trees)
+      if (t.levels > l) s += (l == 0) ? 1 : level_nodes(l - 1);
+    m = std::max(m, s);
+  }
+  return m;
+}
+
+static int64_t max_lvl_for(const std::vector<TreeHost>& trees) {
+  int64_t m = 0;
+  int Lmax = 0;
+  for (auto& t : trees) Lmax = std::max(Lmax, t.levels);
+  for (int l = 0; l < Lmax; ++l) {
+    int64_t s = 0;
+    for (auto& t : trees)
+      if (t.levels > l) s += level_nodes(l);
+    m = std::max(m, s);
+  }
+  return m;
+}
+
+// ---------------------------------------------------------------------------
+// tunables (points per tile by level size; largest job run as one fused wave)
+// ---------------------------------------------------------------------------
+
+struct Tuning {
+  int fused_max = 512;
+  int min_tile = 256;
+  int target_tiles = 1024;
+  int max_tile = 4096;
+  int reg_tile = 512;
+  int reg_chunk = 4;
+};
+static Tuning g_tune;
+
+extern "C" int hgmm_set_tuning(int fused_max, int min_tile, int target_tiles, int max_tile, int reg_tile) {
+  if (fused_max >= 0) g_tune.fused_max = fused_max;
+  if (min_tile > 0) g_tune.min_tile = (min_tile + 63) / 64 * 64;
+  if (target_tiles > 0) g_tune.target_tiles = target_tiles;
+  if (max_tile > 0) g_tune.max_tile = (max_tile + 63) / 64 * 64;
+  if (reg_tile > 0) g_tune.reg_tile = (reg_tile + 255) / 256 * 256;
+  return HGMM_OK;
+}
+
+static int tile_points(int64_t level_points) {
+  int64_t t = level_points / std::max(1, g_tune.target_tiles);
+  t = (t + 63) / 64 * 64;
+  t = std::max<int64_t>(t, g_tune.min_tile);
+  t = std::min<int64_t>(t, g_tune.max_tile);
+  return (int)t;
+}
+
+// ---------------------------------------------------------------------------
+// optional event timing of the kernel launches (benchmark instrumentation)
+// ---------------------------------------------------------------------------
+
+enum ProfKind { PK_EM_TILE = 0, PK_EM_FUSED, PK_PARTITION, PK_SCATTER, PK_DESCEND, PK_NORMAL, PK_ROOT, PK_OTHER,
+                PK_COUNT };
+
+struct ProfPending {
+  int kind;
+  double units;
+  hipEvent_t a, b;
+  int tag;  // registration iteration of a descend/normal launch, -1 otherwise
+};
+
+struct ProfState {
+  bool on = false;
+  double ms[PK_COUNT] = {0};
+  int64_t launches[PK_COUNT] = {0};
+  double units[PK_COUNT] = {0};
+  std::vector<hipEvent_t> pool;
+  std::vector<ProfPending> pending;
+};
+static ProfState g_prof;
+
+static hipEvent_t prof_event() {
+  if (!g_prof.pool.empty()) {
+    hipEvent_t e = g_prof.pool.back();
+    g_prof.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+struct ProfScope {
+  ProfPending p;
+  hipStream_t s;
+  bool on;
+  ProfScope(int kind, double units, hipStream_t st, int tag = -1) : s(st), on(g_prof.on) {
+    if (!on) return;
+    p.kind = kind; p.units = units; p.tag = tag;
+    p.a = prof_event(); p.b = prof_event();
+    (void)hipEventRecord(p.a, s);
+  }
+  ~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(p.b, s);
+    g_prof.pending.push_back(p);
+  }
+};
+
+// Folds the timed launches into the totals (call after the stream was
+// synchronised).  Registration launches with tag >= iters_done were no-ops
+// after convergence and are not counted.
+static void prof_collect(int iters_done = 1 << 30) {
+  for (auto& p : g_prof.pending) {
+    float ms = 0.f;
+    if (p.tag < iters_done && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      g_prof.ms[p.kind] += ms;
+      g_prof.launches[p.kind] += 1;
+      g_prof.units[p.kind] += p.units;
+    }
+    g_prof.pool.push_back(p.a);
+    g_prof.pool.push_back(p.b);
+  }
+  g_prof.pending.clear();
+}
+
+extern "C" int hgmm_profile(int enable) {
+  g_prof.on = enable != 0;
+  return HGMM_OK;
+}
+
+extern "C" void hgmm_profile_reset(void) {
+  for (int k = 0; k < PK_COUNT; ++k) { g_prof.ms[k] = 0; g_prof.launches[k] = 0; g_prof.units[k] = 0; }
+}
+
+extern "C" int hgmm_profile_read(int kind, double* total_ms, int64_t* launches, double* units) {
+  if (kind < 0 || kind >= PK_COUNT) return fail(HGMM_EINVAL, "profile kind %d out of range", kind);
+  if (total_ms) *total_ms = g_prof.ms[kind];
+  if (launches) *launches = g_prof.launches[kind];
+  if (units) *units = g_prof.units[kind];
+  return HGMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// construction
+// ---------------------------------------------------------------------------
+
+struct BuildInput {
+  const float* xs;
+  const float* ys;
+  const float* zs;
+};
+
+static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p, char* ws, size_t ws_bytes,
+                     hipStream_t s) {
+  const int B = (int)f->trees.size();
+  int64_t n_total = 0;
+  int Lmax = 0;
+  for (auto& t : f->trees) { n_total += t.n_points; Lmax = std::max(Lmax, t.levels); }
+  BuildLayout Ly = build_layout(n_total, max_jobs_for(f->trees), max_lvl_for(f->trees));
+  if (ws_bytes < Ly.total) return fail(HGMM_EINVAL, "build workspace too small: %zu < %zu", ws_bytes, Ly.total);
+  float* pts[2] = {(float*)(ws + Ly.pts[0]), (float*)(ws + Ly.pts[1])};
+  int* perm[2] = {(int*)(ws + Ly.perm[0]), (int*)(ws + Ly.perm[1])};
+  uint8_t* child = (uint8_t*)(ws + Ly.child);
+  Tile* d_tiles = (Tile*)(ws + Ly.tiles);
+  int* d_tile_ids = (int*)(ws + Ly.tile_ids);
+  int* d_job_ids = (int*)(ws + Ly.job_ids);
+  Job* d_jobs = (Job*)(ws + Ly.jobs);
+  double* d_partials = (double*)(ws + Ly.partials);
+  int* d_tile_counts = (int*)(ws + Ly.tile_counts);
+  int* d_tile_base = (int*)(ws + Ly.tile_base);
+  unsigned* d_counters = (unsigned*)(ws + Ly.counters);
+  int2* d_lvl = (int2*)(ws + Ly.lvl_info);
+
+  // staging: trees | jobs | tiles | tile ids | job ids | level info
+  size_t st_trees = 0;
+  size_t st_jobs = align_up(st_trees + sizeof(TreeDev) * 2 * B);
+  size_t st_tiles = align_up(st_jobs + sizeof(Job) * Ly.max_jobs);
+  size_t st_tids = align_up(st_tiles + sizeof(Tile) * Ly.max_tiles);
+  size_t st_jids = align_up(st_tids + sizeof(int) * Ly.max_tiles);
+  size_t st_lvl = align_up(st_jids + sizeof(int) * Ly.max_jobs);
+  size_t st_end = align_up(st_lvl + sizeof(int2) * Ly.max_lvl);
+  int rc = grow_stage(f, st_end);
+  if (rc) return rc;
+  char* H = f->h_stage;
+  TreeDev* h_trees = (TreeDev*)(H + st_trees);
+  Job* h_jobs = (Job*)(H + st_jobs);
+  Tile* h_tiles = (Tile*)(H + st_tiles);
+  int* h_tids = (int*)(H + st_tids);
+  int* h_jids = (int*)(H + st_jids);
+  int2* h_lvl = (int2*)(H + st_lvl);
+
+  for (int b = 0; b < B; ++b) {
+    TreeDev& T = h_trees[b];
+    memset(&T, 0, sizeof(T));
+    T.node_base = f->trees[b].node_base;
+    T.point_off = f->trees[b].point_off;
+    T.label_base = f->trees[b].label_base;
+    T.levels = f->trees[b].levels;
+    T.n_points = (int32_t)f->trees[b].n_points;
+  }
+  HIP_TRY(hipMemcpyAsync(f->d_trees, h_trees, sizeof(TreeDev) * B, hipMemcpyHostToDevice, s));
+  const int64_t nodes_total = f->total_nodes();
+  launch_fill_u32(f->d_nodes, 0u, (int64_t)(sizeof(NodeD) / 4) * nodes_total, s);
+  launch_fill_u32(f->d_tab, 0u, (int64_t)(sizeof(NodeF) / 4) * nodes_total, s);
+  int64_t nlab = 0;
+  for (auto& t : f->trees) nlab += (int64_t)t.levels * t.n_points;
+  launch_fill_u32(f->d_labels, 0xFFFFFFFFu, nlab, s);
+  launch_fill_u32(d_counters, 0u, Ly.max_jobs, s);
+  HIP_LAUNCHED();
+
+  // level-compact bases: lvl_base[l][b]
+  std::vector<std::vector<int64_t>> lvl_base(Lmax, std::vector<int64_t>(B, -1));
+  std::vector<int64_t> lvl_size(Lmax, 0);
+  for (int l = 0; l < Lmax; ++l)
+    for (int b = 0; b < B; ++b)
+      if (f->trees[b].levels > l) { lvl_base[l][b] = lvl_size[l]; lvl_size[l] += level_nodes(l); }
+
+  const float* cx = in.xs;
+  const float* cy = in.ys;
+  const float* cz = in.zs;
+  const int* cperm = nullptr;
+  int ping = 0;
+  std::vector<Job> jobs;
+  jobs.reserve(1024);
+
+  for (int l = 0; l < Lmax; ++l) {
+    // ---- plan the jobs of level l (parents at level l-1, roots at level 0)
+    jobs.clear();
+    int64_t level_points = 0;
+    if (l == 0) {
+      for (int b = 0; b < B; ++b) {
+        const TreeHost& t = f->trees[b];
+        Job j;
+        j.start = (int32_t)t.point_off;
+        j.count = (int32_t)t.n_points;
+        j.parent = -1;
+        j.child_base = (int32_t)t.node_base;
+        j.child_lvl = (int32_t)lvl_base[0][b];
+        j.tree = b;
+        jobs.push_back(j);
+        level_points += t.n_points;
+      }
+    } else {
+      for (int b = 0; b < B; ++b) {
+        const TreeHost& t = f->trees[b];
+        if (t.levels <= l) continue;
+        const int64_t pb = lvl_base[l - 1][b];
+        const int64_t np = level_nodes(l - 1);
+        for (int64_t k = 0; k < np; ++k) {
+          const int2 info = h_lvl[pb + k];
+          if (info.y <= 0) continue;
+          Job j;
+          j.start = info.x;
+          j.count = info.y;
+          j.parent = (int32_t)(t.node_base + level_off(l - 1) + k);
+          j.child_base = (int32_t)(t.node_base + level_off(l) + 8 * k);
+          j.child_lvl = (int32_t)(lvl_base[l][b] + 8 * k);
+          j.tree = b;
+          jobs.push_back(j);
+          level_points += info.y;
+        }
+      }
+    }
+    const int njobs = (int)jobs.size();
+    if (njobs == 0) break;
+    const int tpts = tile_points(level_points);
+    int ntiles = 0, nbig = 0, nsmall = 0;
+    for (int j = 0; j < njobs; ++j) {
+      Job& jb = jobs[j];
+      jb.tile_first = ntiles;
+      jb.ntiles = (jb.count + tpts - 1) / tpts;
+      const bool small = jb.count <= g_tune.fused_max;
+      for (int t = 0; t < jb.ntiles; ++t) {
+        Tile& T = h_tiles[ntiles];
+        T.start = jb.start + t * tpts;
+        T.end = std::min(jb.start + jb.count, T.start + tpts);
+        T.job = j;
+        T.pad = 0;
+        if (!small) h_tids[nbig++] = ntiles;
+        ++ntiles;
+      }
+      if (small) h_jids[nsmall++] = j;
+      h_jobs[j] = jb;
+    }
+    if (ntiles > Ly.max_tiles || njobs > Ly.max_jobs) return fail(HGMM_EINVAL, "internal: tile plan overflow");
+    HIP_TRY(hipMemcpyAsync(d_jobs, h_jobs, sizeof(Job) * njobs, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_tiles, h_tiles, sizeof(Tile) * ntiles, hipMemcpyHostToDevice, s));
+    if (nbig) HIP_TRY(hipMemcpyAsync(d_tile_ids, h_tids, sizeof(int) * nbig, hipMemcpyHostToDevice, s));
+    if (nsmall) HIP_TRY(hipMemcpyAsync(d_job_ids, h_jids, sizeof(int) * nsmall, hipMemcpyHostToDevice, s));
+
+    if (l == 0) {
+      {
+        ProfScope ps(PK_ROOT, (double)level_points, s);
+        launch_root(cx, cy, cz, d_tiles, ntiles, d_jobs, f->d_trees, d_partials, (size_t)Ly.max_tiles, d_counters,
+                    p.reg_eps, s);
+      }
+      HIP_LAUNCHED();
+      HIP_TRY(hipMemcpyAsync(h_trees + B, f->d_trees, sizeof(TreeDev) * B, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      prof_collect();
+      for (int b = 0; b < B; ++b)
+        if (h_trees[B + b].status != 0) return fail(HGMM_ENONFINITE, "non-finite coordinate in cloud %d", b);
+    }
+
+    // ---- EM for the 8 children of every job
+    launch_init_children(d_jobs, njobs, f->d_trees, f->d_nodes, f->d_tab, p.reg_eps, s);
+    int64_t big_points = 0, small_points = 0;
+    for (int j = 0; j < njobs; ++j) (jobs[j].count <= g_tune.fused_max ? small_points : big_points) += jobs[j].count;
+    if (nbig)
+      for (int it = 0; it < p.build_iters; ++it) {
+        ProfScope ps(PK_EM_TILE, (double)big_points, s);
+        launch_em_tiles(cx, cy, cz, d_tiles, d_tile_ids, nbig, d_jobs, f->d_tab, f->d_nodes, d_partials,
+                        (size_t)Ly.max_tiles, d_counters, p.reg_eps, p.min_mass, s);
+      }
+    if (nsmall && p.build_iters > 0) {
+      ProfScope ps(PK_EM_FUSED, (double)small_points * p.build_iters, s);
+      launch_em_fused(cx, cy, cz, d_job_ids, nsmall, d_jobs, f->d_tab, f->d_nodes, p.build_iters, p.reg_eps,
+                      p.min_mass, (g_tune.fused_max + 63) / 64 * 64, s);
+    }
+    // ---- hard partition, child ranges, stable split, per-node statistics
+    {
+      ProfScope ps(PK_PARTITION, (double)level_points, s);
+      launch_partition(cx, cy, cz, d_tiles, ntiles, d_jobs, f->d_tab, f->d_nodes, child, d_tile_counts, s);
+    }
+    launch_fill_u32(d_lvl, 0u, 2 * lvl_size[l], s);
+    launch_prefix(d_jobs, njobs, d_tile_counts, d_tile_base, f->d_nodes, d_lvl, s);
+    float* nx = pts[ping];
+    float* ny = nx + n_total;
+    float* nz = ny + n_total;
+    {
+      ProfScope ps(PK_SCATTER, (double)level_points, s);
+      launch_scatter(cx, cy, cz, cperm, d_tiles, ntiles, d_jobs, f->d_trees, child, d_tile_base, nx, ny, nz,
+                     perm[ping], f->d_labels, l, level_off(l), s);
+    }
+    launch_finalize_level(d_jobs, njobs, f->d_nodes, f->d_tab, s);
+    HIP_LAUNCHED();
+    cx = nx; cy = ny; cz = nz;
+    cperm = perm[ping];
+    ping ^= 1;
+    if (l + 1 < Lmax) {
+      HIP_TRY(hipMemcpyAsync(h_lvl, d_lvl, sizeof(int2) * lvl_size[l], hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      prof_collect();
+    }
+  }
+  // origin and extent back to the host copy
+  HIP_TRY(hipMemcpyAsync(h_trees + B, f->d_trees, sizeof(TreeDev) * B, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  prof_collect();
+  f->has_labels = true;
+  return HGMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// registration
+// ---------------------------------------------------------------------------
+
+struct RegRun {
+  int max_iters;
+  double lambda_c, tol_rot, tol_trans_rel;
+};
+
+static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, const float* zs,
+                        const std::vector<int64_t>& offs, const double* R0, const double* t0, int per_pair,
+                        const RegRun& rr, char* ws, size_t ws_bytes, hipStream_t s, int mode_estep,
+                        int32_t* stop_out, float* gamma_out, double* bins_ext, PoseState* h_out, double* h_norm) {
+  const int P = (int)offs.size() - 1;
+  const int64_t n_total = offs.back();
+  const int64_t nodes_total = f->total_nodes();
+  RegLayout Ly = reg_layout(n_total, nodes_total, P);
+  if (ws_bytes < Ly.total) return fail(HGMM_EINVAL, "register workspace too small: %zu < %zu", ws_bytes, Ly.total);
+  double* d_bins = bins_ext ? bins_ext : (double*)(ws + Ly.bins);
+  double* d_partials = (double*)(ws + Ly.partials);
+  unsigned* d_counters = (unsigned*)(ws + Ly.counters);
+  PoseState* d_state = (PoseState*)(ws + Ly.state);
+  int64_t* d_nmov = (int64_t*)(ws + Ly.nmov);
+  Tile* d_tiles = (Tile*)(ws + Ly.tiles);
+  double* d_out = (double*)(ws + Ly.out);
+  double* d_pose0 = d_out + 28 * P;
+  double* d_dpart = (double*)(ws + Ly.dpart);
+  unsigned* d_dcount = (unsigned*)(ws + Ly.dcount);
+  int2* d_ptiles = (int2*)(ws + Ly.ptiles);
+
+  size_t s_tiles = 0;
+  size_t s_nmov = align_up(s_tiles + sizeof(Tile) * Ly.max_tiles);
+  size_t s_pose = align_up(s_nmov + sizeof(int64_t) * P);
+  size_t s_res = align_up(s_pose + sizeof(double) * 12 * P);
+  size_t s_norm = align_up(s_res + sizeof(PoseState) * P);
+  size_t s_pt = align_up(s_norm + sizeof(double) * 28 * P);
+  size_t s_end = align_up(s_pt + sizeof(int2) * P);
+  int rc = grow_stage(f, s_end);
+  if (rc) return rc;
+  char* H = f->h_stage;
+  Tile* h_tiles = (Tile*)(H + s_tiles);
+  int64_t* h_nmov = (int64_t*)(H + s_nmov);
+  double* h_pose = (double*)(H + s_pose);
+  PoseState* h_res = (PoseState*)(H + s_res);
+  double* h_nrm = (double*)(H + s_norm);
+  int2* h_pt = (int2*)(H + s_pt);
+
+  int ntiles = 0;
+  const int rt = g_tune.reg_tile;
+  for (int b = 0; b < P; ++b) {
+    h_nmov[b] = offs[b + 1] - offs[b];
+    h_pt[b].x = ntiles;
+    for (int64_t st0 = offs[b]; st0 < offs[b + 1]; st0 += rt) {
+      Tile& T = h_tiles[ntiles++];
+      T.start = (int32_t)st0;
+      T.end = (int32_t)std::min<int64_t>(offs[b + 1], st0 + rt);
+      T.job = b;
+      T.pad = 0;
+    }
+    h_pt[b].y = ntiles - h_pt[b].x;
+  }
+  if (ntiles > Ly.max_tiles) return fail(HGMM_EINVAL, "internal: registration tile overflow");
+  const int npose = per_pair ? P : 1;
+  for (int b = 0; b < npose; ++b) {
+    for (int i = 0; i < 9; ++i) h_pose[12 * b + i] = R0 ? R0[9 * b + i] : (i % 4 == 0 ? 1.0 : 0.0);
+    for (int i = 0; i < 3; ++i) h_pose[12 * b + 9 + i] = t0 ? t0[3 * b + i] : 0.0;
+  }
+  HIP_TRY(hipMemcpyAsync(d_tiles, h_tiles, sizeof(Tile) * ntiles, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_ptiles, h_pt, sizeof(int2) * P, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_nmov, h_nmov, sizeof(int64_t) * P, hipMemcpyHostToDevice, s));
+  // pose rows are 12 doubles: R (9) then t (3)
+  HIP_TRY(hipMemcpyAsync(d_pose0, h_pose, sizeof(double) * 12 * npose, hipMemcpyHostToDevice, s));
+  launch_fill_u32(d_bins, 0u, 2 * 6 * nodes_total, s);
+  launch_fill_u32(d_counters, 0u, P, s);
+  launch_fill_u32(d_dcount, 0u, P, s);
+  launch_set_stop_flags(f->d_tab, f->d_nodes, nodes_total, rr.lambda_c, s);
+  launch_init_pose(d_state, P, d_pose0, d_pose0 + 9, per_pair ? 12 : 0, s);
+  HIP_LAUNCHED();
+  const size_t pstride = (size_t)Ly.max_tiles;
+  if (mode_estep) {
+    launch_descend(xs, ys, zs, d_tiles, ntiles, d_ptiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins, d_dpart,
+                   pstride, d_dcount, stop_out, gamma_out, s);
+    if (h_norm) {
+      launch_normal(d_bins, f->d_nodes, f->d_trees, d_state, d_nmov, P, d_partials, d_counters, 1, 0.0, 0.0, d_out, s);
+      HIP_TRY(hipMemcpyAsync(h_nrm, d_out, sizeof(double) * 28 * P, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      memcpy(h_norm, h_nrm, sizeof(double) * 28 * P);
+    }
+    HIP_LAUNCHED();
+    return HGMM_OK;
+  }
+  // E/M iterations in chunks; between chunks the host checks whether every
+  // pair has converged so that no further launches are queued
+  int it = 0;
+  const int chunk = std::max(1, g_tune.reg_chunk);
+  while (it < rr.max_iters) {
+    const int end = std::min(rr.max_iters, it + chunk);
+    for (; it < end; ++it) {
+      {
+        ProfScope ps(PK_DESCEND, (double)n_total, s, it);
+        launch_descend(xs, ys, zs, d_tiles, ntiles, d_ptiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins,
+                       d_dpart, pstride, d_dcount, nullptr, nullptr, s);
+      }
+      {
+        ProfScope ps(PK_NORMAL, (double)nodes_total, s, it);
+        launch_normal(d_bins, f->d_nodes, f->d_trees, d_state, d_nmov, P, d_partials, d_counters, 0, rr.tol_rot,
+                      rr.tol_trans_rel, d_out, s);
+      }
+    }
+    HIP_LAUNCHED();
+    HIP_TRY(hipMemcpyAsync(h_res, d_state, sizeof(PoseState) * P, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    bool all_done = true;
+    for (int b = 0; b < P; ++b) all_done = all_done && (h_res[b].done != 0);
+    if (all_done) break;
+  }
+  {
+    int done_iters = 0;
+    for (int b = 0; b < P; ++b) done_iters = std::max(done_iters, (int)h_res[b].iters);
+    prof_collect(done_iters);
+  }
+  memcpy(h_out, h_res, sizeof(PoseState) * P);
+  return HGMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* hgmm_last_error(void) { return g_err.c_str(); }
+
+int hgmm_params_default(hgmm_build_params* bp, hgmm_reg_params* rp) {
+  if (bp) { bp->levels = 2; bp->build_iters = 30; bp->reg_eps = 1e-6; bp->min_mass = 1.0; }
+  if (rp) { rp->max_iters = 30; rp->pad_ = 0; rp->lambda_c = 0.01; rp->tol_rot = 1e-6; rp->tol_trans_rel = 1e-6; }
+  return HGMM_OK;
+}
+
+int64_t hgmm_tree_nodes(int levels) {
+  if (levels < 1 || levels > HGMM_MAX_LEVELS) return -1;
+  return tree_nodes(levels);
+}
+
+int64_t hgmm_level_offset(int level) {
+  if (level < 0 || level > HGMM_MAX_LEVELS) return -1;
+  return level_off(level);
+}
+
+size_t hgmm_build_workspace_bytes(int64_t n, int levels) {
+  if (levels < 1 || levels > HGMM_MAX_LEVELS || n < 0) return 0;
+  std::vector<TreeHost> t(1);
+  t[0].levels = levels;
+  t[0].n_points = n;
+  return build_layout(n, max_jobs_for(t), max_lvl_for(t)).total;
+}
+
+size_t hgmm_register_workspace_bytes(int64_t n, int levels) {
+  if (levels < 1 || levels > HGMM_MAX_LEVELS || n < 0) return 0;
+  return reg_layout(n, tree_nodes(levels), 1).total;
+}
+
+static int check_build_params(const hgmm_build_params* p) {
+  if (!p) return fail(HGMM_EINVAL, "null build params");
+  if (p->levels < 1 || p->levels > HGMM_MAX_LEVELS) return fail(HGMM_EINVAL, "levels %d outside [1, 6]", p->levels);
+  if (p->build_iters < 0) return fail(HGMM_EINVAL, "build_iters < 0");
+  if (!(p->reg_eps > 0.0) || !std::isfinite(p->reg_eps)) return fail(HGMM_EINVAL, "reg_eps must be positive");
+  if (!(p->min_mass >= 0.0)) return fail(HGMM_EINVAL, "min_mass must be >= 0");
+  return HGMM_OK;
+}
+
+int hgmm_build(const float* d_xyz, int64_t n, const hgmm_build_params* p, void* d_ws, size_t ws_bytes, void* stream,
+               hgmm_tree* tree) {
+  int rc = check_build_params(p);
+  if (rc) return rc;
+  if (!d_xyz || !d_ws || !tree) return fail(HGMM_EINVAL, "null pointer argument");
+  if (n < 8) return fail(HGMM_ETOOFEW, "need at least 8 points, got %lld", (long long)n);
+  if (n > (int64_t)INT32_MAX / 2) return fail(HGMM_EINVAL, "too many points");
+  hgmm_forest_s* f = *tree;
+  const bool fresh = (f == nullptr);
+  if (fresh) f = new hgmm_forest_s();
+  HIP_TRY(hipGetDevice(&f->device));
+  f->trees.assign(1, TreeHost{p->levels, n, 0, 0, 0});
+  rc = setup_forest(f);
+  if (!rc) {
+    BuildInput in{d_xyz, d_xyz + n, d_xyz + 2 * n};
+    rc = run_build(f, in, *p, (char*)d_ws, ws_bytes, (hipStream_t)stream);
+  }
+  if (rc && fresh) { free_forest(f); return rc; }
+  *tree = f;
+  return rc;
+}
+
+int hgmm_register(hgmm_tree tree, const float* d_xyz, int64_t n, const hgmm_reg_params* p, const double* R0,
+                  const double* t0, void* d_ws, size_t ws_bytes, void* stream, double R[9], double t[3], int* iters,
+                  double* loglik) {
+  if (n < 1) return fail(HGMM_ETOOFEW, "empty cloud");
+  if (!tree || !d_xyz || !p || !d_ws || !R || !t || !iters) return fail(HGMM_EINVAL, "null pointer argument");
+  if (n > (int64_t)INT32_MAX / 2) return fail(HGMM_EINVAL, "too many points");
+  if (p->max_iters < 1) return fail(HGMM_EINVAL, "max_iters must be >= 1");
+  if (tree->trees.size() != 1) return fail(HGMM_EINVAL, "hgmm_register takes a single-tree handle");
+  std::vector<int64_t> offs = {0, n};
+  RegRun rr{p->max_iters, p->lambda_c, p->tol_rot, p->tol_trans_rel};
+  PoseState res;
+  int rc = run_register(tree, d_xyz, d_xyz + n, d_xyz + 2 * n, offs, R0, t0, 0, rr, (char*)d_ws, ws_bytes,
+                        (hipStream_t)stream, 0, nullptr, nullptr, nullptr, &res, nullptr);
+  if (rc) return rc;
+  for (int i = 0; i < 9; ++i) R[i] = res.R[i];
+  for (int i = 0; i < 3; ++i) t[i] = res.t[i];
+  *iters = res.iters;
+  if (loglik) *loglik = res.loglik;
+  if (res.status != 0) return fail(res.status, "normal equations not positive definite at iteration %d", res.iters);
+  return HGMM_OK;
+}
+
+int hgmm_estep(hgmm_tree tree, const float* d_xyz, int64_t n, const double R[9], const double t[3], double lambda_c,
+               void* d_ws, size_t ws_bytes, void* stream, int32_t* d_stop_node, float* d_gamma, double* d_bins,
+               double* loglik) {
+  if (!tree || !d_xyz || !R || !t || !d_ws) return fail(HGMM_EINVAL, "null pointer argument");
+  if (n < 1) return fail(HGMM_ETOOFEW, "empty cloud");
+  if (tree->trees.size() != 1) return fail(HGMM_EINVAL, "hgmm_estep takes a single-tree handle");
+  std::vector<int64_t> offs = {0, n};
+  RegRun rr{1, lambda_c, 0.0, 0.0};
+  double nrm[28];
+  int rc = run_register(tree, d_xyz, d_xyz + n, d_xyz + 2 * n, offs, R, t, 0, rr, (char*)d_ws, ws_bytes,
+                        (hipStream_t)stream, 1, d_stop_node, d_gamma, d_bins, nullptr, loglik ? nrm : nullptr);
+  if (rc) return rc;
+  if (loglik) *loglik = nrm[27];
+  return HGMM_OK;
+}
+
+int hgmm_normal_equations(hgmm_tree tree, const double* d_bins, int64_t n, void* d_ws, size_t ws_bytes, void* stream,
+                          double H[36], double g[6]) {
+  if (!tree || !d_bins || !d_ws || !H || !g) return fail(HGMM_EINVAL, "null pointer argument");
+  if (tree->trees.size() != 1) return fail(HGMM_EINVAL, "single-tree handle expected");
+  const int64_t nodes_total = tree->total_nodes();
+  RegLayout Ly = reg_layout(n, nodes_total, 1);
+  if (ws_bytes < Ly.total) return fail(HGMM_EINVAL, "workspace too small");
+  char* ws = (char*)d_ws;
+  hipStream_t s = (hipStream_t)stream;
+  int rc = grow_stage(tree, 4096);
+  if (rc) return rc;
+  double* h = (double*)tree->h_stage;
+  int64_t* hn = (int64_t*)(tree->h_stage + 1024);
+  for (int i = 0; i < 12; ++i) h[i] = (i < 9) ? (i % 4 == 0 ? 1.0 : 0.0) : 0.0;
+  *hn = n;
+  double* d_out = (double*)(ws + Ly.out);
+  double* d_pose0 = d_out + 28;
+  int64_t* d_nmov = (int64_t*)(ws + Ly.nmov);
+  HIP_TRY(hipMemcpyAsync(d_pose0, h, sizeof(double) * 12, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_nmov, hn, sizeof(int64_t), hipMemcpyHostToDevice, s));
+  launch_fill_u32(ws + Ly.counters, 0u, 1, s);
+  launch_init_pose((PoseState*)(ws + Ly.state), 1, d_pose0, d_pose0 + 9, 0, s);
+  // the kernel reads the bins without modifying them in mode 1
+  launch_normal(const_cast<double*>(d_bins), tree->d_nodes, tree->d_trees, (PoseState*)(ws + Ly.state), d_nmov, 1,
+                (double*)(ws + Ly.partials), (unsigned*)(ws + Ly.counters), 1, 0.0, 0.0, d_out, s);
+  HIP_LAUNCHED();
+  double* hres = h + 16;
+  HIP_TRY(hipMemcpyAsync(hres, d_out, sizeof(double) * 28, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  int idx = 0;
+  for (int i = 0; i < 6; ++i)
+    for (int j = i; j < 6; ++j) { H[6 * i + j] = hres[idx]; H[6 * j + i] = hres[idx]; ++idx; }
+  for (int i = 0; i < 6; ++i) g[i] = hres[21 + i];
+  return HGMM_OK;
+}
+
+int hgmm_tree_info(hgmm_tree tree, int index, int* levels, int64_t* n_nodes, double origin[3], double* extent) {
+  if (!tree || index < 0 || index >= (int)tree->trees.size()) return fail(HGMM_EINVAL, "bad tree index");
+  TreeDev T;
+  HIP_TRY(hipMemcpy(&T, tree->d_trees + index, sizeof(TreeDev), hipMemcpyDeviceToHost));
+  if (levels) *levels = tree->trees[index].levels;
+  if (n_nodes) *n_nodes = tree_nodes(tree->trees[index].levels);
+  if (origin) for (int i = 0; i < 3; ++i) origin[i] = T.origin[i];
+  if (extent) *extent = T.extent;
+  return HGMM_OK;
+}
+
+int hgmm_tree_export(hgmm_tree tree, int index, hgmm_tree_host* out) {
+  if (!tree || !out || index < 0 || index >= (int)tree->trees.size()) return fail(HGMM_EINVAL, "bad argument");
+  const TreeHost& th = tree->trees[index];
+  const int64_t nn = tree_nodes(th.levels);
+  std::vector<NodeD> nd((size_t)nn);
+  TreeDev T;
+  HIP_TRY(hipMemcpy(nd.data(), tree->d_nodes + th.node_base, sizeof(NodeD) * nn, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(&T, tree->d_trees + index, sizeof(TreeDev), hipMemcpyDeviceToHost));
+  out->levels = th.levels;
+  out->n_points = th.n_points;
+  for (int i = 0; i < 3; ++i) out->origin[i] = T.origin[i];
+  out->extent = T.extent;
+  for (int64_t g = 0; g < nn; ++g) {
+    const NodeD& a = nd[g];
+    if (out->live) out->live[g] = a.live;
+    if (out->has_children) out->has_children[g] = a.has_children;
+    if (out->count) out->count[g] = a.count;
+    if (out->pi) out->pi[g] = a.pi;
+    if (out->pig) out->pig[g] = a.pig;
+    if (out->kappa) out->kappa[g] = a.kappa;
+    for (int i = 0; i < 3; ++i) {
+      if (out->mu) out->mu[3 * g + i] = a.mu[i];
+      if (out->lam) out->lam[3 * g + i] = a.lam[i];
+    }
+    for (int i = 0; i < 6; ++i)
+      if (out->cov) out->cov[6 * g + i] = a.cov[i];
+    for (int i = 0; i < 9; ++i)
+      if (out->evec) out->evec[9 * g + i] = a.evec[i];
+  }
+  return HGMM_OK;
+}
+
+int hgmm_tree_labels(hgmm_tree tree, int index, int32_t* d_labels, void* stream) {
+  if (!tree || !d_labels || index < 0 || index >= (int)tree->trees.size()) return fail(HGMM_EINVAL, "bad argument");
+  if (!tree->has_labels) return fail(HGMM_EINVAL, "this handle has no labels (imported tree)");
+  const TreeHost& th = tree->trees[index];
+  HIP_TRY(hipMemcpyAsync(d_labels, tree->d_labels + th.label_base, sizeof(int32_t) * th.levels * th.n_points,
+                         hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return HGMM_OK;
+}
+
+int hgmm_tree_import(const hgmm_tree_host* in, void* stream, hgmm_tree* out) {
+  if (!in || !out || !in->live || !in->has_children || !in->pi || !in->pig || !in->mu || !in->cov || !in->lam ||
+      !in->evec || !in->kappa)
+    return fail(HGMM_EINVAL, "null pointer argument");
+  if (in->levels < 1 || in->levels > HGMM_MAX_LEVELS) return fail(HGMM_EINVAL, "levels outside [1, 6]");
+  hgmm_forest_s* f = new hgmm_forest_s();
+  (void)hipGetDevice(&f->device);
+  f->trees.assign(1, TreeHost{in->levels, std::max<int64_t>(in->n_points, 1), 0, 0, 0});
+  int rc = setup_forest(f);
+  if (rc) { free_forest(f); return rc; }
+  const int64_t nn = tree_nodes(in->levels);
+  std::vector<NodeD> nd((size_t)nn);
+  for (int64_t g = 0; g < nn; ++g) {
+    NodeD& a = nd[g];
+    memset(&a, 0, sizeof(a));
+    a.live = in->live[g];
+    a.has_children = in->has_children[g];
+    a.count = in->count ? in->count[g] : 0;
+    a.pi = in->pi[g];
+    a.pig = in->pig[g];
+    a.kappa = in->kappa[g];
+    for (int i = 0; i < 3; ++i) { a.mu[i] = in->mu[3 * g + i]; a.lam[i] = in->lam[3 * g + i]; }
+    for (int i = 0; i < 6; ++i) a.cov[i] = in->cov[6 * g + i];
+    for (int i = 0; i < 9; ++i) a.evec[i] = in->evec[9 * g + i];
+  }
+  TreeDev T;
+  memset(&T, 0, sizeof(T));
+  for (int i = 0; i < 3; ++i) T.origin[i] = in->origin[i];
+  T.extent = in->extent;
+  T.levels = in->levels;
+  T.n_points = (int32_t)f->trees[0].n_points;
+  hipStream_t s = (hipStream_t)stream;
+  auto body = [&]() -> int {
+    HIP_TRY(hipMemcpyAsync(f->d_nodes, nd.data(), sizeof(NodeD) * nn, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(f->d_trees, &T, sizeof(TreeDev), hipMemcpyHostToDevice, s));
+    launch_import_nodes(f->d_nodes, f->d_tab, nn, s);
+    HIP_LAUNCHED();
+    HIP_TRY(hipStreamSynchronize(s));
+    return HGMM_OK;
+  };
+  rc = body();
+  if (rc) { free_forest(f); return rc; }
+  f->has_labels = false;
+  *out = f;
+  return HGMM_OK;
+}
+
+void hgmm_tree_destroy(hgmm_tree tree) { free_forest(tree); }
+
+}  // extern "C"

@@ -1,0 +1,51 @@
+// Host-side declarations of the kernel launchers (one translation unit per
+// kernel family; the C ABI in hgmm_api.hip drives them).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hgmm_dev.h"
+
+namespace hgmm {
+
+void launch_fill_u32(void* p, uint32_t v, int64_t n_words, hipStream_t s);
+
+// build
+void launch_root(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles, const Job* jobs,
+                 TreeDev* trees, double* partials, size_t pstride, unsigned* counters, double eps, hipStream_t s);
+void launch_init_children(const Job* jobs, int njobs, const TreeDev* trees, NodeD* nodes, NodeF* tab, double eps,
+                          hipStream_t s);
+void launch_em_tiles(const float* xs, const float* ys, const float* zs, const Tile* tiles, const int* tile_ids,
+                     int n, const Job* jobs, NodeF* tab, NodeD* nodes, double* partials, size_t pstride,
+                     unsigned* counters, double eps, double min_mass, hipStream_t s);
+void launch_em_fused(const float* xs, const float* ys, const float* zs, const int* job_ids, int n, const Job* jobs,
+                     NodeF* tab, NodeD* nodes, int iters, double eps, double min_mass, int cap, hipStream_t s);
+void launch_partition(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
+                      const Job* jobs, const NodeF* tab, const NodeD* nodes, uint8_t* child, int* tile_counts,
+                      hipStream_t s);
+void launch_prefix(const Job* jobs, int njobs, const int* tile_counts, int* tile_base, NodeD* nodes, int2* lvl_info,
+                   hipStream_t s);
+void launch_scatter(const float* xs, const float* ys, const float* zs, const int* perm, const Tile* tiles, int ntiles,
+                    const Job* jobs, const TreeDev* trees, const uint8_t* child, const int* tile_base, float* xo,
+                    float* yo, float* zo, int* perm_out, int32_t* labels, int level, int64_t level_off,
+                    hipStream_t s);
+void launch_finalize_level(const Job* jobs, int njobs, NodeD* nodes, NodeF* tab, hipStream_t s);
+
+// registration
+void launch_set_stop_flags(NodeF* tab, const NodeD* nodes, int64_t n, double lambda_c, hipStream_t s);
+void launch_init_pose(PoseState* st, int npairs, const double* R0, const double* t0, int stride, hipStream_t s);
+void launch_descend(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
+                    const int2* pair_tiles, const TreeDev* trees, const NodeF* tab, const NodeD* nodes,
+                    const PoseState* st, double* bins, double* partials, size_t pstride, unsigned* counters,
+                    int32_t* stop_out, float* gamma_out, hipStream_t s);
+void launch_normal(double* bins, const NodeD* nodes, const TreeDev* trees, PoseState* st, const int64_t* n_moving,
+                   int npairs, double* partials, unsigned* counters, int mode, double tol_rot, double tol_trans_rel,
+                   double* out, hipStream_t s);
+int normal_blocks_per_pair();
+int normal_values();
+
+// import / export
+void launch_import_nodes(NodeD* nodes, NodeF* tab, int64_t n, hipStream_t s);
+
+}  // namespace hgmm

@@ -1,0 +1,496 @@
+// GMM-Tree registration kernels (gfx950).
+//
+// E-step (Sec. 4.1, Algorithm 1): every point of the moving cloud is
+// transformed in FP64, then descends the tree along the most likely child
+// (8 FP32 Mahalanobis scores per level, FP64 re-check of near ties) until the
+// chosen node is simple enough (complexity <= lambda_c), has no live children,
+// or is on the last level.  The point's weight at that node is its posterior
+// among the siblings of the last level visited.  Per-node moments are
+// aggregated across equal stop nodes inside a wavefront and added to FP64
+// bins.
+// M-step (Sec. 4.2, Eq. 8-16): per node with mass, the three eigen-directions
+// contribute weighted point-to-plane rows to 6x6 normal equations; the sums
+// are reduced in a fixed order and the last block solves them by Cholesky and
+// applies the exact rotation of the solved angle vector.
+#include "hgmm_dev.h"
+#include "hgmm_host.h"
+
+namespace hgmm {
+
+__device__ __forceinline__ unsigned ticket_add_r(unsigned* c) {
+  return __hip_atomic_fetch_add(c, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int64_t lvl_off(int l) {
+  // (8^(l+1) - 8) / 7
+  int64_t p = 8;
+  int64_t o = 0;
+  for (int i = 0; i < l; ++i) { o += p; p *= 8; }
+  return o;
+}
+
+__global__ void set_stop_flags_kernel(NodeF* tab, const NodeD* __restrict__ nodes, int64_t n, double lambda_c) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  uint32_t f = tab[g].flags & ~F_STOP;
+  if ((f & F_LIVE) && nodes[g].kappa <= lambda_c) f |= F_STOP;
+  tab[g].flags = f;
+}
+
+// Initial transform of every pair: rows of `stride` doubles (stride 0 = the
+// same transform for all pairs).
+__global__ void init_pose_kernel(PoseState* st, int npairs, const double* __restrict__ R0, const double* __restrict__ t0,
+                                 int stride) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= npairs) return;
+  PoseState& S = st[b];
+  const double* R = R0 + (size_t)stride * b;
+  const double* t = t0 + (size_t)stride * b;
+  for (int i = 0; i < 9; ++i) S.R[i] = R[i];
+  for (int i = 0; i < 3; ++i) S.t[i] = t[i];
+  for (int i = 0; i < 6; ++i) S.x[i] = 0.0;
+  S.loglik = 0.0;
+  S.iters = 0;
+  S.done = 0;
+  S.status = 0;
+}
+
+// Scores of the 8 children at C for p and the most likely live one.
+template <typename NodePtr>
+__device__ __forceinline__ int choose_child(NodePtr C, const NodeD* __restrict__ nodes, int64_t gbase, double p0,
+                                            double p1, double p2, float (&s)[8], float (&q)[8], float (&m)[8],
+                                            uint32_t& livemask) {
+  livemask = 0u;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t f = C[k].flags;
+    if (f & F_LIVE) {
+      livemask |= 1u << k;
+      s[k] = score32(C[k], p0, p1, p2, q[k], m[k]);
+    } else {
+      s[k] = -INFINITY; q[k] = 0.f; m[k] = 0.f;
+    }
+  }
+  int k1 = -1;
+  float s1 = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if ((livemask >> k & 1u) && (k1 < 0 || s[k] > s1)) { s1 = s[k]; k1 = k; }
+  int k2 = -1;
+  float s2 = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if ((livemask >> k & 1u) && k != k1 && (k2 < 0 || s[k] > s2)) { s2 = s[k]; k2 = k; }
+  if (k2 >= 0) {
+    float e1 = 0.f, e2 = 0.f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (k == k1) e1 = score_err(C[k], q[k], m[k]);
+      if (k == k2) e2 = score_err(C[k], q[k], m[k]);
+    }
+    if (s1 - s2 <= 2.f * (e1 + e2)) {
+      double best = -INFINITY;
+      int kb = k1;
+      bool first = true;
+      for (int k = 0; k < 8; ++k) {
+        if (!(livemask >> k & 1u)) continue;
+        double v = score64(nodes[gbase + k], p0, p1, p2);
+        if (first || v > best) { best = v; kb = k; first = false; }
+      }
+      k1 = kb;
+    }
+  }
+  return k1;
+}
+
+constexpr int kLdsNodes = 72;  // levels 0 and 1 of one tree
+
+// One E-step over the tiles of every pair.  tiles[].job is the pair index.
+// Points stopping at the LDS-resident levels (0 and 1) are binned in FP64 LDS
+// accumulators; each block writes them as value-major partials and the last
+// block of the pair folds them in a fixed order.  Deeper stop nodes receive few
+// points each and are added with FP64 atomics.
+__global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
+                                                      const float* __restrict__ zs, const Tile* __restrict__ tiles,
+                                                      const int2* __restrict__ pair_tiles,
+                                                      const TreeDev* __restrict__ trees, const NodeF* __restrict__ tab,
+                                                      const NodeD* __restrict__ nodes, const PoseState* __restrict__ st,
+                                                      double* bins, double* partials, size_t pstride,
+                                                      unsigned* counters, int32_t* stop_out, float* gamma_out) {
+  const Tile tl = tiles[blockIdx.x];
+  const int pair = tl.job;
+  if (st[pair].done) return;
+  const TreeDev& T = trees[pair];
+  const int L = T.levels;
+  const int64_t nb = T.node_base;
+  __shared__ NodeF lds[kLdsNodes];
+  __shared__ double lbin[kLdsNodes * 6];
+  __shared__ unsigned tk;
+  const int nl = L >= 2 ? 72 : 8;
+  for (int i = threadIdx.x; i < nl; i += blockDim.x) {
+    const float4* s = reinterpret_cast<const float4*>(&tab[nb + i]);
+    float4* d = reinterpret_cast<float4*>(&lds[i]);
+    d[0] = s[0]; d[1] = s[1]; d[2] = s[2]; d[3] = s[3];
+  }
+  for (int i = threadIdx.x; i < kLdsNodes * 6; i += blockDim.x) lbin[i] = 0.0;
+  __syncthreads();
+  const double R0 = st[pair].R[0], R1 = st[pair].R[1], R2 = st[pair].R[2], R3 = st[pair].R[3],
+               R4 = st[pair].R[4], R5 = st[pair].R[5], R6 = st[pair].R[6], R7 = st[pair].R[7],
+               R8 = st[pair].R[8], t0 = st[pair].t[0], t1 = st[pair].t[1], t2 = st[pair].t[2];
+  const int lane = __lane_id();
+  for (int b0 = tl.start; b0 < tl.end; b0 += blockDim.x) {
+    const int i = b0 + threadIdx.x;
+    const bool valid = i < tl.end;
+    int64_t g = -1;
+    float gam = 0.f, d0 = 0.f, d1 = 0.f, d2 = 0.f, dm2 = 0.f;
+    if (valid) {
+      const double z0 = xs[i], z1 = ys[i], z2 = zs[i];
+      const double p0 = R0 * z0 + R1 * z1 + R2 * z2 + t0;
+      const double p1 = R3 * z0 + R4 * z1 + R5 * z2 + t1;
+      const double p2 = R6 * z0 + R7 * z1 + R8 * z2 + t2;
+      int parent = 0;
+      float s[8], q[8], m[8];
+      uint32_t lm;
+      for (int l = 0; l < L; ++l) {
+        const int64_t lbase = lvl_off(l) + 8 * (int64_t)parent;
+        int k;
+        uint32_t flags;
+        float err[8];
+        if (l < 2) {
+          const NodeF* C = lds + lbase;
+          k = choose_child(C, nodes, nb + lbase, p0, p1, p2, s, q, m, lm);
+          flags = k >= 0 ? C[k].flags : 0u;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) err[j] = score_err(C[j], q[j], m[j]);
+        } else {
+          const NodeF* C = tab + nb + lbase;
+          k = choose_child(C, nodes, nb + lbase, p0, p1, p2, s, q, m, lm);
+          flags = k >= 0 ? C[k].flags : 0u;
+          if (k >= 0 && ((flags & F_STOP) || !(flags & F_HASCH) || (l == L - 1))) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) err[j] = score_err(C[j], q[j], m[j]);
+          }
+        }
+        if (k < 0) break;  // no live node here: the point is left unassigned
+        const bool stop = (flags & F_STOP) || !(flags & F_HASCH) || (l == L - 1);
+        if (stop) {
+          // weight of the point at the chosen node: its posterior among the
+          // live siblings, gamma = 1 / sum_j 2^(s_j - s_k)
+          float sk = s[0], ek = err[0];
+#pragma unroll
+          for (int j = 1; j < 8; ++j) {
+            sk = (j == k) ? s[j] : sk;
+            ek = (j == k) ? err[j] : ek;
+          }
+          float den = 0.f, bnd = 0.f;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            if (!(lm >> j & 1u)) continue;
+            const float tj = __builtin_amdgcn_exp2f(s[j] - sk);
+            den += tj;
+            if (j != k) bnd = fmaf(tj, err[j] + ek, bnd);
+          }
+          gam = 1.0f / den;
+          // rounding bound of gamma from the FP32 score bounds; above 1e-6
+          // (relative) the sibling scores are recomputed in FP64
+          if (0.6931472f * bnd * gam > 1e-6f) {
+            double s64[8];
+            double skd = 0.0;
+            for (int j = 0; j < 8; ++j) {
+              s64[j] = (lm >> j & 1u) ? score64(nodes[nb + lbase + j], p0, p1, p2) : 0.0;
+              if (j == k) skd = s64[j];
+            }
+            float den64 = 0.f;
+            for (int j = 0; j < 8; ++j)
+              if (lm >> j & 1u) den64 += __builtin_amdgcn_exp2f((float)(s64[j] - skd));
+            gam = 1.0f / den64;
+          }
+          g = nb + lbase + k;
+          break;
+        }
+        parent = 8 * parent + k;
+      }
+      if (g < 0) {
+        if (stop_out) stop_out[i] = -1;
+        if (gamma_out) gamma_out[i] = 0.f;
+      }
+    }
+    if (valid && g >= 0) {
+      const double z0 = xs[i], z1 = ys[i], z2 = zs[i];
+      const double p0 = R0 * z0 + R1 * z1 + R2 * z2 + t0;
+      const double p1 = R3 * z0 + R4 * z1 + R5 * z2 + t1;
+      const double p2 = R6 * z0 + R7 * z1 + R8 * z2 + t2;
+      // offset from the node mean (one FP32 rounding of an FP64 difference) and
+      // the squared Mahalanobis distance in FP64
+      const NodeD& Nd = nodes[g];
+      const double e0 = p0 - Nd.mu[0], e1 = p1 - Nd.mu[1], e2 = p2 - Nd.mu[2];
+      d0 = (float)e0;
+      d1 = (float)e1;
+      d2 = (float)e2;
+      const double w0 = Nd.winv[0] * e0;
+      const double w1 = Nd.winv[1] * e0 + Nd.winv[2] * e1;
+      const double w2 = Nd.winv[3] * e0 + Nd.winv[4] * e1 + Nd.winv[5] * e2;
+      dm2 = (float)(w0 * w0 + w1 * w1 + w2 * w2);
+      if (stop_out) stop_out[i] = (int32_t)(g - nb);
+      if (gamma_out) gamma_out[i] = gam;
+    }
+    // aggregate equal stop nodes inside the wave, then one FP64 atomic per node
+    bool pend = valid && g >= 0;
+    unsigned long long pending = __ballot(pend);
+    while (pending) {
+      const int leader = __ffsll((long long)pending) - 1;
+      const int64_t key = __shfl(g, leader, 64);
+      const bool mine = pend && (g == key);
+      const unsigned long long mm = __ballot(mine);
+      const float v0 = wave_sum(mine ? gam : 0.f);
+      const float v1 = wave_sum(mine ? gam * d0 : 0.f);
+      const float v2 = wave_sum(mine ? gam * d1 : 0.f);
+      const float v3 = wave_sum(mine ? gam * d2 : 0.f);
+      const float v5 = wave_sum(mine ? dm2 : 0.f);
+      if (lane == leader) {
+        const int64_t local = key - nb;
+        double* B = (local < nl) ? lbin + local * 6 : bins + key * 6;
+        unsafeAtomicAdd(B + 0, (double)v0);
+        unsafeAtomicAdd(B + 1, (double)v1);
+        unsafeAtomicAdd(B + 2, (double)v2);
+        unsafeAtomicAdd(B + 3, (double)v3);
+        unsafeAtomicAdd(B + 4, (double)__popcll(mm));
+        unsafeAtomicAdd(B + 5, (double)v5);
+      }
+      pend = pend && !mine;
+      pending &= ~mm;
+    }
+  }
+  __syncthreads();
+  const int2 pt = pair_tiles[pair];  // first tile and tile count of the pair
+  const int slot = blockIdx.x - pt.x;
+  for (int i = threadIdx.x; i < nl * 6; i += blockDim.x) partials[(size_t)i * pstride + pt.x + slot] = lbin[i];
+  __threadfence();
+  if (threadIdx.x == 0) tk = ticket_add_r(&counters[pair]);
+  __syncthreads();
+  if (tk != (unsigned)pt.y - 1) return;
+  __threadfence();
+  // last block of the pair: fixed-order fold of the block partials
+  const int wv = threadIdx.x >> 6;
+  for (int i = wv; i < nl * 6; i += (int)(blockDim.x >> 6)) {
+    const double v = wave_sum_range(partials + (size_t)i * pstride + pt.x, pt.y, lane);
+    if (lane == 0) bins[nb * 6 + i] = v;
+  }
+  if (threadIdx.x == 0) counters[pair] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// M-step
+// ---------------------------------------------------------------------------
+
+constexpr int kNormBlocks = 8;  // blocks per pair
+constexpr int kNV = 28;         // 21 (upper H) + 6 (g) + 1 (log-likelihood numerator)
+
+__device__ inline bool chol6_solve(const double* Hu /*21 upper*/, double shift, const double* g, double* x) {
+  double A[6][6];
+  int idx = 0;
+  for (int i = 0; i < 6; ++i)
+    for (int j = i; j < 6; ++j) { A[i][j] = Hu[idx]; A[j][i] = Hu[idx]; ++idx; }
+  double Lm[6][6];
+  for (int j = 0; j < 6; ++j) {
+    double d = A[j][j] + shift;
+    for (int k = 0; k < j; ++k) d -= Lm[j][k] * Lm[j][k];
+    if (!(d > 0.0)) return false;
+    Lm[j][j] = sqrt(d);
+    for (int i = j + 1; i < 6; ++i) {
+      double v = A[i][j];
+      for (int k = 0; k < j; ++k) v -= Lm[i][k] * Lm[j][k];
+      Lm[i][j] = v / Lm[j][j];
+    }
+  }
+  double y[6];
+  for (int i = 0; i < 6; ++i) {
+    double v = g[i];
+    for (int k = 0; k < i; ++k) v -= Lm[i][k] * y[k];
+    y[i] = v / Lm[i][i];
+  }
+  for (int i = 5; i >= 0; --i) {
+    double v = y[i];
+    for (int k = i + 1; k < 6; ++k) v -= Lm[k][i] * x[k];
+    x[i] = v / Lm[i][i];
+  }
+  return true;
+}
+
+// mode 0: reduce, zero the bins, solve and update the pose.
+// mode 1: reduce only; H, g and the log-likelihood go to out[pair * 28 ..].
+__global__ __launch_bounds__(256) void normal_kernel(double* bins, const NodeD* __restrict__ nodes,
+                                                     const TreeDev* __restrict__ trees, PoseState* st,
+                                                     const int64_t* __restrict__ n_moving, double* partials,
+                                                     unsigned* counters, int mode, double tol_rot,
+                                                     double tol_trans_rel, double* out) {
+  const int pair = blockIdx.x / kNormBlocks;
+  const int chunk = blockIdx.x % kNormBlocks;
+  PoseState& S = st[pair];
+  if (S.done) return;
+  const TreeDev& T = trees[pair];
+  const int64_t nn = lvl_off(T.levels);
+  const int64_t per = (nn + kNormBlocks - 1) / kNormBlocks;
+  const int64_t g0 = T.node_base + chunk * per;
+  const int64_t g1 = T.node_base + min(nn, (chunk + 1) * per);
+  const double N = (double)n_moving[pair];
+  const double o0 = T.origin[0], o1 = T.origin[1], o2 = T.origin[2];
+  double acc[kNV];
+#pragma unroll
+  for (int v = 0; v < kNV; ++v) acc[v] = 0.0;
+  for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
+    double* B = bins + g * 6;
+    const double m0 = B[0];
+    if (!(m0 > 0.0)) continue;
+    const double D0 = B[1], D1 = B[2], D2 = B[3], cnt = B[4], Ls = B[5];
+    if (mode == 0) { B[0] = 0.0; B[1] = 0.0; B[2] = 0.0; B[3] = 0.0; B[4] = 0.0; B[5] = 0.0; }
+    const NodeD& nd = nodes[g];
+    const double pis = m0 / N;
+    const double dl0 = D0 / m0, dl1 = D1 / m0, dl2 = D2 / m0;
+    // mu* relative to the rotation centre
+    const double c0 = nd.mu[0] + dl0 - o0, c1 = nd.mu[1] + dl1 - o1, c2 = nd.mu[2] + dl2 - o2;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const double n0 = nd.evec[3 * l], n1 = nd.evec[3 * l + 1], n2 = nd.evec[3 * l + 2];
+      const double w = pis / nd.lam[l];
+      const double a[6] = {c1 * n2 - c2 * n1, c2 * n0 - c0 * n2, c0 * n1 - c1 * n0, n0, n1, n2};
+      const double r = n0 * dl0 + n1 * dl1 + n2 * dl2;
+      int idx = 0;
+#pragma unroll
+      for (int u = 0; u < 6; ++u) {
+#pragma unroll
+        for (int v = u; v < 6; ++v) { acc[idx] += w * a[u] * a[v]; ++idx; }
+      }
+#pragma unroll
+      for (int u = 0; u < 6; ++u) acc[21 + u] -= w * a[u] * r;
+    }
+    acc[27] += cnt * (log(nd.pig) - 0.5 * nd.logdet) - 0.5 * Ls;
+  }
+  __shared__ double red[4][kNV];
+  __shared__ unsigned tk;
+  const int lane = __lane_id(), wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < kNV; ++v) {
+    double s = wave_sum_d(acc[v]);
+    if (lane == 0) red[wv][v] = s;
+  }
+  __syncthreads();
+  double* P = partials + (size_t)blockIdx.x * kNV;
+  if (threadIdx.x < kNV) P[threadIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+  __threadfence();
+  if (threadIdx.x == 0) tk = ticket_add_r(&counters[pair]);
+  __syncthreads();
+  if (tk != (unsigned)kNormBlocks - 1) return;
+  __threadfence();
+  __shared__ double tot[kNV];
+  if (threadIdx.x < kNV) {
+    double s = 0.0;
+    for (int c = 0; c < kNormBlocks; ++c) s += partials[(size_t)(pair * kNormBlocks + c) * kNV + threadIdx.x];
+    tot[threadIdx.x] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  counters[pair] = 0;
+  const double ll = tot[27] / N - 1.5 * kLog2Pi;
+  if (mode == 1) {
+    for (int v = 0; v < kNV; ++v) out[pair * kNV + v] = tot[v];
+    out[pair * kNV + 27] = ll;
+    return;
+  }
+  S.loglik = ll;
+  S.iters += 1;
+  double x[6];
+  bool ok = chol6_solve(tot, 0.0, tot + 21, x);
+  if (!ok) {
+    double tr = tot[0] + tot[6] + tot[11] + tot[15] + tot[18] + tot[20];
+    ok = (tr > 0.0) && chol6_solve(tot, 1e-12 * tr, tot + 21, x);
+  }
+  if (!ok) {
+    S.status = -6;
+    S.done = 1;
+    return;
+  }
+  for (int i = 0; i < 6; ++i) S.x[i] = x[i];
+  // exact rotation of the angle vector omega (Rodrigues), composed on the left
+  const double w0 = x[0], w1 = x[1], w2 = x[2];
+  const double th = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+  double A, Bc;
+  if (th < 1e-12) { A = 1.0; Bc = 0.0; }
+  else { A = sin(th) / th; Bc = (1.0 - cos(th)) / (th * th); }
+  const double K[9] = {0, -w2, w1, w2, 0, -w0, -w1, w0, 0};
+  double Ri[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double k2 = K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j] + K[3 * i + 2] * K[6 + j];
+      Ri[3 * i + j] = (i == j ? 1.0 : 0.0) + A * K[3 * i + j] + Bc * k2;
+    }
+  double Rn[9], tn[3];
+  const double dt0 = S.t[0] - o0, dt1 = S.t[1] - o1, dt2 = S.t[2] - o2;
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) Rn[3 * i + j] = Ri[3 * i] * S.R[j] + Ri[3 * i + 1] * S.R[3 + j] + Ri[3 * i + 2] * S.R[6 + j];
+    tn[i] = Ri[3 * i] * dt0 + Ri[3 * i + 1] * dt1 + Ri[3 * i + 2] * dt2 + T.origin[i] + x[3 + i];
+  }
+  for (int i = 0; i < 9; ++i) S.R[i] = Rn[i];
+  for (int i = 0; i < 3; ++i) S.t[i] = tn[i];
+  const double tau = sqrt(x[3] * x[3] + x[4] * x[4] + x[5] * x[5]);
+  if (th < tol_rot && tau < tol_trans_rel * T.extent) S.done = 1;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+
+void launch_set_stop_flags(NodeF* tab, const NodeD* nodes, int64_t n, double lambda_c, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(set_stop_flags_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tab, nodes, n, lambda_c);
+}
+
+void launch_init_pose(PoseState* st, int npairs, const double* R0, const double* t0, int stride, hipStream_t s) {
+  hipLaunchKernelGGL(init_pose_kernel, dim3((npairs + 63) / 64), dim3(64), 0, s, st, npairs, R0, t0, stride);
+}
+
+// Scoring records of an imported tree.
+__global__ void import_nodes_kernel(NodeD* nodes, NodeF* tab, int64_t n) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  NodeD& a = nodes[g];
+  NodeF nf;
+  NodeD tmp;
+  uint32_t flags = 0u;
+  if (a.live && make_node(a.mu, a.cov, a.pi, tmp, nf)) {
+    for (int i = 0; i < 6; ++i) a.winv[i] = tmp.winv[i];
+    a.c = tmp.c;
+    a.logdet = tmp.logdet;
+    flags = F_LIVE | (a.has_children ? F_HASCH : 0u);
+  } else {
+    a.live = 0;
+    nf = NodeF{};
+  }
+  nf.flags = flags;
+  tab[g] = nf;
+}
+
+void launch_import_nodes(NodeD* nodes, NodeF* tab, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(import_nodes_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nodes, tab, n);
+}
+
+void launch_descend(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
+                    const int2* pair_tiles, const TreeDev* trees, const NodeF* tab, const NodeD* nodes,
+                    const PoseState* st, double* bins, double* partials, size_t pstride, unsigned* counters,
+                    int32_t* stop_out, float* gamma_out, hipStream_t s) {
+  hipLaunchKernelGGL(descend_kernel, dim3(ntiles), dim3(256), 0, s, xs, ys, zs, tiles, pair_tiles, trees, tab, nodes,
+                     st, bins, partials, pstride, counters, stop_out, gamma_out);
+}
+
+void launch_normal(double* bins, const NodeD* nodes, const TreeDev* trees, PoseState* st, const int64_t* n_moving,
+                   int npairs, double* partials, unsigned* counters, int mode, double tol_rot, double tol_trans_rel,
+                   double* out, hipStream_t s) {
+  hipLaunchKernelGGL(normal_kernel, dim3(npairs * kNormBlocks), dim3(256), 0, s, bins, nodes, trees, st, n_moving,
+                     partials, counters, mode, tol_rot, tol_trans_rel, out);
+}
+
+int normal_blocks_per_pair() { return kNormBlocks; }
+int normal_values() { return kNV; }
+
+}  // namespace hgmm
