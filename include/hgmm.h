@@ -167,6 +167,82 @@ int hgmm_estep(hgmm_tree tree, const float *d_xyz, int64_t n, const double R[9],
 int hgmm_normal_equations(hgmm_tree tree, const double *d_bins, int64_t n, void *d_ws, size_t ws_bytes,
                           void *stream, double H[36], double g[6]);
 
+/* ---- batched form: many uneven clouds in one call ----------------------
+ * Clouds are concatenated CSR-style into one SoA buffer of offsets[B] points
+ * (x[total], y[total], z[total]); cloud b occupies [offsets[b], offsets[b+1])
+ * (offsets and levels are host arrays, offsets[0] = 0).  Every level of every
+ * tree is fitted by the same kernel launches; the forest handle holds B trees
+ * (tree b built from cloud b with levels[b] levels; p->levels is ignored).
+ * hgmm_register_batch registers target cloud b onto tree b of the forest
+ * (same CSR layout, its own offsets), starting from R0[9 b..], t0[3 b..]
+ * (host, nullable = identity); active (host, nullable) skips pairs whose
+ * flag is 0 (their outputs are R0, t0 and 0 iterations).  Returns per pair R (B x 9), t (B x 3),
+ * iters, loglik (nullable) and status (nullable; with status NULL a singular
+ * pair makes the call return HGMM_ESINGULAR).  Both synchronise `stream`. */
+size_t hgmm_build_batch_workspace_bytes(const int64_t *offsets, const int32_t *levels, int B);
+int hgmm_build_batch(const float *d_xyz, const int64_t *offsets, const int32_t *levels, int B,
+                     const hgmm_build_params *p, void *d_ws, size_t ws_bytes, void *stream, hgmm_tree *forest);
+size_t hgmm_register_batch_workspace_bytes(hgmm_tree forest, const int64_t *offsets, int B);
+int hgmm_register_batch(hgmm_tree forest, const float *d_xyz, const int64_t *offsets, int B,
+                        const hgmm_reg_params *p, const double *R0, const double *t0, const int32_t *active,
+                        void *d_ws, size_t ws_bytes, void *stream, double *R, double *t, int *iters, double *loglik,
+                        int *status);
+/* Mean log-likelihood of every target cloud at a fixed transform (R: B x 9,
+ * t: B x 3, host): one E-step (Algorithm 1) per pair. */
+int hgmm_estep_batch(hgmm_tree forest, const float *d_xyz, const int64_t *offsets, int B, const double *R,
+                     const double *t, double lambda_c, void *d_ws, size_t ws_bytes, void *stream, double *loglik);
+
+/* ---- learned warm start ---------------------------------------------------
+ * Not part of the paper: a small network that maps the coarse GMMs of both
+ * clouds to an initial transform for hgmm_register / hgmm_register_batch.
+ *
+ * Features (hgmm_warm_features): for each listed tree, the 64 nodes of level 1
+ * as (global weight, mean (3), upper covariance xx xy xz yy yz zz (6)) in the
+ * cloud's canonical frame u = E (p - c) / s, where c is the cloud mean, s its
+ * RMS radius and E the principal axes of the root covariance (rows, sign rule
+ * of the node eigenvectors, last row negated if det E < 0).  Dead nodes are
+ * zero.  d_feat receives n x 640 floats, d_frames n x 13 doubles (E row-major,
+ * c, s); all device memory.  Synchronises `stream`.
+ *
+ * Network (hgmm_mlp): 1280 -> 512 -> 512 -> 512 -> 9, exact GELU after the
+ * hidden layers; bf16 weights and activations into v_mfma_f32_16x16x32_bf16
+ * with FP32 accumulation, FP32 biases, FP32 master weights and Adam state.
+ * Input row = [source 640 | target 640] FP32 (converted to bf16 inside);
+ * output row = [first two columns of Rc (6), tc (3)] where Rc, tc map target
+ * canonical coordinates to source canonical coordinates.  Parameters are
+ * flattened W1 b1 W2 b2 W3 b3 W4 b4 with W_l row-major [in x out]
+ * (hgmm_mlp_param_count() floats).  The loss of a row against target T is
+ * sum_c w_c (y_c - T_c)^2 / 2 with w = 1 on the 6D part and trans_weight on
+ * the translation, averaged over rows.
+ *
+ * hgmm_warm_head_pose turns rows into transforms (Gram-Schmidt on the 6D
+ * part, composed with the two frames): d_R0 (P x 9), d_t0 (P x 3) doubles;
+ * hgmm_warm_head_target is its inverse for training targets. */
+typedef struct hgmm_mlp_s *hgmm_mlp;
+int64_t hgmm_mlp_param_count(void);
+int hgmm_mlp_create(uint64_t seed, hgmm_mlp *out);
+void hgmm_mlp_destroy(hgmm_mlp mlp);
+int hgmm_mlp_get_params(hgmm_mlp mlp, float *host_params);
+int hgmm_mlp_set_params(hgmm_mlp mlp, const float *host_params);
+int hgmm_mlp_forward(hgmm_mlp mlp, const float *d_X, int P, float *d_Y, void *stream);
+/* One Adam step (lr, beta 0.9 / 0.999, eps 1e-8) on rows d_X against d_T;
+ * *loss (nullable, host) is the mean loss before the step. */
+int hgmm_mlp_train_step(hgmm_mlp mlp, const float *d_X, const float *d_T, int P, float lr, float trans_weight,
+                        void *stream, double *loss);
+/* Forward + backward only; host_grads (nullable) receives the parameter
+ * gradients in the flattened layout. */
+int hgmm_mlp_backward(hgmm_mlp mlp, const float *d_X, const float *d_T, int P, float trans_weight, void *stream,
+                      float *host_grads, double *loss);
+int hgmm_warm_features(hgmm_tree forest, const int32_t *h_tree_ids, int n, double reg_eps, float *d_feat,
+                       double *d_frames, void *stream);
+int hgmm_warm_head_pose(const float *d_Y, const double *d_fr_src, const double *d_fr_tgt, int P, double *d_R0,
+                        double *d_t0, void *stream);
+int hgmm_warm_head_target(const double *d_R, const double *d_t, const double *d_fr_src, const double *d_fr_tgt, int P,
+                          float *d_T, void *stream);
+/* C = op(A) op(B) on the MLP's bf16 MFMA GEMM (A, B raw bf16, C FP32). */
+int hgmm_gemm_bf16(int ta, int tb, int M, int N, int K, const uint16_t *d_A, int lda, const uint16_t *d_B, int ldb,
+                   float *d_C, int ldc, void *stream);
+
 /* FP64 host copy of tree `index` of the forest (all arrays caller-allocated). */
 int hgmm_tree_export(hgmm_tree tree, int index, hgmm_tree_host *out);
 /* Per-point node labels of tree `index`: d_labels[l * n_points + i] is the

@@ -10,6 +10,14 @@ from .api import (  # noqa: F401
     Workspace,
     hgmm_build,
     hgmm_register,
+    hgmm_build_batch,
+    hgmm_register_batch,
+    hgmm_estep_batch,
+    MLP,
+    hgmm_warm_features,
+    hgmm_warm_head_pose,
+    hgmm_warm_head_target,
+    hgmm_gemm_bf16,
     hgmm_estep,
     hgmm_normal_equations,
     hgmm_tree_import,

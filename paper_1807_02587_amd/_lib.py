@@ -46,6 +46,24 @@ SIGNATURES = {
     "hgmm_tree_info": (C.c_int, [P, C.c_int, P, P, P, P]),
     "hgmm_tree_destroy": (None, [P]),
     "hgmm_set_tuning": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
+    "hgmm_build_batch_workspace_bytes": (C.c_size_t, [P, P, C.c_int]),
+    "hgmm_build_batch": (C.c_int, [P, P, P, C.c_int, P, P, C.c_size_t, P, P]),
+    "hgmm_register_batch_workspace_bytes": (C.c_size_t, [P, P, C.c_int]),
+    "hgmm_register_batch": (C.c_int, [P, P, P, C.c_int, P, P, P, P, P, C.c_size_t, P, P, P, P, P, P]),
+    "hgmm_estep_batch": (C.c_int, [P, P, P, C.c_int, P, P, D, P, C.c_size_t, P, P]),
+    "hgmm_mlp_param_count": (I64, []),
+    "hgmm_mlp_create": (C.c_int, [C.c_uint64, P]),
+    "hgmm_mlp_destroy": (None, [P]),
+    "hgmm_mlp_get_params": (C.c_int, [P, P]),
+    "hgmm_mlp_set_params": (C.c_int, [P, P]),
+    "hgmm_mlp_forward": (C.c_int, [P, P, C.c_int, P, P]),
+    "hgmm_mlp_train_step": (C.c_int, [P, P, P, C.c_int, C.c_float, C.c_float, P, P]),
+    "hgmm_mlp_backward": (C.c_int, [P, P, P, C.c_int, C.c_float, P, P, P]),
+    "hgmm_warm_features": (C.c_int, [P, P, C.c_int, D, P, P, P]),
+    "hgmm_warm_head_pose": (C.c_int, [P, P, P, C.c_int, P, P, P]),
+    "hgmm_warm_head_target": (C.c_int, [P, P, P, P, C.c_int, P, P]),
+    "hgmm_gemm_bf16": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, P, C.c_int, P, C.c_int, P,
+                                 C.c_int, P]),
     "hgmm_profile": (C.c_int, [C.c_int]),
     "hgmm_profile_reset": (None, []),
     "hgmm_profile_read": (C.c_int, [C.c_int, P, P, P]),

@@ -231,3 +231,170 @@ def hgmm_profile_read(kind) -> dict:
     u = C.c_double(0)
     check(_lib.load().hgmm_profile_read(k, C.byref(ms), C.byref(n), C.byref(u)), "hgmm_profile_read")
     return dict(ms=ms.value, launches=n.value, units=u.value)
+
+
+def hgmm_build_batch(xyz: torch.Tensor, offsets, levels, build_iters: int = 30, reg_eps: float = 1e-6,
+                     min_mass: float = 1.0, ws: Workspace | None = None, forest: Tree | None = None,
+                     stream=None) -> Tree:
+    """Forest of len(levels) trees from CSR-concatenated clouds (SoA (3, total))."""
+    xyz = _cloud(xyz)
+    lib = _lib.load()
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    lev = np.ascontiguousarray(np.asarray(levels, dtype=np.int32))
+    B = len(lev)
+    assert off.shape == (B + 1,) and off[-1] == xyz.shape[1]
+    p = BuildParams(int(lev.max()), build_iters, reg_eps, min_mass)
+    ws = ws or Workspace(xyz.device)
+    wptr, wlen = ws.ptr(lib.hgmm_build_batch_workspace_bytes(off.ctypes.data_as(C.c_void_p),
+                                                             lev.ctypes.data_as(C.c_void_p), B))
+    h = C.c_void_p(forest.handle.value if forest is not None else None)
+    check(lib.hgmm_build_batch(C.c_void_p(xyz.data_ptr()), off.ctypes.data_as(C.c_void_p),
+                               lev.ctypes.data_as(C.c_void_p), B, C.byref(p), wptr, wlen, _stream(stream),
+                               C.byref(h)), "hgmm_build_batch")
+    if forest is not None:
+        forest.handle, forest.n_points, forest.levels, forest.ntrees = h, int(off[-1]), int(lev.max()), B
+        forest.offsets, forest.tree_levels = off, lev
+        return forest
+    t = Tree(h, int(off[-1]), int(lev.max()), B)
+    t.offsets, t.tree_levels = off, lev
+    return t
+
+
+def hgmm_register_batch(forest: Tree, xyz: torch.Tensor, offsets, max_iters: int = 30, lambda_c: float = 0.01,
+                        tol_rot: float = 1e-6, tol_trans_rel: float = 1e-6, R0=None, t0=None, active=None,
+                        ws: Workspace | None = None, stream=None) -> dict:
+    xyz = _cloud(xyz)
+    lib = _lib.load()
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    B = len(off) - 1
+    p = RegParams(max_iters, 0, lambda_c, tol_rot, tol_trans_rel)
+    R0a = None if R0 is None else np.ascontiguousarray(np.asarray(R0, dtype=np.float64).reshape(B, 9))
+    t0a = None if t0 is None else np.ascontiguousarray(np.asarray(t0, dtype=np.float64).reshape(B, 3))
+    ws = ws or Workspace(xyz.device)
+    wptr, wlen = ws.ptr(lib.hgmm_register_batch_workspace_bytes(forest.handle, off.ctypes.data_as(C.c_void_p), B))
+    R = np.zeros((B, 9))
+    t = np.zeros((B, 3))
+    iters = np.zeros(B, np.int32)
+    ll = np.zeros(B)
+    st = np.zeros(B, np.int32)
+    act = None if active is None else np.ascontiguousarray(np.asarray(active, dtype=np.int32))
+    check(lib.hgmm_register_batch(forest.handle, C.c_void_p(xyz.data_ptr()), off.ctypes.data_as(C.c_void_p), B,
+                                  C.byref(p), None if R0a is None else R0a.ctypes.data_as(C.c_void_p),
+                                  None if t0a is None else t0a.ctypes.data_as(C.c_void_p),
+                                  None if act is None else act.ctypes.data_as(C.c_void_p), wptr, wlen,
+                                  _stream(stream), R.ctypes.data_as(C.c_void_p), t.ctypes.data_as(C.c_void_p),
+                                  iters.ctypes.data_as(C.c_void_p), ll.ctypes.data_as(C.c_void_p),
+                                  st.ctypes.data_as(C.c_void_p)), "hgmm_register_batch")
+    return dict(R=R.reshape(B, 3, 3), t=t, iters=iters, loglik=ll, status=st)
+
+
+def hgmm_estep_batch(forest: Tree, xyz: torch.Tensor, offsets, R, t, lambda_c: float = 0.01,
+                     ws: Workspace | None = None, stream=None) -> np.ndarray:
+    """Mean log-likelihood per pair at fixed transforms R (B,3,3), t (B,3)."""
+    xyz = _cloud(xyz)
+    lib = _lib.load()
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    B = len(off) - 1
+    Ra = np.ascontiguousarray(np.asarray(R, dtype=np.float64).reshape(B, 9))
+    ta = np.ascontiguousarray(np.asarray(t, dtype=np.float64).reshape(B, 3))
+    ws = ws or Workspace(xyz.device)
+    wptr, wlen = ws.ptr(lib.hgmm_register_batch_workspace_bytes(forest.handle, off.ctypes.data_as(C.c_void_p), B))
+    ll = np.zeros(B)
+    check(lib.hgmm_estep_batch(forest.handle, C.c_void_p(xyz.data_ptr()), off.ctypes.data_as(C.c_void_p), B,
+                               Ra.ctypes.data_as(C.c_void_p), ta.ctypes.data_as(C.c_void_p), lambda_c, wptr, wlen,
+                               _stream(stream), ll.ctypes.data_as(C.c_void_p)), "hgmm_estep_batch")
+    return ll
+
+
+class MLP:
+    """Owning wrapper of an hgmm_mlp handle (the warm-start network)."""
+
+    def __init__(self, seed: int = 0):
+        self.lib = _lib.load()
+        self.handle = C.c_void_p(None)
+        check(self.lib.hgmm_mlp_create(C.c_uint64(seed), C.byref(self.handle)), "hgmm_mlp_create")
+        self.n_params = int(self.lib.hgmm_mlp_param_count())
+
+    def __del__(self):
+        try:
+            if self.handle is not None and self.handle.value:
+                self.lib.hgmm_mlp_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, np.float32)
+        check(self.lib.hgmm_mlp_get_params(self.handle, out.ctypes.data_as(C.c_void_p)), "hgmm_mlp_get_params")
+        return out
+
+    def set_params(self, params) -> None:
+        a = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        assert a.shape == (self.n_params,)
+        check(self.lib.hgmm_mlp_set_params(self.handle, a.ctypes.data_as(C.c_void_p)), "hgmm_mlp_set_params")
+
+    def forward(self, X: torch.Tensor, stream=None) -> torch.Tensor:
+        assert X.is_cuda and X.dtype == torch.float32 and X.is_contiguous() and X.shape[1] == 1280
+        Y = torch.empty((X.shape[0], 9), dtype=torch.float32, device=X.device)
+        check(self.lib.hgmm_mlp_forward(self.handle, C.c_void_p(X.data_ptr()), X.shape[0], C.c_void_p(Y.data_ptr()),
+                                        _stream(stream)), "hgmm_mlp_forward")
+        return Y
+
+    def train_step(self, X: torch.Tensor, T: torch.Tensor, lr: float, trans_weight: float = 1.0,
+                   want_loss: bool = True, stream=None):
+        loss = C.c_double(0)
+        check(self.lib.hgmm_mlp_train_step(self.handle, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+                                           X.shape[0], C.c_float(lr), C.c_float(trans_weight), _stream(stream),
+                                           C.byref(loss) if want_loss else None), "hgmm_mlp_train_step")
+        return loss.value if want_loss else None
+
+    def backward(self, X: torch.Tensor, T: torch.Tensor, trans_weight: float = 1.0, stream=None):
+        g = np.zeros(self.n_params, np.float32)
+        loss = C.c_double(0)
+        check(self.lib.hgmm_mlp_backward(self.handle, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+                                         X.shape[0], C.c_float(trans_weight), _stream(stream),
+                                         g.ctypes.data_as(C.c_void_p), C.byref(loss)), "hgmm_mlp_backward")
+        return g, loss.value
+
+
+def hgmm_warm_features(forest: Tree, tree_ids, reg_eps: float = 1e-6, stream=None):
+    """(features (n, 640) float32 CUDA, frames (n, 13) float64 CUDA) of the listed trees."""
+    ids = np.ascontiguousarray(np.asarray(tree_ids, dtype=np.int32))
+    n = len(ids)
+    feat = torch.empty((n, 640), dtype=torch.float32, device="cuda")
+    fr = torch.empty((n, 13), dtype=torch.float64, device="cuda")
+    check(_lib.load().hgmm_warm_features(forest.handle, ids.ctypes.data_as(C.c_void_p), n, reg_eps,
+                                         C.c_void_p(feat.data_ptr()), C.c_void_p(fr.data_ptr()), _stream(stream)),
+          "hgmm_warm_features")
+    return feat, fr
+
+
+def hgmm_warm_head_pose(Y: torch.Tensor, fr_src: torch.Tensor, fr_tgt: torch.Tensor, stream=None):
+    P = Y.shape[0]
+    R0 = torch.empty((P, 9), dtype=torch.float64, device="cuda")
+    t0 = torch.empty((P, 3), dtype=torch.float64, device="cuda")
+    check(_lib.load().hgmm_warm_head_pose(C.c_void_p(Y.data_ptr()), C.c_void_p(fr_src.data_ptr()),
+                                          C.c_void_p(fr_tgt.data_ptr()), P, C.c_void_p(R0.data_ptr()),
+                                          C.c_void_p(t0.data_ptr()), _stream(stream)), "hgmm_warm_head_pose")
+    return R0, t0
+
+
+def hgmm_warm_head_target(R: torch.Tensor, t: torch.Tensor, fr_src: torch.Tensor, fr_tgt: torch.Tensor, stream=None):
+    P = R.shape[0]
+    T = torch.empty((P, 9), dtype=torch.float32, device="cuda")
+    check(_lib.load().hgmm_warm_head_target(C.c_void_p(R.data_ptr()), C.c_void_p(t.data_ptr()),
+                                            C.c_void_p(fr_src.data_ptr()), C.c_void_p(fr_tgt.data_ptr()), P,
+                                            C.c_void_p(T.data_ptr()), _stream(stream)), "hgmm_warm_head_target")
+    return T
+
+
+def hgmm_gemm_bf16(A_bits: torch.Tensor, B_bits: torch.Tensor, M, N, K, ta=False, tb=False, lda=None, ldb=None,
+                   stream=None) -> torch.Tensor:
+    """C = op(A) op(B) with raw bf16 operands (int16 tensors holding bf16 bit patterns)."""
+    lda = lda if lda is not None else (M if ta else K)
+    ldb = ldb if ldb is not None else (K if tb else N)
+    Cm = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    check(_lib.load().hgmm_gemm_bf16(int(ta), int(tb), M, N, K, C.c_void_p(A_bits.data_ptr()), lda,
+                                     C.c_void_p(B_bits.data_ptr()), ldb, C.c_void_p(Cm.data_ptr()), N,
+                                     _stream(stream)), "hgmm_gemm_bf16")
+    return Cm

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhgmm.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["build_kernels.hip", "register_kernels.hip", "warm_kernels.hip", "batch_tuner.hip", "hgmm_api.hip"]
+SOURCES = ["build_kernels.hip", "register_kernels.hip", "warm_kernels.hip", "mlp_api.hip", "hgmm_api.hip"]
 ARCH = "gfx950"
 
 

@@ -35,10 +35,6 @@ void launch_fill_u32(void* p, uint32_t v, int64_t n_words, hipStream_t s) {
   hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, v, n_words);
 }
 
-__device__ __forceinline__ unsigned ticket_add(unsigned* c) {
-  return __hip_atomic_fetch_add(c, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __device__ __forceinline__ void copy_nodef(NodeF& dst, const NodeF& src) {
   const float4* s = reinterpret_cast<const float4*>(&src);
   float4* d = reinterpret_cast<float4*>(&dst);
@@ -51,8 +47,7 @@ __device__ __forceinline__ void copy_nodef(NodeF& dst, const NodeF& src) {
 
 __global__ __launch_bounds__(64) void root_mean_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
                                                        const float* __restrict__ zs, const Tile* __restrict__ tiles,
-                                                       const Job* __restrict__ jobs, TreeDev* trees,
-                                                       double* partials, size_t pstride, unsigned* counters) {
+                                                       double* partials, size_t pstride) {
   const Tile tl = tiles[blockIdx.x];
   const int lane = threadIdx.x;
   double s0 = 0, s1 = 0, s2 = 0;
@@ -65,7 +60,7 @@ __global__ __launch_bounds__(64) void root_mean_kernel(const float* __restrict__
     lo0 = fminf(lo0, x); lo1 = fminf(lo1, y); lo2 = fminf(lo2, z);
     hi0 = fmaxf(hi0, x); hi1 = fmaxf(hi1, y); hi2 = fmaxf(hi2, z);
   }
-  s0 = wave_sum_d(s0); s1 = wave_sum_d(s1); s2 = wave_sum_d(s2);
+  s0 = wave_sum_dd(s0); s1 = wave_sum_dd(s1); s2 = wave_sum_dd(s2);
   for (int m = 32; m >= 1; m >>= 1) {
     lo0 = fminf(lo0, __shfl_xor(lo0, m, 64)); lo1 = fminf(lo1, __shfl_xor(lo1, m, 64));
     lo2 = fminf(lo2, __shfl_xor(lo2, m, 64)); hi0 = fmaxf(hi0, __shfl_xor(hi0, m, 64));
@@ -77,14 +72,13 @@ __global__ __launch_bounds__(64) void root_mean_kernel(const float* __restrict__
                              (double)hi2, (double)bad};
     for (int v = 0; v < 10; ++v) partials[(size_t)v * pstride + blockIdx.x] = vals[v];
   }
-  __threadfence();
-  __shared__ unsigned tk;
-  const Job jb = jobs[tl.job];
-  if (lane == 0) tk = ticket_add(&counters[tl.job]);
-  __syncthreads();
-  if (tk != (unsigned)jb.ntiles - 1) return;
-  __threadfence();
-  // the last tile of the tree folds all tile partials (lanes stride over tiles)
+}
+
+// One wave per tree: fixed-order fold of the root-mean tile partials.
+__global__ __launch_bounds__(64) void root_mean_fold_kernel(const Job* __restrict__ jobs, TreeDev* trees,
+                                                            const double* __restrict__ partials, size_t pstride) {
+  const Job jb = jobs[blockIdx.x];
+  const int lane = threadIdx.x;
   const double a0 = wave_sum_range(partials + 0 * pstride + jb.tile_first, jb.ntiles, lane);
   const double a1 = wave_sum_range(partials + 1 * pstride + jb.tile_first, jb.ntiles, lane);
   const double a2 = wave_sum_range(partials + 2 * pstride + jb.tile_first, jb.ntiles, lane);
@@ -107,14 +101,13 @@ __global__ __launch_bounds__(64) void root_mean_kernel(const float* __restrict__
     T.origin[0] = a0 / n; T.origin[1] = a1 / n; T.origin[2] = a2 / n;
     T.extent = sqrt((h0 - l0) * (h0 - l0) + (h1 - l1) * (h1 - l1) + (h2 - l2) * (h2 - l2));
     if (b > 0) T.status = -3;
-    counters[tl.job] = 0;
   }
 }
 
 __global__ __launch_bounds__(64) void root_cov_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
                                                       const float* __restrict__ zs, const Tile* __restrict__ tiles,
-                                                      const Job* __restrict__ jobs, TreeDev* trees, double* partials,
-                                                      size_t pstride, unsigned* counters, double eps) {
+                                                      const Job* __restrict__ jobs, const TreeDev* __restrict__ trees,
+                                                      double* partials, size_t pstride) {
   const Tile tl = tiles[blockIdx.x];
   const Job jb = jobs[tl.job];
   const int lane = threadIdx.x;
@@ -124,18 +117,19 @@ __global__ __launch_bounds__(64) void root_cov_kernel(const float* __restrict__ 
     double d0 = (double)xs[i] - o0, d1 = (double)ys[i] - o1, d2 = (double)zs[i] - o2;
     c[0] += d0 * d0; c[1] += d0 * d1; c[2] += d0 * d2; c[3] += d1 * d1; c[4] += d1 * d2; c[5] += d2 * d2;
   }
-  for (int k = 0; k < 6; ++k) c[k] = wave_sum_d(c[k]);
+  for (int k = 0; k < 6; ++k) c[k] = wave_sum_dd(c[k]);
   if (lane < 6) {
     double v = c[0];
     for (int k = 1; k < 6; ++k) v = (lane == k) ? c[k] : v;
     partials[(size_t)lane * pstride + blockIdx.x] = v;
   }
-  __threadfence();
-  __shared__ unsigned tk;
-  if (lane == 0) tk = ticket_add(&counters[tl.job]);
-  __syncthreads();
-  if (tk != (unsigned)jb.ntiles - 1) return;
-  __threadfence();
+}
+
+__global__ __launch_bounds__(64) void root_cov_fold_kernel(const Job* __restrict__ jobs, TreeDev* trees,
+                                                           const double* __restrict__ partials, size_t pstride,
+                                                           double eps) {
+  const Job jb = jobs[blockIdx.x];
+  const int lane = threadIdx.x;
   double a[6];
   for (int k = 0; k < 6; ++k) a[k] = wave_sum_range(partials + k * pstride + jb.tile_first, jb.ntiles, lane);
   if (lane == 0) {
@@ -144,7 +138,6 @@ __global__ __launch_bounds__(64) void root_cov_kernel(const float* __restrict__ 
     for (int k = 0; k < 6; ++k) T.root_cov[k] = a[k] / n;
     T.root_cov[0] += eps; T.root_cov[3] += eps; T.root_cov[5] += eps;
     eig_sym3(T.root_cov, T.root_lam, T.root_evec);
-    counters[tl.job] = 0;
   }
 }
 
@@ -318,21 +311,19 @@ __device__ __forceinline__ uint32_t live_mask(const NodeF* ch) {
   return m;
 }
 
-// One EM iteration for the tiles of the large jobs; the last tile of each job
-// performs the M-step.
+// One EM iteration over the tiles of the large jobs: FP64 tile partials of the
+// 80 moment sums, stored value-major (partials[v * pstride + tile]).
 __global__ __launch_bounds__(64) void em_tile_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
                                                      const float* __restrict__ zs, const Tile* __restrict__ tiles,
                                                      const int* __restrict__ tile_ids, const Job* __restrict__ jobs,
-                                                     NodeF* tab, NodeD* nodes, double* partials, size_t pstride,
-                                                     unsigned* counters, double eps, double min_mass) {
+                                                     const NodeF* __restrict__ tab, double* partials,
+                                                     size_t pstride) {
   const int tid = tile_ids[blockIdx.x];
   const Tile tl = tiles[tid];
   const Job jb = jobs[tl.job];
   const int lane = threadIdx.x;
   __shared__ NodeF ch[8];
   __shared__ float red[80];
-  __shared__ double tot[80];
-  __shared__ unsigned tk;
   if (lane < 8) copy_nodef(ch[lane], tab[jb.child_base + lane]);
   __syncthreads();
   const uint32_t live = live_mask(ch);
@@ -340,31 +331,26 @@ __global__ __launch_bounds__(64) void em_tile_kernel(const float* __restrict__ x
   em_range(xs, ys, zs, tl.start, tl.end, lane, ch, live, a);
   wave_reduce80(a, red, lane);
   __syncthreads();
-  // tile partials are stored value-major: partials[v * pstride + tile]
   partials[(size_t)lane * pstride + tid] = red[lane];
   if (lane < 16) partials[(size_t)(64 + lane) * pstride + tid] = red[64 + lane];
-  __threadfence();
-  if (lane == 0) tk = ticket_add(&counters[tl.job]);
-  __syncthreads();
-  if (tk != (unsigned)jb.ntiles - 1) return;
-  __threadfence();
-  // last tile of the job: fixed-order FP64 combination of the tile partials,
-  // the lanes striding over the job's tiles
-  if (jb.ntiles <= 64) {
-    for (int v = 0; v < 80; ++v) {
-      const double x = lane < jb.ntiles ? partials[(size_t)v * pstride + jb.tile_first + lane] : 0.0;
-      const double t = wave_sum_dd(x);
-      if (lane == 0) tot[v] = t;
-    }
-  } else {
-    for (int v = 0; v < 80; ++v) {
-      const double t = wave_sum_range(partials + (size_t)v * pstride + jb.tile_first, jb.ntiles, lane);
-      if (lane == 0) tot[v] = t;
-    }
+}
+
+// M-step of the large jobs: one wave per job folds its tile partials in a
+// fixed order and updates the 8 children.
+__global__ __launch_bounds__(64) void em_mstep_kernel(const int* __restrict__ job_ids, const Job* __restrict__ jobs,
+                                                      NodeF* tab, NodeD* nodes, const double* __restrict__ partials,
+                                                      size_t pstride, double eps, double min_mass) {
+  const Job jb = jobs[job_ids[blockIdx.x]];
+  const int lane = threadIdx.x;
+  __shared__ NodeF ch[8];
+  __shared__ double tot[80];
+  if (lane < 8) copy_nodef(ch[lane], tab[jb.child_base + lane]);
+  for (int v = 0; v < 80; ++v) {
+    const double t = wave_sum_range(partials + (size_t)v * pstride + jb.tile_first, jb.ntiles, lane);
+    if (lane == 0) tot[v] = t;
   }
   __syncthreads();
   mstep_children(tot, ch, tab, nodes, jb.child_base, eps, min_mass, lane);
-  if (lane == 0) counters[tl.job] = 0;
 }
 
 // All EM iterations of one small job inside one wave; the job's points are
@@ -613,11 +599,11 @@ __global__ __launch_bounds__(64) void finalize_level_kernel(const Job* __restric
 // ---------------------------------------------------------------------------
 
 void launch_root(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles, const Job* jobs,
-                 TreeDev* trees, double* partials, size_t pstride, unsigned* counters, double eps, hipStream_t s) {
-  hipLaunchKernelGGL(root_mean_kernel, dim3(ntiles), dim3(64), 0, s, xs, ys, zs, tiles, jobs, trees, partials, pstride,
-                     counters);
-  hipLaunchKernelGGL(root_cov_kernel, dim3(ntiles), dim3(64), 0, s, xs, ys, zs, tiles, jobs, trees, partials, pstride,
-                     counters, eps);
+                 int njobs, TreeDev* trees, double* partials, size_t pstride, double eps, hipStream_t s) {
+  hipLaunchKernelGGL(root_mean_kernel, dim3(ntiles), dim3(64), 0, s, xs, ys, zs, tiles, partials, pstride);
+  hipLaunchKernelGGL(root_mean_fold_kernel, dim3(njobs), dim3(64), 0, s, jobs, trees, partials, pstride);
+  hipLaunchKernelGGL(root_cov_kernel, dim3(ntiles), dim3(64), 0, s, xs, ys, zs, tiles, jobs, trees, partials, pstride);
+  hipLaunchKernelGGL(root_cov_fold_kernel, dim3(njobs), dim3(64), 0, s, jobs, trees, partials, pstride, eps);
 }
 
 void launch_init_children(const Job* jobs, int njobs, const TreeDev* trees, NodeD* nodes, NodeF* tab, double eps,
@@ -628,10 +614,12 @@ void launch_init_children(const Job* jobs, int njobs, const TreeDev* trees, Node
 }
 
 void launch_em_tiles(const float* xs, const float* ys, const float* zs, const Tile* tiles, const int* tile_ids,
-                     int n, const Job* jobs, NodeF* tab, NodeD* nodes, double* partials, size_t pstride,
-                     unsigned* counters, double eps, double min_mass, hipStream_t s) {
-  hipLaunchKernelGGL(em_tile_kernel, dim3(n), dim3(64), 0, s, xs, ys, zs, tiles, tile_ids, jobs, tab, nodes, partials,
-                     pstride, counters, eps, min_mass);
+                     int n, const int* bigjob_ids, int nbigjobs, const Job* jobs, NodeF* tab, NodeD* nodes,
+                     double* partials, size_t pstride, double eps, double min_mass, hipStream_t s) {
+  hipLaunchKernelGGL(em_tile_kernel, dim3(n), dim3(64), 0, s, xs, ys, zs, tiles, tile_ids, jobs, tab, partials,
+                     pstride);
+  hipLaunchKernelGGL(em_mstep_kernel, dim3(nbigjobs), dim3(64), 0, s, bigjob_ids, jobs, tab, nodes, partials, pstride,
+                     eps, min_mass);
 }
 
 void launch_em_fused(const float* xs, const float* ys, const float* zs, const int* job_ids, int n, const Job* jobs,

@@ -13,6 +13,7 @@
 #include "../../include/hgmm.h"
 #include "hgmm_dev.h"
 #include "hgmm_host.h"
+#include "hgmm_internal.h"
 
 using namespace hgmm;
 
@@ -24,6 +25,16 @@ static thread_local std::string g_err;
 
 static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hgmm_fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -81,6 +92,10 @@ struct hgmm_forest_s {
     return s;
   }
 };
+
+int hgmm_forest_size(const hgmm_forest_s* f) { return (int)f->trees.size(); }
+TreeDev* hgmm_forest_trees(hgmm_forest_s* f) { return f->d_trees; }
+NodeD* hgmm_forest_nodes(hgmm_forest_s* f) { return f->d_nodes; }
 
 static void free_forest(hgmm_forest_s* f) {
   if (!f) return;
@@ -171,7 +186,7 @@ static BuildLayout build_layout(int64_t n_total, int64_t max_jobs, int64_t max_l
 }
 
 struct RegLayout {
-  size_t bins, partials, counters, state, nmov, tiles, out, dpart, dcount, ptiles, total;
+  size_t bins, partials, counters, state, nmov, tiles, out, dpart, dcount, ptiles, active, total;
   int64_t max_tiles;
 };
 
@@ -180,11 +195,12 @@ static RegLayout reg_layout(int64_t n_total, int64_t nodes, int npairs) {
   L.max_tiles = n_total / 256 + npairs + 1;
   size_t o = 0;
   L.bins = o; o = align_up(o + sizeof(double) * 6 * (size_t)std::max<int64_t>(nodes, 1));
-  L.partials = o; o = align_up(o + sizeof(double) * 28 * (size_t)normal_blocks_per_pair() * npairs);
+  L.partials = o; o = align_up(o + sizeof(double) * 28 * (size_t)npairs);
   L.counters = o; o = align_up(o + sizeof(unsigned) * (size_t)npairs);
   L.dpart = o; o = align_up(o + sizeof(double) * 72 * 6 * (size_t)L.max_tiles);
   L.dcount = o; o = align_up(o + sizeof(unsigned) * (size_t)npairs);
   L.ptiles = o; o = align_up(o + sizeof(int2) * (size_t)npairs);
+  L.active = o; o = align_up(o + sizeof(int) * (size_t)npairs);
   L.state = o; o = align_up(o + sizeof(PoseState) * (size_t)npairs);
   L.nmov = o; o = align_up(o + sizeof(int64_t) * (size_t)npairs);
   L.tiles = o; o = align_up(o + sizeof(Tile) * (size_t)L.max_tiles);
@@ -401,7 +417,6 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
   int64_t nlab = 0;
   for (auto& t : f->trees) nlab += (int64_t)t.levels * t.n_points;
   launch_fill_u32(f->d_labels, 0xFFFFFFFFu, nlab, s);
-  launch_fill_u32(d_counters, 0u, Ly.max_jobs, s);
   HIP_LAUNCHED();
 
   // level-compact bases: lvl_base[l][b]
@@ -460,7 +475,9 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
     const int njobs = (int)jobs.size();
     if (njobs == 0) break;
     const int tpts = tile_points(level_points);
-    int ntiles = 0, nbig = 0, nsmall = 0;
+    int ntiles = 0, nbig = 0, nsmall = 0, nbigjobs = 0;
+    for (int j = 0; j < njobs; ++j)
+      if (jobs[j].count <= g_tune.fused_max) h_jids[nsmall++] = j;
     for (int j = 0; j < njobs; ++j) {
       Job& jb = jobs[j];
       jb.tile_first = ntiles;
@@ -475,19 +492,19 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
         if (!small) h_tids[nbig++] = ntiles;
         ++ntiles;
       }
-      if (small) h_jids[nsmall++] = j;
+      if (!small) h_jids[nsmall + nbigjobs++] = j;
       h_jobs[j] = jb;
     }
     if (ntiles > Ly.max_tiles || njobs > Ly.max_jobs) return fail(HGMM_EINVAL, "internal: tile plan overflow");
     HIP_TRY(hipMemcpyAsync(d_jobs, h_jobs, sizeof(Job) * njobs, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d_tiles, h_tiles, sizeof(Tile) * ntiles, hipMemcpyHostToDevice, s));
     if (nbig) HIP_TRY(hipMemcpyAsync(d_tile_ids, h_tids, sizeof(int) * nbig, hipMemcpyHostToDevice, s));
-    if (nsmall) HIP_TRY(hipMemcpyAsync(d_job_ids, h_jids, sizeof(int) * nsmall, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_job_ids, h_jids, sizeof(int) * njobs, hipMemcpyHostToDevice, s));
 
     if (l == 0) {
       {
         ProfScope ps(PK_ROOT, (double)level_points, s);
-        launch_root(cx, cy, cz, d_tiles, ntiles, d_jobs, f->d_trees, d_partials, (size_t)Ly.max_tiles, d_counters,
+        launch_root(cx, cy, cz, d_tiles, ntiles, d_jobs, njobs, f->d_trees, d_partials, (size_t)Ly.max_tiles,
                     p.reg_eps, s);
       }
       HIP_LAUNCHED();
@@ -505,8 +522,8 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
     if (nbig)
       for (int it = 0; it < p.build_iters; ++it) {
         ProfScope ps(PK_EM_TILE, (double)big_points, s);
-        launch_em_tiles(cx, cy, cz, d_tiles, d_tile_ids, nbig, d_jobs, f->d_tab, f->d_nodes, d_partials,
-                        (size_t)Ly.max_tiles, d_counters, p.reg_eps, p.min_mass, s);
+        launch_em_tiles(cx, cy, cz, d_tiles, d_tile_ids, nbig, d_job_ids + nsmall, nbigjobs, d_jobs, f->d_tab,
+                        f->d_nodes, d_partials, (size_t)Ly.max_tiles, p.reg_eps, p.min_mass, s);
       }
     if (nsmall && p.build_iters > 0) {
       ProfScope ps(PK_EM_FUSED, (double)small_points * p.build_iters, s);
@@ -559,7 +576,8 @@ struct RegRun {
 static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, const float* zs,
                         const std::vector<int64_t>& offs, const double* R0, const double* t0, int per_pair,
                         const RegRun& rr, char* ws, size_t ws_bytes, hipStream_t s, int mode_estep,
-                        int32_t* stop_out, float* gamma_out, double* bins_ext, PoseState* h_out, double* h_norm) {
+                        int32_t* stop_out, float* gamma_out, double* bins_ext, PoseState* h_out, double* h_norm,
+                        const int32_t* active = nullptr) {
   const int P = (int)offs.size() - 1;
   const int64_t n_total = offs.back();
   const int64_t nodes_total = f->total_nodes();
@@ -583,7 +601,8 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   size_t s_res = align_up(s_pose + sizeof(double) * 12 * P);
   size_t s_norm = align_up(s_res + sizeof(PoseState) * P);
   size_t s_pt = align_up(s_norm + sizeof(double) * 28 * P);
-  size_t s_end = align_up(s_pt + sizeof(int2) * P);
+  size_t s_act = align_up(s_pt + sizeof(int2) * P);
+  size_t s_end = align_up(s_act + sizeof(int) * P);
   int rc = grow_stage(f, s_end);
   if (rc) return rc;
   char* H = f->h_stage;
@@ -593,6 +612,8 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   PoseState* h_res = (PoseState*)(H + s_res);
   double* h_nrm = (double*)(H + s_norm);
   int2* h_pt = (int2*)(H + s_pt);
+  int* h_act = (int*)(H + s_act);
+  int* d_act = (int*)(ws + Ly.active);
 
   int ntiles = 0;
   const int rt = g_tune.reg_tile;
@@ -619,18 +640,22 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   HIP_TRY(hipMemcpyAsync(d_nmov, h_nmov, sizeof(int64_t) * P, hipMemcpyHostToDevice, s));
   // pose rows are 12 doubles: R (9) then t (3)
   HIP_TRY(hipMemcpyAsync(d_pose0, h_pose, sizeof(double) * 12 * npose, hipMemcpyHostToDevice, s));
+  if (active) {
+    for (int b = 0; b < P; ++b) h_act[b] = active[b] ? 1 : 0;
+    HIP_TRY(hipMemcpyAsync(d_act, h_act, sizeof(int) * P, hipMemcpyHostToDevice, s));
+  }
   launch_fill_u32(d_bins, 0u, 2 * 6 * nodes_total, s);
-  launch_fill_u32(d_counters, 0u, P, s);
-  launch_fill_u32(d_dcount, 0u, P, s);
   launch_set_stop_flags(f->d_tab, f->d_nodes, nodes_total, rr.lambda_c, s);
-  launch_init_pose(d_state, P, d_pose0, d_pose0 + 9, per_pair ? 12 : 0, s);
+  launch_init_pose(d_state, P, d_pose0, d_pose0 + 9, per_pair ? 12 : 0, active ? d_act : nullptr, s);
   HIP_LAUNCHED();
   const size_t pstride = (size_t)Ly.max_tiles;
   if (mode_estep) {
-    launch_descend(xs, ys, zs, d_tiles, ntiles, d_ptiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins, d_dpart,
-                   pstride, d_dcount, stop_out, gamma_out, s);
+    launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins, d_dpart, pstride,
+                   stop_out, gamma_out, s);
+    launch_fold_bins(d_ptiles, f->d_trees, d_dpart, pstride, d_bins, P, s);
     if (h_norm) {
-      launch_normal(d_bins, f->d_nodes, f->d_trees, d_state, d_nmov, P, d_partials, d_counters, 1, 0.0, 0.0, d_out, s);
+      launch_normal(d_bins, d_dpart, pstride, d_ptiles, f->d_nodes, f->d_trees, d_state, d_nmov, P, 1, 0.0, 0.0, d_out,
+                    s);
       HIP_TRY(hipMemcpyAsync(h_nrm, d_out, sizeof(double) * 28 * P, hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       memcpy(h_norm, h_nrm, sizeof(double) * 28 * P);
@@ -647,12 +672,12 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
     for (; it < end; ++it) {
       {
         ProfScope ps(PK_DESCEND, (double)n_total, s, it);
-        launch_descend(xs, ys, zs, d_tiles, ntiles, d_ptiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins,
-                       d_dpart, pstride, d_dcount, nullptr, nullptr, s);
+        launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins, d_dpart,
+                       pstride, nullptr, nullptr, s);
       }
       {
         ProfScope ps(PK_NORMAL, (double)nodes_total, s, it);
-        launch_normal(d_bins, f->d_nodes, f->d_trees, d_state, d_nmov, P, d_partials, d_counters, 0, rr.tol_rot,
+        launch_normal(d_bins, d_dpart, pstride, d_ptiles, f->d_nodes, f->d_trees, d_state, d_nmov, P, 0, rr.tol_rot,
                       rr.tol_trans_rel, d_out, s);
       }
     }
@@ -798,11 +823,10 @@ int hgmm_normal_equations(hgmm_tree tree, const double* d_bins, int64_t n, void*
   int64_t* d_nmov = (int64_t*)(ws + Ly.nmov);
   HIP_TRY(hipMemcpyAsync(d_pose0, h, sizeof(double) * 12, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(d_nmov, hn, sizeof(int64_t), hipMemcpyHostToDevice, s));
-  launch_fill_u32(ws + Ly.counters, 0u, 1, s);
-  launch_init_pose((PoseState*)(ws + Ly.state), 1, d_pose0, d_pose0 + 9, 0, s);
+  launch_init_pose((PoseState*)(ws + Ly.state), 1, d_pose0, d_pose0 + 9, 0, nullptr, s);
   // the kernel reads the bins without modifying them in mode 1
-  launch_normal(const_cast<double*>(d_bins), tree->d_nodes, tree->d_trees, (PoseState*)(ws + Ly.state), d_nmov, 1,
-                (double*)(ws + Ly.partials), (unsigned*)(ws + Ly.counters), 1, 0.0, 0.0, d_out, s);
+  launch_normal(const_cast<double*>(d_bins), nullptr, 0, nullptr, tree->d_nodes, tree->d_trees,
+                (PoseState*)(ws + Ly.state), d_nmov, 1, 1, 0.0, 0.0, d_out, s);
   HIP_LAUNCHED();
   double* hres = h + 16;
   HIP_TRY(hipMemcpyAsync(hres, d_out, sizeof(double) * 28, hipMemcpyDeviceToHost, s));
@@ -910,6 +934,108 @@ int hgmm_tree_import(const hgmm_tree_host* in, void* stream, hgmm_tree* out) {
   if (rc) { free_forest(f); return rc; }
   f->has_labels = false;
   *out = f;
+  return HGMM_OK;
+}
+
+static int check_offsets(const int64_t* offsets, int B) {
+  if (!offsets || B < 1) return fail(HGMM_EINVAL, "null offsets or empty batch");
+  if (offsets[0] != 0) return fail(HGMM_EINVAL, "offsets[0] must be 0");
+  for (int b = 0; b < B; ++b)
+    if (offsets[b + 1] < offsets[b]) return fail(HGMM_EINVAL, "offsets must be non-decreasing");
+  if (offsets[B] > (int64_t)INT32_MAX / 2) return fail(HGMM_EINVAL, "too many points");
+  return HGMM_OK;
+}
+
+size_t hgmm_build_batch_workspace_bytes(const int64_t* offsets, const int32_t* levels, int B) {
+  if (check_offsets(offsets, B) || !levels) return 0;
+  std::vector<TreeHost> t((size_t)B);
+  for (int b = 0; b < B; ++b) {
+    if (levels[b] < 1 || levels[b] > HGMM_MAX_LEVELS) return 0;
+    t[b] = TreeHost{levels[b], offsets[b + 1] - offsets[b], 0, 0, 0};
+  }
+  return build_layout(offsets[B], max_jobs_for(t), max_lvl_for(t)).total;
+}
+
+size_t hgmm_register_batch_workspace_bytes(hgmm_tree forest, const int64_t* offsets, int B) {
+  if (!forest || check_offsets(offsets, B) || B != (int)forest->trees.size()) return 0;
+  return reg_layout(offsets[B], forest->total_nodes(), B).total;
+}
+
+int hgmm_build_batch(const float* d_xyz, const int64_t* offsets, const int32_t* levels, int B,
+                     const hgmm_build_params* p, void* d_ws, size_t ws_bytes, void* stream, hgmm_tree* forest) {
+  int rc = check_build_params(p);
+  if (rc) return rc;
+  if ((rc = check_offsets(offsets, B))) return rc;
+  if (!d_xyz || !d_ws || !forest || !levels) return fail(HGMM_EINVAL, "null pointer argument");
+  for (int b = 0; b < B; ++b) {
+    if (levels[b] < 1 || levels[b] > HGMM_MAX_LEVELS) return fail(HGMM_EINVAL, "levels[%d] outside [1, 6]", b);
+    if (offsets[b + 1] - offsets[b] < 8) return fail(HGMM_ETOOFEW, "cloud %d has fewer than 8 points", b);
+  }
+  hgmm_forest_s* f = *forest;
+  const bool fresh = (f == nullptr);
+  if (fresh) f = new hgmm_forest_s();
+  HIP_TRY(hipGetDevice(&f->device));
+  f->trees.resize((size_t)B);
+  for (int b = 0; b < B; ++b) f->trees[b] = TreeHost{levels[b], offsets[b + 1] - offsets[b], 0, 0, 0};
+  rc = setup_forest(f);
+  if (!rc) {
+    const int64_t n = offsets[B];
+    BuildInput in{d_xyz, d_xyz + n, d_xyz + 2 * n};
+    rc = run_build(f, in, *p, (char*)d_ws, ws_bytes, (hipStream_t)stream);
+  }
+  if (rc && fresh) { free_forest(f); return rc; }
+  *forest = f;
+  return rc;
+}
+
+int hgmm_register_batch(hgmm_tree forest, const float* d_xyz, const int64_t* offsets, int B,
+                        const hgmm_reg_params* p, const double* R0, const double* t0, const int32_t* active,
+                        void* d_ws, size_t ws_bytes, void* stream, double* R, double* t, int* iters, double* loglik,
+                        int* status) {
+  int rc = check_offsets(offsets, B);
+  if (rc) return rc;
+  if (!forest || !d_xyz || !p || !d_ws || !R || !t || !iters) return fail(HGMM_EINVAL, "null pointer argument");
+  if (B != (int)forest->trees.size()) return fail(HGMM_EINVAL, "batch size %d != forest size %d", B,
+                                                   (int)forest->trees.size());
+  if (p->max_iters < 1) return fail(HGMM_EINVAL, "max_iters must be >= 1");
+  for (int b = 0; b < B; ++b)
+    if (offsets[b + 1] - offsets[b] < 1) return fail(HGMM_ETOOFEW, "cloud %d to register is empty", b);
+  std::vector<int64_t> offs(offsets, offsets + B + 1);
+  RegRun rr{p->max_iters, p->lambda_c, p->tol_rot, p->tol_trans_rel};
+  std::vector<PoseState> res((size_t)B);
+  const int64_t n = offsets[B];
+  rc = run_register(forest, d_xyz, d_xyz + n, d_xyz + 2 * n, offs, R0, t0, 1, rr, (char*)d_ws, ws_bytes,
+                    (hipStream_t)stream, 0, nullptr, nullptr, nullptr, res.data(), nullptr, active);
+  if (rc) return rc;
+  int worst = HGMM_OK;
+  for (int b = 0; b < B; ++b) {
+    for (int i = 0; i < 9; ++i) R[9 * b + i] = res[b].R[i];
+    for (int i = 0; i < 3; ++i) t[3 * b + i] = res[b].t[i];
+    iters[b] = res[b].iters;
+    if (loglik) loglik[b] = res[b].loglik;
+    if (status) status[b] = res[b].status;
+    if (res[b].status != 0) worst = res[b].status;
+  }
+  if (worst != HGMM_OK && !status) return fail(worst, "normal equations not positive definite for some pair");
+  return HGMM_OK;
+}
+
+int hgmm_estep_batch(hgmm_tree forest, const float* d_xyz, const int64_t* offsets, int B, const double* R,
+                     const double* t, double lambda_c, void* d_ws, size_t ws_bytes, void* stream, double* loglik) {
+  int rc = check_offsets(offsets, B);
+  if (rc) return rc;
+  if (!forest || !d_xyz || !d_ws || !loglik) return fail(HGMM_EINVAL, "null pointer argument");
+  if (B != (int)forest->trees.size()) return fail(HGMM_EINVAL, "batch size != forest size");
+  for (int b = 0; b < B; ++b)
+    if (offsets[b + 1] - offsets[b] < 1) return fail(HGMM_ETOOFEW, "cloud %d is empty", b);
+  std::vector<int64_t> offs(offsets, offsets + B + 1);
+  RegRun rr{1, lambda_c, 0.0, 0.0};
+  std::vector<double> nrm(28 * (size_t)B);
+  const int64_t n = offsets[B];
+  rc = run_register(forest, d_xyz, d_xyz + n, d_xyz + 2 * n, offs, R, t, 1, rr, (char*)d_ws, ws_bytes,
+                    (hipStream_t)stream, 1, nullptr, nullptr, nullptr, nullptr, nrm.data());
+  if (rc) return rc;
+  for (int b = 0; b < B; ++b) loglik[b] = nrm[28 * (size_t)b + 27];
   return HGMM_OK;
 }
 

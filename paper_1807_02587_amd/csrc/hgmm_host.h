@@ -13,12 +13,12 @@ void launch_fill_u32(void* p, uint32_t v, int64_t n_words, hipStream_t s);
 
 // build
 void launch_root(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles, const Job* jobs,
-                 TreeDev* trees, double* partials, size_t pstride, unsigned* counters, double eps, hipStream_t s);
+                 int njobs, TreeDev* trees, double* partials, size_t pstride, double eps, hipStream_t s);
 void launch_init_children(const Job* jobs, int njobs, const TreeDev* trees, NodeD* nodes, NodeF* tab, double eps,
                           hipStream_t s);
 void launch_em_tiles(const float* xs, const float* ys, const float* zs, const Tile* tiles, const int* tile_ids,
-                     int n, const Job* jobs, NodeF* tab, NodeD* nodes, double* partials, size_t pstride,
-                     unsigned* counters, double eps, double min_mass, hipStream_t s);
+                     int n, const int* bigjob_ids, int nbigjobs, const Job* jobs, NodeF* tab, NodeD* nodes,
+                     double* partials, size_t pstride, double eps, double min_mass, hipStream_t s);
 void launch_em_fused(const float* xs, const float* ys, const float* zs, const int* job_ids, int n, const Job* jobs,
                      NodeF* tab, NodeD* nodes, int iters, double eps, double min_mass, int cap, hipStream_t s);
 void launch_partition(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
@@ -34,15 +34,16 @@ void launch_finalize_level(const Job* jobs, int njobs, NodeD* nodes, NodeF* tab,
 
 // registration
 void launch_set_stop_flags(NodeF* tab, const NodeD* nodes, int64_t n, double lambda_c, hipStream_t s);
-void launch_init_pose(PoseState* st, int npairs, const double* R0, const double* t0, int stride, hipStream_t s);
+void launch_init_pose(PoseState* st, int npairs, const double* R0, const double* t0, int stride, const int* active,
+                      hipStream_t s);
 void launch_descend(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
-                    const int2* pair_tiles, const TreeDev* trees, const NodeF* tab, const NodeD* nodes,
-                    const PoseState* st, double* bins, double* partials, size_t pstride, unsigned* counters,
-                    int32_t* stop_out, float* gamma_out, hipStream_t s);
-void launch_normal(double* bins, const NodeD* nodes, const TreeDev* trees, PoseState* st, const int64_t* n_moving,
-                   int npairs, double* partials, unsigned* counters, int mode, double tol_rot, double tol_trans_rel,
-                   double* out, hipStream_t s);
-int normal_blocks_per_pair();
+                    const TreeDev* trees, const NodeF* tab, const NodeD* nodes, const PoseState* st, double* bins,
+                    double* partials, size_t pstride, int32_t* stop_out, float* gamma_out, hipStream_t s);
+void launch_fold_bins(const int2* pair_tiles, const TreeDev* trees, const double* partials, size_t pstride,
+                      double* bins, int npairs, hipStream_t s);
+void launch_normal(double* bins, const double* dpart, size_t pstride, const int2* pair_tiles, const NodeD* nodes,
+                   const TreeDev* trees, PoseState* st, const int64_t* n_moving, int npairs, int mode, double tol_rot,
+                   double tol_trans_rel, double* out, hipStream_t s);
 int normal_values();
 
 // import / export

@@ -17,10 +17,6 @@
 
 namespace hgmm {
 
-__device__ __forceinline__ unsigned ticket_add_r(unsigned* c) {
-  return __hip_atomic_fetch_add(c, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __device__ __forceinline__ int64_t lvl_off(int l) {
   // (8^(l+1) - 8) / 7
   int64_t p = 8;
@@ -40,7 +36,7 @@ __global__ void set_stop_flags_kernel(NodeF* tab, const NodeD* __restrict__ node
 // Initial transform of every pair: rows of `stride` doubles (stride 0 = the
 // same transform for all pairs).
 __global__ void init_pose_kernel(PoseState* st, int npairs, const double* __restrict__ R0, const double* __restrict__ t0,
-                                 int stride) {
+                                 int stride, const int* __restrict__ active) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= npairs) return;
   PoseState& S = st[b];
@@ -51,7 +47,7 @@ __global__ void init_pose_kernel(PoseState* st, int npairs, const double* __rest
   for (int i = 0; i < 6; ++i) S.x[i] = 0.0;
   S.loglik = 0.0;
   S.iters = 0;
-  S.done = 0;
+  S.done = (active && !active[b]) ? 1 : 0;
   S.status = 0;
 }
 
@@ -107,16 +103,15 @@ constexpr int kLdsNodes = 72;  // levels 0 and 1 of one tree
 
 // One E-step over the tiles of every pair.  tiles[].job is the pair index.
 // Points stopping at the LDS-resident levels (0 and 1) are binned in FP64 LDS
-// accumulators; each block writes them as value-major partials and the last
-// block of the pair folds them in a fixed order.  Deeper stop nodes receive few
-// points each and are added with FP64 atomics.
+// accumulators, written as value-major block partials and folded in a fixed
+// order by the next kernel (no cross-block handoff inside this kernel).
+// Deeper stop nodes receive few points each and are added with FP64 atomics.
 __global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
                                                       const float* __restrict__ zs, const Tile* __restrict__ tiles,
-                                                      const int2* __restrict__ pair_tiles,
                                                       const TreeDev* __restrict__ trees, const NodeF* __restrict__ tab,
                                                       const NodeD* __restrict__ nodes, const PoseState* __restrict__ st,
                                                       double* bins, double* partials, size_t pstride,
-                                                      unsigned* counters, int32_t* stop_out, float* gamma_out) {
+                                                      int32_t* stop_out, float* gamma_out) {
   const Tile tl = tiles[blockIdx.x];
   const int pair = tl.job;
   if (st[pair].done) return;
@@ -125,7 +120,6 @@ __global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ 
   const int64_t nb = T.node_base;
   __shared__ NodeF lds[kLdsNodes];
   __shared__ double lbin[kLdsNodes * 6];
-  __shared__ unsigned tk;
   const int nl = L >= 2 ? 72 : 8;
   for (int i = threadIdx.x; i < nl; i += blockDim.x) {
     const float4* s = reinterpret_cast<const float4*>(&tab[nb + i]);
@@ -262,29 +256,34 @@ __global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ 
     }
   }
   __syncthreads();
-  const int2 pt = pair_tiles[pair];  // first tile and tile count of the pair
-  const int slot = blockIdx.x - pt.x;
-  for (int i = threadIdx.x; i < nl * 6; i += blockDim.x) partials[(size_t)i * pstride + pt.x + slot] = lbin[i];
-  __threadfence();
-  if (threadIdx.x == 0) tk = ticket_add_r(&counters[pair]);
-  __syncthreads();
-  if (tk != (unsigned)pt.y - 1) return;
-  __threadfence();
-  // last block of the pair: fixed-order fold of the block partials
-  const int wv = threadIdx.x >> 6;
-  for (int i = wv; i < nl * 6; i += (int)(blockDim.x >> 6)) {
+  // block partials of the LDS-resident levels, value-major; the normal-equation
+  // kernel folds them in a fixed order
+  for (int i = threadIdx.x; i < nl * 6; i += blockDim.x) partials[(size_t)i * pstride + blockIdx.x] = lbin[i];
+}
+
+// Writes the folded LDS-level moments into the node bins (for callers that
+// read the bins directly).  One block per pair.
+__global__ __launch_bounds__(256) void fold_bins_kernel(const int2* __restrict__ pair_tiles,
+                                                        const TreeDev* __restrict__ trees,
+                                                        const double* __restrict__ partials, size_t pstride,
+                                                        double* bins) {
+  const int pair = blockIdx.x;
+  const TreeDev& T = trees[pair];
+  const int nl = T.levels >= 2 ? 72 : 8;
+  const int2 pt = pair_tiles[pair];
+  const int lane = __lane_id(), wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int i = wv; i < nl * 6; i += nw) {
     const double v = wave_sum_range(partials + (size_t)i * pstride + pt.x, pt.y, lane);
-    if (lane == 0) bins[nb * 6 + i] = v;
+    if (lane == 0) bins[T.node_base * 6 + i] = v;
   }
-  if (threadIdx.x == 0) counters[pair] = 0;
 }
 
 // ---------------------------------------------------------------------------
 // M-step
 // ---------------------------------------------------------------------------
 
-constexpr int kNormBlocks = 8;  // blocks per pair
-constexpr int kNV = 28;         // 21 (upper H) + 6 (g) + 1 (log-likelihood numerator)
+constexpr int kNormThreads = 1024;  // one block per pair
+constexpr int kNV = 28;             // 21 (upper H) + 6 (g) + 1 (log-likelihood numerator)
 
 __device__ inline bool chol6_solve(const double* Hu /*21 upper*/, double shift, const double* g, double* x) {
   double A[6][6];
@@ -317,80 +316,90 @@ __device__ inline bool chol6_solve(const double* Hu /*21 upper*/, double shift, 
   return true;
 }
 
-// mode 0: reduce, zero the bins, solve and update the pose.
-// mode 1: reduce only; H, g and the log-likelihood go to out[pair * 28 ..].
-__global__ __launch_bounds__(256) void normal_kernel(double* bins, const NodeD* __restrict__ nodes,
-                                                     const TreeDev* __restrict__ trees, PoseState* st,
-                                                     const int64_t* __restrict__ n_moving, double* partials,
-                                                     unsigned* counters, int mode, double tol_rot,
-                                                     double tol_trans_rel, double* out) {
-  const int pair = blockIdx.x / kNormBlocks;
-  const int chunk = blockIdx.x % kNormBlocks;
+// Contribution of one node with moments b = {M0, D (3), count, sum d2} to the
+// normal equations (Eq. 11-16, increment about the model mean o) and to the
+// log-likelihood numerator.
+__device__ __forceinline__ void node_terms(const NodeD& nd, const double* b, double N, double o0, double o1, double o2,
+                                           double (&acc)[kNV]) {
+  const double m0 = b[0];
+  const double pis = m0 / N;
+  const double dl0 = b[1] / m0, dl1 = b[2] / m0, dl2 = b[3] / m0;
+  const double c0 = nd.mu[0] + dl0 - o0, c1 = nd.mu[1] + dl1 - o1, c2 = nd.mu[2] + dl2 - o2;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const double n0 = nd.evec[3 * l], n1 = nd.evec[3 * l + 1], n2 = nd.evec[3 * l + 2];
+    const double w = pis / nd.lam[l];
+    const double a[6] = {c1 * n2 - c2 * n1, c2 * n0 - c0 * n2, c0 * n1 - c1 * n0, n0, n1, n2};
+    const double r = n0 * dl0 + n1 * dl1 + n2 * dl2;
+    int idx = 0;
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+#pragma unroll
+      for (int v = u; v < 6; ++v) { acc[idx] += w * a[u] * a[v]; ++idx; }
+    }
+#pragma unroll
+    for (int u = 0; u < 6; ++u) acc[21 + u] -= w * a[u] * r;
+  }
+  acc[27] += b[4] * (log(nd.pig) - 0.5 * nd.logdet) - 0.5 * b[5];
+}
+
+// One block per pair.  mode 0: normal equations from this iteration's moments
+// (LDS-level nodes folded from the descent's block partials, deeper nodes read
+// and cleared from the bins), Cholesky solve and pose update.  mode 1: the
+// same sums from the bins alone, written to out[pair * 28 ..] (H upper, g,
+// mean log-likelihood).
+__global__ __launch_bounds__(kNormThreads) void normal_kernel(double* bins, const double* __restrict__ dpart,
+                                                              size_t pstride, const int2* __restrict__ pair_tiles,
+                                                              const NodeD* __restrict__ nodes,
+                                                              const TreeDev* __restrict__ trees, PoseState* st,
+                                                              const int64_t* __restrict__ n_moving, int mode,
+                                                              double tol_rot, double tol_trans_rel, double* out) {
+  const int pair = blockIdx.x;
   PoseState& S = st[pair];
   if (S.done) return;
   const TreeDev& T = trees[pair];
   const int64_t nn = lvl_off(T.levels);
-  const int64_t per = (nn + kNormBlocks - 1) / kNormBlocks;
-  const int64_t g0 = T.node_base + chunk * per;
-  const int64_t g1 = T.node_base + min(nn, (chunk + 1) * per);
+  const int64_t nb = T.node_base;
+  const int nl = T.levels >= 2 ? 72 : 8;
   const double N = (double)n_moving[pair];
   const double o0 = T.origin[0], o1 = T.origin[1], o2 = T.origin[2];
+  const int lane = __lane_id(), wv = threadIdx.x >> 6;
   double acc[kNV];
 #pragma unroll
   for (int v = 0; v < kNV; ++v) acc[v] = 0.0;
-  for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
-    double* B = bins + g * 6;
+  const bool from_partials = (mode == 0);
+  if (from_partials) {
+    const int2 pt = pair_tiles[pair];
+    for (int node = wv; node < nl; node += kNormThreads / 64) {
+      double b[6];
+#pragma unroll
+      for (int v = 0; v < 6; ++v) b[v] = wave_sum_range(dpart + (size_t)(node * 6 + v) * pstride + pt.x, pt.y, lane);
+      if (lane == 0 && b[0] > 0.0) node_terms(nodes[nb + node], b, N, o0, o1, o2, acc);
+    }
+  }
+  for (int64_t g = (from_partials ? nl : 0) + threadIdx.x; g < nn; g += kNormThreads) {
+    double* B = bins + (nb + g) * 6;
     const double m0 = B[0];
     if (!(m0 > 0.0)) continue;
-    const double D0 = B[1], D1 = B[2], D2 = B[3], cnt = B[4], Ls = B[5];
+    double b[6] = {m0, B[1], B[2], B[3], B[4], B[5]};
     if (mode == 0) { B[0] = 0.0; B[1] = 0.0; B[2] = 0.0; B[3] = 0.0; B[4] = 0.0; B[5] = 0.0; }
-    const NodeD& nd = nodes[g];
-    const double pis = m0 / N;
-    const double dl0 = D0 / m0, dl1 = D1 / m0, dl2 = D2 / m0;
-    // mu* relative to the rotation centre
-    const double c0 = nd.mu[0] + dl0 - o0, c1 = nd.mu[1] + dl1 - o1, c2 = nd.mu[2] + dl2 - o2;
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-      const double n0 = nd.evec[3 * l], n1 = nd.evec[3 * l + 1], n2 = nd.evec[3 * l + 2];
-      const double w = pis / nd.lam[l];
-      const double a[6] = {c1 * n2 - c2 * n1, c2 * n0 - c0 * n2, c0 * n1 - c1 * n0, n0, n1, n2};
-      const double r = n0 * dl0 + n1 * dl1 + n2 * dl2;
-      int idx = 0;
-#pragma unroll
-      for (int u = 0; u < 6; ++u) {
-#pragma unroll
-        for (int v = u; v < 6; ++v) { acc[idx] += w * a[u] * a[v]; ++idx; }
-      }
-#pragma unroll
-      for (int u = 0; u < 6; ++u) acc[21 + u] -= w * a[u] * r;
-    }
-    acc[27] += cnt * (log(nd.pig) - 0.5 * nd.logdet) - 0.5 * Ls;
+    node_terms(nodes[nb + g], b, N, o0, o1, o2, acc);
   }
-  __shared__ double red[4][kNV];
-  __shared__ unsigned tk;
-  const int lane = __lane_id(), wv = threadIdx.x >> 6;
+  __shared__ double red[kNormThreads / 64][kNV];
+  __shared__ double tot[kNV];
 #pragma unroll
   for (int v = 0; v < kNV; ++v) {
-    double s = wave_sum_d(acc[v]);
-    if (lane == 0) red[wv][v] = s;
+    const double sv = wave_sum_dd(acc[v]);
+    if (lane == 0) red[wv][v] = sv;
   }
   __syncthreads();
-  double* P = partials + (size_t)blockIdx.x * kNV;
-  if (threadIdx.x < kNV) P[threadIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
-  __threadfence();
-  if (threadIdx.x == 0) tk = ticket_add_r(&counters[pair]);
-  __syncthreads();
-  if (tk != (unsigned)kNormBlocks - 1) return;
-  __threadfence();
-  __shared__ double tot[kNV];
   if (threadIdx.x < kNV) {
-    double s = 0.0;
-    for (int c = 0; c < kNormBlocks; ++c) s += partials[(size_t)(pair * kNormBlocks + c) * kNV + threadIdx.x];
-    tot[threadIdx.x] = s;
+    double sv = 0.0;
+    for (int w = 0; w < kNormThreads / 64; ++w) sv += red[w][threadIdx.x];
+    tot[threadIdx.x] = sv;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  counters[pair] = 0;
   const double ll = tot[27] / N - 1.5 * kLog2Pi;
   if (mode == 1) {
     for (int v = 0; v < kNV; ++v) out[pair * kNV + v] = tot[v];
@@ -445,8 +454,9 @@ void launch_set_stop_flags(NodeF* tab, const NodeD* nodes, int64_t n, double lam
   hipLaunchKernelGGL(set_stop_flags_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tab, nodes, n, lambda_c);
 }
 
-void launch_init_pose(PoseState* st, int npairs, const double* R0, const double* t0, int stride, hipStream_t s) {
-  hipLaunchKernelGGL(init_pose_kernel, dim3((npairs + 63) / 64), dim3(64), 0, s, st, npairs, R0, t0, stride);
+void launch_init_pose(PoseState* st, int npairs, const double* R0, const double* t0, int stride, const int* active,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(init_pose_kernel, dim3((npairs + 63) / 64), dim3(64), 0, s, st, npairs, R0, t0, stride, active);
 }
 
 // Scoring records of an imported tree.
@@ -476,21 +486,24 @@ void launch_import_nodes(NodeD* nodes, NodeF* tab, int64_t n, hipStream_t s) {
 }
 
 void launch_descend(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
-                    const int2* pair_tiles, const TreeDev* trees, const NodeF* tab, const NodeD* nodes,
-                    const PoseState* st, double* bins, double* partials, size_t pstride, unsigned* counters,
-                    int32_t* stop_out, float* gamma_out, hipStream_t s) {
-  hipLaunchKernelGGL(descend_kernel, dim3(ntiles), dim3(256), 0, s, xs, ys, zs, tiles, pair_tiles, trees, tab, nodes,
-                     st, bins, partials, pstride, counters, stop_out, gamma_out);
+                    const TreeDev* trees, const NodeF* tab, const NodeD* nodes, const PoseState* st, double* bins,
+                    double* partials, size_t pstride, int32_t* stop_out, float* gamma_out, hipStream_t s) {
+  hipLaunchKernelGGL(descend_kernel, dim3(ntiles), dim3(256), 0, s, xs, ys, zs, tiles, trees, tab, nodes, st, bins,
+                     partials, pstride, stop_out, gamma_out);
 }
 
-void launch_normal(double* bins, const NodeD* nodes, const TreeDev* trees, PoseState* st, const int64_t* n_moving,
-                   int npairs, double* partials, unsigned* counters, int mode, double tol_rot, double tol_trans_rel,
-                   double* out, hipStream_t s) {
-  hipLaunchKernelGGL(normal_kernel, dim3(npairs * kNormBlocks), dim3(256), 0, s, bins, nodes, trees, st, n_moving,
-                     partials, counters, mode, tol_rot, tol_trans_rel, out);
+void launch_fold_bins(const int2* pair_tiles, const TreeDev* trees, const double* partials, size_t pstride,
+                      double* bins, int npairs, hipStream_t s) {
+  hipLaunchKernelGGL(fold_bins_kernel, dim3(npairs), dim3(256), 0, s, pair_tiles, trees, partials, pstride, bins);
 }
 
-int normal_blocks_per_pair() { return kNormBlocks; }
+void launch_normal(double* bins, const double* dpart, size_t pstride, const int2* pair_tiles, const NodeD* nodes,
+                   const TreeDev* trees, PoseState* st, const int64_t* n_moving, int npairs, int mode, double tol_rot,
+                   double tol_trans_rel, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(normal_kernel, dim3(npairs), dim3(kNormThreads), 0, s, bins, dpart, pstride, pair_tiles, nodes,
+                     trees, st, n_moving, mode, tol_rot, tol_trans_rel, out);
+}
+
 int normal_values() { return kNV; }
 
 }  // namespace hgmm

@@ -1,0 +1,148 @@
+"""Learned warm start for batched registration (orchestration of library calls).
+
+Pipeline per batch of pairs (every arithmetic step runs in the library's HIP
+kernels; this module only sequences calls and moves handles around):
+
+1. build the source forest (levels per pair) and a 2-level target forest;
+2. level-1 features of both trees in canonical frames (hgmm_warm_features);
+3. network forward (hgmm_mlp_forward) -> 6D rotation + translation;
+4. head -> initial transforms (hgmm_warm_head_pose);
+5. batched registration from those transforms;
+6. fallback: pairs whose final log-likelihood is below the log-likelihood of
+   the identity transform (one E-step, hgmm_estep_batch) are registered again
+   from the identity.
+
+Training data come from the batched GPU scene generator; the label of a pair
+is the plain method's converged pose when started at the ground truth.
+"""
+
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import api as hg
+
+
+@dataclass
+class WarmConfig:
+    src_levels: int = 2
+    tgt_levels: int = 2
+    reg_eps: float = 1e-6
+    min_mass: float = 1.0
+    lambda_c: float = 0.01
+    max_iters: int = 30
+    trans_weight: float = 1.0
+
+
+def _eye_batch(B):
+    return np.broadcast_to(np.eye(3), (B, 3, 3)).copy(), np.zeros((B, 3))
+
+
+def features_for(src_forest, tgt_forest, B, cfg: WarmConfig):
+    fs, frs = hg.hgmm_warm_features(src_forest, np.arange(B), cfg.reg_eps)
+    ft, frt = hg.hgmm_warm_features(tgt_forest, np.arange(B), cfg.reg_eps)
+    return torch.cat([fs, ft], dim=1).contiguous(), frs, frt
+
+
+def training_set(n_pairs: int, seed: int, cfg: WarmConfig = WarmConfig(), chunk: int = 1024, n: int = 10_000,
+                 max_angle_deg: float = 90.0, log=None):
+    """(X (n_pairs, 1280) float32, T (n_pairs, 9) float32) on the GPU."""
+    from synth.torch_scenes import cube_pairs
+    Xs, Ts = [], []
+    ws = hg.Workspace()
+    done = 0
+    c = 0
+    t0 = time.time()
+    while done < n_pairs:
+        B = min(chunk, n_pairs - done)
+        S = cube_pairs(seed * 100_003 + c, B, n=n, max_angle_deg=max_angle_deg)
+        off = S.offsets.numpy()
+        src_f = hg.hgmm_build_batch(S.src, off, [cfg.src_levels] * B, reg_eps=cfg.reg_eps, min_mass=cfg.min_mass,
+                                    ws=ws)
+        tgt_f = hg.hgmm_build_batch(S.tgt, off, [cfg.tgt_levels] * B, reg_eps=cfg.reg_eps, min_mass=cfg.min_mass,
+                                    ws=ws)
+        X, frs, frt = features_for(src_f, tgt_f, B, cfg)
+        lab = hg.hgmm_register_batch(src_f, S.tgt, off, max_iters=cfg.max_iters, lambda_c=cfg.lambda_c,
+                                     R0=S.R_true.cpu().numpy(), t0=S.t_true.cpu().numpy(), ws=ws)
+        R = torch.from_numpy(lab["R"].reshape(B, 9)).cuda()
+        t = torch.from_numpy(lab["t"]).cuda()
+        T = hg.hgmm_warm_head_target(R, t, frs, frt)
+        Xs.append(X)
+        Ts.append(T)
+        done += B
+        c += 1
+        if log:
+            log(f"training pairs {done}/{n_pairs} ({time.time() - t0:.1f} s)")
+    return torch.cat(Xs).contiguous(), torch.cat(Ts).contiguous()
+
+
+def train(mlp, X, T, epochs: int = 20, batch: int = 512, lr: float = 1e-3, lr_min: float = 1e-5, seed: int = 0,
+          cfg: WarmConfig = WarmConfig(), log=None):
+    """Adam with cosine learning-rate decay; returns the per-epoch mean losses."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    N = X.shape[0]
+    steps_per_epoch = N // batch
+    total = max(1, epochs * steps_per_epoch)
+    hist = []
+    step = 0
+    for ep in range(epochs):
+        perm = torch.randperm(N, generator=g, device="cuda")
+        acc, cnt = 0.0, 0
+        for i in range(steps_per_epoch):
+            idx = perm[i * batch:(i + 1) * batch]
+            xb = X.index_select(0, idx).contiguous()
+            tb = T.index_select(0, idx).contiguous()
+            rate = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * step / total))
+            want = (i % 50 == 0) or i == steps_per_epoch - 1
+            loss = mlp.train_step(xb, tb, rate, cfg.trans_weight, want_loss=want)
+            if want:
+                acc += loss
+                cnt += 1
+            step += 1
+        hist.append(acc / max(cnt, 1))
+        if log:
+            log(f"epoch {ep + 1}/{epochs}: loss {hist[-1]:.5f}")
+    return hist
+
+
+def register_warm(mlp, src, tgt, src_off, tgt_off, src_levels, cfg: WarmConfig = WarmConfig(), ws=None,
+                  src_forest=None):
+    """Warm-started batched registration with the likelihood fallback.
+
+    Returns dict(R (B,3,3), t, iters, loglik, fallback (B,) bool, R0, t0, forest)."""
+    ws = ws or hg.Workspace()
+    B = len(src_levels)
+    if src_forest is None:
+        src_forest = hg.hgmm_build_batch(src, src_off, src_levels, reg_eps=cfg.reg_eps, min_mass=cfg.min_mass, ws=ws)
+    tgt_forest = hg.hgmm_build_batch(tgt, tgt_off, [cfg.tgt_levels] * B, reg_eps=cfg.reg_eps, min_mass=cfg.min_mass,
+                                     ws=ws)
+    X, frs, frt = features_for(src_forest, tgt_forest, B, cfg)
+    Y = mlp.forward(X)
+    R0, t0 = hg.hgmm_warm_head_pose(Y, frs, frt)
+    R0 = R0.cpu().numpy().reshape(B, 3, 3)
+    t0 = t0.cpu().numpy()
+    r = hg.hgmm_register_batch(src_forest, tgt, tgt_off, max_iters=cfg.max_iters, lambda_c=cfg.lambda_c, R0=R0,
+                               t0=t0, ws=ws)
+    Ri, ti = _eye_batch(B)
+    ll_id = hg.hgmm_estep_batch(src_forest, tgt, tgt_off, Ri, ti, lambda_c=cfg.lambda_c, ws=ws)
+    fb = (r["loglik"] < ll_id) | (r["status"] != 0)
+    if fb.any():
+        r2 = hg.hgmm_register_batch(src_forest, tgt, tgt_off, max_iters=cfg.max_iters, lambda_c=cfg.lambda_c,
+                                    R0=Ri, t0=ti, active=fb.astype(np.int32), ws=ws)
+        for k in ("R", "t", "iters", "loglik", "status"):
+            r[k] = np.where(fb.reshape((B,) + (1,) * (r[k].ndim - 1)), r2[k], r[k])
+    r.update(fallback=fb, R0=R0, t0=t0, forest=src_forest)
+    return r
+
+
+def rotation_errors_deg(R, R_true):
+    R = np.asarray(R).reshape(-1, 3, 3)
+    Rt = np.asarray(R_true).reshape(-1, 3, 3)
+    c = (np.einsum("bij,bij->b", R, Rt) - 1.0) / 2.0
+    return np.degrees(np.arccos(np.clip(c, -1.0, 1.0)))
