@@ -59,6 +59,75 @@ def _workload(name):
     return p, PRESETS[name], desc
 
 
+WEIGHTS = os.path.join(ROOT, "paper_1807_02587_amd", "weights", "warm_mlp.npy")
+
+
+def batch_section(args, hg):
+    """The uneven batch (256 unit-cube pairs, N log-uniform in [2e3, 2e5],
+    rotation U(0, 45 deg), depth ceil(log8(N/50))) registered three ways:
+    one pair at a time (plain form), batched from identity, batched with the
+    learned warm start and its likelihood fallback."""
+    import torch
+    from paper_1807_02587_amd import warmstart as W
+    from synth.torch_scenes import uneven_batch
+
+    src, tgt, off, lv, Rt, tt = uneven_batch(3000, args.batch_pairs)
+    B = len(lv)
+    ws = hg.Workspace()
+    cfg = W.WarmConfig()
+
+    def plain_sequential(k_list):
+        Rs = []
+        tree = None
+        for k in k_list:
+            s_k = src[:, off[k]:off[k + 1]].contiguous()
+            t_k = tgt[:, off[k]:off[k + 1]].contiguous()
+            tree = hg.hgmm_build(s_k, levels=int(lv[k]), ws=ws, tree=tree)
+            Rs.append(hg.hgmm_register(tree, t_k, ws=ws, raise_singular=False)["R"])
+        return np.array(Rs)
+
+    def batched_plain():
+        forest = hg.hgmm_build_batch(src, off, lv, ws=ws)
+        return hg.hgmm_register_batch(forest, tgt, off, ws=ws)["R"]
+
+    net = None
+    if os.path.exists(WEIGHTS):
+        net = hg.MLP(seed=0)
+        net.set_params(np.load(WEIGHTS))
+
+    def batched_warm():
+        return W.register_warm(net, src, tgt, off, off, lv, cfg, ws=ws)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    plain_sequential(range(min(8, B)))
+    Rp, tp = timed(lambda: plain_sequential(range(B)))
+    batched_plain()
+    Rb, tb = timed(batched_plain)
+    out = {"workload": f"{B} unit-cube pairs, N log-uniform [2e3, 2e5] (total {int(off[-1])} points per side), "
+                       "rotation U(0,45 deg), levels ceil(log8(N/50))",
+           "plain_sequential_pairs_s": round(B / tp, 2),
+           "plain_sequential_median_rot_err_deg": round(float(np.median(W.rotation_errors_deg(Rp, Rt))), 4),
+           "batched_pairs_s": round(B / tb, 2),
+           "batched_median_rot_err_deg": round(float(np.median(W.rotation_errors_deg(Rb, Rt))), 4)}
+    if net is not None:
+        batched_warm()
+        rw, tw = timed(batched_warm)
+        ew = W.rotation_errors_deg(rw["R"], Rt)
+        out.update({"batched_warm_pairs_s": round(B / tw, 2),
+                    "batched_warm_median_rot_err_deg": round(float(np.median(ew)), 4),
+                    "batched_warm_success_0p5": round(float(np.mean(ew <= 0.5)), 4),
+                    "warm_fallback_rate": round(float(np.mean(rw["fallback"])), 4),
+                    "speedup_batched_warm_vs_plain": round(tp / tw, 2)})
+    out["speedup_batched_vs_plain"] = round(tp / tb, 2)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +136,10 @@ def main():
     ap.add_argument("--workload", default="lidar", choices=["lidar", "small", "depth"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--batch-pairs", type=int, default=256)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 256 MiB device copy and a few steps (for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
@@ -91,6 +164,19 @@ def main():
         tree = hg.hgmm_build(src, levels=pr["levels"], reg_eps=pr["reg_eps"], min_mass=pr["min_mass"], ws=ws_b,
                              tree=tree)
         return hg.hgmm_register(tree, tgt, lambda_c=pr["lambda_c"], ws=ws_r, raise_singular=False)
+
+    if args.copy_calibration:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE give the
+        # scale from counter units to bytes
+        a = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        for _ in range(max(1, args.steps)):
+            step()
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4, "steps": args.steps}), flush=True)
+        return
 
     for _ in range(args.warmup):
         step()
@@ -155,6 +241,8 @@ def main():
                "sample": f"{reps} full pair(s) of the same workload (build {n1} + register {n2} points), "
                          f"single-threaded FP64, {t_c:.1f} s"}
 
+    batched = None if args.no_batch else batch_section(args, hg)
+
     out = {
         "metric": "cloud pairs registered/s (build + register)",
         "value": round(args.steps / sec, 3),
@@ -178,6 +266,7 @@ def main():
         "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in prof.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
 

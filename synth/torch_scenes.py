@@ -120,3 +120,26 @@ def cube_pairs(seed: int, B: int, n: int = 10_000, max_angle_deg: float = 90.0, 
     t_true = -torch.einsum("bij,bj->bi", R_true, tg)
     return TorchPairs(src=soa(src), tgt=soa(tgt), offsets=offsets, R_true=R_true, t_true=t_true,
                       angle_deg=torch.rad2deg(ang))
+
+
+def uneven_batch(seed_base: int = 3000, count: int = 256, n_min: int = 2_000, n_max: int = 200_000,
+                 max_angle_deg: float = 45.0, leaf_points: float = 50.0, device="cuda"):
+    """``count`` pairs with N log-uniform in [n_min, n_max] (same N draw as the
+    NumPy ``scenes.uneven_batch``), concatenated CSR; tree depth per pair is
+    ceil(log8(N / leaf_points)).  Returns (src, tgt, offsets (B+1,), levels (B,),
+    R_true (B,3,3), t_true (B,3)) with the clouds on ``device``."""
+    import numpy as np
+    srcs, tgts, Rs, ts, lv, ns = [], [], [], [], [], []
+    for k in range(count):
+        g = np.random.Generator(np.random.PCG64(np.random.SeedSequence((seed_base + k, 7))))
+        nk = int(round(math.exp(g.uniform(math.log(n_min), math.log(n_max)))))
+        P = cube_pairs(seed_base + k, 1, n=nk, max_angle_deg=max_angle_deg, device=device)
+        srcs.append(P.src)
+        tgts.append(P.tgt)
+        Rs.append(P.R_true[0])
+        ts.append(P.t_true[0])
+        lv.append(max(1, int(math.ceil(math.log(nk / leaf_points, 8)))))
+        ns.append(nk)
+    off = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    return (torch.cat(srcs, 1).contiguous(), torch.cat(tgts, 1).contiguous(), off, np.array(lv, np.int32),
+            torch.stack(Rs).cpu().numpy(), torch.stack(ts).cpu().numpy())
