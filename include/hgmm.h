@@ -257,25 +257,63 @@ int hgmm_tree_import(const hgmm_tree_host *in, void *stream, hgmm_tree *out);
 int hgmm_tree_info(hgmm_tree tree, int index, int *levels, int64_t *n_nodes, double origin[3], double *extent);
 void hgmm_tree_destroy(hgmm_tree tree);
 
-/* Launch-shape knobs of the construction and registration kernels (process
- * wide; a negative value keeps the current setting).  fused_max: parents with
- * at most this many points run all their EM iterations inside one wavefront;
- * min_tile / max_tile / target_tiles: points per construction tile are
- * level_points / target_tiles rounded up to a multiple of 64 and clamped to
- * [min_tile, max_tile]; reg_tile: points per registration block (multiple of
- * 256).  Defaults 512, 256, 1024, 4096, 256.  Not thread-safe against
- * concurrent builds. */
-int hgmm_set_tuning(int fused_max, int min_tile, int target_tiles, int max_tile, int reg_tile);
+/* Launch shapes of the construction and registration kernels (process wide,
+ * the search space of the autotuner).  Construction of a level: a parent with
+ * at most block64_max points runs all its EM iterations in one 64-thread
+ * block, at most block256_max in one 256-thread block, at most block512_max
+ * in one 512-thread block; a larger parent is cut into tiles of one wavefront
+ * and each EM iteration is one tile launch plus one M-step launch.  Points per
+ * tile are level_points / target_tiles rounded up to a multiple of 64 and
+ * clamped to [min_tile, max_tile].  Registration: reg_tile points per
+ * 256-thread descent block (a multiple of 256); reg_chunk iterations are
+ * queued between two convergence checks on the host.
+ * Defaults 256, 2048, 8192, 256, 1024, 4096, 512, 4. */
+typedef struct hgmm_tuning {
+  int32_t block64_max, block256_max, block512_max;
+  int32_t min_tile, target_tiles, max_tile;
+  int32_t reg_tile, reg_chunk;
+} hgmm_tuning;
+
+/* Set (after validation) or read the launch shapes.  hgmm_set_tuning returns
+ * HGMM_EINVAL, changing nothing, unless 0 <= block64_max <= block256_max <=
+ * block512_max <= 1<<20, 64 <= min_tile <= max_tile <= 1<<20,
+ * target_tiles >= 1, 256 <= reg_tile <= 1<<20 and 1 <= reg_chunk <= 64.
+ * Values are rounded up to the multiples stated above.  Not thread-safe
+ * against concurrent calls of the library. */
+int hgmm_set_tuning(const hgmm_tuning *t);
+int hgmm_get_tuning(hgmm_tuning *t);
+
+/* Autotuner of the launch shapes for one workload.  Builds the forest of the
+ * B source clouds (CSR: d_src SoA over src_offsets[B], levels[b] per tree,
+ * parameters bp) and, when d_tgt is not NULL, registers the B target clouds
+ * (tgt_offsets, parameters rp, from the identity) under candidate settings,
+ * timing each run with HIP events on `stream` (best of `reps`), and moves one
+ * knob at a time to the fastest of its candidates for up to `passes` sweeps.
+ * On success the fastest setting is in effect and copied to *best, with its
+ * time in *best_ms and the time of the starting setting in *start_ms (either
+ * may be NULL).  d_ws must hold both the construction and the registration
+ * workspace of this batch.  On failure the starting setting is restored.
+ * The search runs the whole workload tens of times; results of the method do
+ * not depend on the launch shapes beyond floating-point summation order. */
+/* Workspace bytes for hgmm_autotune (tgt_offsets may be NULL: construction
+ * only); 0 for invalid arguments. */
+size_t hgmm_autotune_workspace_bytes(const int64_t *src_offsets, const int32_t *levels, const int64_t *tgt_offsets,
+                                     int B);
+int hgmm_autotune(const float *d_src, const int64_t *src_offsets, const int32_t *levels, int B,
+                  const float *d_tgt, const int64_t *tgt_offsets, const hgmm_build_params *bp,
+                  const hgmm_reg_params *rp, void *d_ws, size_t ws_bytes, void *stream, int reps,
+                  int passes, hgmm_tuning *best, double *best_ms, double *start_ms);
 
 /* Benchmark instrumentation.  hgmm_profile(1) brackets every kernel launch
  * of hgmm_build / hgmm_register with HIP events on the caller's stream;
  * hgmm_profile_read returns, per kernel kind, the summed event time (ms), the
  * number of timed launches and the work units they processed (points, or
- * point-iterations for the fused construction kernel, or nodes for the
+ * point-iterations for the block construction kernels, or nodes for the
  * normal equations).  Registration launches after convergence (which exit at
  * once) are not counted.  Kinds: 0 construction EM tile iteration,
- * 1 fused construction EM, 2 partition, 3 stable split, 4 registration
- * descent, 5 normal equations + solve, 6 root statistics.  Process-wide, not
+ * 1 construction EM in one block per parent, 2 partition, 3 stable split, 4 registration
+ * descent, 5 normal equations + solve, 6 root statistics, 7 construction
+ * M-step of the tiled parents (units: parents).  Process-wide, not
  * thread-safe. */
 int hgmm_profile(int enable);
 void hgmm_profile_reset(void);

@@ -5,6 +5,7 @@ PyTorch provides device memory and streams; every step of construction and
 registration runs in the library's HIP kernels.
 """
 
+from ._lib import HgmmError  # noqa: F401
 from .api import (  # noqa: F401
     Tree,
     Workspace,
@@ -24,6 +25,9 @@ from .api import (  # noqa: F401
     hgmm_tree_nodes,
     hgmm_level_offset,
     hgmm_set_tuning,
+    hgmm_get_tuning,
+    hgmm_autotune,
+    TUNING_KEYS,
     library_path,
     hgmm_profile,
     hgmm_profile_reset,

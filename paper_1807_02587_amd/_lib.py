@@ -17,6 +17,11 @@ class BuildParams(C.Structure):
     _fields_ = [("levels", C.c_int32), ("build_iters", C.c_int32), ("reg_eps", D), ("min_mass", D)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [(k, C.c_int32) for k in ("block64_max", "block256_max", "block512_max", "min_tile", "target_tiles",
+                                          "max_tile", "reg_tile", "reg_chunk")]
+
+
 class RegParams(C.Structure):
     _fields_ = [("max_iters", C.c_int32), ("pad_", C.c_int32), ("lambda_c", D), ("tol_rot", D),
                 ("tol_trans_rel", D)]
@@ -45,7 +50,10 @@ SIGNATURES = {
     "hgmm_tree_import": (C.c_int, [P, P, P]),
     "hgmm_tree_info": (C.c_int, [P, C.c_int, P, P, P, P]),
     "hgmm_tree_destroy": (None, [P]),
-    "hgmm_set_tuning": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
+    "hgmm_set_tuning": (C.c_int, [P]),
+    "hgmm_get_tuning": (C.c_int, [P]),
+    "hgmm_autotune_workspace_bytes": (C.c_size_t, [P, P, P, C.c_int]),
+    "hgmm_autotune": (C.c_int, [P, P, P, C.c_int, P, P, P, P, P, C.c_size_t, P, C.c_int, C.c_int, P, P, P]),
     "hgmm_build_batch_workspace_bytes": (C.c_size_t, [P, P, C.c_int]),
     "hgmm_build_batch": (C.c_int, [P, P, P, C.c_int, P, P, C.c_size_t, P, P]),
     "hgmm_register_batch_workspace_bytes": (C.c_size_t, [P, P, C.c_int]),

@@ -31,6 +31,16 @@ def _cloud(xyz: torch.Tensor) -> torch.Tensor:
     return xyz
 
 
+def _dev(t, shape, dtype, name):
+    """Require a contiguous CUDA tensor of exactly this shape and dtype (None = any size)."""
+    ok = (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()
+          and t.dim() == len(shape) and all(s is None or s == d for s, d in zip(shape, t.shape)))
+    if not ok:
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor of shape {shape}, "
+                         f"got {getattr(t, 'dtype', type(t))} {tuple(getattr(t, 'shape', ()))}")
+    return t
+
+
 class Workspace:
     """Grow-only device scratch buffer handed to the library."""
 
@@ -56,8 +66,61 @@ def hgmm_level_offset(level: int) -> int:
     return int(_lib.load().hgmm_level_offset(level))
 
 
-def hgmm_set_tuning(fused_max=-1, min_tile=-1, target_tiles=-1, max_tile=-1, reg_tile=-1):
-    check(_lib.load().hgmm_set_tuning(fused_max, min_tile, target_tiles, max_tile, reg_tile), "hgmm_set_tuning")
+TUNING_KEYS = ("block64_max", "block256_max", "block512_max", "min_tile", "target_tiles", "max_tile", "reg_tile",
+               "reg_chunk")
+
+
+def hgmm_get_tuning() -> dict:
+    t = _lib.Tuning()
+    check(_lib.load().hgmm_get_tuning(C.byref(t)), "hgmm_get_tuning")
+    return {k: int(getattr(t, k)) for k in TUNING_KEYS}
+
+
+def hgmm_autotune(src: torch.Tensor, src_offsets, levels, tgt: torch.Tensor | None = None, tgt_offsets=None,
+                  build_iters: int = 30, reg_eps: float = 1e-6, min_mass: float = 1.0, max_iters: int = 30,
+                  lambda_c: float = 0.01, tol_rot: float = 1e-6, tol_trans_rel: float = 1e-6, reps: int = 2,
+                  passes: int = 2, ws: "Workspace | None" = None, stream=None) -> dict:
+    """Time candidate launch shapes on this batch (construction, plus registration
+    from the identity when ``tgt`` is given) and keep the fastest in effect."""
+    src = _cloud(src)
+    lib = _lib.load()
+    soff = np.ascontiguousarray(np.asarray(src_offsets, dtype=np.int64))
+    lev = np.ascontiguousarray(np.asarray(levels, dtype=np.int32))
+    B = len(lev)
+    assert soff.shape == (B + 1,) and soff[-1] == src.shape[1]
+    bp = BuildParams(int(lev.max()), build_iters, reg_eps, min_mass)
+    rp = RegParams(max_iters, 0, lambda_c, tol_rot, tol_trans_rel)
+    toff = None
+    if tgt is not None:
+        tgt = _cloud(tgt)
+        toff = np.ascontiguousarray(np.asarray(tgt_offsets, dtype=np.int64))
+        assert toff.shape == (B + 1,) and toff[-1] == tgt.shape[1]
+    need = lib.hgmm_autotune_workspace_bytes(soff.ctypes.data_as(C.c_void_p), lev.ctypes.data_as(C.c_void_p),
+                                             None if toff is None else toff.ctypes.data_as(C.c_void_p), B)
+    if need == 0:
+        raise ValueError("invalid offsets or levels")
+    ws = ws or Workspace(src.device)
+    wptr, wlen = ws.ptr(need)
+    best = _lib.Tuning()
+    bms, sms = C.c_double(0), C.c_double(0)
+    check(lib.hgmm_autotune(C.c_void_p(src.data_ptr()), soff.ctypes.data_as(C.c_void_p), lev.ctypes.data_as(C.c_void_p),
+                            B, None if tgt is None else C.c_void_p(tgt.data_ptr()),
+                            None if toff is None else toff.ctypes.data_as(C.c_void_p), C.byref(bp), C.byref(rp), wptr,
+                            wlen, _stream(stream), reps, passes, C.byref(best), C.byref(bms), C.byref(sms)),
+          "hgmm_autotune")
+    return dict(tuning={k: int(getattr(best, k)) for k in TUNING_KEYS}, best_ms=bms.value, start_ms=sms.value)
+
+
+def hgmm_set_tuning(**knobs) -> dict:
+    """Change some launch shapes (names as in TUNING_KEYS); returns the previous setting."""
+    old = hgmm_get_tuning()
+    unknown = set(knobs) - set(TUNING_KEYS)
+    if unknown:
+        raise KeyError(f"unknown tuning knobs {sorted(unknown)}")
+    new = dict(old, **{k: int(v) for k, v in knobs.items()})
+    t = _lib.Tuning(*[new[k] for k in TUNING_KEYS])
+    check(_lib.load().hgmm_set_tuning(C.byref(t)), "hgmm_set_tuning")
+    return old
 
 
 class Tree:
@@ -100,8 +163,13 @@ class Tree:
         return out
 
     def labels(self, index: int = 0, n_points: int | None = None, stream=None) -> torch.Tensor:
-        n = self.n_points if n_points is None else n_points
-        lab = torch.empty((self.levels, n), dtype=torch.int32, device="cuda")
+        """(levels, n) int32 most-likely-child labels of tree ``index`` (local node index at each level)."""
+        if getattr(self, "offsets", None) is not None:
+            n, L = int(self.offsets[index + 1] - self.offsets[index]), int(self.tree_levels[index])
+        else:
+            n, L = self.n_points, self.levels
+        n = n if n_points is None else n_points
+        lab = torch.empty((L, n), dtype=torch.int32, device="cuda")
         check(_lib.load().hgmm_tree_labels(self.handle, index, C.c_void_p(lab.data_ptr()), _stream(stream)),
               "hgmm_tree_labels")
         torch.cuda.current_stream().synchronize()
@@ -213,7 +281,8 @@ def hgmm_tree_import(src, stream=None) -> Tree:
     return Tree(h, int(get("n_points")), levels)
 
 
-PROFILE_KINDS = {"em_tile": 0, "em_fused": 1, "partition": 2, "scatter": 3, "descend": 4, "normal": 5, "root": 6}
+PROFILE_KINDS = {"em_tile": 0, "em_block": 1, "partition": 2, "scatter": 3, "descend": 4, "normal": 5, "root": 6,
+                 "em_mstep": 7}
 
 
 def hgmm_profile(enable: bool = True) -> None:
@@ -334,7 +403,9 @@ class MLP:
         check(self.lib.hgmm_mlp_set_params(self.handle, a.ctypes.data_as(C.c_void_p)), "hgmm_mlp_set_params")
 
     def forward(self, X: torch.Tensor, stream=None) -> torch.Tensor:
-        assert X.is_cuda and X.dtype == torch.float32 and X.is_contiguous() and X.shape[1] == 1280
+        _dev(X, (None, 1280), torch.float32, "X")
+        if X.shape[0] < 1:
+            raise ValueError("X needs at least one row")
         Y = torch.empty((X.shape[0], 9), dtype=torch.float32, device=X.device)
         check(self.lib.hgmm_mlp_forward(self.handle, C.c_void_p(X.data_ptr()), X.shape[0], C.c_void_p(Y.data_ptr()),
                                         _stream(stream)), "hgmm_mlp_forward")
@@ -342,6 +413,8 @@ class MLP:
 
     def train_step(self, X: torch.Tensor, T: torch.Tensor, lr: float, trans_weight: float = 1.0,
                    want_loss: bool = True, stream=None):
+        _dev(X, (None, 1280), torch.float32, "X")
+        _dev(T, (X.shape[0], 9), torch.float32, "T")
         loss = C.c_double(0)
         check(self.lib.hgmm_mlp_train_step(self.handle, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
                                            X.shape[0], C.c_float(lr), C.c_float(trans_weight), _stream(stream),
@@ -349,6 +422,8 @@ class MLP:
         return loss.value if want_loss else None
 
     def backward(self, X: torch.Tensor, T: torch.Tensor, trans_weight: float = 1.0, stream=None):
+        _dev(X, (None, 1280), torch.float32, "X")
+        _dev(T, (X.shape[0], 9), torch.float32, "T")
         g = np.zeros(self.n_params, np.float32)
         loss = C.c_double(0)
         check(self.lib.hgmm_mlp_backward(self.handle, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
@@ -370,7 +445,9 @@ def hgmm_warm_features(forest: Tree, tree_ids, reg_eps: float = 1e-6, stream=Non
 
 
 def hgmm_warm_head_pose(Y: torch.Tensor, fr_src: torch.Tensor, fr_tgt: torch.Tensor, stream=None):
-    P = Y.shape[0]
+    P = _dev(Y, (None, 9), torch.float32, "Y").shape[0]
+    _dev(fr_src, (P, 13), torch.float64, "fr_src")
+    _dev(fr_tgt, (P, 13), torch.float64, "fr_tgt")
     R0 = torch.empty((P, 9), dtype=torch.float64, device="cuda")
     t0 = torch.empty((P, 3), dtype=torch.float64, device="cuda")
     check(_lib.load().hgmm_warm_head_pose(C.c_void_p(Y.data_ptr()), C.c_void_p(fr_src.data_ptr()),
@@ -380,7 +457,10 @@ def hgmm_warm_head_pose(Y: torch.Tensor, fr_src: torch.Tensor, fr_tgt: torch.Ten
 
 
 def hgmm_warm_head_target(R: torch.Tensor, t: torch.Tensor, fr_src: torch.Tensor, fr_tgt: torch.Tensor, stream=None):
-    P = R.shape[0]
+    P = _dev(R, (None, 9), torch.float64, "R").shape[0]
+    _dev(t, (P, 3), torch.float64, "t")
+    _dev(fr_src, (P, 13), torch.float64, "fr_src")
+    _dev(fr_tgt, (P, 13), torch.float64, "fr_tgt")
     T = torch.empty((P, 9), dtype=torch.float32, device="cuda")
     check(_lib.load().hgmm_warm_head_target(C.c_void_p(R.data_ptr()), C.c_void_p(t.data_ptr()),
                                             C.c_void_p(fr_src.data_ptr()), C.c_void_p(fr_tgt.data_ptr()), P,
@@ -393,6 +473,12 @@ def hgmm_gemm_bf16(A_bits: torch.Tensor, B_bits: torch.Tensor, M, N, K, ta=False
     """C = op(A) op(B) with raw bf16 operands (int16 tensors holding bf16 bit patterns)."""
     lda = lda if lda is not None else (M if ta else K)
     ldb = ldb if ldb is not None else (K if tb else N)
+    for X, rows, ld, cols, nm in ((A_bits, K if ta else M, lda, M if ta else K, "A"),
+                                  (B_bits, N if tb else K, ldb, K if tb else N, "B")):
+        if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype in (torch.int16, torch.bfloat16)
+                and X.is_contiguous() and ld >= cols and X.numel() >= (rows - 1) * ld + cols):
+            raise ValueError(f"{nm} must be a contiguous 16-bit CUDA tensor holding a {rows} x {cols} matrix "
+                             f"with leading dimension {ld}")
     Cm = torch.empty((M, N), dtype=torch.float32, device="cuda")
     check(_lib.load().hgmm_gemm_bf16(int(ta), int(tb), M, N, K, C.c_void_p(A_bits.data_ptr()), lda,
                                      C.c_void_p(B_bits.data_ptr()), ldb, C.c_void_p(Cm.data_ptr()), N,

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhgmm.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["build_kernels.hip", "register_kernels.hip", "warm_kernels.hip", "mlp_api.hip", "hgmm_api.hip"]
+SOURCES = ["build_kernels.hip", "register_kernels.hip", "warm_kernels.hip", "mlp_api.hip", "hgmm_api.hip",
+           "hgmm_autotune.hip"]
 ARCH = "gfx950"
 
 
@@ -42,7 +43,10 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    missing = [s for s in SOURCES if not os.path.exists(os.path.join(CSRC, s))]
+    if missing:
+        raise FileNotFoundError(f"missing HIP sources: {missing}")
+    srcs = list(SOURCES)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + f".tmp{os.getpid()}"

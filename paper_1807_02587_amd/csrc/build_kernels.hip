@@ -7,9 +7,10 @@
 // (Sec. 3, Eq. 2-3), turns them into responsibilities and accumulates the
 // responsibility-weighted zeroth, first and second moments of every child
 // about the child's current mean (80 FP32 sums per lane).  The sums are
-// reduced across the wave with DPP, written as FP64 tile partials, and the
-// last tile of a parent to finish combines them in a fixed order and runs the
-// FP64 M-step for the 8 children.  Parents with few points run all their EM
+// reduced across the wave with DPP and written as FP64 tile partials; a
+// second launch folds each parent's partials in a fixed order and runs the
+// FP64 M-step for its 8 children, so no block waits on another and no
+// device-scope fence is needed.  Parents with few points run all their EM
 // iterations inside one wave instead (em_fused_kernel).
 #include "hgmm_dev.h"
 #include "hgmm_host.h"
@@ -79,10 +80,10 @@ __global__ __launch_bounds__(64) void root_mean_fold_kernel(const Job* __restric
                                                             const double* __restrict__ partials, size_t pstride) {
   const Job jb = jobs[blockIdx.x];
   const int lane = threadIdx.x;
-  const double a0 = wave_sum_range(partials + 0 * pstride + jb.tile_first, jb.ntiles, lane);
-  const double a1 = wave_sum_range(partials + 1 * pstride + jb.tile_first, jb.ntiles, lane);
-  const double a2 = wave_sum_range(partials + 2 * pstride + jb.tile_first, jb.ntiles, lane);
-  const double b = wave_sum_range(partials + 9 * pstride + jb.tile_first, jb.ntiles, lane);
+  double a[3], bb[1];
+  wave_fold<3, 8>(partials + jb.tile_first, pstride, jb.ntiles, lane, a);
+  wave_fold<1, 8>(partials + 9 * pstride + jb.tile_first, pstride, jb.ntiles, lane, bb);
+  const double a0 = a[0], a1 = a[1], a2 = a[2], b = bb[0];
   double l0 = INFINITY, l1 = INFINITY, l2 = INFINITY, h0 = -INFINITY, h1 = -INFINITY, h2 = -INFINITY;
   for (int t = lane; t < jb.ntiles; t += 64) {
     const size_t c = (size_t)jb.tile_first + t;
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(64) void root_cov_fold_kernel(const Job* __restrict
   const Job jb = jobs[blockIdx.x];
   const int lane = threadIdx.x;
   double a[6];
-  for (int k = 0; k < 6; ++k) a[k] = wave_sum_range(partials + k * pstride + jb.tile_first, jb.ntiles, lane);
+  wave_fold<6, 8>(partials + jb.tile_first, pstride, jb.ntiles, lane, a);
   if (lane == 0) {
     TreeDev& T = trees[jb.tree];
     double n = (double)jb.count;
@@ -237,26 +238,52 @@ __device__ __forceinline__ void em_point(const NodeF* ch, uint32_t live, double 
   }
 }
 
-template <typename FP>
-__device__ __forceinline__ void em_range(FP xs, FP ys, FP zs, int start, int end, int lane,
+template <int STRIDE, typename FP>
+__device__ __forceinline__ void em_range(FP xs, FP ys, FP zs, int start, int end, int first,
                                          const NodeF* ch, uint32_t live, float (&a)[8][10]) {
 #pragma unroll
   for (int k = 0; k < 8; ++k)
 #pragma unroll
     for (int v = 0; v < 10; ++v) a[k][v] = 0.f;
-  for (int i = start + lane; i < end; i += 64) em_point(ch, live, (double)xs[i], (double)ys[i], (double)zs[i], a);
+  for (int i = start + first; i < end; i += STRIDE) {
+    // the children's parameters are re-read from LDS (broadcast reads) for
+    // every point instead of being held in ~100 registers across the loop
+    asm volatile("" ::: "memory");
+    em_point(ch, live, (double)xs[i], (double)ys[i], (double)zs[i], a);
+  }
 }
 
-// Sum the 80 per-lane accumulators over the wave; out[v] (v < 80) is valid in
-// every lane as a wave-uniform value written to the LDS array red (80 floats).
-__device__ __forceinline__ void wave_reduce80(float (&a)[8][10], float* red, int lane) {
+// One butterfly step of the row reduce-scatter: the first H values are kept
+// by the lane whose role is "low", the next H by its partner; each lane adds
+// the partner's copy of the half it keeps (DPP pattern CTRL pairs the lanes).
+template <int H, int CTRL>
+__device__ __forceinline__ void rs_step(float (&a)[8][10], bool hi) {
 #pragma unroll
-  for (int k = 0; k < 8; ++k)
+  for (int i = 0; i < H; ++i) {
+    const float lo_v = a[i / 10][i % 10], hi_v = a[(i + H) / 10][(i + H) % 10];
+    const float keep = hi ? hi_v : lo_v;
+    const float send = hi ? lo_v : hi_v;
+    a[i / 10][i % 10] = keep + dpp_f<CTRL>(send);
+  }
+}
+
+// Reduce-scatter of the 80 per-lane sums over each 16-lane row in four
+// butterfly steps (row mirror, half-row mirror, quad xor 2, quad xor 1).
+// Afterwards lane r of a row holds the row totals of values 5r .. 5r+4 in
+// a[0][0..4].  Fixed data flow, so the result does not depend on timing.
+__device__ __forceinline__ void row_reduce_scatter80(float (&a)[8][10], int r) {
+  rs_step<40, 0x140>(a, r >= 8);
+  rs_step<20, 0x141>(a, (r & 7) >= 4);
+  rs_step<10, 0x4E>(a, (r & 2) != 0);
+  rs_step<5, 0xB1>(a, (r & 1) != 0);
+}
+
+// Row totals of all lanes of a block into rows[tid / 16][0..79].
+__device__ __forceinline__ void rows_store80(float (&a)[8][10], float (*rows)[80], int tid) {
+  row_reduce_scatter80(a, tid & 15);
+  float* out = rows[tid >> 4] + 5 * (tid & 15);
 #pragma unroll
-    for (int v = 0; v < 10; ++v) {
-      float t = wave_sum(a[k][v]);
-      if (lane == 0) red[k * 10 + v] = t;
-    }
+  for (int j = 0; j < 5; ++j) out[j] = a[0][j];
 }
 
 // FP64 M-step of the 8 children of one parent from the 80 combined sums
@@ -323,69 +350,71 @@ __global__ __launch_bounds__(64) void em_tile_kernel(const float* __restrict__ x
   const Job jb = jobs[tl.job];
   const int lane = threadIdx.x;
   __shared__ NodeF ch[8];
-  __shared__ float red[80];
+  __shared__ float rows[4][80];
   if (lane < 8) copy_nodef(ch[lane], tab[jb.child_base + lane]);
   __syncthreads();
   const uint32_t live = live_mask(ch);
   float a[8][10];
-  em_range(xs, ys, zs, tl.start, tl.end, lane, ch, live, a);
-  wave_reduce80(a, red, lane);
+  em_range<64>(xs, ys, zs, tl.start, tl.end, lane, ch, live, a);
+  rows_store80(a, rows, lane);
   __syncthreads();
-  partials[(size_t)lane * pstride + tid] = red[lane];
-  if (lane < 16) partials[(size_t)(64 + lane) * pstride + tid] = red[64 + lane];
+  for (int v = lane; v < 80; v += 64)
+    partials[(size_t)v * pstride + tid] = ((double)rows[0][v] + (double)rows[1][v]) + ((double)rows[2][v] + (double)rows[3][v]);
 }
 
-// M-step of the large jobs: one wave per job folds its tile partials in a
-// fixed order and updates the 8 children.
-__global__ __launch_bounds__(64) void em_mstep_kernel(const int* __restrict__ job_ids, const Job* __restrict__ jobs,
-                                                      NodeF* tab, NodeD* nodes, const double* __restrict__ partials,
-                                                      size_t pstride, double eps, double min_mass) {
+// M-step of the large jobs: one block of 16 waves per job; wave w folds the
+// tile partials of values 5w .. 5w+4 in a fixed order, then wave 0 updates the
+// 8 children.
+constexpr int kMstepThreads = 1024;
+__global__ __launch_bounds__(kMstepThreads) void em_mstep_kernel(const int* __restrict__ job_ids,
+                                                                 const Job* __restrict__ jobs, NodeF* tab,
+                                                                 NodeD* nodes, const double* __restrict__ partials,
+                                                                 size_t pstride, double eps, double min_mass) {
   const Job jb = jobs[job_ids[blockIdx.x]];
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   __shared__ NodeF ch[8];
   __shared__ double tot[80];
-  if (lane < 8) copy_nodef(ch[lane], tab[jb.child_base + lane]);
-  for (int v = 0; v < 80; ++v) {
-    const double t = wave_sum_range(partials + (size_t)v * pstride + jb.tile_first, jb.ntiles, lane);
-    if (lane == 0) tot[v] = t;
-  }
+  if (tid < 8) copy_nodef(ch[tid], tab[jb.child_base + tid]);
+  double t[5];
+  wave_fold<5, 8>(partials + (size_t)(5 * wv) * pstride + jb.tile_first, pstride, jb.ntiles, lane, t);
+  if (lane == 0)
+    for (int j = 0; j < 5; ++j) tot[5 * wv + j] = t[j];
   __syncthreads();
-  mstep_children(tot, ch, tab, nodes, jb.child_base, eps, min_mass, lane);
+  if (tid < 64) mstep_children(tot, ch, tab, nodes, jb.child_base, eps, min_mass, lane);
 }
 
-// All EM iterations of one small job inside one wave; the job's points are
-// staged once in LDS (cap points, dynamic shared memory) when they fit.
-__global__ __launch_bounds__(64) void em_fused_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
+// All EM iterations of one job inside one block of NT threads: each thread
+// accumulates the moments of every NT-th point of the job (the job's points
+// stay in L1/L2 across iterations), the block reduces them (row butterflies,
+// then the rows in FP64 in a fixed order) and wave 0 runs the FP64 M-step.
+// One launch covers every iteration.
+template <int NT>
+__global__ __launch_bounds__(NT) void em_block_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
                                                       const float* __restrict__ zs, const int* __restrict__ job_ids,
                                                       const Job* __restrict__ jobs, NodeF* tab, NodeD* nodes,
-                                                      int iters, double eps, double min_mass, int cap) {
+                                                      int iters, double eps, double min_mass) {
+  constexpr int NR = NT / 16;
   const Job jb = jobs[job_ids[blockIdx.x]];
-  const int lane = threadIdx.x;
-  extern __shared__ float spts[];
+  const int tid = threadIdx.x;
   __shared__ NodeF ch[8];
-  __shared__ float red[80];
+  __shared__ float rows[NR][80];
   __shared__ double tot[80];
-  if (lane < 8) copy_nodef(ch[lane], tab[jb.child_base + lane]);
-  const bool staged = jb.count <= cap;
-  if (staged)
-    for (int i = lane; i < jb.count; i += 64) {
-      spts[i] = xs[jb.start + i];
-      spts[cap + i] = ys[jb.start + i];
-      spts[2 * cap + i] = zs[jb.start + i];
-    }
+  if (tid < 8) copy_nodef(ch[tid], tab[jb.child_base + tid]);
   __syncthreads();
   for (int it = 0; it < iters; ++it) {
     const uint32_t live = live_mask(ch);
     if (live == 0u) break;
     float a[8][10];
-    if (staged) em_range(spts, spts + cap, spts + 2 * cap, 0, jb.count, lane, ch, live, a);
-    else em_range(xs, ys, zs, jb.start, jb.start + jb.count, lane, ch, live, a);
-    wave_reduce80(a, red, lane);
+    em_range<NT>(xs, ys, zs, jb.start, jb.start + jb.count, tid, ch, live, a);
+    rows_store80(a, rows, tid);
     __syncthreads();
-    tot[lane] = (double)red[lane];
-    if (lane < 16) tot[64 + lane] = (double)red[64 + lane];
+    for (int v = tid; v < 80; v += NT) {
+      double t = 0.0;
+      for (int q = 0; q < NR; ++q) t += (double)rows[q][v];
+      tot[v] = t;
+    }
     __syncthreads();
-    mstep_children(tot, ch, tab, nodes, jb.child_base, eps, min_mass, lane);
+    if (tid < 64) mstep_children(tot, ch, tab, nodes, jb.child_base, eps, min_mass, tid);
     __syncthreads();
   }
 }
@@ -613,20 +642,31 @@ void launch_init_children(const Job* jobs, int njobs, const TreeDev* trees, Node
                      eps);
 }
 
-void launch_em_tiles(const float* xs, const float* ys, const float* zs, const Tile* tiles, const int* tile_ids,
-                     int n, const int* bigjob_ids, int nbigjobs, const Job* jobs, NodeF* tab, NodeD* nodes,
-                     double* partials, size_t pstride, double eps, double min_mass, hipStream_t s) {
+void launch_em_tile(const float* xs, const float* ys, const float* zs, const Tile* tiles, const int* tile_ids, int n,
+                    const Job* jobs, const NodeF* tab, double* partials, size_t pstride, hipStream_t s) {
   hipLaunchKernelGGL(em_tile_kernel, dim3(n), dim3(64), 0, s, xs, ys, zs, tiles, tile_ids, jobs, tab, partials,
                      pstride);
-  hipLaunchKernelGGL(em_mstep_kernel, dim3(nbigjobs), dim3(64), 0, s, bigjob_ids, jobs, tab, nodes, partials, pstride,
-                     eps, min_mass);
 }
 
-void launch_em_fused(const float* xs, const float* ys, const float* zs, const int* job_ids, int n, const Job* jobs,
-                     NodeF* tab, NodeD* nodes, int iters, double eps, double min_mass, int cap, hipStream_t s) {
-  cap = std::min(cap, 4096);
-  hipLaunchKernelGGL(em_fused_kernel, dim3(n), dim3(64), (size_t)cap * 12, s, xs, ys, zs, job_ids, jobs, tab, nodes,
-                     iters, eps, min_mass, cap);
+void launch_em_mstep(const int* job_ids, int n, const Job* jobs, NodeF* tab, NodeD* nodes, const double* partials,
+                     size_t pstride, double eps, double min_mass, hipStream_t s) {
+  hipLaunchKernelGGL(em_mstep_kernel, dim3(n), dim3(kMstepThreads), 0, s, job_ids, jobs, tab, nodes, partials,
+                     pstride, eps, min_mass);
+}
+
+void launch_em_block(int nt, const float* xs, const float* ys, const float* zs, const int* job_ids, int n,
+                     const Job* jobs, NodeF* tab, NodeD* nodes, int iters, double eps, double min_mass,
+                     hipStream_t s) {
+  if (n <= 0) return;
+  if (nt == 64)
+    hipLaunchKernelGGL(em_block_kernel<64>, dim3(n), dim3(64), 0, s, xs, ys, zs, job_ids, jobs, tab, nodes, iters,
+                       eps, min_mass);
+  else if (nt == 256)
+    hipLaunchKernelGGL(em_block_kernel<256>, dim3(n), dim3(256), 0, s, xs, ys, zs, job_ids, jobs, tab, nodes, iters,
+                       eps, min_mass);
+  else
+    hipLaunchKernelGGL(em_block_kernel<512>, dim3(n), dim3(512), 0, s, xs, ys, zs, job_ids, jobs, tab, nodes, iters,
+                       eps, min_mass);
 }
 
 void launch_partition(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,

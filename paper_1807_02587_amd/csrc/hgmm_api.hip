@@ -236,25 +236,31 @@ static int64_t max_lvl_for(const std::vector<TreeHost>& trees) {
 }
 
 // ---------------------------------------------------------------------------
-// tunables (points per tile by level size; largest job run as one fused wave)
+// launch shapes (process wide; see hgmm_tuning)
 // ---------------------------------------------------------------------------
 
-struct Tuning {
-  int fused_max = 512;
-  int min_tile = 256;
-  int target_tiles = 1024;
-  int max_tile = 4096;
-  int reg_tile = 512;
-  int reg_chunk = 4;
-};
-static Tuning g_tune;
+static hgmm_tuning g_tune = {256, 2048, 8192, 256, 1024, 4096, 512, 4};
 
-extern "C" int hgmm_set_tuning(int fused_max, int min_tile, int target_tiles, int max_tile, int reg_tile) {
-  if (fused_max >= 0) g_tune.fused_max = fused_max;
-  if (min_tile > 0) g_tune.min_tile = (min_tile + 63) / 64 * 64;
-  if (target_tiles > 0) g_tune.target_tiles = target_tiles;
-  if (max_tile > 0) g_tune.max_tile = (max_tile + 63) / 64 * 64;
-  if (reg_tile > 0) g_tune.reg_tile = (reg_tile + 255) / 256 * 256;
+extern "C" int hgmm_set_tuning(const hgmm_tuning* t) {
+  if (!t) return fail(HGMM_EINVAL, "null tuning");
+  const int lim = 1 << 20;
+  if (!(0 <= t->block64_max && t->block64_max <= t->block256_max && t->block256_max <= t->block512_max &&
+        t->block512_max <= lim))
+    return fail(HGMM_EINVAL, "block thresholds must satisfy 0 <= b64 <= b256 <= b512 <= 2^20");
+  if (!(64 <= t->min_tile && t->min_tile <= t->max_tile && t->max_tile <= lim && t->target_tiles >= 1))
+    return fail(HGMM_EINVAL, "tile sizes must satisfy 64 <= min_tile <= max_tile <= 2^20, target_tiles >= 1");
+  if (!(256 <= t->reg_tile && t->reg_tile <= lim && 1 <= t->reg_chunk && t->reg_chunk <= 64))
+    return fail(HGMM_EINVAL, "reg_tile must be in [256, 2^20] and reg_chunk in [1, 64]");
+  g_tune = *t;
+  g_tune.min_tile = (t->min_tile + 63) / 64 * 64;
+  g_tune.max_tile = (t->max_tile + 63) / 64 * 64;
+  g_tune.reg_tile = (t->reg_tile + 255) / 256 * 256;
+  return HGMM_OK;
+}
+
+extern "C" int hgmm_get_tuning(hgmm_tuning* t) {
+  if (!t) return fail(HGMM_EINVAL, "null tuning");
+  *t = g_tune;
   return HGMM_OK;
 }
 
@@ -270,7 +276,7 @@ static int tile_points(int64_t level_points) {
 // optional event timing of the kernel launches (benchmark instrumentation)
 // ---------------------------------------------------------------------------
 
-enum ProfKind { PK_EM_TILE = 0, PK_EM_FUSED, PK_PARTITION, PK_SCATTER, PK_DESCEND, PK_NORMAL, PK_ROOT, PK_OTHER,
+enum ProfKind { PK_EM_TILE = 0, PK_EM_BLOCK, PK_PARTITION, PK_SCATTER, PK_DESCEND, PK_NORMAL, PK_ROOT, PK_EM_MSTEP,
                 PK_COUNT };
 
 struct ProfPending {
@@ -475,26 +481,37 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
     const int njobs = (int)jobs.size();
     if (njobs == 0) break;
     const int tpts = tile_points(level_points);
-    int ntiles = 0, nbig = 0, nsmall = 0, nbigjobs = 0;
-    for (int j = 0; j < njobs; ++j)
-      if (jobs[j].count <= g_tune.fused_max) h_jids[nsmall++] = j;
+    // job classes: 0..2 one block of 64 / 256 / 512 threads per job for all
+    // iterations, 3 tiled; h_jids lists the jobs class by class
+    int ntiles = 0, nbig = 0;
+    int cls_n[4] = {0, 0, 0, 0}, cls_off[5] = {0, 0, 0, 0, 0};
+    int64_t cls_points[4] = {0, 0, 0, 0};
+    auto job_class = [](int count) {
+      return count <= g_tune.block64_max ? 0 : count <= g_tune.block256_max ? 1 : count <= g_tune.block512_max ? 2 : 3;
+    };
+    for (int j = 0; j < njobs; ++j) { cls_n[job_class(jobs[j].count)] += 1; cls_points[job_class(jobs[j].count)] += jobs[j].count; }
+    for (int c = 0; c < 4; ++c) cls_off[c + 1] = cls_off[c] + cls_n[c];
+    {
+      int fill[4] = {cls_off[0], cls_off[1], cls_off[2], cls_off[3]};
+      for (int j = 0; j < njobs; ++j) h_jids[fill[job_class(jobs[j].count)]++] = j;
+    }
     for (int j = 0; j < njobs; ++j) {
       Job& jb = jobs[j];
       jb.tile_first = ntiles;
       jb.ntiles = (jb.count + tpts - 1) / tpts;
-      const bool small = jb.count <= g_tune.fused_max;
+      const bool tiled = job_class(jb.count) == 3;
       for (int t = 0; t < jb.ntiles; ++t) {
         Tile& T = h_tiles[ntiles];
         T.start = jb.start + t * tpts;
         T.end = std::min(jb.start + jb.count, T.start + tpts);
         T.job = j;
         T.pad = 0;
-        if (!small) h_tids[nbig++] = ntiles;
+        if (tiled) h_tids[nbig++] = ntiles;
         ++ntiles;
       }
-      if (!small) h_jids[nsmall + nbigjobs++] = j;
       h_jobs[j] = jb;
     }
+    const int nbigjobs = cls_n[3];
     if (ntiles > Ly.max_tiles || njobs > Ly.max_jobs) return fail(HGMM_EINVAL, "internal: tile plan overflow");
     HIP_TRY(hipMemcpyAsync(d_jobs, h_jobs, sizeof(Job) * njobs, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d_tiles, h_tiles, sizeof(Tile) * ntiles, hipMemcpyHostToDevice, s));
@@ -517,18 +534,24 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
 
     // ---- EM for the 8 children of every job
     launch_init_children(d_jobs, njobs, f->d_trees, f->d_nodes, f->d_tab, p.reg_eps, s);
-    int64_t big_points = 0, small_points = 0;
-    for (int j = 0; j < njobs; ++j) (jobs[j].count <= g_tune.fused_max ? small_points : big_points) += jobs[j].count;
     if (nbig)
       for (int it = 0; it < p.build_iters; ++it) {
-        ProfScope ps(PK_EM_TILE, (double)big_points, s);
-        launch_em_tiles(cx, cy, cz, d_tiles, d_tile_ids, nbig, d_job_ids + nsmall, nbigjobs, d_jobs, f->d_tab,
-                        f->d_nodes, d_partials, (size_t)Ly.max_tiles, p.reg_eps, p.min_mass, s);
+        {
+          ProfScope ps(PK_EM_TILE, (double)cls_points[3], s);
+          launch_em_tile(cx, cy, cz, d_tiles, d_tile_ids, nbig, d_jobs, f->d_tab, d_partials, (size_t)Ly.max_tiles, s);
+        }
+        ProfScope ps(PK_EM_MSTEP, (double)nbigjobs, s);
+        launch_em_mstep(d_job_ids + cls_off[3], nbigjobs, d_jobs, f->d_tab, f->d_nodes, d_partials,
+                        (size_t)Ly.max_tiles, p.reg_eps, p.min_mass, s);
       }
-    if (nsmall && p.build_iters > 0) {
-      ProfScope ps(PK_EM_FUSED, (double)small_points * p.build_iters, s);
-      launch_em_fused(cx, cy, cz, d_job_ids, nsmall, d_jobs, f->d_tab, f->d_nodes, p.build_iters, p.reg_eps,
-                      p.min_mass, (g_tune.fused_max + 63) / 64 * 64, s);
+    if (p.build_iters > 0) {
+      const int nts[3] = {64, 256, 512};
+      for (int c = 0; c < 3; ++c) {
+        if (!cls_n[c]) continue;
+        ProfScope ps(PK_EM_BLOCK, (double)cls_points[c] * p.build_iters, s);
+        launch_em_block(nts[c], cx, cy, cz, d_job_ids + cls_off[c], cls_n[c], d_jobs, f->d_tab, f->d_nodes,
+                        p.build_iters, p.reg_eps, p.min_mass, s);
+      }
     }
     // ---- hard partition, child ranges, stable split, per-node statistics
     {
@@ -959,6 +982,16 @@ size_t hgmm_build_batch_workspace_bytes(const int64_t* offsets, const int32_t* l
 size_t hgmm_register_batch_workspace_bytes(hgmm_tree forest, const int64_t* offsets, int B) {
   if (!forest || check_offsets(offsets, B) || B != (int)forest->trees.size()) return 0;
   return reg_layout(offsets[B], forest->total_nodes(), B).total;
+}
+
+size_t hgmm_autotune_workspace_bytes(const int64_t* src_offsets, const int32_t* levels, const int64_t* tgt_offsets,
+                                     int B) {
+  const size_t b = hgmm_build_batch_workspace_bytes(src_offsets, levels, B);
+  if (b == 0 || !tgt_offsets) return b;
+  if (check_offsets(tgt_offsets, B)) return 0;
+  int64_t nodes = 0;
+  for (int i = 0; i < B; ++i) nodes += tree_nodes(levels[i]);
+  return std::max(b, reg_layout(tgt_offsets[B], nodes, B).total);
 }
 
 int hgmm_build_batch(const float* d_xyz, const int64_t* offsets, const int32_t* levels, int B,

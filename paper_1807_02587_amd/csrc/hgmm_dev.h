@@ -145,6 +145,33 @@ __device__ __forceinline__ double wave_sum_range(const double* p, int count, int
   return wave_sum_dd(s);
 }
 
+// Fixed-order FP64 totals of NV rows of `count` values each, row v starting at
+// p + v * stride.  Lane l adds elements l, l + 64, l + 128, ... in that order;
+// every round first issues the loads of U elements of all NV rows (NV * U
+// independent loads in flight), then adds them.  Wave-uniform results.
+template <int NV, int U>
+__device__ __forceinline__ void wave_fold(const double* __restrict__ p, size_t stride, int count, int lane,
+                                          double (&out)[NV]) {
+  double s[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) s[v] = 0.0;
+  for (int base = 0; base < count; base += 64 * U) {
+    double x[NV][U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int i = base + lane + 64 * k;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) x[v][k] = (i < count) ? p[(size_t)v * stride + i] : 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int k = 0; k < U; ++k) s[v] += x[v][k];
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) out[v] = wave_sum_dd(s[v]);
+}
+
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 // ---------------------------------------------------------------------------

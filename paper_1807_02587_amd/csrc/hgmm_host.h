@@ -16,11 +16,15 @@ void launch_root(const float* xs, const float* ys, const float* zs, const Tile* 
                  int njobs, TreeDev* trees, double* partials, size_t pstride, double eps, hipStream_t s);
 void launch_init_children(const Job* jobs, int njobs, const TreeDev* trees, NodeD* nodes, NodeF* tab, double eps,
                           hipStream_t s);
-void launch_em_tiles(const float* xs, const float* ys, const float* zs, const Tile* tiles, const int* tile_ids,
-                     int n, const int* bigjob_ids, int nbigjobs, const Job* jobs, NodeF* tab, NodeD* nodes,
-                     double* partials, size_t pstride, double eps, double min_mass, hipStream_t s);
-void launch_em_fused(const float* xs, const float* ys, const float* zs, const int* job_ids, int n, const Job* jobs,
-                     NodeF* tab, NodeD* nodes, int iters, double eps, double min_mass, int cap, hipStream_t s);
+// one EM iteration of the tiled jobs: tile partials, then the fold + M-step
+void launch_em_tile(const float* xs, const float* ys, const float* zs, const Tile* tiles, const int* tile_ids, int n,
+                    const Job* jobs, const NodeF* tab, double* partials, size_t pstride, hipStream_t s);
+void launch_em_mstep(const int* job_ids, int n, const Job* jobs, NodeF* tab, NodeD* nodes, const double* partials,
+                     size_t pstride, double eps, double min_mass, hipStream_t s);
+// all EM iterations of n jobs, one block of nt (64, 256 or 512) threads per job
+void launch_em_block(int nt, const float* xs, const float* ys, const float* zs, const int* job_ids, int n,
+                     const Job* jobs, NodeF* tab, NodeD* nodes, int iters, double eps, double min_mass,
+                     hipStream_t s);
 void launch_partition(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
                       const Job* jobs, const NodeF* tab, const NodeD* nodes, uint8_t* child, int* tile_counts,
                       hipStream_t s);

@@ -33,7 +33,7 @@ struct hgmm_mlp_s {
   int cap = 0;          // activation buffers sized for this many rows
   uint16_t* X = nullptr;
   float* Z[4] = {};
-  uint16_t* H[4] = {};  // H[0] unused (X), H[1..3] bf16 activations
+  uint16_t* H[4] = {};  // H[l]: bf16 input of layer l (P x kDims[l]); H[0] unused (X)
   float* dH = nullptr;
   float* dZf = nullptr;
   uint16_t* dZb = nullptr;
@@ -67,9 +67,11 @@ static int mlp_reserve(hgmm_mlp_s* m, int P) {
   mlp_free_acts(m);
   int rc = 0;
   rc |= dalloc(m->X, (int64_t)P * 1280);
+  // Z[l] is the pre-activation output of layer l (P x kDims[l+1]); H[l] is
+  // the bf16 input of layer l (P x kDims[l]), H[0] unused (the input is X)
   for (int l = 0; l < 4; ++l) {
     rc |= dalloc(m->Z[l], (int64_t)P * kDims[l + 1]);
-    rc |= dalloc(m->H[l], (int64_t)P * kDims[l + 1]);
+    if (l > 0) rc |= dalloc(m->H[l], (int64_t)P * kDims[l]);
   }
   rc |= dalloc(m->dH, (int64_t)P * 512);
   rc |= dalloc(m->dZf, (int64_t)P * 512);

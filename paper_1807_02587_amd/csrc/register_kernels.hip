@@ -6,12 +6,14 @@
 // chosen node is simple enough (complexity <= lambda_c), has no live children,
 // or is on the last level.  The point's weight at that node is its posterior
 // among the siblings of the last level visited.  Per-node moments are
-// aggregated across equal stop nodes inside a wavefront and added to FP64
-// bins.
-// M-step (Sec. 4.2, Eq. 8-16): per node with mass, the three eigen-directions
-// contribute weighted point-to-plane rows to 6x6 normal equations; the sums
-// are reduced in a fixed order and the last block solves them by Cholesky and
-// applies the exact rotation of the solved angle vector.
+// aggregated across equal stop nodes inside a wavefront; the 72 nodes of the
+// first two levels are binned in FP64 LDS and written as per-block partials,
+// deeper nodes are added to FP64 bins in HBM.
+// M-step (Sec. 4.2, Eq. 8-16): one 1024-thread block per pair folds the block
+// partials in a fixed order, lets every node with mass contribute weighted
+// point-to-plane rows along its three eigen-directions to the 6x6 normal
+// equations, solves them by Cholesky and applies the exact rotation of the
+// solved angle vector.
 #include "hgmm_dev.h"
 #include "hgmm_host.h"
 
@@ -272,9 +274,11 @@ __global__ __launch_bounds__(256) void fold_bins_kernel(const int2* __restrict__
   const int nl = T.levels >= 2 ? 72 : 8;
   const int2 pt = pair_tiles[pair];
   const int lane = __lane_id(), wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int i = wv; i < nl * 6; i += nw) {
-    const double v = wave_sum_range(partials + (size_t)i * pstride + pt.x, pt.y, lane);
-    if (lane == 0) bins[T.node_base * 6 + i] = v;
+  for (int node = wv; node < nl; node += nw) {
+    double v[6];
+    wave_fold<6, 4>(partials + (size_t)node * 6 * pstride + pt.x, pstride, pt.y, lane, v);
+    if (lane == 0)
+      for (int j = 0; j < 6; ++j) bins[(T.node_base + node) * 6 + j] = v[j];
   }
 }
 
@@ -364,19 +368,29 @@ __global__ __launch_bounds__(kNormThreads) void normal_kernel(double* bins, cons
   const double N = (double)n_moving[pair];
   const double o0 = T.origin[0], o1 = T.origin[1], o2 = T.origin[2];
   const int lane = __lane_id(), wv = threadIdx.x >> 6;
-  double acc[kNV];
-#pragma unroll
-  for (int v = 0; v < kNV; ++v) acc[v] = 0.0;
   const bool from_partials = (mode == 0);
+  // phase 1: fixed-order fold of the LDS-level nodes' block partials
+  __shared__ double lb[kLdsNodes * 6];
   if (from_partials) {
     const int2 pt = pair_tiles[pair];
     for (int node = wv; node < nl; node += kNormThreads / 64) {
       double b[6];
-#pragma unroll
-      for (int v = 0; v < 6; ++v) b[v] = wave_sum_range(dpart + (size_t)(node * 6 + v) * pstride + pt.x, pt.y, lane);
-      if (lane == 0 && b[0] > 0.0) node_terms(nodes[nb + node], b, N, o0, o1, o2, acc);
+      wave_fold<6, 4>(dpart + (size_t)node * 6 * pstride + pt.x, pstride, pt.y, lane, b);
+      if (lane == 0)
+        for (int j = 0; j < 6; ++j) lb[node * 6 + j] = b[j];
     }
+    __syncthreads();
   }
+  // phase 2: every node with mass adds its rows to the normal equations
+  double acc[kNV];
+#pragma unroll
+  for (int v = 0; v < kNV; ++v) acc[v] = 0.0;
+  if (from_partials)
+    for (int node = threadIdx.x; node < nl; node += kNormThreads) {
+      double b[6] = {lb[node * 6], lb[node * 6 + 1], lb[node * 6 + 2], lb[node * 6 + 3], lb[node * 6 + 4],
+                     lb[node * 6 + 5]};
+      if (b[0] > 0.0) node_terms(nodes[nb + node], b, N, o0, o1, o2, acc);
+    }
   for (int64_t g = (from_partials ? nl : 0) + threadIdx.x; g < nn; g += kNormThreads) {
     double* B = bins + (nb + g) * 6;
     const double m0 = B[0];

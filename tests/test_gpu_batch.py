@@ -1,0 +1,181 @@
+"""Batched form (many uneven pairs per call) against the FP64 oracle, tree by
+tree and pair by pair, and against itself under a partial activity mask.
+
+The forest's trees are fitted by shared launches whose tiling depends on the
+whole batch, so a tree is not bit-identical to a single-cloud build of the same
+points; it is held to the same per-level EM tolerances against the oracle.
+Registration of pair b depends only on pair b's tree, points and pose, so a
+pair's result does not depend on which other pairs are active.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import rotation_angle_deg, rotation_from_axis_angle, small_pair
+from gpu_helpers import compare_build_levels, to_oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EM1_TOL = dict(pi=1e-5, mu=1e-5, cov=1e-5)
+EM30_TOL = dict(pi=2e-3, mu=1e-3, cov=1e-2)
+POSE_TOL = 1e-4
+
+# (source points, target points, levels, seed): uneven sizes, one tree per depth
+# 1..3 and a cloud of 64 points
+CASES = [(3000, 2500, 2, 11), (777, 900, 1, 12), (5000, 4100, 3, 13), (10_000, 10_000, 2, 14), (64, 64, 1, 15)]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def hg():
+    import paper_1807_02587_amd as hg
+    assert torch.cuda.is_available()
+    return hg
+
+
+@pytest.fixture(scope="module")
+def batch():
+    pairs = [small_pair(seed, n=n, n_tgt=m, max_angle_deg=20) for n, m, _, seed in CASES]
+    src = np.concatenate([p.src for p in pairs], axis=1)
+    tgt = np.concatenate([p.tgt for p in pairs], axis=1)
+    soff = np.concatenate([[0], np.cumsum([p.src.shape[1] for p in pairs])]).astype(np.int64)
+    toff = np.concatenate([[0], np.cumsum([p.tgt.shape[1] for p in pairs])]).astype(np.int64)
+    levels = [L for _, _, L, _ in CASES]
+    return pairs, src, tgt, soff, toff, levels
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _starts(pairs):
+    """0.5 degree and 0.05 % of the extent away from the truth (the method is local)."""
+    R0 = np.stack([rotation_from_axis_angle([0.2, 0.9, -0.3], math.radians(0.5)) @ p.R_true for p in pairs])
+    t0 = np.stack([p.t_true + 0.0005 * p.extent * np.array([0.5, -0.2, 0.3]) for p in pairs])
+    return R0, t0
+
+
+MAX_ITERS = 100
+
+
+@pytest.mark.parametrize("iters", [1, 30])
+def test_build_batch_vs_oracle(hg, batch, iters):
+    pairs, src, _, soff, _, levels = batch
+    forest = hg.hgmm_build_batch(_cuda(src), soff, levels, build_iters=iters)
+    tol = EM1_TOL if iters == 1 else EM30_TOL
+    for b, p in enumerate(pairs):
+        log(f"[batch build] tree {b} n={p.src.shape[1]} levels={levels[b]} iters={iters}")
+        host = forest.export(b)
+        assert host["levels"] == levels[b] and host["n_points"] == p.src.shape[1]
+        glab = forest.labels(b).cpu().numpy()
+        assert glab.shape == (levels[b], p.src.shape[1])
+        compare_build_levels(oracle, host, glab, p.src, levels[b], 1e-6, 1.0, iters, tol, log,
+                             min_parent=0 if iters == 1 else 64)
+
+
+def test_register_batch_vs_oracle(hg, batch):
+    pairs, src, tgt, soff, toff, levels = batch
+    forest = hg.hgmm_build_batch(_cuda(src), soff, levels)
+    R0, t0 = _starts(pairs)
+    r = hg.hgmm_register_batch(forest, _cuda(tgt), toff, R0=R0, t0=t0, max_iters=MAX_ITERS)
+    compared = 0
+    for b, p in enumerate(pairs):
+        host = forest.export(b)
+        o = oracle.register(to_oracle(oracle, host), p.tgt, R0=R0[b], t0=t0[b], max_iters=MAX_ITERS)
+        dang = math.radians(rotation_angle_deg(r["R"][b], o["R"]))
+        dt = np.linalg.norm(r["t"][b] - o["t"]) / host["extent"]
+        log(f"[batch register] pair {b}: iters gpu {r['iters'][b]} oracle {o['iters']} status {r['status'][b]} "
+            f"{o['status']}  pose diff {dang:.2e} rad {dt:.2e} ext  err vs truth "
+            f"{rotation_angle_deg(r['R'][b], p.R_true):.4f} deg")
+        assert r["status"][b] == o["status"]
+        if o["status"] == 0 and o["iters"] < MAX_ITERS:
+            assert dang < POSE_TOL and dt < POSE_TOL
+            assert abs(int(r["iters"][b]) - o["iters"]) <= 2
+            assert abs(r["loglik"][b] - o["loglik"]) <= 1e-4 * max(1.0, abs(o["loglik"]))
+            compared += 1
+    assert compared >= 3
+
+
+def test_register_batch_active_mask_and_estep(hg, batch):
+    pairs, src, tgt, soff, toff, levels = batch
+    forest = hg.hgmm_build_batch(_cuda(src), soff, levels)
+    R0, t0 = _starts(pairs)
+    tg = _cuda(tgt)
+    full = hg.hgmm_register_batch(forest, tg, toff, R0=R0, t0=t0)
+    act = np.array([1, 0, 1, 0, 1], np.int32)
+    part = hg.hgmm_register_batch(forest, tg, toff, R0=R0, t0=t0, active=act)
+    for b in range(len(pairs)):
+        if act[b]:
+            np.testing.assert_array_equal(part["R"][b], full["R"][b])
+            np.testing.assert_array_equal(part["t"][b], full["t"][b])
+            assert part["iters"][b] == full["iters"][b]
+        else:
+            np.testing.assert_array_equal(part["R"][b], R0[b])
+            np.testing.assert_array_equal(part["t"][b], t0[b])
+            assert part["iters"][b] == 0
+    # one E-step per pair at the starting poses: mean log-likelihood against the oracle's
+    ll = hg.hgmm_estep_batch(forest, tg, toff, R0, t0)
+    for b, p in enumerate(pairs):
+        o = oracle.estep(to_oracle(oracle, forest.export(b)), p.tgt, R0[b], t0[b])
+        log(f"[batch estep] pair {b}: loglik gpu {ll[b]:.9f} oracle {o['loglik']:.9f}")
+        assert abs(ll[b] - o["loglik"]) <= 1e-5 * max(1.0, abs(o["loglik"]))
+
+
+def test_batch_argument_checks(hg, batch):
+    from paper_1807_02587_amd import HgmmError
+    pairs, src, tgt, soff, toff, levels = batch
+    forest = hg.hgmm_build_batch(_cuda(src), soff, levels)
+    with pytest.raises(HgmmError):   # batch size differs from the forest's
+        hg.hgmm_register_batch(forest, _cuda(tgt[:, :toff[2]]), toff[:3])
+    bad = soff.copy()
+    bad[2] = bad[1] - 1
+    with pytest.raises((HgmmError, AssertionError)):
+        hg.hgmm_build_batch(_cuda(src), bad, levels)
+    with pytest.raises(HgmmError):   # a cloud of fewer than 8 points
+        hg.hgmm_build_batch(_cuda(src[:, :12]), np.array([0, 5, 12]), [1, 1])
+
+
+def test_tiled_and_block_paths_agree(hg, batch):
+    """The same forest built with every parent tiled and with every parent in one
+    block: one EM iteration from identical initial children agrees to the FP32
+    moment tolerance (only the summation order differs)."""
+    pairs, src, _, soff, _, levels = batch
+    old = hg.hgmm_get_tuning()
+    try:
+        hg.hgmm_set_tuning(block64_max=0, block256_max=0, block512_max=0)
+        tiled = hg.hgmm_build_batch(_cuda(src), soff, levels, build_iters=1)
+        hg.hgmm_set_tuning(block64_max=1 << 20, block256_max=1 << 20, block512_max=1 << 20)
+        block = hg.hgmm_build_batch(_cuda(src), soff, levels, build_iters=1)
+    finally:
+        hg.hgmm_set_tuning(**old)
+    for b in range(len(pairs)):
+        a, c = tiled.export(b), block.export(b)
+        sl = slice(0, 8)   # level 0 starts from identical children in both
+        np.testing.assert_array_equal(a["live"][sl], c["live"][sl])
+        np.testing.assert_allclose(a["pi"][sl], c["pi"][sl], rtol=1e-5)
+        np.testing.assert_allclose(a["mu"][sl], c["mu"][sl], rtol=0, atol=1e-5 * a["extent"])
+
+
+def test_autotune_small_batch(hg, batch):
+    pairs, src, tgt, soff, toff, levels = batch
+    old = hg.hgmm_get_tuning()
+    try:
+        r = hg.hgmm_autotune(_cuda(src), soff, levels, _cuda(tgt), toff, reps=1, passes=1)
+        log(f"[autotune] {r}")
+        assert r["best_ms"] > 0 and r["best_ms"] <= r["start_ms"] * 1.0001
+        assert hg.hgmm_get_tuning() == r["tuning"]
+        # the tuned setting still builds a valid forest
+        f = hg.hgmm_build_batch(_cuda(src), soff, levels)
+        for b in range(len(pairs)):
+            h = f.export(b)
+            assert abs(h["pi"][:8][h["live"][:8] == 1].sum() - 1.0) < 1e-9
+    finally:
+        hg.hgmm_set_tuning(**old)
