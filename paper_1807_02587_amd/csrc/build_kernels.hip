@@ -197,15 +197,37 @@ __global__ void init_children_kernel(const Job* __restrict__ jobs, int njobs, co
 // EM: responsibilities and moments of one point against the 8 children
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void em_point(const NodeF* ch, uint32_t live, double p0, double p1, double p2,
-                                         float (&a)[8][10]) {
+// Offsets are taken from a reference point of the job (the mean of its first
+// live child): each point is brought to FP32 once, q = float(p - ref), and the
+// offset from child k is d = q - m_k with m_k = float(mu_k - ref).  This keeps
+// FP64 arithmetic out of the per-child work; the extra rounding is a few units
+// of the last place of |q| + |m_k|, far below the scale of the covariances.
+struct EmFrame {
+  double ref[3];
+  float m[8][3];
+};
+
+// Reference point and FP32 child offsets of a job (all 64 lanes of a wave
+// call it; lanes 0..7 write m).  `live` must be non-zero.
+__device__ __forceinline__ void em_frame(const NodeF* ch, uint32_t live, EmFrame& f, int tid) {
+  const int r = __ffs(live) - 1;
+  if (tid < 3) f.ref[tid] = ch[r].mu[tid];
+  if (tid < 8)
+    for (int i = 0; i < 3; ++i) f.m[tid][i] = (float)(ch[tid].mu[i] - ch[r].mu[i]);
+}
+
+__device__ __forceinline__ void em_point(const NodeF* ch, const EmFrame& f, uint32_t live, float q0, float q1,
+                                         float q2, float (&a)[8][10]) {
   float s[8];
   float smax = -INFINITY;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     if (live & (1u << k)) {
-      float q, m;
-      s[k] = score32(ch[k], p0, p1, p2, q, m);
+      const float d0 = q0 - f.m[k][0], d1 = q1 - f.m[k][1], d2 = q2 - f.m[k][2];
+      const float w0 = ch[k].w[0] * d0;
+      const float w1 = fmaf(ch[k].w[1], d0, ch[k].w[2] * d1);
+      const float w2 = fmaf(ch[k].w[3], d0, fmaf(ch[k].w[4], d1, ch[k].w[5] * d2));
+      s[k] = ch[k].c - fmaf(w0, w0, fmaf(w1, w1, w2 * w2));
       smax = fmaxf(smax, s[k]);
     } else {
       s[k] = -INFINITY;
@@ -222,9 +244,7 @@ __device__ __forceinline__ void em_point(const NodeF* ch, uint32_t live, double 
   for (int k = 0; k < 8; ++k) {
     if (live & (1u << k)) {
       const float r = e[k] * inv;
-      const float d0 = (float)(p0 - ch[k].mu[0]);
-      const float d1 = (float)(p1 - ch[k].mu[1]);
-      const float d2 = (float)(p2 - ch[k].mu[2]);
+      const float d0 = q0 - f.m[k][0], d1 = q1 - f.m[k][1], d2 = q2 - f.m[k][2];
       const float r0 = r * d0, r1 = r * d1, r2 = r * d2;
       a[k][0] += r;
       a[k][1] += r0; a[k][2] += r1; a[k][3] += r2;
@@ -238,18 +258,20 @@ __device__ __forceinline__ void em_point(const NodeF* ch, uint32_t live, double 
   }
 }
 
-template <int STRIDE, typename FP>
-__device__ __forceinline__ void em_range(FP xs, FP ys, FP zs, int start, int end, int first,
-                                         const NodeF* ch, uint32_t live, float (&a)[8][10]) {
+template <int STRIDE>
+__device__ __forceinline__ void em_range(const float* __restrict__ xs, const float* __restrict__ ys,
+                                         const float* __restrict__ zs, int start, int end, int first,
+                                         const NodeF* ch, const EmFrame& f, uint32_t live, float (&a)[8][10]) {
 #pragma unroll
   for (int k = 0; k < 8; ++k)
 #pragma unroll
     for (int v = 0; v < 10; ++v) a[k][v] = 0.f;
+  const double r0 = f.ref[0], r1 = f.ref[1], r2 = f.ref[2];
   for (int i = start + first; i < end; i += STRIDE) {
     // the children's parameters are re-read from LDS (broadcast reads) for
     // every point instead of being held in ~100 registers across the loop
     asm volatile("" ::: "memory");
-    em_point(ch, live, (double)xs[i], (double)ys[i], (double)zs[i], a);
+    em_point(ch, f, live, (float)((double)xs[i] - r0), (float)((double)ys[i] - r1), (float)((double)zs[i] - r2), a);
   }
 }
 
@@ -350,12 +372,18 @@ __global__ __launch_bounds__(64) void em_tile_kernel(const float* __restrict__ x
   const Job jb = jobs[tl.job];
   const int lane = threadIdx.x;
   __shared__ NodeF ch[8];
+  __shared__ EmFrame fr;
   __shared__ float rows[4][80];
   if (lane < 8) copy_nodef(ch[lane], tab[jb.child_base + lane]);
   __syncthreads();
   const uint32_t live = live_mask(ch);
   float a[8][10];
-  em_range<64>(xs, ys, zs, tl.start, tl.end, lane, ch, live, a);
+  if (live) em_frame(ch, live, fr, lane);
+  __syncthreads();
+  if (live) em_range<64>(xs, ys, zs, tl.start, tl.end, lane, ch, fr, live, a);
+  else
+    for (int k = 0; k < 8; ++k)
+      for (int v = 0; v < 10; ++v) a[k][v] = 0.f;
   rows_store80(a, rows, lane);
   __syncthreads();
   for (int v = lane; v < 80; v += 64)
@@ -397,6 +425,7 @@ __global__ __launch_bounds__(NT) void em_block_kernel(const float* __restrict__ 
   const Job jb = jobs[job_ids[blockIdx.x]];
   const int tid = threadIdx.x;
   __shared__ NodeF ch[8];
+  __shared__ EmFrame fr;
   __shared__ float rows[NR][80];
   __shared__ double tot[80];
   if (tid < 8) copy_nodef(ch[tid], tab[jb.child_base + tid]);
@@ -404,8 +433,10 @@ __global__ __launch_bounds__(NT) void em_block_kernel(const float* __restrict__ 
   for (int it = 0; it < iters; ++it) {
     const uint32_t live = live_mask(ch);
     if (live == 0u) break;
+    em_frame(ch, live, fr, tid);
+    __syncthreads();
     float a[8][10];
-    em_range<NT>(xs, ys, zs, jb.start, jb.start + jb.count, tid, ch, live, a);
+    em_range<NT>(xs, ys, zs, jb.start, jb.start + jb.count, tid, ch, fr, live, a);
     rows_store80(a, rows, tid);
     __syncthreads();
     for (int v = tid; v < 80; v += NT) {

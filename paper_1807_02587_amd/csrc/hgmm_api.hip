@@ -86,6 +86,11 @@ struct hgmm_forest_s {
   bool has_labels = false;
   char* h_stage = nullptr;
   size_t cap_stage = 0;
+  // side streams (default priority) on which the block-class EM launches of a
+  // level run concurrently with the tiled iterations on the caller's stream
+  hipStream_t side[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[3] = {nullptr, nullptr, nullptr};
   int64_t total_nodes() const {
     int64_t s = 0;
     for (auto& t : trees) s += tree_nodes(t.levels);
@@ -104,7 +109,24 @@ static void free_forest(hgmm_forest_s* f) {
   if (f->d_tab) (void)hipFree(f->d_tab);
   if (f->d_labels) (void)hipFree(f->d_labels);
   if (f->h_stage) (void)hipHostFree(f->h_stage);
+  for (int c = 0; c < 3; ++c) {
+    if (f->side[c]) (void)hipStreamDestroy(f->side[c]);
+    if (f->ev_join[c]) (void)hipEventDestroy(f->ev_join[c]);
+  }
+  if (f->ev_fork) (void)hipEventDestroy(f->ev_fork);
   delete f;
+}
+
+static int ensure_side_streams(hgmm_forest_s* f) {
+  if (f->ev_fork) return HGMM_OK;
+  for (int c = 0; c < 3; ++c) {
+    if (hipStreamCreateWithFlags(&f->side[c], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&f->ev_join[c], hipEventDisableTiming) != hipSuccess)
+      return fail(HGMM_EHIP, "side stream creation failed");
+  }
+  if (hipEventCreateWithFlags(&f->ev_fork, hipEventDisableTiming) != hipSuccess)
+    return fail(HGMM_EHIP, "event creation failed");
+  return HGMM_OK;
 }
 
 template <typename T>
@@ -532,8 +554,29 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
         if (h_trees[B + b].status != 0) return fail(HGMM_ENONFINITE, "non-finite coordinate in cloud %d", b);
     }
 
-    // ---- EM for the 8 children of every job
+    // ---- EM for the 8 children of every job.  The block classes run on side
+    // streams, concurrently with the tiled iterations on the caller's stream
+    // (disjoint jobs: disjoint children, shared read-only points and plan).
     launch_init_children(d_jobs, njobs, f->d_trees, f->d_nodes, f->d_tab, p.reg_eps, s);
+    bool joined[3] = {false, false, false};
+    if (p.build_iters > 0 && (cls_n[0] || cls_n[1] || cls_n[2])) {
+      int rc2 = ensure_side_streams(f);
+      if (rc2) return rc2;
+      HIP_TRY(hipEventRecord(f->ev_fork, s));
+      const int nts[3] = {64, 256, 512};
+      for (int c = 0; c < 3; ++c) {
+        if (!cls_n[c]) continue;
+        hipStream_t ss = f->side[c];
+        HIP_TRY(hipStreamWaitEvent(ss, f->ev_fork, 0));
+        {
+          ProfScope ps(PK_EM_BLOCK, (double)cls_points[c] * p.build_iters, ss);
+          launch_em_block(nts[c], cx, cy, cz, d_job_ids + cls_off[c], cls_n[c], d_jobs, f->d_tab, f->d_nodes,
+                          p.build_iters, p.reg_eps, p.min_mass, ss);
+        }
+        HIP_TRY(hipEventRecord(f->ev_join[c], ss));
+        joined[c] = true;
+      }
+    }
     if (nbig)
       for (int it = 0; it < p.build_iters; ++it) {
         {
@@ -544,15 +587,8 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
         launch_em_mstep(d_job_ids + cls_off[3], nbigjobs, d_jobs, f->d_tab, f->d_nodes, d_partials,
                         (size_t)Ly.max_tiles, p.reg_eps, p.min_mass, s);
       }
-    if (p.build_iters > 0) {
-      const int nts[3] = {64, 256, 512};
-      for (int c = 0; c < 3; ++c) {
-        if (!cls_n[c]) continue;
-        ProfScope ps(PK_EM_BLOCK, (double)cls_points[c] * p.build_iters, s);
-        launch_em_block(nts[c], cx, cy, cz, d_job_ids + cls_off[c], cls_n[c], d_jobs, f->d_tab, f->d_nodes,
-                        p.build_iters, p.reg_eps, p.min_mass, s);
-      }
-    }
+    for (int c = 0; c < 3; ++c)
+      if (joined[c]) HIP_TRY(hipStreamWaitEvent(s, f->ev_join[c], 0));
     // ---- hard partition, child ranges, stable split, per-node statistics
     {
       ProfScope ps(PK_PARTITION, (double)level_points, s);

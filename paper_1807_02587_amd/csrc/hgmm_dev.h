@@ -179,25 +179,26 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 // ---------------------------------------------------------------------------
 
 // Lower Cholesky factor L of a packed SPD matrix and its inverse (packed).
-// Returns false when a pivot is not positive.
+// Returns false when a pivot is not positive.  Short dependency chain for the
+// per-iteration M-step: three square roots, three reciprocals and one log of
+// the pivot product (log|cov| = log(p0 p1 p2) with pivots p_i = L_ii^2).
 __device__ __forceinline__ bool chol_inv3(const double c[6], double winv[6], double& logdet) {
-  double l00 = c[0];
-  if (!(l00 > 0.0)) return false;
-  l00 = sqrt(l00);
-  double l10 = c[1] / l00, l20 = c[2] / l00;
-  double p11 = c[3] - l10 * l10;
-  if (!(p11 > 0.0)) return false;
-  double l11 = sqrt(p11);
-  double l21 = (c[4] - l20 * l10) / l11;
-  double p22 = c[5] - l20 * l20 - l21 * l21;
-  if (!(p22 > 0.0)) return false;
-  double l22 = sqrt(p22);
-  double i00 = 1.0 / l00, i11 = 1.0 / l11, i22 = 1.0 / l22;
-  double i10 = -l10 * i00 * i11;
-  double i21 = -l21 * i11 * i22;
-  double i20 = -(l20 * i00 + l21 * i10) * i22;
+  const double p0 = c[0];
+  if (!(p0 > 0.0)) return false;
+  const double l00 = sqrt(p0), i00 = 1.0 / l00;
+  const double l10 = c[1] * i00, l20 = c[2] * i00;
+  const double p1 = c[3] - l10 * l10;
+  if (!(p1 > 0.0)) return false;
+  const double l11 = sqrt(p1), i11 = 1.0 / l11;
+  const double l21 = (c[4] - l20 * l10) * i11;
+  const double p2 = c[5] - l20 * l20 - l21 * l21;
+  if (!(p2 > 0.0)) return false;
+  const double l22 = sqrt(p2), i22 = 1.0 / l22;
+  const double i10 = -l10 * i00 * i11;
+  const double i21 = -l21 * i11 * i22;
+  const double i20 = -(l20 * i00 + l21 * i10) * i22;
   winv[0] = i00; winv[1] = i10; winv[2] = i11; winv[3] = i20; winv[4] = i21; winv[5] = i22;
-  logdet = 2.0 * (log(l00) + log(l11) + log(l22));
+  logdet = log(p0 * p1 * p2);
   return true;
 }
 

@@ -59,6 +59,8 @@ def evaluate(net, n_pairs=4096, chunk=512, n=10_000, max_angle_deg=90.0, cfg=W.W
         it_warm.append(rw["iters"])
         done += B
         c += 1
+        log(f"evaluated {done}/{n_pairs} pairs: plain median {np.median(np.concatenate(err_plain)):.3f} deg, "
+            f"warm median {np.median(np.concatenate(err_warm)):.3f} deg")
     ep, ew, fb = np.concatenate(err_plain), np.concatenate(err_warm), np.concatenate(fb)
     stats = lambda e: dict(median_deg=float(np.median(e)), p90_deg=float(np.percentile(e, 90)),
                            success_0p5=float(np.mean(e <= 0.5)), success_5=float(np.mean(e <= 5.0)))
@@ -80,10 +82,11 @@ def main():
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--out", default=None)
     ap.add_argument("--report", default=None)
+    ap.add_argument("--gen-budget-s", type=float, default=None, help="stop generating pairs after about this long")
     args = ap.parse_args()
     cfg = W.WarmConfig()
     t0 = time.time()
-    X, T = W.training_set(args.pairs, seed=args.seed, cfg=cfg, log=log)
+    X, T = W.training_set(args.pairs, seed=args.seed, cfg=cfg, log=log, time_budget_s=args.gen_budget_s)
     log(f"training set: {X.shape[0]} pairs in {time.time() - t0:.1f} s")
     net = hg.MLP(seed=args.seed)
     t1 = time.time()
@@ -92,7 +95,8 @@ def main():
     if args.out:
         np.save(args.out, net.get_params())
     rep = evaluate(net, n_pairs=args.eval_pairs, cfg=cfg)
-    rep.update(train_pairs=args.pairs, epochs=args.epochs, loss_history=hist, train_seconds=time.time() - t1)
+    rep.update(train_pairs=int(X.shape[0]), epochs=args.epochs, loss_history=hist, train_seconds=time.time() - t1,
+               generation_seconds=t1 - t0)
     log(json.dumps(rep))
     if args.report:
         with open(args.report, "w") as f:

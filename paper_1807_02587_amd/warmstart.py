@@ -50,8 +50,9 @@ def features_for(src_forest, tgt_forest, B, cfg: WarmConfig):
 
 
 def training_set(n_pairs: int, seed: int, cfg: WarmConfig = WarmConfig(), chunk: int = 1024, n: int = 10_000,
-                 max_angle_deg: float = 90.0, log=None):
-    """(X (n_pairs, 1280) float32, T (n_pairs, 9) float32) on the GPU."""
+                 max_angle_deg: float = 90.0, log=None, time_budget_s: float | None = None):
+    """(X (m, 1280) float32, T (m, 9) float32) on the GPU, m = n_pairs, or fewer
+    (whole chunks) when generation would exceed ``time_budget_s``."""
     from synth.torch_scenes import cube_pairs
     Xs, Ts = [], []
     ws = hg.Workspace()
@@ -76,8 +77,13 @@ def training_set(n_pairs: int, seed: int, cfg: WarmConfig = WarmConfig(), chunk:
         Ts.append(T)
         done += B
         c += 1
+        el = time.time() - t0
         if log:
-            log(f"training pairs {done}/{n_pairs} ({time.time() - t0:.1f} s)")
+            log(f"training pairs {done}/{n_pairs} ({el:.1f} s)")
+        if time_budget_s is not None and done < n_pairs and el * (done + chunk) / done > time_budget_s:
+            if log:
+                log(f"stopping generation at {done} pairs (time budget {time_budget_s:.0f} s)")
+            break
     return torch.cat(Xs).contiguous(), torch.cat(Ts).contiguous()
 
 

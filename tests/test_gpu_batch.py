@@ -95,13 +95,14 @@ def test_register_batch_vs_oracle(hg, batch):
         log(f"[batch register] pair {b}: iters gpu {r['iters'][b]} oracle {o['iters']} status {r['status'][b]} "
             f"{o['status']}  pose diff {dang:.2e} rad {dt:.2e} ext  err vs truth "
             f"{rotation_angle_deg(r['R'][b], p.R_true):.4f} deg")
-        assert r["status"][b] == o["status"]
-        if o["status"] == 0 and o["iters"] < MAX_ITERS:
-            assert dang < POSE_TOL and dt < POSE_TOL
-            assert abs(int(r["iters"][b]) - o["iters"]) <= 2
-            assert abs(r["loglik"][b] - o["loglik"]) <= 1e-4 * max(1.0, abs(o["loglik"]))
-            compared += 1
-    assert compared >= 3
+        # the same trajectory, whether or not it converges (small clouds at
+        # lambda_c = 0.01 can drift away from the truth under the method itself)
+        assert r["status"][b] == o["status"] == 0
+        assert dang < POSE_TOL and dt < POSE_TOL
+        assert abs(int(r["iters"][b]) - o["iters"]) <= 2
+        assert abs(r["loglik"][b] - o["loglik"]) <= 1e-4 * max(1.0, abs(o["loglik"]))
+        compared += o["iters"] < MAX_ITERS
+    log(f"[batch register] {compared} of {len(pairs)} pairs converged within {MAX_ITERS} iterations")
 
 
 def test_register_batch_active_mask_and_estep(hg, batch):
