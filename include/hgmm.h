@@ -266,18 +266,25 @@ void hgmm_tree_destroy(hgmm_tree tree);
  * tile are level_points / target_tiles rounded up to a multiple of 64 and
  * clamped to [min_tile, max_tile].  Registration: reg_tile points per
  * 256-thread descent block (a multiple of 256); reg_chunk iterations are
- * queued between two convergence checks on the host.
- * Defaults 256, 2048, 8192, 256, 1024, 4096, 512, 4. */
+ * queued between two convergence checks on the host.  reg_graph = 1 captures
+ * one chunk (descent + normal equations, reg_chunk times) in a hipGraph on a
+ * library-owned stream joined to the caller's by events; the instantiated
+ * graph is kept in the tree handle and reused while the call's sizes,
+ * buffers and knobs stay the same.  Timing with hgmm_profile(1) uses plain
+ * launches.
+ * Defaults 256, 2048, 8192, 256, 1024, 4096, 512, 4, 0. */
 typedef struct hgmm_tuning {
   int32_t block64_max, block256_max, block512_max;
   int32_t min_tile, target_tiles, max_tile;
   int32_t reg_tile, reg_chunk;
+  int32_t reg_graph;  /* 1: each chunk of registration iterations is one hipGraph launch */
 } hgmm_tuning;
 
 /* Set (after validation) or read the launch shapes.  hgmm_set_tuning returns
  * HGMM_EINVAL, changing nothing, unless 0 <= block64_max <= block256_max <=
  * block512_max <= 1<<20, 64 <= min_tile <= max_tile <= 1<<20,
- * target_tiles >= 1, 256 <= reg_tile <= 1<<20 and 1 <= reg_chunk <= 64.
+ * target_tiles >= 1, 256 <= reg_tile <= 1<<20, 1 <= reg_chunk <= 64 and
+ * reg_graph in {0, 1}.
  * Values are rounded up to the multiples stated above.  Not thread-safe
  * against concurrent calls of the library. */
 int hgmm_set_tuning(const hgmm_tuning *t);

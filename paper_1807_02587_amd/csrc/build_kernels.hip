@@ -258,20 +258,58 @@ __device__ __forceinline__ void em_point(const NodeF* ch, const EmFrame& f, uint
   }
 }
 
-template <int STRIDE>
+// Up to KP points of one thread (points first, first + STRIDE, ...) held in
+// registers: loaded once with all loads in flight together, then reused (by
+// every EM iteration of a block-per-parent job).
+template <int KP>
+struct PointCache {
+  float x[KP], y[KP], z[KP];
+};
+
+template <int STRIDE, int KP>
+__device__ __forceinline__ void load_points(const float* __restrict__ xs, const float* __restrict__ ys,
+                                            const float* __restrict__ zs, int start, int end, int first,
+                                            PointCache<KP>& c) {
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int i = start + first + k * STRIDE;
+    const bool ok = i < end;
+    c.x[k] = ok ? xs[i] : 0.f;
+    c.y[k] = ok ? ys[i] : 0.f;
+    c.z[k] = ok ? zs[i] : 0.f;
+  }
+}
+
+// Moments of this thread's points of [start, end): the first KP come from the
+// cache, any further ones are streamed with the next point's loads issued
+// before the current point's arithmetic.
+template <int STRIDE, int KP>
 __device__ __forceinline__ void em_range(const float* __restrict__ xs, const float* __restrict__ ys,
                                          const float* __restrict__ zs, int start, int end, int first,
-                                         const NodeF* ch, const EmFrame& f, uint32_t live, float (&a)[8][10]) {
+                                         const PointCache<KP>& c, const NodeF* ch, const EmFrame& f,
+                                         uint32_t live, float (&a)[8][10]) {
 #pragma unroll
   for (int k = 0; k < 8; ++k)
 #pragma unroll
     for (int v = 0; v < 10; ++v) a[k][v] = 0.f;
   const double r0 = f.ref[0], r1 = f.ref[1], r2 = f.ref[2];
-  for (int i = start + first; i < end; i += STRIDE) {
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    if (start + first + k * STRIDE >= end) break;
     // the children's parameters are re-read from LDS (broadcast reads) for
     // every point instead of being held in ~100 registers across the loop
     asm volatile("" ::: "memory");
-    em_point(ch, f, live, (float)((double)xs[i] - r0), (float)((double)ys[i] - r1), (float)((double)zs[i] - r2), a);
+    em_point(ch, f, live, (float)((double)c.x[k] - r0), (float)((double)c.y[k] - r1), (float)((double)c.z[k] - r2),
+             a);
+  }
+  int i = start + first + KP * STRIDE;
+  if (i >= end) return;
+  float nx = xs[i], ny = ys[i], nz = zs[i];
+  for (; i < end; i += STRIDE) {
+    const float px = nx, py = ny, pz = nz;
+    if (i + STRIDE < end) { nx = xs[i + STRIDE]; ny = ys[i + STRIDE]; nz = zs[i + STRIDE]; }
+    asm volatile("" ::: "memory");
+    em_point(ch, f, live, (float)((double)px - r0), (float)((double)py - r1), (float)((double)pz - r2), a);
   }
 }
 
@@ -380,7 +418,11 @@ __global__ __launch_bounds__(64) void em_tile_kernel(const float* __restrict__ x
   float a[8][10];
   if (live) em_frame(ch, live, fr, lane);
   __syncthreads();
-  if (live) em_range<64>(xs, ys, zs, tl.start, tl.end, lane, ch, fr, live, a);
+  if (live) {
+    PointCache<4> pc;
+    load_points<64>(xs, ys, zs, tl.start, tl.end, lane, pc);
+    em_range<64>(xs, ys, zs, tl.start, tl.end, lane, pc, ch, fr, live, a);
+  }
   else
     for (int k = 0; k < 8; ++k)
       for (int v = 0; v < 10; ++v) a[k][v] = 0.f;
@@ -429,6 +471,8 @@ __global__ __launch_bounds__(NT) void em_block_kernel(const float* __restrict__ 
   __shared__ float rows[NR][80];
   __shared__ double tot[80];
   if (tid < 8) copy_nodef(ch[tid], tab[jb.child_base + tid]);
+  PointCache<8> pc;
+  load_points<NT>(xs, ys, zs, jb.start, jb.start + jb.count, tid, pc);
   __syncthreads();
   for (int it = 0; it < iters; ++it) {
     const uint32_t live = live_mask(ch);
@@ -436,7 +480,7 @@ __global__ __launch_bounds__(NT) void em_block_kernel(const float* __restrict__ 
     em_frame(ch, live, fr, tid);
     __syncthreads();
     float a[8][10];
-    em_range<NT>(xs, ys, zs, jb.start, jb.start + jb.count, tid, ch, fr, live, a);
+    em_range<NT>(xs, ys, zs, jb.start, jb.start + jb.count, tid, pc, ch, fr, live, a);
     rows_store80(a, rows, tid);
     __syncthreads();
     for (int v = tid; v < 80; v += NT) {

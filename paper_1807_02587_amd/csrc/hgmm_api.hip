@@ -91,6 +91,12 @@ struct hgmm_forest_s {
   hipStream_t side[3] = {nullptr, nullptr, nullptr};
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[3] = {nullptr, nullptr, nullptr};
+  // registration chunk graph (reg_graph = 1): capture stream, fork/join
+  // events, the instantiated graph and the launch arguments it was built for
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev_g0 = nullptr, ev_g1 = nullptr;
+  hipGraphExec_t reg_exec = nullptr;
+  std::vector<uint64_t> reg_key;
   int64_t total_nodes() const {
     int64_t s = 0;
     for (auto& t : trees) s += tree_nodes(t.levels);
@@ -114,7 +120,20 @@ static void free_forest(hgmm_forest_s* f) {
     if (f->ev_join[c]) (void)hipEventDestroy(f->ev_join[c]);
   }
   if (f->ev_fork) (void)hipEventDestroy(f->ev_fork);
+  if (f->reg_exec) (void)hipGraphExecDestroy(f->reg_exec);
+  if (f->gstream) (void)hipStreamDestroy(f->gstream);
+  if (f->ev_g0) (void)hipEventDestroy(f->ev_g0);
+  if (f->ev_g1) (void)hipEventDestroy(f->ev_g1);
   delete f;
+}
+
+static int ensure_graph_stream(hgmm_forest_s* f) {
+  if (f->gstream) return HGMM_OK;
+  if (hipStreamCreateWithFlags(&f->gstream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&f->ev_g0, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&f->ev_g1, hipEventDisableTiming) != hipSuccess)
+    return fail(HGMM_EHIP, "graph stream creation failed");
+  return HGMM_OK;
 }
 
 static int ensure_side_streams(hgmm_forest_s* f) {
@@ -261,7 +280,7 @@ static int64_t max_lvl_for(const std::vector<TreeHost>& trees) {
 // launch shapes (process wide; see hgmm_tuning)
 // ---------------------------------------------------------------------------
 
-static hgmm_tuning g_tune = {256, 2048, 8192, 256, 1024, 4096, 512, 4};
+static hgmm_tuning g_tune = {256, 2048, 8192, 256, 1024, 4096, 512, 4, 0};
 
 extern "C" int hgmm_set_tuning(const hgmm_tuning* t) {
   if (!t) return fail(HGMM_EINVAL, "null tuning");
@@ -273,6 +292,7 @@ extern "C" int hgmm_set_tuning(const hgmm_tuning* t) {
     return fail(HGMM_EINVAL, "tile sizes must satisfy 64 <= min_tile <= max_tile <= 2^20, target_tiles >= 1");
   if (!(256 <= t->reg_tile && t->reg_tile <= lim && 1 <= t->reg_chunk && t->reg_chunk <= 64))
     return fail(HGMM_EINVAL, "reg_tile must be in [256, 2^20] and reg_chunk in [1, 64]");
+  if (t->reg_graph != 0 && t->reg_graph != 1) return fail(HGMM_EINVAL, "reg_graph must be 0 or 1");
   g_tune = *t;
   g_tune.min_tile = (t->min_tile + 63) / 64 * 64;
   g_tune.max_tile = (t->max_tile + 63) / 64 * 64;
@@ -713,8 +733,8 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
                    stop_out, gamma_out, s);
     launch_fold_bins(d_ptiles, f->d_trees, d_dpart, pstride, d_bins, P, s);
     if (h_norm) {
-      launch_normal(d_bins, d_dpart, pstride, d_ptiles, f->d_nodes, f->d_trees, d_state, d_nmov, P, 1, 0.0, 0.0, d_out,
-                    s);
+      launch_normal(d_bins, d_dpart, pstride, d_ptiles, f->d_nodes, f->d_trees, d_state, d_nmov, P, 1, 0.0, 0.0, 1,
+                    d_out, s);
       HIP_TRY(hipMemcpyAsync(h_nrm, d_out, sizeof(double) * 28 * P, hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       memcpy(h_norm, h_nrm, sizeof(double) * 28 * P);
@@ -726,6 +746,51 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   // pair has converged so that no further launches are queued
   int it = 0;
   const int chunk = std::max(1, g_tune.reg_chunk);
+  if (g_tune.reg_graph && !g_prof.on) {
+    int rc2 = ensure_graph_stream(f);
+    if (rc2) return rc2;
+    uint64_t tr, tt;
+    memcpy(&tr, &rr.tol_rot, 8);
+    memcpy(&tt, &rr.tol_trans_rel, 8);
+    const std::vector<uint64_t> key = {(uint64_t)xs, (uint64_t)ys, (uint64_t)zs, (uint64_t)d_tiles, (uint64_t)ntiles,
+                                       (uint64_t)f->d_trees, (uint64_t)f->d_tab, (uint64_t)f->d_nodes,
+                                       (uint64_t)d_state, (uint64_t)d_bins, (uint64_t)d_dpart, (uint64_t)pstride,
+                                       (uint64_t)d_ptiles, (uint64_t)d_nmov, (uint64_t)P, (uint64_t)chunk, tr, tt,
+                                       (uint64_t)rr.max_iters, (uint64_t)d_out};
+    if (!f->reg_exec || f->reg_key != key) {
+      if (f->reg_exec) { (void)hipGraphExecDestroy(f->reg_exec); f->reg_exec = nullptr; }
+      f->reg_key.clear();
+      HIP_TRY(hipStreamBeginCapture(f->gstream, hipStreamCaptureModeThreadLocal));
+      for (int c = 0; c < chunk; ++c) {
+        launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins, d_dpart,
+                       pstride, nullptr, nullptr, f->gstream);
+        launch_normal(d_bins, d_dpart, pstride, d_ptiles, f->d_nodes, f->d_trees, d_state, d_nmov, P, 0, rr.tol_rot,
+                      rr.tol_trans_rel, rr.max_iters, d_out, f->gstream);
+      }
+      hipGraph_t graph = nullptr;
+      const hipError_t ec = hipStreamEndCapture(f->gstream, &graph);
+      if (ec != hipSuccess || !graph) return fail(HGMM_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+      const hipError_t ei = hipGraphInstantiate(&f->reg_exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) { f->reg_exec = nullptr; return fail(HGMM_EHIP, "graph instantiation failed"); }
+      f->reg_key = key;
+    }
+    HIP_TRY(hipEventRecord(f->ev_g0, s));
+    HIP_TRY(hipStreamWaitEvent(f->gstream, f->ev_g0, 0));
+    while (it < rr.max_iters) {
+      HIP_TRY(hipGraphLaunch(f->reg_exec, f->gstream));
+      it += chunk;
+      HIP_TRY(hipMemcpyAsync(h_res, d_state, sizeof(PoseState) * P, hipMemcpyDeviceToHost, f->gstream));
+      HIP_TRY(hipStreamSynchronize(f->gstream));
+      bool all_done = true;
+      for (int b = 0; b < P; ++b) all_done = all_done && (h_res[b].done != 0);
+      if (all_done) break;
+    }
+    HIP_TRY(hipEventRecord(f->ev_g1, f->gstream));
+    HIP_TRY(hipStreamWaitEvent(s, f->ev_g1, 0));
+    memcpy(h_out, h_res, sizeof(PoseState) * P);
+    return HGMM_OK;
+  }
   while (it < rr.max_iters) {
     const int end = std::min(rr.max_iters, it + chunk);
     for (; it < end; ++it) {
@@ -737,7 +802,7 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
       {
         ProfScope ps(PK_NORMAL, (double)nodes_total, s, it);
         launch_normal(d_bins, d_dpart, pstride, d_ptiles, f->d_nodes, f->d_trees, d_state, d_nmov, P, 0, rr.tol_rot,
-                      rr.tol_trans_rel, d_out, s);
+                      rr.tol_trans_rel, rr.max_iters, d_out, s);
       }
     }
     HIP_LAUNCHED();
@@ -885,7 +950,7 @@ int hgmm_normal_equations(hgmm_tree tree, const double* d_bins, int64_t n, void*
   launch_init_pose((PoseState*)(ws + Ly.state), 1, d_pose0, d_pose0 + 9, 0, nullptr, s);
   // the kernel reads the bins without modifying them in mode 1
   launch_normal(const_cast<double*>(d_bins), nullptr, 0, nullptr, tree->d_nodes, tree->d_trees,
-                (PoseState*)(ws + Ly.state), d_nmov, 1, 1, 0.0, 0.0, d_out, s);
+                (PoseState*)(ws + Ly.state), d_nmov, 1, 1, 0.0, 0.0, 1, d_out, s);
   HIP_LAUNCHED();
   double* hres = h + 16;
   HIP_TRY(hipMemcpyAsync(hres, d_out, sizeof(double) * 28, hipMemcpyDeviceToHost, s));

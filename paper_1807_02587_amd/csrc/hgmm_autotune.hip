@@ -32,6 +32,7 @@ const std::vector<Knob>& knobs() {
       {&hgmm_tuning::max_tile, {1024, 2048, 4096, 8192}},
       {&hgmm_tuning::reg_tile, {256, 512, 1024, 2048}},
       {&hgmm_tuning::reg_chunk, {2, 4, 8, 16}},
+      {&hgmm_tuning::reg_graph, {0, 1}},
   };
   return k;
 }

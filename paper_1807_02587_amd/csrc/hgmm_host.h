@@ -47,7 +47,7 @@ void launch_fold_bins(const int2* pair_tiles, const TreeDev* trees, const double
                       double* bins, int npairs, hipStream_t s);
 void launch_normal(double* bins, const double* dpart, size_t pstride, const int2* pair_tiles, const NodeD* nodes,
                    const TreeDev* trees, PoseState* st, const int64_t* n_moving, int npairs, int mode, double tol_rot,
-                   double tol_trans_rel, double* out, hipStream_t s);
+                   double tol_trans_rel, int max_iters, double* out, hipStream_t s);
 int normal_values();
 
 // import / export

@@ -357,7 +357,8 @@ __global__ __launch_bounds__(kNormThreads) void normal_kernel(double* bins, cons
                                                               const NodeD* __restrict__ nodes,
                                                               const TreeDev* __restrict__ trees, PoseState* st,
                                                               const int64_t* __restrict__ n_moving, int mode,
-                                                              double tol_rot, double tol_trans_rel, double* out) {
+                                                              double tol_rot, double tol_trans_rel, int max_iters,
+                                                              double* out) {
   const int pair = blockIdx.x;
   PoseState& S = st[pair];
   if (S.done) return;
@@ -456,7 +457,7 @@ __global__ __launch_bounds__(kNormThreads) void normal_kernel(double* bins, cons
   for (int i = 0; i < 9; ++i) S.R[i] = Rn[i];
   for (int i = 0; i < 3; ++i) S.t[i] = tn[i];
   const double tau = sqrt(x[3] * x[3] + x[4] * x[4] + x[5] * x[5]);
-  if (th < tol_rot && tau < tol_trans_rel * T.extent) S.done = 1;
+  if ((th < tol_rot && tau < tol_trans_rel * T.extent) || S.iters >= max_iters) S.done = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -513,9 +514,9 @@ void launch_fold_bins(const int2* pair_tiles, const TreeDev* trees, const double
 
 void launch_normal(double* bins, const double* dpart, size_t pstride, const int2* pair_tiles, const NodeD* nodes,
                    const TreeDev* trees, PoseState* st, const int64_t* n_moving, int npairs, int mode, double tol_rot,
-                   double tol_trans_rel, double* out, hipStream_t s) {
+                   double tol_trans_rel, int max_iters, double* out, hipStream_t s) {
   hipLaunchKernelGGL(normal_kernel, dim3(npairs), dim3(kNormThreads), 0, s, bins, dpart, pstride, pair_tiles, nodes,
-                     trees, st, n_moving, mode, tol_rot, tol_trans_rel, out);
+                     trees, st, n_moving, mode, tol_rot, tol_trans_rel, max_iters, out);
 }
 
 int normal_values() { return kNV; }

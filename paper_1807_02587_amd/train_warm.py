@@ -6,8 +6,9 @@
 Training pairs: unit-cube plane+sphere scenes, 10k points per cloud, rotation
 angle U(0, 90 deg), translation U(-0.1, 0.1)^3; label = the plain method's
 converged pose started at the ground truth.  Evaluation: held-out pairs
-(seeds >= 1e6) registered three ways on the same trees: plain method from
-identity, and warm start with the likelihood fallback.
+(seeds >= 1e6) registered by the plain method from the identity and by the
+warm start under both fallback rules (plain-method likelihood, the default;
+identity-pose likelihood).
 """
 
 from __future__ import annotations
@@ -29,7 +30,8 @@ def log(msg):
     print(msg, flush=True)
 
 
-def evaluate(net, n_pairs=4096, chunk=512, n=10_000, max_angle_deg=90.0, cfg=W.WarmConfig(), seed=10**6):
+def evaluate(net, n_pairs=4096, chunk=512, n=10_000, max_angle_deg=90.0, cfg=W.WarmConfig(), seed=10**6,
+             fallback="plain"):
     from synth.torch_scenes import cube_pairs
     err_plain, err_warm, fb, it_plain, it_warm, t_plain, t_warm = [], [], [], [], [], 0.0, 0.0
     ws = hg.Workspace()
@@ -47,7 +49,7 @@ def evaluate(net, n_pairs=4096, chunk=512, n=10_000, max_angle_deg=90.0, cfg=W.W
         rp = hg.hgmm_register_batch(forest, S.tgt, off, max_iters=cfg.max_iters, lambda_c=cfg.lambda_c, ws=ws)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        rw = W.register_warm(net, S.src, S.tgt, off, off, [cfg.src_levels] * B, cfg, ws=ws)
+        rw = W.register_warm(net, S.src, S.tgt, off, off, [cfg.src_levels] * B, cfg, ws=ws, fallback=fallback)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         t_plain += t1 - t0
@@ -64,7 +66,7 @@ def evaluate(net, n_pairs=4096, chunk=512, n=10_000, max_angle_deg=90.0, cfg=W.W
     ep, ew, fb = np.concatenate(err_plain), np.concatenate(err_warm), np.concatenate(fb)
     stats = lambda e: dict(median_deg=float(np.median(e)), p90_deg=float(np.percentile(e, 90)),
                            success_0p5=float(np.mean(e <= 0.5)), success_5=float(np.mean(e <= 5.0)))
-    return dict(pairs=n_pairs, points_per_cloud=n, max_angle_deg=max_angle_deg,
+    return dict(pairs=n_pairs, points_per_cloud=n, max_angle_deg=max_angle_deg, fallback_rule=fallback,
                 plain=dict(**stats(ep), mean_iters=float(np.mean(np.concatenate(it_plain))),
                            pairs_per_s=n_pairs / t_plain),
                 warm=dict(**stats(ew), mean_iters=float(np.mean(np.concatenate(it_warm))),
@@ -83,18 +85,22 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--report", default=None)
     ap.add_argument("--gen-budget-s", type=float, default=None, help="stop generating pairs after about this long")
+    ap.add_argument("--init", default=None, help="start from these weights (.npy) instead of a fresh network")
     args = ap.parse_args()
     cfg = W.WarmConfig()
     t0 = time.time()
     X, T = W.training_set(args.pairs, seed=args.seed, cfg=cfg, log=log, time_budget_s=args.gen_budget_s)
     log(f"training set: {X.shape[0]} pairs in {time.time() - t0:.1f} s")
     net = hg.MLP(seed=args.seed)
+    if args.init:
+        net.set_params(np.load(args.init))
     t1 = time.time()
     hist = W.train(net, X, T, epochs=args.epochs, batch=args.batch, lr=args.lr, cfg=cfg, log=log)
     log(f"training: {time.time() - t1:.1f} s")
     if args.out:
         np.save(args.out, net.get_params())
-    rep = evaluate(net, n_pairs=args.eval_pairs, cfg=cfg)
+    rep = evaluate(net, n_pairs=args.eval_pairs, cfg=cfg, fallback="plain")
+    rep["identity_rule"] = evaluate(net, n_pairs=args.eval_pairs, cfg=cfg, fallback="identity")["warm"]
     rep.update(train_pairs=int(X.shape[0]), epochs=args.epochs, loss_history=hist, train_seconds=time.time() - t1,
                generation_seconds=t1 - t0)
     log(json.dumps(rep))

@@ -8,9 +8,12 @@ kernels; this module only sequences calls and moves handles around):
 3. network forward (hgmm_mlp_forward) -> 6D rotation + translation;
 4. head -> initial transforms (hgmm_warm_head_pose);
 5. batched registration from those transforms;
-6. fallback: pairs whose final log-likelihood is below the log-likelihood of
-   the identity transform (one E-step, hgmm_estep_batch) are registered again
-   from the identity.
+6. fallback: the plain method from the identity is the judge.  Rule "plain"
+   (default): every pair is also registered from the identity (one more
+   batched call) and keeps whichever result has the higher final
+   log-likelihood.  Rule "identity" (cheaper): a pair whose final
+   log-likelihood is below the log-likelihood of the identity transform (one
+   E-step, hgmm_estep_batch) is registered again from the identity.
 
 Training data come from the batched GPU scene generator; the label of a pair
 is the plain method's converged pose when started at the ground truth.
@@ -118,8 +121,9 @@ def train(mlp, X, T, epochs: int = 20, batch: int = 512, lr: float = 1e-3, lr_mi
 
 
 def register_warm(mlp, src, tgt, src_off, tgt_off, src_levels, cfg: WarmConfig = WarmConfig(), ws=None,
-                  src_forest=None):
-    """Warm-started batched registration with the likelihood fallback.
+                  src_forest=None, fallback: str = "plain"):
+    """Warm-started batched registration with the likelihood fallback
+    (``fallback`` = "plain" or "identity", see the module docstring).
 
     Returns dict(R (B,3,3), t, iters, loglik, fallback (B,) bool, R0, t0, forest)."""
     ws = ws or hg.Workspace()
@@ -136,11 +140,20 @@ def register_warm(mlp, src, tgt, src_off, tgt_off, src_levels, cfg: WarmConfig =
     r = hg.hgmm_register_batch(src_forest, tgt, tgt_off, max_iters=cfg.max_iters, lambda_c=cfg.lambda_c, R0=R0,
                                t0=t0, ws=ws)
     Ri, ti = _eye_batch(B)
-    ll_id = hg.hgmm_estep_batch(src_forest, tgt, tgt_off, Ri, ti, lambda_c=cfg.lambda_c, ws=ws)
-    fb = (r["loglik"] < ll_id) | (r["status"] != 0)
-    if fb.any():
+    if fallback == "plain":
         r2 = hg.hgmm_register_batch(src_forest, tgt, tgt_off, max_iters=cfg.max_iters, lambda_c=cfg.lambda_c,
-                                    R0=Ri, t0=ti, active=fb.astype(np.int32), ws=ws)
+                                    R0=Ri, t0=ti, ws=ws)
+        fb = ((r["loglik"] < r2["loglik"]) & (r2["status"] == 0)) | (r["status"] != 0)
+    elif fallback == "identity":
+        ll_id = hg.hgmm_estep_batch(src_forest, tgt, tgt_off, Ri, ti, lambda_c=cfg.lambda_c, ws=ws)
+        fb = (r["loglik"] < ll_id) | (r["status"] != 0)
+        r2 = None
+        if fb.any():
+            r2 = hg.hgmm_register_batch(src_forest, tgt, tgt_off, max_iters=cfg.max_iters, lambda_c=cfg.lambda_c,
+                                        R0=Ri, t0=ti, active=fb.astype(np.int32), ws=ws)
+    else:
+        raise ValueError(f"unknown fallback rule {fallback!r}")
+    if r2 is not None:
         for k in ("R", "t", "iters", "loglik", "status"):
             r[k] = np.where(fb.reshape((B,) + (1,) * (r[k].ndim - 1)), r2[k], r[k])
     r.update(fallback=fb, R0=R0, t0=t0, forest=src_forest)

@@ -180,3 +180,28 @@ def test_autotune_small_batch(hg, batch):
             assert abs(h["pi"][:8][h["live"][:8] == 1].sum() - 1.0) < 1e-9
     finally:
         hg.hgmm_set_tuning(**old)
+
+
+def test_register_graph_matches_stream(hg, batch):
+    """reg_graph = 1 (each chunk one hipGraph launch, graph cached in the handle)
+    gives bit-identical results to plain launches, on every replay, with eager
+    work between the calls; max_iters need not be a multiple of the chunk."""
+    pairs, src, tgt, soff, toff, levels = batch
+    forest = hg.hgmm_build_batch(_cuda(src), soff, levels)
+    R0, t0 = _starts(pairs)
+    tg = _cuda(tgt)
+    old = hg.hgmm_get_tuning()
+    try:
+        for max_iters in (25, 7):
+            hg.hgmm_set_tuning(reg_graph=0, reg_chunk=2)
+            ref = hg.hgmm_register_batch(forest, tg, toff, R0=R0, t0=t0, max_iters=max_iters)
+            assert np.all(ref["iters"] <= max_iters)
+            hg.hgmm_set_tuning(reg_graph=1, reg_chunk=2)
+            for rep in range(3):
+                r = hg.hgmm_register_batch(forest, tg, toff, R0=R0, t0=t0, max_iters=max_iters)
+                hg.hgmm_estep_batch(forest, tg, toff, R0, t0)   # eager work between replays
+                torch.cuda.synchronize()
+                for k in ("R", "t", "iters", "loglik", "status"):
+                    np.testing.assert_array_equal(r[k], ref[k], err_msg=f"{k} replay {rep} max_iters {max_iters}")
+    finally:
+        hg.hgmm_set_tuning(**old)
