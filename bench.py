@@ -46,6 +46,23 @@ DESC_FLOP_PER_LEVEL = 8 * 19
 DESC_BYTES_PER_POINT = 12
 
 
+TRAFFIC = os.path.join(ROOT, "profiles", "lidar_hbm_traffic.json")
+
+
+def _traffic(family):
+    """HBM bytes per launch of a kernel family from the committed FETCH_SIZE /
+    WRITE_SIZE summary, or None when there is none or the kernels changed since."""
+    from paper_1807_02587_amd import profiling
+    try:
+        with open(TRAFFIC) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sources_sha1") != profiling.sources_sha1() or family not in t.get("families", {}):
+        return None
+    return t["families"][family]["bytes_per_launch"]
+
+
 def _workload(name):
     from paper_1807_02587_amd.presets import PRESETS
     from synth import depth_pair, lidar_pair, small_pair
@@ -117,28 +134,40 @@ def batch_section(args, hg):
 
     # plain form: one pair at a time, default launch shapes
     defaults = hg.hgmm_get_tuning()
-    plain_sequential(range(min(8, B)))
-    Rp, tp = timed(lambda: plain_sequential(range(B)))
     out = {"workload": f"{B} unit-cube pairs, N log-uniform [2e3, 2e5] (total {int(off[-1])} points per side), "
                        "rotation U(0,45 deg), levels ceil(log8(N/50))"}
-    out.update(summary("plain_sequential", Rp, tp))
+    tp = None
+    if not args.batch_only:
+        plain_sequential(range(min(8, B)))
+        Rp, tp = timed(lambda: plain_sequential(range(B)))
+        out.update(summary("plain_sequential", Rp, tp))
     # batched forms: launch shapes from the autotuner on this batch (outside the timed runs)
-    from paper_1807_02587_amd import autotune
-    t_tune = time.perf_counter()
-    tun = autotune.tuned(src, off, lv, tgt, off, use_cache=False, reps=1, passes=1, ws=ws)
-    out["autotune"] = {"tuning": tun["tuning"], "search_s": round(time.perf_counter() - t_tune, 2),
-                       "start_ms": round(tun["start_ms"], 2), "best_ms": round(tun["best_ms"], 2)}
+    if args.batch_tuning_json:
+        with open(args.batch_tuning_json) as f:
+            hg.hgmm_set_tuning(**json.load(f))
+        out["autotune"] = {"tuning": hg.hgmm_get_tuning(), "from": args.batch_tuning_json}
+    else:
+        from paper_1807_02587_amd import autotune
+        t_tune = time.perf_counter()
+        tun = autotune.tuned(src, off, lv, tgt, off, use_cache=False, reps=1, passes=1, ws=ws)
+        out["autotune"] = {"tuning": tun["tuning"], "search_s": round(time.perf_counter() - t_tune, 2),
+                           "start_ms": round(tun["start_ms"], 2), "best_ms": round(tun["best_ms"], 2)}
+    if args.save_batch_tuning:
+        with open(args.save_batch_tuning, "w") as f:
+            json.dump(hg.hgmm_get_tuning(), f)
     batched_plain()
     Rb, tb = timed(batched_plain)
     out.update(summary("batched", Rb, tb))
-    out["speedup_batched_vs_plain"] = round(tp / tb, 2)
+    if tp:
+        out["speedup_batched_vs_plain"] = round(tp / tb, 2)
     if net is not None:
         batched_warm()
         rw, tw = timed(batched_warm)
         out.update(summary("batched_warm", rw["R"], tw))
         out["warm_fallback_rate"] = round(float(np.mean(rw["fallback"])), 4)
-        out["speedup_batched_warm_vs_plain"] = round(tp / tw, 2)
-        if out["plain_sequential_ok_0p5"] > 0:
+        if tp:
+            out["speedup_batched_warm_vs_plain"] = round(tp / tw, 2)
+        if tp and out["plain_sequential_ok_0p5"] > 0:
             out["speedup_ok_pairs_s_batched_warm_vs_plain"] = round(
                 out["batched_warm_ok_pairs_s"] / out["plain_sequential_ok_pairs_s"], 2)
     hg.hgmm_set_tuning(**defaults)
@@ -217,6 +246,10 @@ def main():
     ap.add_argument("--batch-pairs", type=int, default=256)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched and warm-start sections")
     ap.add_argument("--warm-pairs", type=int, default=1024)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched forms of the uneven batch (for profiling them)")
+    ap.add_argument("--batch-tuning-json", default=None, help="launch shapes of the batched forms from this file")
+    ap.add_argument("--save-batch-tuning", default=None, help="write the batched forms' launch shapes to this file")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--tuning-json", default=None, help="launch shapes from this file instead of the autotuner")
     ap.add_argument("--save-tuning", default=None, help="write the launch shapes used to this file")
@@ -231,6 +264,11 @@ def main():
     import torch
     import paper_1807_02587_amd as hg
     from synth import rotation_angle_deg
+
+    if args.batch_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"batched": batch_section(args, hg)}), flush=True)
+        return
 
     p, pr, desc = _workload(args.workload)
     dev = torch.device("cuda", 0)
@@ -249,7 +287,10 @@ def main():
 
     if args.copy_calibration:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE give the
-        # scale from counter units to bytes
+        # scale from counter units to bytes; then steps with the given shapes
+        if args.tuning_json:
+            with open(args.tuning_json) as f:
+                hg.hgmm_set_tuning(**json.load(f))
         a = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
         b = torch.empty_like(a)
         b.copy_(a)
@@ -319,7 +360,7 @@ def main():
     ds = prof["descend"]
     achieved = flop / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None, "kernel": kname,
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": _traffic(dom), "kernel": kname,
                 "launches": launches, "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
                 "flop_per_launch": round(flop / max(launches, 1)),
                 "frac_of_packed_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4),

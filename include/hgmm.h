@@ -261,8 +261,9 @@ void hgmm_tree_destroy(hgmm_tree tree);
  * the search space of the autotuner).  Construction of a level: a parent with
  * at most block64_max points runs all its EM iterations in one 64-thread
  * block, at most block256_max in one 256-thread block, at most block512_max
- * in one 512-thread block; a larger parent is cut into tiles of one wavefront
- * and each EM iteration is one tile launch plus one M-step launch.  Points per
+ * in one 512-thread block; a larger parent is cut into tiles of 256 threads
+ * and each EM iteration is one tile launch (which also runs the previous
+ * iteration's M-step), plus one final M-step launch per level.  Points per
  * tile are level_points / target_tiles rounded up to a multiple of 64 and
  * clamped to [min_tile, max_tile].  Registration: reg_tile points per
  * 256-thread descent block (a multiple of 256); reg_chunk iterations are
@@ -272,7 +273,7 @@ void hgmm_tree_destroy(hgmm_tree tree);
  * graph is kept in the tree handle and reused while the call's sizes,
  * buffers and knobs stay the same.  Timing with hgmm_profile(1) uses plain
  * launches.
- * Defaults 256, 2048, 8192, 256, 1024, 4096, 512, 4, 0. */
+ * Defaults 256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0. */
 typedef struct hgmm_tuning {
   int32_t block64_max, block256_max, block512_max;
   int32_t min_tile, target_tiles, max_tile;

@@ -350,6 +350,7 @@ __device__ __forceinline__ void rows_store80(float (&a)[8][10], float (*rows)[80
 // (moments about the means the E-step used).  Runs on one full wave; lanes 0..7
 // own one child each.  Updates the LDS copy of the children, the FP32 table
 // and the FP64 node records.
+template <bool GLOBAL = true>
 __device__ __forceinline__ void mstep_children(const double* tot, NodeF* ch, NodeF* tab, NodeD* nodes,
                                                int child_base, double eps, double min_mass, int lane) {
   bool live = false;
@@ -376,16 +377,20 @@ __device__ __forceinline__ void mstep_children(const double* tot, NodeF* ch, Nod
                        A[7] * inv - dl1 * dl1 + eps, A[8] * inv - dl1 * dl2, A[9] * inv - dl2 * dl2 + eps};
       live = make_node(mu, cov, N / total, nd, nf);
     }
-    NodeD& out = nodes[g];
     if (live) {
-      for (int i = 0; i < 3; ++i) out.mu[i] = nd.mu[i];
-      for (int i = 0; i < 6; ++i) { out.cov[i] = nd.cov[i]; out.winv[i] = nd.winv[i]; }
-      out.pi = nd.pi; out.c = nd.c; out.logdet = nd.logdet; out.live = 1;
-      copy_nodef(tab[g], nf);
+      if (GLOBAL) {
+        NodeD& out = nodes[g];
+        for (int i = 0; i < 3; ++i) out.mu[i] = nd.mu[i];
+        for (int i = 0; i < 6; ++i) { out.cov[i] = nd.cov[i]; out.winv[i] = nd.winv[i]; }
+        out.pi = nd.pi; out.c = nd.c; out.logdet = nd.logdet; out.live = 1;
+        copy_nodef(tab[g], nf);
+      }
       copy_nodef(ch[lane], nf);
     } else {
-      out.live = 0; out.pi = 0.0;
-      tab[g].flags = 0u;
+      if (GLOBAL) {
+        nodes[g].live = 0; nodes[g].pi = 0.0;
+        tab[g].flags = 0u;
+      }
       ch[lane].flags = 0u;
     }
   }
@@ -398,53 +403,82 @@ __device__ __forceinline__ uint32_t live_mask(const NodeF* ch) {
   return m;
 }
 
-// One EM iteration over the tiles of the large jobs: FP64 tile partials of the
-// 80 moment sums, stored value-major (partials[v * pstride + tile]).
-__global__ __launch_bounds__(64) void em_tile_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
-                                                     const float* __restrict__ zs, const Tile* __restrict__ tiles,
-                                                     const int* __restrict__ tile_ids, const Job* __restrict__ jobs,
-                                                     const NodeF* __restrict__ tab, double* partials,
-                                                     size_t pstride) {
-  const int tid = tile_ids[blockIdx.x];
-  const Tile tl = tiles[tid];
+// One EM iteration of the tiled (large) jobs, with the previous iteration's
+// M-step folded in.  Every block of a job folds the job's tile partials of
+// iteration it-1 in the same fixed order and runs the same FP64 M-step, so
+// all its blocks hold bit-identical children; the job's first tile publishes
+// them for the next launch (ping-pong child records, one set of 8 per tiled
+// job, slot = Tile::pad).  The first iteration starts from the initial
+// children in the scoring table.  Tile partials of the 80 moment sums are
+// FP64, value-major (part_next[v * pstride + tile]), ping-pong as well.
+constexpr int kTileThreads = 256;
+__global__ __launch_bounds__(kTileThreads) void em_tile_kernel(
+    const float* __restrict__ xs, const float* __restrict__ ys, const float* __restrict__ zs,
+    const Tile* __restrict__ tiles, const int* __restrict__ tile_ids, const Job* __restrict__ jobs,
+    const NodeF* __restrict__ tab, const NodeF* __restrict__ ch_prev, NodeF* ch_next,
+    const double* __restrict__ part_prev, double* part_next, size_t pstride, double eps, double min_mass,
+    int first) {
+  constexpr int NT = kTileThreads, NR = NT / 16, NW = NT / 64;
+  const int tix = tile_ids[blockIdx.x];
+  const Tile tl = tiles[tix];
   const Job jb = jobs[tl.job];
-  const int lane = threadIdx.x;
+  const int slot = tl.pad;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   __shared__ NodeF ch[8];
   __shared__ EmFrame fr;
-  __shared__ float rows[4][80];
-  if (lane < 8) copy_nodef(ch[lane], tab[jb.child_base + lane]);
+  __shared__ float rows[NR][80];
+  __shared__ double tot[80];
+  if (tid < 8) copy_nodef(ch[tid], first ? tab[jb.child_base + tid] : ch_prev[(size_t)slot * 8 + tid]);
+  if (!first) {
+    // wave w folds value groups w, w + NW, ... of 5 values each
+    for (int v0 = 5 * wv; v0 < 80; v0 += 5 * NW) {
+      double t[5];
+      wave_fold<5, 4>(part_prev + (size_t)v0 * pstride + jb.tile_first, pstride, jb.ntiles, lane, t);
+      if (lane == 0)
+        for (int j = 0; j < 5; ++j) tot[v0 + j] = t[j];
+    }
+    __syncthreads();
+    if (tid < 64) mstep_children<false>(tot, ch, nullptr, nullptr, 0, eps, min_mass, lane);
+  }
   __syncthreads();
+  if (tix == jb.tile_first && tid < 8) copy_nodef(ch_next[(size_t)slot * 8 + tid], ch[tid]);
   const uint32_t live = live_mask(ch);
   float a[8][10];
-  if (live) em_frame(ch, live, fr, lane);
+  if (live) em_frame(ch, live, fr, tid);
   __syncthreads();
   if (live) {
     PointCache<4> pc;
-    load_points<64>(xs, ys, zs, tl.start, tl.end, lane, pc);
-    em_range<64>(xs, ys, zs, tl.start, tl.end, lane, pc, ch, fr, live, a);
-  }
-  else
+    load_points<NT>(xs, ys, zs, tl.start, tl.end, tid, pc);
+    em_range<NT>(xs, ys, zs, tl.start, tl.end, tid, pc, ch, fr, live, a);
+  } else {
     for (int k = 0; k < 8; ++k)
       for (int v = 0; v < 10; ++v) a[k][v] = 0.f;
-  rows_store80(a, rows, lane);
+  }
+  rows_store80(a, rows, tid);
   __syncthreads();
-  for (int v = lane; v < 80; v += 64)
-    partials[(size_t)v * pstride + tid] = ((double)rows[0][v] + (double)rows[1][v]) + ((double)rows[2][v] + (double)rows[3][v]);
+  for (int v = tid; v < 80; v += NT) {
+    double t = 0.0;
+    for (int q = 0; q < NR; ++q) t += (double)rows[q][v];
+    part_next[(size_t)v * pstride + tix] = t;
+  }
 }
 
-// M-step of the large jobs: one block of 16 waves per job; wave w folds the
-// tile partials of values 5w .. 5w+4 in a fixed order, then wave 0 updates the
-// 8 children.
+// Final M-step of the tiled jobs after the last iteration: one block of 16
+// waves per job (block b = the job's slot among the tiled jobs); wave w folds
+// the tile partials of values 5w .. 5w+4 in a fixed order, then wave 0 runs
+// the M-step from the children of that iteration (chsrc) and writes the node
+// records.
 constexpr int kMstepThreads = 1024;
 __global__ __launch_bounds__(kMstepThreads) void em_mstep_kernel(const int* __restrict__ job_ids,
                                                                  const Job* __restrict__ jobs, NodeF* tab,
                                                                  NodeD* nodes, const double* __restrict__ partials,
-                                                                 size_t pstride, double eps, double min_mass) {
+                                                                 size_t pstride, double eps, double min_mass,
+                                                                 const NodeF* __restrict__ chsrc) {
   const Job jb = jobs[job_ids[blockIdx.x]];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   __shared__ NodeF ch[8];
   __shared__ double tot[80];
-  if (tid < 8) copy_nodef(ch[tid], tab[jb.child_base + tid]);
+  if (tid < 8) copy_nodef(ch[tid], chsrc[(size_t)blockIdx.x * 8 + tid]);
   double t[5];
   wave_fold<5, 8>(partials + (size_t)(5 * wv) * pstride + jb.tile_first, pstride, jb.ntiles, lane, t);
   if (lane == 0)
@@ -718,15 +752,16 @@ void launch_init_children(const Job* jobs, int njobs, const TreeDev* trees, Node
 }
 
 void launch_em_tile(const float* xs, const float* ys, const float* zs, const Tile* tiles, const int* tile_ids, int n,
-                    const Job* jobs, const NodeF* tab, double* partials, size_t pstride, hipStream_t s) {
-  hipLaunchKernelGGL(em_tile_kernel, dim3(n), dim3(64), 0, s, xs, ys, zs, tiles, tile_ids, jobs, tab, partials,
-                     pstride);
+                    const Job* jobs, const NodeF* tab, const NodeF* ch_prev, NodeF* ch_next, const double* part_prev,
+                    double* part_next, size_t pstride, double eps, double min_mass, int first, hipStream_t s) {
+  hipLaunchKernelGGL(em_tile_kernel, dim3(n), dim3(kTileThreads), 0, s, xs, ys, zs, tiles, tile_ids, jobs, tab,
+                     ch_prev, ch_next, part_prev, part_next, pstride, eps, min_mass, first);
 }
 
 void launch_em_mstep(const int* job_ids, int n, const Job* jobs, NodeF* tab, NodeD* nodes, const double* partials,
-                     size_t pstride, double eps, double min_mass, hipStream_t s) {
+                     size_t pstride, double eps, double min_mass, const NodeF* chsrc, hipStream_t s) {
   hipLaunchKernelGGL(em_mstep_kernel, dim3(n), dim3(kMstepThreads), 0, s, job_ids, jobs, tab, nodes, partials,
-                     pstride, eps, min_mass);
+                     pstride, eps, min_mass, chsrc);
 }
 
 void launch_em_block(int nt, const float* xs, const float* ys, const float* zs, const int* job_ids, int n,

@@ -199,8 +199,8 @@ static int setup_forest(hgmm_forest_s* f) {
 static size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
 struct BuildLayout {
-  size_t pts[2], perm[2], child, tiles, tile_ids, job_ids, jobs, partials, tile_counts, tile_base, counters,
-      lvl_info, total;
+  size_t pts[2], perm[2], child, tiles, tile_ids, job_ids, jobs, partials, partials2, chbuf, tile_counts, tile_base,
+      counters, lvl_info, total;
   int64_t max_tiles, max_jobs, max_lvl;
 };
 
@@ -218,6 +218,8 @@ static BuildLayout build_layout(int64_t n_total, int64_t max_jobs, int64_t max_l
   L.job_ids = o; o = align_up(o + sizeof(int) * (size_t)L.max_jobs);
   L.jobs = o; o = align_up(o + sizeof(Job) * (size_t)L.max_jobs);
   L.partials = o; o = align_up(o + sizeof(double) * 80 * (size_t)L.max_tiles);
+  L.partials2 = o; o = align_up(o + sizeof(double) * 80 * (size_t)L.max_tiles);
+  L.chbuf = o; o = align_up(o + sizeof(NodeF) * 8 * 2 * (size_t)L.max_jobs);
   L.tile_counts = o; o = align_up(o + sizeof(int) * 9 * (size_t)L.max_tiles);
   L.tile_base = o; o = align_up(o + sizeof(int) * 9 * (size_t)L.max_tiles);
   L.counters = o; o = align_up(o + sizeof(unsigned) * (size_t)L.max_jobs);
@@ -280,7 +282,7 @@ static int64_t max_lvl_for(const std::vector<TreeHost>& trees) {
 // launch shapes (process wide; see hgmm_tuning)
 // ---------------------------------------------------------------------------
 
-static hgmm_tuning g_tune = {256, 2048, 8192, 256, 1024, 4096, 512, 4, 0};
+static hgmm_tuning g_tune = {256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0};
 
 extern "C" int hgmm_set_tuning(const hgmm_tuning* t) {
   if (!t) return fail(HGMM_EINVAL, "null tuning");
@@ -426,6 +428,8 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
   int* d_job_ids = (int*)(ws + Ly.job_ids);
   Job* d_jobs = (Job*)(ws + Ly.jobs);
   double* d_partials = (double*)(ws + Ly.partials);
+  double* d_part[2] = {d_partials, (double*)(ws + Ly.partials2)};
+  NodeF* d_ch[2] = {(NodeF*)(ws + Ly.chbuf), (NodeF*)(ws + Ly.chbuf) + 8 * (size_t)Ly.max_jobs};
   int* d_tile_counts = (int*)(ws + Ly.tile_counts);
   int* d_tile_base = (int*)(ws + Ly.tile_base);
   unsigned* d_counters = (unsigned*)(ws + Ly.counters);
@@ -533,9 +537,16 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
     };
     for (int j = 0; j < njobs; ++j) { cls_n[job_class(jobs[j].count)] += 1; cls_points[job_class(jobs[j].count)] += jobs[j].count; }
     for (int c = 0; c < 4; ++c) cls_off[c + 1] = cls_off[c] + cls_n[c];
+    // slot of each tiled job among the tiled jobs (its child records in the
+    // ping-pong buffers and its block in the final M-step)
+    std::vector<int> slot_of((size_t)njobs, 0);
     {
       int fill[4] = {cls_off[0], cls_off[1], cls_off[2], cls_off[3]};
-      for (int j = 0; j < njobs; ++j) h_jids[fill[job_class(jobs[j].count)]++] = j;
+      for (int j = 0; j < njobs; ++j) {
+        const int c = job_class(jobs[j].count);
+        if (c == 3) slot_of[(size_t)j] = fill[3] - cls_off[3];
+        h_jids[fill[c]++] = j;
+      }
     }
     for (int j = 0; j < njobs; ++j) {
       Job& jb = jobs[j];
@@ -547,7 +558,7 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
         T.start = jb.start + t * tpts;
         T.end = std::min(jb.start + jb.count, T.start + tpts);
         T.job = j;
-        T.pad = 0;
+        T.pad = tiled ? slot_of[(size_t)j] : 0;
         if (tiled) h_tids[nbig++] = ntiles;
         ++ntiles;
       }
@@ -597,16 +608,17 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
         joined[c] = true;
       }
     }
-    if (nbig)
+    if (nbig && p.build_iters > 0) {
       for (int it = 0; it < p.build_iters; ++it) {
-        {
-          ProfScope ps(PK_EM_TILE, (double)cls_points[3], s);
-          launch_em_tile(cx, cy, cz, d_tiles, d_tile_ids, nbig, d_jobs, f->d_tab, d_partials, (size_t)Ly.max_tiles, s);
-        }
-        ProfScope ps(PK_EM_MSTEP, (double)nbigjobs, s);
-        launch_em_mstep(d_job_ids + cls_off[3], nbigjobs, d_jobs, f->d_tab, f->d_nodes, d_partials,
-                        (size_t)Ly.max_tiles, p.reg_eps, p.min_mass, s);
+        ProfScope ps(PK_EM_TILE, (double)cls_points[3], s);
+        launch_em_tile(cx, cy, cz, d_tiles, d_tile_ids, nbig, d_jobs, f->d_tab, d_ch[(it + 1) & 1], d_ch[it & 1],
+                       d_part[(it + 1) & 1], d_part[it & 1], (size_t)Ly.max_tiles, p.reg_eps, p.min_mass, it == 0, s);
       }
+      const int last = (p.build_iters - 1) & 1;
+      ProfScope ps(PK_EM_MSTEP, (double)nbigjobs, s);
+      launch_em_mstep(d_job_ids + cls_off[3], nbigjobs, d_jobs, f->d_tab, f->d_nodes, d_part[last],
+                      (size_t)Ly.max_tiles, p.reg_eps, p.min_mass, d_ch[last], s);
+    }
     for (int c = 0; c < 3; ++c)
       if (joined[c]) HIP_TRY(hipStreamWaitEvent(s, f->ev_join[c], 0));
     // ---- hard partition, child ranges, stable split, per-node statistics

@@ -3,6 +3,7 @@
     python -m paper_1807_02587_amd.profiling stats <dir>/<name>_kernel_stats.csv
     python -m paper_1807_02587_amd.profiling steps <dir>/<name>_kernel_trace.csv [first_kernel]
     python -m paper_1807_02587_amd.profiling counters <dir>/<name>_counter_collection.csv
+    python -m paper_1807_02587_amd.profiling traffic <fetch.csv> <write.csv> <copy_bytes> <out.json>
 
 ``stats`` prints the per-kernel table (calls, total/average/min/max us,
 share) of a ``--kernel-trace --stats`` run; ``steps`` splits the kernel trace
@@ -10,14 +11,26 @@ into steps at each launch of ``first_kernel`` (default root_mean_kernel, the
 first kernel of a construction) and prints, for the last full step, the span,
 the summed kernel time, the summed gaps between kernels and the kernel time
 by kernel; ``counters`` prints, per kernel, the mean per-dispatch value of
-every collected counter of a ``--pmc`` run.
+every collected counter of a ``--pmc`` run; ``traffic`` turns a FETCH_SIZE
+pass and a WRITE_SIZE pass (KiB per dispatch) into HBM bytes per launch of
+each kernel family, scaled by what the same counters read for the largest
+plain copy of ``copy_bytes`` bytes in the same runs, and stamps the result
+with a hash of the kernel sources (a figure is stale once they change).
 """
 
 from __future__ import annotations
 
 import collections
 import csv
+import hashlib
+import json
+import os
 import sys
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+KERNEL_SOURCES = ("build_kernels.hip", "register_kernels.hip", "hgmm_dev.h")
+FAMILIES = {"em_block": "em_block_kernel", "em_tile": "em_tile_kernel", "em_mstep": "em_mstep_kernel",
+            "descend": "descend_kernel", "normal": "normal_kernel", "partition": "partition_kernel"}
 
 
 def _short(name: str) -> str:
@@ -55,6 +68,54 @@ def counters(path: str) -> str:
     return "\n".join(out)
 
 
+def sources_sha1() -> str:
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _per_dispatch(path: str, counter: str) -> dict:
+    """kernel name -> list of per-dispatch values of one counter (summed over its instances)."""
+    per = collections.defaultdict(float)
+    names = {}
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name", r.get("Counter-Name")) != counter:
+            continue
+        d = r.get("Dispatch_Id", r.get("Dispatch-Id"))
+        per[d] += float(r.get("Counter_Value", r.get("Counter-Value", 0)))
+        names[d] = r.get("Kernel_Name", r.get("Kernel-Name", "?"))
+    out = collections.defaultdict(list)
+    for d, v in per.items():
+        out[names[d]].append(v)
+    return out
+
+
+def traffic(fetch_csv: str, write_csv: str, copy_bytes: float) -> dict:
+    fetch = _per_dispatch(fetch_csv, "FETCH_SIZE")
+    write = _per_dispatch(write_csv, "WRITE_SIZE")
+    # the calibration copy: the largest single dispatch of a kernel that is not the library's
+    cf = max(v for k, vs in fetch.items() if "hgmm::" not in k for v in vs)
+    cw = max(v for k, vs in write.items() if "hgmm::" not in k for v in vs)
+    sf, sw = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
+    fam = {}
+    for key, prefix in FAMILIES.items():
+        fv = [v for k, vs in fetch.items() if _short(k).startswith(prefix) or
+              _short(k).startswith("void " + prefix) for v in vs]
+        wv = [v for k, vs in write.items() if _short(k).startswith(prefix) or
+              _short(k).startswith("void " + prefix) for v in vs]
+        if not fv or not wv:
+            continue
+        f_b = sum(fv) / len(fv) * 1024.0 * sf
+        w_b = sum(wv) / len(wv) * 1024.0 * sw
+        fam[key] = {"dispatches": len(fv), "fetch_bytes_per_launch": round(f_b), "write_bytes_per_launch": round(w_b),
+                    "bytes_per_launch": round(f_b + w_b)}
+    return {"copy": {"bytes": copy_bytes, "fetch_kib": cf, "write_kib": cw, "scale_fetch": round(sf, 4),
+                     "scale_write": round(sw, 4)},
+            "families": fam, "kernel_sources_sha1": sources_sha1()}
+
+
 def steps(path: str, first: str = "root_mean_kernel") -> str:
     rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Start_Timestamp"]))
     name = lambda r: _short(r["Kernel_Name"])
@@ -84,5 +145,10 @@ if __name__ == "__main__":
         print(stats(path))
     elif mode == "steps":
         print(steps(path, *sys.argv[3:4]))
+    elif mode == "traffic":
+        res = traffic(path, sys.argv[3], float(sys.argv[4]))
+        with open(sys.argv[5], "w") as f:
+            json.dump(res, f, indent=1)
+        print(json.dumps(res, indent=1))
     else:
         print(counters(path))
