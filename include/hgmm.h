@@ -272,20 +272,24 @@ void hgmm_tree_destroy(hgmm_tree tree);
  * library-owned stream joined to the caller's by events; the instantiated
  * graph is kept in the tree handle and reused while the call's sizes,
  * buffers and knobs stay the same.  Timing with hgmm_profile(1) uses plain
- * launches.
- * Defaults 256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0. */
+ * launches.  reg_sort = 1 sorts the moving points of every pair by the Morton
+ * code of their position in the model tree's frame (one radix sort per call,
+ * inside the workspace) so that neighbouring lanes stop at the same nodes;
+ * the results change only by summation order.
+ * Defaults 256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0. */
 typedef struct hgmm_tuning {
   int32_t block64_max, block256_max, block512_max;
   int32_t min_tile, target_tiles, max_tile;
   int32_t reg_tile, reg_chunk;
   int32_t reg_graph;  /* 1: each chunk of registration iterations is one hipGraph launch */
+  int32_t reg_sort;   /* 1: the moving cloud is put in Morton order once per registration call */
 } hgmm_tuning;
 
 /* Set (after validation) or read the launch shapes.  hgmm_set_tuning returns
  * HGMM_EINVAL, changing nothing, unless 0 <= block64_max <= block256_max <=
  * block512_max <= 1<<20, 64 <= min_tile <= max_tile <= 1<<20,
  * target_tiles >= 1, 256 <= reg_tile <= 1<<20, 1 <= reg_chunk <= 64 and
- * reg_graph in {0, 1}.
+ * reg_graph, reg_sort in {0, 1}.
  * Values are rounded up to the multiples stated above.  Not thread-safe
  * against concurrent calls of the library. */
 int hgmm_set_tuning(const hgmm_tuning *t);

@@ -229,7 +229,9 @@ static BuildLayout build_layout(int64_t n_total, int64_t max_jobs, int64_t max_l
 }
 
 struct RegLayout {
-  size_t bins, partials, counters, state, nmov, tiles, out, dpart, dcount, ptiles, active, total;
+  size_t bins, partials, counters, state, nmov, tiles, out, dpart, dcount, ptiles, active, keys, keys2, vals, perm,
+      sxyz, sort_temp, total;
+  size_t sort_temp_bytes;
   int64_t max_tiles;
 };
 
@@ -248,6 +250,14 @@ static RegLayout reg_layout(int64_t n_total, int64_t nodes, int npairs) {
   L.nmov = o; o = align_up(o + sizeof(int64_t) * (size_t)npairs);
   L.tiles = o; o = align_up(o + sizeof(Tile) * (size_t)L.max_tiles);
   L.out = o; o = align_up(o + sizeof(double) * 28 * (size_t)npairs + sizeof(double) * 12 * npairs);
+  // Morton ordering of the moving points (reg_sort)
+  L.keys = o; o = align_up(o + sizeof(uint64_t) * (size_t)n_total);
+  L.keys2 = o; o = align_up(o + sizeof(uint64_t) * (size_t)n_total);
+  L.vals = o; o = align_up(o + sizeof(int) * (size_t)n_total);
+  L.perm = o; o = align_up(o + sizeof(int) * (size_t)n_total);
+  L.sxyz = o; o = align_up(o + sizeof(float) * 3 * (size_t)n_total);
+  L.sort_temp_bytes = sort_temp_bytes(n_total, npairs);
+  L.sort_temp = o; o = align_up(o + L.sort_temp_bytes);
   L.total = o;
   return L;
 }
@@ -282,7 +292,7 @@ static int64_t max_lvl_for(const std::vector<TreeHost>& trees) {
 // launch shapes (process wide; see hgmm_tuning)
 // ---------------------------------------------------------------------------
 
-static hgmm_tuning g_tune = {256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0};
+static hgmm_tuning g_tune = {256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0};
 
 extern "C" int hgmm_set_tuning(const hgmm_tuning* t) {
   if (!t) return fail(HGMM_EINVAL, "null tuning");
@@ -295,6 +305,7 @@ extern "C" int hgmm_set_tuning(const hgmm_tuning* t) {
   if (!(256 <= t->reg_tile && t->reg_tile <= lim && 1 <= t->reg_chunk && t->reg_chunk <= 64))
     return fail(HGMM_EINVAL, "reg_tile must be in [256, 2^20] and reg_chunk in [1, 64]");
   if (t->reg_graph != 0 && t->reg_graph != 1) return fail(HGMM_EINVAL, "reg_graph must be 0 or 1");
+  if (t->reg_sort != 0 && t->reg_sort != 1) return fail(HGMM_EINVAL, "reg_sort must be 0 or 1");
   g_tune = *t;
   g_tune.min_tile = (t->min_tile + 63) / 64 * 64;
   g_tune.max_tile = (t->max_tile + 63) / 64 * 64;
@@ -735,6 +746,17 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
     for (int b = 0; b < P; ++b) h_act[b] = active[b] ? 1 : 0;
     HIP_TRY(hipMemcpyAsync(d_act, h_act, sizeof(int) * P, hipMemcpyHostToDevice, s));
   }
+  const int* d_perm = nullptr;
+  if (g_tune.reg_sort && n_total > 0) {
+    float* sx = (float*)(ws + Ly.sxyz);
+    float* sy = sx + n_total;
+    float* sz = sy + n_total;
+    HIP_TRY(launch_sort_points(xs, ys, zs, d_tiles, ntiles, f->d_trees, P, n_total, (uint64_t*)(ws + Ly.keys),
+                               (uint64_t*)(ws + Ly.keys2), (int*)(ws + Ly.vals), (int*)(ws + Ly.perm),
+                               ws + Ly.sort_temp, Ly.sort_temp_bytes, sx, sy, sz, s));
+    xs = sx; ys = sy; zs = sz;
+    d_perm = (const int*)(ws + Ly.perm);
+  }
   launch_fill_u32(d_bins, 0u, 2 * 6 * nodes_total, s);
   launch_set_stop_flags(f->d_tab, f->d_nodes, nodes_total, rr.lambda_c, s);
   launch_init_pose(d_state, P, d_pose0, d_pose0 + 9, per_pair ? 12 : 0, active ? d_act : nullptr, s);
@@ -742,7 +764,7 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   const size_t pstride = (size_t)Ly.max_tiles;
   if (mode_estep) {
     launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins, d_dpart, pstride,
-                   stop_out, gamma_out, s);
+                   stop_out, gamma_out, d_perm, s);
     launch_fold_bins(d_ptiles, f->d_trees, d_dpart, pstride, d_bins, P, s);
     if (h_norm) {
       launch_normal(d_bins, d_dpart, pstride, d_ptiles, f->d_nodes, f->d_trees, d_state, d_nmov, P, 1, 0.0, 0.0, 1,
@@ -775,7 +797,7 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
       HIP_TRY(hipStreamBeginCapture(f->gstream, hipStreamCaptureModeThreadLocal));
       for (int c = 0; c < chunk; ++c) {
         launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins, d_dpart,
-                       pstride, nullptr, nullptr, f->gstream);
+                       pstride, nullptr, nullptr, nullptr, f->gstream);
         launch_normal(d_bins, d_dpart, pstride, d_ptiles, f->d_nodes, f->d_trees, d_state, d_nmov, P, 0, rr.tol_rot,
                       rr.tol_trans_rel, rr.max_iters, d_out, f->gstream);
       }
@@ -809,7 +831,7 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
       {
         ProfScope ps(PK_DESCEND, (double)n_total, s, it);
         launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins, d_dpart,
-                       pstride, nullptr, nullptr, s);
+                       pstride, nullptr, nullptr, nullptr, s);
       }
       {
         ProfScope ps(PK_NORMAL, (double)nodes_total, s, it);

@@ -33,6 +33,7 @@ const std::vector<Knob>& knobs() {
       {&hgmm_tuning::reg_tile, {256, 512, 1024, 2048}},
       {&hgmm_tuning::reg_chunk, {2, 4, 8, 16}},
       {&hgmm_tuning::reg_graph, {0, 1}},
+      {&hgmm_tuning::reg_sort, {0, 1}},
   };
   return k;
 }

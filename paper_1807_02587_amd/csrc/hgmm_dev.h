@@ -19,17 +19,29 @@ enum : uint32_t { F_LIVE = 1u, F_STOP = 2u, F_HASCH = 4u };
 // FP64 record of one tree node.  mu is in absolute model coordinates; cov
 // includes the eps*I regularisation; winv is the inverse of the lower Cholesky
 // factor of cov, packed [00, 10, 11, 20, 21, 22]; c = log(pi) - log|cov|/2
-// with pi the weight inside the sibling group.
+// with pi the weight inside the sibling group.  The FP64 scoring fields (mu,
+// winv, c) come first, 80 contiguous bytes (NodeS).
 struct NodeD {
   double mu[3];
+  double winv[6];
+  double c;
   double cov[6];
   double lam[3];
   double evec[9];
-  double winv[6];
-  double pi, pig, kappa, c, logdet;
+  double pi, pig, kappa, logdet;
   int32_t live, has_children;
   int64_t count;
 };
+
+// The FP64 scoring prefix of a NodeD (same layout as its first 80 bytes).
+struct NodeS {
+  double mu[3];
+  double winv[6];
+  double c;
+};
+static_assert(sizeof(NodeS) == 80, "NodeS is the 80-byte prefix of NodeD");
+static_assert(__builtin_offsetof(NodeD, winv) == 24 && __builtin_offsetof(NodeD, c) == 72,
+              "the FP64 scoring fields lead NodeD");
 
 // FP32 scoring record of one node, 64 bytes.  The score of a point p is
 //   s = c - |W d|^2,  d = float(p - mu)  (the subtraction in FP64),
@@ -298,8 +310,9 @@ __device__ __forceinline__ float score_err(const NodeF& t, float q, float m) {
   return t.errc + 4.f * kU * q + fmaf(gm, q, gm);
 }
 
-// FP64 score in the same log2 units, from the FP64 node record.
-__device__ __forceinline__ double score64(const NodeD& n, double p0, double p1, double p2) {
+// FP64 score in the same log2 units, from the FP64 scoring fields.
+template <typename N>
+__device__ __forceinline__ double score64(const N& n, double p0, double p1, double p2) {
   double d0 = p0 - n.mu[0], d1 = p1 - n.mu[1], d2 = p2 - n.mu[2];
   double w0 = n.winv[0] * d0;
   double w1 = n.winv[1] * d0 + n.winv[2] * d1;

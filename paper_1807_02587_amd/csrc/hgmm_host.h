@@ -44,15 +44,25 @@ void launch_finalize_level(const Job* jobs, int njobs, NodeD* nodes, NodeF* tab,
 void launch_set_stop_flags(NodeF* tab, const NodeD* nodes, int64_t n, double lambda_c, hipStream_t s);
 void launch_init_pose(PoseState* st, int npairs, const double* R0, const double* t0, int stride, const int* active,
                       hipStream_t s);
+// perm (nullable): original index of each point when the cloud was reordered,
+// for the per-point outputs stop_out / gamma_out
 void launch_descend(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
                     const TreeDev* trees, const NodeF* tab, const NodeD* nodes, const PoseState* st, double* bins,
-                    double* partials, size_t pstride, int32_t* stop_out, float* gamma_out, hipStream_t s);
+                    double* partials, size_t pstride, int32_t* stop_out, float* gamma_out, const int* perm,
+                    hipStream_t s);
 void launch_fold_bins(const int2* pair_tiles, const TreeDev* trees, const double* partials, size_t pstride,
                       double* bins, int npairs, hipStream_t s);
 void launch_normal(double* bins, const double* dpart, size_t pstride, const int2* pair_tiles, const NodeD* nodes,
                    const TreeDev* trees, PoseState* st, const int64_t* n_moving, int npairs, int mode, double tol_rot,
                    double tol_trans_rel, int max_iters, double* out, hipStream_t s);
 int normal_values();
+
+// spatial ordering of the moving clouds (Morton order inside each pair)
+size_t sort_temp_bytes(int64_t n, int npairs);
+hipError_t launch_sort_points(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
+                              const TreeDev* trees, int npairs, int64_t n, uint64_t* keys, uint64_t* keys_out,
+                              int* vals, int* perm, void* temp, size_t temp_bytes, float* xo, float* yo, float* zo,
+                              hipStream_t s);
 
 // import / export
 void launch_import_nodes(NodeD* nodes, NodeF* tab, int64_t n, hipStream_t s);

@@ -53,11 +53,11 @@ __global__ void init_pose_kernel(PoseState* st, int npairs, const double* __rest
   S.status = 0;
 }
 
-// Scores of the 8 children at C for p and the most likely live one.
-template <typename NodePtr>
-__device__ __forceinline__ int choose_child(NodePtr C, const NodeD* __restrict__ nodes, int64_t gbase, double p0,
-                                            double p1, double p2, float (&s)[8], float (&q)[8], float (&m)[8],
-                                            uint32_t& livemask) {
+// Scores of the 8 children at C for p and the most likely live one; S holds
+// the children's FP64 scoring fields for the near-tie re-check.
+template <typename NodePtr, typename S64Ptr>
+__device__ __forceinline__ int choose_child(NodePtr C, S64Ptr S, double p0, double p1, double p2, float (&s)[8],
+                                            float (&q)[8], float (&m)[8], uint32_t& livemask) {
   livemask = 0u;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -92,7 +92,7 @@ __device__ __forceinline__ int choose_child(NodePtr C, const NodeD* __restrict__
       bool first = true;
       for (int k = 0; k < 8; ++k) {
         if (!(livemask >> k & 1u)) continue;
-        double v = score64(nodes[gbase + k], p0, p1, p2);
+        double v = score64(S[k], p0, p1, p2);
         if (first || v > best) { best = v; kb = k; first = false; }
       }
       k1 = kb;
@@ -102,6 +102,23 @@ __device__ __forceinline__ int choose_child(NodePtr C, const NodeD* __restrict__
 }
 
 constexpr int kLdsNodes = 72;  // levels 0 and 1 of one tree
+
+// gamma of the stop child k among the live siblings, with FP64 scores for k
+// and for every sibling whose FP32 weight 2^(s_j - s_k) exceeds 2^-40; the
+// weights of the others (each below 2^-40) are kept from FP32, so their
+// rounding moves gamma by less than 1e-11 relative.
+template <typename S64Ptr>
+__device__ __forceinline__ float gamma_fp64(S64Ptr S, uint32_t lm, int k, const float (&s)[8], float sk, double p0,
+                                            double p1, double p2) {
+  const double skd = score64(S[k], p0, p1, p2);
+  float den = 1.0f;
+  for (int j = 0; j < 8; ++j) {
+    if (!(lm >> j & 1u) || j == k) continue;
+    const float dj = s[j] - sk;
+    den += __builtin_amdgcn_exp2f(dj > -40.f ? (float)(score64(S[j], p0, p1, p2) - skd) : dj);
+  }
+  return 1.0f / den;
+}
 
 // One E-step over the tiles of every pair.  tiles[].job is the pair index.
 // Points stopping at the LDS-resident levels (0 and 1) are binned in FP64 LDS
@@ -113,7 +130,8 @@ __global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ 
                                                       const TreeDev* __restrict__ trees, const NodeF* __restrict__ tab,
                                                       const NodeD* __restrict__ nodes, const PoseState* __restrict__ st,
                                                       double* bins, double* partials, size_t pstride,
-                                                      int32_t* stop_out, float* gamma_out) {
+                                                      int32_t* stop_out, float* gamma_out,
+                                                      const int* __restrict__ perm) {
   const Tile tl = tiles[blockIdx.x];
   const int pair = tl.job;
   if (st[pair].done) return;
@@ -121,12 +139,17 @@ __global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ 
   const int L = T.levels;
   const int64_t nb = T.node_base;
   __shared__ NodeF lds[kLdsNodes];
+  __shared__ NodeS lds64[kLdsNodes];
   __shared__ double lbin[kLdsNodes * 6];
   const int nl = L >= 2 ? 72 : 8;
   for (int i = threadIdx.x; i < nl; i += blockDim.x) {
     const float4* s = reinterpret_cast<const float4*>(&tab[nb + i]);
     float4* d = reinterpret_cast<float4*>(&lds[i]);
     d[0] = s[0]; d[1] = s[1]; d[2] = s[2]; d[3] = s[3];
+    const NodeD& nd = nodes[nb + i];
+    for (int k = 0; k < 3; ++k) lds64[i].mu[k] = nd.mu[k];
+    for (int k = 0; k < 6; ++k) lds64[i].winv[k] = nd.winv[k];
+    lds64[i].c = nd.c;
   }
   for (int i = threadIdx.x; i < kLdsNodes * 6; i += blockDim.x) lbin[i] = 0.0;
   __syncthreads();
@@ -154,13 +177,13 @@ __global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ 
         float err[8];
         if (l < 2) {
           const NodeF* C = lds + lbase;
-          k = choose_child(C, nodes, nb + lbase, p0, p1, p2, s, q, m, lm);
+          k = choose_child(C, lds64 + lbase, p0, p1, p2, s, q, m, lm);
           flags = k >= 0 ? C[k].flags : 0u;
 #pragma unroll
           for (int j = 0; j < 8; ++j) err[j] = score_err(C[j], q[j], m[j]);
         } else {
           const NodeF* C = tab + nb + lbase;
-          k = choose_child(C, nodes, nb + lbase, p0, p1, p2, s, q, m, lm);
+          k = choose_child(C, nodes + nb + lbase, p0, p1, p2, s, q, m, lm);
           flags = k >= 0 ? C[k].flags : 0u;
           if (k >= 0 && ((flags & F_STOP) || !(flags & F_HASCH) || (l == L - 1))) {
 #pragma unroll
@@ -189,26 +212,18 @@ __global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ 
           gam = 1.0f / den;
           // rounding bound of gamma from the FP32 score bounds; above 1e-6
           // (relative) the sibling scores are recomputed in FP64
-          if (0.6931472f * bnd * gam > 1e-6f) {
-            double s64[8];
-            double skd = 0.0;
-            for (int j = 0; j < 8; ++j) {
-              s64[j] = (lm >> j & 1u) ? score64(nodes[nb + lbase + j], p0, p1, p2) : 0.0;
-              if (j == k) skd = s64[j];
-            }
-            float den64 = 0.f;
-            for (int j = 0; j < 8; ++j)
-              if (lm >> j & 1u) den64 += __builtin_amdgcn_exp2f((float)(s64[j] - skd));
-            gam = 1.0f / den64;
-          }
+          if (0.6931472f * bnd * gam > 1e-6f)
+            gam = (l < 2) ? gamma_fp64(lds64 + lbase, lm, k, s, sk, p0, p1, p2)
+                          : gamma_fp64(nodes + nb + lbase, lm, k, s, sk, p0, p1, p2);
           g = nb + lbase + k;
           break;
         }
         parent = 8 * parent + k;
       }
       if (g < 0) {
-        if (stop_out) stop_out[i] = -1;
-        if (gamma_out) gamma_out[i] = 0.f;
+        const int oi = perm ? perm[i] : i;
+        if (stop_out) stop_out[oi] = -1;
+        if (gamma_out) gamma_out[oi] = 0.f;
       }
     }
     if (valid && g >= 0) {
@@ -217,18 +232,21 @@ __global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ 
       const double p1 = R3 * z0 + R4 * z1 + R5 * z2 + t1;
       const double p2 = R6 * z0 + R7 * z1 + R8 * z2 + t2;
       // offset from the node mean (one FP32 rounding of an FP64 difference) and
-      // the squared Mahalanobis distance in FP64
-      const NodeD& Nd = nodes[g];
-      const double e0 = p0 - Nd.mu[0], e1 = p1 - Nd.mu[1], e2 = p2 - Nd.mu[2];
+      // the squared Mahalanobis distance in FP64 (levels 0-1 from LDS)
+      const int64_t lg = g - nb;
+      const double* mu = (lg < nl) ? lds64[lg].mu : nodes[g].mu;
+      const double* wi = (lg < nl) ? lds64[lg].winv : nodes[g].winv;
+      const double e0 = p0 - mu[0], e1 = p1 - mu[1], e2 = p2 - mu[2];
       d0 = (float)e0;
       d1 = (float)e1;
       d2 = (float)e2;
-      const double w0 = Nd.winv[0] * e0;
-      const double w1 = Nd.winv[1] * e0 + Nd.winv[2] * e1;
-      const double w2 = Nd.winv[3] * e0 + Nd.winv[4] * e1 + Nd.winv[5] * e2;
+      const double w0 = wi[0] * e0;
+      const double w1 = wi[1] * e0 + wi[2] * e1;
+      const double w2 = wi[3] * e0 + wi[4] * e1 + wi[5] * e2;
       dm2 = (float)(w0 * w0 + w1 * w1 + w2 * w2);
-      if (stop_out) stop_out[i] = (int32_t)(g - nb);
-      if (gamma_out) gamma_out[i] = gam;
+      const int oi = perm ? perm[i] : i;
+      if (stop_out) stop_out[oi] = (int32_t)(g - nb);
+      if (gamma_out) gamma_out[oi] = gam;
     }
     // aggregate equal stop nodes inside the wave, then one FP64 atomic per node
     bool pend = valid && g >= 0;
@@ -502,9 +520,10 @@ void launch_import_nodes(NodeD* nodes, NodeF* tab, int64_t n, hipStream_t s) {
 
 void launch_descend(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
                     const TreeDev* trees, const NodeF* tab, const NodeD* nodes, const PoseState* st, double* bins,
-                    double* partials, size_t pstride, int32_t* stop_out, float* gamma_out, hipStream_t s) {
+                    double* partials, size_t pstride, int32_t* stop_out, float* gamma_out, const int* perm,
+                    hipStream_t s) {
   hipLaunchKernelGGL(descend_kernel, dim3(ntiles), dim3(256), 0, s, xs, ys, zs, tiles, trees, tab, nodes, st, bins,
-                     partials, pstride, stop_out, gamma_out);
+                     partials, pstride, stop_out, gamma_out, perm);
 }
 
 void launch_fold_bins(const int2* pair_tiles, const TreeDev* trees, const double* partials, size_t pstride,

@@ -205,3 +205,54 @@ def test_register_graph_matches_stream(hg, batch):
                     np.testing.assert_array_equal(r[k], ref[k], err_msg=f"{k} replay {rep} max_iters {max_iters}")
     finally:
         hg.hgmm_set_tuning(**old)
+
+
+def test_morton_sorted_registration_matches(hg, batch):
+    """reg_sort = 1 (moving points in Morton order inside each pair) changes only
+    how points are grouped into wavefronts: per-point stop nodes and weights of
+    the E-step are identical (reported in the caller's point order), while the
+    FP32 per-wave partial sums regroup, so bins, the one-step log-likelihood and
+    registered poses agree to FP32 summation rounding."""
+    pairs, src, tgt, soff, toff, levels = batch
+    forest = hg.hgmm_build_batch(_cuda(src), soff, levels)
+    R0, t0 = _starts(pairs)
+    tg = _cuda(tgt)
+    old = hg.hgmm_get_tuning()
+    try:
+        hg.hgmm_set_tuning(reg_sort=0)
+        ref = hg.hgmm_register_batch(forest, tg, toff, R0=R0, t0=t0, max_iters=10)
+        ll0 = hg.hgmm_estep_batch(forest, tg, toff, R0, t0)
+        hg.hgmm_set_tuning(reg_sort=1)
+        r = hg.hgmm_register_batch(forest, tg, toff, R0=R0, t0=t0, max_iters=10)
+        ll1 = hg.hgmm_estep_batch(forest, tg, toff, R0, t0)
+    finally:
+        hg.hgmm_set_tuning(**old)
+    np.testing.assert_allclose(ll1, ll0, rtol=1e-6)
+    np.testing.assert_allclose(r["R"], ref["R"], atol=1e-6)
+    np.testing.assert_allclose(r["t"], ref["t"], atol=1e-6)
+    assert np.all(np.abs(r["iters"] - ref["iters"]) <= 1)
+
+
+def test_morton_sorted_estep_points_match(hg):
+    from synth import small_pair
+    p = small_pair(102, n=7_777, n_tgt=5_013, max_angle_deg=8)
+    tree = hg.hgmm_build(_cuda(p.src), levels=3)
+    tg = _cuda(p.tgt)
+    old = hg.hgmm_get_tuning()
+    try:
+        hg.hgmm_set_tuning(reg_sort=0)
+        a = hg.hgmm_estep(tree, tg, p.R_true, p.t_true)
+        hg.hgmm_set_tuning(reg_sort=1)
+        b = hg.hgmm_estep(tree, tg, p.R_true, p.t_true)
+    finally:
+        hg.hgmm_set_tuning(**old)
+    np.testing.assert_array_equal(b["stop_node"].cpu().numpy(), a["stop_node"].cpu().numpy())
+    np.testing.assert_array_equal(b["gamma"].cpu().numpy(), a["gamma"].cpu().numpy())
+    ba, bb = a["bins"].cpu().numpy(), b["bins"].cpu().numpy()
+    act = ba[:, 0] > 0
+    ext = tree.info()["extent"]
+    # M0 and counts relative; first moments normalised by M0 * extent; sum d^2 relative
+    np.testing.assert_array_equal(bb[:, 4], ba[:, 4])
+    assert np.all(np.abs(bb[act, 0] - ba[act, 0]) <= 1e-6 * ba[act, 0])
+    assert np.all(np.abs(bb[act, 1:4] - ba[act, 1:4]) <= 1e-6 * ba[act, :1] * ext)
+    assert np.all(np.abs(bb[act, 5] - ba[act, 5]) <= 1e-6 * ba[act, 5])
