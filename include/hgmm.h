@@ -261,8 +261,8 @@ void hgmm_tree_destroy(hgmm_tree tree);
  * the search space of the autotuner).  Construction of a level: a parent with
  * at most block64_max points runs all its EM iterations in one 64-thread
  * block, at most block256_max in one 256-thread block, at most block512_max
- * in one 512-thread block; a larger parent is cut into tiles of 256 threads
- * and each EM iteration is one tile launch (which also runs the previous
+ * in one 512-thread block; a larger parent is cut into tiles of tile_threads
+ * threads and each EM iteration is one tile launch (which also runs the previous
  * iteration's M-step), plus one final M-step launch per level.  Points per
  * tile are level_points / target_tiles rounded up to a multiple of 64 and
  * clamped to [min_tile, max_tile].  Registration: reg_tile points per
@@ -276,20 +276,21 @@ void hgmm_tree_destroy(hgmm_tree tree);
  * code of their position in the model tree's frame (one radix sort per call,
  * inside the workspace) so that neighbouring lanes stop at the same nodes;
  * the results change only by summation order.
- * Defaults 256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0. */
+ * Defaults 256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0, 256. */
 typedef struct hgmm_tuning {
   int32_t block64_max, block256_max, block512_max;
   int32_t min_tile, target_tiles, max_tile;
   int32_t reg_tile, reg_chunk;
   int32_t reg_graph;  /* 1: each chunk of registration iterations is one hipGraph launch */
   int32_t reg_sort;   /* 1: the moving cloud is put in Morton order once per registration call */
+  int32_t tile_threads; /* threads per construction tile: 256, 512 or 1024 */
 } hgmm_tuning;
 
 /* Set (after validation) or read the launch shapes.  hgmm_set_tuning returns
  * HGMM_EINVAL, changing nothing, unless 0 <= block64_max <= block256_max <=
  * block512_max <= 1<<20, 64 <= min_tile <= max_tile <= 1<<20,
  * target_tiles >= 1, 256 <= reg_tile <= 1<<20, 1 <= reg_chunk <= 64 and
- * reg_graph, reg_sort in {0, 1}.
+ * reg_graph, reg_sort in {0, 1} and tile_threads in {256, 512, 1024}.
  * Values are rounded up to the multiples stated above.  Not thread-safe
  * against concurrent calls of the library. */
 int hgmm_set_tuning(const hgmm_tuning *t);

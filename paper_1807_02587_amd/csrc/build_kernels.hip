@@ -411,14 +411,14 @@ __device__ __forceinline__ uint32_t live_mask(const NodeF* ch) {
 // job, slot = Tile::pad).  The first iteration starts from the initial
 // children in the scoring table.  Tile partials of the 80 moment sums are
 // FP64, value-major (part_next[v * pstride + tile]), ping-pong as well.
-constexpr int kTileThreads = 256;
-__global__ __launch_bounds__(kTileThreads) void em_tile_kernel(
+template <int NT, int KP>
+__global__ __launch_bounds__(NT) void em_tile_kernel(
     const float* __restrict__ xs, const float* __restrict__ ys, const float* __restrict__ zs,
     const Tile* __restrict__ tiles, const int* __restrict__ tile_ids, const Job* __restrict__ jobs,
     const NodeF* __restrict__ tab, const NodeF* __restrict__ ch_prev, NodeF* ch_next,
     const double* __restrict__ part_prev, double* part_next, size_t pstride, double eps, double min_mass,
     int first) {
-  constexpr int NT = kTileThreads, NR = NT / 16, NW = NT / 64;
+  constexpr int NR = NT / 16, NW = NT / 64;
   const int tix = tile_ids[blockIdx.x];
   const Tile tl = tiles[tix];
   const Job jb = jobs[tl.job];
@@ -428,6 +428,9 @@ __global__ __launch_bounds__(kTileThreads) void em_tile_kernel(
   __shared__ EmFrame fr;
   __shared__ float rows[NR][80];
   __shared__ double tot[80];
+  // this block's points are requested first; their latency overlaps the fold
+  PointCache<KP> pc;
+  load_points<NT>(xs, ys, zs, tl.start, tl.end, tid, pc);
   if (tid < 8) copy_nodef(ch[tid], first ? tab[jb.child_base + tid] : ch_prev[(size_t)slot * 8 + tid]);
   if (!first) {
     // wave w folds value groups w, w + NW, ... of 5 values each
@@ -447,8 +450,6 @@ __global__ __launch_bounds__(kTileThreads) void em_tile_kernel(
   if (live) em_frame(ch, live, fr, tid);
   __syncthreads();
   if (live) {
-    PointCache<4> pc;
-    load_points<NT>(xs, ys, zs, tl.start, tl.end, tid, pc);
     em_range<NT>(xs, ys, zs, tl.start, tl.end, tid, pc, ch, fr, live, a);
   } else {
     for (int k = 0; k < 8; ++k)
@@ -751,11 +752,19 @@ void launch_init_children(const Job* jobs, int njobs, const TreeDev* trees, Node
                      eps);
 }
 
-void launch_em_tile(const float* xs, const float* ys, const float* zs, const Tile* tiles, const int* tile_ids, int n,
-                    const Job* jobs, const NodeF* tab, const NodeF* ch_prev, NodeF* ch_next, const double* part_prev,
-                    double* part_next, size_t pstride, double eps, double min_mass, int first, hipStream_t s) {
-  hipLaunchKernelGGL(em_tile_kernel, dim3(n), dim3(kTileThreads), 0, s, xs, ys, zs, tiles, tile_ids, jobs, tab,
-                     ch_prev, ch_next, part_prev, part_next, pstride, eps, min_mass, first);
+void launch_em_tile(int nt, const float* xs, const float* ys, const float* zs, const Tile* tiles, const int* tile_ids,
+                    int n, const Job* jobs, const NodeF* tab, const NodeF* ch_prev, NodeF* ch_next,
+                    const double* part_prev, double* part_next, size_t pstride, double eps, double min_mass, int first,
+                    hipStream_t s) {
+  if (nt == 1024)
+    hipLaunchKernelGGL((em_tile_kernel<1024, 2>), dim3(n), dim3(1024), 0, s, xs, ys, zs, tiles, tile_ids, jobs, tab,
+                       ch_prev, ch_next, part_prev, part_next, pstride, eps, min_mass, first);
+  else if (nt == 512)
+    hipLaunchKernelGGL((em_tile_kernel<512, 4>), dim3(n), dim3(512), 0, s, xs, ys, zs, tiles, tile_ids, jobs, tab,
+                       ch_prev, ch_next, part_prev, part_next, pstride, eps, min_mass, first);
+  else
+    hipLaunchKernelGGL((em_tile_kernel<256, 4>), dim3(n), dim3(256), 0, s, xs, ys, zs, tiles, tile_ids, jobs, tab,
+                       ch_prev, ch_next, part_prev, part_next, pstride, eps, min_mass, first);
 }
 
 void launch_em_mstep(const int* job_ids, int n, const Job* jobs, NodeF* tab, NodeD* nodes, const double* partials,

@@ -292,7 +292,7 @@ static int64_t max_lvl_for(const std::vector<TreeHost>& trees) {
 // launch shapes (process wide; see hgmm_tuning)
 // ---------------------------------------------------------------------------
 
-static hgmm_tuning g_tune = {256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0};
+static hgmm_tuning g_tune = {256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0, 256};
 
 extern "C" int hgmm_set_tuning(const hgmm_tuning* t) {
   if (!t) return fail(HGMM_EINVAL, "null tuning");
@@ -306,6 +306,8 @@ extern "C" int hgmm_set_tuning(const hgmm_tuning* t) {
     return fail(HGMM_EINVAL, "reg_tile must be in [256, 2^20] and reg_chunk in [1, 64]");
   if (t->reg_graph != 0 && t->reg_graph != 1) return fail(HGMM_EINVAL, "reg_graph must be 0 or 1");
   if (t->reg_sort != 0 && t->reg_sort != 1) return fail(HGMM_EINVAL, "reg_sort must be 0 or 1");
+  if (t->tile_threads != 256 && t->tile_threads != 512 && t->tile_threads != 1024)
+    return fail(HGMM_EINVAL, "tile_threads must be 256, 512 or 1024");
   g_tune = *t;
   g_tune.min_tile = (t->min_tile + 63) / 64 * 64;
   g_tune.max_tile = (t->max_tile + 63) / 64 * 64;
@@ -622,7 +624,8 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
     if (nbig && p.build_iters > 0) {
       for (int it = 0; it < p.build_iters; ++it) {
         ProfScope ps(PK_EM_TILE, (double)cls_points[3], s);
-        launch_em_tile(cx, cy, cz, d_tiles, d_tile_ids, nbig, d_jobs, f->d_tab, d_ch[(it + 1) & 1], d_ch[it & 1],
+        launch_em_tile(g_tune.tile_threads, cx, cy, cz, d_tiles, d_tile_ids, nbig, d_jobs, f->d_tab, d_ch[(it + 1) & 1],
+                       d_ch[it & 1],
                        d_part[(it + 1) & 1], d_part[it & 1], (size_t)Ly.max_tiles, p.reg_eps, p.min_mass, it == 0, s);
       }
       const int last = (p.build_iters - 1) & 1;

@@ -27,9 +27,10 @@ const std::vector<Knob>& knobs() {
       {&hgmm_tuning::block64_max, {0, 128, 256, 512}},
       {&hgmm_tuning::block256_max, {256, 512, 1024, 2048}},
       {&hgmm_tuning::block512_max, {1024, 2048, 4096, 8192}},
-      {&hgmm_tuning::min_tile, {256, 512, 1024, 2048}},
+      {&hgmm_tuning::tile_threads, {256, 512, 1024}},
+      {&hgmm_tuning::min_tile, {256, 512, 1024, 2048, 4096}},
       {&hgmm_tuning::target_tiles, {256, 512, 1024, 2048, 4096}},
-      {&hgmm_tuning::max_tile, {1024, 2048, 4096, 8192}},
+      {&hgmm_tuning::max_tile, {1024, 2048, 4096, 8192, 16384}},
       {&hgmm_tuning::reg_tile, {256, 512, 1024, 2048}},
       {&hgmm_tuning::reg_chunk, {2, 4, 8, 16}},
       {&hgmm_tuning::reg_graph, {0, 1}},

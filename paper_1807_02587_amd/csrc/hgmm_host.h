@@ -20,9 +20,10 @@ void launch_init_children(const Job* jobs, int njobs, const TreeDev* trees, Node
 // previous iteration's M-step; children and partials ping-pong between the
 // *_prev and *_next buffers; then, after the last iteration, the final M-step
 // from that iteration's children (chsrc, one set of 8 per tiled job)
-void launch_em_tile(const float* xs, const float* ys, const float* zs, const Tile* tiles, const int* tile_ids, int n,
-                    const Job* jobs, const NodeF* tab, const NodeF* ch_prev, NodeF* ch_next, const double* part_prev,
-                    double* part_next, size_t pstride, double eps, double min_mass, int first, hipStream_t s);
+void launch_em_tile(int nt, const float* xs, const float* ys, const float* zs, const Tile* tiles, const int* tile_ids,
+                    int n, const Job* jobs, const NodeF* tab, const NodeF* ch_prev, NodeF* ch_next,
+                    const double* part_prev, double* part_next, size_t pstride, double eps, double min_mass, int first,
+                    hipStream_t s);
 void launch_em_mstep(const int* job_ids, int n, const Job* jobs, NodeF* tab, NodeD* nodes, const double* partials,
                      size_t pstride, double eps, double min_mass, const NodeF* chsrc, hipStream_t s);
 // all EM iterations of n jobs, one block of nt (64, 256 or 512) threads per job
