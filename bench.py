@@ -46,6 +46,35 @@ DESC_FLOP_PER_LEVEL = 8 * 19
 DESC_BYTES_PER_POINT = 12
 
 
+def roofline_of(prof, depth, traffic=False):
+    """ALU roofline of the kernel family with the largest summed event time.
+    prof: hgmm_profile_read per kind; depth: mean levels visited per point by
+    the descent (for its FLOP count)."""
+    cand = {"em_tile": ("em_tile_kernel (construction EM iteration of large parents)", EM_FLOP_PER_POINT_ITER,
+                        EM_BYTES_PER_POINT_ITER),
+            "em_block": ("em_block_kernel (all construction EM iterations, one block per parent)",
+                         EM_FLOP_PER_POINT_ITER, EM_BYTES_PER_POINT_ITER),
+            "descend": ("descend_kernel (registration E-step)", DESC_FLOP_FIXED + DESC_FLOP_PER_LEVEL * depth,
+                        DESC_BYTES_PER_POINT)}
+    dom = max(cand, key=lambda k: prof[k]["ms"])
+    kname, flop_unit, bytes_unit = cand[dom]
+    ms, launches, units = prof[dom]["ms"], prof[dom]["launches"], prof[dom]["units"]
+    flop, byts = units * flop_unit, units * bytes_unit
+    achieved = flop / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": _traffic(dom) if traffic else None,
+            "kernel": kname, "launches": launches, "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
+            "flop_per_launch": round(flop / max(launches, 1)),
+            "frac_of_packed_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4),
+            "achieved_hbm_GBs": round(byts / (ms * 1e-3) / 1e9, 1) if ms > 0 else 0.0}
+
+
+def mean_depth(stop, level_offsets):
+    """Mean number of levels a point visited, from its stop node (index in its tree)."""
+    st = stop[stop >= 0]
+    return float(np.mean(np.searchsorted(level_offsets, st, side="right"))) if st.size else 0.0
+
+
 TRAFFIC = os.path.join(ROOT, "profiles", "lidar_hbm_traffic.json")
 
 
@@ -107,9 +136,13 @@ def batch_section(args, hg):
             Rs.append(hg.hgmm_register(tree, t_k, ws=ws, raise_singular=False)["R"])
         return np.array(Rs)
 
+    last = {}
+
     def batched_plain():
         forest = hg.hgmm_build_batch(src, off, lv, ws=ws)
-        return hg.hgmm_register_batch(forest, tgt, off, ws=ws)["R"]
+        r = hg.hgmm_register_batch(forest, tgt, off, ws=ws)
+        last.update(forest=forest, r=r)
+        return r["R"]
 
     net = None
     if os.path.exists(WEIGHTS):
@@ -160,6 +193,22 @@ def batch_section(args, hg):
     out.update(summary("batched", Rb, tb))
     if tp:
         out["speedup_batched_vs_plain"] = round(tp / tb, 2)
+    # the batched plain form once more with HIP events around every launch:
+    # per-kernel durations and the roofline of its dominant kernel
+    hg.hgmm_profile_reset()
+    hg.hgmm_profile(True)
+    batched_plain()
+    torch.cuda.synchronize()
+    hg.hgmm_profile(False)
+    prof = {k: hg.hgmm_profile_read(k) for k in hg.PROFILE_KINDS}
+    _, stop = hg.hgmm_estep_batch(last["forest"], tgt, off, last["r"]["R"], last["r"]["t"], ws=ws, stop_nodes=True)
+    offs_l = np.array([hg.hgmm_level_offset(l) for l in range(8)])
+    depth = mean_depth(stop.cpu().numpy(), offs_l)
+    ds = prof["descend"]
+    out["profiled"] = {"kernels_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
+                       "mean_levels_visited": round(depth, 3),
+                       "estep_mpts_s": round(ds["units"] / (ds["ms"] * 1e-3) / 1e6, 1) if ds["ms"] > 0 else None,
+                       "roofline": roofline_of(prof, depth)}
     if net is not None:
         batched_warm()
         rw, tw = timed(batched_warm)
@@ -344,27 +393,10 @@ def main():
     e = hg.hgmm_estep(tree, tgt, r["R"], r["t"], lambda_c=pr["lambda_c"])
     off = np.array([hg.hgmm_level_offset(l) for l in range(pr["levels"] + 1)])
     stop = e["stop_node"].cpu().numpy()
-    depth = float(np.mean(np.searchsorted(off, stop, side="right")))
+    depth = mean_depth(stop, off)
 
-    # dominant kernel (largest summed time) and its roofline
-    cand = {"em_tile": ("em_tile_kernel (construction EM iteration of large parents)", EM_FLOP_PER_POINT_ITER,
-                        EM_BYTES_PER_POINT_ITER),
-            "em_block": ("em_block_kernel (all construction EM iterations, one block per parent)",
-                         EM_FLOP_PER_POINT_ITER, EM_BYTES_PER_POINT_ITER),
-            "descend": ("descend_kernel (registration E-step)", DESC_FLOP_FIXED + DESC_FLOP_PER_LEVEL * depth,
-                        DESC_BYTES_PER_POINT)}
-    dom = max(cand, key=lambda k: prof[k]["ms"])
-    kname, flop_unit, bytes_unit = cand[dom]
-    ms, launches, units = prof[dom]["ms"], prof[dom]["launches"], prof[dom]["units"]
-    flop, byts = units * flop_unit, units * bytes_unit
+    roofline = roofline_of(prof, depth, traffic=True)
     ds = prof["descend"]
-    achieved = flop / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": _traffic(dom), "kernel": kname,
-                "launches": launches, "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
-                "flop_per_launch": round(flop / max(launches, 1)),
-                "frac_of_packed_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4),
-                "achieved_hbm_GBs": round(byts / (ms * 1e-3) / 1e9, 1) if ms > 0 else 0.0}
     estep_mpts = ds["units"] / (ds["ms"] * 1e-3) / 1e6 if ds["ms"] > 0 else 0.0
 
     cpu = None

@@ -87,10 +87,12 @@ typedef struct {
  * variant of Sec. 5).  The loop stops after max_iters E/M iterations or once
  * the angle of the rotation increment is below tol_rot (radians) and the norm
  * of the translation increment is below tol_trans_rel times the model's
- * bounding-box diagonal. */
+ * bounding-box diagonal.  max_levels > 0 caps the descent at that many levels
+ * (level max_levels-1 acts as the last level, as in a tree built with
+ * max_levels levels); 0 uses every level of the tree. */
 typedef struct {
   int32_t max_iters;   /* default 30 */
-  int32_t pad_;
+  int32_t max_levels;  /* default 0 (all levels) */
   double lambda_c;     /* default 0.01 */
   double tol_rot;      /* default 1e-6 */
   double tol_trans_rel;/* default 1e-6 */
@@ -188,9 +190,12 @@ int hgmm_register_batch(hgmm_tree forest, const float *d_xyz, const int64_t *off
                         void *d_ws, size_t ws_bytes, void *stream, double *R, double *t, int *iters, double *loglik,
                         int *status);
 /* Mean log-likelihood of every target cloud at a fixed transform (R: B x 9,
- * t: B x 3, host): one E-step (Algorithm 1) per pair. */
+ * t: B x 3, host): one E-step (Algorithm 1) per pair.  d_stop (nullable,
+ * device, offsets[B] int32) receives each point's stop node (index inside its
+ * pair's tree, -1 if unassigned). */
 int hgmm_estep_batch(hgmm_tree forest, const float *d_xyz, const int64_t *offsets, int B, const double *R,
-                     const double *t, double lambda_c, void *d_ws, size_t ws_bytes, void *stream, double *loglik);
+                     const double *t, double lambda_c, void *d_ws, size_t ws_bytes, void *stream, double *loglik,
+                     int32_t *d_stop);
 
 /* ---- learned warm start ---------------------------------------------------
  * Not part of the paper: a small network that maps the coarse GMMs of both
@@ -276,7 +281,9 @@ void hgmm_tree_destroy(hgmm_tree tree);
  * code of their position in the model tree's frame (one radix sort per call,
  * inside the workspace) so that neighbouring lanes stop at the same nodes;
  * the results change only by summation order.
- * Defaults 256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0, 256. */
+ * reg_lds_levels = 3 also stages level 2 (512 nodes, 37 KB per block), which
+ * pays for large registration tiles.
+ * Defaults 256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0, 256, 2. */
 typedef struct hgmm_tuning {
   int32_t block64_max, block256_max, block512_max;
   int32_t min_tile, target_tiles, max_tile;
@@ -284,13 +291,15 @@ typedef struct hgmm_tuning {
   int32_t reg_graph;  /* 1: each chunk of registration iterations is one hipGraph launch */
   int32_t reg_sort;   /* 1: the moving cloud is put in Morton order once per registration call */
   int32_t tile_threads; /* threads per construction tile: 256, 512 or 1024 */
+  int32_t reg_lds_levels; /* tree levels whose scoring records the descent stages in LDS: 2 or 3 */
 } hgmm_tuning;
 
 /* Set (after validation) or read the launch shapes.  hgmm_set_tuning returns
  * HGMM_EINVAL, changing nothing, unless 0 <= block64_max <= block256_max <=
  * block512_max <= 1<<20, 64 <= min_tile <= max_tile <= 1<<20,
  * target_tiles >= 1, 256 <= reg_tile <= 1<<20, 1 <= reg_chunk <= 64 and
- * reg_graph, reg_sort in {0, 1} and tile_threads in {256, 512, 1024}.
+ * reg_graph, reg_sort in {0, 1}, tile_threads in {256, 512, 1024} and
+ * reg_lds_levels in {2, 3}.
  * Values are rounded up to the multiples stated above.  Not thread-safe
  * against concurrent calls of the library. */
 int hgmm_set_tuning(const hgmm_tuning *t);

@@ -19,11 +19,11 @@ class BuildParams(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [(k, C.c_int32) for k in ("block64_max", "block256_max", "block512_max", "min_tile", "target_tiles",
-                                          "max_tile", "reg_tile", "reg_chunk", "reg_graph", "reg_sort", "tile_threads")]
+                                          "max_tile", "reg_tile", "reg_chunk", "reg_graph", "reg_sort", "tile_threads", "reg_lds_levels")]
 
 
 class RegParams(C.Structure):
-    _fields_ = [("max_iters", C.c_int32), ("pad_", C.c_int32), ("lambda_c", D), ("tol_rot", D),
+    _fields_ = [("max_iters", C.c_int32), ("max_levels", C.c_int32), ("lambda_c", D), ("tol_rot", D),
                 ("tol_trans_rel", D)]
 
 
@@ -58,7 +58,7 @@ SIGNATURES = {
     "hgmm_build_batch": (C.c_int, [P, P, P, C.c_int, P, P, C.c_size_t, P, P]),
     "hgmm_register_batch_workspace_bytes": (C.c_size_t, [P, P, C.c_int]),
     "hgmm_register_batch": (C.c_int, [P, P, P, C.c_int, P, P, P, P, P, C.c_size_t, P, P, P, P, P, P]),
-    "hgmm_estep_batch": (C.c_int, [P, P, P, C.c_int, P, P, D, P, C.c_size_t, P, P]),
+    "hgmm_estep_batch": (C.c_int, [P, P, P, C.c_int, P, P, D, P, C.c_size_t, P, P, P]),
     "hgmm_mlp_param_count": (I64, []),
     "hgmm_mlp_create": (C.c_int, [C.c_uint64, P]),
     "hgmm_mlp_destroy": (None, [P]),

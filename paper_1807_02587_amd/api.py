@@ -67,7 +67,7 @@ def hgmm_level_offset(level: int) -> int:
 
 
 TUNING_KEYS = ("block64_max", "block256_max", "block512_max", "min_tile", "target_tiles", "max_tile", "reg_tile",
-               "reg_chunk", "reg_graph", "reg_sort", "tile_threads")
+               "reg_chunk", "reg_graph", "reg_sort", "tile_threads", "reg_lds_levels")
 
 
 def hgmm_get_tuning() -> dict:
@@ -201,11 +201,11 @@ def _pose_args(R0, t0):
 
 def hgmm_register(tree: Tree, xyz: torch.Tensor, max_iters: int = 30, lambda_c: float = 0.01,
                   tol_rot: float = 1e-6, tol_trans_rel: float = 1e-6, R0=None, t0=None,
-                  ws: Workspace | None = None, stream=None, raise_singular: bool = True) -> dict:
+                  ws: Workspace | None = None, stream=None, raise_singular: bool = True, max_levels: int = 0) -> dict:
     xyz = _cloud(xyz)
     lib = _lib.load()
     n = xyz.shape[1]
-    p = RegParams(max_iters, 0, lambda_c, tol_rot, tol_trans_rel)
+    p = RegParams(max_iters, max_levels, lambda_c, tol_rot, tol_trans_rel)
     R0a, t0a = _pose_args(R0, t0)
     ws = ws or Workspace(xyz.device)
     wptr, wlen = ws.ptr(lib.hgmm_register_workspace_bytes(n, tree.levels))
@@ -331,12 +331,12 @@ def hgmm_build_batch(xyz: torch.Tensor, offsets, levels, build_iters: int = 30, 
 
 def hgmm_register_batch(forest: Tree, xyz: torch.Tensor, offsets, max_iters: int = 30, lambda_c: float = 0.01,
                         tol_rot: float = 1e-6, tol_trans_rel: float = 1e-6, R0=None, t0=None, active=None,
-                        ws: Workspace | None = None, stream=None) -> dict:
+                        ws: Workspace | None = None, stream=None, max_levels: int = 0) -> dict:
     xyz = _cloud(xyz)
     lib = _lib.load()
     off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
     B = len(off) - 1
-    p = RegParams(max_iters, 0, lambda_c, tol_rot, tol_trans_rel)
+    p = RegParams(max_iters, max_levels, lambda_c, tol_rot, tol_trans_rel)
     R0a = None if R0 is None else np.ascontiguousarray(np.asarray(R0, dtype=np.float64).reshape(B, 9))
     t0a = None if t0 is None else np.ascontiguousarray(np.asarray(t0, dtype=np.float64).reshape(B, 3))
     ws = ws or Workspace(xyz.device)
@@ -358,8 +358,10 @@ def hgmm_register_batch(forest: Tree, xyz: torch.Tensor, offsets, max_iters: int
 
 
 def hgmm_estep_batch(forest: Tree, xyz: torch.Tensor, offsets, R, t, lambda_c: float = 0.01,
-                     ws: Workspace | None = None, stream=None) -> np.ndarray:
-    """Mean log-likelihood per pair at fixed transforms R (B,3,3), t (B,3)."""
+                     ws: Workspace | None = None, stream=None, stop_nodes: bool = False):
+    """Mean log-likelihood per pair at fixed transforms R (B,3,3), t (B,3); with
+    stop_nodes=True also each point's stop node (int32 CUDA tensor, index inside
+    its pair's tree, -1 if unassigned)."""
     xyz = _cloud(xyz)
     lib = _lib.load()
     off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
@@ -369,9 +371,14 @@ def hgmm_estep_batch(forest: Tree, xyz: torch.Tensor, offsets, R, t, lambda_c: f
     ws = ws or Workspace(xyz.device)
     wptr, wlen = ws.ptr(lib.hgmm_register_batch_workspace_bytes(forest.handle, off.ctypes.data_as(C.c_void_p), B))
     ll = np.zeros(B)
+    stop = torch.empty(int(off[-1]), dtype=torch.int32, device=xyz.device) if stop_nodes else None
     check(lib.hgmm_estep_batch(forest.handle, C.c_void_p(xyz.data_ptr()), off.ctypes.data_as(C.c_void_p), B,
                                Ra.ctypes.data_as(C.c_void_p), ta.ctypes.data_as(C.c_void_p), lambda_c, wptr, wlen,
-                               _stream(stream), ll.ctypes.data_as(C.c_void_p)), "hgmm_estep_batch")
+                               _stream(stream), ll.ctypes.data_as(C.c_void_p),
+                               None if stop is None else C.c_void_p(stop.data_ptr())), "hgmm_estep_batch")
+    if stop_nodes:
+        torch.cuda.current_stream().synchronize()
+        return ll, stop
     return ll
 
 

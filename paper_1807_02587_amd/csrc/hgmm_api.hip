@@ -292,7 +292,7 @@ static int64_t max_lvl_for(const std::vector<TreeHost>& trees) {
 // launch shapes (process wide; see hgmm_tuning)
 // ---------------------------------------------------------------------------
 
-static hgmm_tuning g_tune = {256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0, 256};
+static hgmm_tuning g_tune = {256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0, 256, 2};
 
 extern "C" int hgmm_set_tuning(const hgmm_tuning* t) {
   if (!t) return fail(HGMM_EINVAL, "null tuning");
@@ -308,6 +308,7 @@ extern "C" int hgmm_set_tuning(const hgmm_tuning* t) {
   if (t->reg_sort != 0 && t->reg_sort != 1) return fail(HGMM_EINVAL, "reg_sort must be 0 or 1");
   if (t->tile_threads != 256 && t->tile_threads != 512 && t->tile_threads != 1024)
     return fail(HGMM_EINVAL, "tile_threads must be 256, 512 or 1024");
+  if (t->reg_lds_levels != 2 && t->reg_lds_levels != 3) return fail(HGMM_EINVAL, "reg_lds_levels must be 2 or 3");
   g_tune = *t;
   g_tune.min_tile = (t->min_tile + 63) / 64 * 64;
   g_tune.max_tile = (t->max_tile + 63) / 64 * 64;
@@ -591,11 +592,9 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
                     p.reg_eps, s);
       }
       HIP_LAUNCHED();
-      HIP_TRY(hipMemcpyAsync(h_trees + B, f->d_trees, sizeof(TreeDev) * B, hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      prof_collect();
-      for (int b = 0; b < B; ++b)
-        if (h_trees[B + b].status != 0) return fail(HGMM_ENONFINITE, "non-finite coordinate in cloud %d", b);
+      // a non-finite coordinate is reported after the build: the kernels stay
+      // in bounds on non-finite values (such children fail their Cholesky and
+      // die), so no synchronisation is spent on it here
     }
 
     // ---- EM for the 8 children of every job.  The block classes run on side
@@ -661,10 +660,12 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
       prof_collect();
     }
   }
-  // origin and extent back to the host copy
+  // origin, extent and status back to the host copy
   HIP_TRY(hipMemcpyAsync(h_trees + B, f->d_trees, sizeof(TreeDev) * B, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   prof_collect();
+  for (int b = 0; b < B; ++b)
+    if (h_trees[B + b].status != 0) return fail(HGMM_ENONFINITE, "non-finite coordinate in cloud %d", b);
   f->has_labels = true;
   return HGMM_OK;
 }
@@ -676,6 +677,7 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
 struct RegRun {
   int max_iters;
   double lambda_c, tol_rot, tol_trans_rel;
+  int max_levels;  // 0: every level of the tree
 };
 
 static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, const float* zs,
@@ -767,7 +769,7 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   const size_t pstride = (size_t)Ly.max_tiles;
   if (mode_estep) {
     launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins, d_dpart, pstride,
-                   stop_out, gamma_out, d_perm, s);
+                   stop_out, gamma_out, d_perm, g_tune.reg_lds_levels, rr.max_levels, s);
     launch_fold_bins(d_ptiles, f->d_trees, d_dpart, pstride, d_bins, P, s);
     if (h_norm) {
       launch_normal(d_bins, d_dpart, pstride, d_ptiles, f->d_nodes, f->d_trees, d_state, d_nmov, P, 1, 0.0, 0.0, 1,
@@ -793,14 +795,14 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
                                        (uint64_t)f->d_trees, (uint64_t)f->d_tab, (uint64_t)f->d_nodes,
                                        (uint64_t)d_state, (uint64_t)d_bins, (uint64_t)d_dpart, (uint64_t)pstride,
                                        (uint64_t)d_ptiles, (uint64_t)d_nmov, (uint64_t)P, (uint64_t)chunk, tr, tt,
-                                       (uint64_t)rr.max_iters, (uint64_t)d_out};
+                                       (uint64_t)rr.max_iters, (uint64_t)rr.max_levels, (uint64_t)d_out};
     if (!f->reg_exec || f->reg_key != key) {
       if (f->reg_exec) { (void)hipGraphExecDestroy(f->reg_exec); f->reg_exec = nullptr; }
       f->reg_key.clear();
       HIP_TRY(hipStreamBeginCapture(f->gstream, hipStreamCaptureModeThreadLocal));
       for (int c = 0; c < chunk; ++c) {
         launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins, d_dpart,
-                       pstride, nullptr, nullptr, nullptr, f->gstream);
+                       pstride, nullptr, nullptr, nullptr, g_tune.reg_lds_levels, rr.max_levels, f->gstream);
         launch_normal(d_bins, d_dpart, pstride, d_ptiles, f->d_nodes, f->d_trees, d_state, d_nmov, P, 0, rr.tol_rot,
                       rr.tol_trans_rel, rr.max_iters, d_out, f->gstream);
       }
@@ -834,7 +836,7 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
       {
         ProfScope ps(PK_DESCEND, (double)n_total, s, it);
         launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins, d_dpart,
-                       pstride, nullptr, nullptr, nullptr, s);
+                       pstride, nullptr, nullptr, nullptr, g_tune.reg_lds_levels, rr.max_levels, s);
       }
       {
         ProfScope ps(PK_NORMAL, (double)nodes_total, s, it);
@@ -868,7 +870,7 @@ const char* hgmm_last_error(void) { return g_err.c_str(); }
 
 int hgmm_params_default(hgmm_build_params* bp, hgmm_reg_params* rp) {
   if (bp) { bp->levels = 2; bp->build_iters = 30; bp->reg_eps = 1e-6; bp->min_mass = 1.0; }
-  if (rp) { rp->max_iters = 30; rp->pad_ = 0; rp->lambda_c = 0.01; rp->tol_rot = 1e-6; rp->tol_trans_rel = 1e-6; }
+  if (rp) { rp->max_iters = 30; rp->max_levels = 0; rp->lambda_c = 0.01; rp->tol_rot = 1e-6; rp->tol_trans_rel = 1e-6; }
   return HGMM_OK;
 }
 
@@ -935,7 +937,7 @@ int hgmm_register(hgmm_tree tree, const float* d_xyz, int64_t n, const hgmm_reg_
   if (p->max_iters < 1) return fail(HGMM_EINVAL, "max_iters must be >= 1");
   if (tree->trees.size() != 1) return fail(HGMM_EINVAL, "hgmm_register takes a single-tree handle");
   std::vector<int64_t> offs = {0, n};
-  RegRun rr{p->max_iters, p->lambda_c, p->tol_rot, p->tol_trans_rel};
+  RegRun rr{p->max_iters, p->lambda_c, p->tol_rot, p->tol_trans_rel, p->max_levels};
   PoseState res;
   int rc = run_register(tree, d_xyz, d_xyz + n, d_xyz + 2 * n, offs, R0, t0, 0, rr, (char*)d_ws, ws_bytes,
                         (hipStream_t)stream, 0, nullptr, nullptr, nullptr, &res, nullptr);
@@ -955,7 +957,7 @@ int hgmm_estep(hgmm_tree tree, const float* d_xyz, int64_t n, const double R[9],
   if (n < 1) return fail(HGMM_ETOOFEW, "empty cloud");
   if (tree->trees.size() != 1) return fail(HGMM_EINVAL, "hgmm_estep takes a single-tree handle");
   std::vector<int64_t> offs = {0, n};
-  RegRun rr{1, lambda_c, 0.0, 0.0};
+  RegRun rr{1, lambda_c, 0.0, 0.0, 0};
   double nrm[28];
   int rc = run_register(tree, d_xyz, d_xyz + n, d_xyz + 2 * n, offs, R, t, 0, rr, (char*)d_ws, ws_bytes,
                         (hipStream_t)stream, 1, d_stop_node, d_gamma, d_bins, nullptr, loglik ? nrm : nullptr);
@@ -1172,7 +1174,7 @@ int hgmm_register_batch(hgmm_tree forest, const float* d_xyz, const int64_t* off
   for (int b = 0; b < B; ++b)
     if (offsets[b + 1] - offsets[b] < 1) return fail(HGMM_ETOOFEW, "cloud %d to register is empty", b);
   std::vector<int64_t> offs(offsets, offsets + B + 1);
-  RegRun rr{p->max_iters, p->lambda_c, p->tol_rot, p->tol_trans_rel};
+  RegRun rr{p->max_iters, p->lambda_c, p->tol_rot, p->tol_trans_rel, p->max_levels};
   std::vector<PoseState> res((size_t)B);
   const int64_t n = offsets[B];
   rc = run_register(forest, d_xyz, d_xyz + n, d_xyz + 2 * n, offs, R0, t0, 1, rr, (char*)d_ws, ws_bytes,
@@ -1192,7 +1194,8 @@ int hgmm_register_batch(hgmm_tree forest, const float* d_xyz, const int64_t* off
 }
 
 int hgmm_estep_batch(hgmm_tree forest, const float* d_xyz, const int64_t* offsets, int B, const double* R,
-                     const double* t, double lambda_c, void* d_ws, size_t ws_bytes, void* stream, double* loglik) {
+                     const double* t, double lambda_c, void* d_ws, size_t ws_bytes, void* stream, double* loglik,
+                     int32_t* d_stop) {
   int rc = check_offsets(offsets, B);
   if (rc) return rc;
   if (!forest || !d_xyz || !d_ws || !loglik) return fail(HGMM_EINVAL, "null pointer argument");
@@ -1200,11 +1203,11 @@ int hgmm_estep_batch(hgmm_tree forest, const float* d_xyz, const int64_t* offset
   for (int b = 0; b < B; ++b)
     if (offsets[b + 1] - offsets[b] < 1) return fail(HGMM_ETOOFEW, "cloud %d is empty", b);
   std::vector<int64_t> offs(offsets, offsets + B + 1);
-  RegRun rr{1, lambda_c, 0.0, 0.0};
+  RegRun rr{1, lambda_c, 0.0, 0.0, 0};
   std::vector<double> nrm(28 * (size_t)B);
   const int64_t n = offsets[B];
   rc = run_register(forest, d_xyz, d_xyz + n, d_xyz + 2 * n, offs, R, t, 1, rr, (char*)d_ws, ws_bytes,
-                    (hipStream_t)stream, 1, nullptr, nullptr, nullptr, nullptr, nrm.data());
+                    (hipStream_t)stream, 1, d_stop, nullptr, nullptr, nullptr, nrm.data());
   if (rc) return rc;
   for (int b = 0; b < B; ++b) loglik[b] = nrm[28 * (size_t)b + 27];
   return HGMM_OK;

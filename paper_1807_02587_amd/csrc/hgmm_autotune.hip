@@ -35,6 +35,7 @@ const std::vector<Knob>& knobs() {
       {&hgmm_tuning::reg_chunk, {2, 4, 8, 16}},
       {&hgmm_tuning::reg_graph, {0, 1}},
       {&hgmm_tuning::reg_sort, {0, 1}},
+      {&hgmm_tuning::reg_lds_levels, {2, 3}},
   };
   return k;
 }

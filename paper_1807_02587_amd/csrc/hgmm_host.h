@@ -50,7 +50,7 @@ void launch_init_pose(PoseState* st, int npairs, const double* R0, const double*
 void launch_descend(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
                     const TreeDev* trees, const NodeF* tab, const NodeD* nodes, const PoseState* st, double* bins,
                     double* partials, size_t pstride, int32_t* stop_out, float* gamma_out, const int* perm,
-                    hipStream_t s);
+                    int lds_levels, int max_levels, hipStream_t s);
 void launch_fold_bins(const int2* pair_tiles, const TreeDev* trees, const double* partials, size_t pstride,
                       double* bins, int npairs, hipStream_t s);
 void launch_normal(double* bins, const double* dpart, size_t pstride, const int2* pair_tiles, const NodeD* nodes,

@@ -125,27 +125,36 @@ __device__ __forceinline__ float gamma_fp64(S64Ptr S, uint32_t lm, int k, const 
 // accumulators, written as value-major block partials and folded in a fixed
 // order by the next kernel (no cross-block handoff inside this kernel).
 // Deeper stop nodes receive few points each and are added with FP64 atomics.
+// NLEV: number of leading tree levels whose FP32 scoring records are staged in
+// LDS (2: the 72 nodes of levels 0-1; 3: also the 512 of level 2, 37 KB).
+// The FP64 scoring prefix and the FP64 bins are staged for levels 0-1.
+template <int NLEV>
 __global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
                                                       const float* __restrict__ zs, const Tile* __restrict__ tiles,
                                                       const TreeDev* __restrict__ trees, const NodeF* __restrict__ tab,
                                                       const NodeD* __restrict__ nodes, const PoseState* __restrict__ st,
                                                       double* bins, double* partials, size_t pstride,
                                                       int32_t* stop_out, float* gamma_out,
-                                                      const int* __restrict__ perm) {
+                                                      const int* __restrict__ perm, int max_levels) {
   const Tile tl = tiles[blockIdx.x];
   const int pair = tl.job;
   if (st[pair].done) return;
   const TreeDev& T = trees[pair];
-  const int L = T.levels;
+  // levels the descent may use (a cap acts like a tree built with fewer levels)
+  const int L = (max_levels > 0 && max_levels < T.levels) ? max_levels : T.levels;
   const int64_t nb = T.node_base;
-  __shared__ NodeF lds[kLdsNodes];
+  constexpr int kStaged = NLEV >= 3 ? 584 : kLdsNodes;
+  __shared__ NodeF lds[kStaged];
   __shared__ NodeS lds64[kLdsNodes];
   __shared__ double lbin[kLdsNodes * 6];
-  const int nl = L >= 2 ? 72 : 8;
-  for (int i = threadIdx.x; i < nl; i += blockDim.x) {
+  const int nl = T.levels >= 2 ? 72 : 8;  // LDS-binned nodes: as the normal-equation fold expects
+  const int nst = L >= NLEV ? kStaged : (L >= 2 ? 72 : 8);
+  for (int i = threadIdx.x; i < nst; i += blockDim.x) {
     const float4* s = reinterpret_cast<const float4*>(&tab[nb + i]);
     float4* d = reinterpret_cast<float4*>(&lds[i]);
     d[0] = s[0]; d[1] = s[1]; d[2] = s[2]; d[3] = s[3];
+  }
+  for (int i = threadIdx.x; i < nl; i += blockDim.x) {
     const NodeD& nd = nodes[nb + i];
     for (int k = 0; k < 3; ++k) lds64[i].mu[k] = nd.mu[k];
     for (int k = 0; k < 6; ++k) lds64[i].winv[k] = nd.winv[k];
@@ -182,7 +191,7 @@ __global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ 
 #pragma unroll
           for (int j = 0; j < 8; ++j) err[j] = score_err(C[j], q[j], m[j]);
         } else {
-          const NodeF* C = tab + nb + lbase;
+          const NodeF* C = (l < NLEV) ? lds + lbase : tab + nb + lbase;
           k = choose_child(C, nodes + nb + lbase, p0, p1, p2, s, q, m, lm);
           flags = k >= 0 ? C[k].flags : 0u;
           if (k >= 0 && ((flags & F_STOP) || !(flags & F_HASCH) || (l == L - 1))) {
@@ -521,9 +530,13 @@ void launch_import_nodes(NodeD* nodes, NodeF* tab, int64_t n, hipStream_t s) {
 void launch_descend(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
                     const TreeDev* trees, const NodeF* tab, const NodeD* nodes, const PoseState* st, double* bins,
                     double* partials, size_t pstride, int32_t* stop_out, float* gamma_out, const int* perm,
-                    hipStream_t s) {
-  hipLaunchKernelGGL(descend_kernel, dim3(ntiles), dim3(256), 0, s, xs, ys, zs, tiles, trees, tab, nodes, st, bins,
-                     partials, pstride, stop_out, gamma_out, perm);
+                    int lds_levels, int max_levels, hipStream_t s) {
+  if (lds_levels >= 3)
+    hipLaunchKernelGGL(descend_kernel<3>, dim3(ntiles), dim3(256), 0, s, xs, ys, zs, tiles, trees, tab, nodes, st, bins,
+                       partials, pstride, stop_out, gamma_out, perm, max_levels);
+  else
+    hipLaunchKernelGGL(descend_kernel<2>, dim3(ntiles), dim3(256), 0, s, xs, ys, zs, tiles, trees, tab, nodes, st, bins,
+                       partials, pstride, stop_out, gamma_out, perm, max_levels);
 }
 
 void launch_fold_bins(const int2* pair_tiles, const TreeDev* trees, const double* partials, size_t pstride,

@@ -7,7 +7,8 @@ kernels; this module only sequences calls and moves handles around):
 2. level-1 features of both trees in canonical frames (hgmm_warm_features);
 3. network forward (hgmm_mlp_forward) -> 6D rotation + translation;
 4. head -> initial transforms (hgmm_warm_head_pose);
-5. batched registration from those transforms;
+5. batched registration from those transforms, coarse to fine: first with
+   the descent capped at cfg.coarse_levels levels, then with the whole tree;
 6. fallback: the plain method from the identity is the judge.  Rule "plain"
    (default): every pair is also registered from the identity (one more
    batched call) and keeps whichever result has the higher final
@@ -40,6 +41,9 @@ class WarmConfig:
     lambda_c: float = 0.01
     max_iters: int = 30
     trans_weight: float = 1.0
+    # coarse-to-fine: from the network's pose, first register with the descent
+    # capped at this many levels (wider basin), then with the whole tree; 0 off
+    coarse_levels: int = 2
 
 
 def _eye_batch(B):
@@ -137,8 +141,15 @@ def register_warm(mlp, src, tgt, src_off, tgt_off, src_levels, cfg: WarmConfig =
     R0, t0 = hg.hgmm_warm_head_pose(Y, frs, frt)
     R0 = R0.cpu().numpy().reshape(B, 3, 3)
     t0 = t0.cpu().numpy()
-    r = hg.hgmm_register_batch(src_forest, tgt, tgt_off, max_iters=cfg.max_iters, lambda_c=cfg.lambda_c, R0=R0,
-                               t0=t0, ws=ws)
+    Rs, ts = R0, t0
+    if cfg.coarse_levels and max(int(v) for v in np.atleast_1d(src_levels)) > cfg.coarse_levels:
+        rc = hg.hgmm_register_batch(src_forest, tgt, tgt_off, max_iters=cfg.max_iters, lambda_c=cfg.lambda_c,
+                                    R0=R0, t0=t0, ws=ws, max_levels=cfg.coarse_levels)
+        ok = (rc["status"] == 0).reshape(B, 1)
+        Rs = np.where(ok.reshape(B, 1, 1), rc["R"], R0)
+        ts = np.where(ok, rc["t"], t0)
+    r = hg.hgmm_register_batch(src_forest, tgt, tgt_off, max_iters=cfg.max_iters, lambda_c=cfg.lambda_c, R0=Rs,
+                               t0=ts, ws=ws)
     Ri, ti = _eye_batch(B)
     if fallback == "plain":
         r2 = hg.hgmm_register_batch(src_forest, tgt, tgt_off, max_iters=cfg.max_iters, lambda_c=cfg.lambda_c,

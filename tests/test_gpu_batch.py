@@ -122,12 +122,19 @@ def test_register_batch_active_mask_and_estep(hg, batch):
             np.testing.assert_array_equal(part["R"][b], R0[b])
             np.testing.assert_array_equal(part["t"][b], t0[b])
             assert part["iters"][b] == 0
-    # one E-step per pair at the starting poses: mean log-likelihood against the oracle's
-    ll = hg.hgmm_estep_batch(forest, tg, toff, R0, t0)
+    # one E-step per pair at the starting poses: mean log-likelihood and every
+    # point's stop node against the oracle's (exact outside flagged near ties)
+    ll, stop = hg.hgmm_estep_batch(forest, tg, toff, R0, t0, stop_nodes=True)
+    stop = stop.cpu().numpy()
     for b, p in enumerate(pairs):
         o = oracle.estep(to_oracle(oracle, forest.export(b)), p.tgt, R0[b], t0[b])
-        log(f"[batch estep] pair {b}: loglik gpu {ll[b]:.9f} oracle {o['loglik']:.9f}")
+        g = stop[toff[b]:toff[b + 1]]
+        flagged = o["min_gap"] < 1e-6
+        mism = (g != o["stop_node"]) & ~flagged
+        log(f"[batch estep] pair {b}: loglik gpu {ll[b]:.9f} oracle {o['loglik']:.9f}; stop-node mismatches "
+            f"{mism.sum()} (flagged {flagged.sum()})")
         assert abs(ll[b] - o["loglik"]) <= 1e-5 * max(1.0, abs(o["loglik"]))
+        assert mism.sum() == 0
 
 
 def test_batch_argument_checks(hg, batch):
@@ -256,3 +263,28 @@ def test_morton_sorted_estep_points_match(hg):
     assert np.all(np.abs(bb[act, 0] - ba[act, 0]) <= 1e-6 * ba[act, 0])
     assert np.all(np.abs(bb[act, 1:4] - ba[act, 1:4]) <= 1e-6 * ba[act, :1] * ext)
     assert np.all(np.abs(bb[act, 5] - ba[act, 5]) <= 1e-6 * ba[act, 5])
+
+
+def test_level2_lds_staging_matches(hg):
+    """reg_lds_levels = 3 (level-2 scoring records staged in LDS) computes the
+    same descent: identical stop nodes and weights, bins equal to the rounding
+    of FP64 atomic order."""
+    from synth import small_pair
+    p = small_pair(102, n=7_777, n_tgt=5_013, max_angle_deg=8)
+    tree = hg.hgmm_build(_cuda(p.src), levels=4)
+    tg = _cuda(p.tgt)
+    old = hg.hgmm_get_tuning()
+    try:
+        hg.hgmm_set_tuning(reg_lds_levels=2)
+        a = hg.hgmm_estep(tree, tg, p.R_true, p.t_true, lambda_c=0.0)
+        ra = hg.hgmm_register(tree, tg, R0=p.R_true, t0=p.t_true, max_iters=5)
+        hg.hgmm_set_tuning(reg_lds_levels=3)
+        b = hg.hgmm_estep(tree, tg, p.R_true, p.t_true, lambda_c=0.0)
+        rb = hg.hgmm_register(tree, tg, R0=p.R_true, t0=p.t_true, max_iters=5)
+    finally:
+        hg.hgmm_set_tuning(**old)
+    np.testing.assert_array_equal(b["stop_node"].cpu().numpy(), a["stop_node"].cpu().numpy())
+    np.testing.assert_array_equal(b["gamma"].cpu().numpy(), a["gamma"].cpu().numpy())
+    ba, bb = a["bins"].cpu().numpy(), b["bins"].cpu().numpy()
+    np.testing.assert_allclose(bb, ba, rtol=1e-12, atol=1e-12 * np.abs(ba).max())
+    np.testing.assert_allclose(rb["R"], ra["R"], atol=1e-9)

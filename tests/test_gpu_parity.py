@@ -193,6 +193,29 @@ def test_register_parity(hg, name, lam):
     assert abs(r["iters"] - o["iters"]) <= 2
 
 
+def test_register_level_cap_matches_truncated_tree(hg):
+    """max_levels = 2 on a 3-level tree registers exactly like the oracle on the
+    same tree cut after its first two levels (the cap makes level 1 the last)."""
+    p, L, eps, mm = _case("small_ragged")
+    tree, host, _ = _build(hg, p, L, eps, mm)
+    n2 = oracle.level_offset(2)
+    cut = {k: (v[:n2] if isinstance(v, np.ndarray) and v.shape[:1] == host["live"].shape else v)
+           for k, v in host.items()}
+    cut["levels"] = 2
+    cut["has_children"] = np.where(np.arange(n2) >= 8, 0, cut["has_children"])
+    ot = to_oracle(oracle, cut)
+    R0 = rotation_from_axis_angle([0.2, 0.9, -0.3], math.radians(1.0)) @ p.R_true
+    t0 = p.t_true + 0.001 * p.extent * np.array([0.5, -0.2, 0.3])
+    r = hg.hgmm_register(tree, _cuda(p.tgt), R0=R0, t0=t0, max_levels=2)
+    o = oracle.register(ot, p.tgt, R0=R0, t0=t0)
+    dang = math.radians(rotation_angle_deg(r["R"], o["R"]))
+    dt = np.linalg.norm(r["t"] - o["t"]) / host["extent"]
+    log(f"[level cap] iters gpu {r['iters']} oracle {o['iters']}  pose diff {dang:.2e} rad {dt:.2e} ext")
+    assert dang < POSE_TOL and dt < POSE_TOL
+    assert abs(r["iters"] - o["iters"]) <= 2
+    assert abs(r["loglik"] - o["loglik"]) <= 1e-5 * max(1.0, abs(o["loglik"]))
+
+
 def test_register_exact_recovery_blobs(hg):
     xyz, ids, _ = blob_tree_cloud(0)
     tree, host, labels = _build(hg, type("P", (), {"src": xyz})(), 2)
