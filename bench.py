@@ -46,10 +46,11 @@ DESC_FLOP_PER_LEVEL = 8 * 19
 DESC_BYTES_PER_POINT = 12
 
 
-def roofline_of(prof, depth, traffic=False):
+def roofline_of(prof, depth, traffic=None):
     """ALU roofline of the kernel family with the largest summed event time.
     prof: hgmm_profile_read per kind; depth: mean levels visited per point by
-    the descent (for its FLOP count)."""
+    the descent (for its FLOP count); traffic: which committed counter summary
+    ("lidar" or "batch") gives the HBM bytes per launch, or None."""
     cand = {"em_tile": ("em_tile_kernel (construction EM iteration of large parents)", EM_FLOP_PER_POINT_ITER,
                         EM_BYTES_PER_POINT_ITER),
             "em_block": ("em_block_kernel (all construction EM iterations, one block per parent)",
@@ -62,7 +63,7 @@ def roofline_of(prof, depth, traffic=False):
     flop, byts = units * flop_unit, units * bytes_unit
     achieved = flop / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": _traffic(dom) if traffic else None,
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": _traffic(dom, traffic) if traffic else None,
             "kernel": kname, "launches": launches, "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
             "flop_per_launch": round(flop / max(launches, 1)),
             "frac_of_packed_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4),
@@ -75,15 +76,16 @@ def mean_depth(stop, level_offsets):
     return float(np.mean(np.searchsorted(level_offsets, st, side="right"))) if st.size else 0.0
 
 
-TRAFFIC = os.path.join(ROOT, "profiles", "lidar_hbm_traffic.json")
+TRAFFIC = {"lidar": os.path.join(ROOT, "profiles", "lidar_hbm_traffic.json"),
+           "batch": os.path.join(ROOT, "profiles", "batch_hbm_traffic.json")}
 
 
-def _traffic(family):
+def _traffic(family, which):
     """HBM bytes per launch of a kernel family from the committed FETCH_SIZE /
     WRITE_SIZE summary, or None when there is none or the kernels changed since."""
     from paper_1807_02587_amd import profiling
     try:
-        with open(TRAFFIC) as f:
+        with open(TRAFFIC[which]) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -125,6 +127,21 @@ def batch_section(args, hg):
     B = len(lv)
     ws = hg.Workspace()
     cfg = W.WarmConfig()
+    if args.copy_calibration:
+        # counter calibration: a plain copy of known size, then the batched
+        # plain form twice with the given launch shapes
+        a = torch.empty(args.copy_mib << 18, dtype=torch.float32, device=src.device).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        if args.batch_tuning_json:
+            with open(args.batch_tuning_json) as f:
+                hg.hgmm_set_tuning(**json.load(f))
+        for _ in range(2):
+            forest = hg.hgmm_build_batch(src, off, lv, ws=ws)
+            hg.hgmm_register_batch(forest, tgt, off, ws=ws)
+        torch.cuda.synchronize()
+        return {"copy_bytes": a.numel() * 4, "steps": 2}
 
     def plain_sequential(k_list):
         Rs = []
@@ -208,7 +225,7 @@ def batch_section(args, hg):
     out["profiled"] = {"kernels_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
                        "mean_levels_visited": round(depth, 3),
                        "estep_mpts_s": round(ds["units"] / (ds["ms"] * 1e-3) / 1e6, 1) if ds["ms"] > 0 else None,
-                       "roofline": roofline_of(prof, depth)}
+                       "roofline": roofline_of(prof, depth, traffic="batch")}
     if net is not None:
         batched_warm()
         rw, tw = timed(batched_warm)
@@ -303,7 +320,8 @@ def main():
     ap.add_argument("--tuning-json", default=None, help="launch shapes from this file instead of the autotuner")
     ap.add_argument("--save-tuning", default=None, help="write the launch shapes used to this file")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a 256 MiB device copy and a few steps (for counter calibration)")
+                    help="only run a device copy of --copy-mib MiB and a few steps (for counter calibration)")
+    ap.add_argument("--copy-mib", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
@@ -340,7 +358,7 @@ def main():
         if args.tuning_json:
             with open(args.tuning_json) as f:
                 hg.hgmm_set_tuning(**json.load(f))
-        a = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        a = torch.empty(args.copy_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
@@ -395,7 +413,7 @@ def main():
     stop = e["stop_node"].cpu().numpy()
     depth = mean_depth(stop, off)
 
-    roofline = roofline_of(prof, depth, traffic=True)
+    roofline = roofline_of(prof, depth, traffic="lidar")
     ds = prof["descend"]
     estep_mpts = ds["units"] / (ds["ms"] * 1e-3) / 1e6 if ds["ms"] > 0 else 0.0
 

@@ -16,6 +16,7 @@
 #include "hgmm_host.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace hgmm {
 
@@ -202,59 +203,107 @@ __global__ void init_children_kernel(const Job* __restrict__ jobs, int njobs, co
 // offset from child k is d = q - m_k with m_k = float(mu_k - ref).  This keeps
 // FP64 arithmetic out of the per-child work; the extra rounding is a few units
 // of the last place of |q| + |m_k|, far below the scale of the covariances.
-struct EmFrame {
+struct __align__(16) EmFrame {
+  float p[8][10];  // per child: mean - reference point [3], scoring rows [6], constant
   double ref[3];
-  float m[8][3];
 };
 
-// Reference point and FP32 child offsets of a job (all 64 lanes of a wave
-// call it; lanes 0..7 write m).  `live` must be non-zero.
+// Reference point and FP32 child parameters of a job in its local frame (all
+// 64 lanes of a wave call it; lanes 0..7 write their child).  A dead child
+// gets offset 0, rows 0 and constant -inf: its score is -inf, so its
+// responsibility and moment contributions are exactly 0.  `live` must be
+// non-zero.
 __device__ __forceinline__ void em_frame(const NodeF* ch, uint32_t live, EmFrame& f, int tid) {
   const int r = __ffs(live) - 1;
   if (tid < 3) f.ref[tid] = ch[r].mu[tid];
-  if (tid < 8)
-    for (int i = 0; i < 3; ++i) f.m[tid][i] = (float)(ch[tid].mu[i] - ch[r].mu[i]);
+  if (tid < 8) {
+    const bool on = (live >> tid) & 1u;
+    float* q = f.p[tid];
+    for (int i = 0; i < 3; ++i) q[i] = on ? (float)(ch[tid].mu[i] - ch[r].mu[i]) : 0.f;
+    for (int i = 0; i < 6; ++i) q[3 + i] = on ? ch[tid].w[i] : 0.f;
+    q[9] = on ? ch[tid].c : -INFINITY;
+  }
 }
 
-__device__ __forceinline__ void em_point(const NodeF* ch, const EmFrame& f, uint32_t live, float q0, float q1,
-                                         float q2, float (&a)[8][10]) {
+// Two ways to hand the children's parameters (the same for every lane) to
+// the per-point E-step.  ChildParams reads the frame once (20 aligned 16-byte
+// LDS reads) into scalar registers, where they stay for all points of the
+// iteration: best when a block runs many points per iteration.  FrameParams
+// re-reads them from LDS (broadcast reads) for every point: no set-up cost,
+// best for a one-iteration tile launch with few points per thread.
+struct ChildParams {
+  float pm[8][3], pw[8][6], pc[8];
+  __device__ float m(int k, int i) const { return pm[k][i]; }
+  __device__ float w(int k, int i) const { return pw[k][i]; }
+  __device__ float c(int k) const { return pc[k]; }
+};
+
+struct FrameParams {
+  const EmFrame& f;
+  __device__ float m(int k, int i) const { return f.p[k][i]; }
+  __device__ float w(int k, int i) const { return f.p[k][3 + i]; }
+  __device__ float c(int k) const { return f.p[k][9]; }
+};
+
+__device__ __forceinline__ float uniform_f(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+__device__ __forceinline__ void child_params(const EmFrame& f, ChildParams& u) {
+  const float4* src = reinterpret_cast<const float4*>(&f.p[0][0]);
+  float t[80];
+#pragma unroll
+  for (int j = 0; j < 20; ++j) {
+    const float4 v = src[j];
+    t[4 * j] = v.x; t[4 * j + 1] = v.y; t[4 * j + 2] = v.z; t[4 * j + 3] = v.w;
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) u.pm[k][i] = uniform_f(t[10 * k + i]);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) u.pw[k][i] = uniform_f(t[10 * k + 3 + i]);
+    u.pc[k] = uniform_f(t[10 * k + 9]);
+  }
+}
+
+// Responsibilities of the 8 children for one point (local frame) and its
+// moment contributions (about each child's mean).  Branch-free: dead
+// children carry the score -inf (see em_frame), so the scheduler can
+// interleave the 8 independent score chains.
+template <typename P>
+__device__ __forceinline__ void em_point(const P& u, float q0, float q1, float q2, float (&a)[8][10]) {
   float s[8];
   float smax = -INFINITY;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    if (live & (1u << k)) {
-      const float d0 = q0 - f.m[k][0], d1 = q1 - f.m[k][1], d2 = q2 - f.m[k][2];
-      const float w0 = ch[k].w[0] * d0;
-      const float w1 = fmaf(ch[k].w[1], d0, ch[k].w[2] * d1);
-      const float w2 = fmaf(ch[k].w[3], d0, fmaf(ch[k].w[4], d1, ch[k].w[5] * d2));
-      s[k] = ch[k].c - fmaf(w0, w0, fmaf(w1, w1, w2 * w2));
-      smax = fmaxf(smax, s[k]);
-    } else {
-      s[k] = -INFINITY;
-    }
+    const float d0 = q0 - u.m(k, 0), d1 = q1 - u.m(k, 1), d2 = q2 - u.m(k, 2);
+    const float w0 = u.w(k, 0) * d0;
+    const float w1 = fmaf(u.w(k, 1), d0, u.w(k, 2) * d1);
+    const float w2 = fmaf(u.w(k, 3), d0, fmaf(u.w(k, 4), d1, u.w(k, 5) * d2));
+    s[k] = u.c(k) - fmaf(w0, w0, fmaf(w1, w1, w2 * w2));
+    smax = fmaxf(smax, s[k]);
   }
   float e[8], sum = 0.f;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    e[k] = (live & (1u << k)) ? __builtin_amdgcn_exp2f(s[k] - smax) : 0.f;
+    e[k] = __builtin_amdgcn_exp2f(s[k] - smax);
     sum += e[k];
   }
   const float inv = 1.0f / sum;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    if (live & (1u << k)) {
-      const float r = e[k] * inv;
-      const float d0 = q0 - f.m[k][0], d1 = q1 - f.m[k][1], d2 = q2 - f.m[k][2];
-      const float r0 = r * d0, r1 = r * d1, r2 = r * d2;
-      a[k][0] += r;
-      a[k][1] += r0; a[k][2] += r1; a[k][3] += r2;
-      a[k][4] = fmaf(r0, d0, a[k][4]);
-      a[k][5] = fmaf(r0, d1, a[k][5]);
-      a[k][6] = fmaf(r0, d2, a[k][6]);
-      a[k][7] = fmaf(r1, d1, a[k][7]);
-      a[k][8] = fmaf(r1, d2, a[k][8]);
-      a[k][9] = fmaf(r2, d2, a[k][9]);
-    }
+    const float r = e[k] * inv;
+    const float d0 = q0 - u.m(k, 0), d1 = q1 - u.m(k, 1), d2 = q2 - u.m(k, 2);
+    const float r0 = r * d0, r1 = r * d1, r2 = r * d2;
+    a[k][0] += r;
+    a[k][1] += r0; a[k][2] += r1; a[k][3] += r2;
+    a[k][4] = fmaf(r0, d0, a[k][4]);
+    a[k][5] = fmaf(r0, d1, a[k][5]);
+    a[k][6] = fmaf(r0, d2, a[k][6]);
+    a[k][7] = fmaf(r1, d1, a[k][7]);
+    a[k][8] = fmaf(r1, d2, a[k][8]);
+    a[k][9] = fmaf(r2, d2, a[k][9]);
   }
 }
 
@@ -283,24 +332,19 @@ __device__ __forceinline__ void load_points(const float* __restrict__ xs, const 
 // Moments of this thread's points of [start, end): the first KP come from the
 // cache, any further ones are streamed with the next point's loads issued
 // before the current point's arithmetic.
-template <int STRIDE, int KP>
-__device__ __forceinline__ void em_range(const float* __restrict__ xs, const float* __restrict__ ys,
-                                         const float* __restrict__ zs, int start, int end, int first,
-                                         const PointCache<KP>& c, const NodeF* ch, const EmFrame& f,
-                                         uint32_t live, float (&a)[8][10]) {
-#pragma unroll
-  for (int k = 0; k < 8; ++k)
-#pragma unroll
-    for (int v = 0; v < 10; ++v) a[k][v] = 0.f;
-  const double r0 = f.ref[0], r1 = f.ref[1], r2 = f.ref[2];
+template <int STRIDE, int KP, bool LDS_PARAMS, typename P>
+__device__ __forceinline__ void em_points(const float* __restrict__ xs, const float* __restrict__ ys,
+                                          const float* __restrict__ zs, int start, int end, int first,
+                                          const PointCache<KP>& c, const P& u, const double (&ref)[3],
+                                          float (&a)[8][10]) {
+  const double r0 = ref[0], r1 = ref[1], r2 = ref[2];
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
     if (start + first + k * STRIDE >= end) break;
-    // the children's parameters are re-read from LDS (broadcast reads) for
-    // every point instead of being held in ~100 registers across the loop
-    asm volatile("" ::: "memory");
-    em_point(ch, f, live, (float)((double)c.x[k] - r0), (float)((double)c.y[k] - r1), (float)((double)c.z[k] - r2),
-             a);
+    // with LDS parameters, re-read them for every point rather than holding
+    // ~80 of them in vector registers across the loop
+    if constexpr (LDS_PARAMS) asm volatile("" ::: "memory");
+    em_point(u, (float)((double)c.x[k] - r0), (float)((double)c.y[k] - r1), (float)((double)c.z[k] - r2), a);
   }
   int i = start + first + KP * STRIDE;
   if (i >= end) return;
@@ -308,8 +352,29 @@ __device__ __forceinline__ void em_range(const float* __restrict__ xs, const flo
   for (; i < end; i += STRIDE) {
     const float px = nx, py = ny, pz = nz;
     if (i + STRIDE < end) { nx = xs[i + STRIDE]; ny = ys[i + STRIDE]; nz = zs[i + STRIDE]; }
-    asm volatile("" ::: "memory");
-    em_point(ch, f, live, (float)((double)px - r0), (float)((double)py - r1), (float)((double)pz - r2), a);
+    if constexpr (LDS_PARAMS) asm volatile("" ::: "memory");
+    em_point(u, (float)((double)px - r0), (float)((double)py - r1), (float)((double)pz - r2), a);
+  }
+}
+
+// E-step and moment sums of the points first, first + STRIDE, ... of
+// [start, end): the first KP from the register cache, the rest streamed.
+// HOIST selects scalar-register (ChildParams) or LDS (FrameParams) parameters.
+template <int STRIDE, int KP, bool HOIST>
+__device__ __forceinline__ void em_range(const float* __restrict__ xs, const float* __restrict__ ys,
+                                         const float* __restrict__ zs, int start, int end, int first,
+                                         const PointCache<KP>& c, const EmFrame& f, float (&a)[8][10]) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int v = 0; v < 10; ++v) a[k][v] = 0.f;
+  if constexpr (HOIST) {
+    ChildParams u;
+    child_params(f, u);
+    em_points<STRIDE, KP, false>(xs, ys, zs, start, end, first, c, u, f.ref, a);
+  } else {
+    const FrameParams u{f};
+    em_points<STRIDE, KP, true>(xs, ys, zs, start, end, first, c, u, f.ref, a);
   }
 }
 
@@ -450,7 +515,7 @@ __global__ __launch_bounds__(NT) void em_tile_kernel(
   if (live) em_frame(ch, live, fr, tid);
   __syncthreads();
   if (live) {
-    em_range<NT>(xs, ys, zs, tl.start, tl.end, tid, pc, ch, fr, live, a);
+    em_range<NT, KP, false>(xs, ys, zs, tl.start, tl.end, tid, pc, fr, a);
   } else {
     for (int k = 0; k < 8; ++k)
       for (int v = 0; v < 10; ++v) a[k][v] = 0.f;
@@ -515,7 +580,7 @@ __global__ __launch_bounds__(NT) void em_block_kernel(const float* __restrict__ 
     em_frame(ch, live, fr, tid);
     __syncthreads();
     float a[8][10];
-    em_range<NT>(xs, ys, zs, jb.start, jb.start + jb.count, tid, pc, ch, fr, live, a);
+    em_range<NT, 8, true>(xs, ys, zs, jb.start, jb.start + jb.count, tid, pc, fr, a);
     rows_store80(a, rows, tid);
     __syncthreads();
     for (int v = tid; v < 80; v += NT) {

@@ -58,16 +58,19 @@ __global__ void init_pose_kernel(PoseState* st, int npairs, const double* __rest
 template <typename NodePtr, typename S64Ptr>
 __device__ __forceinline__ int choose_child(NodePtr C, S64Ptr S, double p0, double p1, double p2, float (&s)[8],
                                             float (&q)[8], float (&m)[8], uint32_t& livemask) {
+  // branch-free over the children (every lane scores all 8; a dead child's
+  // record is read but its values are replaced), so the 8 independent
+  // chains interleave
   livemask = 0u;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const uint32_t f = C[k].flags;
-    if (f & F_LIVE) {
-      livemask |= 1u << k;
-      s[k] = score32(C[k], p0, p1, p2, q[k], m[k]);
-    } else {
-      s[k] = -INFINITY; q[k] = 0.f; m[k] = 0.f;
-    }
+    const bool on = (C[k].flags & F_LIVE) != 0u;
+    livemask |= on ? (1u << k) : 0u;
+    float qk, mk;
+    const float sk = score32(C[k], p0, p1, p2, qk, mk);
+    s[k] = on ? sk : -INFINITY;
+    q[k] = on ? qk : 0.f;
+    m[k] = on ? mk : 0.f;
   }
   int k1 = -1;
   float s1 = -INFINITY;
