@@ -413,37 +413,43 @@ __device__ __forceinline__ void rows_store80(float (&a)[8][10], float (*rows)[80
 
 // FP64 M-step of the 8 children of one parent from the 80 combined sums
 // (moments about the means the E-step used).  Runs on one full wave; lanes 0..7
-// own one child each.  Updates the LDS copy of the children, the FP32 table
-// and the FP64 node records.
-template <bool GLOBAL = true>
+// own one child each.  Updates the LDS copy of the children; GLOBAL: also the
+// FP32 table and the FP64 node records (the final iteration), else only the
+// FP32 scoring records are formed (make_nodef_fast).  FRAME: the same lanes
+// also write the next E-step's frame (what em_frame would compute from the
+// updated children).
+template <bool GLOBAL = true, bool FRAME = false>
 __device__ __forceinline__ void mstep_children(const double* tot, NodeF* ch, NodeF* tab, NodeD* nodes,
-                                               int child_base, double eps, double min_mass, int lane) {
-  bool live = false;
-  double N = 0.0;
-  if (lane < 8) {
-    live = (ch[lane].flags & F_LIVE) != 0;
-    N = tot[lane * 10];
-    if (live && !(N >= min_mass)) live = false;
+                                               int child_base, double eps, double min_mass, int lane,
+                                               EmFrame* fr = nullptr) {
+  // surviving mass of the parent, summed pairwise in the same order on every lane
+  double v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const double n = tot[k * 10];
+    v[k] = ((ch[k].flags & F_LIVE) && n >= min_mass) ? n : 0.0;
   }
-  double total = live ? N : 0.0;
-  total += __shfl_xor(total, 1, 64);
-  total += __shfl_xor(total, 2, 64);
-  total += __shfl_xor(total, 4, 64);
+  const double total = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+  bool live = false;
+  double mu[3] = {0.0, 0.0, 0.0};
+  NodeF nf;
   if (lane < 8) {
     const int g = child_base + lane;
+    const double N = tot[lane * 10];
+    live = (ch[lane].flags & F_LIVE) != 0 && N >= min_mass;
     NodeD nd;
-    NodeF nf;
     if (live) {
       const double* A = tot + lane * 10;
       const double inv = 1.0 / N;
       const double dl0 = A[1] * inv, dl1 = A[2] * inv, dl2 = A[3] * inv;
-      double mu[3] = {ch[lane].mu[0] + dl0, ch[lane].mu[1] + dl1, ch[lane].mu[2] + dl2};
+      mu[0] = ch[lane].mu[0] + dl0; mu[1] = ch[lane].mu[1] + dl1; mu[2] = ch[lane].mu[2] + dl2;
       double cov[6] = {A[4] * inv - dl0 * dl0 + eps, A[5] * inv - dl0 * dl1, A[6] * inv - dl0 * dl2,
                        A[7] * inv - dl1 * dl1 + eps, A[8] * inv - dl1 * dl2, A[9] * inv - dl2 * dl2 + eps};
-      live = make_node(mu, cov, N / total, nd, nf);
+      if constexpr (GLOBAL) live = make_node(mu, cov, N / total, nd, nf);
+      else live = make_nodef_fast(mu, cov, N / total, nf);
     }
     if (live) {
-      if (GLOBAL) {
+      if constexpr (GLOBAL) {
         NodeD& out = nodes[g];
         for (int i = 0; i < 3; ++i) out.mu[i] = nd.mu[i];
         for (int i = 0; i < 6; ++i) { out.cov[i] = nd.cov[i]; out.winv[i] = nd.winv[i]; }
@@ -452,11 +458,27 @@ __device__ __forceinline__ void mstep_children(const double* tot, NodeF* ch, Nod
       }
       copy_nodef(ch[lane], nf);
     } else {
-      if (GLOBAL) {
+      if constexpr (GLOBAL) {
         nodes[g].live = 0; nodes[g].pi = 0.0;
         tab[g].flags = 0u;
       }
       ch[lane].flags = 0u;
+    }
+  }
+  if constexpr (FRAME) {
+    const uint64_t lm = __ballot(live);
+    if (lm != 0ull) {
+      const int r = __ffsll((long long)lm) - 1;
+      const double f0 = __shfl(mu[0], r, 64), f1 = __shfl(mu[1], r, 64), f2 = __shfl(mu[2], r, 64);
+      if (lane < 8) {
+        float* q = fr->p[lane];
+        q[0] = live ? (float)(mu[0] - f0) : 0.f;
+        q[1] = live ? (float)(mu[1] - f1) : 0.f;
+        q[2] = live ? (float)(mu[2] - f2) : 0.f;
+        for (int i = 0; i < 6; ++i) q[3 + i] = live ? nf.w[i] : 0.f;
+        q[9] = live ? nf.c : -INFINITY;
+      }
+      if (lane == 0) { fr->ref[0] = f0; fr->ref[1] = f1; fr->ref[2] = f2; }
     }
   }
 }
@@ -506,14 +528,16 @@ __global__ __launch_bounds__(NT) void em_tile_kernel(
         for (int j = 0; j < 5; ++j) tot[v0 + j] = t[j];
     }
     __syncthreads();
-    if (tid < 64) mstep_children<false>(tot, ch, nullptr, nullptr, 0, eps, min_mass, lane);
+    if (tid < 64) mstep_children<false, true>(tot, ch, nullptr, nullptr, 0, eps, min_mass, lane, &fr);
   }
   __syncthreads();
   if (tix == jb.tile_first && tid < 8) copy_nodef(ch_next[(size_t)slot * 8 + tid], ch[tid]);
   const uint32_t live = live_mask(ch);
   float a[8][10];
-  if (live) em_frame(ch, live, fr, tid);
-  __syncthreads();
+  if (first) {  // uniform: the frame of the initial children
+    if (live) em_frame(ch, live, fr, tid);
+    __syncthreads();
+  }
   if (live) {
     em_range<NT, KP, false>(xs, ys, zs, tl.start, tl.end, tid, pc, fr, a);
   } else {
@@ -553,13 +577,16 @@ __global__ __launch_bounds__(kMstepThreads) void em_mstep_kernel(const int* __re
   if (tid < 64) mstep_children(tot, ch, tab, nodes, jb.child_base, eps, min_mass, lane);
 }
 
+// (Two waves per SIMD: with the children's parameters in scalar registers
+// the compiler would otherwise trade occupancy 2 for 1 to keep more in flight,
+// which is slower when many small parents share a compute unit.)
 // All EM iterations of one job inside one block of NT threads: each thread
 // accumulates the moments of every NT-th point of the job (the job's points
 // stay in L1/L2 across iterations), the block reduces them (row butterflies,
 // then the rows in FP64 in a fixed order) and wave 0 runs the FP64 M-step.
 // One launch covers every iteration.
 template <int NT>
-__global__ __launch_bounds__(NT) void em_block_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void em_block_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
                                                       const float* __restrict__ zs, const int* __restrict__ job_ids,
                                                       const Job* __restrict__ jobs, NodeF* tab, NodeD* nodes,
                                                       int iters, double eps, double min_mass) {
@@ -574,11 +601,13 @@ __global__ __launch_bounds__(NT) void em_block_kernel(const float* __restrict__ 
   PointCache<8> pc;
   load_points<NT>(xs, ys, zs, jb.start, jb.start + jb.count, tid, pc);
   __syncthreads();
+  {
+    const uint32_t live0 = live_mask(ch);
+    if (live0) em_frame(ch, live0, fr, tid);
+  }
+  __syncthreads();
   for (int it = 0; it < iters; ++it) {
-    const uint32_t live = live_mask(ch);
-    if (live == 0u) break;
-    em_frame(ch, live, fr, tid);
-    __syncthreads();
+    if (live_mask(ch) == 0u) break;
     float a[8][10];
     em_range<NT, 8, true>(xs, ys, zs, jb.start, jb.start + jb.count, tid, pc, fr, a);
     rows_store80(a, rows, tid);
@@ -589,8 +618,19 @@ __global__ __launch_bounds__(NT) void em_block_kernel(const float* __restrict__ 
       tot[v] = t;
     }
     __syncthreads();
-    if (tid < 64) mstep_children(tot, ch, tab, nodes, jb.child_base, eps, min_mass, tid);
+    if (tid < 64) {
+      // intermediate iterations update the LDS children and the next frame;
+      // the last one writes the node records
+      if (it + 1 < iters) mstep_children<false, true>(tot, ch, nullptr, nullptr, 0, eps, min_mass, tid, &fr);
+      else mstep_children<true, false>(tot, ch, tab, nodes, jb.child_base, eps, min_mass, tid);
+    }
     __syncthreads();
+  }
+  // every child died in an intermediate iteration: record that
+  if (live_mask(ch) == 0u && tid < 8) {
+    const int g = jb.child_base + tid;
+    nodes[g].live = 0; nodes[g].pi = 0.0;
+    tab[g].flags = 0u;
   }
 }
 

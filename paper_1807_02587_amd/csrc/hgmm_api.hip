@@ -242,7 +242,7 @@ static RegLayout reg_layout(int64_t n_total, int64_t nodes, int npairs) {
   L.bins = o; o = align_up(o + sizeof(double) * 6 * (size_t)std::max<int64_t>(nodes, 1));
   L.partials = o; o = align_up(o + sizeof(double) * 28 * (size_t)npairs);
   L.counters = o; o = align_up(o + sizeof(unsigned) * (size_t)npairs);
-  L.dpart = o; o = align_up(o + sizeof(double) * 72 * 6 * (size_t)L.max_tiles);
+  L.dpart = o; o = align_up(o + sizeof(double) * (72 * 6 + 2) * (size_t)L.max_tiles);  // values + node masks
   L.dcount = o; o = align_up(o + sizeof(unsigned) * (size_t)npairs);
   L.ptiles = o; o = align_up(o + sizeof(int2) * (size_t)npairs);
   L.active = o; o = align_up(o + sizeof(int) * (size_t)npairs);

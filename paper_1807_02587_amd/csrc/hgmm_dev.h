@@ -184,6 +184,35 @@ __device__ __forceinline__ void wave_fold(const double* __restrict__ p, size_t s
   for (int v = 0; v < NV; ++v) out[v] = wave_sum_dd(s[v]);
 }
 
+// wave_fold of the partials of one node that carry a set bit in a per-partial
+// mask word (bit `bit` of mask[i]).  A partial without it is an exact zero
+// that was not written: it is not read and 0.0 is added in its place, so the
+// sum, its order and its rounding are those of the dense fold.
+template <int NV, int U>
+__device__ __forceinline__ void wave_fold_masked(const double* __restrict__ p, size_t stride,
+                                                 const uint64_t* __restrict__ mask, int bit, int count, int lane,
+                                                 double (&out)[NV]) {
+  double s[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) s[v] = 0.0;
+  for (int base = 0; base < count; base += 64 * U) {
+    double x[NV][U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int i = base + lane + 64 * k;
+      const bool on = i < count && ((mask[i] >> bit) & 1ull);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) x[v][k] = on ? p[(size_t)v * stride + i] : 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int k = 0; k < U; ++k) s[v] += x[v][k];
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) out[v] = wave_sum_dd(s[v]);
+}
+
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 // ---------------------------------------------------------------------------
@@ -285,6 +314,49 @@ __device__ inline bool make_node(const double mu[3], const double cov[6], double
   float r2 = fabsf(nf.w[3]) + fabsf(nf.w[4]) + fabsf(nf.w[5]);
   g = fmaxf(r0, fmaxf(r1, r2));
   nf.c = (float)(nd.c * kLog2e);
+  nf.flags = F_LIVE;
+  nf.errc = 2.f * kU * fabsf(nf.c) * 1.0001f;
+  nf.errg = 9.f * kU * g * 1.0001f;
+  return true;
+}
+
+// FP64 1/sqrt(x) for a positive normal x: the hardware estimate refined by
+// two Newton steps (each at least doubles the number of correct bits).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
+// The FP32 scoring record alone (what an intermediate EM iteration needs):
+// the same Cholesky inverse as chol_inv3 with the three pivots' inverse
+// square roots taken directly, and one logarithm for the constant,
+// log2(pi) - log2|cov| / 2 = log2(pi / (L00 L11 L22)).
+__device__ inline bool make_nodef_fast(const double mu[3], const double c[6], double pi, NodeF& nf) {
+  const double p0 = c[0];
+  if (!(pi > 0.0) || !(p0 > 0.0)) return false;
+  const double i00 = rsqrt_nr(p0);
+  const double l10 = c[1] * i00, l20 = c[2] * i00;
+  const double p1 = c[3] - l10 * l10;
+  if (!(p1 > 0.0)) return false;
+  const double i11 = rsqrt_nr(p1);
+  const double l21 = (c[4] - l20 * l10) * i11;
+  const double p2 = c[5] - l20 * l20 - l21 * l21;
+  if (!(p2 > 0.0)) return false;
+  const double i22 = rsqrt_nr(p2);
+  const double i10 = -l10 * i00 * i11;
+  const double i21 = -l21 * i11 * i22;
+  const double i20 = -(l20 * i00 + l21 * i10) * i22;
+  const double winv[6] = {i00, i10, i11, i20, i21, i22};
+  for (int i = 0; i < 3; ++i) nf.mu[i] = mu[i];
+  for (int i = 0; i < 6; ++i) nf.w[i] = (float)(winv[i] * kWScale);
+  const float r0 = fabsf(nf.w[0]);
+  const float r1 = fabsf(nf.w[1]) + fabsf(nf.w[2]);
+  const float r2 = fabsf(nf.w[3]) + fabsf(nf.w[4]) + fabsf(nf.w[5]);
+  const float g = fmaxf(r0, fmaxf(r1, r2));
+  nf.c = (float)log2(pi * i00 * i11 * i22);
   nf.flags = F_LIVE;
   nf.errc = 2.f * kU * fabsf(nf.c) * 1.0001f;
   nf.errg = 9.f * kU * g * 1.0001f;

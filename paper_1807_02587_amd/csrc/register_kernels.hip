@@ -104,7 +104,8 @@ __device__ __forceinline__ int choose_child(NodePtr C, S64Ptr S, double p0, doub
   return k1;
 }
 
-constexpr int kLdsNodes = 72;  // levels 0 and 1 of one tree
+constexpr int kLdsNodes = 72;             // levels 0 and 1 of one tree
+constexpr int kLdsRows = kLdsNodes * 6;  // value rows of the block partials (mask rows follow)
 
 // gamma of the stop child k among the live siblings, with FP64 scores for k
 // and for every sibling whose FP32 weight 2^(s_j - s_k) exceeds 2^-40; the
@@ -288,9 +289,18 @@ __global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ 
     }
   }
   __syncthreads();
-  // block partials of the LDS-resident levels, value-major; the normal-equation
-  // kernel folds them in a fixed order
-  for (int i = threadIdx.x; i < nl * 6; i += blockDim.x) partials[(size_t)i * pstride + blockIdx.x] = lbin[i];
+  // block partials of the LDS-resident levels, value-major, for the nodes this
+  // block's points reached, and a mask of those nodes (rows kLdsRows and
+  // kLdsRows + 1: nodes 0-63, 64-71); the normal-equation kernel folds them
+  // in a fixed order.  Points reach only a few of the 72 nodes per block.
+  for (int i = threadIdx.x; i < nl * 6; i += blockDim.x)
+    if (lbin[(i / 6) * 6 + 4] > 0.0) partials[(size_t)i * pstride + blockIdx.x] = lbin[i];
+  if (threadIdx.x < 128) {
+    const int node = threadIdx.x;
+    const uint64_t m = __ballot(node < nl && lbin[node * 6 + 4] > 0.0);
+    if (lane == 0)
+      reinterpret_cast<uint64_t*>(partials + (size_t)(kLdsRows + (node >> 6)) * pstride)[blockIdx.x] = m;
+  }
 }
 
 // Writes the folded LDS-level moments into the node bins (for callers that
@@ -306,7 +316,9 @@ __global__ __launch_bounds__(256) void fold_bins_kernel(const int2* __restrict__
   const int lane = __lane_id(), wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int node = wv; node < nl; node += nw) {
     double v[6];
-    wave_fold<6, 4>(partials + (size_t)node * 6 * pstride + pt.x, pstride, pt.y, lane, v);
+    const uint64_t* mask = reinterpret_cast<const uint64_t*>(partials + (size_t)(kLdsRows + (node >> 6)) * pstride);
+    wave_fold_masked<6, 4>(partials + (size_t)node * 6 * pstride + pt.x, pstride, mask + pt.x, node & 63, pt.y, lane,
+                           v);
     if (lane == 0)
       for (int j = 0; j < 6; ++j) bins[(T.node_base + node) * 6 + j] = v[j];
   }
@@ -406,7 +418,9 @@ __global__ __launch_bounds__(kNormThreads) void normal_kernel(double* bins, cons
     const int2 pt = pair_tiles[pair];
     for (int node = wv; node < nl; node += kNormThreads / 64) {
       double b[6];
-      wave_fold<6, 4>(dpart + (size_t)node * 6 * pstride + pt.x, pstride, pt.y, lane, b);
+      const uint64_t* mask = reinterpret_cast<const uint64_t*>(dpart + (size_t)(kLdsRows + (node >> 6)) * pstride);
+      wave_fold_masked<6, 4>(dpart + (size_t)node * 6 * pstride + pt.x, pstride, mask + pt.x, node & 63, pt.y, lane,
+                             b);
       if (lane == 0)
         for (int j = 0; j < 6; ++j) lb[node * 6 + j] = b[j];
     }
