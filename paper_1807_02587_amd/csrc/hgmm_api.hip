@@ -213,6 +213,8 @@ static BuildLayout build_layout(int64_t n_total, int64_t max_jobs, int64_t max_l
   for (int k = 0; k < 2; ++k) { L.pts[k] = o; o = align_up(o + sizeof(float) * 3 * (size_t)n_total); }
   for (int k = 0; k < 2; ++k) { L.perm[k] = o; o = align_up(o + sizeof(int) * (size_t)n_total); }
   L.child = o; o = align_up(o + (size_t)n_total);
+  // level plan region [tiles, partials): holds the packed jobs | tiles | tile
+  // ids | job ids of one level (at most these four maxima)
   L.tiles = o; o = align_up(o + sizeof(Tile) * (size_t)L.max_tiles);
   L.tile_ids = o; o = align_up(o + sizeof(int) * (size_t)L.max_tiles);
   L.job_ids = o; o = align_up(o + sizeof(int) * (size_t)L.max_jobs);
@@ -229,8 +231,8 @@ static BuildLayout build_layout(int64_t n_total, int64_t max_jobs, int64_t max_l
 }
 
 struct RegLayout {
-  size_t bins, partials, counters, state, nmov, tiles, out, dpart, dcount, ptiles, active, keys, keys2, vals, perm,
-      sxyz, sort_temp, total;
+  size_t bins, partials, counters, state, nmov, tiles, out, dpart, dcount, ptiles, active, pose, keys, keys2, vals,
+      perm, sxyz, sort_temp, total;
   size_t sort_temp_bytes;
   int64_t max_tiles;
 };
@@ -244,10 +246,13 @@ static RegLayout reg_layout(int64_t n_total, int64_t nodes, int npairs) {
   L.counters = o; o = align_up(o + sizeof(unsigned) * (size_t)npairs);
   L.dpart = o; o = align_up(o + sizeof(double) * (72 * 6 + 2) * (size_t)L.max_tiles);  // values + node masks
   L.dcount = o; o = align_up(o + sizeof(unsigned) * (size_t)npairs);
+  // per-pair inputs uploaded together: tile ranges | point counts | start
+  // poses (12 doubles: R row-major, t) | active flags
   L.ptiles = o; o = align_up(o + sizeof(int2) * (size_t)npairs);
+  L.nmov = o; o = align_up(o + sizeof(int64_t) * (size_t)npairs);
+  L.pose = o; o = align_up(o + sizeof(double) * 12 * (size_t)npairs);
   L.active = o; o = align_up(o + sizeof(int) * (size_t)npairs);
   L.state = o; o = align_up(o + sizeof(PoseState) * (size_t)npairs);
-  L.nmov = o; o = align_up(o + sizeof(int64_t) * (size_t)npairs);
   L.tiles = o; o = align_up(o + sizeof(Tile) * (size_t)L.max_tiles);
   L.out = o; o = align_up(o + sizeof(double) * 28 * (size_t)npairs + sizeof(double) * 12 * npairs);
   // Morton ordering of the moving points (reg_sort)
@@ -437,10 +442,13 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
   float* pts[2] = {(float*)(ws + Ly.pts[0]), (float*)(ws + Ly.pts[1])};
   int* perm[2] = {(int*)(ws + Ly.perm[0]), (int*)(ws + Ly.perm[1])};
   uint8_t* child = (uint8_t*)(ws + Ly.child);
-  Tile* d_tiles = (Tile*)(ws + Ly.tiles);
-  int* d_tile_ids = (int*)(ws + Ly.tile_ids);
-  int* d_job_ids = (int*)(ws + Ly.job_ids);
-  Job* d_jobs = (Job*)(ws + Ly.jobs);
+  // the level plan (jobs | tiles | tile ids | job ids) is packed into the
+  // region [Ly.tiles, Ly.partials) and uploaded with one copy per level
+  char* d_plan = ws + Ly.tiles;
+  Tile* d_tiles = nullptr;
+  int* d_tile_ids = nullptr;
+  int* d_job_ids = nullptr;
+  Job* d_jobs = nullptr;
   double* d_partials = (double*)(ws + Ly.partials);
   double* d_part[2] = {d_partials, (double*)(ws + Ly.partials2)};
   NodeF* d_ch[2] = {(NodeF*)(ws + Ly.chbuf), (NodeF*)(ws + Ly.chbuf) + 8 * (size_t)Ly.max_jobs};
@@ -580,10 +588,25 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
     }
     const int nbigjobs = cls_n[3];
     if (ntiles > Ly.max_tiles || njobs > Ly.max_jobs) return fail(HGMM_EINVAL, "internal: tile plan overflow");
-    HIP_TRY(hipMemcpyAsync(d_jobs, h_jobs, sizeof(Job) * njobs, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(d_tiles, h_tiles, sizeof(Tile) * ntiles, hipMemcpyHostToDevice, s));
-    if (nbig) HIP_TRY(hipMemcpyAsync(d_tile_ids, h_tids, sizeof(int) * nbig, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(d_job_ids, h_jids, sizeof(int) * njobs, hipMemcpyHostToDevice, s));
+    {
+      // pack the plan behind the jobs in the staging buffer (every table moves
+      // to a lower or equal offset, in order, so nothing is overwritten before
+      // it is moved) and upload it with one copy; the previous level's copy
+      // has completed (the stream was synchronised for the level sizes)
+      const size_t o_tiles = align_up(sizeof(Job) * (size_t)njobs);
+      const size_t o_tids = align_up(o_tiles + sizeof(Tile) * (size_t)ntiles);
+      const size_t o_jids = align_up(o_tids + sizeof(int) * (size_t)nbig);
+      const size_t o_end = o_jids + sizeof(int) * (size_t)njobs;
+      char* hp = (char*)h_jobs;
+      memmove(hp + o_tiles, h_tiles, sizeof(Tile) * (size_t)ntiles);
+      memmove(hp + o_tids, h_tids, sizeof(int) * (size_t)nbig);
+      memmove(hp + o_jids, h_jids, sizeof(int) * (size_t)njobs);
+      HIP_TRY(hipMemcpyAsync(d_plan, hp, o_end, hipMemcpyHostToDevice, s));
+      d_jobs = (Job*)d_plan;
+      d_tiles = (Tile*)(d_plan + o_tiles);
+      d_tile_ids = (int*)(d_plan + o_tids);
+      d_job_ids = (int*)(d_plan + o_jids);
+    }
 
     if (l == 0) {
       {
@@ -697,19 +720,22 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   int64_t* d_nmov = (int64_t*)(ws + Ly.nmov);
   Tile* d_tiles = (Tile*)(ws + Ly.tiles);
   double* d_out = (double*)(ws + Ly.out);
-  double* d_pose0 = d_out + 28 * P;
+  double* d_pose0 = (double*)(ws + Ly.pose);
   double* d_dpart = (double*)(ws + Ly.dpart);
   unsigned* d_dcount = (unsigned*)(ws + Ly.dcount);
   int2* d_ptiles = (int2*)(ws + Ly.ptiles);
 
+  // staging: tiles | per-pair inputs (the device layout from Ly.ptiles on) |
+  // results | normal-equation sums
   size_t s_tiles = 0;
-  size_t s_nmov = align_up(s_tiles + sizeof(Tile) * Ly.max_tiles);
-  size_t s_pose = align_up(s_nmov + sizeof(int64_t) * P);
-  size_t s_res = align_up(s_pose + sizeof(double) * 12 * P);
+  size_t s_up = align_up(s_tiles + sizeof(Tile) * Ly.max_tiles);
+  size_t s_pt = s_up;
+  size_t s_nmov = s_up + (Ly.nmov - Ly.ptiles);
+  size_t s_pose = s_up + (Ly.pose - Ly.ptiles);
+  size_t s_act = s_up + (Ly.active - Ly.ptiles);
+  size_t s_res = align_up(s_act + sizeof(int) * P);
   size_t s_norm = align_up(s_res + sizeof(PoseState) * P);
-  size_t s_pt = align_up(s_norm + sizeof(double) * 28 * P);
-  size_t s_act = align_up(s_pt + sizeof(int2) * P);
-  size_t s_end = align_up(s_act + sizeof(int) * P);
+  size_t s_end = align_up(s_norm + sizeof(double) * 28 * P);
   int rc = grow_stage(f, s_end);
   if (rc) return rc;
   char* H = f->h_stage;
@@ -742,15 +768,14 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
     for (int i = 0; i < 9; ++i) h_pose[12 * b + i] = R0 ? R0[9 * b + i] : (i % 4 == 0 ? 1.0 : 0.0);
     for (int i = 0; i < 3; ++i) h_pose[12 * b + 9 + i] = t0 ? t0[3 * b + i] : 0.0;
   }
-  HIP_TRY(hipMemcpyAsync(d_tiles, h_tiles, sizeof(Tile) * ntiles, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(d_ptiles, h_pt, sizeof(int2) * P, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(d_nmov, h_nmov, sizeof(int64_t) * P, hipMemcpyHostToDevice, s));
-  // pose rows are 12 doubles: R (9) then t (3)
-  HIP_TRY(hipMemcpyAsync(d_pose0, h_pose, sizeof(double) * 12 * npose, hipMemcpyHostToDevice, s));
-  if (active) {
+  if (active)
     for (int b = 0; b < P; ++b) h_act[b] = active[b] ? 1 : 0;
-    HIP_TRY(hipMemcpyAsync(d_act, h_act, sizeof(int) * P, hipMemcpyHostToDevice, s));
-  }
+  // two uploads: the tiles, then the per-pair block (up to the active flags
+  // when given, else up to the start poses in use; pose rows are 12 doubles)
+  HIP_TRY(hipMemcpyAsync(d_tiles, h_tiles, sizeof(Tile) * ntiles, hipMemcpyHostToDevice, s));
+  const size_t up_bytes = active ? (Ly.active - Ly.ptiles) + sizeof(int) * P
+                                 : (Ly.pose - Ly.ptiles) + sizeof(double) * 12 * npose;
+  HIP_TRY(hipMemcpyAsync(d_ptiles, h_pt, up_bytes, hipMemcpyHostToDevice, s));
   const int* d_perm = nullptr;
   if (g_tune.reg_sort && n_total > 0) {
     float* sx = (float*)(ws + Ly.sxyz);
