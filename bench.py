@@ -57,6 +57,10 @@ def roofline_of(prof, depth, traffic=None):
                          EM_FLOP_PER_POINT_ITER, EM_BYTES_PER_POINT_ITER),
             "descend": ("descend_kernel (registration E-step)", DESC_FLOP_FIXED + DESC_FLOP_PER_LEVEL * depth,
                         DESC_BYTES_PER_POINT)}
+    fam_frac = {}
+    for k, (_, fu, _) in cand.items():
+        if prof[k]["ms"] > 0:
+            fam_frac[k] = round(prof[k]["units"] * fu / (prof[k]["ms"] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4)
     dom = max(cand, key=lambda k: prof[k]["ms"])
     kname, flop_unit, bytes_unit = cand[dom]
     ms, launches, units = prof[dom]["ms"], prof[dom]["launches"], prof[dom]["units"]
@@ -67,7 +71,8 @@ def roofline_of(prof, depth, traffic=None):
             "kernel": kname, "launches": launches, "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
             "flop_per_launch": round(flop / max(launches, 1)),
             "frac_of_packed_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4),
-            "achieved_hbm_GBs": round(byts / (ms * 1e-3) / 1e9, 1) if ms > 0 else 0.0}
+            "achieved_hbm_GBs": round(byts / (ms * 1e-3) / 1e9, 1) if ms > 0 else 0.0,
+            "frac_by_family": fam_frac}
 
 
 def mean_depth(stop, level_offsets):

@@ -139,12 +139,39 @@ def steps(path: str, first: str = "root_mean_kernel") -> str:
     return "\n".join(out)
 
 
+def timeline(path: str, first: str = "root_mean_kernel") -> str:
+    """Kernels of the last complete step of a kernel trace in start order, runs
+    of one kernel on one queue merged: start, end, span (us from the step's
+    first kernel), queue, count, busy time."""
+    rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Start_Timestamp"]))
+    name = lambda r: _short(r["Kernel_Name"])
+    marks = [i for i, r in enumerate(rows) if name(r) == first]
+    if len(marks) < 2:
+        return "fewer than two steps in the trace"
+    seg = rows[marks[-2]:marks[-1]]
+    t0 = int(seg[0]["Start_Timestamp"])
+    runs = []
+    for r in seg:
+        n, q = name(r).replace("void ", "")[:34], r.get("Queue_Id", "?")
+        s, e = (int(r["Start_Timestamp"]) - t0) / 1e3, (int(r["End_Timestamp"]) - t0) / 1e3
+        if runs and runs[-1][0] == n and runs[-1][4] == q:
+            runs[-1][2] = e
+            runs[-1][3] += 1
+            runs[-1][5] += e - s
+        else:
+            runs.append([n, s, e, 1, q, e - s])
+    return "\n".join(f"{s:9.1f} {e:9.1f} {e - s:8.1f}  q{q:>3} x{c:<3} busy {busy:8.1f}  {n}"
+                     for n, s, e, c, q, busy in runs)
+
+
 if __name__ == "__main__":
     mode, path = sys.argv[1], sys.argv[2]
     if mode == "stats":
         print(stats(path))
     elif mode == "steps":
         print(steps(path, *sys.argv[3:4]))
+    elif mode == "timeline":
+        print(timeline(path, *sys.argv[3:4]))
     elif mode == "traffic":
         res = traffic(path, sys.argv[3], float(sys.argv[4]))
         with open(sys.argv[5], "w") as f:
