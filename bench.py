@@ -72,7 +72,7 @@ def roofline_of(prof, depth, traffic=None):
             "flop_per_launch": round(flop / max(launches, 1)),
             "frac_of_packed_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4),
             "achieved_hbm_GBs": round(byts / (ms * 1e-3) / 1e9, 1) if ms > 0 else 0.0,
-            "frac_by_family": fam_frac}
+            "frac_by_family": fam_frac, **(_valu(dom, traffic) if traffic else {})}
 
 
 def mean_depth(stop, level_offsets):
@@ -97,6 +97,27 @@ def _traffic(family, which):
     if t.get("kernel_sources_sha1") != profiling.sources_sha1() or family not in t.get("families", {}):
         return None
     return t["families"][family]["bytes_per_launch"]
+
+
+VALU = {"lidar": os.path.join(ROOT, "profiles", "lidar_valu.json"),
+        "batch": os.path.join(ROOT, "profiles", "batch_valu.json")}
+
+
+def _valu(family, which):
+    """VALU busy and lane utilisation (percent) and the counted FLOP rate over
+    the kernel-trace time of a kernel family, from the committed counter pass,
+    or {} when there is none or the kernels changed since."""
+    from paper_1807_02587_amd import profiling
+    try:
+        with open(VALU[which]) as f:
+            v = json.load(f)
+    except (OSError, ValueError):
+        return {}
+    if v.get("kernel_sources_sha1") != profiling.sources_sha1() or family not in v.get("families", {}):
+        return {}
+    f = v["families"][family]
+    return {"valu_busy_pct": f["valu_busy_pct"], "valu_utilization_pct": f["valu_utilization_pct"],
+            "counted_flop_frac": f["counted_frac"]}
 
 
 def _workload(name):
@@ -243,6 +264,51 @@ def batch_section(args, hg):
                 out["batched_warm_ok_pairs_s"] / out["plain_sequential_ok_pairs_s"], 2)
     hg.hgmm_set_tuning(**defaults)
     return out
+
+
+def depth_section(args, hg):
+    """The depth-camera pair (640x480 camera in a furnished room, about 2.9e5
+    points per view, 5 levels, the precision form's workload): build of the
+    source tree plus registration from the identity per step, with launch
+    shapes from the autotuner on this pair (chosen before the timed steps)."""
+    import torch
+    from synth import rotation_angle_deg
+    p, pr, desc = _workload("depth")
+    dev = torch.device("cuda", 0)
+    src = torch.from_numpy(p.src).to(dev)
+    tgt = torch.from_numpy(p.tgt).to(dev)
+    n1, n2 = p.src.shape[1], p.tgt.shape[1]
+    ws_b, ws_r = hg.Workspace(dev), hg.Workspace(dev)
+    keep = hg.hgmm_get_tuning()
+    tree = None
+
+    def step():
+        nonlocal tree
+        tree = hg.hgmm_build(src, levels=pr["levels"], reg_eps=pr["reg_eps"], min_mass=pr["min_mass"], ws=ws_b,
+                             tree=tree)
+        return hg.hgmm_register(tree, tgt, lambda_c=pr["lambda_c"], ws=ws_r, raise_singular=False)
+
+    try:
+        tun = hg.hgmm_autotune(src, [0, n1], [pr["levels"]], tgt, [0, n2], reg_eps=pr["reg_eps"],
+                               min_mass=pr["min_mass"], lambda_c=pr["lambda_c"], reps=1, passes=1)
+        for _ in range(2):
+            step()
+        torch.cuda.synchronize()
+        steps = max(3, args.steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = step()
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        shapes = hg.hgmm_get_tuning()
+    finally:
+        hg.hgmm_set_tuning(**keep)
+    return {"workload": f"depth: {desc}", "points_src": n1, "points_tgt": n2, "levels": pr["levels"],
+            "reg_eps": pr["reg_eps"], "min_mass": pr["min_mass"], "steps": steps,
+            "pairs_s": round(steps / sec, 2), "ms_per_step": round(sec / steps * 1e3, 3),
+            "rot_err_deg": round(rotation_angle_deg(r["R"], p.R_true), 4), "iters": int(r["iters"]),
+            "autotune_ms": {"start": round(tun["start_ms"], 3), "best": round(tun["best_ms"], 3)},
+            "launch_shapes": shapes}
 
 
 def warm_section(args, hg):
@@ -439,6 +505,7 @@ def main():
 
     batched = None if args.no_batch else batch_section(args, hg)
     warm_form = None if args.no_batch else warm_section(args, hg)
+    depth_form = None if args.no_batch else depth_section(args, hg)
 
     out = {
         "metric": "cloud pairs registered/s (build + register)",
@@ -469,6 +536,7 @@ def main():
         "cpu_baseline": cpu,
         "batched": batched,
         "warm_start": warm_form,
+        "depth_camera": depth_form,
     }
     print(json.dumps(out), flush=True)
 

@@ -4,6 +4,8 @@
     python -m paper_1807_02587_amd.profiling steps <dir>/<name>_kernel_trace.csv [first_kernel]
     python -m paper_1807_02587_amd.profiling counters <dir>/<name>_counter_collection.csv
     python -m paper_1807_02587_amd.profiling traffic <fetch.csv> <write.csv> <copy_bytes> <out.json>
+    python -m paper_1807_02587_amd.profiling timeline <dir>/<name>_kernel_trace.csv [first_kernel]
+    python -m paper_1807_02587_amd.profiling valu <dir>/<name>_counter_collection.csv <dir>/<name>_kernel_trace.csv <out.json>
 
 ``stats`` prints the per-kernel table (calls, total/average/min/max us,
 share) of a ``--kernel-trace --stats`` run; ``steps`` splits the kernel trace
@@ -15,7 +17,10 @@ every collected counter of a ``--pmc`` run; ``traffic`` turns a FETCH_SIZE
 pass and a WRITE_SIZE pass (KiB per dispatch) into HBM bytes per launch of
 each kernel family, scaled by what the same counters read for the largest
 plain copy of ``copy_bytes`` bytes in the same runs, and stamps the result
-with a hash of the kernel sources (a figure is stale once they change).
+with a hash of the kernel sources (a figure is stale once they change);
+``timeline`` lists the kernels of the last full step in start order; ``valu``
+turns a pass of VALU_COUNTERS with ``--kernel-trace`` into VALU busy and lane
+utilisation and the counted FLOP rate per kernel family.
 """
 
 from __future__ import annotations
@@ -116,6 +121,51 @@ def traffic(fetch_csv: str, write_csv: str, copy_bytes: float) -> dict:
             "families": fam, "kernel_sources_sha1": sources_sha1()}
 
 
+VALU_COUNTERS = ("VALUBusy", "VALUUtilization", "SQ_INSTS_VALU_FLOPS_FP32", "SQ_INSTS_VALU_FLOPS_FP32_TRANS",
+                 "SQ_INSTS_VALU_FLOPS_FP64")
+
+
+def valu(counter_csv: str, trace_csv: str, peak_tflops: float = 78.6) -> dict:
+    """Per kernel family, from a ``--pmc`` run of VALU_COUNTERS with
+    ``--kernel-trace``: mean VALUBusy (percent of the kernel's GPU time with a
+    VALU instruction in flight, per CU), mean VALUUtilization (active lanes per
+    VALU instruction, percent of 64), the FP32 (with transcendentals) and FP64
+    FLOPs the hardware counted per dispatch, the mean kernel duration from the
+    trace, and the counted FLOP rate as a fraction of ``peak_tflops``.
+
+    The SQ_INSTS_VALU_FLOPS_* counters count per wave instruction (an FMA as 2),
+    not per lane, so they are scaled by the wave size, 64.  Check on the LiDAR
+    construction: em_tile_kernel's transcendental count times 64 is exactly its
+    8 exp2 and 1 reciprocal per point-iteration."""
+    dur = {}
+    for r in csv.DictReader(open(trace_csv)):
+        dur[r.get("Dispatch_Id", r.get("Dispatch-Id"))] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    names = {}
+    for r in csv.DictReader(open(counter_csv)):
+        c = r.get("Counter_Name", r.get("Counter-Name"))
+        if c not in VALU_COUNTERS:
+            continue
+        d = r.get("Dispatch_Id", r.get("Dispatch-Id"))
+        per[d][c] += float(r.get("Counter_Value", r.get("Counter-Value", 0)))
+        names[d] = _short(r.get("Kernel_Name", r.get("Kernel-Name", "?")))
+    fam = {}
+    for key, prefix in FAMILIES.items():
+        ds = [d for d, n in names.items() if n.replace("void ", "").startswith(prefix) and d in dur]
+        if not ds:
+            continue
+        mean = lambda c: sum(per[d][c] for d in ds) / len(ds)
+        f32 = 64.0 * (mean("SQ_INSTS_VALU_FLOPS_FP32") + mean("SQ_INSTS_VALU_FLOPS_FP32_TRANS"))
+        f64 = 64.0 * mean("SQ_INSTS_VALU_FLOPS_FP64")
+        t = sum(dur[d] for d in ds) / len(ds)
+        rate = (f32 + f64) / t / 1e12 if t > 0 else 0.0
+        fam[key] = {"dispatches": len(ds), "valu_busy_pct": round(mean("VALUBusy"), 2),
+                    "valu_utilization_pct": round(mean("VALUUtilization"), 2), "fp32_flop_per_launch": round(f32),
+                    "fp64_flop_per_launch": round(f64), "mean_us": round(t * 1e6, 2),
+                    "counted_tflops": round(rate, 3), "counted_frac": round(rate / peak_tflops, 4)}
+    return {"families": fam, "peak_tflops": peak_tflops, "kernel_sources_sha1": sources_sha1()}
+
+
 def steps(path: str, first: str = "root_mean_kernel") -> str:
     rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Start_Timestamp"]))
     name = lambda r: _short(r["Kernel_Name"])
@@ -172,6 +222,11 @@ if __name__ == "__main__":
         print(steps(path, *sys.argv[3:4]))
     elif mode == "timeline":
         print(timeline(path, *sys.argv[3:4]))
+    elif mode == "valu":
+        res = valu(path, sys.argv[3])
+        with open(sys.argv[4], "w") as f:
+            json.dump(res, f, indent=1)
+        print(json.dumps(res, indent=1))
     elif mode == "traffic":
         res = traffic(path, sys.argv[3], float(sys.argv[4]))
         with open(sys.argv[5], "w") as f:

@@ -1,0 +1,108 @@
+"""Precision form on the depth-camera pair (640x480 camera, about 2.9e5 points,
+5 levels): every output of the FP32 / FP64 path against the FP64 oracle, in
+one report (printed, one line per output), each held to its tolerance.
+
+Outputs: the tree (every level after one EM iteration from the GPU's parent
+level: weights, means, covariances), the E-step at a pose 1 degree from the
+truth (stop nodes, responsibilities, per-node moments, log-likelihood), the
+normal equations from identical moments (H, g), and the registered pose from
+a start 1 degree and 0.1 % of the extent away from the truth.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import depth_pair, rotation_angle_deg, rotation_from_axis_angle
+from gpu_helpers import compare_build_levels, gpu_bins_from_oracle, rel_err, to_oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FLAG_GAP = 1e-6
+EM1_TOL = dict(pi=1e-5, mu=1e-5, cov=1e-5)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_depth_pair_errors_per_output():
+    import paper_1807_02587_amd as hg
+    from paper_1807_02587_amd.presets import PRESETS
+    pr = PRESETS["depth"]
+    L, eps, mm = pr["levels"], pr["reg_eps"], pr["min_mass"]
+    p = depth_pair(2000)
+    rep = []
+
+    # tree: one EM iteration per level from the GPU's parent level
+    tree1 = hg.hgmm_build(_cuda(p.src), levels=L, reg_eps=eps, min_mass=mm, build_iters=1)
+    h1 = tree1.export()
+    w = compare_build_levels(oracle, h1, tree1.labels().cpu().numpy(), p.src, L, eps, mm, 1, EM1_TOL, log)
+    rep += [("tree pi (rel)", w["pi"], 1e-5), ("tree mu (/ extent)", w["mu"], 1e-5),
+            ("tree cov (/ trace)", w["cov"], 1e-5)]
+
+    # the 30-iteration tree the rest runs on
+    tree = hg.hgmm_build(_cuda(p.src), levels=L, reg_eps=eps, min_mass=mm)
+    host = tree.export()
+    ot = to_oracle(oracle, host)
+
+    # E-step
+    R = rotation_from_axis_angle([0.3, -1.0, 0.4], math.radians(1.0)) @ p.R_true
+    t = p.t_true + 0.001 * p.extent * np.array([1.0, -0.5, 0.25])
+    g = hg.hgmm_estep(tree, _cuda(p.tgt), R, t, lambda_c=pr["lambda_c"])
+    o = oracle.estep(ot, p.tgt, R, t, lambda_c=pr["lambda_c"])
+    stop = g["stop_node"].cpu().numpy()
+    flagged = o["min_gap"] < FLAG_GAP
+    mism = int(((stop != o["stop_node"]) & ~flagged).sum())
+    ok = ~flagged & (stop == o["stop_node"]) & (o["stop_node"] >= 0)
+    gam = g["gamma"].cpu().numpy().astype(np.float64)
+    e_gam = float((np.abs(gam[ok] - o["gamma"][ok]) / o["gamma"][ok]).max())
+    gb = g["bins"].cpu().numpy()
+    ob = gpu_bins_from_oracle(host, o["bins"])
+    touched = np.zeros(len(ob), bool)
+    touched[o["stop_node"][flagged & (o["stop_node"] >= 0)]] = True
+    touched[stop[flagged & (stop >= 0)]] = True
+    sel = (ob[:, 4] >= 1) & ~touched
+    e_m0 = float(rel_err(gb[sel, 0], ob[sel, 0], 1e-30).max())
+    e_d = float((np.abs(gb[sel, 1:4] - ob[sel, 1:4]).max(1) / (ob[sel, 0] * host["extent"])).max())
+    e_q = float(rel_err(gb[sel, 5], ob[sel, 5], 1.0).max())
+    cnt_equal = bool(np.array_equal(gb[sel, 4], ob[sel, 4]))
+    e_ll = abs(g["loglik"] - o["loglik"]) / max(1.0, abs(o["loglik"]))
+    rep += [("E-step stop nodes: mismatches outside flagged near-ties", mism, 0),
+            ("E-step gamma (rel)", e_gam, 1e-4), ("E-step bin mass M0 (rel)", e_m0, 1e-5),
+            ("E-step bin offset D (/ M0 extent)", e_d, 1e-5), ("E-step bin sum of d^2 (rel)", e_q, 1e-4),
+            ("E-step log-likelihood (rel)", e_ll, 1e-5)]
+    log(f"[precision] {flagged.sum()} of {len(stop)} points flagged as near ties; {sel.sum()} bins compared; "
+        f"counts identical: {cnt_equal}")
+
+    # normal equations from identical moments
+    n = p.tgt.shape[1]
+    Ho, go = oracle.normal_equations(ot, o["bins"], n)
+    Hg, gg = hg.hgmm_normal_equations(tree, _cuda(ob), n)
+    rep += [("normal equations H (rel to max)", float(np.abs(Hg - Ho).max() / np.abs(Ho).max()), 1e-10),
+            ("normal equations g (rel to max)", float(np.abs(gg - go).max() / np.abs(go).max()), 1e-9)]
+
+    # registration from near the truth
+    R0 = rotation_from_axis_angle([0.2, 0.9, -0.3], math.radians(1.0)) @ p.R_true
+    t0 = p.t_true + 0.001 * p.extent * np.array([0.5, -0.2, 0.3])
+    r = hg.hgmm_register(tree, _cuda(p.tgt), R0=R0, t0=t0, lambda_c=pr["lambda_c"])
+    ro = oracle.register(ot, p.tgt, R0=R0, t0=t0, lambda_c=pr["lambda_c"])
+    rep += [("pose rotation (rad)", math.radians(rotation_angle_deg(r["R"], ro["R"])), 1e-4),
+            ("pose translation (/ extent)", float(np.linalg.norm(r["t"] - ro["t"]) / host["extent"]), 1e-4),
+            ("iterations (difference)", abs(int(r["iters"]) - int(ro["iters"])), 2)]
+    log(f"[precision] depth pair: {p.src.shape[1]} + {n} points, {L} levels; registration {r['iters']} iterations, "
+        f"error vs truth {rotation_angle_deg(r['R'], p.R_true):.4f} deg")
+    log("[precision] output | error against the FP64 oracle | tolerance")
+    for name, err, tol in rep:
+        log(f"[precision] {name} | {err:.3g} | {tol:g}")
+    assert cnt_equal
+    for name, err, tol in rep:
+        assert err <= tol, name
