@@ -182,7 +182,8 @@ def batch_section(args, hg):
     last = {}
 
     def batched_plain():
-        forest = hg.hgmm_build_batch(src, off, lv, ws=ws)
+        # the handle is reused, as a caller registering batch after batch would
+        forest = hg.hgmm_build_batch(src, off, lv, ws=ws, forest=last.get("forest"))
         r = hg.hgmm_register_batch(forest, tgt, off, ws=ws)
         last.update(forest=forest, r=r)
         return r["R"]

@@ -19,7 +19,8 @@ class BuildParams(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [(k, C.c_int32) for k in ("block64_max", "block256_max", "block512_max", "min_tile", "target_tiles",
-                                          "max_tile", "reg_tile", "reg_chunk", "reg_graph", "reg_sort", "tile_threads", "reg_lds_levels")]
+                                          "max_tile", "reg_tile", "reg_chunk", "reg_graph", "reg_sort", "tile_threads", "reg_lds_levels",
+                                          "build_graph")]
 
 
 class RegParams(C.Structure):
@@ -39,6 +40,7 @@ SIGNATURES = {
     "hgmm_params_default": (C.c_int, [P, P]),
     "hgmm_tree_nodes": (I64, [C.c_int]),
     "hgmm_level_offset": (I64, [C.c_int]),
+    "hgmm_build_graph_stats": (C.c_int, [P, P, P, P]),
     "hgmm_build_workspace_bytes": (C.c_size_t, [I64, C.c_int]),
     "hgmm_register_workspace_bytes": (C.c_size_t, [I64, C.c_int]),
     "hgmm_build": (C.c_int, [P, I64, P, P, C.c_size_t, P, P]),

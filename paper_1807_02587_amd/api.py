@@ -67,7 +67,7 @@ def hgmm_level_offset(level: int) -> int:
 
 
 TUNING_KEYS = ("block64_max", "block256_max", "block512_max", "min_tile", "target_tiles", "max_tile", "reg_tile",
-               "reg_chunk", "reg_graph", "reg_sort", "tile_threads", "reg_lds_levels")
+               "reg_chunk", "reg_graph", "reg_sort", "tile_threads", "reg_lds_levels", "build_graph")
 
 
 def hgmm_get_tuning() -> dict:
@@ -161,6 +161,14 @@ class Tree:
         check(_lib.load().hgmm_tree_export(self.handle, index, C.byref(th)), "hgmm_tree_export")
         out.update(levels=th.levels, n_points=th.n_points, origin=np.array(th.origin[:]), extent=th.extent)
         return out
+
+    def graph_stats(self) -> dict:
+        """Constructions of this handle so far: graph replays, graphs captured,
+        host-planned constructions (see build_graph in hgmm_tuning)."""
+        r, c, h = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+        check(_lib.load().hgmm_build_graph_stats(self.handle, C.byref(r), C.byref(c), C.byref(h)),
+              "hgmm_build_graph_stats")
+        return dict(replays=r.value, captures=c.value, host_builds=h.value)
 
     def labels(self, index: int = 0, n_points: int | None = None, stream=None) -> torch.Tensor:
         """(levels, n) int32 most-likely-child labels of tree ``index`` (local node index at each level)."""

@@ -37,6 +37,12 @@ void launch_fill_u32(void* p, uint32_t v, int64_t n_words, hipStream_t s) {
   hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, v, n_words);
 }
 
+// Work items of a launch: blockIdx.x, blockIdx.x + gridDim.x, ... below n, or
+// below *dn when the count lives on the device (a level planned on the device,
+// launched with a fixed grid).  With dn null and one block per item this is
+// exactly one item per block.
+__device__ __forceinline__ int work_count(const int* dn, int n) { return dn ? *dn : n; }
+
 __device__ __forceinline__ void copy_nodef(NodeF& dst, const NodeF& src) {
   const float4* s = reinterpret_cast<const float4*>(&src);
   float4* d = reinterpret_cast<float4*>(&dst);
@@ -49,8 +55,10 @@ __device__ __forceinline__ void copy_nodef(NodeF& dst, const NodeF& src) {
 
 __global__ __launch_bounds__(64) void root_mean_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
                                                        const float* __restrict__ zs, const Tile* __restrict__ tiles,
-                                                       double* partials, size_t pstride) {
-  const Tile tl = tiles[blockIdx.x];
+                                                       double* partials, size_t pstride, const int* dn, int n) {
+  const int nw = work_count(dn, n);
+  for (int w = blockIdx.x; w < nw; w += gridDim.x) {
+  const Tile tl = tiles[w];
   const int lane = threadIdx.x;
   double s0 = 0, s1 = 0, s2 = 0;
   float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY, hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
@@ -72,14 +80,18 @@ __global__ __launch_bounds__(64) void root_mean_kernel(const float* __restrict__
   if (lane == 0) {
     const double vals[10] = {s0, s1, s2, (double)lo0, (double)lo1, (double)lo2, (double)hi0, (double)hi1,
                              (double)hi2, (double)bad};
-    for (int v = 0; v < 10; ++v) partials[(size_t)v * pstride + blockIdx.x] = vals[v];
+    for (int v = 0; v < 10; ++v) partials[(size_t)v * pstride + w] = vals[v];
+  }
   }
 }
 
 // One wave per tree: fixed-order fold of the root-mean tile partials.
 __global__ __launch_bounds__(64) void root_mean_fold_kernel(const Job* __restrict__ jobs, TreeDev* trees,
-                                                            const double* __restrict__ partials, size_t pstride) {
-  const Job jb = jobs[blockIdx.x];
+                                                            const double* __restrict__ partials, size_t pstride,
+                                                            const int* dn, int n) {
+  const int nw = work_count(dn, n);
+  for (int w = blockIdx.x; w < nw; w += gridDim.x) {
+  const Job jb = jobs[w];
   const int lane = threadIdx.x;
   double a[3], bb[1];
   wave_fold<3, 8>(partials + jb.tile_first, pstride, jb.ntiles, lane, a);
@@ -104,13 +116,16 @@ __global__ __launch_bounds__(64) void root_mean_fold_kernel(const Job* __restric
     T.extent = sqrt((h0 - l0) * (h0 - l0) + (h1 - l1) * (h1 - l1) + (h2 - l2) * (h2 - l2));
     if (b > 0) T.status = -3;
   }
+  }
 }
 
 __global__ __launch_bounds__(64) void root_cov_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
                                                       const float* __restrict__ zs, const Tile* __restrict__ tiles,
                                                       const Job* __restrict__ jobs, const TreeDev* __restrict__ trees,
-                                                      double* partials, size_t pstride) {
-  const Tile tl = tiles[blockIdx.x];
+                                                      double* partials, size_t pstride, const int* dn, int n) {
+  const int nw = work_count(dn, n);
+  for (int w = blockIdx.x; w < nw; w += gridDim.x) {
+  const Tile tl = tiles[w];
   const Job jb = jobs[tl.job];
   const int lane = threadIdx.x;
   const double o0 = trees[jb.tree].origin[0], o1 = trees[jb.tree].origin[1], o2 = trees[jb.tree].origin[2];
@@ -123,14 +138,17 @@ __global__ __launch_bounds__(64) void root_cov_kernel(const float* __restrict__ 
   if (lane < 6) {
     double v = c[0];
     for (int k = 1; k < 6; ++k) v = (lane == k) ? c[k] : v;
-    partials[(size_t)lane * pstride + blockIdx.x] = v;
+    partials[(size_t)lane * pstride + w] = v;
+  }
   }
 }
 
 __global__ __launch_bounds__(64) void root_cov_fold_kernel(const Job* __restrict__ jobs, TreeDev* trees,
                                                            const double* __restrict__ partials, size_t pstride,
-                                                           double eps) {
-  const Job jb = jobs[blockIdx.x];
+                                                           double eps, const int* dn, int n) {
+  const int nw = work_count(dn, n);
+  for (int w = blockIdx.x; w < nw; w += gridDim.x) {
+  const Job jb = jobs[w];
   const int lane = threadIdx.x;
   double a[6];
   wave_fold<6, 8>(partials + jb.tile_first, pstride, jb.ntiles, lane, a);
@@ -141,6 +159,7 @@ __global__ __launch_bounds__(64) void root_cov_fold_kernel(const Job* __restrict
     T.root_cov[0] += eps; T.root_cov[3] += eps; T.root_cov[5] += eps;
     eig_sym3(T.root_cov, T.root_lam, T.root_evec);
   }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -148,10 +167,10 @@ __global__ __launch_bounds__(64) void root_cov_fold_kernel(const Job* __restrict
 // ---------------------------------------------------------------------------
 
 __global__ void init_children_kernel(const Job* __restrict__ jobs, int njobs, const TreeDev* __restrict__ trees,
-                                     NodeD* nodes, NodeF* tab, double eps) {
-  int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = gid >> 3, k = gid & 7;
-  if (j >= njobs) return;
+                                     NodeD* nodes, NodeF* tab, double eps, const int* dn) {
+  const int nj = work_count(dn, njobs);
+  for (int gid = blockIdx.x * blockDim.x + threadIdx.x; gid < 8 * nj; gid += gridDim.x * blockDim.x) {
+  const int j = gid >> 3, k = gid & 7;
   const Job jb = jobs[j];
   double pmu[3], plam[3], pev[9];
   if (jb.parent < 0) {
@@ -191,6 +210,7 @@ __global__ void init_children_kernel(const Job* __restrict__ jobs, int njobs, co
   } else {
     out.live = 0; out.pi = 0.0;
     tab[g].flags = 0u;
+  }
   }
 }
 
@@ -504,9 +524,11 @@ __global__ __launch_bounds__(NT) void em_tile_kernel(
     const Tile* __restrict__ tiles, const int* __restrict__ tile_ids, const Job* __restrict__ jobs,
     const NodeF* __restrict__ tab, const NodeF* __restrict__ ch_prev, NodeF* ch_next,
     const double* __restrict__ part_prev, double* part_next, size_t pstride, double eps, double min_mass,
-    int first) {
+    int first, const int* dn, int n) {
   constexpr int NR = NT / 16, NW = NT / 64;
-  const int tix = tile_ids[blockIdx.x];
+  const int nw = work_count(dn, n);
+  for (int w = blockIdx.x; w < nw; w += gridDim.x) {
+  const int tix = tile_ids[w];
   const Tile tl = tiles[tix];
   const Job jb = jobs[tl.job];
   const int slot = tl.pad;
@@ -551,6 +573,8 @@ __global__ __launch_bounds__(NT) void em_tile_kernel(
     for (int q = 0; q < NR; ++q) t += (double)rows[q][v];
     part_next[(size_t)v * pstride + tix] = t;
   }
+  __syncthreads();  // the block's LDS is reused by its next tile
+  }
 }
 
 // Final M-step of the tiled jobs after the last iteration: one block of 16
@@ -563,18 +587,23 @@ __global__ __launch_bounds__(kMstepThreads) void em_mstep_kernel(const int* __re
                                                                  const Job* __restrict__ jobs, NodeF* tab,
                                                                  NodeD* nodes, const double* __restrict__ partials,
                                                                  size_t pstride, double eps, double min_mass,
-                                                                 const NodeF* __restrict__ chsrc) {
-  const Job jb = jobs[job_ids[blockIdx.x]];
+                                                                 const NodeF* __restrict__ chsrc, const int* dn, int n,
+                                                                 const int* doff) {
+  const int nw = work_count(dn, n), base = doff ? *doff : 0;
+  for (int w = blockIdx.x; w < nw; w += gridDim.x) {
+  const Job jb = jobs[job_ids[base + w]];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   __shared__ NodeF ch[8];
   __shared__ double tot[80];
-  if (tid < 8) copy_nodef(ch[tid], chsrc[(size_t)blockIdx.x * 8 + tid]);
+  if (tid < 8) copy_nodef(ch[tid], chsrc[(size_t)w * 8 + tid]);
   double t[5];
   wave_fold<5, 8>(partials + (size_t)(5 * wv) * pstride + jb.tile_first, pstride, jb.ntiles, lane, t);
   if (lane == 0)
     for (int j = 0; j < 5; ++j) tot[5 * wv + j] = t[j];
   __syncthreads();
   if (tid < 64) mstep_children(tot, ch, tab, nodes, jb.child_base, eps, min_mass, lane);
+  __syncthreads();
+  }
 }
 
 // (Two waves per SIMD: with the children's parameters in scalar registers
@@ -589,9 +618,12 @@ template <int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void em_block_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
                                                       const float* __restrict__ zs, const int* __restrict__ job_ids,
                                                       const Job* __restrict__ jobs, NodeF* tab, NodeD* nodes,
-                                                      int iters, double eps, double min_mass) {
+                                                      int iters, double eps, double min_mass, const int* dn, int n,
+                                                      const int* doff) {
   constexpr int NR = NT / 16;
-  const Job jb = jobs[job_ids[blockIdx.x]];
+  const int nw = work_count(dn, n), base = doff ? *doff : 0;
+  for (int w = blockIdx.x; w < nw; w += gridDim.x) {
+  const Job jb = jobs[job_ids[base + w]];
   const int tid = threadIdx.x;
   __shared__ NodeF ch[8];
   __shared__ EmFrame fr;
@@ -632,6 +664,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void em
     nodes[g].live = 0; nodes[g].pi = 0.0;
     tab[g].flags = 0u;
   }
+  __syncthreads();  // the block's LDS is reused by its next job
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -643,8 +677,10 @@ __global__ __launch_bounds__(64) void partition_kernel(const float* __restrict__
                                                        const float* __restrict__ zs, const Tile* __restrict__ tiles,
                                                        const Job* __restrict__ jobs, const NodeF* __restrict__ tab,
                                                        const NodeD* __restrict__ nodes, uint8_t* child_out,
-                                                       int* tile_counts) {
-  const Tile tl = tiles[blockIdx.x];
+                                                       int* tile_counts, const int* dn, int n) {
+  const int nw = work_count(dn, n);
+  for (int w = blockIdx.x; w < nw; w += gridDim.x) {
+  const Tile tl = tiles[w];
   const Job jb = jobs[tl.job];
   const int lane = threadIdx.x;
   __shared__ NodeF ch[8];
@@ -702,15 +738,20 @@ __global__ __launch_bounds__(64) void partition_kernel(const float* __restrict__
     int v = cnt[0];
 #pragma unroll
     for (int b = 1; b < 9; ++b) v = (lane == b) ? cnt[b] : v;
-    tile_counts[(size_t)blockIdx.x * 9 + lane] = v;
+    tile_counts[(size_t)w * 9 + lane] = v;
+  }
+  __syncthreads();
   }
 }
 
 // Per job: exclusive prefix of the bucket counts over its tiles, the start and
 // size of every child's range, and the child partition sizes.
 __global__ __launch_bounds__(64) void prefix_kernel(const Job* __restrict__ jobs, const int* __restrict__ tile_counts,
-                                                    int* tile_base, NodeD* nodes, int2* lvl_info) {
-  const Job jb = jobs[blockIdx.x];
+                                                    int* tile_base, NodeD* nodes, int2* lvl_info, const int* dn,
+                                                    int n) {
+  const int nw = work_count(dn, n);
+  for (int w = blockIdx.x; w < nw; w += gridDim.x) {
+  const Job jb = jobs[w];
   const int lane = threadIdx.x;
   const int chunk = (jb.ntiles + 63) / 64;
   const int t0 = jb.tile_first + lane * chunk;
@@ -754,6 +795,7 @@ __global__ __launch_bounds__(64) void prefix_kernel(const Job* __restrict__ jobs
     nodes[jb.child_base + lane].count = ct;
     lvl_info[jb.child_lvl + lane] = make_int2(jb.start + st, ct);
   }
+  }
 }
 
 // Stable 9-way split of each job's range by child (8 = no live child): moves
@@ -763,13 +805,16 @@ __global__ __launch_bounds__(64) void scatter_kernel(const float* __restrict__ x
                                                      const Tile* __restrict__ tiles, const Job* __restrict__ jobs,
                                                      const TreeDev* __restrict__ trees, const uint8_t* __restrict__ child,
                                                      const int* __restrict__ tile_base, float* xo, float* yo, float* zo,
-                                                     int* perm_out, int32_t* labels, int level, int64_t level_off) {
-  const Tile tl = tiles[blockIdx.x];
+                                                     int* perm_out, int32_t* labels, int level, int64_t level_off,
+                                                     const int* dn, int n) {
+  const int nw = work_count(dn, n);
+  for (int w = blockIdx.x; w < nw; w += gridDim.x) {
+  const Tile tl = tiles[w];
   const Job jb = jobs[tl.job];
   const TreeDev& T = trees[jb.tree];
   const int lane = threadIdx.x;
   __shared__ int base[9];
-  if (lane < 9) base[lane] = tile_base[(size_t)blockIdx.x * 9 + lane];
+  if (lane < 9) base[lane] = tile_base[(size_t)w * 9 + lane];
   __syncthreads();
   const int local_child0 = (int)(jb.child_base - T.node_base - level_off);
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -801,15 +846,20 @@ __global__ __launch_bounds__(64) void scatter_kernel(const float* __restrict__ x
     }
     __syncthreads();
   }
+  __syncthreads();
+  }
 }
 
 // Eigen-decomposition, complexity and global weight of the new level's nodes;
 // the parent learns whether it has live children.
 __global__ __launch_bounds__(64) void finalize_level_kernel(const Job* __restrict__ jobs, int njobs, NodeD* nodes,
-                                                            NodeF* tab) {
-  const int gid = blockIdx.x * 64 + threadIdx.x;
+                                                            NodeF* tab, const int* dn) {
+  const int nj = work_count(dn, njobs);
+  // the loop bound is uniform over the wave, so the ballot below sees all lanes
+  for (int base = blockIdx.x * 64; base < 8 * nj; base += gridDim.x * 64) {
+  const int gid = base + threadIdx.x;
   const int j = gid >> 3, k = gid & 7;
-  const bool valid = j < njobs;
+  const bool valid = j < nj;
   bool live = false;
   Job jb;
   if (valid) {
@@ -817,7 +867,7 @@ __global__ __launch_bounds__(64) void finalize_level_kernel(const Job* __restric
     live = nodes[jb.child_base + k].live != 0;
   }
   const unsigned long long bal = __ballot(live);
-  if (!valid) return;
+  if (!valid) continue;
   const int lane = threadIdx.x;
   const bool any = ((bal >> (lane & ~7)) & 0xFFull) != 0ull;
   if (k == 0 && jb.parent >= 0) {
@@ -828,7 +878,7 @@ __global__ __launch_bounds__(64) void finalize_level_kernel(const Job* __restric
   nd.has_children = 0;
   if (!live) {
     nd.count = 0;
-    return;
+    continue;
   }
   double lam[3], ev[9];
   eig_sym3(nd.cov, lam, ev);
@@ -836,86 +886,295 @@ __global__ __launch_bounds__(64) void finalize_level_kernel(const Job* __restric
   for (int i = 0; i < 9; ++i) nd.evec[i] = ev[i];
   nd.kappa = lam[2] / (lam[0] + lam[1] + lam[2]);
   nd.pig = nd.pi * (jb.parent >= 0 ? nodes[jb.parent].pig : 1.0);
+  }
 }
 
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 
+// ---------------------------------------------------------------------------
+// level planning on the device (for construction captured in one graph)
+// ---------------------------------------------------------------------------
+
+// Job of parent item i of a level: item i is entry i / per of the level's tree
+// list, parent k = i % per of that tree (at level 0 the tree root itself).
+__device__ __forceinline__ void plan_item(int64_t i, int per, int level, int64_t loff_prev, int64_t loff_cur,
+                                          const LevelTree* __restrict__ lt, const int2* __restrict__ lvl_prev,
+                                          const TreeDev* __restrict__ trees, Job& j) {
+  const int e = (int)(i / per), k = (int)(i % per);
+  const LevelTree L = lt[e];
+  const TreeDev& T = trees[L.b];
+  j.tree = L.b;
+  if (level == 0) {
+    j.start = (int32_t)T.point_off;
+    j.count = T.n_points;
+    j.parent = -1;
+    j.child_base = (int32_t)T.node_base;
+    j.child_lvl = L.cur_base;
+  } else {
+    const int2 inf = lvl_prev[L.prev_base + k];
+    j.start = inf.x;
+    j.count = inf.y;
+    j.parent = (int32_t)(T.node_base + loff_prev + k);
+    j.child_base = (int32_t)(T.node_base + loff_cur + 8 * (int64_t)k);
+    j.child_lvl = L.cur_base + 8 * k;
+  }
+}
+
+// The plan of one level, as the host planner makes it and in the same order:
+// a job per parent with points (every tree root at level 0), in tree order
+// then parent order; the job ids class by class (class by point count:
+// thresholds b64 / b256 / b512, else tiled); tiles of tpts points, job after
+// job; the tile ids of the tiled jobs; the slot of a tiled job (its rank among
+// the tiled jobs) in its tiles' pad.  One block; two passes over the parents
+// (totals, then an ordered block scan).  Sets plan[PL_ERR] instead of writing
+// past max_jobs / max_tiles.
+constexpr int kPlanThreads = 1024;
+__global__ __launch_bounds__(kPlanThreads) void plan_level_kernel(
+    const LevelTree* __restrict__ lt, int nlt, int per, int level, int64_t loff_prev, int64_t loff_cur,
+    const int2* __restrict__ lvl_prev, const TreeDev* __restrict__ trees, int b64, int b256, int b512,
+    int target_tiles, int min_tile, int max_tile, int max_jobs, int max_tiles, Job* jobs, int* job_ids, Tile* tiles,
+    int* tile_ids, int* plan) {
+  constexpr int NV = 7, NW = kPlanThreads / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t total = (int64_t)nlt * per;
+  __shared__ unsigned long long s_points;
+  __shared__ int s_cls[4], s_off[5], s_tpts, s_err;
+  __shared__ int s_woff[NW][NV], s_btot[NV], s_carry[NV];
+  // items of the current chunk, for writing its tiles with the whole block:
+  // chunk-local first tile, global first tile, first tile id (tiled jobs),
+  // job, start, points, slot (tiled) or -1
+  __shared__ int s_tl[kPlanThreads], s_tg[kPlanThreads], s_bf[kPlanThreads], s_jid[kPlanThreads],
+      s_st[kPlanThreads], s_ct[kPlanThreads], s_sl[kPlanThreads];
+  if (tid == 0) {
+    s_points = 0ull;
+    s_err = 0;
+    for (int c = 0; c < 4; ++c) s_cls[c] = 0;
+    for (int k = 0; k < NV; ++k) s_carry[k] = 0;
+  }
+  __syncthreads();
+  auto cls_of = [&](int count) { return count <= b64 ? 0 : count <= b256 ? 1 : count <= b512 ? 2 : 3; };
+  // pass 1: points of the level and jobs per class
+  {
+    unsigned long long pts = 0ull;
+    int cl[4] = {0, 0, 0, 0};
+    for (int64_t i = tid; i < total; i += kPlanThreads) {
+      Job j;
+      plan_item(i, per, level, loff_prev, loff_cur, lt, lvl_prev, trees, j);
+      if (level == 0 || j.count > 0) {
+        pts += (unsigned long long)j.count;
+        cl[cls_of(j.count)] += 1;
+      }
+    }
+    atomicAdd(&s_points, pts);
+    for (int c = 0; c < 4; ++c) atomicAdd(&s_cls[c], cl[c]);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int64_t t = (int64_t)s_points / (target_tiles > 1 ? target_tiles : 1);
+    t = (t + 63) / 64 * 64;
+    t = t > min_tile ? t : min_tile;
+    t = t < max_tile ? t : max_tile;
+    s_tpts = (int)t;
+    s_off[0] = 0;
+    for (int c = 0; c < 4; ++c) s_off[c + 1] = s_off[c] + s_cls[c];
+  }
+  __syncthreads();
+  const int tpts = s_tpts;
+  // pass 2: ordered exclusive scan of (job, job of class 0..3, tiles, tiles of
+  // tiled jobs) over the parents, 1024 at a time
+  for (int64_t base = 0; base < total; base += kPlanThreads) {
+    const int64_t i = base + tid;
+    Job j;
+    j.count = 0;
+    bool valid = false;
+    if (i < total) {
+      plan_item(i, per, level, loff_prev, loff_cur, lt, lvl_prev, trees, j);
+      valid = (level == 0 || j.count > 0);
+    }
+    const int c = valid ? cls_of(j.count) : -1;
+    const int ntl = valid ? (j.count + tpts - 1) / tpts : 0;
+    int v[NV] = {valid ? 1 : 0, c == 0, c == 1, c == 2, c == 3, ntl, c == 3 ? ntl : 0};
+    int inc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      int x = v[k];
+      for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(x, d, 64);
+        if (lane >= d) x += u;
+      }
+      inc[k] = x;
+      if (lane == 63) s_woff[wv][k] = x;
+    }
+    __syncthreads();
+    if (tid < NV) {
+      int run = 0;
+      for (int w = 0; w < NW; ++w) {
+        const int x = s_woff[w][tid];
+        s_woff[w][tid] = run;
+        run += x;
+      }
+      s_btot[tid] = run;
+    }
+    __syncthreads();
+    {
+      int ex[NV];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) ex[k] = s_carry[k] + s_woff[wv][k] + inc[k] - v[k];
+      const int jid = ex[0], pos = valid ? ex[1 + c] : 0, tfirst = ex[5], bfirst = ex[6];
+      s_tl[tid] = tfirst - s_carry[5];
+      s_jid[tid] = -1;
+      if (valid) {
+        if (jid >= max_jobs || s_off[c] + pos >= max_jobs || tfirst + ntl > max_tiles) {
+          s_err = 1;
+        } else {
+          j.tile_first = tfirst;
+          j.ntiles = ntl;
+          jobs[jid] = j;
+          job_ids[s_off[c] + pos] = jid;
+          s_tg[tid] = tfirst;
+          s_bf[tid] = bfirst;
+          s_jid[tid] = jid;
+          s_st[tid] = j.start;
+          s_ct[tid] = j.count;
+          s_sl[tid] = (c == 3) ? pos : -1;
+        }
+      }
+    }
+    __syncthreads();
+    // the chunk's tiles, one per thread: tile u belongs to the last item whose
+    // chunk-local first tile is <= u (items without tiles share the offset of
+    // the next one)
+    const int nct = s_btot[5];
+    for (int u = tid; u < nct; u += kPlanThreads) {
+      int lo = 0, hi = kPlanThreads - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_tl[mid] <= u) lo = mid;
+        else hi = mid - 1;
+      }
+      if (s_jid[lo] < 0) continue;  // an overflowed item (s_err is set)
+      const int t = u - s_tl[lo];
+      Tile T;
+      T.start = s_st[lo] + t * tpts;
+      T.end = min(s_st[lo] + s_ct[lo], T.start + tpts);
+      T.job = s_jid[lo];
+      T.pad = s_sl[lo] >= 0 ? s_sl[lo] : 0;
+      tiles[s_tg[lo] + t] = T;
+      if (s_sl[lo] >= 0) tile_ids[s_bf[lo] + t] = s_tg[lo] + t;
+    }
+    __syncthreads();
+    if (tid < NV) s_carry[tid] += s_btot[tid];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    // after an overflow the level does no work (every count 0); the host
+    // reports plan[PL_ERR]
+    const int ok = s_err ? 0 : 1;
+    plan[PL_NJOBS] = ok * s_carry[0];
+    plan[PL_NTILES] = ok * s_carry[5];
+    plan[PL_NBIG] = ok * s_carry[6];
+    for (int c = 0; c < 4; ++c) plan[PL_CLS_N + c] = ok * s_cls[c];
+    for (int c = 0; c < 5; ++c) plan[PL_CLS_OFF + c] = ok * s_off[c];
+    plan[PL_TPTS] = tpts;
+    plan[PL_ERR] = s_err;
+  }
+}
+
+void launch_plan_level(const LevelTree* lt, int nlt, int per, int level, int64_t loff_prev, int64_t loff_cur,
+                       const int2* lvl_prev, const TreeDev* trees, int b64, int b256, int b512, int target_tiles,
+                       int min_tile, int max_tile, int max_jobs, int max_tiles, Job* jobs, int* job_ids, Tile* tiles,
+                       int* tile_ids, int* plan, hipStream_t s) {
+  hipLaunchKernelGGL(plan_level_kernel, dim3(1), dim3(kPlanThreads), 0, s, lt, nlt, per, level, loff_prev, loff_cur,
+                     lvl_prev, trees, b64, b256, b512, target_tiles, min_tile, max_tile, max_jobs, max_tiles, jobs,
+                     job_ids, tiles, tile_ids, plan);
+}
+
+// Launchers.  With a device count dn (a level planned on the device) the
+// kernels read their number of work items from *dn and the n given here is
+// the (fixed) grid; without it n is the number of work items, one block each.
 void launch_root(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles, const Job* jobs,
-                 int njobs, TreeDev* trees, double* partials, size_t pstride, double eps, hipStream_t s) {
-  hipLaunchKernelGGL(root_mean_kernel, dim3(ntiles), dim3(64), 0, s, xs, ys, zs, tiles, partials, pstride);
-  hipLaunchKernelGGL(root_mean_fold_kernel, dim3(njobs), dim3(64), 0, s, jobs, trees, partials, pstride);
-  hipLaunchKernelGGL(root_cov_kernel, dim3(ntiles), dim3(64), 0, s, xs, ys, zs, tiles, jobs, trees, partials, pstride);
-  hipLaunchKernelGGL(root_cov_fold_kernel, dim3(njobs), dim3(64), 0, s, jobs, trees, partials, pstride, eps);
+                 int njobs, TreeDev* trees, double* partials, size_t pstride, double eps, hipStream_t s,
+                 const int* dntiles, const int* dnjobs) {
+  hipLaunchKernelGGL(root_mean_kernel, dim3(ntiles), dim3(64), 0, s, xs, ys, zs, tiles, partials, pstride, dntiles,
+                     ntiles);
+  hipLaunchKernelGGL(root_mean_fold_kernel, dim3(njobs), dim3(64), 0, s, jobs, trees, partials, pstride, dnjobs,
+                     njobs);
+  hipLaunchKernelGGL(root_cov_kernel, dim3(ntiles), dim3(64), 0, s, xs, ys, zs, tiles, jobs, trees, partials, pstride,
+                     dntiles, ntiles);
+  hipLaunchKernelGGL(root_cov_fold_kernel, dim3(njobs), dim3(64), 0, s, jobs, trees, partials, pstride, eps, dnjobs,
+                     njobs);
 }
 
 void launch_init_children(const Job* jobs, int njobs, const TreeDev* trees, NodeD* nodes, NodeF* tab, double eps,
-                          hipStream_t s) {
+                          hipStream_t s, const int* dn) {
   int threads = njobs * 8;
   hipLaunchKernelGGL(init_children_kernel, dim3((threads + 63) / 64), dim3(64), 0, s, jobs, njobs, trees, nodes, tab,
-                     eps);
+                     eps, dn);
 }
 
 void launch_em_tile(int nt, const float* xs, const float* ys, const float* zs, const Tile* tiles, const int* tile_ids,
                     int n, const Job* jobs, const NodeF* tab, const NodeF* ch_prev, NodeF* ch_next,
                     const double* part_prev, double* part_next, size_t pstride, double eps, double min_mass, int first,
-                    hipStream_t s) {
+                    hipStream_t s, const int* dn) {
   if (nt == 1024)
     hipLaunchKernelGGL((em_tile_kernel<1024, 2>), dim3(n), dim3(1024), 0, s, xs, ys, zs, tiles, tile_ids, jobs, tab,
-                       ch_prev, ch_next, part_prev, part_next, pstride, eps, min_mass, first);
+                       ch_prev, ch_next, part_prev, part_next, pstride, eps, min_mass, first, dn, n);
   else if (nt == 512)
     hipLaunchKernelGGL((em_tile_kernel<512, 4>), dim3(n), dim3(512), 0, s, xs, ys, zs, tiles, tile_ids, jobs, tab,
-                       ch_prev, ch_next, part_prev, part_next, pstride, eps, min_mass, first);
+                       ch_prev, ch_next, part_prev, part_next, pstride, eps, min_mass, first, dn, n);
   else
     hipLaunchKernelGGL((em_tile_kernel<256, 4>), dim3(n), dim3(256), 0, s, xs, ys, zs, tiles, tile_ids, jobs, tab,
-                       ch_prev, ch_next, part_prev, part_next, pstride, eps, min_mass, first);
+                       ch_prev, ch_next, part_prev, part_next, pstride, eps, min_mass, first, dn, n);
 }
 
 void launch_em_mstep(const int* job_ids, int n, const Job* jobs, NodeF* tab, NodeD* nodes, const double* partials,
-                     size_t pstride, double eps, double min_mass, const NodeF* chsrc, hipStream_t s) {
+                     size_t pstride, double eps, double min_mass, const NodeF* chsrc, hipStream_t s, const int* dn,
+                     const int* doff) {
   hipLaunchKernelGGL(em_mstep_kernel, dim3(n), dim3(kMstepThreads), 0, s, job_ids, jobs, tab, nodes, partials,
-                     pstride, eps, min_mass, chsrc);
+                     pstride, eps, min_mass, chsrc, dn, n, doff);
 }
 
 void launch_em_block(int nt, const float* xs, const float* ys, const float* zs, const int* job_ids, int n,
                      const Job* jobs, NodeF* tab, NodeD* nodes, int iters, double eps, double min_mass,
-                     hipStream_t s) {
+                     hipStream_t s, const int* dn, const int* doff) {
   if (n <= 0) return;
   if (nt == 64)
     hipLaunchKernelGGL(em_block_kernel<64>, dim3(n), dim3(64), 0, s, xs, ys, zs, job_ids, jobs, tab, nodes, iters,
-                       eps, min_mass);
+                       eps, min_mass, dn, n, doff);
   else if (nt == 256)
     hipLaunchKernelGGL(em_block_kernel<256>, dim3(n), dim3(256), 0, s, xs, ys, zs, job_ids, jobs, tab, nodes, iters,
-                       eps, min_mass);
+                       eps, min_mass, dn, n, doff);
   else
     hipLaunchKernelGGL(em_block_kernel<512>, dim3(n), dim3(512), 0, s, xs, ys, zs, job_ids, jobs, tab, nodes, iters,
-                       eps, min_mass);
+                       eps, min_mass, dn, n, doff);
 }
 
 void launch_partition(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
                       const Job* jobs, const NodeF* tab, const NodeD* nodes, uint8_t* child, int* tile_counts,
-                      hipStream_t s) {
+                      hipStream_t s, const int* dn) {
   hipLaunchKernelGGL(partition_kernel, dim3(ntiles), dim3(64), 0, s, xs, ys, zs, tiles, jobs, tab, nodes, child,
-                     tile_counts);
+                     tile_counts, dn, ntiles);
 }
 
 void launch_prefix(const Job* jobs, int njobs, const int* tile_counts, int* tile_base, NodeD* nodes, int2* lvl_info,
-                   hipStream_t s) {
-  hipLaunchKernelGGL(prefix_kernel, dim3(njobs), dim3(64), 0, s, jobs, tile_counts, tile_base, nodes, lvl_info);
+                   hipStream_t s, const int* dn) {
+  hipLaunchKernelGGL(prefix_kernel, dim3(njobs), dim3(64), 0, s, jobs, tile_counts, tile_base, nodes, lvl_info, dn,
+                     njobs);
 }
 
 void launch_scatter(const float* xs, const float* ys, const float* zs, const int* perm, const Tile* tiles, int ntiles,
                     const Job* jobs, const TreeDev* trees, const uint8_t* child, const int* tile_base, float* xo,
                     float* yo, float* zo, int* perm_out, int32_t* labels, int level, int64_t level_off,
-                    hipStream_t s) {
+                    hipStream_t s, const int* dn) {
   hipLaunchKernelGGL(scatter_kernel, dim3(ntiles), dim3(64), 0, s, xs, ys, zs, perm, tiles, jobs, trees, child,
-                     tile_base, xo, yo, zo, perm_out, labels, level, level_off);
+                     tile_base, xo, yo, zo, perm_out, labels, level, level_off, dn, ntiles);
 }
 
-void launch_finalize_level(const Job* jobs, int njobs, NodeD* nodes, NodeF* tab, hipStream_t s) {
+void launch_finalize_level(const Job* jobs, int njobs, NodeD* nodes, NodeF* tab, hipStream_t s, const int* dn) {
   int threads = njobs * 8;
-  hipLaunchKernelGGL(finalize_level_kernel, dim3((threads + 63) / 64), dim3(64), 0, s, jobs, njobs, nodes, tab);
+  hipLaunchKernelGGL(finalize_level_kernel, dim3((threads + 63) / 64), dim3(64), 0, s, jobs, njobs, nodes, tab, dn);
 }
 
 }  // namespace hgmm

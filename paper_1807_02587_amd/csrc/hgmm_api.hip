@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "../../include/hgmm.h"
@@ -97,6 +98,16 @@ struct hgmm_forest_s {
   hipEvent_t ev_g0 = nullptr, ev_g1 = nullptr;
   hipGraphExec_t reg_exec = nullptr;
   std::vector<uint64_t> reg_key;
+  // construction graph (build_graph = 1): every level planned on the device,
+  // all launches of a construction in one graph, cached for the same shapes
+  hipGraphExec_t bld_exec = nullptr;
+  std::vector<uint64_t> bld_key;
+  // per-level work counts of the last host-planned construction (njobs,
+  // ntiles, nbig, jobs per class) and the shape they belong to: the graph's
+  // fixed grids are sized from them
+  std::vector<std::array<int, 7>> hint;
+  std::vector<uint64_t> hint_key;
+  int64_t n_graph_replays = 0, n_graph_captures = 0, n_host_builds = 0;
   int64_t total_nodes() const {
     int64_t s = 0;
     for (auto& t : trees) s += tree_nodes(t.levels);
@@ -121,6 +132,7 @@ static void free_forest(hgmm_forest_s* f) {
   }
   if (f->ev_fork) (void)hipEventDestroy(f->ev_fork);
   if (f->reg_exec) (void)hipGraphExecDestroy(f->reg_exec);
+  if (f->bld_exec) (void)hipGraphExecDestroy(f->bld_exec);
   if (f->gstream) (void)hipStreamDestroy(f->gstream);
   if (f->ev_g0) (void)hipEventDestroy(f->ev_g0);
   if (f->ev_g1) (void)hipEventDestroy(f->ev_g1);
@@ -200,11 +212,11 @@ static size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
 struct BuildLayout {
   size_t pts[2], perm[2], child, tiles, tile_ids, job_ids, jobs, partials, partials2, chbuf, tile_counts, tile_base,
-      counters, lvl_info, total;
+      counters, lvl_info, level_trees, plans, total;
   int64_t max_tiles, max_jobs, max_lvl;
 };
 
-static BuildLayout build_layout(int64_t n_total, int64_t max_jobs, int64_t max_lvl) {
+static BuildLayout build_layout(int64_t n_total, int64_t max_jobs, int64_t max_lvl, int B, int Lmax) {
   BuildLayout L;
   L.max_jobs = std::max<int64_t>(max_jobs, 1);
   L.max_tiles = n_total / 64 + L.max_jobs + 1;
@@ -226,6 +238,10 @@ static BuildLayout build_layout(int64_t n_total, int64_t max_jobs, int64_t max_l
   L.tile_base = o; o = align_up(o + sizeof(int) * 9 * (size_t)L.max_tiles);
   L.counters = o; o = align_up(o + sizeof(unsigned) * (size_t)L.max_jobs);
   L.lvl_info = o; o = align_up(o + sizeof(int2) * (size_t)L.max_lvl);
+  // construction planned on the device: the trees of every level and the
+  // level plans (PlanField ints)
+  L.level_trees = o; o = align_up(o + sizeof(LevelTree) * (size_t)std::max(B, 1) * (size_t)std::max(Lmax, 1));
+  L.plans = o; o = align_up(o + sizeof(int) * PL_SIZE * (size_t)std::max(Lmax, 1));
   L.total = o;
   return L;
 }
@@ -297,7 +313,7 @@ static int64_t max_lvl_for(const std::vector<TreeHost>& trees) {
 // launch shapes (process wide; see hgmm_tuning)
 // ---------------------------------------------------------------------------
 
-static hgmm_tuning g_tune = {256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0, 256, 2};
+static hgmm_tuning g_tune = {256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0, 256, 2, 0};
 
 extern "C" int hgmm_set_tuning(const hgmm_tuning* t) {
   if (!t) return fail(HGMM_EINVAL, "null tuning");
@@ -314,6 +330,7 @@ extern "C" int hgmm_set_tuning(const hgmm_tuning* t) {
   if (t->tile_threads != 256 && t->tile_threads != 512 && t->tile_threads != 1024)
     return fail(HGMM_EINVAL, "tile_threads must be 256, 512 or 1024");
   if (t->reg_lds_levels != 2 && t->reg_lds_levels != 3) return fail(HGMM_EINVAL, "reg_lds_levels must be 2 or 3");
+  if (t->build_graph != 0 && t->build_graph != 1) return fail(HGMM_EINVAL, "build_graph must be 0 or 1");
   g_tune = *t;
   g_tune.min_tile = (t->min_tile + 63) / 64 * 64;
   g_tune.max_tile = (t->max_tile + 63) / 64 * 64;
@@ -431,13 +448,31 @@ struct BuildInput {
   const float* zs;
 };
 
+// The shape of a construction: clouds (sizes, depths), parameters and launch
+// shapes; a construction graph, and the work counts that size its grids,
+// belong to one shape.
+static std::vector<uint64_t> build_shape_key(const hgmm_forest_s* f, const hgmm_build_params& p) {
+  uint64_t eps_bits, mm_bits;
+  memcpy(&eps_bits, &p.reg_eps, 8);
+  memcpy(&mm_bits, &p.min_mass, 8);
+  std::vector<uint64_t> key = {(uint64_t)f->trees.size(), (uint64_t)p.build_iters, eps_bits, mm_bits};
+  // every launch shape except build_graph itself (a host-planned construction
+  // records the counts a later graph construction uses)
+  hgmm_tuning tu = g_tune;
+  tu.build_graph = 0;
+  const int32_t* tv = (const int32_t*)&tu;
+  for (size_t k = 0; k < sizeof(hgmm_tuning) / sizeof(int32_t); ++k) key.push_back((uint64_t)(uint32_t)tv[k]);
+  for (auto& t : f->trees) key.push_back(((uint64_t)t.levels << 40) | (uint64_t)t.n_points);
+  return key;
+}
+
 static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p, char* ws, size_t ws_bytes,
                      hipStream_t s) {
   const int B = (int)f->trees.size();
   int64_t n_total = 0;
   int Lmax = 0;
   for (auto& t : f->trees) { n_total += t.n_points; Lmax = std::max(Lmax, t.levels); }
-  BuildLayout Ly = build_layout(n_total, max_jobs_for(f->trees), max_lvl_for(f->trees));
+  BuildLayout Ly = build_layout(n_total, max_jobs_for(f->trees), max_lvl_for(f->trees), B, Lmax);
   if (ws_bytes < Ly.total) return fail(HGMM_EINVAL, "build workspace too small: %zu < %zu", ws_bytes, Ly.total);
   float* pts[2] = {(float*)(ws + Ly.pts[0]), (float*)(ws + Ly.pts[1])};
   int* perm[2] = {(int*)(ws + Ly.perm[0]), (int*)(ws + Ly.perm[1])};
@@ -508,6 +543,7 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
   std::vector<Job> jobs;
   jobs.reserve(1024);
 
+  std::vector<std::array<int, 7>> hint((size_t)Lmax, std::array<int, 7>{0, 0, 0, 0, 0, 0, 0});
   for (int l = 0; l < Lmax; ++l) {
     // ---- plan the jobs of level l (parents at level l-1, roots at level 0)
     jobs.clear();
@@ -588,6 +624,7 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
     }
     const int nbigjobs = cls_n[3];
     if (ntiles > Ly.max_tiles || njobs > Ly.max_jobs) return fail(HGMM_EINVAL, "internal: tile plan overflow");
+    hint[l] = {njobs, ntiles, nbig, cls_n[0], cls_n[1], cls_n[2], cls_n[3]};
     {
       // pack the plan behind the jobs in the staging buffer (every table moves
       // to a lower or equal offset, in order, so nothing is overwritten before
@@ -687,6 +724,213 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
   HIP_TRY(hipMemcpyAsync(h_trees + B, f->d_trees, sizeof(TreeDev) * B, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   prof_collect();
+  for (int b = 0; b < B; ++b)
+    if (h_trees[B + b].status != 0) return fail(HGMM_ENONFINITE, "non-finite coordinate in cloud %d", b);
+  f->hint = hint;
+  f->hint_key = build_shape_key(f, p);
+  f->n_host_builds += 1;
+  f->has_labels = true;
+  return HGMM_OK;
+}
+
+// Construction with every level planned on the device (plan_level_kernel makes
+// the host planner's plan) and every launch of the construction, all levels,
+// in one graph whose kernels read their work counts from the level plans.
+// Grids are sized from the work counts of the last host-planned construction
+// of the same shape (the first call of a shape runs run_build, which records
+// them); a block class or the tiled iterations of a level that had no work
+// then are left out of the graph, and a call whose plan has work there is
+// redone by run_build.  The graph is captured once per shape and hints
+// (cloud sizes and depths, buffers, parameters, launch shapes) and cached in
+// the handle; a call uploads the tree records and the per-level tree lists,
+// replays the graph on the handle's stream and reads back the status and the
+// level plans.  Results equal those of run_build.
+static int run_build_graph(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p, char* ws, size_t ws_bytes,
+                           hipStream_t s) {
+  const int B = (int)f->trees.size();
+  int64_t n_total = 0;
+  int Lmax = 0;
+  for (auto& t : f->trees) { n_total += t.n_points; Lmax = std::max(Lmax, t.levels); }
+  if (f->hint_key != build_shape_key(f, p) || (int)f->hint.size() != Lmax)
+    return run_build(f, in, p, ws, ws_bytes, s);
+  const std::vector<std::array<int, 7>> hint = f->hint;
+  BuildLayout Ly = build_layout(n_total, max_jobs_for(f->trees), max_lvl_for(f->trees), B, Lmax);
+  if (ws_bytes < Ly.total) return fail(HGMM_EINVAL, "build workspace too small: %zu < %zu", ws_bytes, Ly.total);
+  int rc = ensure_graph_stream(f);
+  if (!rc) rc = ensure_side_streams(f);
+  if (rc) return rc;
+  hipStream_t gs = f->gstream;
+
+  // per-level lists of the trees that have the level, and level-compact bases
+  std::vector<std::vector<int64_t>> lvl_base(Lmax, std::vector<int64_t>(B, -1));
+  std::vector<int64_t> lvl_size(Lmax, 0);
+  for (int l = 0; l < Lmax; ++l)
+    for (int b = 0; b < B; ++b)
+      if (f->trees[b].levels > l) { lvl_base[l][b] = lvl_size[l]; lvl_size[l] += level_nodes(l); }
+  std::vector<int> lt_off(Lmax + 1, 0);
+  for (int l = 0; l < Lmax; ++l) {
+    int c = 0;
+    for (int b = 0; b < B; ++b) c += (f->trees[b].levels > l);
+    lt_off[l + 1] = lt_off[l] + c;
+  }
+  const size_t st_trees = 0;
+  const size_t st_lt = align_up(st_trees + sizeof(TreeDev) * 2 * B);
+  const size_t st_plan = align_up(st_lt + sizeof(LevelTree) * (size_t)std::max(lt_off[Lmax], 1));
+  const size_t st_end = align_up(st_plan + sizeof(int) * PL_SIZE * (size_t)Lmax);
+  rc = grow_stage(f, st_end);
+  if (rc) return rc;
+  char* H = f->h_stage;
+  TreeDev* h_trees = (TreeDev*)(H + st_trees);
+  LevelTree* h_lt = (LevelTree*)(H + st_lt);
+  int* h_plan = (int*)(H + st_plan);
+  for (int b = 0; b < B; ++b) {
+    TreeDev& T = h_trees[b];
+    memset(&T, 0, sizeof(T));
+    T.node_base = f->trees[b].node_base;
+    T.point_off = f->trees[b].point_off;
+    T.label_base = f->trees[b].label_base;
+    T.levels = f->trees[b].levels;
+    T.n_points = (int32_t)f->trees[b].n_points;
+  }
+  for (int l = 0; l < Lmax; ++l) {
+    int c = lt_off[l];
+    for (int b = 0; b < B; ++b)
+      if (f->trees[b].levels > l)
+        h_lt[c++] = LevelTree{b, l > 0 ? (int32_t)lvl_base[l - 1][b] : -1, (int32_t)lvl_base[l][b], 0};
+  }
+
+  float* pts[2] = {(float*)(ws + Ly.pts[0]), (float*)(ws + Ly.pts[1])};
+  int* perm[2] = {(int*)(ws + Ly.perm[0]), (int*)(ws + Ly.perm[1])};
+  uint8_t* child = (uint8_t*)(ws + Ly.child);
+  Tile* d_tiles = (Tile*)(ws + Ly.tiles);
+  int* d_tile_ids = (int*)(ws + Ly.tile_ids);
+  int* d_job_ids = (int*)(ws + Ly.job_ids);
+  Job* d_jobs = (Job*)(ws + Ly.jobs);
+  double* d_partials = (double*)(ws + Ly.partials);
+  double* d_part[2] = {d_partials, (double*)(ws + Ly.partials2)};
+  NodeF* d_ch[2] = {(NodeF*)(ws + Ly.chbuf), (NodeF*)(ws + Ly.chbuf) + 8 * (size_t)Ly.max_jobs};
+  int* d_tile_counts = (int*)(ws + Ly.tile_counts);
+  int* d_tile_base = (int*)(ws + Ly.tile_base);
+  int2* d_lvl = (int2*)(ws + Ly.lvl_info);
+  LevelTree* d_lt = (LevelTree*)(ws + Ly.level_trees);
+  int* d_plans = (int*)(ws + Ly.plans);
+
+  uint64_t eps_bits, mm_bits;
+  memcpy(&eps_bits, &p.reg_eps, 8);
+  memcpy(&mm_bits, &p.min_mass, 8);
+  std::vector<uint64_t> key = {(uint64_t)ws, (uint64_t)in.xs, (uint64_t)in.ys, (uint64_t)in.zs, (uint64_t)n_total,
+                               (uint64_t)B, (uint64_t)Lmax, (uint64_t)f->d_trees, (uint64_t)f->d_nodes,
+                               (uint64_t)f->d_tab, (uint64_t)f->d_labels, (uint64_t)p.build_iters, eps_bits, mm_bits};
+  const int32_t* tv = (const int32_t*)&g_tune;
+  for (size_t k = 0; k < sizeof(hgmm_tuning) / sizeof(int32_t); ++k) key.push_back((uint64_t)(uint32_t)tv[k]);
+  for (auto& t : f->trees) key.push_back(((uint64_t)t.levels << 40) | (uint64_t)t.n_points);
+  for (auto& h : hint)
+    for (int v : h) key.push_back((uint64_t)(uint32_t)v);
+
+  if (!f->bld_exec || f->bld_key != key) {
+    if (f->bld_exec) { (void)hipGraphExecDestroy(f->bld_exec); f->bld_exec = nullptr; }
+    f->bld_key.clear();
+    // grids from the hinted work counts with some slack; the kernels loop
+    // over their work items, so any count is covered
+    const int mj = (int)Ly.max_jobs, mt = (int)Ly.max_tiles;
+    auto grid = [](int h, int cap) { return std::max(1, std::min(cap, h + h / 8 + 8)); };
+    const int nts[3] = {64, 256, 512};
+    HIP_TRY(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+    const int64_t nodes_total = f->total_nodes();
+    launch_fill_u32(f->d_nodes, 0u, (int64_t)(sizeof(NodeD) / 4) * nodes_total, gs);
+    launch_fill_u32(f->d_tab, 0u, (int64_t)(sizeof(NodeF) / 4) * nodes_total, gs);
+    int64_t nlab = 0;
+    for (auto& t : f->trees) nlab += (int64_t)t.levels * t.n_points;
+    launch_fill_u32(f->d_labels, 0xFFFFFFFFu, nlab, gs);
+    const float* cx = in.xs;
+    const float* cy = in.ys;
+    const float* cz = in.zs;
+    const int* cperm = nullptr;
+    int ping = 0;
+    bool ok = true;
+    for (int l = 0; l < Lmax && ok; ++l) {
+      const int* pl = d_plans + (size_t)l * PL_SIZE;
+      const std::array<int, 7>& h = hint[l];
+      const int G_jobs = grid(h[0], mj), G_tiles = grid(h[1], mt), G_tile = grid(h[2], mt), G_mstep = grid(h[6], mj);
+      const int G_thr = G_jobs;
+      const int G_block[3] = {grid(h[3], mj), grid(h[4], mj), grid(h[5], mj)};
+      launch_plan_level(d_lt + lt_off[l], lt_off[l + 1] - lt_off[l], l == 0 ? 1 : (int)level_nodes(l - 1), l,
+                        l > 0 ? level_off(l - 1) : 0, level_off(l), d_lvl, f->d_trees, g_tune.block64_max,
+                        g_tune.block256_max, g_tune.block512_max, g_tune.target_tiles, g_tune.min_tile,
+                        g_tune.max_tile, mj, mt, d_jobs, d_job_ids, d_tiles, d_tile_ids, (int*)pl, gs);
+      if (l == 0)
+        launch_root(cx, cy, cz, d_tiles, G_tiles, d_jobs, G_jobs, f->d_trees, d_partials, (size_t)Ly.max_tiles,
+                    p.reg_eps, gs, pl + PL_NTILES, pl + PL_NJOBS);
+      launch_init_children(d_jobs, G_thr, f->d_trees, f->d_nodes, f->d_tab, p.reg_eps, gs, pl + PL_NJOBS);
+      if (p.build_iters > 0) {
+        ok = ok && hipEventRecord(f->ev_fork, gs) == hipSuccess;
+        for (int c = 0; c < 3 && ok; ++c) {
+          if (h[3 + c] == 0) continue;  // no job of this class in the hinted plan
+          ok = ok && hipStreamWaitEvent(f->side[c], f->ev_fork, 0) == hipSuccess;
+          launch_em_block(nts[c], cx, cy, cz, d_job_ids, G_block[c], d_jobs, f->d_tab, f->d_nodes, p.build_iters,
+                          p.reg_eps, p.min_mass, f->side[c], pl + PL_CLS_N + c, pl + PL_CLS_OFF + c);
+          ok = ok && hipEventRecord(f->ev_join[c], f->side[c]) == hipSuccess;
+        }
+        if (h[2] > 0) {  // tiled parents in the hinted plan
+          for (int it = 0; it < p.build_iters; ++it)
+            launch_em_tile(g_tune.tile_threads, cx, cy, cz, d_tiles, d_tile_ids, G_tile, d_jobs, f->d_tab,
+                           d_ch[(it + 1) & 1], d_ch[it & 1], d_part[(it + 1) & 1], d_part[it & 1],
+                           (size_t)Ly.max_tiles, p.reg_eps, p.min_mass, it == 0, gs, pl + PL_NBIG);
+          const int last = (p.build_iters - 1) & 1;
+          launch_em_mstep(d_job_ids, G_mstep, d_jobs, f->d_tab, f->d_nodes, d_part[last], (size_t)Ly.max_tiles,
+                          p.reg_eps, p.min_mass, d_ch[last], gs, pl + PL_CLS_N + 3, pl + PL_CLS_OFF + 3);
+        }
+        for (int c = 0; c < 3 && ok; ++c)
+          if (h[3 + c] > 0) ok = ok && hipStreamWaitEvent(gs, f->ev_join[c], 0) == hipSuccess;
+      }
+      launch_partition(cx, cy, cz, d_tiles, G_tiles, d_jobs, f->d_tab, f->d_nodes, child, d_tile_counts, gs,
+                       pl + PL_NTILES);
+      launch_fill_u32(d_lvl, 0u, 2 * lvl_size[l], gs);
+      launch_prefix(d_jobs, G_jobs, d_tile_counts, d_tile_base, f->d_nodes, d_lvl, gs, pl + PL_NJOBS);
+      float* nx = pts[ping];
+      float* ny = nx + n_total;
+      float* nz = ny + n_total;
+      launch_scatter(cx, cy, cz, cperm, d_tiles, G_tiles, d_jobs, f->d_trees, child, d_tile_base, nx, ny, nz,
+                     perm[ping], f->d_labels, l, level_off(l), gs, pl + PL_NTILES);
+      launch_finalize_level(d_jobs, G_thr, f->d_nodes, f->d_tab, gs, pl + PL_NJOBS);
+      cx = nx; cy = ny; cz = nz;
+      cperm = perm[ping];
+      ping ^= 1;
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(gs, &graph);
+    if (!ok || ec != hipSuccess || !graph) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return fail(HGMM_EHIP, "construction graph capture failed: %s", hipGetErrorString(ec));
+    }
+    const hipError_t ei = hipGraphInstantiate(&f->bld_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) { f->bld_exec = nullptr; return fail(HGMM_EHIP, "construction graph instantiation failed"); }
+    f->bld_key = key;
+    f->n_graph_captures += 1;
+  }
+  // inputs of this call, then the graph on the handle's stream
+  HIP_TRY(hipMemcpyAsync(f->d_trees, h_trees, sizeof(TreeDev) * B, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_lt, h_lt, sizeof(LevelTree) * (size_t)std::max(lt_off[Lmax], 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(f->ev_g0, s));
+  HIP_TRY(hipStreamWaitEvent(gs, f->ev_g0, 0));
+  HIP_TRY(hipGraphLaunch(f->bld_exec, gs));
+  HIP_TRY(hipEventRecord(f->ev_g1, gs));
+  HIP_TRY(hipStreamWaitEvent(s, f->ev_g1, 0));
+  // origin, extent and status, and the plans' overflow flags
+  HIP_TRY(hipMemcpyAsync(h_trees + B, f->d_trees, sizeof(TreeDev) * B, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h_plan, d_plans, sizeof(int) * PL_SIZE * Lmax, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int l = 0; l < Lmax; ++l)
+    if (h_plan[l * PL_SIZE + PL_ERR]) return fail(HGMM_EINVAL, "internal: device plan overflow at level %d", l);
+  // work in a phase the graph leaves out: redo the construction host-planned
+  for (int l = 0; l < Lmax; ++l) {
+    const int* pl = h_plan + l * PL_SIZE;
+    bool missed = hint[l][2] == 0 && p.build_iters > 0 && pl[PL_NBIG] > 0;
+    for (int c = 0; c < 3; ++c) missed = missed || (hint[l][3 + c] == 0 && p.build_iters > 0 && pl[PL_CLS_N + c] > 0);
+    if (missed) return run_build(f, in, p, ws, ws_bytes, s);
+  }
+  f->n_graph_replays += 1;
   for (int b = 0; b < B; ++b)
     if (h_trees[B + b].status != 0) return fail(HGMM_ENONFINITE, "non-finite coordinate in cloud %d", b);
   f->has_labels = true;
@@ -904,6 +1148,14 @@ int64_t hgmm_tree_nodes(int levels) {
   return tree_nodes(levels);
 }
 
+int hgmm_build_graph_stats(hgmm_tree tree, int64_t* replays, int64_t* captures, int64_t* host_builds) {
+  if (!tree || !replays || !captures || !host_builds) return fail(HGMM_EINVAL, "null pointer argument");
+  *replays = tree->n_graph_replays;
+  *captures = tree->n_graph_captures;
+  *host_builds = tree->n_host_builds;
+  return HGMM_OK;
+}
+
 int64_t hgmm_level_offset(int level) {
   if (level < 0 || level > HGMM_MAX_LEVELS) return -1;
   return level_off(level);
@@ -914,7 +1166,7 @@ size_t hgmm_build_workspace_bytes(int64_t n, int levels) {
   std::vector<TreeHost> t(1);
   t[0].levels = levels;
   t[0].n_points = n;
-  return build_layout(n, max_jobs_for(t), max_lvl_for(t)).total;
+  return build_layout(n, max_jobs_for(t), max_lvl_for(t), 1, levels).total;
 }
 
 size_t hgmm_register_workspace_bytes(int64_t n, int levels) {
@@ -946,7 +1198,8 @@ int hgmm_build(const float* d_xyz, int64_t n, const hgmm_build_params* p, void* 
   rc = setup_forest(f);
   if (!rc) {
     BuildInput in{d_xyz, d_xyz + n, d_xyz + 2 * n};
-    rc = run_build(f, in, *p, (char*)d_ws, ws_bytes, (hipStream_t)stream);
+    rc = (g_tune.build_graph && !g_prof.on) ? run_build_graph(f, in, *p, (char*)d_ws, ws_bytes, (hipStream_t)stream)
+                                            : run_build(f, in, *p, (char*)d_ws, ws_bytes, (hipStream_t)stream);
   }
   if (rc && fresh) { free_forest(f); return rc; }
   *tree = f;
@@ -1141,7 +1394,9 @@ size_t hgmm_build_batch_workspace_bytes(const int64_t* offsets, const int32_t* l
     if (levels[b] < 1 || levels[b] > HGMM_MAX_LEVELS) return 0;
     t[b] = TreeHost{levels[b], offsets[b + 1] - offsets[b], 0, 0, 0};
   }
-  return build_layout(offsets[B], max_jobs_for(t), max_lvl_for(t)).total;
+  int Lmax = 0;
+  for (auto& x : t) Lmax = std::max(Lmax, x.levels);
+  return build_layout(offsets[B], max_jobs_for(t), max_lvl_for(t), B, Lmax).total;
 }
 
 size_t hgmm_register_batch_workspace_bytes(hgmm_tree forest, const int64_t* offsets, int B) {
@@ -1179,7 +1434,8 @@ int hgmm_build_batch(const float* d_xyz, const int64_t* offsets, const int32_t* 
   if (!rc) {
     const int64_t n = offsets[B];
     BuildInput in{d_xyz, d_xyz + n, d_xyz + 2 * n};
-    rc = run_build(f, in, *p, (char*)d_ws, ws_bytes, (hipStream_t)stream);
+    rc = (g_tune.build_graph && !g_prof.on) ? run_build_graph(f, in, *p, (char*)d_ws, ws_bytes, (hipStream_t)stream)
+                                            : run_build(f, in, *p, (char*)d_ws, ws_bytes, (hipStream_t)stream);
   }
   if (rc && fresh) { free_forest(f); return rc; }
   *forest = f;

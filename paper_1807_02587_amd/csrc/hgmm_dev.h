@@ -89,6 +89,20 @@ struct TreeDev {
   int32_t pad;
 };
 
+// One tree that has a given level (levels > level): its index in the forest,
+// the level-compact base of its nodes one level up (the parents; -1 at level
+// 0) and at the level itself.
+struct LevelTree {
+  int32_t b, prev_base, cur_base, pad;
+};
+
+// Fields of a level plan made on the device (ints): jobs, tiles, tiles of the
+// tiled jobs, jobs per class (block of 64 / 256 / 512 threads, tiled), start of
+// each class in the class-ordered job list, points per tile, and an overflow
+// flag.
+enum PlanField { PL_NJOBS = 0, PL_NTILES = 1, PL_NBIG = 2, PL_CLS_N = 3, PL_CLS_OFF = 7, PL_TPTS = 12, PL_ERR = 13,
+                 PL_SIZE = 16 };
+
 // Registration state of one pair, FP64, device resident.
 struct PoseState {
   double R[9];

@@ -11,11 +11,15 @@ namespace hgmm {
 
 void launch_fill_u32(void* p, uint32_t v, int64_t n_words, hipStream_t s);
 
-// build
+// build.  With a device count (dn, dntiles, dnjobs: a level planned on the
+// device) the kernels read their number of work items from it and the count
+// given as an int is the fixed grid; with nullptr it is the number of items.
+// em_block / em_mstep take their jobs from job_ids + *doff when doff is given.
 void launch_root(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles, const Job* jobs,
-                 int njobs, TreeDev* trees, double* partials, size_t pstride, double eps, hipStream_t s);
+                 int njobs, TreeDev* trees, double* partials, size_t pstride, double eps, hipStream_t s,
+                 const int* dntiles = nullptr, const int* dnjobs = nullptr);
 void launch_init_children(const Job* jobs, int njobs, const TreeDev* trees, NodeD* nodes, NodeF* tab, double eps,
-                          hipStream_t s);
+                          hipStream_t s, const int* dn = nullptr);
 // one EM iteration of the tiled jobs (iteration 0: first = 1), folding in the
 // previous iteration's M-step; children and partials ping-pong between the
 // *_prev and *_next buffers; then, after the last iteration, the final M-step
@@ -23,23 +27,32 @@ void launch_init_children(const Job* jobs, int njobs, const TreeDev* trees, Node
 void launch_em_tile(int nt, const float* xs, const float* ys, const float* zs, const Tile* tiles, const int* tile_ids,
                     int n, const Job* jobs, const NodeF* tab, const NodeF* ch_prev, NodeF* ch_next,
                     const double* part_prev, double* part_next, size_t pstride, double eps, double min_mass, int first,
-                    hipStream_t s);
+                    hipStream_t s, const int* dn = nullptr);
 void launch_em_mstep(const int* job_ids, int n, const Job* jobs, NodeF* tab, NodeD* nodes, const double* partials,
-                     size_t pstride, double eps, double min_mass, const NodeF* chsrc, hipStream_t s);
+                     size_t pstride, double eps, double min_mass, const NodeF* chsrc, hipStream_t s,
+                     const int* dn = nullptr, const int* doff = nullptr);
 // all EM iterations of n jobs, one block of nt (64, 256 or 512) threads per job
 void launch_em_block(int nt, const float* xs, const float* ys, const float* zs, const int* job_ids, int n,
                      const Job* jobs, NodeF* tab, NodeD* nodes, int iters, double eps, double min_mass,
-                     hipStream_t s);
+                     hipStream_t s, const int* dn = nullptr, const int* doff = nullptr);
 void launch_partition(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
                       const Job* jobs, const NodeF* tab, const NodeD* nodes, uint8_t* child, int* tile_counts,
-                      hipStream_t s);
+                      hipStream_t s, const int* dn = nullptr);
 void launch_prefix(const Job* jobs, int njobs, const int* tile_counts, int* tile_base, NodeD* nodes, int2* lvl_info,
-                   hipStream_t s);
+                   hipStream_t s, const int* dn = nullptr);
 void launch_scatter(const float* xs, const float* ys, const float* zs, const int* perm, const Tile* tiles, int ntiles,
                     const Job* jobs, const TreeDev* trees, const uint8_t* child, const int* tile_base, float* xo,
                     float* yo, float* zo, int* perm_out, int32_t* labels, int level, int64_t level_off,
-                    hipStream_t s);
-void launch_finalize_level(const Job* jobs, int njobs, NodeD* nodes, NodeF* tab, hipStream_t s);
+                    hipStream_t s, const int* dn = nullptr);
+void launch_finalize_level(const Job* jobs, int njobs, NodeD* nodes, NodeF* tab, hipStream_t s,
+                           const int* dn = nullptr);
+
+// the plan of one level on the device (jobs, class-ordered job ids, tiles,
+// tile ids of the tiled jobs, and the PlanField counts in plan)
+void launch_plan_level(const LevelTree* lt, int nlt, int per, int level, int64_t loff_prev, int64_t loff_cur,
+                       const int2* lvl_prev, const TreeDev* trees, int b64, int b256, int b512, int target_tiles,
+                       int min_tile, int max_tile, int max_jobs, int max_tiles, Job* jobs, int* job_ids, Tile* tiles,
+                       int* tile_ids, int* plan, hipStream_t s);
 
 // registration
 void launch_set_stop_flags(NodeF* tab, const NodeD* nodes, int64_t n, double lambda_c, hipStream_t s);
