@@ -15,9 +15,11 @@ from .oracle import (  # noqa: F401
     build_root,
     build_level,
     estep,
+    estep_flat,
     normal_equations,
     solve_update,
     register,
+    register_flat,
     level_offset,
     level_nodes,
 )

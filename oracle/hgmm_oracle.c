@@ -16,6 +16,8 @@
  *   - cluster-reduced criterion in PCA form ............... Sec. 4.2, Eq. 8-11
  *   - weighted point-to-plane least squares with a
  *     small-angle linearisation ........................... Sec. 4.2, appendix Eq. 12-16
+ *   - the single-level variant "GMM J=n" (every component
+ *     scored for every point, no tree descent) ............ Sec. 5, list of variants
  * Plain loops, no blocking, no SIMD, libm only.
  */
 #include "hgmm_oracle.h"
@@ -585,6 +587,119 @@ int oracle_register(const ot_tree *t, const float *xyz, int64_t n, int max_iters
       for (int k = 0; k < 3; ++k) tr[16 + k] = tv[k];
       tr[19] = st;
     }
+    if (st != OT_OK) break;
+    double wn = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    double tn = sqrt(x[3] * x[3] + x[4] * x[4] + x[5] * x[5]);
+    if (wn < tol_rot && tn < tol_trans) break;
+  }
+  if (loglik) *loglik = ll;
+  free(bins);
+  return st;
+}
+
+/* Single-level variant ("GMM J=n", Sec. 5 list of variants): the live nodes of
+ * one tree level form a mixture of J = 8^(level+1) components with their
+ * global weights pi^g.  Every point is scored against every component (Eq. 2-3
+ * with pi^g), associated with the most likely one (lowest index on exact
+ * ties) and weighted by its posterior among all of them; the moments of
+ * Algorithm 1 go to that component.  Renormalising the weights over the level
+ * would cancel in the argmax and the posterior; the log-likelihood uses pi^g
+ * as the tree's E-step does.  min_gap: top-2 score gap (natural log units). */
+int oracle_estep_flat(const ot_tree *t, int level, const float *xyz, int64_t n, const double R[9],
+                      const double tv[3], int32_t *stop_node, double *gamma, double *min_gap, double *bins,
+                      double *loglik) {
+  if (level < 0 || level >= t->levels) return OT_EINVAL;
+  const float *x = xyz, *y = xyz + n, *z = xyz + 2 * n;
+  const int64_t g0 = oracle_level_offset(level), J = oracle_level_offset(level + 1) - g0;
+  double *Lc = (double *)malloc(sizeof(double) * 9 * (size_t)J);
+  double *cst = (double *)malloc(sizeof(double) * (size_t)J);
+  double *ld = (double *)malloc(sizeof(double) * (size_t)J);
+  for (int64_t j = 0; j < J; ++j) {
+    const int64_t g = g0 + j;
+    if (!t->live[g]) continue;
+    double Lm[3][3];
+    if (!chol3(t->cov + 6 * g, Lm)) { free(Lc); free(cst); free(ld); return OT_ESINGULAR; }
+    memcpy(Lc + 9 * j, Lm, sizeof(Lm));
+    ld[j] = logdet_from_chol(Lm);
+    cst[j] = log(t->pig[g]) - 0.5 * ld[j];
+  }
+  if (bins) memset(bins, 0, sizeof(double) * 6 * (size_t)t->n_nodes);
+  double ll = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double p[3] = {x[i], y[i], z[i]};
+    double q[3];
+    for (int r = 0; r < 3; ++r) q[r] = R[3 * r] * p[0] + R[3 * r + 1] * p[1] + R[3 * r + 2] * p[2] + tv[r];
+    int64_t kb = -1;
+    double sb = -INFINITY, s2 = -INFINITY;
+    for (int64_t j = 0; j < J; ++j) {
+      const int64_t g = g0 + j;
+      if (!t->live[g]) continue;
+      double d[3] = {q[0] - t->mu[3 * g], q[1] - t->mu[3 * g + 1], q[2] - t->mu[3 * g + 2]};
+      double Lm[3][3];
+      memcpy(Lm, Lc + 9 * j, sizeof(Lm));
+      const double sj = cst[j] - 0.5 * maha2(Lm, d);
+      if (kb < 0 || sj > sb) { s2 = sb; sb = sj; kb = j; }
+      else if (sj > s2) s2 = sj;
+    }
+    if (kb < 0) {  /* no live component at this level */
+      if (stop_node) stop_node[i] = -1;
+      if (gamma) gamma[i] = 0.0;
+      if (min_gap) min_gap[i] = INFINITY;
+      continue;
+    }
+    /* posterior of the chosen component: 1 / sum_j exp(s_j - s_best) */
+    double den = 0.0;
+    for (int64_t j = 0; j < J; ++j) {
+      const int64_t g = g0 + j;
+      if (!t->live[g]) continue;
+      double d[3] = {q[0] - t->mu[3 * g], q[1] - t->mu[3 * g + 1], q[2] - t->mu[3 * g + 2]};
+      double Lm[3][3];
+      memcpy(Lm, Lc + 9 * j, sizeof(Lm));
+      den += exp(cst[j] - 0.5 * maha2(Lm, d) - sb);
+    }
+    const double gm = 1.0 / den;
+    const int64_t g = g0 + kb;
+    double d[3] = {q[0] - t->mu[3 * g], q[1] - t->mu[3 * g + 1], q[2] - t->mu[3 * g + 2]};
+    double Lm[3][3];
+    memcpy(Lm, Lc + 9 * kb, sizeof(Lm));
+    const double m2 = maha2(Lm, d);
+    if (stop_node) stop_node[i] = (int32_t)g;
+    if (gamma) gamma[i] = gm;
+    if (min_gap) min_gap[i] = (s2 > -INFINITY) ? sb - s2 : INFINITY;
+    if (bins) {
+      double *b = bins + 6 * g;
+      b[0] += gm;
+      b[1] += gm * q[0];
+      b[2] += gm * q[1];
+      b[3] += gm * q[2];
+      b[4] += 1.0;
+      b[5] += m2;
+    }
+    ll += log(t->pig[g]) - 0.5 * ld[kb] - 0.5 * m2 - 1.5 * LOG_2PI;
+  }
+  if (loglik) *loglik = ll / (double)n;
+  free(Lc);
+  free(cst);
+  free(ld);
+  return OT_OK;
+}
+
+/* Registration with the single-level variant: the EM loop of oracle_register
+ * with oracle_estep_flat as the E-step. */
+int oracle_register_flat(const ot_tree *t, int level, const float *xyz, int64_t n, int max_iters, double tol_rot,
+                         double tol_trans, double R[9], double tv[3], int *iters, double *loglik) {
+  if (n < 1 || max_iters < 1) return OT_EINVAL;
+  double *bins = (double *)malloc(sizeof(double) * 6 * (size_t)t->n_nodes);
+  int st = OT_OK, it;
+  double ll = 0.0;
+  *iters = 0;
+  for (it = 1; it <= max_iters; ++it) {
+    st = oracle_estep_flat(t, level, xyz, n, R, tv, NULL, NULL, NULL, bins, &ll);
+    if (st != OT_OK) break;
+    double H[36], g[6], x[6] = {0, 0, 0, 0, 0, 0};
+    oracle_normal_equations(t, bins, n, H, g);
+    *iters = it;
+    st = oracle_solve_update(H, g, t->origin, R, tv, x);
     if (st != OT_OK) break;
     double wn = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
     double tn = sqrt(x[3] * x[3] + x[4] * x[4] + x[5] * x[5]);

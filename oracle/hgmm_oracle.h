@@ -76,6 +76,15 @@ int oracle_solve_update(const double H[36], const double g[6], const double orig
 int oracle_register(const ot_tree *t, const float *xyz, int64_t n, int max_iters, double lambda_c,
                     double tol_rot, double tol_trans, double R[9], double tv[3], int *iters,
                     double *loglik, double *trace);
+/* Single-level variant ("GMM J=n"): the live nodes of tree level `level`
+ * (J = 8^(level+1)) as one mixture with their global weights; every point is
+ * scored against every component.  Outputs as oracle_estep (stop_node: the
+ * chosen component, -1 when the level has no live node). */
+int oracle_estep_flat(const ot_tree *t, int level, const float *xyz, int64_t n, const double R[9],
+                      const double tv[3], int32_t *stop_node, double *gamma, double *min_gap, double *bins,
+                      double *loglik);
+int oracle_register_flat(const ot_tree *t, int level, const float *xyz, int64_t n, int max_iters, double tol_rot,
+                         double tol_trans, double R[9], double tv[3], int *iters, double *loglik);
 
 #ifdef __cplusplus
 }

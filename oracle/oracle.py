@@ -60,6 +60,9 @@ def _load():
         lib.oracle_solve_update.argtypes = [P, P, P, P, P, P]
         lib.oracle_register.argtypes = [P, P, C.c_int64, C.c_int, C.c_double, C.c_double, C.c_double,
                                         P, P, P, P, P]
+        lib.oracle_estep_flat.argtypes = [P, C.c_int, P, C.c_int64, P, P, P, P, P, P, P]
+        lib.oracle_register_flat.argtypes = [P, C.c_int, P, C.c_int64, C.c_int, C.c_double, C.c_double,
+                                             P, P, P, P]
         _lib = lib
     return _lib
 
@@ -227,6 +230,42 @@ def estep(tree: OracleTree, xyz, R=None, t=None, lambda_c=0.01):
                             C.byref(ll)), "estep")
     out["loglik"] = ll.value
     return out
+
+
+def estep_flat(tree: OracleTree, level, xyz, R=None, t=None):
+    """Single-level variant ("GMM J=n"): the live nodes of tree level ``level``
+    as one mixture with their global weights, every component scored for every
+    point; stop_node is the chosen component (-1 when the level has none)."""
+    lib = _load()
+    a = _soa(xyz)
+    n = a.shape[1]
+    R = np.eye(3) if R is None else np.ascontiguousarray(R, dtype=np.float64)
+    t = np.zeros(3) if t is None else np.ascontiguousarray(t, dtype=np.float64)
+    out = dict(stop_node=np.zeros(n, np.int32), gamma=np.zeros(n), min_gap=np.zeros(n),
+               bins=np.zeros((tree.n_nodes, 6)))
+    ll = C.c_double(0.0)
+    s = tree._struct()
+    _check(lib.oracle_estep_flat(C.byref(s), int(level), _p(a), n, _p(R), _p(t), _p(out["stop_node"]),
+                                 _p(out["gamma"]), _p(out["min_gap"]), _p(out["bins"]), C.byref(ll)), "estep_flat")
+    out["loglik"] = ll.value
+    return out
+
+
+def register_flat(tree: OracleTree, level, xyz, R0=None, t0=None, max_iters=30, tol_rot=1e-6, tol_trans=None):
+    """EM registration of ``xyz`` with the single-level variant of ``tree``."""
+    lib = _load()
+    a = _soa(xyz)
+    n = a.shape[1]
+    R = np.eye(3) if R0 is None else np.array(R0, dtype=np.float64, order="C")
+    t = np.zeros(3) if t0 is None else np.array(t0, dtype=np.float64, order="C")
+    if tol_trans is None:
+        tol_trans = 1e-6 * tree.extent
+    iters = C.c_int(0)
+    ll = C.c_double(0.0)
+    s = tree._struct()
+    st = lib.oracle_register_flat(C.byref(s), int(level), _p(a), n, max_iters, C.c_double(tol_rot),
+                                  C.c_double(tol_trans), _p(R), _p(t), C.byref(iters), C.byref(ll))
+    return dict(status=st, R=R, t=t, iters=iters.value, loglik=ll.value)
 
 
 def normal_equations(tree: OracleTree, bins, n):

@@ -549,3 +549,94 @@ def test_equivariance_exact_rotation(oracle_mod):
     np.testing.assert_allclose(b["R"] @ G, a["R"], atol=1e-12)
     np.testing.assert_allclose(b["t"], a["t"], atol=1e-12)
     np.testing.assert_allclose(a["trace"][:, 0], b["trace"][:, 0], rtol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# single-level variant ("GMM J=n", Sec. 5): every component of one level
+# --------------------------------------------------------------------------
+
+def test_flat_estep_bruteforce(oracle_mod):
+    """Level 1 (64 components) scored exhaustively with scipy densities and global weights."""
+    p = small_pair(5, n=2500)
+    tree, _ = oracle_mod.build_tree(p.src, 2)
+    R = rotation_from_axis_angle([0.4, -1.0, 0.1], 0.04)
+    t = np.array([-0.01, 0.02, 0.005])
+    e = oracle_mod.estep_flat(tree, 1, p.tgt, R, t)
+    Y = p.tgt.T.astype(np.float64) @ R.T + t
+    live = [g for g in range(8, 72) if tree.live[g]]
+    lp = np.stack([math.log(tree.pig[g]) + stats.multivariate_normal(tree.mu[g], _unpack(tree.cov[g])).logpdf(Y)
+                   for g in live], axis=1)
+    best = np.array(live)[np.argmax(lp, axis=1)]
+    np.testing.assert_array_equal(e["stop_node"], best)
+    np.testing.assert_allclose(e["gamma"], np.exp(lp.max(1) - logsumexp(lp, axis=1)), rtol=1e-9)
+    srt = np.sort(lp, axis=1)
+    np.testing.assert_allclose(e["min_gap"], srt[:, -1] - srt[:, -2], rtol=1e-9, atol=1e-9)
+    gam = e["gamma"]
+    nn = tree.n_nodes
+    np.testing.assert_allclose(e["bins"][:, 0], np.bincount(best, weights=gam, minlength=nn), rtol=1e-12)
+    for c in range(3):
+        np.testing.assert_allclose(e["bins"][:, 1 + c], np.bincount(best, weights=gam * Y[:, c], minlength=nn),
+                                   rtol=1e-10, atol=1e-12)
+    np.testing.assert_array_equal(e["bins"][:, 4], np.bincount(best, minlength=nn))
+    assert np.all(e["bins"][:8, :] == 0) and np.all(e["bins"][72:, :] == 0)
+    ll = np.mean(lp.max(1))   # log(pig) + log N of the chosen component, averaged
+    assert abs(e["loglik"] - ll) < 1e-10 * max(1.0, abs(ll))
+
+
+def test_flat_level0_is_tree_descent_stopped_at_level0(oracle_mod):
+    """At level 0 the sibling weights are the global ones and lambda_c = 1 stops every
+    point there, so the flat E-step and the tree E-step give the same result."""
+    p = small_pair(6, n=3000)
+    tree, _ = oracle_mod.build_tree(p.src, 3)
+    R = rotation_from_axis_angle([1.0, 0.3, -0.2], 0.02)
+    t = np.array([0.003, 0.0, -0.004])
+    a = oracle_mod.estep_flat(tree, 0, p.tgt, R, t)
+    b = oracle_mod.estep(tree, p.tgt, R, t, lambda_c=1.0)
+    np.testing.assert_array_equal(a["stop_node"], b["stop_node"])
+    np.testing.assert_allclose(a["gamma"], b["gamma"], rtol=1e-13)
+    np.testing.assert_allclose(a["bins"], b["bins"], rtol=1e-13, atol=1e-13)
+    assert abs(a["loglik"] - b["loglik"]) < 1e-12
+
+
+def test_flat_deepest_level_range_and_conservation(oracle_mod):
+    p = small_pair(7, n=3000)
+    tree, _ = oracle_mod.build_tree(p.src, 3)
+    e = oracle_mod.estep_flat(tree, 2, p.tgt)
+    J = oracle_mod.level_nodes(2)
+    g0 = oracle_mod.level_offset(2)
+    nlive = int(tree.live[g0:g0 + J].sum())
+    assert np.all((e["stop_node"] >= g0) & (e["stop_node"] < g0 + J))
+    assert np.all(tree.live[e["stop_node"]] == 1)
+    assert e["bins"][:, 4].sum() == p.tgt.shape[1]
+    assert np.all(e["gamma"] <= 1.0) and np.all(e["gamma"] >= 1.0 / nlive - 1e-15)
+    # the flat search covers the whole level, so its chosen component scores at least as
+    # high as the one the tree descent reaches at that level
+    d = oracle_mod.estep(tree, p.tgt, lambda_c=0.0)
+    idx = np.nonzero(d["stop_level"] == 2)[0][:200]
+    assert len(idx) > 50
+    Y = p.tgt.T[idx].astype(np.float64)
+
+    def score(g, y):
+        return math.log(tree.pig[g]) + stats.multivariate_normal(tree.mu[g], _unpack(tree.cov[g])).logpdf(y)
+
+    worse = 0
+    for i, y in zip(idx, Y):
+        sf, st = score(e["stop_node"][i], y), score(d["stop_node"][i], y)
+        assert sf >= st - 1e-9
+        worse += sf > st + 1e-9
+    assert worse > 0   # and the greedy descent misses the best component for some points
+    with pytest.raises(RuntimeError):
+        oracle_mod.estep_flat(tree, 3, p.tgt)
+
+
+def test_flat_exact_recovery_blob_tree(oracle_mod):
+    """Noise-free rigid copy of 64 separated blobs registered against level 1 alone."""
+    xyz, ids, _ = blob_tree_cloud(1)
+    tree, labels = oracle_mod.build_tree(xyz, 2)
+    Rg = rotation_from_axis_angle([-1, 2, 0.5], math.radians(4))
+    tg = 0.015 * tree.extent * np.array([-0.3, 0.8, 0.5])
+    tgt = (Rg @ xyz.astype(np.float64) + tg[:, None]).astype(np.float32)
+    r = oracle_mod.register_flat(tree, 1, tgt, max_iters=60, tol_rot=1e-13, tol_trans=1e-13)
+    assert r["status"] == 0 and r["iters"] < 60
+    np.testing.assert_allclose(r["R"], Rg.T, atol=1e-6)
+    np.testing.assert_allclose(r["t"], -Rg.T @ tg, atol=1e-6 * tree.extent)
