@@ -36,7 +36,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_PACKED_TFLOPS = 157.3
 PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
-# Algorithmic work per unit (derivation in the design doc):
+# Algorithmic work per unit (every arithmetic step of the method counted once, FMA = 2 FLOP):
 #  construction EM, per point-iteration: 8 children x (score 19 + softmax 4 + moments 21) FLOP
 EM_FLOP_PER_POINT_ITER = 8 * 44
 EM_BYTES_PER_POINT_ITER = 12
@@ -312,6 +312,62 @@ def depth_section(args, hg):
             "launch_shapes": shapes}
 
 
+# single-level E-step, per point-component pair: FP64 offset 3, whitening of
+# the offset 9, squared norm 5, score 1, rounding bound 5, running maximum /
+# denominator / bound update (with one exp2) 9 FLOP
+FLAT_FLOP_PER_EVAL = 32
+
+
+def variants_section(args, hg, tree, tgt, p, pr, steps):
+    """The paper's registration variants on one tree of the main workload,
+    registration alone from the identity (the tree built once, outside the
+    timed region): adaptive descent (lambda_c as configured), the full tree
+    descent (lambda_c = 0, "GMM-Tree"), and the single-level mixture of every
+    node of one level ("GMM J=n", n = 8^(level+1)) with its linear scan."""
+    import torch
+    from synth import rotation_angle_deg
+    dev = tgt.device
+    ws = hg.Workspace(dev)
+    n = tgt.shape[1]
+    runs = [("adaptive", "tree", pr["lambda_c"])]
+    runs.append(("gmm_tree", "tree", 0.0))
+    for lev in range(1, pr["levels"]):
+        runs.append((f"gmm_j{8 ** (lev + 1)}", "flat", lev))
+    out = {}
+    for name, kind, arg in runs:
+        if kind == "tree":
+            def reg():
+                return hg.hgmm_register(tree, tgt, lambda_c=arg, ws=ws, raise_singular=False)
+        else:
+            def reg():
+                return hg.hgmm_register_flat(tree, tgt, arg, ws=ws, raise_singular=False)
+        reg()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = reg()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        hg.hgmm_profile_reset()
+        hg.hgmm_profile(True)
+        reg()
+        torch.cuda.synchronize()
+        hg.hgmm_profile(False)
+        k = hg.hgmm_profile_read("flat" if kind == "flat" else "descend")
+        row = {"components": (8 ** (arg + 1)) if kind == "flat" else "adaptive" if arg > 0 else "leaves",
+               "ms_per_registration": round(sec * 1e3, 3), "iters": int(r["iters"]),
+               "rot_err_deg": round(rotation_angle_deg(r["R"], p.R_true), 4),
+               "estep_ms_per_iter": round(k["ms"] / max(1, k["launches"]), 4)}
+        if kind == "flat" and k["ms"] > 0:
+            evals = n * (8 ** (arg + 1)) * k["launches"]
+            tf = evals * FLAT_FLOP_PER_EVAL / (k["ms"] * 1e-3) / 1e12
+            row.update({"gevals_s": round(evals / (k["ms"] * 1e-3) / 1e9, 1), "estep_tflops": round(tf, 2),
+                        "frac_fp32": round(tf / PEAK_FP32_TFLOPS, 4)})
+        out[name] = row
+    return {"workload": "registration alone on the main workload's tree, from the identity", "steps": steps,
+            "variants": out}
+
+
 def warm_section(args, hg):
     """Held-out warm-start pairs (10k points per cloud, rotation U(0, 90 deg),
     translation U(-0.1, 0.1)^3, L = 2; seeds disjoint from training): the plain
@@ -396,8 +452,8 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
-              "described in DESIGN.md and not run here.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); registration of independent "
+              "pairs would shard across GPUs by pair, which is not run here.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -504,6 +560,7 @@ def main():
                "sample": f"{reps} full pair(s) of the same workload (build {n1} + register {n2} points), "
                          f"single-threaded FP64, {t_c:.1f} s"}
 
+    variants = None if args.no_batch else variants_section(args, hg, tree, tgt, p, pr, max(3, args.steps // 2))
     batched = None if args.no_batch else batch_section(args, hg)
     warm_form = None if args.no_batch else warm_section(args, hg)
     depth_form = None if args.no_batch else depth_section(args, hg)
@@ -538,6 +595,7 @@ def main():
         "batched": batched,
         "warm_start": warm_form,
         "depth_camera": depth_form,
+        "variants": variants,
     }
     print(json.dumps(out), flush=True)
 

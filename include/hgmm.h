@@ -162,6 +162,26 @@ int hgmm_estep(hgmm_tree tree, const float *d_xyz, int64_t n, const double R[9],
                double lambda_c, void *d_ws, size_t ws_bytes, void *stream, int32_t *d_stop_node,
                float *d_gamma, double *d_bins, double *loglik);
 
+/* ---- single-level variant ("GMM J=n", Sec. 5 list of variants) ---------
+ * The live nodes of tree level `level` (0 <= level < the tree's levels;
+ * J = 8^(level+1) components) form one fixed-complexity mixture with their
+ * global weights; every point is scored against all J components (no tree,
+ * no complexity threshold), assigned to the most likely one (the lowest node
+ * index on an exact tie) with its posterior among all of them as the weight,
+ * and the moments drive the same PCA-form M-step (Eq. 11-16).  Outputs,
+ * workspace (hgmm_register_workspace_bytes), ownership and synchronisation
+ * are those of hgmm_register / hgmm_estep; the stop node is -1 for a point
+ * when the level has no live node; p->lambda_c and p->max_levels are
+ * ignored.  Errors: HGMM_EINVAL (null pointer, level out of range, more than
+ * one tree in the handle, workspace too small), HGMM_ETOOFEW (n < 1),
+ * HGMM_ESINGULAR, HGMM_EHIP. */
+int hgmm_register_flat(hgmm_tree tree, const float *d_xyz, int64_t n, int level, const hgmm_reg_params *p,
+                       const double *R0, const double *t0, void *d_ws, size_t ws_bytes, void *stream, double R[9],
+                       double t[3], int *iters, double *loglik);
+int hgmm_estep_flat(hgmm_tree tree, const float *d_xyz, int64_t n, int level, const double R[9], const double t[3],
+                    void *d_ws, size_t ws_bytes, void *stream, int32_t *d_stop_node, float *d_gamma,
+                    double *d_bins, double *loglik);
+
 /* The PCA-form normal equations (Eq. 11-16) of one M-step from per-node
  * moments in the hgmm_estep layout (device): H (6x6 row-major, host) and g
  * (6, host) with H x = g for the increment x = (omega, tau) of
@@ -349,7 +369,7 @@ int hgmm_autotune(const float *d_src, const int64_t *src_offsets, const int32_t 
  * once) are not counted.  Kinds: 0 construction EM tile iteration,
  * 1 construction EM in one block per parent, 2 partition, 3 stable split, 4 registration
  * descent, 5 normal equations + solve, 6 root statistics, 7 construction
- * M-step of the tiled parents (units: parents).  Process-wide, not
+ * M-step of the tiled parents (units: parents), 8 single-level E-step.  Process-wide, not
  * thread-safe. */
 int hgmm_profile(int enable);
 void hgmm_profile_reset(void);

@@ -10,6 +10,8 @@ from .api import (  # noqa: F401
     Tree,
     Workspace,
     hgmm_build,
+    hgmm_register_flat,
+    hgmm_estep_flat,
     hgmm_register,
     hgmm_build_batch,
     hgmm_register_batch,

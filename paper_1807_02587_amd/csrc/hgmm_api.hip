@@ -248,7 +248,7 @@ static BuildLayout build_layout(int64_t n_total, int64_t max_jobs, int64_t max_l
 
 struct RegLayout {
   size_t bins, partials, counters, state, nmov, tiles, out, dpart, dcount, ptiles, active, pose, keys, keys2, vals,
-      perm, sxyz, sort_temp, total;
+      perm, sxyz, sort_temp, flatf, flats, total;
   size_t sort_temp_bytes;
   int64_t max_tiles;
 };
@@ -279,6 +279,9 @@ static RegLayout reg_layout(int64_t n_total, int64_t nodes, int npairs) {
   L.sxyz = o; o = align_up(o + sizeof(float) * 3 * (size_t)n_total);
   L.sort_temp_bytes = sort_temp_bytes(n_total, npairs);
   L.sort_temp = o; o = align_up(o + L.sort_temp_bytes);
+  // scoring records with global weights (single-level E-step)
+  L.flatf = o; o = align_up(o + sizeof(NodeF) * (size_t)std::max<int64_t>(nodes, 1));
+  L.flats = o; o = align_up(o + sizeof(NodeS) * (size_t)std::max<int64_t>(nodes, 1));
   L.total = o;
   return L;
 }
@@ -357,7 +360,7 @@ static int tile_points(int64_t level_points) {
 // ---------------------------------------------------------------------------
 
 enum ProfKind { PK_EM_TILE = 0, PK_EM_BLOCK, PK_PARTITION, PK_SCATTER, PK_DESCEND, PK_NORMAL, PK_ROOT, PK_EM_MSTEP,
-                PK_COUNT };
+                PK_FLAT, PK_COUNT };
 
 struct ProfPending {
   int kind;
@@ -945,6 +948,7 @@ struct RegRun {
   int max_iters;
   double lambda_c, tol_rot, tol_trans_rel;
   int max_levels;  // 0: every level of the tree
+  int flat_level = -1;  // >= 0: single-level E-step over this level instead of the descent
 };
 
 static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, const float* zs,
@@ -1036,10 +1040,26 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   launch_init_pose(d_state, P, d_pose0, d_pose0 + 9, per_pair ? 12 : 0, active ? d_act : nullptr, s);
   HIP_LAUNCHED();
   const size_t pstride = (size_t)Ly.max_tiles;
+  const bool flat = rr.flat_level >= 0;
+  // one E-step launch (descent, or the single-level scan) and one M-step launch
+  NodeF* d_flatf = (NodeF*)(ws + Ly.flatf);
+  NodeS* d_flats = (NodeS*)(ws + Ly.flats);
+  if (flat) launch_flat_table(f->d_tab, f->d_nodes, d_flatf, d_flats, nodes_total, s);
+  auto estep = [&](hipStream_t q, int32_t* so, float* go, const int* pm) {
+    if (flat)
+      launch_flat_estep(xs, ys, zs, d_tiles, ntiles, f->d_trees, d_flatf, d_flats, d_state, d_bins, so, go, pm,
+                        rr.flat_level, q);
+    else
+      launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins, d_dpart,
+                     pstride, so, go, pm, g_tune.reg_lds_levels, rr.max_levels, q);
+  };
+  auto mstep = [&](hipStream_t q) {
+    launch_normal(d_bins, d_dpart, pstride, d_ptiles, f->d_nodes, f->d_trees, d_state, d_nmov, P, flat ? 2 : 0,
+                  rr.tol_rot, rr.tol_trans_rel, rr.max_iters, d_out, q);
+  };
   if (mode_estep) {
-    launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins, d_dpart, pstride,
-                   stop_out, gamma_out, d_perm, g_tune.reg_lds_levels, rr.max_levels, s);
-    launch_fold_bins(d_ptiles, f->d_trees, d_dpart, pstride, d_bins, P, s);
+    estep(s, stop_out, gamma_out, d_perm);
+    if (!flat) launch_fold_bins(d_ptiles, f->d_trees, d_dpart, pstride, d_bins, P, s);
     if (h_norm) {
       launch_normal(d_bins, d_dpart, pstride, d_ptiles, f->d_nodes, f->d_trees, d_state, d_nmov, P, 1, 0.0, 0.0, 1,
                     d_out, s);
@@ -1064,16 +1084,15 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
                                        (uint64_t)f->d_trees, (uint64_t)f->d_tab, (uint64_t)f->d_nodes,
                                        (uint64_t)d_state, (uint64_t)d_bins, (uint64_t)d_dpart, (uint64_t)pstride,
                                        (uint64_t)d_ptiles, (uint64_t)d_nmov, (uint64_t)P, (uint64_t)chunk, tr, tt,
-                                       (uint64_t)rr.max_iters, (uint64_t)rr.max_levels, (uint64_t)d_out};
+                                       (uint64_t)rr.max_iters, (uint64_t)rr.max_levels, (uint64_t)d_out,
+                                       (uint64_t)(int64_t)rr.flat_level};
     if (!f->reg_exec || f->reg_key != key) {
       if (f->reg_exec) { (void)hipGraphExecDestroy(f->reg_exec); f->reg_exec = nullptr; }
       f->reg_key.clear();
       HIP_TRY(hipStreamBeginCapture(f->gstream, hipStreamCaptureModeThreadLocal));
       for (int c = 0; c < chunk; ++c) {
-        launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins, d_dpart,
-                       pstride, nullptr, nullptr, nullptr, g_tune.reg_lds_levels, rr.max_levels, f->gstream);
-        launch_normal(d_bins, d_dpart, pstride, d_ptiles, f->d_nodes, f->d_trees, d_state, d_nmov, P, 0, rr.tol_rot,
-                      rr.tol_trans_rel, rr.max_iters, d_out, f->gstream);
+        estep(f->gstream, nullptr, nullptr, nullptr);
+        mstep(f->gstream);
       }
       hipGraph_t graph = nullptr;
       const hipError_t ec = hipStreamEndCapture(f->gstream, &graph);
@@ -1103,14 +1122,12 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
     const int end = std::min(rr.max_iters, it + chunk);
     for (; it < end; ++it) {
       {
-        ProfScope ps(PK_DESCEND, (double)n_total, s, it);
-        launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins, d_dpart,
-                       pstride, nullptr, nullptr, nullptr, g_tune.reg_lds_levels, rr.max_levels, s);
+        ProfScope ps(flat ? PK_FLAT : PK_DESCEND, (double)n_total, s, it);
+        estep(s, nullptr, nullptr, nullptr);
       }
       {
         ProfScope ps(PK_NORMAL, (double)nodes_total, s, it);
-        launch_normal(d_bins, d_dpart, pstride, d_ptiles, f->d_nodes, f->d_trees, d_state, d_nmov, P, 0, rr.tol_rot,
-                      rr.tol_trans_rel, rr.max_iters, d_out, s);
+        mstep(s);
       }
     }
     HIP_LAUNCHED();
@@ -1239,6 +1256,57 @@ int hgmm_estep(hgmm_tree tree, const float* d_xyz, int64_t n, const double R[9],
   double nrm[28];
   int rc = run_register(tree, d_xyz, d_xyz + n, d_xyz + 2 * n, offs, R, t, 0, rr, (char*)d_ws, ws_bytes,
                         (hipStream_t)stream, 1, d_stop_node, d_gamma, d_bins, nullptr, loglik ? nrm : nullptr);
+  if (rc) return rc;
+  if (loglik) *loglik = nrm[27];
+  return HGMM_OK;
+}
+
+static int check_flat_level(hgmm_tree tree, int level) {
+  int lmin = 1 << 30;
+  for (auto& t : tree->trees) lmin = std::min(lmin, t.levels);
+  if (level < 0 || level >= lmin)
+    return fail(HGMM_EINVAL, "level %d outside the tree's levels 0..%d", level, lmin - 1);
+  return HGMM_OK;
+}
+
+int hgmm_register_flat(hgmm_tree tree, const float* d_xyz, int64_t n, int level, const hgmm_reg_params* p,
+                       const double* R0, const double* t0, void* d_ws, size_t ws_bytes, void* stream, double R[9],
+                       double t[3], int* iters, double* loglik) {
+  if (n < 1) return fail(HGMM_ETOOFEW, "empty cloud");
+  if (!tree || !d_xyz || !p || !d_ws || !R || !t || !iters) return fail(HGMM_EINVAL, "null pointer argument");
+  if (n > (int64_t)INT32_MAX / 2) return fail(HGMM_EINVAL, "too many points");
+  if (p->max_iters < 1) return fail(HGMM_EINVAL, "max_iters must be >= 1");
+  if (tree->trees.size() != 1) return fail(HGMM_EINVAL, "hgmm_register_flat takes a single-tree handle");
+  int rc = check_flat_level(tree, level);
+  if (rc) return rc;
+  std::vector<int64_t> offs = {0, n};
+  RegRun rr{p->max_iters, 0.0, p->tol_rot, p->tol_trans_rel, 0, level};
+  PoseState res;
+  rc = run_register(tree, d_xyz, d_xyz + n, d_xyz + 2 * n, offs, R0, t0, 0, rr, (char*)d_ws, ws_bytes,
+                    (hipStream_t)stream, 0, nullptr, nullptr, nullptr, &res, nullptr);
+  if (rc) return rc;
+  for (int i = 0; i < 9; ++i) R[i] = res.R[i];
+  for (int i = 0; i < 3; ++i) t[i] = res.t[i];
+  *iters = res.iters;
+  if (loglik) *loglik = res.loglik;
+  if (res.status != 0) return fail(res.status, "normal equations not positive definite at iteration %d", res.iters);
+  return HGMM_OK;
+}
+
+int hgmm_estep_flat(hgmm_tree tree, const float* d_xyz, int64_t n, int level, const double R[9], const double t[3],
+                    void* d_ws, size_t ws_bytes, void* stream, int32_t* d_stop_node, float* d_gamma, double* d_bins,
+                    double* loglik) {
+  if (!tree || !d_xyz || !R || !t || !d_ws) return fail(HGMM_EINVAL, "null pointer argument");
+  if (n < 1) return fail(HGMM_ETOOFEW, "empty cloud");
+  if (n > (int64_t)INT32_MAX / 2) return fail(HGMM_EINVAL, "too many points");
+  if (tree->trees.size() != 1) return fail(HGMM_EINVAL, "hgmm_estep_flat takes a single-tree handle");
+  int rc = check_flat_level(tree, level);
+  if (rc) return rc;
+  std::vector<int64_t> offs = {0, n};
+  RegRun rr{1, 0.0, 0.0, 0.0, 0, level};
+  double nrm[28];
+  rc = run_register(tree, d_xyz, d_xyz + n, d_xyz + 2 * n, offs, R, t, 0, rr, (char*)d_ws, ws_bytes,
+                    (hipStream_t)stream, 1, d_stop_node, d_gamma, d_bins, nullptr, loglik ? nrm : nullptr);
   if (rc) return rc;
   if (loglik) *loglik = nrm[27];
   return HGMM_OK;

@@ -325,6 +325,230 @@ __global__ __launch_bounds__(256) void fold_bins_kernel(const int2* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Single-level E-step ("GMM J=n", Sec. 5 list of variants)
+// ---------------------------------------------------------------------------
+//
+// The live nodes of one tree level form a mixture of J = 8^(level+1)
+// components with their global weights.  Every point is scored against every
+// component (a linear scan instead of the tree's logarithmic descent): FP32
+// scores with their rounding bounds, a running maximum and a running
+// denominator sum_j 2^(s_j - s_max) rescaled whenever the maximum changes.
+// The FP32 winner is re-checked in FP64 over the whole level when another
+// component's score bound reaches it (lowest index wins exact FP64 ties), and
+// the posterior is recomputed in FP64 when its rounding bound exceeds
+// kFlatGammaTol (relative).  Components are staged in LDS in chunks of CH
+// records shared by the block's 256 points; with LBIN the level's moments are
+// accumulated in FP64 LDS bins and added to the node bins once per block,
+// otherwise (J > CH) directly with FP64 atomics after wave aggregation.
+// The tree's scoring records carry the weight inside the sibling group; the
+// single-level mixture needs the global weight, so the E-step reads records
+// rebuilt with it (flat_table_kernel).
+
+constexpr float kFlatGammaTol = 1e-5f;
+
+// Scoring records of every node with the global weight pi^g in the constant:
+// c = log pi^g - log|cov| / 2 (FP64), its FP32 log2 form and rounding bound.
+__global__ void flat_table_kernel(const NodeF* __restrict__ tab, const NodeD* __restrict__ nodes, NodeF* ft,
+                                  NodeS* fs, int64_t n) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const NodeD& nd = nodes[g];
+  NodeF f = tab[g];
+  NodeS v;
+  for (int k = 0; k < 3; ++k) v.mu[k] = nd.mu[k];
+  for (int k = 0; k < 6; ++k) v.winv[k] = nd.winv[k];
+  v.c = 0.0;
+  if ((f.flags & F_LIVE) && nd.pig > 0.0) {
+    v.c = log(nd.pig) - 0.5 * nd.logdet;
+    f.c = (float)(v.c * kLog2e);
+    f.errc = 2.f * kU * fabsf(f.c) * 1.0001f;
+  } else {
+    f.flags = 0u;
+  }
+  ft[g] = f;
+  fs[g] = v;
+}
+
+template <typename NodePtr>
+__device__ double flat_argmax64(NodePtr S, const NodeF* __restrict__ F, int J, double p0, double p1, double p2,
+                                int& kb) {
+  double best = -INFINITY;
+  kb = -1;
+  for (int j = 0; j < J; ++j) {
+    if (!(F[j].flags & F_LIVE)) continue;
+    const double v = score64(S[j], p0, p1, p2);
+    if (kb < 0 || v > best) { best = v; kb = j; }
+  }
+  return best;
+}
+
+// posterior of component k among every live component, FP64 scores for the
+// components within 2^-40 of the FP32 maximum (the rest from FP32)
+template <typename NodePtr>
+__device__ float flat_gamma64(NodePtr S, const NodeF* __restrict__ F, int J, int k, double sk64, float s1,
+                              double p0, double p1, double p2) {
+  double den = 0.0;
+  for (int j = 0; j < J; ++j) {
+    if (!(F[j].flags & F_LIVE)) continue;
+    if (j == k) { den += 1.0; continue; }
+    float q, m;
+    const float dj = score32(F[j], p0, p1, p2, q, m) - s1;
+    den += dj > -40.f ? exp2(score64(S[j], p0, p1, p2) - sk64) : (double)__builtin_amdgcn_exp2f(dj);
+  }
+  return (float)(1.0 / den);
+}
+
+template <int CH, bool LBIN>
+__global__ __launch_bounds__(256) void flat_estep_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
+                                                         const float* __restrict__ zs, const Tile* __restrict__ tiles,
+                                                         const TreeDev* __restrict__ trees,
+                                                         const NodeF* __restrict__ ftab,
+                                                         const NodeS* __restrict__ fs,
+                                                         const PoseState* __restrict__ st, double* bins,
+                                                         int32_t* stop_out, float* gamma_out,
+                                                         const int* __restrict__ perm, int level) {
+  const Tile tl = tiles[blockIdx.x];
+  const int pair = tl.job;
+  if (st[pair].done) return;
+  const TreeDev& T = trees[pair];
+  const int64_t nb = T.node_base;
+  const int64_t g0 = nb + lvl_off(level);
+  const int J = 8 << (3 * level);
+  const NodeF* Fg = ftab + g0;
+  const NodeS* Sg = fs + g0;
+  __shared__ NodeF lds[CH];
+  __shared__ double lbin[LBIN ? CH * 6 : 1];
+  const bool resident = J <= CH;  // the whole level fits: staged once
+  if (resident) {
+    for (int i = threadIdx.x; i < J; i += blockDim.x) {
+      const float4* s = reinterpret_cast<const float4*>(&Fg[i]);
+      float4* d = reinterpret_cast<float4*>(&lds[i]);
+      d[0] = s[0]; d[1] = s[1]; d[2] = s[2]; d[3] = s[3];
+    }
+  }
+  if (LBIN)
+    for (int i = threadIdx.x; i < J * 6; i += blockDim.x) lbin[i] = 0.0;
+  __syncthreads();
+  const double R0 = st[pair].R[0], R1 = st[pair].R[1], R2 = st[pair].R[2], R3 = st[pair].R[3],
+               R4 = st[pair].R[4], R5 = st[pair].R[5], R6 = st[pair].R[6], R7 = st[pair].R[7],
+               R8 = st[pair].R[8], t0 = st[pair].t[0], t1 = st[pair].t[1], t2 = st[pair].t[2];
+  const int lane = __lane_id();
+  for (int b0 = tl.start; b0 < tl.end; b0 += blockDim.x) {
+    const int i = b0 + threadIdx.x;
+    const bool valid = i < tl.end;
+    const double z0 = valid ? (double)xs[i] : 0.0, z1 = valid ? (double)ys[i] : 0.0,
+                 z2 = valid ? (double)zs[i] : 0.0;
+    const double p0 = R0 * z0 + R1 * z1 + R2 * z2 + t0;
+    const double p1 = R3 * z0 + R4 * z1 + R5 * z2 + t1;
+    const double p2 = R6 * z0 + R7 * z1 + R8 * z2 + t2;
+    // running state: maximum s1 (index k1, bound e1), denominator den =
+    // sum_j 2^(s_j - s1), eb = sum_j 2^(s_j - s1) e_j, and ub = the largest
+    // s_j + 2 e_j over the components other than k1
+    float s1 = -__FLT_MAX__, e1 = 0.f, den = 0.f, eb = 0.f, ub = -INFINITY;
+    int k1 = -1;
+    for (int c0 = 0; c0 < J; c0 += CH) {
+      const int nc = J - c0 < CH ? J - c0 : CH;
+      if (!resident) {
+        __syncthreads();  // every lane is done with the previous chunk
+        for (int r = threadIdx.x; r < nc; r += blockDim.x) {
+          const float4* s = reinterpret_cast<const float4*>(&Fg[c0 + r]);
+          float4* d = reinterpret_cast<float4*>(&lds[r]);
+          d[0] = s[0]; d[1] = s[1]; d[2] = s[2]; d[3] = s[3];
+        }
+        __syncthreads();
+      }
+      for (int j = 0; j < nc; ++j) {
+        const NodeF& C = lds[j];
+        if (!(C.flags & F_LIVE)) continue;  // uniform across the block
+        float q, m;
+        const float s = score32(C, p0, p1, p2, q, m);
+        const float e = score_err(C, q, m);
+        const bool up = s > s1;  // strict: the lower index stays on equal FP32 scores
+        const float r = __builtin_amdgcn_exp2f(up ? s1 - s : s - s1);
+        ub = fmaxf(ub, up ? fmaf(2.f, e1, s1) : fmaf(2.f, e, s));
+        den = up ? fmaf(den, r, 1.f) : den + r;
+        eb = up ? fmaf(eb, r, e) : fmaf(r, e, eb);
+        e1 = up ? e : e1;
+        k1 = up ? c0 + j : k1;
+        s1 = up ? s : s1;
+      }
+    }
+    int64_t g = -1;
+    float gam = 0.f, d0 = 0.f, d1 = 0.f, d2 = 0.f, dm2 = 0.f;
+    if (valid && k1 >= 0) {
+      const NodeF* Fs = resident ? lds : Fg;
+      double sk64 = 0.0;
+      bool have64 = false;
+      if (ub >= s1 - 2.f * e1) {  // another component may win in exact arithmetic
+        int kb;
+        sk64 = flat_argmax64(Sg, Fs, J, p0, p1, p2, kb);
+        have64 = true;
+        if (kb != k1) {
+          k1 = kb;
+          float q, m;
+          s1 = score32(Fs[k1], p0, p1, p2, q, m);
+          eb = INFINITY;  // the FP32 sums refer to the old winner: recompute gamma in FP64
+        }
+      }
+      const float gbound = 0.6931472f * (eb + e1 * (den - 2.f)) / den;
+      if (gbound > kFlatGammaTol) {
+        if (!have64) sk64 = score64(Sg[k1], p0, p1, p2);
+        gam = flat_gamma64(Sg, Fs, J, k1, sk64, s1, p0, p1, p2);
+      } else {
+        gam = 1.0f / den;
+      }
+      g = g0 + k1;
+      const NodeS& nd = Sg[k1];
+      const double e0 = p0 - nd.mu[0], ee1 = p1 - nd.mu[1], e2 = p2 - nd.mu[2];
+      d0 = (float)e0;
+      d1 = (float)ee1;
+      d2 = (float)e2;
+      const double w0 = nd.winv[0] * e0;
+      const double w1 = nd.winv[1] * e0 + nd.winv[2] * ee1;
+      const double w2 = nd.winv[3] * e0 + nd.winv[4] * ee1 + nd.winv[5] * e2;
+      dm2 = (float)(w0 * w0 + w1 * w1 + w2 * w2);
+    }
+    if (valid) {
+      const int oi = perm ? perm[i] : i;
+      if (stop_out) stop_out[oi] = g >= 0 ? (int32_t)(g - nb) : -1;
+      if (gamma_out) gamma_out[oi] = gam;
+    }
+    // aggregate equal components inside the wave, then one add per component
+    bool pend = valid && g >= 0;
+    unsigned long long pending = __ballot(pend);
+    while (pending) {
+      const int leader = __ffsll((long long)pending) - 1;
+      const int64_t key = __shfl(g, leader, 64);
+      const bool mine = pend && (g == key);
+      const unsigned long long mm = __ballot(mine);
+      const float v0 = wave_sum(mine ? gam : 0.f);
+      const float v1 = wave_sum(mine ? gam * d0 : 0.f);
+      const float v2 = wave_sum(mine ? gam * d1 : 0.f);
+      const float v3 = wave_sum(mine ? gam * d2 : 0.f);
+      const float v5 = wave_sum(mine ? dm2 : 0.f);
+      if (lane == leader) {
+        double* B = LBIN ? lbin + (key - g0) * 6 : bins + key * 6;
+        unsafeAtomicAdd(B + 0, (double)v0);
+        unsafeAtomicAdd(B + 1, (double)v1);
+        unsafeAtomicAdd(B + 2, (double)v2);
+        unsafeAtomicAdd(B + 3, (double)v3);
+        unsafeAtomicAdd(B + 4, (double)__popcll(mm));
+        unsafeAtomicAdd(B + 5, (double)v5);
+      }
+      pend = pend && !mine;
+      pending &= ~mm;
+    }
+  }
+  if (LBIN) {
+    __syncthreads();
+    for (int r = threadIdx.x; r < J * 6; r += blockDim.x) {
+      const int node = r / 6;
+      if (lbin[node * 6 + 4] > 0.0) unsafeAtomicAdd(bins + (g0 + node) * 6 + (r - node * 6), lbin[r]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // M-step
 // ---------------------------------------------------------------------------
 
@@ -393,7 +617,8 @@ __device__ __forceinline__ void node_terms(const NodeD& nd, const double* b, dou
 // (LDS-level nodes folded from the descent's block partials, deeper nodes read
 // and cleared from the bins), Cholesky solve and pose update.  mode 1: the
 // same sums from the bins alone, written to out[pair * 28 ..] (H upper, g,
-// mean log-likelihood).
+// mean log-likelihood).  mode 2: as mode 0 with every node's moments read and
+// cleared from the bins (the single-level E-step writes no block partials).
 __global__ __launch_bounds__(kNormThreads) void normal_kernel(double* bins, const double* __restrict__ dpart,
                                                               size_t pstride, const int2* __restrict__ pair_tiles,
                                                               const NodeD* __restrict__ nodes,
@@ -441,7 +666,7 @@ __global__ __launch_bounds__(kNormThreads) void normal_kernel(double* bins, cons
     const double m0 = B[0];
     if (!(m0 > 0.0)) continue;
     double b[6] = {m0, B[1], B[2], B[3], B[4], B[5]};
-    if (mode == 0) { B[0] = 0.0; B[1] = 0.0; B[2] = 0.0; B[3] = 0.0; B[4] = 0.0; B[5] = 0.0; }
+    if (mode != 1) { B[0] = 0.0; B[1] = 0.0; B[2] = 0.0; B[3] = 0.0; B[4] = 0.0; B[5] = 0.0; }
     node_terms(nodes[nb + g], b, N, o0, o1, o2, acc);
   }
   __shared__ double red[kNormThreads / 64][kNV];
@@ -554,6 +779,25 @@ void launch_descend(const float* xs, const float* ys, const float* zs, const Til
   else
     hipLaunchKernelGGL(descend_kernel<2>, dim3(ntiles), dim3(256), 0, s, xs, ys, zs, tiles, trees, tab, nodes, st, bins,
                        partials, pstride, stop_out, gamma_out, perm, max_levels);
+}
+
+void launch_flat_table(const NodeF* tab, const NodeD* nodes, NodeF* ft, NodeS* fs, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(flat_table_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tab, nodes, ft, fs, n);
+}
+
+void launch_flat_estep(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
+                       const TreeDev* trees, const NodeF* tab, const NodeS* nodes, const PoseState* st, double* bins,
+                       int32_t* stop_out, float* gamma_out, const int* perm, int level, hipStream_t s) {
+  if (level <= 1)
+    hipLaunchKernelGGL((flat_estep_kernel<64, true>), dim3(ntiles), dim3(256), 0, s, xs, ys, zs, tiles, trees, tab,
+                       nodes, st, bins, stop_out, gamma_out, perm, level);
+  else if (level == 2)
+    hipLaunchKernelGGL((flat_estep_kernel<512, true>), dim3(ntiles), dim3(256), 0, s, xs, ys, zs, tiles, trees, tab,
+                       nodes, st, bins, stop_out, gamma_out, perm, level);
+  else
+    hipLaunchKernelGGL((flat_estep_kernel<512, false>), dim3(ntiles), dim3(256), 0, s, xs, ys, zs, tiles, trees, tab,
+                       nodes, st, bins, stop_out, gamma_out, perm, level);
 }
 
 void launch_fold_bins(const int2* pair_tiles, const TreeDev* trees, const double* partials, size_t pstride,
