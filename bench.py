@@ -153,6 +153,15 @@ def batch_section(args, hg):
     B = len(lv)
     ws = hg.Workspace()
     cfg = W.WarmConfig()
+    if args.variants_only:
+        if args.tuning_json:
+            with open(args.tuning_json) as f:
+                hg.hgmm_set_tuning(**json.load(f))
+        step()
+        print(json.dumps({"variants": variants_section(args, hg, tree, tgt, p, pr, max(1, args.steps))}),
+              flush=True)
+        return
+
     if args.copy_calibration:
         # counter calibration: a plain copy of known size, then the batched
         # plain form twice with the given launch shapes
@@ -450,6 +459,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of --copy-mib MiB and a few steps (for counter calibration)")
     ap.add_argument("--copy-mib", type=int, default=256)
+    ap.add_argument("--variants-only", action="store_true",
+                    help="build the main workload's tree once and run only the registration variants (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); registration of independent "
@@ -479,6 +490,15 @@ def main():
         tree = hg.hgmm_build(src, levels=pr["levels"], reg_eps=pr["reg_eps"], min_mass=pr["min_mass"], ws=ws_b,
                              tree=tree)
         return hg.hgmm_register(tree, tgt, lambda_c=pr["lambda_c"], ws=ws_r, raise_singular=False)
+
+    if args.variants_only:
+        if args.tuning_json:
+            with open(args.tuning_json) as f:
+                hg.hgmm_set_tuning(**json.load(f))
+        step()
+        print(json.dumps({"variants": variants_section(args, hg, tree, tgt, p, pr, max(1, args.steps))}),
+              flush=True)
+        return
 
     if args.copy_calibration:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE give the

@@ -1047,7 +1047,7 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   if (flat) launch_flat_table(f->d_tab, f->d_nodes, d_flatf, d_flats, nodes_total, s);
   auto estep = [&](hipStream_t q, int32_t* so, float* go, const int* pm) {
     if (flat)
-      launch_flat_estep(xs, ys, zs, d_tiles, ntiles, f->d_trees, d_flatf, d_flats, d_state, d_bins, so, go, pm,
+      launch_flat_estep(xs, ys, zs, d_tiles, ntiles, rt, f->d_trees, d_flatf, d_flats, d_state, d_bins, so, go, pm,
                         rr.flat_level, q);
     else
       launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins, d_dpart,

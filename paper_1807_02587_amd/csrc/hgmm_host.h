@@ -66,8 +66,9 @@ void launch_descend(const float* xs, const float* ys, const float* zs, const Til
                     int lds_levels, int max_levels, hipStream_t s);
 void launch_flat_table(const NodeF* tab, const NodeD* nodes, NodeF* ft, NodeS* fs, int64_t n, hipStream_t s);
 void launch_flat_estep(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
-                       const TreeDev* trees, const NodeF* tab, const NodeS* nodes, const PoseState* st, double* bins,
-                       int32_t* stop_out, float* gamma_out, const int* perm, int level, hipStream_t s);
+                       int tile_points, const TreeDev* trees, const NodeF* tab, const NodeS* nodes,
+                       const PoseState* st, double* bins, int32_t* stop_out, float* gamma_out, const int* perm,
+                       int level, hipStream_t s);
 void launch_fold_bins(const int2* pair_tiles, const TreeDev* trees, const double* partials, size_t pstride,
                       double* bins, int npairs, hipStream_t s);
 void launch_normal(double* bins, const double* dpart, size_t pstride, const int2* pair_tiles, const NodeD* nodes,

@@ -336,10 +336,8 @@ __global__ __launch_bounds__(256) void fold_bins_kernel(const int2* __restrict__
 // The FP32 winner is re-checked in FP64 over the whole level when another
 // component's score bound reaches it (lowest index wins exact FP64 ties), and
 // the posterior is recomputed in FP64 when its rounding bound exceeds
-// kFlatGammaTol (relative).  Components are staged in LDS in chunks of CH
-// records shared by the block's 256 points; with LBIN the level's moments are
-// accumulated in FP64 LDS bins and added to the node bins once per block,
-// otherwise (J > CH) directly with FP64 atomics after wave aggregation.
+// kFlatGammaTol (relative).  The moments go to the node bins with FP64
+// atomics after aggregation of equal components inside a wave.
 // The tree's scoring records carry the weight inside the sibling group; the
 // single-level mixture needs the global weight, so the E-step reads records
 // rebuilt with it (flat_table_kernel).
@@ -363,7 +361,10 @@ __global__ void flat_table_kernel(const NodeF* __restrict__ tab, const NodeD* __
     f.c = (float)(v.c * kLog2e);
     f.errc = 2.f * kU * fabsf(f.c) * 1.0001f;
   } else {
-    f.flags = 0u;
+    // a dead component scores -inf for every point (and adds nothing to the
+    // running sums), so the scan needs no liveness test
+    f = NodeF{};
+    f.c = -INFINITY;
   }
   ft[g] = f;
   fs[g] = v;
@@ -398,7 +399,58 @@ __device__ float flat_gamma64(NodePtr S, const NodeF* __restrict__ F, int J, int
   return (float)(1.0 / den);
 }
 
-template <int CH, bool LBIN>
+constexpr int kFlatSlices = 4;  // waves per block; wave w scans slice w of the components
+constexpr int kFlatChunk = 64;  // records of a slice staged in LDS at a time (4 KB per wave)
+
+// Running state of a scan over components for one point: maximum s1 (index
+// k1, bound e1), den = sum_j 2^(s_j - s1), eb = sum_j 2^(s_j - s1) e_j, and
+// ub = the largest s_j + 2 e_j over the components other than k1.
+struct FlatState {
+  float s1, e1, den, eb, ub;
+  int k1;
+};
+
+__device__ __forceinline__ void flat_init(FlatState& a) {
+  a.s1 = -__FLT_MAX__;
+  a.e1 = 0.f;
+  a.den = 0.f;
+  a.eb = 0.f;
+  a.ub = -INFINITY;
+  a.k1 = -1;
+}
+
+__device__ __forceinline__ void flat_add(FlatState& a, float s, float e, int j) {
+  const bool up = s > a.s1;  // strict: the lower index stays on equal FP32 scores
+  const float r = __builtin_amdgcn_exp2f(up ? a.s1 - s : s - a.s1);
+  a.ub = fmaxf(a.ub, up ? fmaf(2.f, a.e1, a.s1) : fmaf(2.f, e, s));
+  a.den = up ? fmaf(a.den, r, 1.f) : a.den + r;
+  a.eb = up ? fmaf(a.eb, r, e) : fmaf(r, e, a.eb);
+  a.e1 = up ? e : a.e1;
+  a.k1 = up ? j : a.k1;
+  a.s1 = up ? s : a.s1;
+}
+
+// a <- a merged with b, where b holds components of higher index than a
+__device__ __forceinline__ void flat_merge(FlatState& a, const FlatState& b) {
+  const bool up = b.s1 > a.s1;
+  const float ws = up ? b.s1 : a.s1, we = up ? b.e1 : a.e1, wd = up ? b.den : a.den, wb = up ? b.eb : a.eb;
+  const float ls = up ? a.s1 : b.s1, le = up ? a.e1 : b.e1, ld = up ? a.den : b.den, lb = up ? a.eb : b.eb;
+  const int wk = up ? b.k1 : a.k1;
+  const float r = __builtin_amdgcn_exp2f(ls - ws);
+  a.ub = fmaxf(fmaxf(a.ub, b.ub), fmaf(2.f, le, ls));
+  a.den = fmaf(ld, r, wd);
+  a.eb = fmaf(lb, r, wb);
+  a.s1 = ws;
+  a.e1 = we;
+  a.k1 = wk;
+}
+
+// Grid (tiles, sub-blocks): block (x, y) takes the 64 P points of tile x from
+// tl.start + 64 P y.  Its 4 waves each scan a quarter of the components for
+// all of those points (P per lane), the component records read as
+// wave-uniform (scalar) loads; the four partial states are merged in LDS in
+// component order, and the first 64 P threads finish one point each.
+template <int P>
 __global__ __launch_bounds__(256) void flat_estep_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
                                                          const float* __restrict__ zs, const Tile* __restrict__ tiles,
                                                          const TreeDev* __restrict__ trees,
@@ -407,144 +459,159 @@ __global__ __launch_bounds__(256) void flat_estep_kernel(const float* __restrict
                                                          const PoseState* __restrict__ st, double* bins,
                                                          int32_t* stop_out, float* gamma_out,
                                                          const int* __restrict__ perm, int level) {
+  constexpr int NP = 64 * P;
   const Tile tl = tiles[blockIdx.x];
+  const int start = tl.start + (int)blockIdx.y * NP;
+  if (start >= tl.end) return;
   const int pair = tl.job;
   if (st[pair].done) return;
+  const int end = tl.end - start < NP ? tl.end : start + NP;
   const TreeDev& T = trees[pair];
   const int64_t nb = T.node_base;
   const int64_t g0 = nb + lvl_off(level);
   const int J = 8 << (3 * level);
-  const NodeF* Fg = ftab + g0;
-  const NodeS* Sg = fs + g0;
-  __shared__ NodeF lds[CH];
-  __shared__ double lbin[LBIN ? CH * 6 : 1];
-  const bool resident = J <= CH;  // the whole level fits: staged once
-  if (resident) {
-    for (int i = threadIdx.x; i < J; i += blockDim.x) {
-      const float4* s = reinterpret_cast<const float4*>(&Fg[i]);
-      float4* d = reinterpret_cast<float4*>(&lds[i]);
-      d[0] = s[0]; d[1] = s[1]; d[2] = s[2]; d[3] = s[3];
-    }
-  }
-  if (LBIN)
-    for (int i = threadIdx.x; i < J * 6; i += blockDim.x) lbin[i] = 0.0;
-  __syncthreads();
+  const NodeF* __restrict__ Fg = ftab + g0;
+  const NodeS* __restrict__ Sg = fs + g0;
   const double R0 = st[pair].R[0], R1 = st[pair].R[1], R2 = st[pair].R[2], R3 = st[pair].R[3],
                R4 = st[pair].R[4], R5 = st[pair].R[5], R6 = st[pair].R[6], R7 = st[pair].R[7],
                R8 = st[pair].R[8], t0 = st[pair].t[0], t1 = st[pair].t[1], t2 = st[pair].t[2];
   const int lane = __lane_id();
-  for (int b0 = tl.start; b0 < tl.end; b0 += blockDim.x) {
-    const int i = b0 + threadIdx.x;
-    const bool valid = i < tl.end;
-    const double z0 = valid ? (double)xs[i] : 0.0, z1 = valid ? (double)ys[i] : 0.0,
-                 z2 = valid ? (double)zs[i] : 0.0;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  double px[P], py[P], pz[P];
+  FlatState S[P];
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    const int i = start + lane + 64 * q;
+    const bool v = i < end;
+    const double z0 = v ? (double)xs[i] : 0.0, z1 = v ? (double)ys[i] : 0.0, z2 = v ? (double)zs[i] : 0.0;
+    px[q] = R0 * z0 + R1 * z1 + R2 * z2 + t0;
+    py[q] = R3 * z0 + R4 * z1 + R5 * z2 + t1;
+    pz[q] = R6 * z0 + R7 * z1 + R8 * z2 + t2;
+    flat_init(S[q]);
+  }
+  const int per = J / kFlatSlices;
+  const int jb = wv * per;
+  // each wave stages its slice through LDS in chunks of kFlatChunk records
+  // and reads them as broadcasts; dead components carry c = -inf
+  __shared__ NodeF lds[kFlatSlices][kFlatChunk];
+  for (int c0 = 0; c0 < per; c0 += kFlatChunk) {
+    const int nc = per - c0 < kFlatChunk ? per - c0 : kFlatChunk;
+    for (int r = lane; r < nc; r += 64) {
+      const float4* s = reinterpret_cast<const float4*>(&Fg[jb + c0 + r]);
+      float4* d = reinterpret_cast<float4*>(&lds[wv][r]);
+      d[0] = s[0]; d[1] = s[1]; d[2] = s[2]; d[3] = s[3];
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int jj = 0; jj < nc; ++jj) {
+      const NodeF& C = lds[wv][jj];
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        float qq, m;
+        const float s = score32(C, px[q], py[q], pz[q], qq, m);
+        flat_add(S[q], s, score_err(C, qq, m), jb + c0 + jj);
+      }
+    }
+    __syncthreads();
+  }
+  __shared__ float ms[kFlatSlices][5][NP];
+  __shared__ int mk[kFlatSlices][NP];
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    const int r = lane + 64 * q;
+    ms[wv][0][r] = S[q].s1;
+    ms[wv][1][r] = S[q].e1;
+    ms[wv][2][r] = S[q].den;
+    ms[wv][3][r] = S[q].eb;
+    ms[wv][4][r] = S[q].ub;
+    mk[wv][r] = S[q].k1;
+  }
+  __syncthreads();
+  const int r = (int)threadIdx.x;
+  if (r >= NP) return;  // whole waves leave; no barrier follows
+  FlatState A;
+  {
+    A.s1 = ms[0][0][r]; A.e1 = ms[0][1][r]; A.den = ms[0][2][r]; A.eb = ms[0][3][r]; A.ub = ms[0][4][r];
+    A.k1 = mk[0][r];
+#pragma unroll
+    for (int w = 1; w < kFlatSlices; ++w) {
+      FlatState B;
+      B.s1 = ms[w][0][r]; B.e1 = ms[w][1][r]; B.den = ms[w][2][r]; B.eb = ms[w][3][r]; B.ub = ms[w][4][r];
+      B.k1 = mk[w][r];
+      flat_merge(A, B);
+    }
+  }
+  const int i = start + r;
+  const bool valid = i < end;
+  int64_t g = -1;
+  float gam = 0.f, d0 = 0.f, d1 = 0.f, d2 = 0.f, dm2 = 0.f;
+  if (valid && A.k1 >= 0) {
+    const double z0 = xs[i], z1 = ys[i], z2 = zs[i];
     const double p0 = R0 * z0 + R1 * z1 + R2 * z2 + t0;
     const double p1 = R3 * z0 + R4 * z1 + R5 * z2 + t1;
     const double p2 = R6 * z0 + R7 * z1 + R8 * z2 + t2;
-    // running state: maximum s1 (index k1, bound e1), denominator den =
-    // sum_j 2^(s_j - s1), eb = sum_j 2^(s_j - s1) e_j, and ub = the largest
-    // s_j + 2 e_j over the components other than k1
-    float s1 = -__FLT_MAX__, e1 = 0.f, den = 0.f, eb = 0.f, ub = -INFINITY;
-    int k1 = -1;
-    for (int c0 = 0; c0 < J; c0 += CH) {
-      const int nc = J - c0 < CH ? J - c0 : CH;
-      if (!resident) {
-        __syncthreads();  // every lane is done with the previous chunk
-        for (int r = threadIdx.x; r < nc; r += blockDim.x) {
-          const float4* s = reinterpret_cast<const float4*>(&Fg[c0 + r]);
-          float4* d = reinterpret_cast<float4*>(&lds[r]);
-          d[0] = s[0]; d[1] = s[1]; d[2] = s[2]; d[3] = s[3];
-        }
-        __syncthreads();
-      }
-      for (int j = 0; j < nc; ++j) {
-        const NodeF& C = lds[j];
-        if (!(C.flags & F_LIVE)) continue;  // uniform across the block
+    int k1 = A.k1;
+    float s1 = A.s1, eb = A.eb;
+    double sk64 = 0.0;
+    bool have64 = false;
+    if (A.ub >= s1 - 2.f * A.e1) {  // another component may win in exact arithmetic
+      int kb;
+      sk64 = flat_argmax64(Sg, Fg, J, p0, p1, p2, kb);
+      have64 = true;
+      if (kb != k1) {
+        k1 = kb;
         float q, m;
-        const float s = score32(C, p0, p1, p2, q, m);
-        const float e = score_err(C, q, m);
-        const bool up = s > s1;  // strict: the lower index stays on equal FP32 scores
-        const float r = __builtin_amdgcn_exp2f(up ? s1 - s : s - s1);
-        ub = fmaxf(ub, up ? fmaf(2.f, e1, s1) : fmaf(2.f, e, s));
-        den = up ? fmaf(den, r, 1.f) : den + r;
-        eb = up ? fmaf(eb, r, e) : fmaf(r, e, eb);
-        e1 = up ? e : e1;
-        k1 = up ? c0 + j : k1;
-        s1 = up ? s : s1;
+        s1 = score32(Fg[k1], p0, p1, p2, q, m);
+        eb = INFINITY;  // the FP32 sums refer to the old winner: recompute gamma in FP64
       }
     }
-    int64_t g = -1;
-    float gam = 0.f, d0 = 0.f, d1 = 0.f, d2 = 0.f, dm2 = 0.f;
-    if (valid && k1 >= 0) {
-      const NodeF* Fs = resident ? lds : Fg;
-      double sk64 = 0.0;
-      bool have64 = false;
-      if (ub >= s1 - 2.f * e1) {  // another component may win in exact arithmetic
-        int kb;
-        sk64 = flat_argmax64(Sg, Fs, J, p0, p1, p2, kb);
-        have64 = true;
-        if (kb != k1) {
-          k1 = kb;
-          float q, m;
-          s1 = score32(Fs[k1], p0, p1, p2, q, m);
-          eb = INFINITY;  // the FP32 sums refer to the old winner: recompute gamma in FP64
-        }
-      }
-      const float gbound = 0.6931472f * (eb + e1 * (den - 2.f)) / den;
-      if (gbound > kFlatGammaTol) {
-        if (!have64) sk64 = score64(Sg[k1], p0, p1, p2);
-        gam = flat_gamma64(Sg, Fs, J, k1, sk64, s1, p0, p1, p2);
-      } else {
-        gam = 1.0f / den;
-      }
-      g = g0 + k1;
-      const NodeS& nd = Sg[k1];
-      const double e0 = p0 - nd.mu[0], ee1 = p1 - nd.mu[1], e2 = p2 - nd.mu[2];
-      d0 = (float)e0;
-      d1 = (float)ee1;
-      d2 = (float)e2;
-      const double w0 = nd.winv[0] * e0;
-      const double w1 = nd.winv[1] * e0 + nd.winv[2] * ee1;
-      const double w2 = nd.winv[3] * e0 + nd.winv[4] * ee1 + nd.winv[5] * e2;
-      dm2 = (float)(w0 * w0 + w1 * w1 + w2 * w2);
+    const float gbound = 0.6931472f * (eb + A.e1 * (A.den - 2.f)) / A.den;
+    if (gbound > kFlatGammaTol) {
+      if (!have64) sk64 = score64(Sg[k1], p0, p1, p2);
+      gam = flat_gamma64(Sg, Fg, J, k1, sk64, s1, p0, p1, p2);
+    } else {
+      gam = 1.0f / A.den;
     }
-    if (valid) {
-      const int oi = perm ? perm[i] : i;
-      if (stop_out) stop_out[oi] = g >= 0 ? (int32_t)(g - nb) : -1;
-      if (gamma_out) gamma_out[oi] = gam;
-    }
-    // aggregate equal components inside the wave, then one add per component
-    bool pend = valid && g >= 0;
-    unsigned long long pending = __ballot(pend);
-    while (pending) {
-      const int leader = __ffsll((long long)pending) - 1;
-      const int64_t key = __shfl(g, leader, 64);
-      const bool mine = pend && (g == key);
-      const unsigned long long mm = __ballot(mine);
-      const float v0 = wave_sum(mine ? gam : 0.f);
-      const float v1 = wave_sum(mine ? gam * d0 : 0.f);
-      const float v2 = wave_sum(mine ? gam * d1 : 0.f);
-      const float v3 = wave_sum(mine ? gam * d2 : 0.f);
-      const float v5 = wave_sum(mine ? dm2 : 0.f);
-      if (lane == leader) {
-        double* B = LBIN ? lbin + (key - g0) * 6 : bins + key * 6;
-        unsafeAtomicAdd(B + 0, (double)v0);
-        unsafeAtomicAdd(B + 1, (double)v1);
-        unsafeAtomicAdd(B + 2, (double)v2);
-        unsafeAtomicAdd(B + 3, (double)v3);
-        unsafeAtomicAdd(B + 4, (double)__popcll(mm));
-        unsafeAtomicAdd(B + 5, (double)v5);
-      }
-      pend = pend && !mine;
-      pending &= ~mm;
-    }
+    g = g0 + k1;
+    const NodeS& nd = Sg[k1];
+    const double e0 = p0 - nd.mu[0], e1 = p1 - nd.mu[1], e2 = p2 - nd.mu[2];
+    d0 = (float)e0;
+    d1 = (float)e1;
+    d2 = (float)e2;
+    const double w0 = nd.winv[0] * e0;
+    const double w1 = nd.winv[1] * e0 + nd.winv[2] * e1;
+    const double w2 = nd.winv[3] * e0 + nd.winv[4] * e1 + nd.winv[5] * e2;
+    dm2 = (float)(w0 * w0 + w1 * w1 + w2 * w2);
   }
-  if (LBIN) {
-    __syncthreads();
-    for (int r = threadIdx.x; r < J * 6; r += blockDim.x) {
-      const int node = r / 6;
-      if (lbin[node * 6 + 4] > 0.0) unsafeAtomicAdd(bins + (g0 + node) * 6 + (r - node * 6), lbin[r]);
+  if (valid) {
+    const int oi = perm ? perm[i] : i;
+    if (stop_out) stop_out[oi] = g >= 0 ? (int32_t)(g - nb) : -1;
+    if (gamma_out) gamma_out[oi] = gam;
+  }
+  // aggregate equal components inside the wave, then one FP64 atomic add each
+  bool pend = valid && g >= 0;
+  unsigned long long pending = __ballot(pend);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const int64_t key = __shfl(g, leader, 64);
+    const bool mine = pend && (g == key);
+    const unsigned long long mm = __ballot(mine);
+    const float v0 = wave_sum(mine ? gam : 0.f);
+    const float v1 = wave_sum(mine ? gam * d0 : 0.f);
+    const float v2 = wave_sum(mine ? gam * d1 : 0.f);
+    const float v3 = wave_sum(mine ? gam * d2 : 0.f);
+    const float v5 = wave_sum(mine ? dm2 : 0.f);
+    if (lane == leader) {
+      double* B = bins + key * 6;
+      unsafeAtomicAdd(B + 0, (double)v0);
+      unsafeAtomicAdd(B + 1, (double)v1);
+      unsafeAtomicAdd(B + 2, (double)v2);
+      unsafeAtomicAdd(B + 3, (double)v3);
+      unsafeAtomicAdd(B + 4, (double)__popcll(mm));
+      unsafeAtomicAdd(B + 5, (double)v5);
     }
+    pend = pend && !mine;
+    pending &= ~mm;
   }
 }
 
@@ -787,17 +854,13 @@ void launch_flat_table(const NodeF* tab, const NodeD* nodes, NodeF* ft, NodeS* f
 }
 
 void launch_flat_estep(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
-                       const TreeDev* trees, const NodeF* tab, const NodeS* nodes, const PoseState* st, double* bins,
-                       int32_t* stop_out, float* gamma_out, const int* perm, int level, hipStream_t s) {
-  if (level <= 1)
-    hipLaunchKernelGGL((flat_estep_kernel<64, true>), dim3(ntiles), dim3(256), 0, s, xs, ys, zs, tiles, trees, tab,
-                       nodes, st, bins, stop_out, gamma_out, perm, level);
-  else if (level == 2)
-    hipLaunchKernelGGL((flat_estep_kernel<512, true>), dim3(ntiles), dim3(256), 0, s, xs, ys, zs, tiles, trees, tab,
-                       nodes, st, bins, stop_out, gamma_out, perm, level);
-  else
-    hipLaunchKernelGGL((flat_estep_kernel<512, false>), dim3(ntiles), dim3(256), 0, s, xs, ys, zs, tiles, trees, tab,
-                       nodes, st, bins, stop_out, gamma_out, perm, level);
+                       int tile_points, const TreeDev* trees, const NodeF* tab, const NodeS* nodes,
+                       const PoseState* st, double* bins, int32_t* stop_out, float* gamma_out, const int* perm,
+                       int level, hipStream_t s) {
+  constexpr int P = 1;
+  const unsigned nsub = (unsigned)((tile_points + 64 * P - 1) / (64 * P));
+  hipLaunchKernelGGL((flat_estep_kernel<P>), dim3(ntiles, nsub), dim3(256), 0, s, xs, ys, zs, tiles, trees, tab,
+                     nodes, st, bins, stop_out, gamma_out, perm, level);
 }
 
 void launch_fold_bins(const int2* pair_tiles, const TreeDev* trees, const double* partials, size_t pstride,
