@@ -46,6 +46,11 @@ DESC_FLOP_PER_LEVEL = 8 * 19
 DESC_BYTES_PER_POINT = 12
 
 
+def progress(msg):
+    """One line on stderr per finished section (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def roofline_of(prof, depth, traffic=None):
     """ALU roofline of the kernel family with the largest summed event time.
     prof: hgmm_profile_read per kind; depth: mean levels visited per point by
@@ -580,9 +585,13 @@ def main():
                "sample": f"{reps} full pair(s) of the same workload (build {n1} + register {n2} points), "
                          f"single-threaded FP64, {t_c:.1f} s"}
 
+    progress("main workload and CPU baseline done")
     variants = None if args.no_batch else variants_section(args, hg, tree, tgt, p, pr, max(3, args.steps // 2))
+    progress("registration variants done")
     batched = None if args.no_batch else batch_section(args, hg)
+    progress("batched section done")
     warm_form = None if args.no_batch else warm_section(args, hg)
+    progress("warm-start section done")
     depth_form = None if args.no_batch else depth_section(args, hg)
 
     out = {
