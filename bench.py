@@ -526,7 +526,12 @@ def main():
         with open(args.tuning_json) as f:
             hg.hgmm_set_tuning(**json.load(f))
     elif not args.no_tune:
-        # launch shapes for this workload, chosen before the timed region
+        # launch shapes for this workload, chosen before the timed region; the
+        # search starts from the shapes profiled for the LiDAR workload
+        start = os.path.join(ROOT, "profiles", "lidar_launch_shapes.json")
+        if args.workload == "lidar" and os.path.exists(start):
+            with open(start) as f:
+                hg.hgmm_set_tuning(**json.load(f))
         tuning = hg.hgmm_autotune(src, [0, n1], [pr["levels"]], tgt, [0, n2], reg_eps=pr["reg_eps"],
                                   min_mass=pr["min_mass"], lambda_c=pr["lambda_c"], reps=2, passes=2)
 
