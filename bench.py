@@ -158,15 +158,6 @@ def batch_section(args, hg):
     B = len(lv)
     ws = hg.Workspace()
     cfg = W.WarmConfig()
-    if args.variants_only:
-        if args.tuning_json:
-            with open(args.tuning_json) as f:
-                hg.hgmm_set_tuning(**json.load(f))
-        step()
-        print(json.dumps({"variants": variants_section(args, hg, tree, tgt, p, pr, max(1, args.steps))}),
-              flush=True)
-        return
-
     if args.copy_calibration:
         # counter calibration: a plain copy of known size, then the batched
         # plain form twice with the given launch shapes
@@ -382,6 +373,73 @@ def variants_section(args, hg, tree, tgt, p, pr, steps):
             "variants": out}
 
 
+def odometry_section(args, hg, frames=16):
+    """Frame-to-frame odometry over a sequence of LiDAR sweeps of the main
+    workload's street (1 m steps, yaw U(-2, 2 deg) per frame, building fronts
+    along the road): the trees of frames 0..F-2 and the registrations of frames
+    1..F-1 onto them in one call (batched), against the same work one frame pair
+    at a time (build + register per pair); drift of the chained poses against
+    the ground truth."""
+    import torch
+    from synth import lidar_sequence, rotation_angle_deg
+    _, pr, _ = _workload("lidar")
+    q = lidar_sequence(1000, frames=frames)
+    F = frames
+    dev = torch.device("cuda", 0)
+    xyz = torch.from_numpy(q.clouds).to(dev)
+    kw = dict(reg_eps=pr["reg_eps"], min_mass=pr["min_mass"])
+    ws = hg.Workspace(dev)
+    forest = None
+
+    def batched(prior=False):
+        nonlocal forest
+        r = hg.hgmm_odometry(xyz, q.offsets, pr["levels"], lambda_c=pr["lambda_c"], prior_restart=prior, ws=ws,
+                             forest=forest, **kw)
+        forest = r["forest"]
+        return r
+
+    frames_t = [xyz[:, int(q.offsets[k]):int(q.offsets[k + 1])].contiguous() for k in range(F)]
+    ws_b, ws_r = hg.Workspace(dev), hg.Workspace(dev)
+    tree = None
+
+    def sequential():
+        nonlocal tree
+        out = []
+        for k in range(F - 1):
+            tree = hg.hgmm_build(frames_t[k], levels=pr["levels"], ws=ws_b, tree=tree, **kw)
+            out.append(hg.hgmm_register(tree, frames_t[k + 1], lambda_c=pr["lambda_c"], ws=ws_r,
+                                        raise_singular=False))
+        return out
+
+    reps = 3
+    path = float(np.sum(np.linalg.norm(np.diff(q.t_abs, axis=0), axis=1)))
+    out = {"workload": f"{F} LiDAR sweeps of the main workload's street, 1 m apart, "
+                       f"{int(np.mean(np.diff(q.offsets)))} points each, {pr['levels']} levels", "path_m": round(path, 2)}
+    for name, fn in (("batched", batched), ("batched_prior_restart", lambda: batched(True)),
+                     ("one_pair_at_a_time", sequential)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        row = {"ms_per_sequence": round(sec * 1e3, 2), "frame_pairs_s": round((F - 1) / sec, 1)}
+        if name != "one_pair_at_a_time":
+            err_rel = [rotation_angle_deg(r["R_rel"][k], q.R_abs[k].T @ q.R_abs[k + 1]) for k in range(F - 1)]
+            drift_t = float(np.linalg.norm(r["t_abs"][-1] - q.t_abs[-1]))
+            row.update({"pair_rot_err_deg_median": round(float(np.median(err_rel)), 4),
+                        "pair_rot_err_deg_max": round(float(np.max(err_rel)), 4),
+                        "pairs_above_1deg": int(np.sum(np.array(err_rel) > 1.0)),
+                        "iters_mean": round(float(np.mean(r["iters"])), 2),
+                        "final_drift_deg": round(rotation_angle_deg(r["R_abs"][-1], q.R_abs[-1]), 4),
+                        "final_drift_m": round(drift_t, 4),
+                        "final_drift_pct_of_path": round(100 * drift_t / path, 3)})
+        out[name] = row
+    out["speedup_batched"] = round(out["batched"]["frame_pairs_s"] / out["one_pair_at_a_time"]["frame_pairs_s"], 2)
+    return out
+
+
 def warm_section(args, hg):
     """Held-out warm-start pairs (10k points per cloud, rotation U(0, 90 deg),
     translation U(-0.1, 0.1)^3, L = 2; seeds disjoint from training): the plain
@@ -464,6 +522,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of --copy-mib MiB and a few steps (for counter calibration)")
     ap.add_argument("--copy-mib", type=int, default=256)
+    ap.add_argument("--odometry-only", action="store_true", help="run only the odometry section")
     ap.add_argument("--variants-only", action="store_true",
                     help="build the main workload's tree once and run only the registration variants (for profiling)")
     args = ap.parse_args()
@@ -495,6 +554,10 @@ def main():
         tree = hg.hgmm_build(src, levels=pr["levels"], reg_eps=pr["reg_eps"], min_mass=pr["min_mass"], ws=ws_b,
                              tree=tree)
         return hg.hgmm_register(tree, tgt, lambda_c=pr["lambda_c"], ws=ws_r, raise_singular=False)
+
+    if args.odometry_only:
+        print(json.dumps({"odometry": odometry_section(args, hg)}), flush=True)
+        return
 
     if args.variants_only:
         if args.tuning_json:
@@ -598,6 +661,8 @@ def main():
     warm_form = None if args.no_batch else warm_section(args, hg)
     progress("warm-start section done")
     depth_form = None if args.no_batch else depth_section(args, hg)
+    progress("depth-camera section done")
+    odometry = None if args.no_batch else odometry_section(args, hg)
 
     out = {
         "metric": "cloud pairs registered/s (build + register)",
@@ -630,6 +695,7 @@ def main():
         "warm_start": warm_form,
         "depth_camera": depth_form,
         "variants": variants,
+        "odometry": odometry,
     }
     print(json.dumps(out), flush=True)
 

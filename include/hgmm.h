@@ -217,6 +217,36 @@ int hgmm_estep_batch(hgmm_tree forest, const float *d_xyz, const int64_t *offset
                      const double *t, double lambda_c, void *d_ws, size_t ws_bytes, void *stream, double *loglik,
                      int32_t *d_stop);
 
+/* ---- frame-to-frame odometry over a scan sequence ----------------------
+ * The paper's LiDAR experiment (Sec. 6): successive sweeps are registered
+ * frame to frame and the transforms are concatenated into a trajectory (no
+ * loop closure, so errors accumulate as drift).  Frames are concatenated
+ * CSR-style into one SoA buffer of offsets[F] points (x[total], y[total],
+ * z[total]; host offsets, offsets[0] = 0, every frame >= 8 points).  One call
+ * builds the trees of frames 0 .. F-2 as one forest (bp->levels each; the
+ * handle in *forest is created or reused, tree k is frame k's model) and
+ * registers frame k+1 onto tree k for every k in one batched call, starting
+ * from R0[9 k..], t0[3 k..] (host, nullable = identity).  With
+ * prior_restart = 1 (and F > 2) every pair is registered a second time in one
+ * more batched call, started from the neighbouring pair's result (pair k from
+ * pair k-1's transform, the motion of the frame before; pair 0 from pair
+ * 1's), and keeps whichever run ends with the higher mean log-likelihood of
+ * its last E-step; this guards the chain against a pair that leaves the
+ * method's basin from its first start.  Outputs (host):
+ * R_rel (F-1 x 9), t_rel (F-1 x 3) with frame-k coordinates = R_rel[k]
+ * (frame-(k+1) coordinates) + t_rel[k]; R_abs (F x 9), t_abs (F x 3), the
+ * pose of every frame in frame 0 (frame 0 the identity), composed in FP64;
+ * iters and status (nullable) per frame pair.  A singular pair keeps its last
+ * good transform in the chain and, with status NULL, makes the call return
+ * HGMM_ESINGULAR.  Errors: HGMM_EINVAL (F < 2, bad offsets or parameters,
+ * null pointer, workspace below hgmm_odometry_workspace_bytes),
+ * HGMM_ETOOFEW, HGMM_ENONFINITE, HGMM_EHIP.  Synchronises `stream`. */
+size_t hgmm_odometry_workspace_bytes(const int64_t *offsets, int F, int levels);
+int hgmm_odometry(const float *d_xyz, const int64_t *offsets, int F, const hgmm_build_params *bp,
+                  const hgmm_reg_params *rp, const double *R0, const double *t0, int prior_restart, void *d_ws,
+                  size_t ws_bytes, void *stream, hgmm_tree *forest, double *R_rel, double *t_rel, double *R_abs,
+                  double *t_abs, int *iters, int *status);
+
 /* ---- learned warm start ---------------------------------------------------
  * Not part of the paper: a small network that maps the coarse GMMs of both
  * clouds to an initial transform for hgmm_register / hgmm_register_batch.

@@ -20,6 +20,7 @@ from .oracle import (  # noqa: F401
     solve_update,
     register,
     register_flat,
+    compose_chain,
     level_offset,
     level_nodes,
 )

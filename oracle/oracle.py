@@ -307,3 +307,21 @@ def register(tree: OracleTree, xyz, R0=None, t0=None, max_iters=30, lambda_c=0.0
     st = lib.oracle_register(C.byref(s), _p(a), n, max_iters, C.c_double(lambda_c), C.c_double(tol_rot),
                              C.c_double(tol_trans), _p(R), _p(t), C.byref(iters), C.byref(ll), _p(trace))
     return dict(status=st, R=R, t=t, iters=iters.value, loglik=ll.value, trace=trace[: iters.value])
+
+
+def compose_chain(R_rel, t_rel):
+    """Poses of a chain of frame-to-frame transforms (the trajectory of the LiDAR
+    experiment, Sec. 6): with frame k coordinates = R_rel[k] @ (frame k+1
+    coordinates) + t_rel[k], frame 0 coordinates = R_abs[k] @ (frame k
+    coordinates) + t_abs[k], where R_abs[0] = I, t_abs[0] = 0 and
+    R_abs[k] = R_abs[k-1] R_rel[k-1], t_abs[k] = R_abs[k-1] t_rel[k-1] + t_abs[k-1]."""
+    R_rel = np.asarray(R_rel, dtype=np.float64)
+    t_rel = np.asarray(t_rel, dtype=np.float64)
+    F = len(R_rel) + 1
+    R_abs = np.zeros((F, 3, 3))
+    t_abs = np.zeros((F, 3))
+    R_abs[0] = np.eye(3)
+    for k in range(1, F):
+        R_abs[k] = R_abs[k - 1] @ R_rel[k - 1]
+        t_abs[k] = R_abs[k - 1] @ t_rel[k - 1] + t_abs[k - 1]
+    return R_abs, t_abs

@@ -11,6 +11,7 @@ from .api import (  # noqa: F401
     Workspace,
     hgmm_build,
     hgmm_register_flat,
+    hgmm_odometry,
     hgmm_estep_flat,
     hgmm_register,
     hgmm_build_batch,

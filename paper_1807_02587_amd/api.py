@@ -413,6 +413,49 @@ def hgmm_register_batch(forest: Tree, xyz: torch.Tensor, offsets, max_iters: int
     return dict(R=R.reshape(B, 3, 3), t=t, iters=iters, loglik=ll, status=st)
 
 
+def hgmm_odometry(xyz: torch.Tensor, offsets, levels: int, build_iters: int = 30, reg_eps: float = 1e-6,
+                  min_mass: float = 1.0, max_iters: int = 30, lambda_c: float = 0.01, tol_rot: float = 1e-6,
+                  tol_trans_rel: float = 1e-6, R0=None, t0=None, prior_restart: bool = False,
+                  ws: Workspace | None = None, forest: Tree | None = None, stream=None) -> dict:
+    """Frame-to-frame odometry over F frames concatenated CSR-style (SoA (3, total)):
+    the trees of frames 0..F-2 built as one forest, frame k+1 registered onto
+    tree k for every k in one call, the transforms chained into each frame's
+    pose in frame 0.  Returns R_rel (F-1,3,3), t_rel (F-1,3), R_abs (F,3,3),
+    t_abs (F,3), iters, status and the forest (tree k = frame k's model).
+    prior_restart: a second start of every pair from the neighbouring pair's
+    motion, keeping the run with the higher log-likelihood."""
+    xyz = _cloud(xyz)
+    lib = _lib.load()
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    F = len(off) - 1
+    assert off[-1] == xyz.shape[1]
+    bp = BuildParams(int(levels), build_iters, reg_eps, min_mass)
+    rp = RegParams(max_iters, 0, lambda_c, tol_rot, tol_trans_rel)
+    R0a = None if R0 is None else np.ascontiguousarray(np.asarray(R0, dtype=np.float64).reshape(F - 1, 9))
+    t0a = None if t0 is None else np.ascontiguousarray(np.asarray(t0, dtype=np.float64).reshape(F - 1, 3))
+    ws = ws or Workspace(xyz.device)
+    wptr, wlen = ws.ptr(lib.hgmm_odometry_workspace_bytes(off.ctypes.data_as(C.c_void_p), F, int(levels)))
+    h = C.c_void_p(forest.handle.value if forest is not None else None)
+    m = max(F - 1, 1)
+    Rr, tr = np.zeros((m, 9)), np.zeros((m, 3))
+    Ra, ta = np.zeros((m + 1, 9)), np.zeros((m + 1, 3))
+    iters, st = np.zeros(m, np.int32), np.zeros(m, np.int32)
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    check(lib.hgmm_odometry(C.c_void_p(xyz.data_ptr()), ptr(off), F, C.byref(bp), C.byref(rp),
+                            None if R0a is None else ptr(R0a), None if t0a is None else ptr(t0a),
+                            1 if prior_restart else 0, wptr, wlen,
+                            _stream(stream), C.byref(h), ptr(Rr), ptr(tr), ptr(Ra), ptr(ta), ptr(iters), ptr(st)),
+          "hgmm_odometry")
+    lev = np.full(F - 1, int(levels), np.int32)
+    if forest is None:
+        forest = Tree(h, int(off[F - 1]), int(levels), F - 1)
+    else:
+        forest.handle, forest.n_points, forest.levels, forest.ntrees = h, int(off[F - 1]), int(levels), F - 1
+    forest.offsets, forest.tree_levels = off[:F].copy(), lev
+    return dict(R_rel=Rr.reshape(F - 1, 3, 3), t_rel=tr, R_abs=Ra.reshape(F, 3, 3), t_abs=ta, iters=iters, status=st,
+                forest=forest)
+
+
 def hgmm_estep_batch(forest: Tree, xyz: torch.Tensor, offsets, R, t, lambda_c: float = 0.01,
                      ws: Workspace | None = None, stream=None, stop_nodes: bool = False):
     """Mean log-likelihood per pair at fixed transforms R (B,3,3), t (B,3); with

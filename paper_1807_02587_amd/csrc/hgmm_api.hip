@@ -1482,12 +1482,11 @@ size_t hgmm_autotune_workspace_bytes(const int64_t* src_offsets, const int32_t* 
   return std::max(b, reg_layout(tgt_offsets[B], nodes, B).total);
 }
 
-int hgmm_build_batch(const float* d_xyz, const int64_t* offsets, const int32_t* levels, int B,
-                     const hgmm_build_params* p, void* d_ws, size_t ws_bytes, void* stream, hgmm_tree* forest) {
-  int rc = check_build_params(p);
-  if (rc) return rc;
-  if ((rc = check_offsets(offsets, B))) return rc;
-  if (!d_xyz || !d_ws || !forest || !levels) return fail(HGMM_EINVAL, "null pointer argument");
+// Forest of B trees from clouds [offsets[b], offsets[b+1]) of the SoA arrays
+// in (whose stride may exceed offsets[B]).
+static int build_forest(const BuildInput& in, const int64_t* offsets, const int32_t* levels, int B,
+                        const hgmm_build_params* p, void* d_ws, size_t ws_bytes, void* stream, hgmm_tree* forest) {
+  int rc;
   for (int b = 0; b < B; ++b) {
     if (levels[b] < 1 || levels[b] > HGMM_MAX_LEVELS) return fail(HGMM_EINVAL, "levels[%d] outside [1, 6]", b);
     if (offsets[b + 1] - offsets[b] < 8) return fail(HGMM_ETOOFEW, "cloud %d has fewer than 8 points", b);
@@ -1499,15 +1498,23 @@ int hgmm_build_batch(const float* d_xyz, const int64_t* offsets, const int32_t* 
   f->trees.resize((size_t)B);
   for (int b = 0; b < B; ++b) f->trees[b] = TreeHost{levels[b], offsets[b + 1] - offsets[b], 0, 0, 0};
   rc = setup_forest(f);
-  if (!rc) {
-    const int64_t n = offsets[B];
-    BuildInput in{d_xyz, d_xyz + n, d_xyz + 2 * n};
+  if (!rc)
     rc = (g_tune.build_graph && !g_prof.on) ? run_build_graph(f, in, *p, (char*)d_ws, ws_bytes, (hipStream_t)stream)
                                             : run_build(f, in, *p, (char*)d_ws, ws_bytes, (hipStream_t)stream);
-  }
   if (rc && fresh) { free_forest(f); return rc; }
   *forest = f;
   return rc;
+}
+
+int hgmm_build_batch(const float* d_xyz, const int64_t* offsets, const int32_t* levels, int B,
+                     const hgmm_build_params* p, void* d_ws, size_t ws_bytes, void* stream, hgmm_tree* forest) {
+  int rc = check_build_params(p);
+  if (rc) return rc;
+  if ((rc = check_offsets(offsets, B))) return rc;
+  if (!d_xyz || !d_ws || !forest || !levels) return fail(HGMM_EINVAL, "null pointer argument");
+  const int64_t n = offsets[B];
+  return build_forest(BuildInput{d_xyz, d_xyz + n, d_xyz + 2 * n}, offsets, levels, B, p, d_ws, ws_bytes, stream,
+                      forest);
 }
 
 int hgmm_register_batch(hgmm_tree forest, const float* d_xyz, const int64_t* offsets, int B,
@@ -1559,6 +1566,91 @@ int hgmm_estep_batch(hgmm_tree forest, const float* d_xyz, const int64_t* offset
                     (hipStream_t)stream, 1, d_stop, nullptr, nullptr, nullptr, nrm.data());
   if (rc) return rc;
   for (int b = 0; b < B; ++b) loglik[b] = nrm[28 * (size_t)b + 27];
+  return HGMM_OK;
+}
+
+// ---- frame-to-frame odometry over a scan sequence -----------------------
+
+size_t hgmm_odometry_workspace_bytes(const int64_t* offsets, int F, int levels) {
+  if (F < 2 || check_offsets(offsets, F) || levels < 1 || levels > HGMM_MAX_LEVELS) return 0;
+  std::vector<int32_t> lv((size_t)F - 1, levels);
+  const size_t b = hgmm_build_batch_workspace_bytes(offsets, lv.data(), F - 1);
+  if (b == 0) return 0;
+  return std::max(b, reg_layout(offsets[F] - offsets[1], (int64_t)(F - 1) * tree_nodes(levels), F - 1).total);
+}
+
+int hgmm_odometry(const float* d_xyz, const int64_t* offsets, int F, const hgmm_build_params* bp,
+                  const hgmm_reg_params* rp, const double* R0, const double* t0, int prior_restart, void* d_ws,
+                  size_t ws_bytes,
+                  void* stream, hgmm_tree* forest, double* R_rel, double* t_rel, double* R_abs, double* t_abs,
+                  int* iters, int* status) {
+  if (F < 2) return fail(HGMM_EINVAL, "a sequence needs at least 2 frames");
+  int rc = check_offsets(offsets, F);
+  if (rc) return rc;
+  if ((rc = check_build_params(bp))) return rc;
+  if (!d_xyz || !rp || !d_ws || !forest || !R_rel || !t_rel || !R_abs || !t_abs || !iters)
+    return fail(HGMM_EINVAL, "null pointer argument");
+  if (rp->max_iters < 1) return fail(HGMM_EINVAL, "max_iters must be >= 1");
+  const size_t need = hgmm_odometry_workspace_bytes(offsets, F, bp->levels);
+  if (need == 0 || ws_bytes < need) return fail(HGMM_EINVAL, "odometry workspace too small: %zu < %zu", ws_bytes, need);
+  const int64_t T = offsets[F];
+  // the trees of frames 0 .. F-2, every level of all of them in the same launches
+  std::vector<int32_t> lv((size_t)F - 1, bp->levels);
+  rc = build_forest(BuildInput{d_xyz, d_xyz + T, d_xyz + 2 * T}, offsets, lv.data(), F - 1, bp, d_ws, ws_bytes,
+                    stream, forest);
+  if (rc) return rc;
+  // frame k+1 registered onto the tree of frame k, all pairs in one call
+  const int64_t o1 = offsets[1];
+  std::vector<int64_t> offs((size_t)F);
+  for (int k = 0; k < F; ++k) offs[k] = offsets[k + 1] - o1;
+  RegRun rr{rp->max_iters, rp->lambda_c, rp->tol_rot, rp->tol_trans_rel, rp->max_levels};
+  std::vector<PoseState> res((size_t)F - 1);
+  rc = run_register(*forest, d_xyz + o1, d_xyz + T + o1, d_xyz + 2 * T + o1, offs, R0, t0, 1, rr, (char*)d_ws,
+                    ws_bytes, (hipStream_t)stream, 0, nullptr, nullptr, nullptr, res.data(), nullptr);
+  if (rc) return rc;
+  if (prior_restart && F > 2) {
+    // second start of every pair from the neighbouring pair's motion (the
+    // frame before; pair 0 from pair 1), all pairs in one call; each pair
+    // keeps the run that ends with the higher log-likelihood
+    std::vector<double> Rp(9 * (size_t)(F - 1)), tp(3 * (size_t)(F - 1));
+    for (int k = 0; k < F - 1; ++k) {
+      const PoseState& S = res[(size_t)(k == 0 ? 1 : k - 1)];
+      for (int i = 0; i < 9; ++i) Rp[9 * (size_t)k + i] = S.R[i];
+      for (int i = 0; i < 3; ++i) tp[3 * (size_t)k + i] = S.t[i];
+    }
+    std::vector<PoseState> res2((size_t)F - 1);
+    rc = run_register(*forest, d_xyz + o1, d_xyz + T + o1, d_xyz + 2 * T + o1, offs, Rp.data(), tp.data(), 1, rr,
+                      (char*)d_ws, ws_bytes, (hipStream_t)stream, 0, nullptr, nullptr, nullptr, res2.data(), nullptr);
+    if (rc) return rc;
+    for (int k = 0; k < F - 1; ++k) {
+      const PoseState& a = res[(size_t)k];
+      const PoseState& b = res2[(size_t)k];
+      if (b.status == 0 && (a.status != 0 || b.loglik > a.loglik)) res[(size_t)k] = b;
+    }
+  }
+  // chain: frame-0 coordinates = R_abs[k] (frame-k coordinates) + t_abs[k]
+  for (int i = 0; i < 9; ++i) R_abs[i] = (i % 4 == 0) ? 1.0 : 0.0;
+  for (int i = 0; i < 3; ++i) t_abs[i] = 0.0;
+  int worst = HGMM_OK;
+  for (int k = 1; k < F; ++k) {
+    const PoseState& S = res[(size_t)k - 1];
+    double* Rr = R_rel + 9 * (size_t)(k - 1);
+    double* tr = t_rel + 3 * (size_t)(k - 1);
+    for (int i = 0; i < 9; ++i) Rr[i] = S.R[i];
+    for (int i = 0; i < 3; ++i) tr[i] = S.t[i];
+    iters[k - 1] = S.iters;
+    if (status) status[k - 1] = S.status;
+    if (S.status != 0) worst = S.status;
+    const double* Rp = R_abs + 9 * (size_t)(k - 1);
+    const double* tp = t_abs + 3 * (size_t)(k - 1);
+    double* Ra = R_abs + 9 * (size_t)k;
+    double* ta = t_abs + 3 * (size_t)k;
+    for (int i = 0; i < 3; ++i) {
+      for (int j = 0; j < 3; ++j) Ra[3 * i + j] = Rp[3 * i] * Rr[j] + Rp[3 * i + 1] * Rr[3 + j] + Rp[3 * i + 2] * Rr[6 + j];
+      ta[i] = Rp[3 * i] * tr[0] + Rp[3 * i + 1] * tr[1] + Rp[3 * i + 2] * tr[2] + tp[i];
+    }
+  }
+  if (worst != HGMM_OK && !status) return fail(worst, "normal equations not positive definite for some frame pair");
   return HGMM_OK;
 }
 

@@ -10,6 +10,8 @@ from .scenes import (  # noqa: F401
     BatchSample,
     small_pair,
     lidar_pair,
+    lidar_sequence,
+    SequenceSample,
     depth_pair,
     uneven_batch,
     rotation_from_axis_angle,

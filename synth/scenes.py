@@ -234,13 +234,8 @@ def _scan(sensor, yaw, boxes, cyls, rng_noise, rings=64, azimuths=1875, max_rang
     return d_loc[keep] * r[:, None]
 
 
-def lidar_pair(seed: int, rings: int = 64, azimuths: int = 1875) -> PairSample:
-    """Two sweeps of a spinning scanner; frame 2 is 1 m forward with a small yaw."""
-    s_scene, _, _, s_noise, s_pose = [
-        np.random.Generator(np.random.PCG64(ss)) for ss in np.random.SeedSequence(seed).spawn(5)
-    ]
-    h = 1.8
-    sensors = [np.array([0.0, 0.0, h]), np.array([1.0, 0.0, h])]
+def _street(s_scene, sensors):
+    """50 axis-aligned boxes (none over a sensor) and 30 upright cylinders."""
     boxes = []
     while len(boxes) < 50:
         side = s_scene.uniform(1.0, 10.0, size=3)
@@ -258,6 +253,17 @@ def lidar_pair(seed: int, rings: int = 64, azimuths: int = 1875) -> PairSample:
         ang = s_scene.uniform(0.0, 2 * np.pi)
         cyls.append((rad * np.cos(ang), rad * np.sin(ang), s_scene.uniform(0.2, 1.0),
                      s_scene.uniform(2.0, 8.0)))
+    return boxes, cyls
+
+
+def lidar_pair(seed: int, rings: int = 64, azimuths: int = 1875) -> PairSample:
+    """Two sweeps of a spinning scanner; frame 2 is 1 m forward with a small yaw."""
+    s_scene, _, _, s_noise, s_pose = [
+        np.random.Generator(np.random.PCG64(ss)) for ss in np.random.SeedSequence(seed).spawn(5)
+    ]
+    h = 1.8
+    sensors = [np.array([0.0, 0.0, h]), np.array([1.0, 0.0, h])]
+    boxes, cyls = _street(s_scene, sensors)
     yaw = math.radians(s_pose.uniform(-2.0, 2.0))
     src = _scan(sensors[0], 0.0, boxes, cyls, s_noise, rings, azimuths)
     tgt = _scan(sensors[1], yaw, boxes, cyls, s_noise, rings, azimuths)
@@ -267,6 +273,55 @@ def lidar_pair(seed: int, rings: int = 64, azimuths: int = 1875) -> PairSample:
                       extent=_extent(src32),
                       meta=dict(kind="lidar", seed=seed, yaw_deg=math.degrees(yaw),
                                 n_src=src.shape[0], n_tgt=tgt.shape[0]))
+
+
+@dataclass
+class SequenceSample:
+    clouds: np.ndarray       # (3, sum N) float32, frame k at [offsets[k], offsets[k+1])
+    offsets: np.ndarray      # (F+1,) int64
+    R_abs: np.ndarray        # (F, 3, 3): frame-0 coordinates = R_abs[k] @ frame-k coordinates + t_abs[k]
+    t_abs: np.ndarray        # (F, 3)
+    meta: dict = field(default_factory=dict)
+
+
+def lidar_sequence(seed: int, frames: int = 16, step_m: float = 1.0, max_turn_deg: float = 2.0,
+                   rings: int = 64, azimuths: int = 1875) -> SequenceSample:
+    """Sweeps of a spinning scanner driving down a street of one static scene
+    (the boxes and cylinders of the LiDAR pair's scene, plus building fronts
+    9-13 m to either side of the road): each frame moves step_m along the
+    current heading, then turns by a yaw drawn from U(-max_turn_deg,
+    max_turn_deg).  Points are in each sensor's own frame; R_abs, t_abs give
+    every frame's pose in frame 0."""
+    s_scene, _, _, s_noise, s_pose = [
+        np.random.Generator(np.random.PCG64(ss)) for ss in np.random.SeedSequence(seed).spawn(5)
+    ]
+    h = 1.8
+    yaws = np.zeros(frames)
+    centres = np.zeros((frames, 3))
+    centres[0] = [0.0, 0.0, h]
+    for k in range(1, frames):
+        heading = rotation_from_axis_angle([0, 0, 1], yaws[k - 1]) @ np.array([step_m, 0.0, 0.0])
+        centres[k] = centres[k - 1] + heading
+        yaws[k] = yaws[k - 1] + math.radians(s_pose.uniform(-max_turn_deg, max_turn_deg))
+    boxes, cyls = _street(s_scene, list(centres))
+    # building fronts lining the road on both sides (gaps between them)
+    for k in range(frames):
+        for side in (-1.0, 1.0):
+            if s_scene.random() < 0.3:
+                continue
+            off = rotation_from_axis_angle([0, 0, 1], yaws[k]) @ np.array([0.0, side * s_scene.uniform(9.0, 13.0),
+                                                                            0.0])
+            half = np.array([s_scene.uniform(1.5, 3.0), s_scene.uniform(1.0, 2.0)])
+            c = centres[k, :2] + off[:2]
+            boxes.append((np.array([c[0] - half[0], c[1] - half[1], 0.0]),
+                          np.array([c[0] + half[0], c[1] + half[1], s_scene.uniform(4.0, 15.0)])))
+    clouds = [_scan(centres[k], yaws[k], boxes, cyls, s_noise, rings, azimuths) for k in range(frames)]
+    offsets = np.concatenate([[0], np.cumsum([c.shape[0] for c in clouds])]).astype(np.int64)
+    R_abs = np.stack([rotation_from_axis_angle([0, 0, 1], y) for y in yaws])
+    t_abs = centres - centres[0]
+    return SequenceSample(clouds=as_soa(np.concatenate(clouds, axis=0)), offsets=offsets, R_abs=R_abs,
+                          t_abs=t_abs, meta=dict(kind="lidar_sequence", seed=seed, frames=frames,
+                                                 yaw_deg=np.degrees(yaws).tolist()))
 
 
 # --------------------------------------------------------------------------

@@ -78,3 +78,29 @@ def test_argument_errors_before_device_work(lib):
     assert lib.hgmm_build(C.c_void_p(16), 100, C.byref(neg_eps), C.c_void_p(16), 1 << 20, None, C.byref(h)) == -1
     assert lib.hgmm_build(None, 100, C.byref(good), C.c_void_p(16), 1 << 20, None, C.byref(h)) == -1
     assert h.value is None
+
+
+def test_odometry_argument_errors_before_device_work(lib):
+    import numpy as np
+    from paper_1807_02587_amd._lib import BuildParams, RegParams
+    bp = BuildParams(2, 30, 1e-6, 1.0)
+    rp = RegParams(30, 0, 0.01, 1e-6, 1e-6)
+    off = np.array([0, 100, 200, 300], np.int64)
+    optr = off.ctypes.data_as(C.c_void_p)
+    need = lib.hgmm_odometry_workspace_bytes(optr, 3, 2)
+    assert need > 0
+    assert lib.hgmm_odometry_workspace_bytes(optr, 1, 2) == 0      # one frame is no sequence
+    assert lib.hgmm_odometry_workspace_bytes(optr, 3, 7) == 0      # levels out of range
+    out = [np.zeros(64) for _ in range(4)]
+    it = np.zeros(4, np.int32)
+    h = C.c_void_p(None)
+    args = lambda F, ws_bytes: (C.c_void_p(16), optr, F, C.byref(bp), C.byref(rp), None, None, 0, C.c_void_p(16),
+                                ws_bytes, None, C.byref(h), *[o.ctypes.data_as(C.c_void_p) for o in out],
+                                it.ctypes.data_as(C.c_void_p), None)
+    assert lib.hgmm_odometry(*args(1, need)) == -1
+    assert lib.hgmm_odometry(*args(3, need - 1)) == -1 and "workspace" in lib.hgmm_last_error().decode()
+    bad = np.array([0, 100, 50, 300], np.int64)
+    assert lib.hgmm_odometry(C.c_void_p(16), bad.ctypes.data_as(C.c_void_p), 3, C.byref(bp), C.byref(rp), None,
+                             None, 0, C.c_void_p(16), need, None, C.byref(h),
+                             *[o.ctypes.data_as(C.c_void_p) for o in out], it.ctypes.data_as(C.c_void_p), None) == -1
+    assert h.value is None

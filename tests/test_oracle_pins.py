@@ -640,3 +640,46 @@ def test_flat_exact_recovery_blob_tree(oracle_mod):
     assert r["status"] == 0 and r["iters"] < 60
     np.testing.assert_allclose(r["R"], Rg.T, atol=1e-6)
     np.testing.assert_allclose(r["t"], -Rg.T @ tg, atol=1e-6 * tree.extent)
+
+
+# --------------------------------------------------------------------------
+# trajectory of frame-to-frame registrations (Sec. 6 LiDAR experiment)
+# --------------------------------------------------------------------------
+
+def test_compose_chain_recovers_absolute_poses(oracle_mod):
+    """Relative transforms taken from known absolute poses (general, non-commuting
+    rotations) chain back to those poses; frame 0 is the identity."""
+    rng = np.random.default_rng(3)
+    F = 7
+    R_abs = np.stack([np.eye(3)] + [Rotation.random(random_state=int(s)).as_matrix()
+                                    for s in rng.integers(0, 1 << 30, F - 1)])
+    t_abs = np.vstack([np.zeros(3), rng.normal(size=(F - 1, 3))])
+    R_rel = np.stack([R_abs[k].T @ R_abs[k + 1] for k in range(F - 1)])
+    t_rel = np.stack([R_abs[k].T @ (t_abs[k + 1] - t_abs[k]) for k in range(F - 1)])
+    Ra, ta = oracle_mod.compose_chain(R_rel, t_rel)
+    np.testing.assert_allclose(Ra, R_abs, atol=1e-12)
+    np.testing.assert_allclose(ta, t_abs, atol=1e-12)
+    # a point seen from frame F-1 lands where the chain of frame changes puts it
+    p = rng.normal(size=3)
+    q = p
+    for k in range(F - 2, -1, -1):
+        q = R_rel[k] @ q + t_rel[k]
+    np.testing.assert_allclose(Ra[-1] @ p + ta[-1], q, atol=1e-12)
+
+
+def test_sequence_ground_truth_is_consistent():
+    """The scan sequence's poses put the sweeps of one static scene on top of
+    each other: frame-1 points mapped into frame 0 lie close to frame-0 points,
+    much closer than with the motion left out."""
+    from scipy.spatial import cKDTree
+    from synth import lidar_sequence
+    q = lidar_sequence(4, frames=2, rings=16, azimuths=600)
+    np.testing.assert_allclose(q.R_abs[0], np.eye(3))
+    np.testing.assert_allclose(q.t_abs[0], 0.0)
+    p0 = q.clouds[:, :q.offsets[1]].T.astype(np.float64)
+    p1 = q.clouds[:, q.offsets[1]:].T.astype(np.float64)
+    near = p1[np.linalg.norm(p1, axis=1) < 15.0]
+    kd = cKDTree(p0)
+    d_true = kd.query(near @ q.R_abs[1].T + q.t_abs[1])[0]
+    d_none = kd.query(near)[0]
+    assert np.median(d_true) < 0.1 and np.median(d_none) > 2 * np.median(d_true)
