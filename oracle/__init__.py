@@ -20,6 +20,8 @@ from .oracle import (  # noqa: F401
     solve_update,
     register,
     register_flat,
+    estep_soft,
+    register_soft,
     compose_chain,
     level_offset,
     level_nodes,

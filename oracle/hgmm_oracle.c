@@ -18,6 +18,8 @@
  *     small-angle linearisation ........................... Sec. 4.2, appendix Eq. 12-16
  *   - the single-level variant "GMM J=n" (every component
  *     scored for every point, no tree descent) ............ Sec. 5, list of variants
+ *   - the soft multi-path E-step: every branch whose path
+ *     expectation stays above a threshold, weighted by it . Sec. 4.1 (logarithmic search)
  * Plain loops, no blocking, no SIMD, libm only.
  */
 #include "hgmm_oracle.h"
@@ -695,6 +697,137 @@ int oracle_register_flat(const ot_tree *t, int level, const float *xyz, int64_t 
   *iters = 0;
   for (it = 1; it <= max_iters; ++it) {
     st = oracle_estep_flat(t, level, xyz, n, R, tv, NULL, NULL, NULL, bins, &ll);
+    if (st != OT_OK) break;
+    double H[36], g[6], x[6] = {0, 0, 0, 0, 0, 0};
+    oracle_normal_equations(t, bins, n, H, g);
+    *iters = it;
+    st = oracle_solve_update(H, g, t->origin, R, tv, x);
+    if (st != OT_OK) break;
+    double wn = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    double tn = sqrt(x[3] * x[3] + x[4] * x[4] + x[5] * x[5]);
+    if (wn < tol_rot && tn < tol_trans) break;
+  }
+  if (loglik) *loglik = ll;
+  free(bins);
+  return st;
+}
+
+/* Soft multi-path E-step (Sec. 4.1, logarithmic search): a point's expectation
+ * of a node is the product of its posteriors among the siblings along the path
+ * from the root (the expectation of a parent is the sum of its children's).
+ * Every branch whose expectation is at least tau is followed; a branch below
+ * tau is pruned with its subtree.  A followed node stops (by the rule of
+ * Algorithm 1: complexity <= lambda_c, no live children, or the last level)
+ * and receives the point with weight E, its path expectation:
+ * bins[g] += {E, E q (3), E, E d_M^2}; the log-likelihood is the E-weighted
+ * log density, sum_i sum_stops E (log pi^g - log|cov|/2 - d_M^2/2) / n - 3/2 log 2 pi.
+ * margin (nullable): per point, the smallest |E - tau| / tau over every
+ * expectation compared with tau (a pruning decision that rounding could flip).
+ * stops (nullable): per point, the number of nodes it reached. */
+int oracle_estep_soft(const ot_tree *t, const float *xyz, int64_t n, const double R[9], const double tv[3],
+                      double lambda_c, double tau, double *bins, double *loglik, double *margin, int32_t *stops) {
+  const float *x = xyz, *y = xyz + n, *z = xyz + 2 * n;
+  const int L = t->levels;
+  double *Lc = (double *)malloc(sizeof(double) * 9 * (size_t)t->n_nodes);
+  double *ld = (double *)malloc(sizeof(double) * (size_t)t->n_nodes);
+  for (int64_t g = 0; g < t->n_nodes; ++g) {
+    if (!t->live[g]) continue;
+    double Lm[3][3];
+    if (!chol3(t->cov + 6 * g, Lm)) { free(Lc); free(ld); return OT_ESINGULAR; }
+    memcpy(Lc + 9 * g, Lm, sizeof(Lm));
+    ld[g] = logdet_from_chol(Lm);
+  }
+  if (bins) memset(bins, 0, sizeof(double) * 6 * (size_t)t->n_nodes);
+  const int cap = 8 * L + 8;
+  int64_t *st_g = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+  int *st_l = (int *)malloc(sizeof(int) * (size_t)cap);
+  double *st_e = (double *)malloc(sizeof(double) * (size_t)cap);
+  double ll = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double p[3] = {x[i], y[i], z[i]};
+    double q[3];
+    for (int r = 0; r < 3; ++r) q[r] = R[3 * r] * p[0] + R[3 * r + 1] * p[1] + R[3 * r + 2] * p[2] + tv[r];
+    double mg = INFINITY;
+    int ns = 0, top = 0;
+    /* a virtual parent of the level-0 nodes with expectation 1 */
+    int64_t parent = -1;
+    int plev = -1;
+    double pe = 1.0;
+    for (;;) {
+      /* expand `parent`: posteriors of its live children, children above tau pushed */
+      const int cl = plev + 1;
+      const int64_t base = oracle_level_offset(cl) + (parent < 0 ? 0 : 8 * (parent - oracle_level_offset(plev)));
+      double s[8], smax = -INFINITY;
+      for (int k = 0; k < 8; ++k) {
+        const int64_t g = base + k;
+        s[k] = -INFINITY;
+        if (!t->live[g]) continue;
+        double d[3] = {q[0] - t->mu[3 * g], q[1] - t->mu[3 * g + 1], q[2] - t->mu[3 * g + 2]};
+        double Lm[3][3];
+        memcpy(Lm, Lc + 9 * g, sizeof(Lm));
+        s[k] = log(t->pi[g]) - 0.5 * ld[g] - 0.5 * maha2(Lm, d);
+        if (s[k] > smax) smax = s[k];
+      }
+      double den = 0.0;
+      for (int k = 0; k < 8; ++k)
+        if (t->live[base + k]) den += exp(s[k] - smax);
+      for (int k = 0; k < 8; ++k) {
+        const int64_t g = base + k;
+        if (!t->live[g]) continue;
+        const double e = pe * exp(s[k] - smax) / den;
+        const double m = fabs(e - tau) / tau;
+        if (m < mg) mg = m;
+        if (e >= tau) { st_g[top] = g; st_l[top] = cl; st_e[top] = e; ++top; }
+      }
+      /* next followed node: stop nodes accumulate, others are expanded */
+      int expanded = 0;
+      while (top > 0 && !expanded) {
+        --top;
+        const int64_t g = st_g[top];
+        const int l = st_l[top];
+        const double e = st_e[top];
+        const int stop = (t->kappa[g] <= lambda_c) || (l == L - 1) || !t->has_children[g];
+        if (!stop) { parent = g; plev = l; pe = e; expanded = 1; break; }
+        double d[3] = {q[0] - t->mu[3 * g], q[1] - t->mu[3 * g + 1], q[2] - t->mu[3 * g + 2]};
+        double Lm[3][3];
+        memcpy(Lm, Lc + 9 * g, sizeof(Lm));
+        const double m2 = maha2(Lm, d);
+        if (bins) {
+          double *b = bins + 6 * g;
+          b[0] += e;
+          b[1] += e * q[0];
+          b[2] += e * q[1];
+          b[3] += e * q[2];
+          b[4] += e;
+          b[5] += e * m2;
+        }
+        ll += e * (log(t->pig[g]) - 0.5 * ld[g] - 0.5 * m2 - 1.5 * LOG_2PI);
+        ++ns;
+      }
+      if (!expanded) break;
+    }
+    if (margin) margin[i] = mg;
+    if (stops) stops[i] = ns;
+  }
+  if (loglik) *loglik = ll / (double)n;
+  free(st_g);
+  free(st_l);
+  free(st_e);
+  free(Lc);
+  free(ld);
+  return OT_OK;
+}
+
+/* Registration with the soft multi-path E-step: the EM loop of oracle_register. */
+int oracle_register_soft(const ot_tree *t, const float *xyz, int64_t n, double lambda_c, double tau, int max_iters,
+                         double tol_rot, double tol_trans, double R[9], double tv[3], int *iters, double *loglik) {
+  if (n < 1 || max_iters < 1 || !(tau > 0.0)) return OT_EINVAL;
+  double *bins = (double *)malloc(sizeof(double) * 6 * (size_t)t->n_nodes);
+  int st = OT_OK, it;
+  double ll = 0.0;
+  *iters = 0;
+  for (it = 1; it <= max_iters; ++it) {
+    st = oracle_estep_soft(t, xyz, n, R, tv, lambda_c, tau, bins, &ll, NULL, NULL);
     if (st != OT_OK) break;
     double H[36], g[6], x[6] = {0, 0, 0, 0, 0, 0};
     oracle_normal_equations(t, bins, n, H, g);

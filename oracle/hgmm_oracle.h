@@ -85,6 +85,14 @@ int oracle_estep_flat(const ot_tree *t, int level, const float *xyz, int64_t n, 
                       double *loglik);
 int oracle_register_flat(const ot_tree *t, int level, const float *xyz, int64_t n, int max_iters, double tol_rot,
                          double tol_trans, double R[9], double tv[3], int *iters, double *loglik);
+/* Soft multi-path E-step: every branch whose path expectation (the product of
+ * sibling posteriors from the root) is at least tau, stop nodes weighted by
+ * it; bins {E, E q (3), E, E d_M^2}; margin: per point the smallest
+ * |E - tau| / tau compared; stops: per point the number of nodes reached. */
+int oracle_estep_soft(const ot_tree *t, const float *xyz, int64_t n, const double R[9], const double tv[3],
+                      double lambda_c, double tau, double *bins, double *loglik, double *margin, int32_t *stops);
+int oracle_register_soft(const ot_tree *t, const float *xyz, int64_t n, double lambda_c, double tau, int max_iters,
+                         double tol_rot, double tol_trans, double R[9], double tv[3], int *iters, double *loglik);
 
 #ifdef __cplusplus
 }

@@ -63,6 +63,9 @@ def _load():
         lib.oracle_estep_flat.argtypes = [P, C.c_int, P, C.c_int64, P, P, P, P, P, P, P]
         lib.oracle_register_flat.argtypes = [P, C.c_int, P, C.c_int64, C.c_int, C.c_double, C.c_double,
                                              P, P, P, P]
+        lib.oracle_estep_soft.argtypes = [P, P, C.c_int64, P, P, C.c_double, C.c_double, P, P, P, P]
+        lib.oracle_register_soft.argtypes = [P, P, C.c_int64, C.c_double, C.c_double, C.c_int, C.c_double,
+                                             C.c_double, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -265,6 +268,42 @@ def register_flat(tree: OracleTree, level, xyz, R0=None, t0=None, max_iters=30, 
     s = tree._struct()
     st = lib.oracle_register_flat(C.byref(s), int(level), _p(a), n, max_iters, C.c_double(tol_rot),
                                   C.c_double(tol_trans), _p(R), _p(t), C.byref(iters), C.byref(ll))
+    return dict(status=st, R=R, t=t, iters=iters.value, loglik=ll.value)
+
+
+def estep_soft(tree: OracleTree, xyz, R=None, t=None, lambda_c=0.01, tau=0.01):
+    """Soft multi-path E-step: every branch whose path expectation is >= tau,
+    stop nodes weighted by it (bins {E, E q, E, E d^2})."""
+    lib = _load()
+    a = _soa(xyz)
+    n = a.shape[1]
+    R = np.eye(3) if R is None else np.ascontiguousarray(R, dtype=np.float64)
+    t = np.zeros(3) if t is None else np.ascontiguousarray(t, dtype=np.float64)
+    out = dict(bins=np.zeros((tree.n_nodes, 6)), margin=np.zeros(n), stops=np.zeros(n, np.int32))
+    ll = C.c_double(0.0)
+    s = tree._struct()
+    _check(lib.oracle_estep_soft(C.byref(s), _p(a), n, _p(R), _p(t), C.c_double(lambda_c), C.c_double(tau),
+                                 _p(out["bins"]), C.byref(ll), _p(out["margin"]), _p(out["stops"])), "estep_soft")
+    out["loglik"] = ll.value
+    return out
+
+
+def register_soft(tree: OracleTree, xyz, R0=None, t0=None, lambda_c=0.01, tau=0.01, max_iters=30, tol_rot=1e-6,
+                  tol_trans=None):
+    """EM registration with the soft multi-path E-step."""
+    lib = _load()
+    a = _soa(xyz)
+    n = a.shape[1]
+    R = np.eye(3) if R0 is None else np.array(R0, dtype=np.float64, order="C")
+    t = np.zeros(3) if t0 is None else np.array(t0, dtype=np.float64, order="C")
+    if tol_trans is None:
+        tol_trans = 1e-6 * tree.extent
+    iters = C.c_int(0)
+    ll = C.c_double(0.0)
+    s = tree._struct()
+    st = lib.oracle_register_soft(C.byref(s), _p(a), n, C.c_double(lambda_c), C.c_double(tau), max_iters,
+                                  C.c_double(tol_rot), C.c_double(tol_trans), _p(R), _p(t), C.byref(iters),
+                                  C.byref(ll))
     return dict(status=st, R=R, t=t, iters=iters.value, loglik=ll.value)
 
 

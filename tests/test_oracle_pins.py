@@ -683,3 +683,105 @@ def test_sequence_ground_truth_is_consistent():
     d_true = kd.query(near @ q.R_abs[1].T + q.t_abs[1])[0]
     d_none = kd.query(near)[0]
     assert np.median(d_true) < 0.1 and np.median(d_none) > 2 * np.median(d_true)
+
+
+# --------------------------------------------------------------------------
+# soft multi-path E-step (Sec. 4.1: a parent's expectation is the sum of its
+# children's; branches below a threshold are pruned)
+# --------------------------------------------------------------------------
+
+def _path_expectations(tree, Y, levels):
+    """Brute force with scipy densities: every node's path expectation (the
+    product of posteriors among siblings with sibling weights pi)."""
+    E = np.zeros((Y.shape[0], tree.n_nodes))
+    for l in range(levels):
+        g0 = oracle_level_offset(l)
+        for grp in range(8 ** l):
+            base = g0 + 8 * grp
+            kids = [base + k for k in range(8) if tree.live[base + k]]
+            if not kids:
+                continue
+            lp = np.stack([math.log(tree.pi[g]) + stats.multivariate_normal(tree.mu[g], _unpack(tree.cov[g])).logpdf(Y)
+                           for g in kids], axis=1)
+            post = np.exp(lp - logsumexp(lp, axis=1, keepdims=True))
+            parent = 1.0 if l == 0 else E[:, oracle_level_offset(l - 1) + grp]
+            for j, g in enumerate(kids):
+                E[:, g] = parent * post[:, j]
+    return E
+
+
+def oracle_level_offset(l):
+    return (8 ** (l + 1) - 8) // 7
+
+
+def test_soft_estep_unpruned_leaves_bruteforce(oracle_mod):
+    """tau -> 0, lambda_c = 0 on a 2-level tree: every point reaches every leaf
+    with the product of its two sibling posteriors; the mass is conserved."""
+    p = small_pair(21, n=1500)
+    tree, _ = oracle_mod.build_tree(p.src, 2)
+    R = rotation_from_axis_angle([0.1, 1.0, 0.3], 0.03)
+    t = np.array([0.01, 0.0, -0.01])
+    e = oracle_mod.estep_soft(tree, p.tgt, R, t, lambda_c=0.0, tau=1e-300)
+    Y = p.tgt.T.astype(np.float64) @ R.T + t
+    E = _path_expectations(tree, Y, 2)
+    leaves = [g for g in range(8, 72) if tree.live[g]]
+    np.testing.assert_allclose(e["bins"][leaves, 0], E[:, leaves].sum(0), rtol=1e-9, atol=1e-12)
+    for c in range(3):
+        np.testing.assert_allclose(e["bins"][leaves, 1 + c], (E[:, leaves] * Y[:, [c]]).sum(0), rtol=1e-8,
+                                   atol=1e-10)
+    np.testing.assert_allclose(e["bins"][:, 4], e["bins"][:, 0])
+    assert abs(e["bins"][:, 0].sum() - Y.shape[0]) < 1e-9
+    assert not np.any(e["bins"][:8])
+
+
+def test_soft_estep_pruning_bruteforce(oracle_mod):
+    """tau = 0.05: a leaf receives a point exactly when its own expectation and
+    its parent's are at least tau (expectations only shrink down a path)."""
+    p = small_pair(22, n=1500)
+    tree, _ = oracle_mod.build_tree(p.src, 2)
+    tau = 0.05
+    e = oracle_mod.estep_soft(tree, p.tgt, lambda_c=0.0, tau=tau)
+    Y = p.tgt.T.astype(np.float64)
+    E = _path_expectations(tree, Y, 2)
+    M0 = np.zeros(tree.n_nodes)
+    cnt = np.zeros(Y.shape[0], int)
+    for g in range(8, 72):
+        if not tree.live[g]:
+            continue
+        par = (g - 8) // 8
+        ok = (E[:, par] >= tau) & (E[:, g] >= tau)
+        M0[g] = E[ok, g].sum()
+        cnt += ok
+    far = e["margin"] > 1e-6
+    assert far.mean() > 0.95
+    np.testing.assert_allclose(e["bins"][8:72, 0], M0[8:72], rtol=1e-8, atol=1e-8)
+    np.testing.assert_array_equal(e["stops"][far], cnt[far])
+    assert e["bins"][:, 0].sum() < Y.shape[0]
+
+
+def test_soft_estep_stops_at_level0_is_soft_posterior(oracle_mod):
+    """lambda_c = 1 stops every followed node at level 0: the masses are the
+    sums of the level-0 posteriors (the E-step of a soft 8-component EM)."""
+    p = small_pair(23, n=1500)
+    tree, _ = oracle_mod.build_tree(p.src, 3)
+    e = oracle_mod.estep_soft(tree, p.tgt, lambda_c=1.0, tau=1e-300)
+    Y = p.tgt.T.astype(np.float64)
+    E = _path_expectations(tree, Y, 1)
+    np.testing.assert_allclose(e["bins"][:8, 0], E[:, :8].sum(0), rtol=1e-9, atol=1e-12)
+    assert not np.any(e["bins"][8:])
+    # every level-0 node whose posterior does not underflow is reached
+    reach = (E[:, :8] >= 1e-300).sum(1)
+    np.testing.assert_array_equal(e["stops"], reach)
+    assert reach.max() == int(np.sum(tree.live[:8]))
+
+
+def test_soft_register_exact_recovery_blob_tree(oracle_mod):
+    xyz, ids, _ = blob_tree_cloud(2)
+    tree, _ = oracle_mod.build_tree(xyz, 2)
+    Rg = rotation_from_axis_angle([2, -1, 0.5], math.radians(4))
+    tg = 0.015 * tree.extent * np.array([0.4, 0.2, -0.7])
+    tgt = (Rg @ xyz.astype(np.float64) + tg[:, None]).astype(np.float32)
+    r = oracle_mod.register_soft(tree, tgt, lambda_c=0.01, tau=0.01, max_iters=60, tol_rot=1e-13, tol_trans=1e-13)
+    assert r["status"] == 0 and r["iters"] < 60
+    np.testing.assert_allclose(r["R"], Rg.T, atol=1e-6)
+    np.testing.assert_allclose(r["t"], -Rg.T @ tg, atol=1e-6 * tree.extent)
