@@ -327,8 +327,10 @@ def variants_section(args, hg, tree, tgt, p, pr, steps):
     """The paper's registration variants on one tree of the main workload,
     registration alone from the identity (the tree built once, outside the
     timed region): adaptive descent (lambda_c as configured), the full tree
-    descent (lambda_c = 0, "GMM-Tree"), and the single-level mixture of every
-    node of one level ("GMM J=n", n = 8^(level+1)) with its linear scan."""
+    descent (lambda_c = 0, "GMM-Tree"), the soft multi-path descent (every
+    branch with path expectation >= 0.01, adaptive stop), and the single-level
+    mixture of every node of one level ("GMM J=n", n = 8^(level+1)) with its
+    linear scan."""
     import torch
     from synth import rotation_angle_deg
     dev = tgt.device
@@ -336,6 +338,7 @@ def variants_section(args, hg, tree, tgt, p, pr, steps):
     n = tgt.shape[1]
     runs = [("adaptive", "tree", pr["lambda_c"])]
     runs.append(("gmm_tree", "tree", 0.0))
+    runs.append(("adaptive_soft_tau0.01", "soft", 0.01))
     for lev in range(1, pr["levels"]):
         runs.append((f"gmm_j{8 ** (lev + 1)}", "flat", lev))
     out = {}
@@ -343,6 +346,9 @@ def variants_section(args, hg, tree, tgt, p, pr, steps):
         if kind == "tree":
             def reg():
                 return hg.hgmm_register(tree, tgt, lambda_c=arg, ws=ws, raise_singular=False)
+        elif kind == "soft":
+            def reg():
+                return hg.hgmm_register_soft(tree, tgt, arg, lambda_c=pr["lambda_c"], ws=ws, raise_singular=False)
         else:
             def reg():
                 return hg.hgmm_register_flat(tree, tgt, arg, ws=ws, raise_singular=False)
@@ -358,7 +364,7 @@ def variants_section(args, hg, tree, tgt, p, pr, steps):
         reg()
         torch.cuda.synchronize()
         hg.hgmm_profile(False)
-        k = hg.hgmm_profile_read("flat" if kind == "flat" else "descend")
+        k = hg.hgmm_profile_read(kind if kind in ("flat", "soft") else "descend")
         row = {"components": (8 ** (arg + 1)) if kind == "flat" else "adaptive" if arg > 0 else "leaves",
                "ms_per_registration": round(sec * 1e3, 3), "iters": int(r["iters"]),
                "rot_err_deg": round(rotation_angle_deg(r["R"], p.R_true), 4),

@@ -182,6 +182,29 @@ int hgmm_estep_flat(hgmm_tree tree, const float *d_xyz, int64_t n, int level, co
                     void *d_ws, size_t ws_bytes, void *stream, int32_t *d_stop_node, float *d_gamma,
                     double *d_bins, double *loglik);
 
+/* ---- soft multi-path E-step (Sec. 4.1, logarithmic search) --------------
+ * A point's expectation of a node is the product of its posteriors among the
+ * siblings along the path from the root (a parent's expectation is the sum
+ * of its children's).  Every branch whose expectation is at least tau
+ * (0 < tau < 1) is followed and a branch below tau is pruned with its
+ * subtree; a followed node that stops by Algorithm 1's rule (complexity <=
+ * lambda_c, no live children, or the last level) receives the point with its
+ * expectation E as the weight.  Per-node moments in the hgmm_estep layout
+ * with the expectation-weighted count and distance sum: {sum E, sum E (T(p) -
+ * mu_node) (3), sum E, sum E d_M^2}; the log-likelihood is the E-weighted mean
+ * log density.  d_stops (device int32, nullable) receives the number of nodes
+ * each point reached.  Registration runs the same M-step (Eq. 11-16).
+ * Outputs, workspace (hgmm_register_workspace_bytes), ownership and
+ * synchronisation as hgmm_register / hgmm_estep.  Errors: HGMM_EINVAL (null
+ * pointer, tau outside (0, 1), more than one tree in the handle, workspace too
+ * small), HGMM_ETOOFEW (n < 1), HGMM_ESINGULAR, HGMM_EHIP. */
+int hgmm_register_soft(hgmm_tree tree, const float *d_xyz, int64_t n, double tau, const hgmm_reg_params *p,
+                       const double *R0, const double *t0, void *d_ws, size_t ws_bytes, void *stream, double R[9],
+                       double t[3], int *iters, double *loglik);
+int hgmm_estep_soft(hgmm_tree tree, const float *d_xyz, int64_t n, double tau, const double R[9], const double t[3],
+                    double lambda_c, void *d_ws, size_t ws_bytes, void *stream, int32_t *d_stops, double *d_bins,
+                    double *loglik);
+
 /* The PCA-form normal equations (Eq. 11-16) of one M-step from per-node
  * moments in the hgmm_estep layout (device): H (6x6 row-major, host) and g
  * (6, host) with H x = g for the increment x = (omega, tau) of
@@ -399,7 +422,8 @@ int hgmm_autotune(const float *d_src, const int64_t *src_offsets, const int32_t 
  * once) are not counted.  Kinds: 0 construction EM tile iteration,
  * 1 construction EM in one block per parent, 2 partition, 3 stable split, 4 registration
  * descent, 5 normal equations + solve, 6 root statistics, 7 construction
- * M-step of the tiled parents (units: parents), 8 single-level E-step.  Process-wide, not
+ * M-step of the tiled parents (units: parents), 8 single-level E-step,
+ * 9 soft multi-path E-step.  Process-wide, not
  * thread-safe. */
 int hgmm_profile(int enable);
 void hgmm_profile_reset(void);

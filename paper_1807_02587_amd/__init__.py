@@ -11,6 +11,8 @@ from .api import (  # noqa: F401
     Workspace,
     hgmm_build,
     hgmm_register_flat,
+    hgmm_register_soft,
+    hgmm_estep_soft,
     hgmm_odometry,
     hgmm_estep_flat,
     hgmm_register,

@@ -48,6 +48,8 @@ SIGNATURES = {
     "hgmm_estep": (C.c_int, [P, P, I64, P, P, D, P, C.c_size_t, P, P, P, P, P]),
     "hgmm_register_flat": (C.c_int, [P, P, I64, C.c_int, P, P, P, P, C.c_size_t, P, P, P, P, P]),
     "hgmm_estep_flat": (C.c_int, [P, P, I64, C.c_int, P, P, P, C.c_size_t, P, P, P, P, P]),
+    "hgmm_register_soft": (C.c_int, [P, P, I64, D, P, P, P, P, C.c_size_t, P, P, P, P, P]),
+    "hgmm_estep_soft": (C.c_int, [P, P, I64, D, P, P, D, P, C.c_size_t, P, P, P, P]),
     "hgmm_normal_equations": (C.c_int, [P, P, I64, P, C.c_size_t, P, P, P]),
     "hgmm_tree_export": (C.c_int, [P, C.c_int, P]),
     "hgmm_tree_labels": (C.c_int, [P, C.c_int, P, P]),

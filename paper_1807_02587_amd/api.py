@@ -302,6 +302,52 @@ def hgmm_estep_flat(tree: Tree, xyz: torch.Tensor, level: int, R=None, t=None, w
     return dict(stop_node=stop, gamma=gam, bins=bins, loglik=ll.value if loglik else None)
 
 
+def hgmm_register_soft(tree: Tree, xyz: torch.Tensor, tau: float = 0.01, max_iters: int = 30,
+                       lambda_c: float = 0.01, tol_rot: float = 1e-6, tol_trans_rel: float = 1e-6, R0=None, t0=None,
+                       ws: Workspace | None = None, stream=None, raise_singular: bool = True) -> dict:
+    """Registration with the soft multi-path E-step (branches with path expectation >= tau)."""
+    xyz = _cloud(xyz)
+    lib = _lib.load()
+    n = xyz.shape[1]
+    p = RegParams(max_iters, 0, lambda_c, tol_rot, tol_trans_rel)
+    R0a, t0a = _pose_args(R0, t0)
+    ws = ws or Workspace(xyz.device)
+    wptr, wlen = ws.ptr(lib.hgmm_register_workspace_bytes(n, tree.levels))
+    R = np.zeros(9)
+    t = np.zeros(3)
+    iters = C.c_int(0)
+    ll = C.c_double(0)
+    rc = lib.hgmm_register_soft(tree.handle, C.c_void_p(xyz.data_ptr()), n, float(tau), C.byref(p),
+                                None if R0a is None else R0a.ctypes.data_as(C.c_void_p),
+                                None if t0a is None else t0a.ctypes.data_as(C.c_void_p), wptr, wlen, _stream(stream),
+                                R.ctypes.data_as(C.c_void_p), t.ctypes.data_as(C.c_void_p), C.byref(iters),
+                                C.byref(ll))
+    if rc != 0 and (raise_singular or rc != -6):
+        check(rc, "hgmm_register_soft")
+    return dict(R=R.reshape(3, 3), t=t, iters=iters.value, loglik=ll.value, status=rc)
+
+
+def hgmm_estep_soft(tree: Tree, xyz: torch.Tensor, tau: float = 0.01, R=None, t=None, lambda_c: float = 0.01,
+                    ws: Workspace | None = None, points: bool = True, loglik: bool = True, stream=None) -> dict:
+    """One soft multi-path E-step at a fixed transform: per-node bins and, per
+    point, the number of nodes reached."""
+    xyz = _cloud(xyz)
+    lib = _lib.load()
+    n = xyz.shape[1]
+    Ra, ta = _pose_args(np.eye(3) if R is None else R, np.zeros(3) if t is None else t)
+    ws = ws or Workspace(xyz.device)
+    wptr, wlen = ws.ptr(lib.hgmm_register_workspace_bytes(n, tree.levels))
+    bins = torch.empty((hgmm_tree_nodes(tree.levels), 6), dtype=torch.float64, device=xyz.device)
+    stops = torch.empty(n, dtype=torch.int32, device=xyz.device) if points else None
+    ll = C.c_double(0)
+    check(lib.hgmm_estep_soft(tree.handle, C.c_void_p(xyz.data_ptr()), n, float(tau), Ra.ctypes.data_as(C.c_void_p),
+                              ta.ctypes.data_as(C.c_void_p), float(lambda_c), wptr, wlen, _stream(stream),
+                              None if stops is None else C.c_void_p(stops.data_ptr()), C.c_void_p(bins.data_ptr()),
+                              C.byref(ll) if loglik else None), "hgmm_estep_soft")
+    torch.cuda.current_stream().synchronize()
+    return dict(stops=stops, bins=bins, loglik=ll.value if loglik else None)
+
+
 def hgmm_normal_equations(tree: Tree, bins: torch.Tensor, n: int, ws: Workspace | None = None, stream=None):
     lib = _lib.load()
     if not (bins.is_cuda and bins.dtype == torch.float64 and bins.is_contiguous()):
@@ -338,7 +384,7 @@ def hgmm_tree_import(src, stream=None) -> Tree:
 
 
 PROFILE_KINDS = {"em_tile": 0, "em_block": 1, "partition": 2, "scatter": 3, "descend": 4, "normal": 5, "root": 6,
-                 "em_mstep": 7, "flat": 8}
+                 "em_mstep": 7, "flat": 8, "soft": 9}
 
 
 def hgmm_profile(enable: bool = True) -> None:

@@ -360,7 +360,7 @@ static int tile_points(int64_t level_points) {
 // ---------------------------------------------------------------------------
 
 enum ProfKind { PK_EM_TILE = 0, PK_EM_BLOCK, PK_PARTITION, PK_SCATTER, PK_DESCEND, PK_NORMAL, PK_ROOT, PK_EM_MSTEP,
-                PK_FLAT, PK_COUNT };
+                PK_FLAT, PK_SOFT, PK_COUNT };
 
 struct ProfPending {
   int kind;
@@ -949,6 +949,7 @@ struct RegRun {
   double lambda_c, tol_rot, tol_trans_rel;
   int max_levels;  // 0: every level of the tree
   int flat_level = -1;  // >= 0: single-level E-step over this level instead of the descent
+  double soft_tau = 0.0;  // > 0: soft multi-path E-step with this pruning threshold instead of the descent
 };
 
 static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, const float* zs,
@@ -1041,12 +1042,16 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   HIP_LAUNCHED();
   const size_t pstride = (size_t)Ly.max_tiles;
   const bool flat = rr.flat_level >= 0;
+  const bool soft = rr.soft_tau > 0.0;
   // one E-step launch (descent, or the single-level scan) and one M-step launch
   NodeF* d_flatf = (NodeF*)(ws + Ly.flatf);
   NodeS* d_flats = (NodeS*)(ws + Ly.flats);
   if (flat) launch_flat_table(f->d_tab, f->d_nodes, d_flatf, d_flats, nodes_total, s);
   auto estep = [&](hipStream_t q, int32_t* so, float* go, const int* pm) {
-    if (flat)
+    if (soft)
+      launch_soft_estep(xs, ys, zs, d_tiles, ntiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins,
+                        (float)rr.soft_tau, so, pm, q);
+    else if (flat)
       launch_flat_estep(xs, ys, zs, d_tiles, ntiles, rt, f->d_trees, d_flatf, d_flats, d_state, d_bins, so, go, pm,
                         rr.flat_level, q);
     else
@@ -1054,12 +1059,13 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
                      pstride, so, go, pm, g_tune.reg_lds_levels, rr.max_levels, q);
   };
   auto mstep = [&](hipStream_t q) {
-    launch_normal(d_bins, d_dpart, pstride, d_ptiles, f->d_nodes, f->d_trees, d_state, d_nmov, P, flat ? 2 : 0,
+    launch_normal(d_bins, d_dpart, pstride, d_ptiles, f->d_nodes, f->d_trees, d_state, d_nmov, P,
+                  (flat || soft) ? 2 : 0,
                   rr.tol_rot, rr.tol_trans_rel, rr.max_iters, d_out, q);
   };
   if (mode_estep) {
     estep(s, stop_out, gamma_out, d_perm);
-    if (!flat) launch_fold_bins(d_ptiles, f->d_trees, d_dpart, pstride, d_bins, P, s);
+    if (!flat && !soft) launch_fold_bins(d_ptiles, f->d_trees, d_dpart, pstride, d_bins, P, s);
     if (h_norm) {
       launch_normal(d_bins, d_dpart, pstride, d_ptiles, f->d_nodes, f->d_trees, d_state, d_nmov, P, 1, 0.0, 0.0, 1,
                     d_out, s);
@@ -1077,7 +1083,8 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   if (g_tune.reg_graph && !g_prof.on) {
     int rc2 = ensure_graph_stream(f);
     if (rc2) return rc2;
-    uint64_t tr, tt;
+    uint64_t tr, tt, soft_key;
+    memcpy(&soft_key, &rr.soft_tau, 8);
     memcpy(&tr, &rr.tol_rot, 8);
     memcpy(&tt, &rr.tol_trans_rel, 8);
     const std::vector<uint64_t> key = {(uint64_t)xs, (uint64_t)ys, (uint64_t)zs, (uint64_t)d_tiles, (uint64_t)ntiles,
@@ -1085,7 +1092,7 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
                                        (uint64_t)d_state, (uint64_t)d_bins, (uint64_t)d_dpart, (uint64_t)pstride,
                                        (uint64_t)d_ptiles, (uint64_t)d_nmov, (uint64_t)P, (uint64_t)chunk, tr, tt,
                                        (uint64_t)rr.max_iters, (uint64_t)rr.max_levels, (uint64_t)d_out,
-                                       (uint64_t)(int64_t)rr.flat_level};
+                                       (uint64_t)(int64_t)rr.flat_level, soft_key};
     if (!f->reg_exec || f->reg_key != key) {
       if (f->reg_exec) { (void)hipGraphExecDestroy(f->reg_exec); f->reg_exec = nullptr; }
       f->reg_key.clear();
@@ -1122,7 +1129,7 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
     const int end = std::min(rr.max_iters, it + chunk);
     for (; it < end; ++it) {
       {
-        ProfScope ps(flat ? PK_FLAT : PK_DESCEND, (double)n_total, s, it);
+        ProfScope ps(soft ? PK_SOFT : flat ? PK_FLAT : PK_DESCEND, (double)n_total, s, it);
         estep(s, nullptr, nullptr, nullptr);
       }
       {
@@ -1307,6 +1314,54 @@ int hgmm_estep_flat(hgmm_tree tree, const float* d_xyz, int64_t n, int level, co
   double nrm[28];
   rc = run_register(tree, d_xyz, d_xyz + n, d_xyz + 2 * n, offs, R, t, 0, rr, (char*)d_ws, ws_bytes,
                     (hipStream_t)stream, 1, d_stop_node, d_gamma, d_bins, nullptr, loglik ? nrm : nullptr);
+  if (rc) return rc;
+  if (loglik) *loglik = nrm[27];
+  return HGMM_OK;
+}
+
+static int check_tau(double tau) {
+  if (!(tau > 0.0 && tau < 1.0)) return fail(HGMM_EINVAL, "pruning threshold tau must be in (0, 1)");
+  return HGMM_OK;
+}
+
+int hgmm_register_soft(hgmm_tree tree, const float* d_xyz, int64_t n, double tau, const hgmm_reg_params* p,
+                       const double* R0, const double* t0, void* d_ws, size_t ws_bytes, void* stream, double R[9],
+                       double t[3], int* iters, double* loglik) {
+  if (n < 1) return fail(HGMM_ETOOFEW, "empty cloud");
+  if (!tree || !d_xyz || !p || !d_ws || !R || !t || !iters) return fail(HGMM_EINVAL, "null pointer argument");
+  if (n > (int64_t)INT32_MAX / 2) return fail(HGMM_EINVAL, "too many points");
+  if (p->max_iters < 1) return fail(HGMM_EINVAL, "max_iters must be >= 1");
+  if (tree->trees.size() != 1) return fail(HGMM_EINVAL, "hgmm_register_soft takes a single-tree handle");
+  int rc = check_tau(tau);
+  if (rc) return rc;
+  std::vector<int64_t> offs = {0, n};
+  RegRun rr{p->max_iters, p->lambda_c, p->tol_rot, p->tol_trans_rel, 0, -1, tau};
+  PoseState res;
+  rc = run_register(tree, d_xyz, d_xyz + n, d_xyz + 2 * n, offs, R0, t0, 0, rr, (char*)d_ws, ws_bytes,
+                    (hipStream_t)stream, 0, nullptr, nullptr, nullptr, &res, nullptr);
+  if (rc) return rc;
+  for (int i = 0; i < 9; ++i) R[i] = res.R[i];
+  for (int i = 0; i < 3; ++i) t[i] = res.t[i];
+  *iters = res.iters;
+  if (loglik) *loglik = res.loglik;
+  if (res.status != 0) return fail(res.status, "normal equations not positive definite at iteration %d", res.iters);
+  return HGMM_OK;
+}
+
+int hgmm_estep_soft(hgmm_tree tree, const float* d_xyz, int64_t n, double tau, const double R[9], const double t[3],
+                    double lambda_c, void* d_ws, size_t ws_bytes, void* stream, int32_t* d_stops, double* d_bins,
+                    double* loglik) {
+  if (!tree || !d_xyz || !R || !t || !d_ws) return fail(HGMM_EINVAL, "null pointer argument");
+  if (n < 1) return fail(HGMM_ETOOFEW, "empty cloud");
+  if (n > (int64_t)INT32_MAX / 2) return fail(HGMM_EINVAL, "too many points");
+  if (tree->trees.size() != 1) return fail(HGMM_EINVAL, "hgmm_estep_soft takes a single-tree handle");
+  int rc = check_tau(tau);
+  if (rc) return rc;
+  std::vector<int64_t> offs = {0, n};
+  RegRun rr{1, lambda_c, 0.0, 0.0, 0, -1, tau};
+  double nrm[28];
+  rc = run_register(tree, d_xyz, d_xyz + n, d_xyz + 2 * n, offs, R, t, 0, rr, (char*)d_ws, ws_bytes,
+                    (hipStream_t)stream, 1, d_stops, nullptr, d_bins, nullptr, loglik ? nrm : nullptr);
   if (rc) return rc;
   if (loglik) *loglik = nrm[27];
   return HGMM_OK;

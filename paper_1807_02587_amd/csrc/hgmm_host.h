@@ -69,6 +69,9 @@ void launch_flat_estep(const float* xs, const float* ys, const float* zs, const 
                        int tile_points, const TreeDev* trees, const NodeF* tab, const NodeS* nodes,
                        const PoseState* st, double* bins, int32_t* stop_out, float* gamma_out, const int* perm,
                        int level, hipStream_t s);
+void launch_soft_estep(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
+                       const TreeDev* trees, const NodeF* tab, const NodeD* nodes, const PoseState* st, double* bins,
+                       float tau, int32_t* stops_out, const int* perm, hipStream_t s);
 void launch_fold_bins(const int2* pair_tiles, const TreeDev* trees, const double* partials, size_t pstride,
                       double* bins, int npairs, hipStream_t s);
 void launch_normal(double* bins, const double* dpart, size_t pstride, const int2* pair_tiles, const NodeD* nodes,

@@ -36,7 +36,7 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 KERNEL_SOURCES = ("build_kernels.hip", "register_kernels.hip", "hgmm_dev.h")
 FAMILIES = {"em_block": "em_block_kernel", "em_tile": "em_tile_kernel", "em_mstep": "em_mstep_kernel",
             "descend": "descend_kernel", "normal": "normal_kernel", "partition": "partition_kernel",
-            "flat": "flat_estep_kernel"}
+            "flat": "flat_estep_kernel", "soft": "soft_estep_kernel"}
 
 
 def _short(name: str) -> str:
