@@ -182,6 +182,21 @@ int hgmm_estep_flat(hgmm_tree tree, const float *d_xyz, int64_t n, int level, co
                     void *d_ws, size_t ws_bytes, void *stream, int32_t *d_stop_node, float *d_gamma,
                     double *d_bins, double *loglik);
 
+/* ---- queries for other consumers of the tree (Sec. 6) -------------------
+ * The log density of every point of d_xyz (n points, SoA FP32, device) under
+ * the tree at the node the adaptive descent of Algorithm 1 stops at (lambda_c
+ * as in hgmm_reg_params), after the transform T(p) = R p + t (host R, t):
+ * d_loglik[i] = log pi^g - log|cov| / 2 - d_M^2 / 2 - 3/2 log 2 pi (device
+ * float, -inf for a point with no live node), and the stop node in d_node
+ * (device int32, nullable; node index inside the tree).  The mean of d_loglik
+ * is hgmm_estep's log-likelihood.  For scoring a scan against a map tree
+ * (loop closure) or per-point occupancy.  Workspace:
+ * hgmm_register_workspace_bytes.  Asynchronous on `stream`.  Errors:
+ * HGMM_EINVAL (null pointer, more than one tree, workspace too small),
+ * HGMM_ETOOFEW (n < 1), HGMM_EHIP. */
+int hgmm_point_loglik(hgmm_tree tree, const float *d_xyz, int64_t n, const double R[9], const double t[3],
+                      double lambda_c, void *d_ws, size_t ws_bytes, void *stream, int32_t *d_node, float *d_loglik);
+
 /* ---- soft multi-path E-step (Sec. 4.1, logarithmic search) --------------
  * A point's expectation of a node is the product of its posteriors among the
  * siblings along the path from the root (a parent's expectation is the sum

@@ -11,6 +11,7 @@ from .api import (  # noqa: F401
     Workspace,
     hgmm_build,
     hgmm_register_flat,
+    hgmm_point_loglik,
     hgmm_register_soft,
     hgmm_estep_soft,
     hgmm_odometry,

@@ -49,6 +49,7 @@ SIGNATURES = {
     "hgmm_register_flat": (C.c_int, [P, P, I64, C.c_int, P, P, P, P, C.c_size_t, P, P, P, P, P]),
     "hgmm_estep_flat": (C.c_int, [P, P, I64, C.c_int, P, P, P, C.c_size_t, P, P, P, P, P]),
     "hgmm_register_soft": (C.c_int, [P, P, I64, D, P, P, P, P, C.c_size_t, P, P, P, P, P]),
+    "hgmm_point_loglik": (C.c_int, [P, P, I64, P, P, D, P, C.c_size_t, P, P, P]),
     "hgmm_estep_soft": (C.c_int, [P, P, I64, D, P, P, D, P, C.c_size_t, P, P, P, P]),
     "hgmm_normal_equations": (C.c_int, [P, P, I64, P, C.c_size_t, P, P, P]),
     "hgmm_tree_export": (C.c_int, [P, C.c_int, P]),

@@ -348,6 +348,24 @@ def hgmm_estep_soft(tree: Tree, xyz: torch.Tensor, tau: float = 0.01, R=None, t=
     return dict(stops=stops, bins=bins, loglik=ll.value if loglik else None)
 
 
+def hgmm_point_loglik(tree: Tree, xyz: torch.Tensor, R=None, t=None, lambda_c: float = 0.01,
+                      ws: Workspace | None = None, stream=None):
+    """Per-point log density under the tree at the adaptive stop node (float32
+    CUDA tensor) and the stop nodes (int32)."""
+    xyz = _cloud(xyz)
+    lib = _lib.load()
+    n = xyz.shape[1]
+    Ra, ta = _pose_args(np.eye(3) if R is None else R, np.zeros(3) if t is None else t)
+    ws = ws or Workspace(xyz.device)
+    wptr, wlen = ws.ptr(lib.hgmm_register_workspace_bytes(n, tree.levels))
+    ll = torch.empty(n, dtype=torch.float32, device=xyz.device)
+    node = torch.empty(n, dtype=torch.int32, device=xyz.device)
+    check(lib.hgmm_point_loglik(tree.handle, C.c_void_p(xyz.data_ptr()), n, Ra.ctypes.data_as(C.c_void_p),
+                                ta.ctypes.data_as(C.c_void_p), float(lambda_c), wptr, wlen, _stream(stream),
+                                C.c_void_p(node.data_ptr()), C.c_void_p(ll.data_ptr())), "hgmm_point_loglik")
+    return ll, node
+
+
 def hgmm_normal_equations(tree: Tree, bins: torch.Tensor, n: int, ws: Workspace | None = None, stream=None):
     lib = _lib.load()
     if not (bins.is_cuda and bins.dtype == torch.float64 and bins.is_contiguous()):

@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhgmm.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 SOURCES = ["build_kernels.hip", "register_kernels.hip", "warm_kernels.hip", "mlp_api.hip", "hgmm_api.hip",
-           "hgmm_autotune.hip", "sort_points.hip", "soft_kernels.hip"]
+           "hgmm_autotune.hip", "sort_points.hip", "soft_kernels.hip",
+           "query_kernels.hip"]
 ARCH = "gfx950"
 
 

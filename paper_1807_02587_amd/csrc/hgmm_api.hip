@@ -1319,6 +1319,28 @@ int hgmm_estep_flat(hgmm_tree tree, const float* d_xyz, int64_t n, int level, co
   return HGMM_OK;
 }
 
+int hgmm_point_loglik(hgmm_tree tree, const float* d_xyz, int64_t n, const double R[9], const double t[3],
+                      double lambda_c, void* d_ws, size_t ws_bytes, void* stream, int32_t* d_node, float* d_loglik) {
+  if (!tree || !d_xyz || !R || !t || !d_ws || !d_loglik) return fail(HGMM_EINVAL, "null pointer argument");
+  if (n < 1) return fail(HGMM_ETOOFEW, "empty cloud");
+  if (n > (int64_t)INT32_MAX / 2) return fail(HGMM_EINVAL, "too many points");
+  if (tree->trees.size() != 1) return fail(HGMM_EINVAL, "hgmm_point_loglik takes a single-tree handle");
+  const RegLayout Ly = reg_layout(n, tree->total_nodes(), 1);
+  if (ws_bytes < Ly.total) return fail(HGMM_EINVAL, "workspace too small: %zu < %zu", ws_bytes, Ly.total);
+  // stop nodes in the caller's buffer, else in the sort's value scratch (free
+  // once the points are ordered)
+  int32_t* stop = d_node ? d_node : (int32_t*)((char*)d_ws + Ly.vals);
+  std::vector<int64_t> offs = {0, n};
+  RegRun rr{1, lambda_c, 0.0, 0.0, 0};
+  int rc = run_register(tree, d_xyz, d_xyz + n, d_xyz + 2 * n, offs, R, t, 0, rr, (char*)d_ws, ws_bytes,
+                        (hipStream_t)stream, 1, stop, nullptr, nullptr, nullptr, nullptr);
+  if (rc) return rc;
+  launch_point_loglik(d_xyz, d_xyz + n, d_xyz + 2 * n, n, stop, tree->d_trees, tree->d_nodes,
+                      (const PoseState*)((char*)d_ws + Ly.state), d_loglik, (hipStream_t)stream);
+  HIP_LAUNCHED();
+  return HGMM_OK;
+}
+
 static int check_tau(double tau) {
   if (!(tau > 0.0 && tau < 1.0)) return fail(HGMM_EINVAL, "pruning threshold tau must be in (0, 1)");
   return HGMM_OK;
