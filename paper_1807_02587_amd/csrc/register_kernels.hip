@@ -447,9 +447,9 @@ __device__ __forceinline__ void flat_merge(FlatState& a, const FlatState& b) {
 
 // Grid (tiles, sub-blocks): block (x, y) takes the 64 P points of tile x from
 // tl.start + 64 P y.  Its 4 waves each scan a quarter of the components for
-// all of those points (P per lane), the component records read as
-// wave-uniform (scalar) loads; the four partial states are merged in LDS in
-// component order, and the first 64 P threads finish one point each.
+// all of those points (P per lane), the quarter staged through LDS and read
+// as broadcasts; the four partial states are merged in LDS in component
+// order, and the first 64 P threads finish one point each.
 template <int P>
 __global__ __launch_bounds__(256) void flat_estep_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
                                                          const float* __restrict__ zs, const Tile* __restrict__ tiles,

@@ -33,7 +33,7 @@ import os
 import sys
 
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
-KERNEL_SOURCES = ("build_kernels.hip", "register_kernels.hip", "hgmm_dev.h")
+KERNEL_SOURCES = ("build_kernels.hip", "register_kernels.hip", "soft_kernels.hip", "query_kernels.hip", "hgmm_dev.h")
 FAMILIES = {"em_block": "em_block_kernel", "em_tile": "em_tile_kernel", "em_mstep": "em_mstep_kernel",
             "descend": "descend_kernel", "normal": "normal_kernel", "partition": "partition_kernel",
             "flat": "flat_estep_kernel", "soft": "soft_estep_kernel"}
