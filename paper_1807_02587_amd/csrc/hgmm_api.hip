@@ -1043,13 +1043,16 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   const size_t pstride = (size_t)Ly.max_tiles;
   const bool flat = rr.flat_level >= 0;
   const bool soft = rr.soft_tau > 0.0;
+  int max_tree_levels = 1;
+  for (auto& tr : f->trees) max_tree_levels = std::max(max_tree_levels, tr.levels);
   // one E-step launch (descent, or the single-level scan) and one M-step launch
   NodeF* d_flatf = (NodeF*)(ws + Ly.flatf);
   NodeS* d_flats = (NodeS*)(ws + Ly.flats);
   if (flat) launch_flat_table(f->d_tab, f->d_nodes, d_flatf, d_flats, nodes_total, s);
   auto estep = [&](hipStream_t q, int32_t* so, float* go, const int* pm) {
     if (soft)
-      launch_soft_estep(xs, ys, zs, d_tiles, ntiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins,
+      launch_soft_estep(xs, ys, zs, d_tiles, ntiles, rt, max_tree_levels, f->d_trees, f->d_tab, f->d_nodes, d_state,
+                        d_bins,
                         (float)rr.soft_tau, so, pm, q);
     else if (flat)
       launch_flat_estep(xs, ys, zs, d_tiles, ntiles, rt, f->d_trees, d_flatf, d_flats, d_state, d_bins, so, go, pm,

@@ -70,8 +70,9 @@ void launch_flat_estep(const float* xs, const float* ys, const float* zs, const 
                        const PoseState* st, double* bins, int32_t* stop_out, float* gamma_out, const int* perm,
                        int level, hipStream_t s);
 void launch_soft_estep(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
-                       const TreeDev* trees, const NodeF* tab, const NodeD* nodes, const PoseState* st, double* bins,
-                       float tau, int32_t* stops_out, const int* perm, hipStream_t s);
+                       int tile_points, int max_levels, const TreeDev* trees, const NodeF* tab, const NodeD* nodes,
+                       const PoseState* st, double* bins, float tau, int32_t* stops_out, const int* perm,
+                       hipStream_t s);
 void launch_point_loglik(const float* xs, const float* ys, const float* zs, int64_t n, const int32_t* stop,
                          const TreeDev* trees, const NodeD* nodes, const PoseState* st, float* out, hipStream_t s);
 void launch_fold_bins(const int2* pair_tiles, const TreeDev* trees, const double* partials, size_t pstride,
