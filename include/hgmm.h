@@ -375,8 +375,10 @@ void hgmm_tree_destroy(hgmm_tree tree);
  * jobs, classes and tiles as the host planner) and runs all launches of a
  * construction as one hipGraph, captured on the first call of a shape (cloud
  * sizes and depths, buffers, parameters, launch shapes) and cached in the
- * handle; no host round trip between levels.  Results equal those of
- * build_graph = 0.  It is not used while hgmm_profile is on.
+ * handle; no host round trip between levels.  build_graph = 2 issues the
+ * same device-planned launches directly on the stream, without a graph (no
+ * capture, no graph launch; the host enqueues while the GPU runs).  Results
+ * equal those of build_graph = 0.  Neither is used while hgmm_profile is on.
  * Defaults 256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0, 256, 2, 0. */
 typedef struct hgmm_tuning {
   int32_t block64_max, block256_max, block512_max;
@@ -386,21 +388,23 @@ typedef struct hgmm_tuning {
   int32_t reg_sort;   /* 1: the moving cloud is put in Morton order once per registration call */
   int32_t tile_threads; /* threads per construction tile: 256, 512 or 1024 */
   int32_t reg_lds_levels; /* tree levels whose scoring records the descent stages in LDS: 2 or 3 */
-  int32_t build_graph;    /* 1: construction planned on the device and run as one hipGraph */
+  int32_t build_graph;    /* 1: construction planned on the device and run as one hipGraph; 2: the same
+                             device-planned launches issued on the stream */
 } hgmm_tuning;
 
-/* Constructions of a handle so far: those run as a replay of its cached
- * construction graph (build_graph = 1), the graphs captured, and those
- * planned on the host (build_graph = 0, the first construction of a new shape
- * with build_graph = 1, and one whose plan had work where the graph's did
- * not).  Host outputs; HGMM_EINVAL on a null argument. */
+/* Constructions of a handle so far: those planned on the device (a replay of
+ * its cached construction graph with build_graph = 1, or the same launches on
+ * the stream with build_graph = 2), the graphs captured, and those planned on
+ * the host (build_graph = 0, the first construction of a new shape with
+ * build_graph = 1 or 2, and one whose plan had work where the device-planned
+ * launches had none).  Host outputs; HGMM_EINVAL on a null argument. */
 int hgmm_build_graph_stats(hgmm_tree tree, int64_t *replays, int64_t *captures, int64_t *host_builds);
 
 /* Set (after validation) or read the launch shapes.  hgmm_set_tuning returns
  * HGMM_EINVAL, changing nothing, unless 0 <= block64_max <= block256_max <=
  * block512_max <= 1<<20, 64 <= min_tile <= max_tile <= 1<<20,
  * target_tiles >= 1, 256 <= reg_tile <= 1<<20, 1 <= reg_chunk <= 64 and
- * reg_graph, reg_sort, build_graph in {0, 1}, tile_threads in
+ * reg_graph, reg_sort in {0, 1}, build_graph in {0, 1, 2}, tile_threads in
  * {256, 512, 1024} and reg_lds_levels in {2, 3}.
  * Values are rounded up to the multiples stated above.  Not thread-safe
  * against concurrent calls of the library. */

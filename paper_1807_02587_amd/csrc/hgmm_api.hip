@@ -100,6 +100,7 @@ struct hgmm_forest_s {
   std::vector<uint64_t> reg_key;
   // construction graph (build_graph = 1): every level planned on the device,
   // all launches of a construction in one graph, cached for the same shapes
+  // (build_graph = 2: the same launches issued on the stream, no graph)
   hipGraphExec_t bld_exec = nullptr;
   std::vector<uint64_t> bld_key;
   // per-level work counts of the last host-planned construction (njobs,
@@ -333,7 +334,7 @@ extern "C" int hgmm_set_tuning(const hgmm_tuning* t) {
   if (t->tile_threads != 256 && t->tile_threads != 512 && t->tile_threads != 1024)
     return fail(HGMM_EINVAL, "tile_threads must be 256, 512 or 1024");
   if (t->reg_lds_levels != 2 && t->reg_lds_levels != 3) return fail(HGMM_EINVAL, "reg_lds_levels must be 2 or 3");
-  if (t->build_graph != 0 && t->build_graph != 1) return fail(HGMM_EINVAL, "build_graph must be 0 or 1");
+  if (t->build_graph < 0 || t->build_graph > 2) return fail(HGMM_EINVAL, "build_graph must be 0, 1 or 2");
   g_tune = *t;
   g_tune.min_tile = (t->min_tile + 63) / 64 * 64;
   g_tune.max_tile = (t->max_tile + 63) / 64 * 64;
@@ -830,15 +831,14 @@ static int run_build_graph(hgmm_forest_s* f, BuildInput in, const hgmm_build_par
   for (auto& h : hint)
     for (int v : h) key.push_back((uint64_t)(uint32_t)v);
 
-  if (!f->bld_exec || f->bld_key != key) {
-    if (f->bld_exec) { (void)hipGraphExecDestroy(f->bld_exec); f->bld_exec = nullptr; }
-    f->bld_key.clear();
+  // every launch of a construction with device-planned levels, on stream gs
+  // (side streams for the block classes); returns false if an event call failed
+  auto enqueue = [&](hipStream_t gs) -> bool {
     // grids from the hinted work counts with some slack; the kernels loop
     // over their work items, so any count is covered
     const int mj = (int)Ly.max_jobs, mt = (int)Ly.max_tiles;
     auto grid = [](int h, int cap) { return std::max(1, std::min(cap, h + h / 8 + 8)); };
     const int nts[3] = {64, 256, 512};
-    HIP_TRY(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
     const int64_t nodes_total = f->total_nodes();
     launch_fill_u32(f->d_nodes, 0u, (int64_t)(sizeof(NodeD) / 4) * nodes_total, gs);
     launch_fill_u32(f->d_tab, 0u, (int64_t)(sizeof(NodeF) / 4) * nodes_total, gs);
@@ -900,6 +900,24 @@ static int run_build_graph(hgmm_forest_s* f, BuildInput in, const hgmm_build_par
       cperm = perm[ping];
       ping ^= 1;
     }
+    return ok;
+  };
+  const bool stream_mode = g_tune.build_graph == 2;
+  if (stream_mode) {
+    // the same launches without a graph: the inputs, then the launches on the
+    // handle's stream, with no host round trip between levels
+    HIP_TRY(hipMemcpyAsync(f->d_trees, h_trees, sizeof(TreeDev) * B, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_lt, h_lt, sizeof(LevelTree) * (size_t)std::max(lt_off[Lmax], 1), hipMemcpyHostToDevice,
+                           s));
+    HIP_TRY(hipEventRecord(f->ev_g0, s));
+    HIP_TRY(hipStreamWaitEvent(gs, f->ev_g0, 0));
+    if (!enqueue(gs)) return fail(HGMM_EHIP, "construction launch sequence failed");
+    HIP_LAUNCHED();
+  } else if (!f->bld_exec || f->bld_key != key) {
+    if (f->bld_exec) { (void)hipGraphExecDestroy(f->bld_exec); f->bld_exec = nullptr; }
+    f->bld_key.clear();
+    HIP_TRY(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+    const bool ok = enqueue(gs);
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(gs, &graph);
     if (!ok || ec != hipSuccess || !graph) {
@@ -912,12 +930,15 @@ static int run_build_graph(hgmm_forest_s* f, BuildInput in, const hgmm_build_par
     f->bld_key = key;
     f->n_graph_captures += 1;
   }
-  // inputs of this call, then the graph on the handle's stream
-  HIP_TRY(hipMemcpyAsync(f->d_trees, h_trees, sizeof(TreeDev) * B, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(d_lt, h_lt, sizeof(LevelTree) * (size_t)std::max(lt_off[Lmax], 1), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipEventRecord(f->ev_g0, s));
-  HIP_TRY(hipStreamWaitEvent(gs, f->ev_g0, 0));
-  HIP_TRY(hipGraphLaunch(f->bld_exec, gs));
+  if (!stream_mode) {
+    // inputs of this call, then the graph on the handle's stream
+    HIP_TRY(hipMemcpyAsync(f->d_trees, h_trees, sizeof(TreeDev) * B, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_lt, h_lt, sizeof(LevelTree) * (size_t)std::max(lt_off[Lmax], 1), hipMemcpyHostToDevice,
+                           s));
+    HIP_TRY(hipEventRecord(f->ev_g0, s));
+    HIP_TRY(hipStreamWaitEvent(gs, f->ev_g0, 0));
+    HIP_TRY(hipGraphLaunch(f->bld_exec, gs));
+  }
   HIP_TRY(hipEventRecord(f->ev_g1, gs));
   HIP_TRY(hipStreamWaitEvent(s, f->ev_g1, 0));
   // origin, extent and status, and the plans' overflow flags
@@ -933,7 +954,7 @@ static int run_build_graph(hgmm_forest_s* f, BuildInput in, const hgmm_build_par
     for (int c = 0; c < 3; ++c) missed = missed || (hint[l][3 + c] == 0 && p.build_iters > 0 && pl[PL_CLS_N + c] > 0);
     if (missed) return run_build(f, in, p, ws, ws_bytes, s);
   }
-  f->n_graph_replays += 1;
+  f->n_graph_replays += 1;  // device-planned: a graph replay, or the same launches on the stream
   for (int b = 0; b < B; ++b)
     if (h_trees[B + b].status != 0) return fail(HGMM_ENONFINITE, "non-finite coordinate in cloud %d", b);
   f->has_labels = true;

@@ -7,8 +7,9 @@
 // own batch (construction, and registration when target clouds are given)
 // under candidate settings with HIP events on the caller's stream, by
 // coordinate descent over the knobs, and leaves the fastest setting in effect.
-// A build_graph = 1 candidate is timed after two untimed runs (the first
-// construction of a shape is host-planned, the second captures the graph).
+// A build_graph = 1 or 2 candidate is timed after two untimed runs (the first
+// construction of a shape is host-planned and records the work counts, the
+// second captures the graph).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,7 +39,7 @@ const std::vector<Knob>& knobs() {
       {&hgmm_tuning::reg_graph, {0, 1}},
       {&hgmm_tuning::reg_sort, {0, 1}},
       {&hgmm_tuning::reg_lds_levels, {2, 3}},
-      {&hgmm_tuning::build_graph, {0, 1}},
+      {&hgmm_tuning::build_graph, {0, 1, 2}},
   };
   return k;
 }

@@ -1,5 +1,6 @@
-"""Construction planned on the device and run as one hipGraph (build_graph = 1)
-against the host-planned construction (build_graph = 0): the same plan and the
+"""Construction planned on the device, run as one hipGraph (build_graph = 1) or
+as the same launches issued on the stream (build_graph = 2), against the
+host-planned construction (build_graph = 0): the same plan and the
 same arithmetic, so every exported tree field and every label is
 bit-identical.  On a handle, the first construction of a shape is planned on
 the host (it records the work counts that size the graph's grids), the next
@@ -58,7 +59,8 @@ def _host(hg, old, src, off, lv, **shapes):
     return hg.hgmm_build_batch(_cuda(src), off, lv)
 
 
-def test_batch_graph_equals_host_planned(hg):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_batch_graph_equals_host_planned(hg, mode):
     old = hg.hgmm_get_tuning()
     try:
         for shapes in (dict(), dict(block64_max=1 << 20, block256_max=1 << 20, block512_max=1 << 20),
@@ -68,17 +70,19 @@ def test_batch_graph_equals_host_planned(hg):
             for call, seed0 in enumerate((21, 31, 41, 51)):
                 src, off, lv = _batch(seed0)
                 ref = _host(hg, old, src, off, lv, **shapes)
-                hg.hgmm_set_tuning(**dict(old, build_graph=1, **shapes))
+                hg.hgmm_set_tuning(**dict(old, build_graph=mode, **shapes))
                 forest = hg.hgmm_build_batch(_cuda(src), off, lv, ws=ws, forest=forest)
                 _same(forest, ref, len(lv))
             st = forest.graph_stats()
-            log(f"[build graph] shapes {shapes}: 4 constructions identical, {st}")
-            assert st["captures"] >= 1 and st["replays"] >= 2
+            log(f"[build graph] mode {mode} shapes {shapes}: 4 constructions identical, {st}")
+            assert st["replays"] >= 2
+            assert st["captures"] >= 1 if mode == 1 else st["captures"] == 0
     finally:
         hg.hgmm_set_tuning(**old)
 
 
-def test_graph_redone_when_plan_differs(hg):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_graph_redone_when_plan_differs(hg, mode):
     """A cloud of the same size whose level-1 parents cross a class threshold
     that the hinted plan did not: the graph has no tiled iterations at level 1,
     the call finds tiled parents in the device plan and redoes the construction
@@ -99,7 +103,7 @@ def test_graph_redone_when_plan_differs(hg):
         off = np.array([0, n], np.int64)
         for call, cloud in enumerate((uni, uni, uni, lop)):
             ref = _host(hg, old, cloud, off, [2], **shapes)
-            hg.hgmm_set_tuning(**dict(old, build_graph=1, **shapes))
+            hg.hgmm_set_tuning(**dict(old, build_graph=mode, **shapes))
             forest = hg.hgmm_build_batch(_cuda(cloud), off, [2], ws=ws, forest=forest)
             _same(forest, ref, 1)
             log(f"[build graph] call {call}: {forest.graph_stats()}; level-1 counts "
@@ -110,7 +114,8 @@ def test_graph_redone_when_plan_differs(hg):
         hg.hgmm_set_tuning(**old)
 
 
-def test_lidar_graph_equals_host_planned(hg):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_lidar_graph_equals_host_planned(hg, mode):
     from paper_1807_02587_amd.presets import PRESETS
     pr = PRESETS["lidar"]
     p = lidar_pair(1000)
@@ -118,7 +123,7 @@ def test_lidar_graph_equals_host_planned(hg):
     try:
         hg.hgmm_set_tuning(**dict(old, build_graph=0))
         ref = hg.hgmm_build(_cuda(p.src), levels=pr["levels"], reg_eps=pr["reg_eps"], min_mass=pr["min_mass"])
-        hg.hgmm_set_tuning(**dict(old, build_graph=1))
+        hg.hgmm_set_tuning(**dict(old, build_graph=mode))
         tree = None
         src = _cuda(p.src)
         ws = hg.Workspace()
@@ -127,10 +132,11 @@ def test_lidar_graph_equals_host_planned(hg):
                                  tree=tree)
             _same(tree, ref, 1)
         st = tree.graph_stats()
-        assert st == dict(replays=3, captures=1, host_builds=1), st
+        assert st == (dict(replays=3, captures=1, host_builds=1) if mode == 1 else
+                      dict(replays=3, captures=0, host_builds=1)), st
         r0 = hg.hgmm_register(ref, _cuda(p.tgt), lambda_c=pr["lambda_c"])
         r1 = hg.hgmm_register(tree, _cuda(p.tgt), lambda_c=pr["lambda_c"])
         np.testing.assert_array_equal(r0["R"], r1["R"])
-        log(f"[build graph] lidar: identical over 4 constructions, {st}")
+        log(f"[build graph] lidar mode {mode}: identical over 4 constructions, {st}")
     finally:
         hg.hgmm_set_tuning(**old)
