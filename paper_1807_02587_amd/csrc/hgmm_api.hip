@@ -1692,6 +1692,8 @@ int hgmm_odometry(const float* d_xyz, const int64_t* offsets, int F, const hgmm_
   if (!d_xyz || !rp || !d_ws || !forest || !R_rel || !t_rel || !R_abs || !t_abs || !iters)
     return fail(HGMM_EINVAL, "null pointer argument");
   if (rp->max_iters < 1) return fail(HGMM_EINVAL, "max_iters must be >= 1");
+  for (int k = 0; k < F; ++k)
+    if (offsets[k + 1] - offsets[k] < 8) return fail(HGMM_ETOOFEW, "frame %d has fewer than 8 points", k);
   const size_t need = hgmm_odometry_workspace_bytes(offsets, F, bp->levels);
   if (need == 0 || ws_bytes < need) return fail(HGMM_EINVAL, "odometry workspace too small: %zu < %zu", ws_bytes, need);
   const int64_t T = offsets[F];

@@ -104,3 +104,8 @@ def test_odometry_argument_errors_before_device_work(lib):
                              None, 0, C.c_void_p(16), need, None, C.byref(h),
                              *[o.ctypes.data_as(C.c_void_p) for o in out], it.ctypes.data_as(C.c_void_p), None) == -1
     assert h.value is None
+    short = np.array([0, 100, 200, 203], np.int64)   # last frame of 3 points
+    assert lib.hgmm_odometry(C.c_void_p(16), short.ctypes.data_as(C.c_void_p), 3, C.byref(bp), C.byref(rp), None,
+                             None, 0, C.c_void_p(16), need, None, C.byref(h),
+                             *[o.ctypes.data_as(C.c_void_p) for o in out], it.ctypes.data_as(C.c_void_p), None) == -2
+    assert h.value is None
