@@ -9,7 +9,7 @@ kernels; this module only sequences calls and moves handles around):
 4. head -> initial transforms (hgmm_warm_head_pose);
 5. batched registration from those transforms, coarse to fine: first with
    the descent capped at cfg.coarse_levels levels, then with the whole tree;
-6. fallback: the plain method from the identity is the judge.  Rule "plain"
+6. fallback: the plain method from the identity is the reference.  Rule "plain"
    (default): every pair is also registered from the identity (one more
    batched call) and keeps whichever result has the higher final
    log-likelihood.  Rule "identity" (cheaper): a pair whose final

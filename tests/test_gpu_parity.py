@@ -28,7 +28,7 @@ FLAG_GAP = 1e-6
 MOMENT_TOL = 1e-5
 POSE_TOL = 1e-4
 # construction after ONE EM iteration from identical parents: the kernel's own
-# FP32 moment error (spec moment tolerance)
+# FP32 moment error (the 1e-5 moment tolerance)
 EM1_TOL = dict(pi=1e-5, mu=1e-5, cov=1e-5)
 # after 30 iterations the FP32 rounding is amplified by the EM map itself, most
 # in small, ill-conditioned partitions; the bound is looser
