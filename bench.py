@@ -375,8 +375,19 @@ def variants_section(args, hg, tree, tgt, p, pr, steps):
             row.update({"gevals_s": round(evals / (k["ms"] * 1e-3) / 1e9, 1), "estep_tflops": round(tf, 2),
                         "frac_fp32": round(tf / PEAK_FP32_TFLOPS, 4)})
         out[name] = row
+    # the per-point density query against the same tree (another consumer of
+    # the model): one descent plus one density per point
+    hg.hgmm_point_loglik(tree, tgt, lambda_c=pr["lambda_c"], ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ll, _ = hg.hgmm_point_loglik(tree, tgt, lambda_c=pr["lambda_c"], ws=ws)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    query = {"ms_per_query": round(sec * 1e3, 4), "mpts_s": round(n / sec / 1e6, 1),
+             "mean_loglik": round(float(ll.mean().item()), 4)}
     return {"workload": "registration alone on the main workload's tree, from the identity", "steps": steps,
-            "variants": out}
+            "variants": out, "point_query": query}
 
 
 def odometry_section(args, hg, frames=16):
