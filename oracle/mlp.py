@@ -4,7 +4,8 @@ The network and its loss are this project's addition (the paper has no learned
 component): 1280 -> 512 -> 512 -> 512 -> 9, exact GELU after the hidden
 layers, loss sum_c w_c (y_c - t_c)^2 / 2 averaged over rows (w = 1 on the 6D
 rotation part, trans_weight on the translation).  Parameters are flattened as
-W1 b1 W2 b2 W3 b3 W4 b4 with W row-major [in x out].
+W1 b1 W2 b2 W3 b3 W4 b4 with W row-major [in x out].  Training uses Adam
+(``adam_step``).
 
 ``bf16=True`` rounds the GEMM operands (inputs, weights, activations, output
 gradients) to bfloat16 exactly where the device network does, so that the
@@ -96,6 +97,27 @@ def loss_and_grad(params, X, T, trans_weight=1.0, bf16=False):
         dH = rnd(dZ) @ rnd(W).T
         dZ = dH * gelu_grad(Zs[i - 1])
     return loss, flatten(grads)
+
+
+def adam_step(params, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba, 2015, Algorithm 1), the optimiser of the
+    network's training.  ``step`` counts from 1.  The first and second moment
+    estimates are exponential averages of the gradient and of its square; each
+    is divided by one minus its decay rate to the power ``step`` (the bias
+    correction), and the parameter moves by lr times the corrected first moment
+    over the square root of the corrected second moment plus eps.
+
+    Returns (params, m, v) after the step, all float64; the inputs are not
+    modified."""
+    if step < 1:
+        raise ValueError("step counts from 1")
+    g = np.asarray(grad, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** step)
+    v_hat = v / (1.0 - beta2 ** step)
+    w = np.asarray(params, dtype=np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps)
+    return w, m, v
 
 
 def six_d_to_rotation(v):

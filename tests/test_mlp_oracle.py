@@ -81,3 +81,38 @@ def test_head_pose_target_round_trip():
                                       (1.0 + 2 ** -7 + 2 ** -12, 1.0078125 + 0.0)])
 def test_bf16_rounding(x, expect):
     assert mlp.bf16_round(np.array([x]))[0] == expect
+
+
+def test_adam_two_steps_by_hand():
+    """Two Adam steps on one weight, worked out by hand (beta 0.9 / 0.999, eps 1e-8,
+    lr 0.1, w0 = 1, gradients +2 then -1):
+    step 1: m = 0.2, v = 0.004, corrections 0.1 and 0.001 give m_hat = 2, v_hat = 4,
+            w = 1 - 0.1 * 2 / (2 + 1e-8) = 0.9000000005;
+    step 2: m = 0.18 - 0.1 = 0.08, v = 0.003996 + 0.001 = 0.004996, corrections
+            0.19 and 0.001999 give m_hat = 8/19, v_hat = 4996/1999 (sqrt 1.5809015228...),
+            w = 0.9000000005 - 0.1 * (8/19) / (1.5809015228... + 1e-8) = 0.87336629670..."""
+    w, m, v = mlp.adam_step(np.array([1.0]), np.zeros(1), np.zeros(1), np.array([2.0]), 1, 0.1)
+    assert m[0] == pytest.approx(0.2, rel=1e-15) and v[0] == pytest.approx(0.004, rel=1e-13)
+    assert w[0] == pytest.approx(0.9000000005, abs=1e-15)
+    w, m, v = mlp.adam_step(w, m, v, np.array([-1.0]), 2, 0.1)
+    assert m[0] == pytest.approx(0.08, rel=1e-13) and v[0] == pytest.approx(0.004996, rel=1e-13)
+    assert w[0] == pytest.approx(0.8733662967024313, abs=1e-14)
+
+
+def test_adam_invariants():
+    """The first step moves every weight by lr in the direction against its
+    gradient whatever the gradient's size (the bias corrections make m_hat = g
+    and v_hat = g^2); a constant gradient keeps that true at every step; the
+    step is invariant to a positive rescaling of the gradient (up to eps)."""
+    rng = np.random.default_rng(11)
+    w0 = rng.normal(size=200)
+    g = rng.choice([-1.0, 1.0], size=200) * 10.0 ** rng.uniform(-2, 3, size=200)
+    w, m, v = mlp.adam_step(w0, np.zeros(200), np.zeros(200), g, 1, 1e-3)
+    np.testing.assert_allclose(w0 - w, 1e-3 * np.sign(g), rtol=1e-5)
+    for step in range(2, 40):
+        w_prev = w
+        w, m, v = mlp.adam_step(w, m, v, g, step, 1e-3)
+        np.testing.assert_allclose(w_prev - w, 1e-3 * np.sign(g), rtol=1e-5)
+    a1, _, _ = mlp.adam_step(w0, 0.3 * g, 0.01 * g * g, g, 5, 1e-3)
+    a2, _, _ = mlp.adam_step(w0, 0.3 * 7.0 * g, 0.01 * 49.0 * g * g, 7.0 * g, 5, 1e-3)
+    np.testing.assert_allclose(a1, a2, rtol=1e-12, atol=1e-9)
