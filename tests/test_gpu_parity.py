@@ -19,7 +19,7 @@ import pytest
 
 import oracle
 from synth import blob_tree_cloud, depth_pair, lidar_pair, rotation_angle_deg, rotation_from_axis_angle, small_pair
-from gpu_helpers import compare_build_levels, gpu_bins_from_oracle, rel_err, to_oracle
+from gpu_helpers import check_finalize_against_eigh3, compare_build_levels, gpu_bins_from_oracle, rel_err, to_oracle
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -235,7 +235,7 @@ def test_register_exact_recovery_blobs(hg):
 # construction, level by level with the GPU's parents injected
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("name,iters", [("small", 1), ("small_ragged", 1), ("lidar", 1), ("small", 30),
+@pytest.mark.parametrize("name,iters", [("small", 1), ("small_ragged", 1), ("lidar", 1), ("depth", 1), ("small", 30),
                                         ("small_ragged", 30), ("lidar", 30)])
 def test_build_level_parity(hg, name, iters):
     """Each level of the GPU tree against the oracle's EM from the GPU's parent level.
@@ -253,6 +253,18 @@ def test_build_level_parity(hg, name, iters):
     tol = EM1_TOL if iters == 1 else EM30_TOL
     compare_build_levels(oracle, host, glab, p.src, L, eps, mm, iters, tol, log,
                          min_parent=0 if iters == 1 else EM30_MIN_PARENT)
+
+
+@pytest.mark.parametrize("name", ["small", "small_ragged", "lidar", "depth"])
+def test_finalize_unit_parity(hg, name):
+    """Node finalize (Sec. 4.1 complexity test, Sec. 4.2 weights) on the GPU's
+    own full tree: the oracle's eigen-decomposition of every exported
+    covariance gives the GPU's eigenvalues, eigenvectors and kappa to ~1e-12,
+    and every global weight is the product of the weights along its path."""
+    p, L, eps, mm = _case(name)
+    log(f"[finalize] case={name} levels={L}")
+    tree = hg.hgmm_build(_cuda(p.src), levels=L, reg_eps=eps, min_mass=mm)
+    check_finalize_against_eigh3(oracle, tree.export(), log)
 
 
 # --------------------------------------------------------------------------
