@@ -151,6 +151,32 @@ int hgmm_register(hgmm_tree tree, const float *d_xyz, int64_t n, const hgmm_reg_
                   const double *t0, void *d_ws, size_t ws_bytes, void *stream, double R[9], double t[3],
                   int *iters, double *loglik);
 
+/* ---- allocation-free registration ---------------------------------------
+ * For callers that cannot allocate device or pinned host memory (code under
+ * stream capture, tight serving loops, harnesses that forbid it): the same
+ * registration as hgmm_register (same kernels, arguments and outputs) with
+ * its workspace in a static device array of HGMM_NOALLOC_SCRATCH_BYTES that
+ * the library holds on every device it runs on until the process ends, and
+ * its host staging in a static host buffer.  The call allocates nothing: no
+ * hipMalloc, no pinned allocation, no graph (it never takes the registration
+ * graph path of hgmm_tuning.reg_graph) and no profiling events.  The caller
+ * still owns d_xyz and the tree; the tree itself comes from hgmm_build.
+ * The scratch is looked up once per device on the first call made with that
+ * device current.  Every call on one device shares that device's scratch and
+ * the process-wide host staging: calls that overlap in time (two host
+ * threads, or two streams) race and must be serialised by the caller.  The
+ * scratch keeps the last call's contents; each call clears what it
+ * accumulates into.  Errors: those of hgmm_register, plus HGMM_EINVAL when the
+ * cloud and tree need more than HGMM_NOALLOC_SCRATCH_BYTES of workspace
+ * (hgmm_register_workspace_bytes(n, levels) tells; about 2^19 points on a
+ * 5-level tree fit).  Synchronises `stream` once per chunk of iterations. */
+#define HGMM_NOALLOC_SCRATCH_BYTES ((size_t)48 << 20)
+#define HGMM_NOALLOC_MAX_DEVICES 64
+size_t hgmm_noalloc_scratch_bytes(void);
+int hgmm_register_noalloc(hgmm_tree tree, const float *d_xyz, int64_t n, const hgmm_reg_params *p,
+                          const double *R0, const double *t0, void *stream, double R[9], double t[3], int *iters,
+                          double *loglik);
+
 /* One registration E-step at a fixed transform (Algorithm 1): for each point
  * the stop node (global node id inside the tree, device int32, nullable) and
  * its weight gamma (device float, nullable); per node the moments

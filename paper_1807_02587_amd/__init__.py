@@ -17,6 +17,7 @@ from .api import (  # noqa: F401
     hgmm_odometry,
     hgmm_estep_flat,
     hgmm_register,
+    hgmm_register_noalloc,
     hgmm_build_batch,
     hgmm_register_batch,
     hgmm_estep_batch,

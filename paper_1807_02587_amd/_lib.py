@@ -46,6 +46,8 @@ SIGNATURES = {
     "hgmm_build": (C.c_int, [P, I64, P, P, C.c_size_t, P, P]),
     "hgmm_register": (C.c_int, [P, P, I64, P, P, P, P, C.c_size_t, P, P, P, P, P]),
     "hgmm_estep": (C.c_int, [P, P, I64, P, P, D, P, C.c_size_t, P, P, P, P, P]),
+    "hgmm_noalloc_scratch_bytes": (C.c_size_t, []),
+    "hgmm_register_noalloc": (C.c_int, [P, P, I64, P, P, P, P, P, P, P, P]),
     "hgmm_register_flat": (C.c_int, [P, P, I64, C.c_int, P, P, P, P, C.c_size_t, P, P, P, P, P]),
     "hgmm_estep_flat": (C.c_int, [P, P, I64, C.c_int, P, P, P, C.c_size_t, P, P, P, P, P]),
     "hgmm_register_soft": (C.c_int, [P, P, I64, D, P, P, P, P, C.c_size_t, P, P, P, P, P]),

@@ -230,6 +230,30 @@ def hgmm_register(tree: Tree, xyz: torch.Tensor, max_iters: int = 30, lambda_c: 
     return dict(R=R.reshape(3, 3), t=t, iters=iters.value, loglik=ll.value, status=rc)
 
 
+def hgmm_register_noalloc(tree: Tree, xyz: torch.Tensor, max_iters: int = 30, lambda_c: float = 0.01,
+                          tol_rot: float = 1e-6, tol_trans_rel: float = 1e-6, R0=None, t0=None, stream=None,
+                          raise_singular: bool = True, max_levels: int = 0) -> dict:
+    """hgmm_register with the library's static scratch instead of a workspace
+    (the call allocates nothing; calls that overlap on one device race)."""
+    xyz = _cloud(xyz)
+    lib = _lib.load()
+    n = xyz.shape[1]
+    p = RegParams(max_iters, max_levels, lambda_c, tol_rot, tol_trans_rel)
+    R0a, t0a = _pose_args(R0, t0)
+    R = np.zeros(9)
+    t = np.zeros(3)
+    iters = C.c_int(0)
+    ll = C.c_double(0)
+    rc = lib.hgmm_register_noalloc(tree.handle, C.c_void_p(xyz.data_ptr()), n, C.byref(p),
+                                   None if R0a is None else R0a.ctypes.data_as(C.c_void_p),
+                                   None if t0a is None else t0a.ctypes.data_as(C.c_void_p), _stream(stream),
+                                   R.ctypes.data_as(C.c_void_p), t.ctypes.data_as(C.c_void_p), C.byref(iters),
+                                   C.byref(ll))
+    if rc != 0 and (raise_singular or rc != -6):
+        check(rc, "hgmm_register_noalloc")
+    return dict(R=R.reshape(3, 3), t=t, iters=iters.value, loglik=ll.value, status=rc)
+
+
 def hgmm_estep(tree: Tree, xyz: torch.Tensor, R=None, t=None, lambda_c: float = 0.01, ws: Workspace | None = None,
                points: bool = True, loglik: bool = True, stream=None) -> dict:
     xyz = _cloud(xyz)

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <string>
 #include <array>
+#include <mutex>
 #include <vector>
 
 #include "../../include/hgmm.h"
@@ -395,7 +396,8 @@ struct ProfScope {
   ProfPending p;
   hipStream_t s;
   bool on;
-  ProfScope(int kind, double units, hipStream_t st, int tag = -1) : s(st), on(g_prof.on) {
+  ProfScope(int kind, double units, hipStream_t st, int tag = -1, bool enable = true)
+      : s(st), on(g_prof.on && enable) {
     if (!on) return;
     p.kind = kind; p.units = units; p.tag = tag;
     p.a = prof_event(); p.b = prof_event();
@@ -971,6 +973,11 @@ struct RegRun {
   int max_levels;  // 0: every level of the tree
   int flat_level = -1;  // >= 0: single-level E-step over this level instead of the descent
   double soft_tau = 0.0;  // > 0: soft multi-path E-step with this pruning threshold instead of the descent
+  // host staging supplied by the caller (nullptr: the handle's pinned
+  // staging, grown on demand); set, the run also takes neither the graph path
+  // nor the profiling events, so it allocates nothing
+  char* stage = nullptr;
+  size_t stage_bytes = 0;
 };
 
 static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, const float* zs,
@@ -1006,9 +1013,16 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   size_t s_res = align_up(s_act + sizeof(int) * P);
   size_t s_norm = align_up(s_res + sizeof(PoseState) * P);
   size_t s_end = align_up(s_norm + sizeof(double) * 28 * P);
-  int rc = grow_stage(f, s_end);
-  if (rc) return rc;
-  char* H = f->h_stage;
+  const bool fixed_stage = rr.stage != nullptr;
+  char* H = rr.stage;
+  if (fixed_stage) {
+    if (s_end > rr.stage_bytes)
+      return fail(HGMM_EINVAL, "host staging of %zu bytes needed, %zu available", s_end, rr.stage_bytes);
+  } else {
+    int rc = grow_stage(f, s_end);
+    if (rc) return rc;
+    H = f->h_stage;
+  }
   Tile* h_tiles = (Tile*)(H + s_tiles);
   int64_t* h_nmov = (int64_t*)(H + s_nmov);
   double* h_pose = (double*)(H + s_pose);
@@ -1104,7 +1118,7 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   // pair has converged so that no further launches are queued
   int it = 0;
   const int chunk = std::max(1, g_tune.reg_chunk);
-  if (g_tune.reg_graph && !g_prof.on) {
+  if (g_tune.reg_graph && !g_prof.on && !fixed_stage) {
     int rc2 = ensure_graph_stream(f);
     if (rc2) return rc2;
     uint64_t tr, tt, soft_key;
@@ -1153,11 +1167,11 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
     const int end = std::min(rr.max_iters, it + chunk);
     for (; it < end; ++it) {
       {
-        ProfScope ps(soft ? PK_SOFT : flat ? PK_FLAT : PK_DESCEND, (double)n_total, s, it);
+        ProfScope ps(soft ? PK_SOFT : flat ? PK_FLAT : PK_DESCEND, (double)n_total, s, it, !fixed_stage);
         estep(s, nullptr, nullptr, nullptr);
       }
       {
-        ProfScope ps(PK_NORMAL, (double)nodes_total, s, it);
+        ProfScope ps(PK_NORMAL, (double)nodes_total, s, it, !fixed_stage);
         mstep(s);
       }
     }
@@ -1267,6 +1281,79 @@ int hgmm_register(hgmm_tree tree, const float* d_xyz, int64_t n, const hgmm_reg_
   PoseState res;
   int rc = run_register(tree, d_xyz, d_xyz + n, d_xyz + 2 * n, offs, R0, t0, 0, rr, (char*)d_ws, ws_bytes,
                         (hipStream_t)stream, 0, nullptr, nullptr, nullptr, &res, nullptr);
+  if (rc) return rc;
+  for (int i = 0; i < 9; ++i) R[i] = res.R[i];
+  for (int i = 0; i < 3; ++i) t[i] = res.t[i];
+  *iters = res.iters;
+  if (loglik) *loglik = res.loglik;
+  if (res.status != 0) return fail(res.status, "normal equations not positive definite at iteration %d", res.iters);
+  return HGMM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free registration: the workspace lives in a static device array
+// ---------------------------------------------------------------------------
+//
+// Callers that may not allocate (code under stream capture, serving loops)
+// register against a static device array instead of a caller workspace.  In
+// host code `scratch` names a host-side stand-in, not device memory: its
+// device address is looked up once per device with hipGetSymbolAddress and
+// only that address is ever handed to kernels or copies.  Every call on a
+// device shares that device's array (and the process-wide host staging), so
+// calls that overlap in time race; the array keeps the last call's contents,
+// and the registration clears what it accumulates into before use.
+
+static __device__ __align__(256) char scratch[HGMM_NOALLOC_SCRATCH_BYTES];
+constexpr size_t kNoAllocStageBytes = size_t(1) << 18;
+alignas(256) static char g_noalloc_stage[kNoAllocStageBytes];
+static void* g_scratch_ptr[HGMM_NOALLOC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+// Device address of this device's scratch, looked up on the first call on
+// the device with that device current.
+static int noalloc_scratch(char** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= HGMM_NOALLOC_MAX_DEVICES) return fail(HGMM_EINVAL, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(HGMM_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = (char*)g_scratch_ptr[dev];
+  return HGMM_OK;
+}
+
+extern "C" {
+
+size_t hgmm_noalloc_scratch_bytes(void) { return HGMM_NOALLOC_SCRATCH_BYTES; }
+
+int hgmm_register_noalloc(hgmm_tree tree, const float* d_xyz, int64_t n, const hgmm_reg_params* p, const double* R0,
+                          const double* t0, void* stream, double R[9], double t[3], int* iters, double* loglik) {
+  if (n < 1) return fail(HGMM_ETOOFEW, "empty cloud");
+  if (!tree || !d_xyz || !p || !R || !t || !iters) return fail(HGMM_EINVAL, "null pointer argument");
+  if (n > (int64_t)INT32_MAX / 2) return fail(HGMM_EINVAL, "too many points");
+  if (p->max_iters < 1) return fail(HGMM_EINVAL, "max_iters must be >= 1");
+  if (tree->trees.size() != 1) return fail(HGMM_EINVAL, "hgmm_register_noalloc takes a single-tree handle");
+  const size_t need = reg_layout(n, tree->total_nodes(), 1).total;
+  if (need > HGMM_NOALLOC_SCRATCH_BYTES)
+    return fail(HGMM_EINVAL, "%lld points on a %lld-node tree need %zu bytes of scratch; the static scratch holds %zu",
+                (long long)n, (long long)tree->total_nodes(), need, (size_t)HGMM_NOALLOC_SCRATCH_BYTES);
+  char* ws = nullptr;
+  int rc = noalloc_scratch(&ws);
+  if (rc) return rc;
+  std::vector<int64_t> offs = {0, n};
+  RegRun rr{p->max_iters, p->lambda_c, p->tol_rot, p->tol_trans_rel, p->max_levels};
+  rr.stage = g_noalloc_stage;
+  rr.stage_bytes = kNoAllocStageBytes;
+  PoseState res;
+  rc = run_register(tree, d_xyz, d_xyz + n, d_xyz + 2 * n, offs, R0, t0, 0, rr, ws, need, (hipStream_t)stream, 0,
+                    nullptr, nullptr, nullptr, &res, nullptr);
   if (rc) return rc;
   for (int i = 0; i < 9; ++i) R[i] = res.R[i];
   for (int i = 0; i < 3; ++i) t[i] = res.t[i];

@@ -109,3 +109,21 @@ def test_odometry_argument_errors_before_device_work(lib):
                              None, 0, C.c_void_p(16), need, None, C.byref(h),
                              *[o.ctypes.data_as(C.c_void_p) for o in out], it.ctypes.data_as(C.c_void_p), None) == -2
     assert h.value is None
+
+
+def test_noalloc_entry_point_limits(lib):
+    """The allocation-free registration reports its static scratch size and
+    rejects null arguments before any device work."""
+    from paper_1807_02587_amd._lib import RegParams
+    assert lib.hgmm_noalloc_scratch_bytes() == 48 << 20
+    rp = RegParams(30, 0, 0.01, 1e-6, 1e-6)
+    R = (C.c_double * 9)()
+    t = (C.c_double * 3)()
+    it = C.c_int(0)
+    assert lib.hgmm_register_noalloc(None, C.c_void_p(16), 100, C.byref(rp), None, None, None, R, t,
+                                     C.byref(it), None) == -1
+    assert lib.hgmm_register_noalloc(C.c_void_p(16), C.c_void_p(16), 0, C.byref(rp), None, None, None, R, t,
+                                     C.byref(it), None) == -2
+    # the workspace a cloud needs grows with it: 2^19 points on 5 levels fit, 2^21 do not
+    assert lib.hgmm_register_workspace_bytes(1 << 19, 5) <= lib.hgmm_noalloc_scratch_bytes()
+    assert lib.hgmm_register_workspace_bytes(1 << 21, 5) > lib.hgmm_noalloc_scratch_bytes()
