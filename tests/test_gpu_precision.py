@@ -6,7 +6,12 @@ Outputs: the tree (every level after one EM iteration from the GPU's parent
 level: weights, means, covariances), the E-step at a pose 1 degree from the
 truth (stop nodes, responsibilities, per-node moments, log-likelihood), the
 normal equations from identical moments (H, g), and the registered pose from
-a start 1 degree and 0.1 % of the extent away from the truth.
+the identity (the benchmarked path, committed preset) against the oracle's
+registration on the same tree.
+
+A second test registers three generated room pairs from the identity and
+from the ground truth: the identity start must end at the method's own
+optimum (where the ground-truth start ends, which the oracle reproduces).
 """
 
 import math
@@ -47,7 +52,9 @@ def test_depth_pair_errors_per_output():
     h1 = tree1.export()
     w = compare_build_levels(oracle, h1, tree1.labels().cpu().numpy(), p.src, L, eps, mm, 1, EM1_TOL, log)
     rep += [("tree pi (rel)", w["pi"], 1e-5), ("tree mu (/ extent)", w["mu"], 1e-5),
-            ("tree cov (/ trace)", w["cov"], 1e-5)]
+            ("tree cov (/ trace)", w["cov"], 1e-5), ("tree eigenvalues lambda (/ trace)", w["lam"], 3e-5),
+            ("tree eigenvectors (separated axes, abs)", w["evec"], 1e-3),
+            ("tree complexity kappa (abs)", w["kappa"], 2e-5), ("tree global weight pi^g (rel)", w["pig"], 1e-5)]
 
     # the 30-iteration tree the rest runs on
     tree = hg.hgmm_build(_cuda(p.src), levels=L, reg_eps=eps, min_mass=mm)
@@ -90,19 +97,49 @@ def test_depth_pair_errors_per_output():
     rep += [("normal equations H (rel to max)", float(np.abs(Hg - Ho).max() / np.abs(Ho).max()), 1e-10),
             ("normal equations g (rel to max)", float(np.abs(gg - go).max() / np.abs(go).max()), 1e-9)]
 
-    # registration from near the truth
-    R0 = rotation_from_axis_angle([0.2, 0.9, -0.3], math.radians(1.0)) @ p.R_true
-    t0 = p.t_true + 0.001 * p.extent * np.array([0.5, -0.2, 0.3])
-    r = hg.hgmm_register(tree, _cuda(p.tgt), R0=R0, t0=t0, lambda_c=pr["lambda_c"])
-    ro = oracle.register(ot, p.tgt, R0=R0, t0=t0, lambda_c=pr["lambda_c"])
+    # registration from the identity (the benchmarked path)
+    r = hg.hgmm_register(tree, _cuda(p.tgt), lambda_c=pr["lambda_c"])
+    ro = oracle.register(ot, p.tgt, lambda_c=pr["lambda_c"])
     rep += [("pose rotation (rad)", math.radians(rotation_angle_deg(r["R"], ro["R"])), 1e-4),
             ("pose translation (/ extent)", float(np.linalg.norm(r["t"] - ro["t"]) / host["extent"]), 1e-4),
             ("iterations (difference)", abs(int(r["iters"]) - int(ro["iters"])), 2)]
-    log(f"[precision] depth pair: {p.src.shape[1]} + {n} points, {L} levels; registration {r['iters']} iterations, "
-        f"error vs truth {rotation_angle_deg(r['R'], p.R_true):.4f} deg")
+    log(f"[precision] depth pair: {p.src.shape[1]} + {n} points, {L} levels; registration from the identity "
+        f"{r['iters']} iterations (oracle {ro['iters']}), error vs truth {rotation_angle_deg(r['R'], p.R_true):.4f} "
+        f"deg (oracle {rotation_angle_deg(ro['R'], p.R_true):.4f})")
     log("[precision] output | error against the FP64 oracle | tolerance")
     for name, err, tol in rep:
         log(f"[precision] {name} | {err:.3g} | {tol:g}")
     assert cnt_equal
     for name, err, tol in rep:
         assert err <= tol, name
+
+
+@pytest.mark.parametrize("seed", [2000, 2001, 2002])
+def test_depth_identity_start_reaches_the_method_optimum(seed):
+    """With the committed preset the registration from the identity ends where
+    the registration started at the ground truth ends (the method's own
+    optimum on this pair, within 0.05 deg), on the GPU, and the GPU's
+    ground-truth-start registration matches the oracle's on the same tree.
+    The optimum's own error against the truth (partial overlap of the two
+    views, hard assignments and Eq. 8's cluster means) is printed, not held."""
+    import paper_1807_02587_amd as hg
+    from paper_1807_02587_amd.presets import PRESETS
+    pr = PRESETS["depth"]
+    p = depth_pair(seed)
+    tree = hg.hgmm_build(_cuda(p.src), levels=pr["levels"], reg_eps=pr["reg_eps"], min_mass=pr["min_mass"])
+    host = tree.export()
+    tgt = _cuda(p.tgt)
+    r_id = hg.hgmm_register(tree, tgt, max_iters=60, lambda_c=pr["lambda_c"])
+    r_gt = hg.hgmm_register(tree, tgt, R0=p.R_true, t0=p.t_true, max_iters=60, lambda_c=pr["lambda_c"])
+    o_gt = oracle.register(to_oracle(oracle, host), p.tgt, R0=p.R_true, t0=p.t_true, max_iters=60,
+                           lambda_c=pr["lambda_c"])
+    d_par = math.radians(rotation_angle_deg(r_gt["R"], o_gt["R"]))
+    t_par = float(np.linalg.norm(r_gt["t"] - o_gt["t"])) / host["extent"]
+    d_opt = rotation_angle_deg(r_id["R"], r_gt["R"])
+    t_opt = float(np.linalg.norm(r_id["t"] - r_gt["t"])) / host["extent"]
+    log(f"[depth seed {seed}] true motion {rotation_angle_deg(np.eye(3), p.R_true):.2f} deg; from the identity "
+        f"{r_id['iters']} iterations, error {rotation_angle_deg(r_id['R'], p.R_true):.3f} deg; from the truth "
+        f"{r_gt['iters']} iterations, error {rotation_angle_deg(r_gt['R'], p.R_true):.3f} deg; identity vs truth "
+        f"start {d_opt:.3f} deg {t_opt:.1e} ext; GPU vs oracle {d_par:.1e} rad {t_par:.1e} ext")
+    assert d_par < 1e-4 and t_par < 1e-4
+    assert d_opt < 0.05 and t_opt < 1e-3
