@@ -26,3 +26,4 @@ from .oracle import (  # noqa: F401
     level_offset,
     level_nodes,
 )
+from . import warm  # noqa: F401

@@ -785,3 +785,89 @@ def test_soft_register_exact_recovery_blob_tree(oracle_mod):
     assert r["status"] == 0 and r["iters"] < 60
     np.testing.assert_allclose(r["R"], Rg.T, atol=1e-6)
     np.testing.assert_allclose(r["t"], -Rg.T @ tg, atol=1e-6 * tree.extent)
+
+
+# --------------------------------------------------------------------------
+# learned warm start: canonical frame, features, start pose (oracle.warm)
+# --------------------------------------------------------------------------
+
+def _hand_tree(oracle_mod, R=np.eye(3), t=np.zeros(3)):
+    """A 2-level tree set by hand: root covariance R diag(4, 1, 0.25) R^T + eps,
+    origin R (1, 2, 3) + t, one live level-1 node (index 5) with weight 0.1,
+    mean R (origin offset (0.5, -0.25, 2)) + origin, covariance
+    R diag(0.04, 0.01, 0.09) R^T."""
+    eps = 1e-6
+    tr = oracle_mod.OracleTree(2)
+    C = R @ np.diag([4.0, 1.0, 0.25]) @ R.T + eps * np.eye(3)
+    tr.root_cov = np.array([C[0, 0], C[0, 1], C[0, 2], C[1, 1], C[1, 2], C[2, 2]])
+    lam, ev = oracle_mod.eigh3(tr.root_cov)
+    tr.root_lam, tr.root_evec = lam, ev
+    tr.origin = R @ np.array([1.0, 2.0, 3.0]) + t
+    g = oracle_mod.level_offset(1) + 5
+    tr.live[g] = 1
+    tr.pig[g] = 0.1
+    tr.mu[g] = tr.origin + R @ np.array([0.5, -0.25, 2.0])
+    S = R @ np.diag([0.04, 0.01, 0.09]) @ R.T
+    tr.cov[g] = [S[0, 0], S[0, 1], S[0, 2], S[1, 1], S[1, 2], S[2, 2]]
+    return tr, eps
+
+
+def test_warm_features_of_a_hand_built_tree(oracle_mod):
+    """In the tree's own principal axes the node's feature row is, by hand,
+    (0.1, (0.5, -0.25, 2) / s, 0.04 / s^2, 0, 0, 0.01 / s^2, 0, 0.09 / s^2)
+    with s = sqrt(4 + 1 + 0.25); every dead node is zeros; the same tree
+    rotated and moved gives the same features."""
+    from oracle import warm
+    tr, eps = _hand_tree(oracle_mod)
+    f = warm.features(tr, eps)
+    s = np.sqrt(5.25)
+    ref = np.zeros(640)
+    ref[50:60] = [0.1, 0.5 / s, -0.25 / s, 2.0 / s, 0.04 / s ** 2, 0.0, 0.0, 0.01 / s ** 2, 0.0, 0.09 / s ** 2]
+    np.testing.assert_allclose(f, ref, atol=1e-12)
+    fr = warm.canonical_frame(tr, eps)
+    np.testing.assert_allclose(fr[:9].reshape(3, 3), np.eye(3), atol=1e-12)
+    np.testing.assert_allclose(fr[9:], [1.0, 2.0, 3.0, s], atol=1e-12)
+    R = rotation_from_axis_angle([1.0, 1.0, 1.0], np.radians(10.0))
+    tr2, _ = _hand_tree(oracle_mod, R, np.array([0.3, -2.0, 5.0]))
+    np.testing.assert_allclose(warm.features(tr2, eps), ref, atol=1e-12)
+
+
+def test_warm_frame_of_a_built_tree(oracle_mod):
+    """On a built tree the frame is a proper rotation that diagonalises the
+    root covariance, c is the centroid and s the RMS distance to it."""
+    from oracle import warm
+    p = small_pair(71, n=3000)
+    tr, _ = oracle_mod.build_tree(p.src, 2, eps=1e-6)
+    fr = warm.canonical_frame(tr, 1e-6)
+    E = fr[:9].reshape(3, 3)
+    assert abs(np.linalg.det(E) - 1.0) < 1e-12
+    np.testing.assert_allclose(E @ E.T, np.eye(3), atol=1e-12)
+    x = p.src.astype(np.float64)
+    c = x.mean(1)
+    S = np.cov(x, bias=True)
+    D = E @ S @ E.T
+    assert np.abs(D - np.diag(np.diag(D))).max() < 1e-12 * np.abs(D).max()
+    np.testing.assert_allclose(fr[9:12], c, atol=1e-12)
+    assert abs(fr[12] - np.sqrt(np.mean(np.sum((x - c[:, None]) ** 2, 0)))) < 1e-12
+
+
+def test_warm_identity_head_maps_a_rotated_copy_back(oracle_mod):
+    """A network whose output is the identity in canonical coordinates (zero
+    weights, last bias (1,0,0, 0,1,0, 0,0,0)) starts a pair from the
+    transform between the two clouds' frames.  For an exact rigid copy,
+    target = R_g source + t_g, with a rotation small enough to keep the
+    eigenvector signs, that start is exactly the inverse motion."""
+    from oracle import mlp, warm
+    p = small_pair(72, n=4000)
+    src = p.src.astype(np.float64)
+    Rg = rotation_from_axis_angle([0.3, -0.5, 0.8], np.radians(6.0))
+    tg = np.array([0.05, -0.02, 0.03])
+    tgt = (Rg @ src + tg[:, None])
+    ts, _ = oracle_mod.build_tree(p.src, 2, eps=1e-6)
+    tt, _ = oracle_mod.build_tree(tgt.astype(np.float32), 2, eps=1e-6)
+    params = np.zeros(mlp.param_count())
+    params[-9:] = [1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0]
+    R0, t0 = warm.initial_pose(params, ts, tt, 1e-6)
+    # tgt was rounded to FP32 before its tree was built: 1e-7 relative
+    np.testing.assert_allclose(R0, Rg.T, atol=1e-6)
+    np.testing.assert_allclose(t0, -Rg.T @ tg, atol=1e-6)
