@@ -405,7 +405,13 @@ void hgmm_tree_destroy(hgmm_tree tree);
  * same device-planned launches directly on the stream, without a graph (no
  * capture, no graph launch; the host enqueues while the GPU runs).  Results
  * equal those of build_graph = 0.  Neither is used while hgmm_profile is on.
- * Defaults 256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0, 256, 2, 0. */
+ * reg_atomics selects how the registration descent adds its moments: 0
+ * (default) in 128-bit fixed point, whose integer sums do not depend on the
+ * order of the additions, so moments and poses are bitwise reproducible from
+ * run to run; 1 as FP64 atomic adds of each wave's FP32 sums into FP64 node
+ * bins, whose order, and so the last bits of the moments of trees of 3 or
+ * more levels, vary between runs (kept to compare against).
+ * Defaults 256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0, 256, 2, 0, 0. */
 typedef struct hgmm_tuning {
   int32_t block64_max, block256_max, block512_max;
   int32_t min_tile, target_tiles, max_tile;
@@ -416,6 +422,7 @@ typedef struct hgmm_tuning {
   int32_t reg_lds_levels; /* tree levels whose scoring records the descent stages in LDS: 2 or 3 */
   int32_t build_graph;    /* 1: construction planned on the device and run as one hipGraph; 2: the same
                              device-planned launches issued on the stream */
+  int32_t reg_atomics;    /* 0: fixed-point moments (reproducible); 1: FP64 atomic moments */
 } hgmm_tuning;
 
 /* Constructions of a handle so far: those planned on the device (a replay of
@@ -473,6 +480,11 @@ int hgmm_autotune(const float *d_src, const int64_t *src_offsets, const int32_t 
 int hgmm_profile(int enable);
 void hgmm_profile_reset(void);
 int hgmm_profile_read(int kind, double *total_ms, int64_t *launches, double *units);
+/* For the registration descent (kind 4): the points its timed launches
+ * actually processed (pairs already converged are skipped inside a launch)
+ * and the tree levels those points scored, counted on the device (one
+ * 64-bit atomic add per block while profiling).  Other kinds report 0. */
+int hgmm_profile_work(int kind, double *points, double *levels);
 
 /* Thread-local description of the last failure on this thread. */
 const char *hgmm_last_error(void);

@@ -20,7 +20,7 @@ class BuildParams(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [(k, C.c_int32) for k in ("block64_max", "block256_max", "block512_max", "min_tile", "target_tiles",
                                           "max_tile", "reg_tile", "reg_chunk", "reg_graph", "reg_sort", "tile_threads", "reg_lds_levels",
-                                          "build_graph")]
+                                          "build_graph", "reg_atomics")]
 
 
 class RegParams(C.Structure):
@@ -86,6 +86,7 @@ SIGNATURES = {
     "hgmm_profile": (C.c_int, [C.c_int]),
     "hgmm_profile_reset": (None, []),
     "hgmm_profile_read": (C.c_int, [C.c_int, P, P, P]),
+    "hgmm_profile_work": (C.c_int, [C.c_int, P, P]),
 }
 
 _lib = None

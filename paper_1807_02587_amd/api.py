@@ -67,7 +67,7 @@ def hgmm_level_offset(level: int) -> int:
 
 
 TUNING_KEYS = ("block64_max", "block256_max", "block512_max", "min_tile", "target_tiles", "max_tile", "reg_tile",
-               "reg_chunk", "reg_graph", "reg_sort", "tile_threads", "reg_lds_levels", "build_graph")
+               "reg_chunk", "reg_graph", "reg_sort", "tile_threads", "reg_lds_levels", "build_graph", "reg_atomics")
 
 
 def hgmm_get_tuning() -> dict:
@@ -443,7 +443,10 @@ def hgmm_profile_read(kind) -> dict:
     n = C.c_int64(0)
     u = C.c_double(0)
     check(_lib.load().hgmm_profile_read(k, C.byref(ms), C.byref(n), C.byref(u)), "hgmm_profile_read")
-    return dict(ms=ms.value, launches=n.value, units=u.value)
+    pts = C.c_double(0)
+    lev = C.c_double(0)
+    check(_lib.load().hgmm_profile_work(k, C.byref(pts), C.byref(lev)), "hgmm_profile_work")
+    return dict(ms=ms.value, launches=n.value, units=u.value, points=pts.value, levels=lev.value)
 
 
 def hgmm_build_batch(xyz: torch.Tensor, offsets, levels, build_iters: int = 30, reg_eps: float = 1e-6,

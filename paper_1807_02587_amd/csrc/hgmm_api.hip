@@ -249,7 +249,7 @@ static BuildLayout build_layout(int64_t n_total, int64_t max_jobs, int64_t max_l
 }
 
 struct RegLayout {
-  size_t bins, partials, counters, state, nmov, tiles, out, dpart, dcount, ptiles, active, pose, keys, keys2, vals,
+  size_t bins, partials, counters, state, nmov, tiles, out, fbins, dcount, ptiles, active, pose, keys, keys2, vals,
       perm, sxyz, sort_temp, flatf, flats, total;
   size_t sort_temp_bytes;
   int64_t max_tiles;
@@ -262,7 +262,7 @@ static RegLayout reg_layout(int64_t n_total, int64_t nodes, int npairs) {
   L.bins = o; o = align_up(o + sizeof(double) * 6 * (size_t)std::max<int64_t>(nodes, 1));
   L.partials = o; o = align_up(o + sizeof(double) * 28 * (size_t)npairs);
   L.counters = o; o = align_up(o + sizeof(unsigned) * (size_t)npairs);
-  L.dpart = o; o = align_up(o + sizeof(double) * (72 * 6 + 2) * (size_t)L.max_tiles);  // values + node masks
+  L.fbins = o; o = align_up(o + sizeof(FixBin) * (size_t)std::max<int64_t>(nodes, 1));  // fixed-point moments
   L.dcount = o; o = align_up(o + sizeof(unsigned) * (size_t)npairs);
   // per-pair inputs uploaded together: tile ranges | point counts | start
   // poses (12 doubles: R row-major, t) | active flags
@@ -318,7 +318,7 @@ static int64_t max_lvl_for(const std::vector<TreeHost>& trees) {
 // launch shapes (process wide; see hgmm_tuning)
 // ---------------------------------------------------------------------------
 
-static hgmm_tuning g_tune = {256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0, 256, 2, 0};
+static hgmm_tuning g_tune = {256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0, 256, 2, 0, 0};
 
 extern "C" int hgmm_set_tuning(const hgmm_tuning* t) {
   if (!t) return fail(HGMM_EINVAL, "null tuning");
@@ -336,6 +336,7 @@ extern "C" int hgmm_set_tuning(const hgmm_tuning* t) {
     return fail(HGMM_EINVAL, "tile_threads must be 256, 512 or 1024");
   if (t->reg_lds_levels != 2 && t->reg_lds_levels != 3) return fail(HGMM_EINVAL, "reg_lds_levels must be 2 or 3");
   if (t->build_graph < 0 || t->build_graph > 2) return fail(HGMM_EINVAL, "build_graph must be 0, 1 or 2");
+  if (t->reg_atomics != 0 && t->reg_atomics != 1) return fail(HGMM_EINVAL, "reg_atomics must be 0 or 1");
   g_tune = *t;
   g_tune.min_tile = (t->min_tile + 63) / 64 * 64;
   g_tune.max_tile = (t->max_tile + 63) / 64 * 64;
@@ -368,16 +369,23 @@ struct ProfPending {
   int kind;
   double units;
   hipEvent_t a, b;
-  int tag;  // registration iteration of a descend/normal launch, -1 otherwise
+  int tag;    // registration iteration of a descend/normal launch, -1 otherwise
+  int wslot;  // device work-counter slot of a descend launch, -1 otherwise
 };
+
+constexpr int kProfWorkSlots = 8192;
 
 struct ProfState {
   bool on = false;
   double ms[PK_COUNT] = {0};
   int64_t launches[PK_COUNT] = {0};
   double units[PK_COUNT] = {0};
+  double points[PK_COUNT] = {0};  // device-counted points processed (descend)
+  double levels[PK_COUNT] = {0};  // device-counted levels those points scored (descend)
   std::vector<hipEvent_t> pool;
   std::vector<ProfPending> pending;
+  unsigned long long* d_work = nullptr;  // 2 counters per slot, allocated when profiling starts
+  int next_slot = 0;
 };
 static ProfState g_prof;
 
@@ -398,10 +406,18 @@ struct ProfScope {
   bool on;
   ProfScope(int kind, double units, hipStream_t st, int tag = -1, bool enable = true)
       : s(st), on(g_prof.on && enable) {
+    p.wslot = -1;
     if (!on) return;
     p.kind = kind; p.units = units; p.tag = tag;
     p.a = prof_event(); p.b = prof_event();
     (void)hipEventRecord(p.a, s);
+  }
+  // device counters of the points this launch processes and the levels they
+  // score (zeroed; nullptr when not profiling or out of slots)
+  unsigned long long* work_slot() {
+    if (!on || !g_prof.d_work || g_prof.next_slot >= kProfWorkSlots) return nullptr;
+    p.wslot = g_prof.next_slot++;
+    return g_prof.d_work + 2 * p.wslot;
   }
   ~ProfScope() {
     if (!on) return;
@@ -414,12 +430,25 @@ struct ProfScope {
 // synchronised).  Registration launches with tag >= iters_done were no-ops
 // after convergence and are not counted.
 static void prof_collect(int iters_done = 1 << 30) {
+  std::vector<unsigned long long> work;
+  if (g_prof.d_work && g_prof.next_slot > 0) {
+    work.resize(2 * (size_t)g_prof.next_slot);
+    if (hipMemcpy(work.data(), g_prof.d_work, sizeof(unsigned long long) * work.size(), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+      work.clear();
+    (void)hipMemset(g_prof.d_work, 0, sizeof(unsigned long long) * 2 * kProfWorkSlots);
+    g_prof.next_slot = 0;
+  }
   for (auto& p : g_prof.pending) {
     float ms = 0.f;
     if (p.tag < iters_done && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       g_prof.ms[p.kind] += ms;
       g_prof.launches[p.kind] += 1;
       g_prof.units[p.kind] += p.units;
+      if (p.wslot >= 0 && (size_t)(2 * p.wslot + 1) < work.size()) {
+        g_prof.points[p.kind] += (double)work[2 * p.wslot];
+        g_prof.levels[p.kind] += (double)work[2 * p.wslot + 1];
+      }
     }
     g_prof.pool.push_back(p.a);
     g_prof.pool.push_back(p.b);
@@ -428,12 +457,28 @@ static void prof_collect(int iters_done = 1 << 30) {
 }
 
 extern "C" int hgmm_profile(int enable) {
+  if (enable && !g_prof.d_work) {
+    if (hipMalloc((void**)&g_prof.d_work, sizeof(unsigned long long) * 2 * kProfWorkSlots) != hipSuccess)
+      return fail(HGMM_ENOMEM, "profiling counters could not be allocated");
+    if (hipMemset(g_prof.d_work, 0, sizeof(unsigned long long) * 2 * kProfWorkSlots) != hipSuccess)
+      return fail(HGMM_EHIP, "profiling counters could not be cleared");
+    g_prof.next_slot = 0;
+  }
   g_prof.on = enable != 0;
   return HGMM_OK;
 }
 
 extern "C" void hgmm_profile_reset(void) {
-  for (int k = 0; k < PK_COUNT; ++k) { g_prof.ms[k] = 0; g_prof.launches[k] = 0; g_prof.units[k] = 0; }
+  for (int k = 0; k < PK_COUNT; ++k) {
+    g_prof.ms[k] = 0; g_prof.launches[k] = 0; g_prof.units[k] = 0; g_prof.points[k] = 0; g_prof.levels[k] = 0;
+  }
+}
+
+extern "C" int hgmm_profile_work(int kind, double* points, double* levels) {
+  if (kind < 0 || kind >= PK_COUNT) return fail(HGMM_EINVAL, "profile kind %d out of range", kind);
+  if (points) *points = g_prof.points[kind];
+  if (levels) *levels = g_prof.levels[kind];
+  return HGMM_OK;
 }
 
 extern "C" int hgmm_profile_read(int kind, double* total_ms, int64_t* launches, double* units) {
@@ -998,7 +1043,7 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   Tile* d_tiles = (Tile*)(ws + Ly.tiles);
   double* d_out = (double*)(ws + Ly.out);
   double* d_pose0 = (double*)(ws + Ly.pose);
-  double* d_dpart = (double*)(ws + Ly.dpart);
+  FixBin* d_fbins = (FixBin*)(ws + Ly.fbins);
   unsigned* d_dcount = (unsigned*)(ws + Ly.dcount);
   int2* d_ptiles = (int2*)(ws + Ly.ptiles);
 
@@ -1072,19 +1117,22 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
     d_perm = (const int*)(ws + Ly.perm);
   }
   launch_fill_u32(d_bins, 0u, 2 * 6 * nodes_total, s);
+  launch_fill_u32(d_fbins, 0u, (int64_t)(sizeof(FixBin) / 4) * nodes_total, s);
   launch_set_stop_flags(f->d_tab, f->d_nodes, nodes_total, rr.lambda_c, s);
   launch_init_pose(d_state, P, d_pose0, d_pose0 + 9, per_pair ? 12 : 0, active ? d_act : nullptr, s);
   HIP_LAUNCHED();
-  const size_t pstride = (size_t)Ly.max_tiles;
   const bool flat = rr.flat_level >= 0;
   const bool soft = rr.soft_tau > 0.0;
+  // the descent's moments as FP64 atomic adds (compared against the
+  // fixed-point default)
+  const bool fp64_atomics = g_tune.reg_atomics != 0 && !flat && !soft;
   int max_tree_levels = 1;
   for (auto& tr : f->trees) max_tree_levels = std::max(max_tree_levels, tr.levels);
   // one E-step launch (descent, or the single-level scan) and one M-step launch
   NodeF* d_flatf = (NodeF*)(ws + Ly.flatf);
   NodeS* d_flats = (NodeS*)(ws + Ly.flats);
   if (flat) launch_flat_table(f->d_tab, f->d_nodes, d_flatf, d_flats, nodes_total, s);
-  auto estep = [&](hipStream_t q, int32_t* so, float* go, const int* pm) {
+  auto estep = [&](hipStream_t q, int32_t* so, float* go, const int* pm, unsigned long long* wk) {
     if (soft)
       launch_soft_estep(xs, ys, zs, d_tiles, ntiles, rt, max_tree_levels, f->d_trees, f->d_tab, f->d_nodes, d_state,
                         d_bins,
@@ -1093,19 +1141,18 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
       launch_flat_estep(xs, ys, zs, d_tiles, ntiles, rt, f->d_trees, d_flatf, d_flats, d_state, d_bins, so, go, pm,
                         rr.flat_level, q);
     else
-      launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_bins, d_dpart,
-                     pstride, so, go, pm, g_tune.reg_lds_levels, rr.max_levels, q);
+      launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_fbins,
+                     fp64_atomics ? d_bins : nullptr, so, go, pm, g_tune.reg_lds_levels, rr.max_levels, wk, q);
   };
   auto mstep = [&](hipStream_t q) {
-    launch_normal(d_bins, d_dpart, pstride, d_ptiles, f->d_nodes, f->d_trees, d_state, d_nmov, P,
-                  (flat || soft) ? 2 : 0,
+    launch_normal(d_bins, d_fbins, f->d_nodes, f->d_trees, d_state, d_nmov, P, (flat || soft || fp64_atomics) ? 2 : 0,
                   rr.tol_rot, rr.tol_trans_rel, rr.max_iters, d_out, q);
   };
   if (mode_estep) {
-    estep(s, stop_out, gamma_out, d_perm);
-    if (!flat && !soft) launch_fold_bins(d_ptiles, f->d_trees, d_dpart, pstride, d_bins, P, s);
+    estep(s, stop_out, gamma_out, d_perm, nullptr);
+    if (!flat && !soft && !fp64_atomics) launch_fold_bins(f->d_trees, d_fbins, d_bins, P, s);
     if (h_norm) {
-      launch_normal(d_bins, d_dpart, pstride, d_ptiles, f->d_nodes, f->d_trees, d_state, d_nmov, P, 1, 0.0, 0.0, 1,
+      launch_normal(d_bins, d_fbins, f->d_nodes, f->d_trees, d_state, d_nmov, P, 1, 0.0, 0.0, 1,
                     d_out, s);
       HIP_TRY(hipMemcpyAsync(h_nrm, d_out, sizeof(double) * 28 * P, hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
@@ -1127,7 +1174,9 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
     memcpy(&tt, &rr.tol_trans_rel, 8);
     const std::vector<uint64_t> key = {(uint64_t)xs, (uint64_t)ys, (uint64_t)zs, (uint64_t)d_tiles, (uint64_t)ntiles,
                                        (uint64_t)f->d_trees, (uint64_t)f->d_tab, (uint64_t)f->d_nodes,
-                                       (uint64_t)d_state, (uint64_t)d_bins, (uint64_t)d_dpart, (uint64_t)pstride,
+                                       (uint64_t)d_state, (uint64_t)d_bins, (uint64_t)d_fbins,
+                                       (uint64_t)g_tune.reg_tile, (uint64_t)g_tune.reg_lds_levels,
+                                       (uint64_t)g_tune.reg_atomics,
                                        (uint64_t)d_ptiles, (uint64_t)d_nmov, (uint64_t)P, (uint64_t)chunk, tr, tt,
                                        (uint64_t)rr.max_iters, (uint64_t)rr.max_levels, (uint64_t)d_out,
                                        (uint64_t)(int64_t)rr.flat_level, soft_key};
@@ -1136,7 +1185,7 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
       f->reg_key.clear();
       HIP_TRY(hipStreamBeginCapture(f->gstream, hipStreamCaptureModeThreadLocal));
       for (int c = 0; c < chunk; ++c) {
-        estep(f->gstream, nullptr, nullptr, nullptr);
+        estep(f->gstream, nullptr, nullptr, nullptr, nullptr);
         mstep(f->gstream);
       }
       hipGraph_t graph = nullptr;
@@ -1168,7 +1217,7 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
     for (; it < end; ++it) {
       {
         ProfScope ps(soft ? PK_SOFT : flat ? PK_FLAT : PK_DESCEND, (double)n_total, s, it, !fixed_stage);
-        estep(s, nullptr, nullptr, nullptr);
+        estep(s, nullptr, nullptr, nullptr, (!soft && !flat) ? ps.work_slot() : nullptr);
       }
       {
         ProfScope ps(PK_NORMAL, (double)nodes_total, s, it, !fixed_stage);
@@ -1522,7 +1571,7 @@ int hgmm_normal_equations(hgmm_tree tree, const double* d_bins, int64_t n, void*
   HIP_TRY(hipMemcpyAsync(d_nmov, hn, sizeof(int64_t), hipMemcpyHostToDevice, s));
   launch_init_pose((PoseState*)(ws + Ly.state), 1, d_pose0, d_pose0 + 9, 0, nullptr, s);
   // the kernel reads the bins without modifying them in mode 1
-  launch_normal(const_cast<double*>(d_bins), nullptr, 0, nullptr, tree->d_nodes, tree->d_trees,
+  launch_normal(const_cast<double*>(d_bins), nullptr, tree->d_nodes, tree->d_trees,
                 (PoseState*)(ws + Ly.state), d_nmov, 1, 1, 0.0, 0.0, 1, d_out, s);
   HIP_LAUNCHED();
   double* hres = h + 16;

@@ -115,6 +115,30 @@ struct PoseState {
   int32_t pad;
 };
 
+// Registration moments of one node in fixed point: M0 = sum gamma, D = sum
+// gamma (T(p) - mu) (3 values), Q = sum of squared Mahalanobis distances, and
+// the number of points.  A contribution v of value j is scaled by an exact or
+// fixed factor (kFixScaleM0 for M0, kFixScaleD / extent for D, kFixScaleQ for
+// Q),
+// split into its integer part hi = floor(v') and 32 fractional bits
+// lo = floor((v' - hi) 2^32), and the two parts are summed in separate 64-bit
+// integers with no carry between them: value' = sum hi + (sum lo) 2^-32.
+// Integer sums do not depend on the order of the additions, so the totals
+// are the same whatever order waves, blocks and XCDs add in, and every add is
+// an atomic add whose result is not needed (no round trip).  Scaled values
+// are saturated at +-2^62.  96 bytes.
+constexpr int kFixVals = 5;
+constexpr double kFixScaleM0 = 1048576.0;  // 2^20: resolution 2^-52, range 2^42 of gamma sums
+constexpr double kFixScaleD = 65536.0;     // 2^16 per extent: resolution 2^-48 extent, range 2^46 extent
+constexpr double kFixScaleQ = 0.00390625;  // 2^-8: resolution 2^-24, range 2^70 of squared distances
+struct FixBin {
+  unsigned long long lo[kFixVals];  // sums of 32-bit fractions
+  long long hi[kFixVals];           // sums of integer parts
+  unsigned long long cnt;
+  unsigned long long pad;
+};
+static_assert(sizeof(FixBin) == 96, "FixBin is 12 words");
+
 // ---------------------------------------------------------------------------
 // wave64 reductions through DPP (all 64 lanes must be active)
 // ---------------------------------------------------------------------------
@@ -228,6 +252,43 @@ __device__ __forceinline__ void wave_fold_masked(const double* __restrict__ p, s
 }
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// ---------------------------------------------------------------------------
+// fixed-point moments (FixBin)
+// ---------------------------------------------------------------------------
+
+// Integer part and 32 fractional bits of a scaled contribution (integer
+// parts within 32 bits, the usual case, take the single-instruction
+// conversion).
+__device__ __forceinline__ void fix_split(double v, unsigned long long& lo, long long& hi) {
+  v = fmin(fmax(v, -4611686018427387904.0), 4611686018427387904.0);
+  const double f = floor(v);
+  lo = (unsigned long long)(unsigned)((v - f) * 4294967296.0);  // v - f in [0, 1), exact
+  hi = (fabs(f) < 2147483648.0) ? (long long)(int)f : (long long)f;
+}
+
+__device__ __forceinline__ double from_fix(unsigned long long lo, long long hi) {
+  return (double)hi + (double)lo * 2.3283064365386963e-10;  // 2^-32
+}
+
+// Adds one split contribution; both words are plain 64-bit integer atomic
+// adds whose results are unused.  Works on LDS and global memory.
+__device__ __forceinline__ void fix_add(unsigned long long* plo, long long* phi, unsigned long long lo, long long hi) {
+  if (lo != 0ull) atomicAdd(plo, lo);
+  if (hi != 0ll) atomicAdd(reinterpret_cast<unsigned long long*>(phi), (unsigned long long)hi);
+}
+
+// The moments {M0, D (3), count, Q} of a fixed-point bin of a tree of the
+// given extent.
+__device__ __forceinline__ void fix_read(const FixBin& F, double extent, double (&b)[6]) {
+  const double uD = (extent > 0.0 ? extent : 1.0) / kFixScaleD;
+  b[0] = from_fix(F.lo[0], F.hi[0]) * (1.0 / kFixScaleM0);
+  b[1] = from_fix(F.lo[1], F.hi[1]) * uD;
+  b[2] = from_fix(F.lo[2], F.hi[2]) * uD;
+  b[3] = from_fix(F.lo[3], F.hi[3]) * uD;
+  b[4] = (double)F.cnt;
+  b[5] = from_fix(F.lo[4], F.hi[4]) * (1.0 / kFixScaleQ);
+}
 
 // ---------------------------------------------------------------------------
 // FP64 3x3 helpers

@@ -60,10 +60,14 @@ void launch_init_pose(PoseState* st, int npairs, const double* R0, const double*
                       hipStream_t s);
 // perm (nullable): original index of each point when the cloud was reordered,
 // for the per-point outputs stop_out / gamma_out
+// grid: 8 * ceil(ntiles / 8) blocks in XCD-aware tile order; fbins receives
+// the fixed-point moments, or, when atomic_bins is given, the moments are
+// added to those FP64 bins with FP64 atomics instead; work (nullable): points
+// processed and levels scored
 void launch_descend(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
-                    const TreeDev* trees, const NodeF* tab, const NodeD* nodes, const PoseState* st, double* bins,
-                    double* partials, size_t pstride, int32_t* stop_out, float* gamma_out, const int* perm,
-                    int lds_levels, int max_levels, hipStream_t s);
+                    const TreeDev* trees, const NodeF* tab, const NodeD* nodes, const PoseState* st, FixBin* fbins,
+                    double* atomic_bins, int32_t* stop_out, float* gamma_out, const int* perm, int lds_levels, int max_levels,
+                    unsigned long long* work, hipStream_t s);
 void launch_flat_table(const NodeF* tab, const NodeD* nodes, NodeF* ft, NodeS* fs, int64_t n, hipStream_t s);
 void launch_flat_estep(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
                        int tile_points, const TreeDev* trees, const NodeF* tab, const NodeS* nodes,
@@ -75,11 +79,10 @@ void launch_soft_estep(const float* xs, const float* ys, const float* zs, const 
                        hipStream_t s);
 void launch_point_loglik(const float* xs, const float* ys, const float* zs, int64_t n, const int32_t* stop,
                          const TreeDev* trees, const NodeD* nodes, const PoseState* st, float* out, hipStream_t s);
-void launch_fold_bins(const int2* pair_tiles, const TreeDev* trees, const double* partials, size_t pstride,
-                      double* bins, int npairs, hipStream_t s);
-void launch_normal(double* bins, const double* dpart, size_t pstride, const int2* pair_tiles, const NodeD* nodes,
-                   const TreeDev* trees, PoseState* st, const int64_t* n_moving, int npairs, int mode, double tol_rot,
-                   double tol_trans_rel, int max_iters, double* out, hipStream_t s);
+void launch_fold_bins(const TreeDev* trees, const FixBin* fbins, double* bins, int npairs, hipStream_t s);
+void launch_normal(double* bins, FixBin* fbins, const NodeD* nodes, const TreeDev* trees, PoseState* st,
+                   const int64_t* n_moving, int npairs, int mode, double tol_rot, double tol_trans_rel, int max_iters,
+                   double* out, hipStream_t s);
 int normal_values();
 
 // spatial ordering of the moving clouds (Morton order inside each pair)

@@ -104,43 +104,76 @@ __device__ __forceinline__ int choose_child(NodePtr C, S64Ptr S, double p0, doub
   return k1;
 }
 
-constexpr int kLdsNodes = 72;             // levels 0 and 1 of one tree
-constexpr int kLdsRows = kLdsNodes * 6;  // value rows of the block partials (mask rows follow)
+constexpr int kLdsNodes = 72;    // levels 0 and 1 of one tree
+// gamma is recomputed from FP64 scores when its FP32 rounding bound exceeds
+// this (relative); the moments' tolerance against the oracle is 1e-5
+constexpr float kGammaTol = 4e-6f;
 
-// gamma of the stop child k among the live siblings, with FP64 scores for k
-// and for every sibling whose FP32 weight 2^(s_j - s_k) exceeds 2^-40; the
-// weights of the others (each below 2^-40) are kept from FP32, so their
-// rounding moves gamma by less than 1e-11 relative.
+// gamma of the stop child k among the live siblings.  Siblings whose FP32
+// weight t_j = 2^(s_j - s_k) contributes more than 1e-7 to gamma's rounding
+// bound (t_j (err_j + err_k) ln 2 gamma) take FP64 scores together with k;
+// the others keep their FP32 weights, so the recomputed gamma is within
+// 8e-7 relative of its FP64 value.
 template <typename S64Ptr>
-__device__ __forceinline__ float gamma_fp64(S64Ptr S, uint32_t lm, int k, const float (&s)[8], float sk, double p0,
-                                            double p1, double p2) {
+__device__ __forceinline__ float gamma_fp64(S64Ptr S, uint32_t lm, int k, const float (&s)[8], const float (&err)[8],
+                                            float sk, float ek, float gam32, double p0, double p1, double p2) {
   const double skd = score64(S[k], p0, p1, p2);
   float den = 1.0f;
   for (int j = 0; j < 8; ++j) {
     if (!(lm >> j & 1u) || j == k) continue;
-    const float dj = s[j] - sk;
-    den += __builtin_amdgcn_exp2f(dj > -40.f ? (float)(score64(S[j], p0, p1, p2) - skd) : dj);
+    const float tj = __builtin_amdgcn_exp2f(s[j] - sk);
+    const bool exact = 0.6931472f * tj * (err[j] + ek) * gam32 > 1e-7f;
+    den += exact ? __builtin_amdgcn_exp2f((float)(score64(S[j], p0, p1, p2) - skd)) : tj;
   }
   return 1.0f / den;
 }
 
-// One E-step over the tiles of every pair.  tiles[].job is the pair index.
-// Points stopping at the LDS-resident levels (0 and 1) are binned in FP64 LDS
-// accumulators, written as value-major block partials and folded in a fixed
-// order by the next kernel (no cross-block handoff inside this kernel).
-// Deeper stop nodes receive few points each and are added with FP64 atomics.
-// NLEV: number of leading tree levels whose FP32 scoring records are staged in
-// LDS (2: the 72 nodes of levels 0-1; 3: also the 512 of level 2, 37 KB).
-// The FP64 scoring prefix and the FP64 bins are staged for levels 0-1.
-template <int NLEV>
+// Adds a row {M0, D (3), count, Q} of sums to a fixed-point bin (sD: the
+// tree's D scale, kFixScaleD / extent).
+__device__ __forceinline__ void fix_add_row(FixBin* B, const double* r, double sD) {
+  const double v[kFixVals] = {r[0] * kFixScaleM0, r[1] * sD, r[2] * sD, r[3] * sD, r[5] * kFixScaleQ};
+#pragma unroll
+  for (int j = 0; j < kFixVals; ++j) {
+    unsigned long long lo;
+    long long hi;
+    fix_split(v[j], lo, hi);
+    fix_add(&B->lo[j], &B->hi[j], lo, hi);
+  }
+  atomicAdd(&B->cnt, (unsigned long long)r[4]);
+}
+
+// One E-step over the tiles of every pair (tiles[].job is the pair index).
+// Each point is transformed in FP64 and descends the tree (Algorithm 1).
+// The moments of equal stop nodes are summed across the wave (FP32).  For the
+// 72 nodes of levels 0-1 one lane adds them in FP64 to the wave's own LDS
+// bins, in the wave's fixed order; at the end of the block the four waves'
+// bins are added in wave order and go to the node bins in HBM.  Deeper stop
+// nodes go to the node bins directly.  The node bins are fixed point
+// (FixBin): integer sums that do not depend on the order in which waves and
+// blocks add, so the moments, and the registration, are bitwise reproducible.
+// NLEV: number of leading tree levels whose FP32 scoring records are staged
+// in LDS (2: the 72 nodes of levels 0-1; 3: also the 512 of level 2, 37 KB).
+// The FP64 scoring prefix is staged for levels 0-1.
+// Grid: 8 * per_xcd blocks.  Consecutive blocks are dispatched to consecutive
+// XCDs, so block b takes tile (b % 8) * per_xcd + b / 8: every XCD works
+// through one contiguous range of tiles (of pairs), whose node records then
+// stay in that XCD's L2.
+// work (nullable, profiling): adds the points processed and the levels they
+// scored to work[0] and work[1].
+// ATOMICS: the comparison mode, in which each wave's sums are added to FP64
+// node bins (bins, 6 values per node) with FP64 atomics instead.
+template <int NLEV, bool ATOMICS>
 __global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
                                                       const float* __restrict__ zs, const Tile* __restrict__ tiles,
-                                                      const TreeDev* __restrict__ trees, const NodeF* __restrict__ tab,
-                                                      const NodeD* __restrict__ nodes, const PoseState* __restrict__ st,
-                                                      double* bins, double* partials, size_t pstride,
-                                                      int32_t* stop_out, float* gamma_out,
-                                                      const int* __restrict__ perm, int max_levels) {
-  const Tile tl = tiles[blockIdx.x];
+                                                      int ntiles, int per_xcd, const TreeDev* __restrict__ trees,
+                                                      const NodeF* __restrict__ tab, const NodeD* __restrict__ nodes,
+                                                      const PoseState* __restrict__ st, FixBin* fbins,
+                                                      double* bins, int32_t* stop_out, float* gamma_out,
+                                                      const int* __restrict__ perm, int max_levels,
+                                                      unsigned long long* work) {
+  const int tix = (int)(blockIdx.x & 7u) * per_xcd + (int)(blockIdx.x >> 3);
+  if (tix >= ntiles) return;
+  const Tile tl = tiles[tix];
   const int pair = tl.job;
   if (st[pair].done) return;
   const TreeDev& T = trees[pair];
@@ -150,8 +183,9 @@ __global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ 
   constexpr int kStaged = NLEV >= 3 ? 584 : kLdsNodes;
   __shared__ NodeF lds[kStaged];
   __shared__ NodeS lds64[kLdsNodes];
-  __shared__ double lbin[kLdsNodes * 6];
-  const int nl = T.levels >= 2 ? 72 : 8;  // LDS-binned nodes: as the normal-equation fold expects
+  __shared__ double wbin[4][kLdsNodes][6];
+  __shared__ unsigned long long wsum[2];
+  const int nl = T.levels >= 2 ? 72 : 8;
   const int nst = L >= NLEV ? kStaged : (L >= 2 ? 72 : 8);
   for (int i = threadIdx.x; i < nst; i += blockDim.x) {
     const float4* s = reinterpret_cast<const float4*>(&tab[nb + i]);
@@ -164,12 +198,19 @@ __global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ 
     for (int k = 0; k < 6; ++k) lds64[i].winv[k] = nd.winv[k];
     lds64[i].c = nd.c;
   }
-  for (int i = threadIdx.x; i < kLdsNodes * 6; i += blockDim.x) lbin[i] = 0.0;
+  {
+    double* z = &wbin[0][0][0];
+    for (int i = threadIdx.x; i < 4 * kLdsNodes * 6; i += blockDim.x) z[i] = 0.0;
+    if (threadIdx.x < 2) wsum[threadIdx.x] = 0ull;
+  }
   __syncthreads();
   const double R0 = st[pair].R[0], R1 = st[pair].R[1], R2 = st[pair].R[2], R3 = st[pair].R[3],
                R4 = st[pair].R[4], R5 = st[pair].R[5], R6 = st[pair].R[6], R7 = st[pair].R[7],
                R8 = st[pair].R[8], t0 = st[pair].t[0], t1 = st[pair].t[1], t2 = st[pair].t[2];
   const int lane = __lane_id();
+  const int wv = threadIdx.x >> 6;
+  const double sD = kFixScaleD / (T.extent > 0.0 ? T.extent : 1.0);
+  unsigned my_points = 0u, my_levels = 0u;
   for (int b0 = tl.start; b0 < tl.end; b0 += blockDim.x) {
     const int i = b0 + threadIdx.x;
     const bool valid = i < tl.end;
@@ -181,33 +222,24 @@ __global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ 
       const double p1 = R3 * z0 + R4 * z1 + R5 * z2 + t1;
       const double p2 = R6 * z0 + R7 * z1 + R8 * z2 + t2;
       int parent = 0;
+      int l = 0;
       float s[8], q[8], m[8];
       uint32_t lm;
-      for (int l = 0; l < L; ++l) {
+      for (; l < L; ++l) {
         const int64_t lbase = lvl_off(l) + 8 * (int64_t)parent;
-        int k;
-        uint32_t flags;
-        float err[8];
-        if (l < 2) {
-          const NodeF* C = lds + lbase;
-          k = choose_child(C, lds64 + lbase, p0, p1, p2, s, q, m, lm);
-          flags = k >= 0 ? C[k].flags : 0u;
+        const bool in_lds = l < 2 || l < NLEV;
+        const NodeF* C = in_lds ? lds + lbase : tab + nb + lbase;
+        const int k = (l < 2) ? choose_child(C, lds64 + lbase, p0, p1, p2, s, q, m, lm)
+                              : choose_child(C, nodes + nb + lbase, p0, p1, p2, s, q, m, lm);
+        if (k < 0) break;  // no live node here: the point is left unassigned
+        const uint32_t flags = C[k].flags;
+        if ((flags & F_STOP) || !(flags & F_HASCH) || (l == L - 1)) {
+          // weight of the point at the chosen node: its posterior among the
+          // live siblings, gamma = 1 / sum_j 2^(s_j - s_k), with the FP32
+          // rounding bound of that sum
+          float err[8];
 #pragma unroll
           for (int j = 0; j < 8; ++j) err[j] = score_err(C[j], q[j], m[j]);
-        } else {
-          const NodeF* C = (l < NLEV) ? lds + lbase : tab + nb + lbase;
-          k = choose_child(C, nodes + nb + lbase, p0, p1, p2, s, q, m, lm);
-          flags = k >= 0 ? C[k].flags : 0u;
-          if (k >= 0 && ((flags & F_STOP) || !(flags & F_HASCH) || (l == L - 1))) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) err[j] = score_err(C[j], q[j], m[j]);
-          }
-        }
-        if (k < 0) break;  // no live node here: the point is left unassigned
-        const bool stop = (flags & F_STOP) || !(flags & F_HASCH) || (l == L - 1);
-        if (stop) {
-          // weight of the point at the chosen node: its posterior among the
-          // live siblings, gamma = 1 / sum_j 2^(s_j - s_k)
           float sk = s[0], ek = err[0];
 #pragma unroll
           for (int j = 1; j < 8; ++j) {
@@ -223,45 +255,37 @@ __global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ 
             if (j != k) bnd = fmaf(tj, err[j] + ek, bnd);
           }
           gam = 1.0f / den;
-          // rounding bound of gamma from the FP32 score bounds; above 1e-6
-          // (relative) the sibling scores are recomputed in FP64
-          if (0.6931472f * bnd * gam > 1e-6f)
-            gam = (l < 2) ? gamma_fp64(lds64 + lbase, lm, k, s, sk, p0, p1, p2)
-                          : gamma_fp64(nodes + nb + lbase, lm, k, s, sk, p0, p1, p2);
+          if (0.6931472f * bnd * gam > kGammaTol)
+            gam = (l < 2) ? gamma_fp64(lds64 + lbase, lm, k, s, err, sk, ek, gam, p0, p1, p2)
+                          : gamma_fp64(nodes + nb + lbase, lm, k, s, err, sk, ek, gam, p0, p1, p2);
           g = nb + lbase + k;
           break;
         }
         parent = 8 * parent + k;
       }
-      if (g < 0) {
-        const int oi = perm ? perm[i] : i;
-        if (stop_out) stop_out[oi] = -1;
-        if (gamma_out) gamma_out[oi] = 0.f;
+      my_points += 1u;
+      my_levels += (unsigned)min(l + 1, L);
+      if (g >= 0) {
+        // offset from the node mean (one FP32 rounding of an FP64 difference)
+        // and the squared Mahalanobis distance in FP64, after the descent so
+        // that lanes stopping at different levels compute them together
+        const int64_t lg = g - nb;
+        const double* mu = (lg < nl) ? lds64[lg].mu : nodes[g].mu;
+        const double* wi = (lg < nl) ? lds64[lg].winv : nodes[g].winv;
+        const double e0 = p0 - mu[0], e1 = p1 - mu[1], e2 = p2 - mu[2];
+        d0 = (float)e0;
+        d1 = (float)e1;
+        d2 = (float)e2;
+        const double w0 = wi[0] * e0;
+        const double w1 = wi[1] * e0 + wi[2] * e1;
+        const double w2 = wi[3] * e0 + wi[4] * e1 + wi[5] * e2;
+        dm2 = (float)(w0 * w0 + w1 * w1 + w2 * w2);
       }
-    }
-    if (valid && g >= 0) {
-      const double z0 = xs[i], z1 = ys[i], z2 = zs[i];
-      const double p0 = R0 * z0 + R1 * z1 + R2 * z2 + t0;
-      const double p1 = R3 * z0 + R4 * z1 + R5 * z2 + t1;
-      const double p2 = R6 * z0 + R7 * z1 + R8 * z2 + t2;
-      // offset from the node mean (one FP32 rounding of an FP64 difference) and
-      // the squared Mahalanobis distance in FP64 (levels 0-1 from LDS)
-      const int64_t lg = g - nb;
-      const double* mu = (lg < nl) ? lds64[lg].mu : nodes[g].mu;
-      const double* wi = (lg < nl) ? lds64[lg].winv : nodes[g].winv;
-      const double e0 = p0 - mu[0], e1 = p1 - mu[1], e2 = p2 - mu[2];
-      d0 = (float)e0;
-      d1 = (float)e1;
-      d2 = (float)e2;
-      const double w0 = wi[0] * e0;
-      const double w1 = wi[1] * e0 + wi[2] * e1;
-      const double w2 = wi[3] * e0 + wi[4] * e1 + wi[5] * e2;
-      dm2 = (float)(w0 * w0 + w1 * w1 + w2 * w2);
       const int oi = perm ? perm[i] : i;
-      if (stop_out) stop_out[oi] = (int32_t)(g - nb);
+      if (stop_out) stop_out[oi] = g >= 0 ? (int32_t)(g - nb) : -1;
       if (gamma_out) gamma_out[oi] = gam;
     }
-    // aggregate equal stop nodes inside the wave, then one FP64 atomic per node
+    // sum equal stop nodes across the wave, then one fixed-point add per node
     bool pend = valid && g >= 0;
     unsigned long long pending = __ballot(pend);
     while (pending) {
@@ -269,58 +293,70 @@ __global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ 
       const int64_t key = __shfl(g, leader, 64);
       const bool mine = pend && (g == key);
       const unsigned long long mm = __ballot(mine);
-      const float v0 = wave_sum(mine ? gam : 0.f);
-      const float v1 = wave_sum(mine ? gam * d0 : 0.f);
-      const float v2 = wave_sum(mine ? gam * d1 : 0.f);
-      const float v3 = wave_sum(mine ? gam * d2 : 0.f);
-      const float v5 = wave_sum(mine ? dm2 : 0.f);
-      if (lane == leader) {
+      const float v[kFixVals] = {wave_sum(mine ? gam : 0.f), wave_sum(mine ? gam * d0 : 0.f),
+                                 wave_sum(mine ? gam * d1 : 0.f), wave_sum(mine ? gam * d2 : 0.f),
+                                 wave_sum(mine ? dm2 : 0.f)};
+      // lanes 0-4 add one value each and lane 5 the count: FP64 atomics into
+      // the node bins (comparison mode), FP64 adds into the wave's own LDS
+      // bins (levels 0-1), or fixed-point adds into the node bins
+      if (lane < 6) {
         const int64_t local = key - nb;
-        double* B = (local < nl) ? lbin + local * 6 : bins + key * 6;
-        unsafeAtomicAdd(B + 0, (double)v0);
-        unsafeAtomicAdd(B + 1, (double)v1);
-        unsafeAtomicAdd(B + 2, (double)v2);
-        unsafeAtomicAdd(B + 3, (double)v3);
-        unsafeAtomicAdd(B + 4, (double)__popcll(mm));
-        unsafeAtomicAdd(B + 5, (double)v5);
+        const float vj = lane == 0 ? v[0] : lane == 1 ? v[1] : lane == 2 ? v[2] : lane == 3 ? v[3] : v[4];
+        const double xj = lane == 5 ? (double)__popcll(mm) : (double)vj;
+        const int col = lane < 4 ? lane : 9 - lane;  // bins order {M0, D, count, Q}
+        if (ATOMICS) {
+          unsafeAtomicAdd(bins + key * 6 + col, xj);
+        } else if (local < nl) {
+          // one lane per value, in the wave's order
+          unsafeAtomicAdd(&wbin[wv][local][col], xj);
+        } else {
+          FixBin& F = fbins[key];
+          if (lane < 5) {
+            const double sc = lane == 0 ? kFixScaleM0 : lane < 4 ? sD : kFixScaleQ;
+            unsigned long long lo;
+            long long hi;
+            fix_split(xj * sc, lo, hi);
+            fix_add(&F.lo[lane], &F.hi[lane], lo, hi);
+          } else {
+            atomicAdd(&F.cnt, (unsigned long long)__popcll(mm));
+          }
+        }
       }
       pend = pend && !mine;
       pending &= ~mm;
     }
   }
   __syncthreads();
-  // block partials of the LDS-resident levels, value-major, for the nodes this
-  // block's points reached, and a mask of those nodes (rows kLdsRows and
-  // kLdsRows + 1: nodes 0-63, 64-71); the normal-equation kernel folds them
-  // in a fixed order.  Points reach only a few of the 72 nodes per block.
-  for (int i = threadIdx.x; i < nl * 6; i += blockDim.x)
-    if (lbin[(i / 6) * 6 + 4] > 0.0) partials[(size_t)i * pstride + blockIdx.x] = lbin[i];
-  if (threadIdx.x < 128) {
-    const int node = threadIdx.x;
-    const uint64_t m = __ballot(node < nl && lbin[node * 6 + 4] > 0.0);
-    if (lane == 0)
-      reinterpret_cast<uint64_t*>(partials + (size_t)(kLdsRows + (node >> 6)) * pstride)[blockIdx.x] = m;
+  // the level-0/1 bins into the node bins in HBM, the four waves' sums added
+  // in wave order
+  for (int e = threadIdx.x; !ATOMICS && e < nl; e += blockDim.x) {
+    double r[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) r[j] = ((wbin[0][e][j] + wbin[1][e][j]) + wbin[2][e][j]) + wbin[3][e][j];
+    if (r[4] > 0.0) fix_add_row(&fbins[nb + e], r, sD);
+  }
+  if (work) {
+    atomicAdd(&wsum[0], (unsigned long long)my_points);
+    atomicAdd(&wsum[1], (unsigned long long)my_levels);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      atomicAdd(&work[0], wsum[0]);
+      atomicAdd(&work[1], wsum[1]);
+    }
   }
 }
 
-// Writes the folded LDS-level moments into the node bins (for callers that
-// read the bins directly).  One block per pair.
-__global__ __launch_bounds__(256) void fold_bins_kernel(const int2* __restrict__ pair_tiles,
-                                                        const TreeDev* __restrict__ trees,
-                                                        const double* __restrict__ partials, size_t pstride,
-                                                        double* bins) {
-  const int pair = blockIdx.x;
-  const TreeDev& T = trees[pair];
-  const int nl = T.levels >= 2 ? 72 : 8;
-  const int2 pt = pair_tiles[pair];
-  const int lane = __lane_id(), wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int node = wv; node < nl; node += nw) {
-    double v[6];
-    const uint64_t* mask = reinterpret_cast<const uint64_t*>(partials + (size_t)(kLdsRows + (node >> 6)) * pstride);
-    wave_fold_masked<6, 4>(partials + (size_t)node * 6 * pstride + pt.x, pstride, mask + pt.x, node & 63, pt.y, lane,
-                           v);
-    if (lane == 0)
-      for (int j = 0; j < 6; ++j) bins[(T.node_base + node) * 6 + j] = v[j];
+// The node bins of the fixed-point moments as FP64 bins {M0, D (3), count,
+// Q} (for callers that read the bins directly).  One block per pair.
+__global__ __launch_bounds__(256) void fold_bins_kernel(const TreeDev* __restrict__ trees,
+                                                        const FixBin* __restrict__ fbins, double* bins) {
+  const TreeDev& T = trees[blockIdx.x];
+  const int64_t nn = lvl_off(T.levels);
+  for (int64_t g = T.node_base + threadIdx.x; g < T.node_base + nn; g += blockDim.x) {
+    double b[6];
+    fix_read(fbins[g], T.extent, b);
+    double* B = bins + g * 6;
+    for (int j = 0; j < 6; ++j) B[j] = b[j];
   }
 }
 
@@ -681,13 +717,12 @@ __device__ __forceinline__ void node_terms(const NodeD& nd, const double* b, dou
 }
 
 // One block per pair.  mode 0: normal equations from this iteration's moments
-// (LDS-level nodes folded from the descent's block partials, deeper nodes read
-// and cleared from the bins), Cholesky solve and pose update.  mode 1: the
-// same sums from the bins alone, written to out[pair * 28 ..] (H upper, g,
-// mean log-likelihood).  mode 2: as mode 0 with every node's moments read and
-// cleared from the bins (the single-level E-step writes no block partials).
-__global__ __launch_bounds__(kNormThreads) void normal_kernel(double* bins, const double* __restrict__ dpart,
-                                                              size_t pstride, const int2* __restrict__ pair_tiles,
+// (the descent's fixed-point node bins, read and cleared), Cholesky solve and
+// pose update.  mode 1: the same sums from the FP64 bins alone, written to
+// out[pair * 28 ..] (H upper, g, mean log-likelihood).  mode 2: as mode 0
+// with every node's moments read and cleared from the FP64 bins (the
+// single-level and soft E-steps add FP64 moments there).
+__global__ __launch_bounds__(kNormThreads) void normal_kernel(double* bins, FixBin* fbins,
                                                               const NodeD* __restrict__ nodes,
                                                               const TreeDev* __restrict__ trees, PoseState* st,
                                                               const int64_t* __restrict__ n_moving, int mode,
@@ -699,42 +734,30 @@ __global__ __launch_bounds__(kNormThreads) void normal_kernel(double* bins, cons
   const TreeDev& T = trees[pair];
   const int64_t nn = lvl_off(T.levels);
   const int64_t nb = T.node_base;
-  const int nl = T.levels >= 2 ? 72 : 8;
   const double N = (double)n_moving[pair];
   const double o0 = T.origin[0], o1 = T.origin[1], o2 = T.origin[2];
   const int lane = __lane_id(), wv = threadIdx.x >> 6;
-  const bool from_partials = (mode == 0);
-  // phase 1: fixed-order fold of the LDS-level nodes' block partials
-  __shared__ double lb[kLdsNodes * 6];
-  if (from_partials) {
-    const int2 pt = pair_tiles[pair];
-    for (int node = wv; node < nl; node += kNormThreads / 64) {
-      double b[6];
-      const uint64_t* mask = reinterpret_cast<const uint64_t*>(dpart + (size_t)(kLdsRows + (node >> 6)) * pstride);
-      wave_fold_masked<6, 4>(dpart + (size_t)node * 6 * pstride + pt.x, pstride, mask + pt.x, node & 63, pt.y, lane,
-                             b);
-      if (lane == 0)
-        for (int j = 0; j < 6; ++j) lb[node * 6 + j] = b[j];
-    }
-    __syncthreads();
-  }
-  // phase 2: every node with mass adds its rows to the normal equations
+  // every node with mass adds its rows to the normal equations
   double acc[kNV];
 #pragma unroll
   for (int v = 0; v < kNV; ++v) acc[v] = 0.0;
-  if (from_partials)
-    for (int node = threadIdx.x; node < nl; node += kNormThreads) {
-      double b[6] = {lb[node * 6], lb[node * 6 + 1], lb[node * 6 + 2], lb[node * 6 + 3], lb[node * 6 + 4],
-                     lb[node * 6 + 5]};
-      if (b[0] > 0.0) node_terms(nodes[nb + node], b, N, o0, o1, o2, acc);
+  for (int64_t g = threadIdx.x; g < nn; g += kNormThreads) {
+    double b[6];
+    if (mode == 0) {
+      FixBin& F = fbins[nb + g];
+      if (F.cnt == 0ull) continue;
+      fix_read(F, T.extent, b);
+#pragma unroll
+      for (int j = 0; j < kFixVals; ++j) { F.lo[j] = 0ull; F.hi[j] = 0ll; }
+      F.cnt = 0ull;
+    } else {
+      double* B = bins + (nb + g) * 6;
+      b[0] = B[0];
+      if (!(b[0] > 0.0)) continue;
+      b[1] = B[1]; b[2] = B[2]; b[3] = B[3]; b[4] = B[4]; b[5] = B[5];
+      if (mode == 2) { B[0] = 0.0; B[1] = 0.0; B[2] = 0.0; B[3] = 0.0; B[4] = 0.0; B[5] = 0.0; }
     }
-  for (int64_t g = (from_partials ? nl : 0) + threadIdx.x; g < nn; g += kNormThreads) {
-    double* B = bins + (nb + g) * 6;
-    const double m0 = B[0];
-    if (!(m0 > 0.0)) continue;
-    double b[6] = {m0, B[1], B[2], B[3], B[4], B[5]};
-    if (mode != 1) { B[0] = 0.0; B[1] = 0.0; B[2] = 0.0; B[3] = 0.0; B[4] = 0.0; B[5] = 0.0; }
-    node_terms(nodes[nb + g], b, N, o0, o1, o2, acc);
+    if (b[0] > 0.0) node_terms(nodes[nb + g], b, N, o0, o1, o2, acc);
   }
   __shared__ double red[kNormThreads / 64][kNV];
   __shared__ double tot[kNV];
@@ -837,15 +860,23 @@ void launch_import_nodes(NodeD* nodes, NodeF* tab, int64_t n, hipStream_t s) {
 }
 
 void launch_descend(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
-                    const TreeDev* trees, const NodeF* tab, const NodeD* nodes, const PoseState* st, double* bins,
-                    double* partials, size_t pstride, int32_t* stop_out, float* gamma_out, const int* perm,
-                    int lds_levels, int max_levels, hipStream_t s) {
-  if (lds_levels >= 3)
-    hipLaunchKernelGGL(descend_kernel<3>, dim3(ntiles), dim3(256), 0, s, xs, ys, zs, tiles, trees, tab, nodes, st, bins,
-                       partials, pstride, stop_out, gamma_out, perm, max_levels);
-  else
-    hipLaunchKernelGGL(descend_kernel<2>, dim3(ntiles), dim3(256), 0, s, xs, ys, zs, tiles, trees, tab, nodes, st, bins,
-                       partials, pstride, stop_out, gamma_out, perm, max_levels);
+                    const TreeDev* trees, const NodeF* tab, const NodeD* nodes, const PoseState* st, FixBin* fbins,
+                    double* atomic_bins, int32_t* stop_out, float* gamma_out, const int* perm, int lds_levels,
+                    int max_levels, unsigned long long* work, hipStream_t s) {
+  if (ntiles <= 0) return;
+  const int per_xcd = (ntiles + 7) / 8;
+  const dim3 grid((unsigned)(8 * per_xcd));
+#define HGMM_DESCEND(NL, AT)                                                                                          \
+  hipLaunchKernelGGL((descend_kernel<NL, AT>), grid, dim3(256), 0, s, xs, ys, zs, tiles, ntiles, per_xcd, trees, tab, \
+                     nodes, st, fbins, atomic_bins, stop_out, gamma_out, perm, max_levels, work)
+  if (atomic_bins) {
+    if (lds_levels >= 3) HGMM_DESCEND(3, true);
+    else HGMM_DESCEND(2, true);
+  } else {
+    if (lds_levels >= 3) HGMM_DESCEND(3, false);
+    else HGMM_DESCEND(2, false);
+  }
+#undef HGMM_DESCEND
 }
 
 void launch_flat_table(const NodeF* tab, const NodeD* nodes, NodeF* ft, NodeS* fs, int64_t n, hipStream_t s) {
@@ -863,16 +894,15 @@ void launch_flat_estep(const float* xs, const float* ys, const float* zs, const 
                      nodes, st, bins, stop_out, gamma_out, perm, level);
 }
 
-void launch_fold_bins(const int2* pair_tiles, const TreeDev* trees, const double* partials, size_t pstride,
-                      double* bins, int npairs, hipStream_t s) {
-  hipLaunchKernelGGL(fold_bins_kernel, dim3(npairs), dim3(256), 0, s, pair_tiles, trees, partials, pstride, bins);
+void launch_fold_bins(const TreeDev* trees, const FixBin* fbins, double* bins, int npairs, hipStream_t s) {
+  hipLaunchKernelGGL(fold_bins_kernel, dim3(npairs), dim3(256), 0, s, trees, fbins, bins);
 }
 
-void launch_normal(double* bins, const double* dpart, size_t pstride, const int2* pair_tiles, const NodeD* nodes,
-                   const TreeDev* trees, PoseState* st, const int64_t* n_moving, int npairs, int mode, double tol_rot,
-                   double tol_trans_rel, int max_iters, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(normal_kernel, dim3(npairs), dim3(kNormThreads), 0, s, bins, dpart, pstride, pair_tiles, nodes,
-                     trees, st, n_moving, mode, tol_rot, tol_trans_rel, max_iters, out);
+void launch_normal(double* bins, FixBin* fbins, const NodeD* nodes, const TreeDev* trees, PoseState* st,
+                   const int64_t* n_moving, int npairs, int mode, double tol_rot, double tol_trans_rel, int max_iters,
+                   double* out, hipStream_t s) {
+  hipLaunchKernelGGL(normal_kernel, dim3(npairs), dim3(kNormThreads), 0, s, bins, fbins, nodes, trees, st, n_moving,
+                     mode, tol_rot, tol_trans_rel, max_iters, out);
 }
 
 int normal_values() { return kNV; }
