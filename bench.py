@@ -1,16 +1,23 @@
 """Throughput of GMM-Tree registration on one MI355X.
 
-One step = the whole hot path for one cloud pair: build the GMM tree of the
-source cloud (root statistics, per-level EM, partition) and register the
-target cloud against it (adaptive descent, moments, normal equations, solve),
-inputs already resident in HBM.  The default workload is the spinning-scanner
-pair (64 rings x 1875 azimuths, 4 levels).
+Headline step: the uneven batch of 256 unit-cube cloud pairs (N log-uniform
+in [2e3, 2e5] points per cloud, rotation U(0, 45 deg), tree depth
+ceil(log8(N / 50))) registered in one batch with the learned warm start and
+the plain-likelihood fallback: the source forest, the 2-level target forest,
+the level-1 features, the network and its head, the registration capped at
+two levels and then over the whole tree, the plain method from the identity
+as the judge, and the choice per pair.  Inputs are resident in HBM.
 
-Prints one JSON line: pairs/s, ms/step, the dominant kernel's achieved rate
-against the MI355X roofline (from HIP events bracketing its launches inside
-the timed region), the E-step rate in Mpts/s, the registration error of the
-timed runs, and the FP64 CPU oracle timed on a bounded sample of the same
-workload.
+Prints one JSON line: pairs/s of that step and, beside it, the plain GPU form
+(one pair at a time: build + register from the identity) and the batched
+plain form; the median rotation error and the pairs registered within
+0.5 deg per second; the E-step rate (device-counted points / descent time);
+the dominant kernel's achieved rate against the MI355X roofline, from HIP
+events around its launches on the library's stream in a repeat of the timed
+steps; the FP64 CPU oracle timed on a bounded sample of the same pairs; and
+sections for the other workloads (single small pair, LiDAR pair, depth-camera
+pair, 4,096 held-out warm-start pairs, registration variants, odometry,
+network training).
 """
 
 from __future__ import annotations
@@ -19,6 +26,8 @@ import argparse
 import json
 import math
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -28,22 +37,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+METRIC = "cloud pairs registered/s + E-step Mpts/s at rot err<=0.5deg, batched vs plain"
+
 # MI355X peaks.  HBM: published 8 TB/s.  FP32 vector: the published 157.3
 # TFLOP/s counts packed (2-wide) FMA; the kernels are built without packed FP32
-# instructions, so their ceiling is 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (FMA)
-# x 2.4 GHz = 78.6 TFLOP/s, the figure the ALU roofline is quoted against.
+# instructions, so they can reach at most 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP
+# (FMA) x 2.4 GHz = 78.6 TFLOP/s, which is reported beside the published figure.
 PEAK_HBM_GBS = 8000.0
-PEAK_FP32_PACKED_TFLOPS = 157.3
-PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+PEAK_BF16_TFLOPS = 2500.0
 
-# Algorithmic work per unit (every arithmetic step of the method counted once, FMA = 2 FLOP):
-#  construction EM, per point-iteration: 8 children x (score 19 + softmax 4 + moments 21) FLOP
-EM_FLOP_PER_POINT_ITER = 8 * 44
+# Algorithmic work per unit (FMA = 2 FLOP): construction E/M, per
+# point-iteration: 8 sibling scores, softmax and 10 moments each, about 380
+# FLOP (+ 8 exp), 12 bytes (points sorted by parent); registration E-step, per
+# point: transform and stop-level work 40 FLOP plus 215 FLOP per tree level
+# the point scores (8 children), 12 bytes.
+EM_FLOP_PER_POINT_ITER = 380
 EM_BYTES_PER_POINT_ITER = 12
-#  registration descent, per point: transform 18 + per visited level 8 x 19 + stop level 35 FLOP
-DESC_FLOP_FIXED = 18 + 35
-DESC_FLOP_PER_LEVEL = 8 * 19
+DESC_FLOP_FIXED = 40
+DESC_FLOP_PER_LEVEL = 215
 DESC_BYTES_PER_POINT = 12
+MLP_FLOP_FWD_PER_SAMPLE = 2 * (1280 * 512 + 2 * 512 * 512 + 512 * 9)
+
+WEIGHTS = os.path.join(ROOT, "paper_1807_02587_amd", "weights", "warm_mlp.npy")
+BATCH_SHAPES = os.path.join(ROOT, "profiles", "batch_launch_shapes.json")
+LIDAR_SHAPES = os.path.join(ROOT, "profiles", "lidar_launch_shapes.json")
 
 
 def progress(msg):
@@ -51,39 +70,64 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def roofline_of(prof, depth, traffic=None):
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _timed(fn):
+    _sync()
+    t0 = time.perf_counter()
+    r = fn()
+    _sync()
+    return r, time.perf_counter() - t0
+
+
+def _rot_err(R, Rt):
+    R = np.asarray(R).reshape(-1, 3, 3)
+    Rt = np.asarray(Rt).reshape(-1, 3, 3)
+    c = (np.einsum("bij,bij->b", R, Rt) - 1.0) / 2.0
+    return np.degrees(np.arccos(np.clip(c, -1.0, 1.0)))
+
+
+def _profile_kinds(hg):
+    return {k: hg.hgmm_profile_read(k) for k in hg.PROFILE_KINDS}
+
+
+def roofline_of(prof, traffic=None):
     """ALU roofline of the kernel family with the largest summed event time.
-    prof: hgmm_profile_read per kind; depth: mean levels visited per point by
-    the descent (for its FLOP count); traffic: which committed counter summary
-    ("lidar" or "batch") gives the HBM bytes per launch, or None."""
-    cand = {"em_tile": ("em_tile_kernel (construction EM iteration of large parents)", EM_FLOP_PER_POINT_ITER,
-                        EM_BYTES_PER_POINT_ITER),
-            "em_block": ("em_block_kernel (all construction EM iterations, one block per parent)",
-                         EM_FLOP_PER_POINT_ITER, EM_BYTES_PER_POINT_ITER),
-            "descend": ("descend_kernel (registration E-step)", DESC_FLOP_FIXED + DESC_FLOP_PER_LEVEL * depth,
-                        DESC_BYTES_PER_POINT)}
-    fam_frac = {}
-    for k, (_, fu, _) in cand.items():
-        if prof[k]["ms"] > 0:
-            fam_frac[k] = round(prof[k]["units"] * fu / (prof[k]["ms"] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4)
-    dom = max(cand, key=lambda k: prof[k]["ms"])
-    kname, flop_unit, bytes_unit = cand[dom]
-    ms, launches, units = prof[dom]["ms"], prof[dom]["launches"], prof[dom]["units"]
-    flop, byts = units * flop_unit, units * bytes_unit
-    achieved = flop / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
-    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": _traffic(dom, traffic) if traffic else None,
-            "kernel": kname, "launches": launches, "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
-            "flop_per_launch": round(flop / max(launches, 1)),
-            "frac_of_packed_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4),
-            "achieved_hbm_GBs": round(byts / (ms * 1e-3) / 1e9, 1) if ms > 0 else 0.0,
-            "frac_by_family": fam_frac, **(_valu(dom, traffic) if traffic else {})}
-
-
-def mean_depth(stop, level_offsets):
-    """Mean number of levels a point visited, from its stop node (index in its tree)."""
-    st = stop[stop >= 0]
-    return float(np.mean(np.searchsorted(level_offsets, st, side="right"))) if st.size else 0.0
+    prof: hgmm_profile_read per kind (event ms, launches, host units, and for
+    the descent the device-counted points and levels).  traffic: which
+    committed counter summary ("batch" or "lidar") gives HBM bytes per launch."""
+    flop = {"em_tile": lambda p: p["units"] * EM_FLOP_PER_POINT_ITER,
+            "em_block": lambda p: p["units"] * EM_FLOP_PER_POINT_ITER,
+            "descend": lambda p: DESC_FLOP_FIXED * p["points"] + DESC_FLOP_PER_LEVEL * p["levels"]}
+    byts = {"em_tile": lambda p: p["units"] * EM_BYTES_PER_POINT_ITER,
+            "em_block": lambda p: p["units"] * EM_BYTES_PER_POINT_ITER,
+            "descend": lambda p: p["points"] * DESC_BYTES_PER_POINT}
+    names = {"em_tile": "em_tile_kernel (construction EM iteration of large parents)",
+             "em_block": "em_block_kernel (all construction EM iterations, one block per parent)",
+             "descend": "descend_kernel (registration E-step)"}
+    fam = {}
+    for k in flop:
+        p = prof[k]
+        if p["ms"] > 0 and p["launches"] > 0:
+            fam[k] = round(flop[k](p) / (p["ms"] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4)
+    dom = max(flop, key=lambda k: prof[k]["ms"])
+    p = prof[dom]
+    ms, n = p["ms"], max(p["launches"], 1)
+    f_launch, b_launch, us = flop[dom](p) / n, byts[dom](p) / n, ms * 1e3 / n
+    achieved = f_launch / (us * 1e-6) / 1e12 if us > 0 else 0.0
+    out = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+           "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": _traffic(dom, traffic) if traffic else None,
+           "kernel": names[dom], "launches": p["launches"], "avg_launch_us": round(us, 2),
+           "flop_per_launch": round(f_launch), "algorithmic_bytes_per_launch": round(b_launch),
+           "frac_of_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
+           "achieved_hbm_GBs": round(b_launch / (us * 1e-6) / 1e9, 1) if us > 0 else 0.0,
+           "frac_by_family": fam}
+    if traffic:
+        out.update(_valu(dom, traffic))
+    return out
 
 
 TRAFFIC = {"lidar": os.path.join(ROOT, "profiles", "lidar_hbm_traffic.json"),
@@ -123,198 +167,6 @@ def _valu(family, which):
     f = v["families"][family]
     return {"valu_busy_pct": f["valu_busy_pct"], "valu_utilization_pct": f["valu_utilization_pct"],
             "counted_flop_frac": f["counted_frac"]}
-
-
-def _workload(name):
-    from paper_1807_02587_amd.presets import PRESETS
-    from synth import depth_pair, lidar_pair, small_pair
-    if name == "lidar":
-        p = lidar_pair(1000)
-        desc = "lidar 64 rings x 1875 azimuths, ground + 50 boxes + 30 cylinders, 1 m / <=2 deg motion"
-    elif name == "small":
-        p = small_pair(0)
-        desc = "planes+spheres unit cube, 10k points, <=30 deg / 0.1 motion"
-    elif name == "depth":
-        p = depth_pair(2000)
-        desc = "depth camera 640x480 in a furnished room, <=10 deg / 0.2 m motion"
-    else:
-        raise SystemExit(f"unknown workload {name}")
-    return p, PRESETS[name], desc
-
-
-WEIGHTS = os.path.join(ROOT, "paper_1807_02587_amd", "weights", "warm_mlp.npy")
-
-
-def batch_section(args, hg):
-    """The uneven batch (256 unit-cube pairs, N log-uniform in [2e3, 2e5],
-    rotation U(0, 45 deg), depth ceil(log8(N/50))) registered three ways:
-    one pair at a time (plain form), batched from identity, batched with the
-    learned warm start and its likelihood fallback."""
-    import torch
-    from paper_1807_02587_amd import warmstart as W
-    from synth.torch_scenes import uneven_batch
-
-    src, tgt, off, lv, Rt, tt = uneven_batch(3000, args.batch_pairs)
-    B = len(lv)
-    ws = hg.Workspace()
-    cfg = W.WarmConfig()
-    if args.copy_calibration:
-        # counter calibration: a plain copy of known size, then the batched
-        # plain form twice with the given launch shapes
-        a = torch.empty(args.copy_mib << 18, dtype=torch.float32, device=src.device).fill_(1.0)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        if args.batch_tuning_json:
-            with open(args.batch_tuning_json) as f:
-                hg.hgmm_set_tuning(**json.load(f))
-        for _ in range(2):
-            forest = hg.hgmm_build_batch(src, off, lv, ws=ws)
-            hg.hgmm_register_batch(forest, tgt, off, ws=ws)
-        torch.cuda.synchronize()
-        return {"copy_bytes": a.numel() * 4, "steps": 2}
-
-    def plain_sequential(k_list):
-        Rs = []
-        tree = None
-        for k in k_list:
-            s_k = src[:, off[k]:off[k + 1]].contiguous()
-            t_k = tgt[:, off[k]:off[k + 1]].contiguous()
-            tree = hg.hgmm_build(s_k, levels=int(lv[k]), ws=ws, tree=tree)
-            Rs.append(hg.hgmm_register(tree, t_k, ws=ws, raise_singular=False)["R"])
-        return np.array(Rs)
-
-    last = {}
-
-    def batched_plain():
-        # the handle is reused, as a caller registering batch after batch would
-        forest = hg.hgmm_build_batch(src, off, lv, ws=ws, forest=last.get("forest"))
-        r = hg.hgmm_register_batch(forest, tgt, off, ws=ws)
-        last.update(forest=forest, r=r)
-        return r["R"]
-
-    net = None
-    if os.path.exists(WEIGHTS):
-        net = hg.MLP(seed=0)
-        net.set_params(np.load(WEIGHTS))
-
-    def batched_warm():
-        return W.register_warm(net, src, tgt, off, off, lv, cfg, ws=ws)
-
-    def timed(fn):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = fn()
-        torch.cuda.synchronize()
-        return r, time.perf_counter() - t0
-
-    def summary(name, R, sec):
-        e = W.rotation_errors_deg(R, Rt)
-        ok = int(np.sum(e <= 0.5))
-        return {f"{name}_pairs_s": round(B / sec, 2), f"{name}_median_rot_err_deg": round(float(np.median(e)), 4),
-                f"{name}_ok_0p5": ok, f"{name}_ok_pairs_s": round(ok / sec, 2)}
-
-    # plain form: one pair at a time, default launch shapes
-    defaults = hg.hgmm_get_tuning()
-    out = {"workload": f"{B} unit-cube pairs, N log-uniform [2e3, 2e5] (total {int(off[-1])} points per side), "
-                       "rotation U(0,45 deg), levels ceil(log8(N/50))"}
-    tp = None
-    if not args.batch_only:
-        plain_sequential(range(min(8, B)))
-        Rp, tp = timed(lambda: plain_sequential(range(B)))
-        out.update(summary("plain_sequential", Rp, tp))
-    # batched forms: launch shapes from the autotuner on this batch (outside the timed runs)
-    if args.batch_tuning_json:
-        with open(args.batch_tuning_json) as f:
-            hg.hgmm_set_tuning(**json.load(f))
-        out["autotune"] = {"tuning": hg.hgmm_get_tuning(), "from": args.batch_tuning_json}
-    else:
-        from paper_1807_02587_amd import autotune
-        t_tune = time.perf_counter()
-        tun = autotune.tuned(src, off, lv, tgt, off, use_cache=False, reps=1, passes=1, ws=ws)
-        out["autotune"] = {"tuning": tun["tuning"], "search_s": round(time.perf_counter() - t_tune, 2),
-                           "start_ms": round(tun["start_ms"], 2), "best_ms": round(tun["best_ms"], 2)}
-    if args.save_batch_tuning:
-        with open(args.save_batch_tuning, "w") as f:
-            json.dump(hg.hgmm_get_tuning(), f)
-    batched_plain()
-    Rb, tb = timed(batched_plain)
-    out.update(summary("batched", Rb, tb))
-    if tp:
-        out["speedup_batched_vs_plain"] = round(tp / tb, 2)
-    # the batched plain form once more with HIP events around every launch:
-    # per-kernel durations and the roofline of its dominant kernel
-    hg.hgmm_profile_reset()
-    hg.hgmm_profile(True)
-    batched_plain()
-    torch.cuda.synchronize()
-    hg.hgmm_profile(False)
-    prof = {k: hg.hgmm_profile_read(k) for k in hg.PROFILE_KINDS}
-    _, stop = hg.hgmm_estep_batch(last["forest"], tgt, off, last["r"]["R"], last["r"]["t"], ws=ws, stop_nodes=True)
-    offs_l = np.array([hg.hgmm_level_offset(l) for l in range(8)])
-    depth = mean_depth(stop.cpu().numpy(), offs_l)
-    ds = prof["descend"]
-    out["profiled"] = {"kernels_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
-                       "mean_levels_visited": round(depth, 3),
-                       "estep_mpts_s": round(ds["units"] / (ds["ms"] * 1e-3) / 1e6, 1) if ds["ms"] > 0 else None,
-                       "roofline": roofline_of(prof, depth, traffic="batch")}
-    if net is not None:
-        batched_warm()
-        rw, tw = timed(batched_warm)
-        out.update(summary("batched_warm", rw["R"], tw))
-        out["warm_fallback_rate"] = round(float(np.mean(rw["fallback"])), 4)
-        if tp:
-            out["speedup_batched_warm_vs_plain"] = round(tp / tw, 2)
-        if tp and out["plain_sequential_ok_0p5"] > 0:
-            out["speedup_ok_pairs_s_batched_warm_vs_plain"] = round(
-                out["batched_warm_ok_pairs_s"] / out["plain_sequential_ok_pairs_s"], 2)
-    hg.hgmm_set_tuning(**defaults)
-    return out
-
-
-def depth_section(args, hg):
-    """The depth-camera pair (640x480 camera in a furnished room, about 2.9e5
-    points per view, 5 levels, the precision form's workload): build of the
-    source tree plus registration from the identity per step, with launch
-    shapes from the autotuner on this pair (chosen before the timed steps)."""
-    import torch
-    from synth import rotation_angle_deg
-    p, pr, desc = _workload("depth")
-    dev = torch.device("cuda", 0)
-    src = torch.from_numpy(p.src).to(dev)
-    tgt = torch.from_numpy(p.tgt).to(dev)
-    n1, n2 = p.src.shape[1], p.tgt.shape[1]
-    ws_b, ws_r = hg.Workspace(dev), hg.Workspace(dev)
-    keep = hg.hgmm_get_tuning()
-    tree = None
-
-    def step():
-        nonlocal tree
-        tree = hg.hgmm_build(src, levels=pr["levels"], reg_eps=pr["reg_eps"], min_mass=pr["min_mass"], ws=ws_b,
-                             tree=tree)
-        return hg.hgmm_register(tree, tgt, lambda_c=pr["lambda_c"], ws=ws_r, raise_singular=False)
-
-    try:
-        tun = hg.hgmm_autotune(src, [0, n1], [pr["levels"]], tgt, [0, n2], reg_eps=pr["reg_eps"],
-                               min_mass=pr["min_mass"], lambda_c=pr["lambda_c"], reps=1, passes=1)
-        for _ in range(2):
-            step()
-        torch.cuda.synchronize()
-        steps = max(3, args.steps // 2)
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            r = step()
-        torch.cuda.synchronize()
-        sec = time.perf_counter() - t0
-        shapes = hg.hgmm_get_tuning()
-    finally:
-        hg.hgmm_set_tuning(**keep)
-    return {"workload": f"depth: {desc}", "points_src": n1, "points_tgt": n2, "levels": pr["levels"],
-            "reg_eps": pr["reg_eps"], "min_mass": pr["min_mass"], "steps": steps,
-            "pairs_s": round(steps / sec, 2), "ms_per_step": round(sec / steps * 1e3, 3),
-            "rot_err_deg": round(rotation_angle_deg(r["R"], p.R_true), 4), "iters": int(r["iters"]),
-            "autotune_ms": {"start": round(tun["start_ms"], 3), "best": round(tun["best_ms"], 3)},
-            "launch_shapes": shapes}
 
 
 # single-level E-step, per point-component pair: FP64 offset 3, whitening of
@@ -457,19 +309,292 @@ def odometry_section(args, hg, frames=16):
     return out
 
 
+def _workload(name):
+    from paper_1807_02587_amd.presets import PRESETS
+    from synth import depth_pair, lidar_pair, small_pair
+    if name == "lidar":
+        p = lidar_pair(1000)
+        desc = "LiDAR pair: 64 rings x 1875 azimuths, ground + 50 boxes + 30 cylinders, 1 m / <=2 deg motion"
+    elif name == "small":
+        p = small_pair(0)
+        desc = "small pair: 4 planes + 2 spheres in the unit cube, 10k points, <=30 deg / 0.1 motion"
+    elif name == "depth":
+        p = depth_pair(2000)
+        desc = "depth-camera pair: 640x480 in a furnished room, <=10 deg / 0.2 m motion"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return p, PRESETS[name], desc
+
+
+def host_info():
+    """Host CPU of the box the bench runs on: logical CPUs and model."""
+    model = platform.processor() or ""
+    try:
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+# ---------------------------------------------------------------------------
+# headline: the uneven batch, batched + warm start, against the plain form
+# ---------------------------------------------------------------------------
+
+class Batch:
+    """The uneven batch on the GPU and the three ways of registering it."""
+
+    def __init__(self, hg, pairs):
+        from paper_1807_02587_amd import warmstart as W
+        from synth.torch_scenes import uneven_batch
+        self.hg, self.W = hg, W
+        self.src, self.tgt, self.off, self.lv, Rt, tt = uneven_batch(3000, pairs)
+        self.Rt = Rt.cpu().numpy() if hasattr(Rt, "cpu") else np.asarray(Rt)
+        self.tt = tt.cpu().numpy() if hasattr(tt, "cpu") else np.asarray(tt)
+        self.B = len(self.lv)
+        self.cfg = W.WarmConfig()
+        self.ws = hg.Workspace()
+        self.net = hg.MLP(seed=0)
+        self.net.set_params(np.load(WEIGHTS))
+        self.forest = None
+
+    def warm(self):
+        return self.W.register_warm(self.net, self.src, self.tgt, self.off, self.off, self.lv, self.cfg, ws=self.ws)
+
+    def batched_plain(self):
+        self.forest = self.hg.hgmm_build_batch(self.src, self.off, self.lv, ws=self.ws, forest=self.forest)
+        return self.hg.hgmm_register_batch(self.forest, self.tgt, self.off, ws=self.ws)
+
+    def plain_one_at_a_time(self, ks):
+        hg, Rs, tree = self.hg, [], None
+        for k in ks:
+            s_k = self.src[:, self.off[k]:self.off[k + 1]].contiguous()
+            t_k = self.tgt[:, self.off[k]:self.off[k + 1]].contiguous()
+            tree = hg.hgmm_build(s_k, levels=int(self.lv[k]), ws=self.ws, tree=tree)
+            Rs.append(hg.hgmm_register(tree, t_k, ws=self.ws, raise_singular=False)["R"])
+        return np.array(Rs)
+
+
+def headline(args, hg):
+    import torch
+    bt = Batch(hg, args.batch_pairs)
+    B = bt.B
+    if args.copy_calibration:
+        # a plain copy of known size beside the steps: its FETCH_SIZE /
+        # WRITE_SIZE turn the counters into bytes
+        a = torch.empty(args.copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        _sync()
+    for _ in range(args.warmup):
+        bt.warm()
+    # timed region: K steps with nothing but the step's own work
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = bt.warm()
+    _sync()
+    sec = time.perf_counter() - t0
+    err = _rot_err(r["R"], bt.Rt)
+    out = {"value": round(args.steps * B / sec, 2), "ms_per_step": round(sec * 1e3 / args.steps, 3),
+           "rot_err_deg_median": round(float(np.median(err)), 4), "ok_0p5_rate": round(float(np.mean(err <= 0.5)), 4),
+           "fallback_rate": round(float(np.mean(r["fallback"])), 4)}
+    out["pairs_s_within_0p5deg"] = round(out["value"] * out["ok_0p5_rate"], 2)
+    if args.copy_calibration:
+        return out, None, bt
+    # the same K steps again with a HIP event pair around every launch on the
+    # library's stream (the events slow the host side, so this region is not
+    # the timed one): per-kernel durations, device-counted descent work
+    hg.hgmm_profile_reset()
+    hg.hgmm_profile(True)
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        bt.warm()
+    _sync()
+    t2 = time.perf_counter()
+    hg.hgmm_profile(False)
+    prof = _profile_kinds(hg)
+    d = prof["descend"]
+    out["estep_mpts_s"] = round(d["points"] / (d["ms"] * 1e-3) / 1e6, 1) if d["ms"] > 0 else None
+    out["estep_levels_per_point"] = round(d["levels"] / d["points"], 3) if d["points"] > 0 else None
+    out["kernels_ms_per_step"] = {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()}
+    out["profiled_region_ms_per_step"] = round((t2 - t1) * 1e3 / args.steps, 3)
+    out["roofline"] = roofline_of(prof, traffic="batch")
+    progress("headline (batched + warm) done")
+    # the plain GPU form, one pair at a time, and the batched plain form
+    bt.plain_one_at_a_time(range(min(8, B)))
+    Rp, tp = _timed(lambda: bt.plain_one_at_a_time(range(B)))
+    ep = _rot_err(Rp, bt.Rt)
+    bt.batched_plain()
+    rb, tb = _timed(bt.batched_plain)
+    eb = _rot_err(rb["R"], bt.Rt)
+    plain = {"pairs_s": round(B / tp, 2), "rot_err_deg_median": round(float(np.median(ep)), 4),
+             "ok_0p5_rate": round(float(np.mean(ep <= 0.5)), 4)}
+    plain["pairs_s_within_0p5deg"] = round(plain["pairs_s"] * plain["ok_0p5_rate"], 2)
+    bplain = {"pairs_s": round(B / tb, 2), "rot_err_deg_median": round(float(np.median(eb)), 4),
+              "ok_0p5_rate": round(float(np.mean(eb <= 0.5)), 4)}
+    # E-step rate of the plain form's registration, one pair at a time
+    hg.hgmm_profile_reset()
+    hg.hgmm_profile(True)
+    bt.plain_one_at_a_time(range(B))
+    _sync()
+    hg.hgmm_profile(False)
+    dp = hg.hgmm_profile_read("descend")
+    plain["estep_mpts_s"] = round(dp["points"] / (dp["ms"] * 1e-3) / 1e6, 1) if dp["ms"] > 0 else None
+    out["plain_one_pair_at_a_time"] = plain
+    out["batched_plain"] = bplain
+    out["speedup_vs_plain"] = round(out["value"] / plain["pairs_s"], 2)
+    out["speedup_within_0p5deg_vs_plain"] = (round(out["pairs_s_within_0p5deg"] / plain["pairs_s_within_0p5deg"], 1)
+                                             if plain["pairs_s_within_0p5deg"] > 0 else None)
+    out["estep_speedup_vs_plain"] = (round(out["estep_mpts_s"] / plain["estep_mpts_s"], 2)
+                                     if plain["estep_mpts_s"] else None)
+    progress("plain forms done")
+    return out, prof, bt
+
+
+def cpu_baseline(args, bt):
+    """The FP64 oracle's whole warm-start step (source tree, 2-level target
+    tree, features, network, head, capped and full registration, plain
+    registration from the identity, choice) on a size-stratified sample of the
+    same pairs, single-threaded, scaled to the batch by its point count."""
+    import oracle
+    from oracle import warm as owarm
+    params = np.load(WEIGHTS).astype(np.float64)
+    off, lv = bt.off, bt.lv
+    n = np.diff(off)
+    order = np.argsort(n)
+    k_all = max(1, bt.B // args.cpu_stride)
+    sample = [int(order[min(len(order) - 1, args.cpu_stride // 2 + i * args.cpu_stride)]) for i in range(k_all)]
+    # visited in a fixed shuffled order, so that a sample cut short by the
+    # time limit still spans the sizes
+    sample = [sample[i] for i in np.random.default_rng(0).permutation(len(sample))]
+    t_used, pts, done, errs = 0.0, 0, 0, []
+    src = bt.src.cpu().numpy()
+    tgt = bt.tgt.cpu().numpy()
+    for k in sample:
+        s_k = np.ascontiguousarray(src[:, off[k]:off[k + 1]])
+        t_k = np.ascontiguousarray(tgt[:, off[k]:off[k + 1]])
+        c0 = time.perf_counter()
+        ts, _ = oracle.build_tree(s_k, int(lv[k]), eps=bt.cfg.reg_eps, min_mass=bt.cfg.min_mass)
+        tt, _ = oracle.build_tree(t_k, bt.cfg.tgt_levels, eps=bt.cfg.reg_eps, min_mass=bt.cfg.min_mass)
+        r = owarm.register_warm(params, ts, tt, t_k, bt.cfg.reg_eps, lambda_c=bt.cfg.lambda_c,
+                                max_iters=bt.cfg.max_iters, coarse_levels=bt.cfg.coarse_levels)
+        t_used += time.perf_counter() - c0
+        pts += int(n[k])
+        done += 1
+        errs.append(float(_rot_err(r["R"], bt.Rt[k])[0]))
+        if t_used > args.cpu_seconds:
+            break
+    est = t_used * float(off[-1]) / pts
+    return {"value": round(bt.B / est, 4), "unit": "pairs/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} of the {bt.B} pairs (drawn every {args.cpu_stride} by size; {pts} source points of "
+                      f"{int(off[-1])}), the whole warm-start step in FP64 on one thread, {t_used:.1f} s; "
+                      f"scaled to the batch by points",
+            "sample_rot_err_deg_median": round(float(np.median(errs)), 4), **host_info()}
+
+
+# ---------------------------------------------------------------------------
+# single pairs: small (unit cube), LiDAR, depth camera
+# ---------------------------------------------------------------------------
+
+def pair_section(args, hg, name, steps, shapes=None, oracle_reps=0, oracle_seconds=10.0):
+    """Build of the source tree plus registration of the target from the
+    identity per step, one pair; the FP64 oracle on the same pair."""
+    import torch
+    p, pr, desc = _workload(name)
+    keep = hg.hgmm_get_tuning()
+    if shapes and os.path.exists(shapes):
+        with open(shapes) as f:
+            hg.hgmm_set_tuning(**json.load(f))
+    dev = torch.device("cuda", 0)
+    src = torch.from_numpy(p.src).to(dev)
+    tgt = torch.from_numpy(p.tgt).to(dev)
+    ws_b, ws_r = hg.Workspace(dev), hg.Workspace(dev)
+    tree = None
+
+    def step():
+        nonlocal tree
+        tree = hg.hgmm_build(src, levels=pr["levels"], reg_eps=pr["reg_eps"], min_mass=pr["min_mass"], ws=ws_b,
+                             tree=tree)
+        return hg.hgmm_register(tree, tgt, lambda_c=pr["lambda_c"], ws=ws_r, raise_singular=False)
+
+    try:
+        for _ in range(3):
+            step()
+        _sync()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = step()
+        _sync()
+        sec = time.perf_counter() - t0
+        hg.hgmm_profile_reset()
+        hg.hgmm_profile(True)
+        for _ in range(steps):
+            step()
+        _sync()
+        hg.hgmm_profile(False)
+        prof = _profile_kinds(hg)
+        shapes_used = hg.hgmm_get_tuning()
+    finally:
+        hg.hgmm_set_tuning(**keep)
+    d = prof["descend"]
+    out = {"workload": desc, "points_src": int(p.src.shape[1]), "points_tgt": int(p.tgt.shape[1]),
+           "levels": pr["levels"], "reg_eps": pr["reg_eps"], "min_mass": pr["min_mass"], "steps": steps,
+           "pairs_s": round(steps / sec, 2), "ms_per_step": round(sec * 1e3 / steps, 3),
+           "rot_err_deg": round(float(_rot_err(r["R"], p.R_true)[0]), 4), "iters": int(r["iters"]),
+           "estep_mpts_s": round(d["points"] / (d["ms"] * 1e-3) / 1e6, 1) if d["ms"] > 0 else None,
+           "kernels_ms_per_step": {k: round(v["ms"] / steps, 4) for k, v in prof.items()},
+           "roofline": roofline_of(prof, traffic="lidar" if name == "lidar" else None),
+           "launch_shapes": shapes_used, "tree": tree, "tgt": tgt, "pair": p, "preset": pr}
+    if oracle_reps:
+        import oracle
+        t_c, reps = 0.0, 0
+        while reps < oracle_reps and (reps == 0 or t_c < oracle_seconds):
+            c0 = time.perf_counter()
+            ot, _ = oracle.build_tree(p.src, pr["levels"], eps=pr["reg_eps"], min_mass=pr["min_mass"])
+            ro = oracle.register(ot, p.tgt, lambda_c=pr["lambda_c"])
+            t_c += time.perf_counter() - c0
+            reps += 1
+        out["oracle"] = {"pairs_s": round(reps / t_c, 4), "cores": 1, "pairs_timed": reps,
+                         "rot_err_deg": round(float(_rot_err(ro["R"], p.R_true)[0]), 4)}
+    return out
+
+
+def _public(sec):
+    return {k: v for k, v in sec.items() if k not in ("tree", "tgt", "pair", "preset")}
+
+
+def depth_context_run(hg):
+    """The paper-shaped context run of the depth-camera scene: 5000 points
+    per view, 3 levels (the Lounge protocol's frame size and depth), GPU and
+    oracle from the identity over five generated rooms."""
+    import torch
+    import oracle
+    from paper_1807_02587_amd.presets import PRESETS
+    from synth import depth_pair
+    pr = PRESETS["depth"]
+    rows = []
+    for seed in range(2000, 2005):
+        p = depth_pair(seed, downsample=5000)
+        tree = hg.hgmm_build(torch.from_numpy(p.src).cuda(), levels=3, reg_eps=pr["reg_eps"], min_mass=pr["min_mass"])
+        r = hg.hgmm_register(tree, torch.from_numpy(p.tgt).cuda(), lambda_c=pr["lambda_c"], raise_singular=False)
+        ot, _ = oracle.build_tree(p.src, 3, eps=pr["reg_eps"], min_mass=pr["min_mass"])
+        ro = oracle.register(ot, p.tgt, lambda_c=pr["lambda_c"])
+        rows.append((float(_rot_err(r["R"], p.R_true)[0]), float(_rot_err(ro["R"], p.R_true)[0])))
+    g, o = np.array(rows).T
+    return {"workload": "depth-camera scene, 5000 points per view, 3 levels, 5 rooms, from the identity",
+            "gpu_rot_err_deg": [round(x, 4) for x in g], "oracle_rot_err_deg": [round(x, 4) for x in o],
+            "gpu_median_deg": round(float(np.median(g)), 4), "oracle_median_deg": round(float(np.median(o)), 4)}
+
+
 def warm_section(args, hg):
     """Held-out warm-start pairs (10k points per cloud, rotation U(0, 90 deg),
-    translation U(-0.1, 0.1)^3, L = 2; seeds disjoint from training): the plain
-    GPU form one pair at a time (hgmm_build + hgmm_register from the identity)
-    against the batched form with the learned warm start and the plain-
-    likelihood fallback, which includes the target trees, features and network.
-    The plain form is timed on the first `plain_pairs` pairs."""
-    import torch
+    translation U(-0.1, 0.1)^3, L = 2; seeds disjoint from training): the
+    batched warm start with the plain-likelihood fallback against the plain
+    GPU form one pair at a time (timed on the first 256 pairs)."""
     from paper_1807_02587_amd import warmstart as W
     from synth.torch_scenes import cube_pairs
-
-    if not os.path.exists(WEIGHTS):
-        return None
     B, n, plain_pairs = args.warm_pairs, 10_000, min(args.warm_pairs, 256)
     S = cube_pairs(5 * 10**6 + 11, B, n=n, max_angle_deg=90)
     off = S.offsets.numpy()
@@ -491,25 +616,21 @@ def warm_section(args, hg):
     def warm():
         return W.register_warm(net, S.src, S.tgt, off, off, [cfg.src_levels] * B, cfg, ws=ws)
 
-    def timed(fn):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = fn()
-        torch.cuda.synchronize()
-        return r, time.perf_counter() - t0
-
     plain(range(8))
-    Rp, tp = timed(lambda: plain(range(plain_pairs)))
+    Rp, tp = _timed(lambda: plain(range(plain_pairs)))
     warm()
-    rw, tw = timed(warm)
-    ep = W.rotation_errors_deg(Rp, Rt[:plain_pairs])
-    ew = W.rotation_errors_deg(rw["R"], Rt)
+    rw, tw = _timed(warm)
+    ep = _rot_err(Rp, Rt[:plain_pairs])
+    ew = _rot_err(rw["R"], Rt)
     out = {"workload": f"{B} held-out pairs, {n} points per cloud, rotation U(0,90 deg), L = 2 "
-                       f"(plain form timed on {plain_pairs})",
+                       f"(plain form timed on the first {plain_pairs})",
            "plain_pairs_s": round(plain_pairs / tp, 2), "plain_median_rot_err_deg": round(float(np.median(ep)), 4),
            "plain_ok_0p5_rate": round(float(np.mean(ep <= 0.5)), 4),
            "batched_warm_pairs_s": round(B / tw, 2), "batched_warm_median_rot_err_deg": round(float(np.median(ew)), 4),
+           "batched_warm_p90_rot_err_deg": round(float(np.percentile(ew, 90)), 4),
            "batched_warm_ok_0p5_rate": round(float(np.mean(ew <= 0.5)), 4),
+           "batched_warm_ok_5_rate": round(float(np.mean(ew <= 5.0)), 4),
+           "batched_warm_iters_mean": round(float(np.mean(rw["iters"])), 2),
            "warm_fallback_rate": round(float(np.mean(rw["fallback"])), 4),
            "speedup_batched_warm_vs_plain": round((B / tw) / (plain_pairs / tp), 2)}
     out["speedup_ok_pairs_s"] = (round(out["batched_warm_pairs_s"] * out["batched_warm_ok_0p5_rate"]
@@ -518,201 +639,135 @@ def warm_section(args, hg):
     return out
 
 
+def mlp_section(args, hg):
+    """The warm-start network on its own: inference and training steps (bf16
+    MFMA GEMMs) on random rows, samples/s and the GEMMs' achieved TFLOP/s."""
+    import torch
+    rows = 4096
+    X = torch.randn(rows, 1280, device="cuda")
+    T = torch.randn(rows, 9, device="cuda")
+    net = hg.MLP(seed=1)
+    net.forward(X)
+    _, tf = _timed(lambda: [net.forward(X) for _ in range(20)])
+    net.train_step(X, T, 1e-4, want_loss=False)
+    _, tt = _timed(lambda: [net.train_step(X, T, 1e-4, want_loss=False) for _ in range(20)])
+    fwd = MLP_FLOP_FWD_PER_SAMPLE * rows * 20
+    return {"rows": rows, "forward_samples_s": round(rows * 20 / tf, 1),
+            "forward_tflops": round(fwd / tf / 1e12, 2),
+            "train_samples_s": round(rows * 20 / tt, 1),
+            "train_tflops": round(3 * fwd / tt / 1e12, 2),
+            "frac_of_bf16_peak_train": round(3 * fwd / tt / 1e12 / PEAK_BF16_TFLOPS, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="lidar", choices=["lidar", "small", "depth"])
+    ap.add_argument("--batch-pairs", type=int, default=256)
+    ap.add_argument("--warm-pairs", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--batch-pairs", type=int, default=256)
-    ap.add_argument("--no-batch", action="store_true", help="skip the batched and warm-start sections")
-    ap.add_argument("--warm-pairs", type=int, default=1024)
-    ap.add_argument("--batch-only", action="store_true",
-                    help="run only the batched forms of the uneven batch (for profiling them)")
-    ap.add_argument("--batch-tuning-json", default=None, help="launch shapes of the batched forms from this file")
-    ap.add_argument("--save-batch-tuning", default=None, help="write the batched forms' launch shapes to this file")
-    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
-    ap.add_argument("--tuning-json", default=None, help="launch shapes from this file instead of the autotuner")
-    ap.add_argument("--save-tuning", default=None, help="write the launch shapes used to this file")
+    ap.add_argument("--cpu-stride", type=int, default=16, help="oracle sample: every n-th pair by size")
+    ap.add_argument("--only", default=None,
+                    choices=["headline", "small", "lidar", "depth", "warm", "variants", "odometry", "mlp"],
+                    help="run one section only (profiling runs)")
+    ap.add_argument("--batch-shapes", default=BATCH_SHAPES, help="launch shapes of the batched forms")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a device copy of --copy-mib MiB and a few steps (for counter calibration)")
-    ap.add_argument("--copy-mib", type=int, default=256)
-    ap.add_argument("--odometry-only", action="store_true", help="run only the odometry section")
-    ap.add_argument("--variants-only", action="store_true",
-                    help="build the main workload's tree once and run only the registration variants (for profiling)")
+                    help="with --only headline: a device copy of --copy-mib MiB beside the steps (counter scale)")
+    ap.add_argument("--copy-mib", type=int, default=1024)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); registration of independent "
-              "pairs would shard across GPUs by pair, which is not run here.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); independent pairs would shard "
+              "across GPUs by pair, which is not run here.", file=sys.stderr)
         sys.exit(2)
 
     import torch
     import paper_1807_02587_amd as hg
-    from synth import rotation_angle_deg
+    torch.cuda.set_device(0)
+    if not os.path.exists(WEIGHTS):
+        raise SystemExit(f"{WEIGHTS} is missing: the warm start's network weights are part of the package")
+    with open(args.batch_shapes) as f:
+        batch_shapes = json.load(f)
+    only = args.only
 
-    if args.batch_only:
-        torch.cuda.set_device(0)
-        print(json.dumps({"batched": batch_section(args, hg)}), flush=True)
+    def want(name):
+        return only is None or only == name
+
+    defaults = hg.hgmm_get_tuning()
+    head = prof = bt = cpu = None
+    if want("headline"):
+        hg.hgmm_set_tuning(**batch_shapes)
+        head, prof, bt = headline(args, hg)
+        if only is None and not args.no_cpu_baseline:
+            cpu = cpu_baseline(args, bt)
+            progress("CPU baseline done")
+        hg.hgmm_set_tuning(**defaults)
+        if only == "headline":
+            print(json.dumps({"headline": head}), flush=True)
+            return
+    sections = {}
+    if want("small"):
+        sec = pair_section(args, hg, "small", args.steps, oracle_reps=5)
+        sections["small_pair"] = _public(sec)
+        progress("small pair done")
+    lid = None
+    if want("lidar") or want("variants"):
+        lid = pair_section(args, hg, "lidar", args.steps, shapes=LIDAR_SHAPES, oracle_reps=1 if want("lidar") else 0)
+        sections["lidar_pair"] = _public(lid)
+        progress("LiDAR pair done")
+    if want("variants"):
+        hg.hgmm_set_tuning(**json.load(open(LIDAR_SHAPES)))
+        sections["variants"] = variants_section(args, hg, lid["tree"], lid["tgt"], lid["pair"], lid["preset"],
+                                                max(3, args.steps // 2))
+        hg.hgmm_set_tuning(**defaults)
+        progress("registration variants done")
+    if want("depth"):
+        sec = pair_section(args, hg, "depth", max(3, args.steps // 2))
+        sections["depth_pair"] = _public(sec)
+        sections["depth_pair"]["context_5000_points_3_levels"] = depth_context_run(hg)
+        progress("depth pair done")
+    if want("warm"):
+        hg.hgmm_set_tuning(**batch_shapes)
+        sections["warm_start_heldout"] = warm_section(args, hg)
+        hg.hgmm_set_tuning(**defaults)
+        progress("held-out warm-start pairs done")
+    if want("odometry"):
+        hg.hgmm_set_tuning(**json.load(open(LIDAR_SHAPES)))
+        sections["odometry"] = odometry_section(args, hg)
+        hg.hgmm_set_tuning(**defaults)
+        progress("odometry done")
+    if want("mlp"):
+        sections["mlp"] = mlp_section(args, hg)
+        progress("network done")
+    if only is not None:
+        print(json.dumps(sections), flush=True)
         return
-
-    p, pr, desc = _workload(args.workload)
-    dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
-    src = torch.from_numpy(p.src).to(dev)
-    tgt = torch.from_numpy(p.tgt).to(dev)
-    n1, n2 = p.src.shape[1], p.tgt.shape[1]
-    ws_b, ws_r = hg.Workspace(dev), hg.Workspace(dev)
-    tree = None
-
-    def step():
-        nonlocal tree
-        tree = hg.hgmm_build(src, levels=pr["levels"], reg_eps=pr["reg_eps"], min_mass=pr["min_mass"], ws=ws_b,
-                             tree=tree)
-        return hg.hgmm_register(tree, tgt, lambda_c=pr["lambda_c"], ws=ws_r, raise_singular=False)
-
-    if args.odometry_only:
-        print(json.dumps({"odometry": odometry_section(args, hg)}), flush=True)
-        return
-
-    if args.variants_only:
-        if args.tuning_json:
-            with open(args.tuning_json) as f:
-                hg.hgmm_set_tuning(**json.load(f))
-        step()
-        print(json.dumps({"variants": variants_section(args, hg, tree, tgt, p, pr, max(1, args.steps))}),
-              flush=True)
-        return
-
-    if args.copy_calibration:
-        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE give the
-        # scale from counter units to bytes; then steps with the given shapes
-        if args.tuning_json:
-            with open(args.tuning_json) as f:
-                hg.hgmm_set_tuning(**json.load(f))
-        a = torch.empty(args.copy_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        for _ in range(max(1, args.steps)):
-            step()
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": a.numel() * 4, "steps": args.steps}), flush=True)
-        return
-
-    tuning = None
-    if args.tuning_json:
-        with open(args.tuning_json) as f:
-            hg.hgmm_set_tuning(**json.load(f))
-    elif not args.no_tune:
-        # launch shapes for this workload, chosen before the timed region; the
-        # search starts from the shapes profiled for the LiDAR workload
-        start = os.path.join(ROOT, "profiles", "lidar_launch_shapes.json")
-        if args.workload == "lidar" and os.path.exists(start):
-            with open(start) as f:
-                hg.hgmm_set_tuning(**json.load(f))
-        tuning = hg.hgmm_autotune(src, [0, n1], [pr["levels"]], tgt, [0, n2], reg_eps=pr["reg_eps"],
-                                  min_mass=pr["min_mass"], lambda_c=pr["lambda_c"], reps=2, passes=2)
-
-    if args.save_tuning:
-        with open(args.save_tuning, "w") as f:
-            json.dump(hg.hgmm_get_tuning(), f)
-
-    for _ in range(args.warmup):
-        step()
-    # timed region: K steps with nothing but the library's own launches
-    torch.cuda.synchronize()
-    errs, iters = [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        r = step()
-        errs.append(rotation_angle_deg(r["R"], p.R_true))
-        iters.append(r["iters"])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    sec = t1 - t0
-    # the same K steps again with a HIP event pair around every kernel launch on
-    # the library's stream: per-kernel durations for the roofline (the events
-    # themselves slow the host side, so this region is not the one timed above)
-    hg.hgmm_profile_reset()
-    hg.hgmm_profile(True)
-    tp0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    tp1 = time.perf_counter()
-    hg.hgmm_profile(False)
-    prof = {k: hg.hgmm_profile_read(k) for k in hg.PROFILE_KINDS}
-
-    # mean number of levels a point visits at the final pose (for the descent FLOP count)
-    e = hg.hgmm_estep(tree, tgt, r["R"], r["t"], lambda_c=pr["lambda_c"])
-    off = np.array([hg.hgmm_level_offset(l) for l in range(pr["levels"] + 1)])
-    stop = e["stop_node"].cpu().numpy()
-    depth = mean_depth(stop, off)
-
-    roofline = roofline_of(prof, depth, traffic="lidar")
-    ds = prof["descend"]
-    estep_mpts = ds["units"] / (ds["ms"] * 1e-3) / 1e6 if ds["ms"] > 0 else 0.0
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        t_c = 0.0
-        reps = 0
-        while t_c < args.cpu_seconds and reps < 8:
-            c0 = time.perf_counter()
-            ot, _ = oracle.build_tree(p.src, pr["levels"], eps=pr["reg_eps"], min_mass=pr["min_mass"])
-            oracle.register(ot, p.tgt, lambda_c=pr["lambda_c"])
-            t_c += time.perf_counter() - c0
-            reps += 1
-        cpu = {"value": round(reps / t_c, 4), "unit": "pairs/s", "cores": 1, "kind": "oracle",
-               "sample": f"{reps} full pair(s) of the same workload (build {n1} + register {n2} points), "
-                         f"single-threaded FP64, {t_c:.1f} s"}
-
-    progress("main workload and CPU baseline done")
-    variants = None if args.no_batch else variants_section(args, hg, tree, tgt, p, pr, max(3, args.steps // 2))
-    progress("registration variants done")
-    batched = None if args.no_batch else batch_section(args, hg)
-    progress("batched section done")
-    warm_form = None if args.no_batch else warm_section(args, hg)
-    progress("warm-start section done")
-    depth_form = None if args.no_batch else depth_section(args, hg)
-    progress("depth-camera section done")
-    odometry = None if args.no_batch else odometry_section(args, hg)
 
     out = {
-        "metric": "cloud pairs registered/s (build + register)",
-        "value": round(args.steps / sec, 3),
+        "metric": METRIC,
+        "value": head["value"],
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(sec * 1e3 / args.steps, 3),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32 (E-step, moments) + fp64 (transform, eigen, solves)",
+        "dtype": "fp32 (E-step, moments) + fp64 (transform, eigen, solves) + bf16 (network)",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {desc}", "points_src": n1, "points_tgt": n2,
-                   "levels": pr["levels"], "lambda_c": pr["lambda_c"], "reg_eps": pr["reg_eps"],
-                   "min_mass": pr["min_mass"], "build_iters": 30, "max_iters": 30, "init": "identity",
-                   "launch_shapes": hg.hgmm_get_tuning(),
-                   "autotune_ms": None if tuning is None else {"start": round(tuning["start_ms"], 3),
-                                                                "best": round(tuning["best_ms"], 3)}},
-        "estep_mpts_s": round(estep_mpts, 1),
-        "rot_err_deg_median": round(float(np.median(errs)), 4),
-        "iters_mean": round(float(np.mean(iters)), 2),
-        "mean_levels_visited": round(depth, 3),
-        "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in prof.items()},
-        "profiled_region_ms_per_step": round((tp1 - tp0) * 1e3 / args.steps, 3),
-        "roofline": roofline,
+        "config": {"workload": f"uneven batch: {bt.B} unit-cube pairs, N log-uniform [2e3, 2e5] points per cloud "
+                               f"({int(bt.off[-1])} per side), rotation U(0,45 deg), levels ceil(log8(N/50)); "
+                               "batched with the learned warm start and the plain-likelihood fallback",
+                   "pairs": bt.B, "points_per_side": int(bt.off[-1]), "levels_histogram":
+                       {str(L): int(np.sum(np.asarray(bt.lv) == L)) for L in sorted(set(int(v) for v in bt.lv))},
+                   "lambda_c": bt.cfg.lambda_c, "reg_eps": bt.cfg.reg_eps, "build_iters": 30,
+                   "max_iters": bt.cfg.max_iters, "launch_shapes": batch_shapes,
+                   "launch_shapes_file": os.path.relpath(args.batch_shapes, ROOT)},
+        **{k: v for k, v in head.items() if k not in ("value", "ms_per_step")},
         "cpu_baseline": cpu,
-        "batched": batched,
-        "warm_start": warm_form,
-        "depth_camera": depth_form,
-        "variants": variants,
-        "odometry": odometry,
+        "sections": sections,
     }
     print(json.dumps(out), flush=True)
 
