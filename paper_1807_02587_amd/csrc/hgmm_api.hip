@@ -249,7 +249,8 @@ static BuildLayout build_layout(int64_t n_total, int64_t max_jobs, int64_t max_l
 }
 
 struct RegLayout {
-  size_t bins, partials, counters, state, nmov, tiles, out, fbins, dcount, ptiles, active, pose, keys, keys2, vals,
+  size_t bins, partials, counters, state, nmov, tiles, out, fbins, regf, dcount, ptiles, active, pose, keys, keys2,
+      vals,
       perm, sxyz, sort_temp, flatf, flats, total;
   size_t sort_temp_bytes;
   int64_t max_tiles;
@@ -263,6 +264,7 @@ static RegLayout reg_layout(int64_t n_total, int64_t nodes, int npairs) {
   L.partials = o; o = align_up(o + sizeof(double) * 28 * (size_t)npairs);
   L.counters = o; o = align_up(o + sizeof(unsigned) * (size_t)npairs);
   L.fbins = o; o = align_up(o + sizeof(FixBin) * (size_t)std::max<int64_t>(nodes, 1));  // fixed-point moments
+  L.regf = o; o = align_up(o + sizeof(NodeF) * (size_t)std::max<int64_t>(nodes, 1));   // descent scoring records
   L.dcount = o; o = align_up(o + sizeof(unsigned) * (size_t)npairs);
   // per-pair inputs uploaded together: tile ranges | point counts | start
   // poses (12 doubles: R row-major, t) | active flags
@@ -1044,6 +1046,7 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   double* d_out = (double*)(ws + Ly.out);
   double* d_pose0 = (double*)(ws + Ly.pose);
   FixBin* d_fbins = (FixBin*)(ws + Ly.fbins);
+  NodeF* d_regf = (NodeF*)(ws + Ly.regf);
   unsigned* d_dcount = (unsigned*)(ws + Ly.dcount);
   int2* d_ptiles = (int2*)(ws + Ly.ptiles);
 
@@ -1119,6 +1122,7 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   launch_fill_u32(d_bins, 0u, 2 * 6 * nodes_total, s);
   launch_fill_u32(d_fbins, 0u, (int64_t)(sizeof(FixBin) / 4) * nodes_total, s);
   launch_set_stop_flags(f->d_tab, f->d_nodes, nodes_total, rr.lambda_c, s);
+  launch_reg_table(f->d_tab, f->d_nodes, d_regf, nodes_total, rr.lambda_c, s);
   launch_init_pose(d_state, P, d_pose0, d_pose0 + 9, per_pair ? 12 : 0, active ? d_act : nullptr, s);
   HIP_LAUNCHED();
   const bool flat = rr.flat_level >= 0;
@@ -1141,7 +1145,7 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
       launch_flat_estep(xs, ys, zs, d_tiles, ntiles, rt, f->d_trees, d_flatf, d_flats, d_state, d_bins, so, go, pm,
                         rr.flat_level, q);
     else
-      launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, f->d_tab, f->d_nodes, d_state, d_fbins,
+      launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, d_regf, f->d_nodes, d_state, d_fbins,
                      fp64_atomics ? d_bins : nullptr, so, go, pm, g_tune.reg_lds_levels, rr.max_levels, wk, q);
   };
   auto mstep = [&](hipStream_t q) {

@@ -35,6 +35,27 @@ __global__ void set_stop_flags_kernel(NodeF* tab, const NodeD* __restrict__ node
   tab[g].flags = f;
 }
 
+// The descent's copy of the scoring records with this call's stop flags, in
+// which a dead node scores -inf with a zero rounding bound (c = -inf, W = 0,
+// errc = errg = 0), so that scoring 8 children needs no liveness test.
+__global__ void reg_table_kernel(const NodeF* __restrict__ tab, const NodeD* __restrict__ nodes, NodeF* rt, int64_t n,
+                                 double lambda_c) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  NodeF r = tab[g];
+  if (r.flags & F_LIVE) {
+    r.flags &= ~F_STOP;
+    if (nodes[g].kappa <= lambda_c) r.flags |= F_STOP;
+  } else {
+    for (int i = 0; i < 6; ++i) r.w[i] = 0.f;
+    r.c = -INFINITY;
+    r.errc = 0.f;
+    r.errg = 0.f;
+    r.flags = 0u;
+  }
+  rt[g] = r;
+}
+
 // Initial transform of every pair: rows of `stride` doubles (stride 0 = the
 // same transform for all pairs).
 __global__ void init_pose_kernel(PoseState* st, int npairs, const double* __restrict__ R0, const double* __restrict__ t0,
@@ -104,6 +125,52 @@ __device__ __forceinline__ int choose_child(NodePtr C, S64Ptr S, double p0, doub
   return k1;
 }
 
+// The most likely child among the 8 descent records at C (dead ones score
+// -inf, so the FP32 pass has no liveness test).  When no child scores above
+// -inf, or the FP32 top-2 gap is inside the rounding bound, the live
+// children are compared in FP64 (lowest index on an exact tie).  Returns the
+// child (-1 when none is live), its FP32 score s1 and bound e1 (infinite
+// when the FP64 comparison picked another child than the FP32 pass).
+template <typename RecPtr, typename S64Ptr>
+__device__ __forceinline__ int choose_child_reg(RecPtr C, S64Ptr S, double p0, double p1, double p2, float (&s)[8],
+                                                float (&q)[8], float (&m)[8], float& s1, float& e1) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s[k] = score32(C[k], p0, p1, p2, q[k], m[k]);
+  int k1 = -1;
+  s1 = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (s[k] > s1) { s1 = s[k]; k1 = k; }
+  int k2 = -1;
+  float s2 = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (k != k1 && s[k] > s2) { s2 = s[k]; k2 = k; }
+  e1 = 0.f;
+  float e2 = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float ek = score_err(C[k], q[k], m[k]);
+    e1 = (k == k1) ? ek : e1;
+    e2 = (k == k2) ? ek : e2;
+  }
+  if (k1 < 0 || (k2 >= 0 && s1 - s2 <= 2.f * (e1 + e2))) {
+    double best = -INFINITY;
+    int kb = -1;
+    for (int k = 0; k < 8; ++k) {
+      if (!(C[k].flags & F_LIVE)) continue;
+      const double v = score64(S[k], p0, p1, p2);
+      if (kb < 0 || v > best) { best = v; kb = k; }
+    }
+    if (kb != k1 && kb >= 0) {
+      k1 = kb;
+      s1 = s[kb];
+      e1 = INFINITY;
+    }
+  }
+  return k1;
+}
+
 constexpr int kLdsNodes = 72;    // levels 0 and 1 of one tree
 // gamma is recomputed from FP64 scores when its FP32 rounding bound exceeds
 // this (relative); the moments' tolerance against the oracle is 1e-5
@@ -115,14 +182,15 @@ constexpr float kGammaTol = 4e-6f;
 // the others keep their FP32 weights, so the recomputed gamma is within
 // 8e-7 relative of its FP64 value.
 template <typename S64Ptr>
-__device__ __forceinline__ float gamma_fp64(S64Ptr S, uint32_t lm, int k, const float (&s)[8], const float (&err)[8],
-                                            float sk, float ek, float gam32, double p0, double p1, double p2) {
+__device__ __forceinline__ float gamma_fp64(S64Ptr S, int k, const float (&s)[8], const float (&err)[8], float sk,
+                                            float ek, float gam32, double p0, double p1, double p2) {
   const double skd = score64(S[k], p0, p1, p2);
   float den = 1.0f;
   for (int j = 0; j < 8; ++j) {
-    if (!(lm >> j & 1u) || j == k) continue;
+    if (j == k) continue;
     const float tj = __builtin_amdgcn_exp2f(s[j] - sk);
-    const bool exact = 0.6931472f * tj * (err[j] + ek) * gam32 > 1e-7f;
+    if (tj == 0.f) continue;  // a dead sibling, or one of weight below 2^-126
+    const bool exact = !(0.6931472f * tj * (err[j] + ek) * gam32 <= 1e-7f);
     den += exact ? __builtin_amdgcn_exp2f((float)(score64(S[j], p0, p1, p2) - skd)) : tj;
   }
   return 1.0f / den;
@@ -159,14 +227,16 @@ __device__ __forceinline__ void fix_add_row(FixBin* B, const double* r, double s
 // through one contiguous range of tiles (of pairs), whose node records then
 // stay in that XCD's L2.
 // work (nullable, profiling): adds the points processed and the levels they
-// scored to work[0] and work[1].
+// scored to work[0] and work[1].  Held to 4 waves per SIMD (at most 128
+// VGPRs) for latency hiding.
+// rtab: the descent's copy of the scoring records (reg_table_kernel).
 // ATOMICS: the comparison mode, in which each wave's sums are added to FP64
 // node bins (bins, 6 values per node) with FP64 atomics instead.
 template <int NLEV, bool ATOMICS>
-__global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void descend_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
                                                       const float* __restrict__ zs, const Tile* __restrict__ tiles,
                                                       int ntiles, int per_xcd, const TreeDev* __restrict__ trees,
-                                                      const NodeF* __restrict__ tab, const NodeD* __restrict__ nodes,
+                                                      const NodeF* __restrict__ rtab, const NodeD* __restrict__ nodes,
                                                       const PoseState* __restrict__ st, FixBin* fbins,
                                                       double* bins, int32_t* stop_out, float* gamma_out,
                                                       const int* __restrict__ perm, int max_levels,
@@ -188,7 +258,7 @@ __global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ 
   const int nl = T.levels >= 2 ? 72 : 8;
   const int nst = L >= NLEV ? kStaged : (L >= 2 ? 72 : 8);
   for (int i = threadIdx.x; i < nst; i += blockDim.x) {
-    const float4* s = reinterpret_cast<const float4*>(&tab[nb + i]);
+    const float4* s = reinterpret_cast<const float4*>(&rtab[nb + i]);
     float4* d = reinterpret_cast<float4*>(&lds[i]);
     d[0] = s[0]; d[1] = s[1]; d[2] = s[2]; d[3] = s[3];
   }
@@ -224,40 +294,34 @@ __global__ __launch_bounds__(256) void descend_kernel(const float* __restrict__ 
       int parent = 0;
       int l = 0;
       float s[8], q[8], m[8];
-      uint32_t lm;
       for (; l < L; ++l) {
         const int64_t lbase = lvl_off(l) + 8 * (int64_t)parent;
         const bool in_lds = l < 2 || l < NLEV;
-        const NodeF* C = in_lds ? lds + lbase : tab + nb + lbase;
-        const int k = (l < 2) ? choose_child(C, lds64 + lbase, p0, p1, p2, s, q, m, lm)
-                              : choose_child(C, nodes + nb + lbase, p0, p1, p2, s, q, m, lm);
+        const NodeF* C = in_lds ? lds + lbase : rtab + nb + lbase;
+        float sk, ek;
+        const int k = (l < 2) ? choose_child_reg(C, lds64 + lbase, p0, p1, p2, s, q, m, sk, ek)
+                              : choose_child_reg(C, nodes + nb + lbase, p0, p1, p2, s, q, m, sk, ek);
         if (k < 0) break;  // no live node here: the point is left unassigned
         const uint32_t flags = C[k].flags;
         if ((flags & F_STOP) || !(flags & F_HASCH) || (l == L - 1)) {
           // weight of the point at the chosen node: its posterior among the
-          // live siblings, gamma = 1 / sum_j 2^(s_j - s_k), with the FP32
-          // rounding bound of that sum
+          // live siblings, gamma = 1 / sum_j 2^(s_j - s_k) (dead siblings
+          // add 2^-inf = 0), with the FP32 rounding bound of that sum
           float err[8];
 #pragma unroll
           for (int j = 0; j < 8; ++j) err[j] = score_err(C[j], q[j], m[j]);
-          float sk = s[0], ek = err[0];
-#pragma unroll
-          for (int j = 1; j < 8; ++j) {
-            sk = (j == k) ? s[j] : sk;
-            ek = (j == k) ? err[j] : ek;
-          }
-          float den = 0.f, bnd = 0.f;
+          float den = 1.f, bnd = 0.f;
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
-            if (!(lm >> j & 1u)) continue;
+            if (j == k) continue;
             const float tj = __builtin_amdgcn_exp2f(s[j] - sk);
             den += tj;
-            if (j != k) bnd = fmaf(tj, err[j] + ek, bnd);
+            bnd = fmaf(tj, err[j] + ek, bnd);
           }
           gam = 1.0f / den;
-          if (0.6931472f * bnd * gam > kGammaTol)
-            gam = (l < 2) ? gamma_fp64(lds64 + lbase, lm, k, s, err, sk, ek, gam, p0, p1, p2)
-                          : gamma_fp64(nodes + nb + lbase, lm, k, s, err, sk, ek, gam, p0, p1, p2);
+          if (!(0.6931472f * bnd * gam <= kGammaTol))
+            gam = (l < 2) ? gamma_fp64(lds64 + lbase, k, s, err, sk, ek, gam, p0, p1, p2)
+                          : gamma_fp64(nodes + nb + lbase, k, s, err, sk, ek, gam, p0, p1, p2);
           g = nb + lbase + k;
           break;
         }
@@ -859,15 +923,20 @@ void launch_import_nodes(NodeD* nodes, NodeF* tab, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(import_nodes_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nodes, tab, n);
 }
 
+void launch_reg_table(const NodeF* tab, const NodeD* nodes, NodeF* rt, int64_t n, double lambda_c, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(reg_table_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tab, nodes, rt, n, lambda_c);
+}
+
 void launch_descend(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
-                    const TreeDev* trees, const NodeF* tab, const NodeD* nodes, const PoseState* st, FixBin* fbins,
+                    const TreeDev* trees, const NodeF* rtab, const NodeD* nodes, const PoseState* st, FixBin* fbins,
                     double* atomic_bins, int32_t* stop_out, float* gamma_out, const int* perm, int lds_levels,
                     int max_levels, unsigned long long* work, hipStream_t s) {
   if (ntiles <= 0) return;
   const int per_xcd = (ntiles + 7) / 8;
   const dim3 grid((unsigned)(8 * per_xcd));
 #define HGMM_DESCEND(NL, AT)                                                                                          \
-  hipLaunchKernelGGL((descend_kernel<NL, AT>), grid, dim3(256), 0, s, xs, ys, zs, tiles, ntiles, per_xcd, trees, tab, \
+  hipLaunchKernelGGL((descend_kernel<NL, AT>), grid, dim3(256), 0, s, xs, ys, zs, tiles, ntiles, per_xcd, trees, rtab,\
                      nodes, st, fbins, atomic_bins, stop_out, gamma_out, perm, max_levels, work)
   if (atomic_bins) {
     if (lds_levels >= 3) HGMM_DESCEND(3, true);
