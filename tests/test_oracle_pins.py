@@ -791,7 +791,7 @@ def test_soft_register_exact_recovery_blob_tree(oracle_mod):
 # learned warm start: canonical frame, features, start pose (oracle.warm)
 # --------------------------------------------------------------------------
 
-def _hand_tree(oracle_mod, R=np.eye(3), t=np.zeros(3)):
+def _warm_hand_tree(oracle_mod, R=np.eye(3), t=np.zeros(3)):
     """A 2-level tree set by hand: root covariance R diag(4, 1, 0.25) R^T + eps,
     origin R (1, 2, 3) + t, one live level-1 node (index 5) with weight 0.1,
     mean R (origin offset (0.5, -0.25, 2)) + origin, covariance
@@ -818,7 +818,7 @@ def test_warm_features_of_a_hand_built_tree(oracle_mod):
     with s = sqrt(4 + 1 + 0.25); every dead node is zeros; the same tree
     rotated and moved gives the same features."""
     from oracle import warm
-    tr, eps = _hand_tree(oracle_mod)
+    tr, eps = _warm_hand_tree(oracle_mod)
     f = warm.features(tr, eps)
     s = np.sqrt(5.25)
     ref = np.zeros(640)
@@ -828,7 +828,7 @@ def test_warm_features_of_a_hand_built_tree(oracle_mod):
     np.testing.assert_allclose(fr[:9].reshape(3, 3), np.eye(3), atol=1e-12)
     np.testing.assert_allclose(fr[9:], [1.0, 2.0, 3.0, s], atol=1e-12)
     R = rotation_from_axis_angle([1.0, 1.0, 1.0], np.radians(10.0))
-    tr2, _ = _hand_tree(oracle_mod, R, np.array([0.3, -2.0, 5.0]))
+    tr2, _ = _warm_hand_tree(oracle_mod, R, np.array([0.3, -2.0, 5.0]))
     np.testing.assert_allclose(warm.features(tr2, eps), ref, atol=1e-12)
 
 
