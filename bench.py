@@ -166,7 +166,8 @@ def _valu(family, which):
         return {}
     f = v["families"][family]
     return {"valu_busy_pct": f["valu_busy_pct"], "valu_utilization_pct": f["valu_utilization_pct"],
-            "counted_flop_frac": f["counted_frac"]}
+            "counted_tflops": f["counted_tflops"],
+            "counted_flop_frac": round(f["counted_tflops"] / PEAK_FP32_TFLOPS, 4)}
 
 
 # single-level E-step, per point-component pair: FP64 offset 3, whitening of
@@ -422,7 +423,13 @@ def headline(args, hg):
     out["profiled_region_ms_per_step"] = round((t2 - t1) * 1e3 / args.steps, 3)
     out["roofline"] = roofline_of(prof, traffic="batch")
     progress("headline (batched + warm) done")
-    # the plain GPU form, one pair at a time, and the batched plain form
+    return out, prof, bt
+
+
+def plain_forms(args, hg, bt, out):
+    """The plain GPU form on the same batch, one pair at a time (build +
+    register from the identity per pair), and the batched plain form."""
+    B = bt.B
     bt.plain_one_at_a_time(range(min(8, B)))
     Rp, tp = _timed(lambda: bt.plain_one_at_a_time(range(B)))
     ep = _rot_err(Rp, bt.Rt)
@@ -450,7 +457,6 @@ def headline(args, hg):
     out["estep_speedup_vs_plain"] = (round(out["estep_mpts_s"] / plain["estep_mpts_s"], 2)
                                      if plain["estep_mpts_s"] else None)
     progress("plain forms done")
-    return out, prof, bt
 
 
 def cpu_baseline(args, bt):
@@ -520,6 +526,12 @@ def pair_section(args, hg, name, steps, shapes=None, oracle_reps=0, oracle_secon
         return hg.hgmm_register(tree, tgt, lambda_c=pr["lambda_c"], ws=ws_r, raise_singular=False)
 
     try:
+        if args.copy_calibration:
+            # a plain copy of known size beside the steps (counter scale)
+            a = torch.empty(args.copy_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
+            b = torch.empty_like(a)
+            b.copy_(a)
+            _sync()
         for _ in range(3):
             step()
         _sync()
@@ -674,7 +686,7 @@ def main():
                     help="run one section only (profiling runs)")
     ap.add_argument("--batch-shapes", default=BATCH_SHAPES, help="launch shapes of the batched forms")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="with --only headline: a device copy of --copy-mib MiB beside the steps (counter scale)")
+                    help="with --only: a device copy of --copy-mib MiB beside the steps (counter scale)")
     ap.add_argument("--copy-mib", type=int, default=1024)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -699,6 +711,8 @@ def main():
     if want("headline"):
         hg.hgmm_set_tuning(**batch_shapes)
         head, prof, bt = headline(args, hg)
+        if only is None:
+            plain_forms(args, hg, bt, head)
         if only is None and not args.no_cpu_baseline:
             cpu = cpu_baseline(args, bt)
             progress("CPU baseline done")

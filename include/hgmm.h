@@ -470,8 +470,8 @@ int hgmm_autotune(const float *d_src, const int64_t *src_offsets, const int32_t 
  * hgmm_profile_read returns, per kernel kind, the summed event time (ms), the
  * number of timed launches and the work units they processed (points, or
  * point-iterations for the block construction kernels, or nodes for the
- * normal equations).  Registration launches after convergence (which exit at
- * once) are not counted.  Kinds: 0 construction EM tile iteration,
+ * normal equations).  Every launch counts, also registration launches
+ * queued after every pair had converged (they exit at once).  Kinds: 0 construction EM tile iteration,
  * 1 construction EM in one block per parent, 2 partition, 3 stable split, 4 registration
  * descent, 5 normal equations + solve, 6 root statistics, 7 construction
  * M-step of the tiled parents (units: parents), 8 single-level E-step,
