@@ -130,7 +130,7 @@ struct PoseState {
 constexpr int kFixVals = 5;
 constexpr double kFixScaleM0 = 1048576.0;  // 2^20: resolution 2^-52, range 2^42 of gamma sums
 constexpr double kFixScaleD = 65536.0;     // 2^16 per extent: resolution 2^-48 extent, range 2^46 extent
-constexpr double kFixScaleQ = 0.00390625;  // 2^-8: resolution 2^-24, range 2^70 of squared distances
+constexpr double kFixScaleQ = 256.0;       // 2^8: resolution 2^-40, range 2^54 of squared distances
 struct FixBin {
   unsigned long long lo[kFixVals];  // sums of 32-bit fractions
   long long hi[kFixVals];           // sums of integer parts

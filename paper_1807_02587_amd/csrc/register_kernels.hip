@@ -130,12 +130,17 @@ __device__ __forceinline__ int choose_child(NodePtr C, S64Ptr S, double p0, doub
 // -inf, or the FP32 top-2 gap is inside the rounding bound, the live
 // children are compared in FP64 (lowest index on an exact tie).  Returns the
 // child (-1 when none is live), its FP32 score s1 and bound e1 (infinite
-// when the FP64 comparison picked another child than the FP32 pass).
+// when the FP64 comparison picked another child than the FP32 pass); err
+// receives every child's FP32 rounding bound.
 template <typename RecPtr, typename S64Ptr>
 __device__ __forceinline__ int choose_child_reg(RecPtr C, S64Ptr S, double p0, double p1, double p2, float (&s)[8],
-                                                float (&q)[8], float (&m)[8], float& s1, float& e1) {
+                                                float (&err)[8], float& s1, float& e1) {
 #pragma unroll
-  for (int k = 0; k < 8; ++k) s[k] = score32(C[k], p0, p1, p2, q[k], m[k]);
+  for (int k = 0; k < 8; ++k) {
+    float q, m;
+    s[k] = score32(C[k], p0, p1, p2, q, m);
+    err[k] = score_err(C[k], q, m);
+  }
   int k1 = -1;
   s1 = -INFINITY;
 #pragma unroll
@@ -150,9 +155,8 @@ __device__ __forceinline__ int choose_child_reg(RecPtr C, S64Ptr S, double p0, d
   float e2 = 0.f;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const float ek = score_err(C[k], q[k], m[k]);
-    e1 = (k == k1) ? ek : e1;
-    e2 = (k == k2) ? ek : e2;
+    e1 = (k == k1) ? err[k] : e1;
+    e2 = (k == k2) ? err[k] : e2;
   }
   if (k1 < 0 || (k2 >= 0 && s1 - s2 <= 2.f * (e1 + e2))) {
     double best = -INFINITY;
@@ -196,29 +200,60 @@ __device__ __forceinline__ float gamma_fp64(S64Ptr S, int k, const float (&s)[8]
   return 1.0f / den;
 }
 
-// Adds a row {M0, D (3), count, Q} of sums to a fixed-point bin (sD: the
-// tree's D scale, kFixScaleD / extent).
-__device__ __forceinline__ void fix_add_row(FixBin* B, const double* r, double sD) {
-  const double v[kFixVals] = {r[0] * kFixScaleM0, r[1] * sD, r[2] * sD, r[3] * sD, r[5] * kFixScaleQ};
+// Runs of equal keys inside the 16-lane rows of a wave.  A run starts at
+// the first lane of a row or where the key differs from the previous lane's.
+// Returns the first lane of this lane's run and sets `end` on the run's last
+// lane.  All 64 lanes must be active.
+__device__ __forceinline__ int row_run(int key, int lane, bool& end) {
+  // the previous lane's key in the row (row_shr:1); the row's first lane
+  // keeps key ^ 1, so it always starts a run
+  const int prev = __builtin_amdgcn_update_dpp(key ^ 1, key, 0x111, 0xF, 0xF, false);
+  const unsigned long long heads = __ballot(prev != key);
+  end = ((lane & 15) == 15) || (((heads >> 1) >> lane) & 1ull);
+  return 63 - __clzll((long long)(heads & ((2ull << lane) - 1ull)));
+}
+
+// One step of the segmented inclusive sum over the runs of row_run (shift SH
+// = 1, 2, 4, 8 in turn): a lane adds the value SH lanes before it when that
+// lane is in its run (`take` 1 or 0).  The data flow is fixed, so the run
+// sums do not depend on timing.
+template <int SH>
+__device__ __forceinline__ void run_step(float (&v)[kFixVals], float take) {
 #pragma unroll
-  for (int j = 0; j < kFixVals; ++j) {
-    unsigned long long lo;
-    long long hi;
-    fix_split(v[j], lo, hi);
-    fix_add(&B->lo[j], &B->hi[j], lo, hi);
-  }
-  atomicAdd(&B->cnt, (unsigned long long)r[4]);
+  for (int j = 0; j < kFixVals; ++j) v[j] = fmaf(dpp_f<0x110 + SH>(v[j]), take, v[j]);
+}
+
+// A run of equal stop nodes staged for its adds: node (local id), number of
+// points and the sums {M0, D (3), Q}.
+struct WaveRun {
+  int key;
+  unsigned n;
+  float v[kFixVals];
+  int pad;
+};
+
+// Orders one wave's LDS writes before its later LDS reads of other lanes'
+// values (a wave's LDS operations complete in order; this keeps the compiler
+// from moving them across).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // One E-step over the tiles of every pair (tiles[].job is the pair index).
-// Each point is transformed in FP64 and descends the tree (Algorithm 1).
-// The moments of equal stop nodes are summed across the wave (FP32).  For the
-// 72 nodes of levels 0-1 one lane adds them in FP64 to the wave's own LDS
-// bins, in the wave's fixed order; at the end of the block the four waves'
-// bins are added in wave order and go to the node bins in HBM.  Deeper stop
-// nodes go to the node bins directly.  The node bins are fixed point
-// (FixBin): integer sums that do not depend on the order in which waves and
-// blocks add, so the moments, and the registration, are bitwise reproducible.
+// Each point is transformed in FP64 and descends the tree (Algorithm 1); the
+// posterior weight at its stop node is formed once per wave after the
+// descent, from the stop level's scores that each lane keeps.
+// Moments: neighbouring lanes of a wave with the same stop node form runs,
+// summed in FP32 by a fixed-order segmented scan inside each 16-lane row and
+// carried across row boundaries; the last lane of each run adds the run's
+// sums and count in fixed point (FixBin):
+// for the 72 nodes of levels 0-1 into block-shared LDS bins, which the block
+// adds to the node bins in HBM at its end, and for deeper nodes into the node
+// bins directly.  Fixed-point sums are integers, whose totals do not depend
+// on the order of the adds, so the moments, and the registration, are
+// bitwise reproducible.
 // NLEV: number of leading tree levels whose FP32 scoring records are staged
 // in LDS (2: the 72 nodes of levels 0-1; 3: also the 512 of level 2, 37 KB).
 // The FP64 scoring prefix is staged for levels 0-1.
@@ -230,8 +265,8 @@ __device__ __forceinline__ void fix_add_row(FixBin* B, const double* r, double s
 // scored to work[0] and work[1].  Held to 4 waves per SIMD (at most 128
 // VGPRs) for latency hiding.
 // rtab: the descent's copy of the scoring records (reg_table_kernel).
-// ATOMICS: the comparison mode, in which each wave's sums are added to FP64
-// node bins (bins, 6 values per node) with FP64 atomics instead.
+// ATOMICS: the comparison mode, in which the run sums are added to FP64 node
+// bins (bins, 6 values per node, every level) with FP64 atomics instead.
 template <int NLEV, bool ATOMICS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void descend_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
                                                       const float* __restrict__ zs, const Tile* __restrict__ tiles,
@@ -253,7 +288,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
   constexpr int kStaged = NLEV >= 3 ? 584 : kLdsNodes;
   __shared__ NodeF lds[kStaged];
   __shared__ NodeS lds64[kLdsNodes];
-  __shared__ double wbin[4][kLdsNodes][6];
+  __shared__ FixBin lfix[kLdsNodes];
+  __shared__ WaveRun wrun[4][64];
   __shared__ unsigned long long wsum[2];
   const int nl = T.levels >= 2 ? 72 : 8;
   const int nst = L >= NLEV ? kStaged : (L >= 2 ? 72 : 8);
@@ -269,8 +305,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
     lds64[i].c = nd.c;
   }
   {
-    double* z = &wbin[0][0][0];
-    for (int i = threadIdx.x; i < 4 * kLdsNodes * 6; i += blockDim.x) z[i] = 0.0;
+    unsigned long long* z = &lfix[0].lo[0];
+    for (int i = threadIdx.x; i < kLdsNodes * (int)(sizeof(FixBin) / 8); i += blockDim.x) z[i] = 0ull;
     if (threadIdx.x < 2) wsum[threadIdx.x] = 0ull;
   }
   __syncthreads();
@@ -293,46 +329,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
       const double p2 = R6 * z0 + R7 * z1 + R8 * z2 + t2;
       int parent = 0;
       int l = 0;
-      float s[8], q[8], m[8];
+      // the stop level's child scores and bounds stay in these registers
+      // while other lanes of the wave descend further
+      float s[8], err[8], sk = 0.f, ek = 0.f;
+      int kst = -1;
+      int64_t lbst = 0;
       for (; l < L; ++l) {
         const int64_t lbase = lvl_off(l) + 8 * (int64_t)parent;
         const bool in_lds = l < 2 || l < NLEV;
         const NodeF* C = in_lds ? lds + lbase : rtab + nb + lbase;
-        float sk, ek;
-        const int k = (l < 2) ? choose_child_reg(C, lds64 + lbase, p0, p1, p2, s, q, m, sk, ek)
-                              : choose_child_reg(C, nodes + nb + lbase, p0, p1, p2, s, q, m, sk, ek);
+        const int k = (l < 2) ? choose_child_reg(C, lds64 + lbase, p0, p1, p2, s, err, sk, ek)
+                              : choose_child_reg(C, nodes + nb + lbase, p0, p1, p2, s, err, sk, ek);
         if (k < 0) break;  // no live node here: the point is left unassigned
         const uint32_t flags = C[k].flags;
         if ((flags & F_STOP) || !(flags & F_HASCH) || (l == L - 1)) {
-          // weight of the point at the chosen node: its posterior among the
-          // live siblings, gamma = 1 / sum_j 2^(s_j - s_k) (dead siblings
-          // add 2^-inf = 0), with the FP32 rounding bound of that sum
-          float err[8];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) err[j] = score_err(C[j], q[j], m[j]);
-          float den = 1.f, bnd = 0.f;
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            if (j == k) continue;
-            const float tj = __builtin_amdgcn_exp2f(s[j] - sk);
-            den += tj;
-            bnd = fmaf(tj, err[j] + ek, bnd);
-          }
-          gam = 1.0f / den;
-          if (!(0.6931472f * bnd * gam <= kGammaTol))
-            gam = (l < 2) ? gamma_fp64(lds64 + lbase, k, s, err, sk, ek, gam, p0, p1, p2)
-                          : gamma_fp64(nodes + nb + lbase, k, s, err, sk, ek, gam, p0, p1, p2);
-          g = nb + lbase + k;
+          kst = k;
+          lbst = lbase;
           break;
         }
         parent = 8 * parent + k;
       }
       my_points += 1u;
       my_levels += (unsigned)min(l + 1, L);
-      if (g >= 0) {
+      if (kst >= 0) {
+        // weight of the point at the chosen node: its posterior among the
+        // live siblings, gamma = 1 / sum_j 2^(s_j - s_k) (dead siblings add
+        // 2^-inf = 0), with the FP32 rounding bound of that sum
+        float den = 1.f, bnd = 0.f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const float tj = (j == kst) ? 0.f : __builtin_amdgcn_exp2f(s[j] - sk);
+          den += tj;
+          bnd = fmaf(tj, err[j] + ek, bnd);
+        }
+        gam = 1.0f / den;
+        if (!(0.6931472f * bnd * gam <= kGammaTol))
+          gam = (lbst < kLdsNodes) ? gamma_fp64(lds64 + lbst, kst, s, err, sk, ek, gam, p0, p1, p2)
+                                   : gamma_fp64(nodes + nb + lbst, kst, s, err, sk, ek, gam, p0, p1, p2);
+        g = nb + lbst + kst;
         // offset from the node mean (one FP32 rounding of an FP64 difference)
-        // and the squared Mahalanobis distance in FP64, after the descent so
-        // that lanes stopping at different levels compute them together
+        // and the squared Mahalanobis distance in FP64
         const int64_t lg = g - nb;
         const double* mu = (lg < nl) ? lds64[lg].mu : nodes[g].mu;
         const double* wi = (lg < nl) ? lds64[lg].winv : nodes[g].winv;
@@ -349,55 +385,82 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
       if (stop_out) stop_out[oi] = g >= 0 ? (int32_t)(g - nb) : -1;
       if (gamma_out) gamma_out[oi] = gam;
     }
-    // sum equal stop nodes across the wave, then one fixed-point add per node
-    bool pend = valid && g >= 0;
-    unsigned long long pending = __ballot(pend);
-    while (pending) {
-      const int leader = __ffsll((long long)pending) - 1;
-      const int64_t key = __shfl(g, leader, 64);
-      const bool mine = pend && (g == key);
-      const unsigned long long mm = __ballot(mine);
-      const float v[kFixVals] = {wave_sum(mine ? gam : 0.f), wave_sum(mine ? gam * d0 : 0.f),
-                                 wave_sum(mine ? gam * d1 : 0.f), wave_sum(mine ? gam * d2 : 0.f),
-                                 wave_sum(mine ? dm2 : 0.f)};
-      // lanes 0-4 add one value each and lane 5 the count: FP64 atomics into
-      // the node bins (comparison mode), FP64 adds into the wave's own LDS
-      // bins (levels 0-1), or fixed-point adds into the node bins
-      if (lane < 6) {
-        const int64_t local = key - nb;
-        const float vj = lane == 0 ? v[0] : lane == 1 ? v[1] : lane == 2 ? v[2] : lane == 3 ? v[3] : v[4];
-        const double xj = lane == 5 ? (double)__popcll(mm) : (double)vj;
-        const int col = lane < 4 ? lane : 9 - lane;  // bins order {M0, D, count, Q}
+    // run sums of {gamma, gamma d (3), d^2} over equal stop nodes in each row
+    // (an unassigned point has key -1 and zero sums)
+    const int key = g >= 0 ? (int)(g - nb) : -1;
+    float v[kFixVals] = {gam, gam * d0, gam * d1, gam * d2, dm2};
+    bool run_end;
+    const int rs = row_run(key, lane, run_end);
+    run_step<1>(v, lane - 1 >= rs ? 1.f : 0.f);
+    run_step<2>(v, lane - 2 >= rs ? 1.f : 0.f);
+    run_step<4>(v, lane - 4 >= rs ? 1.f : 0.f);
+    run_step<8>(v, lane - 8 >= rs ? 1.f : 0.f);
+    // a run that goes on across a row boundary: the boundary lane hands its
+    // sums to the lanes of the next row whose run starts at that row's first
+    // lane (rows in order, so a run over several rows collects all of them),
+    // and only the run's last lane adds
+    int rw = rs;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int bl = 16 * r + 15;
+      if (__builtin_amdgcn_readlane(key, bl) == __builtin_amdgcn_readlane(key, bl + 1)) {
+        const int sb = __builtin_amdgcn_readlane(rw, bl);
+        const bool cont = rw == bl + 1;
+#pragma unroll
+        for (int j = 0; j < kFixVals; ++j) {
+          const float vb = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v[j]), bl));
+          v[j] += cont ? vb : 0.f;
+        }
+        rw = cont ? sb : rw;
+        run_end = run_end && lane != bl;
+      }
+    }
+    // the runs' sums to the bins: the last lane of each run stages them in
+    // the wave's LDS rows, then six neighbouring lanes take one run (five
+    // sums and the count), so each atomic instruction adds to a few whole
+    // bins rather than to one word of many bins
+    const bool emit = run_end && key >= 0;
+    const unsigned long long ends = __ballot(emit);
+    if (ends != 0ull) {
+      wave_lds_sync();  // the previous points' reads of the rows are done
+      if (emit) {
+        WaveRun& w = wrun[wv][__popcll(ends & ((1ull << lane) - 1ull))];
+        w.key = key;
+        w.n = (unsigned)(lane - rw + 1);
+#pragma unroll
+        for (int j = 0; j < kFixVals; ++j) w.v[j] = v[j];
+      }
+      wave_lds_sync();
+      const int nruns = __popcll(ends);
+      for (int r0 = 0; r0 < nruns; r0 += 10) {
+        const int r = r0 + lane / 6, col = lane - 6 * (lane / 6);
+        if (lane >= 60 || r >= nruns) continue;
+        const WaveRun& w = wrun[wv][r];
+        const int k = w.key;
         if (ATOMICS) {
-          unsafeAtomicAdd(bins + key * 6 + col, xj);
-        } else if (local < nl) {
-          // one lane per value, in the wave's order
-          unsafeAtomicAdd(&wbin[wv][local][col], xj);
+          // bins order {M0, D, count, Q}
+          unsafeAtomicAdd(bins + (nb + k) * 6 + (col < 4 ? col : 9 - col), col == 5 ? (double)w.n : (double)w.v[col]);
+        } else if (col == 5) {
+          if (k < nl) atomicAdd(&lfix[k].cnt, (unsigned long long)w.n);
+          else atomicAdd(&fbins[nb + k].cnt, (unsigned long long)w.n);
         } else {
-          FixBin& F = fbins[key];
-          if (lane < 5) {
-            const double sc = lane == 0 ? kFixScaleM0 : lane < 4 ? sD : kFixScaleQ;
-            unsigned long long lo;
-            long long hi;
-            fix_split(xj * sc, lo, hi);
-            fix_add(&F.lo[lane], &F.hi[lane], lo, hi);
-          } else {
-            atomicAdd(&F.cnt, (unsigned long long)__popcll(mm));
-          }
+          unsigned long long lo;
+          long long hi;
+          fix_split((double)w.v[col] * (col == 0 ? kFixScaleM0 : col < 4 ? sD : kFixScaleQ), lo, hi);
+          if (k < nl) fix_add(&lfix[k].lo[col], &lfix[k].hi[col], lo, hi);
+          else fix_add(&fbins[nb + k].lo[col], &fbins[nb + k].hi[col], lo, hi);
         }
       }
-      pend = pend && !mine;
-      pending &= ~mm;
     }
   }
   __syncthreads();
-  // the level-0/1 bins into the node bins in HBM, the four waves' sums added
-  // in wave order
+  // the block's level-0/1 bins into the node bins in HBM
   for (int e = threadIdx.x; !ATOMICS && e < nl; e += blockDim.x) {
-    double r[6];
+    if (lfix[e].cnt == 0ull) continue;
+    FixBin& G = fbins[nb + e];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) r[j] = ((wbin[0][e][j] + wbin[1][e][j]) + wbin[2][e][j]) + wbin[3][e][j];
-    if (r[4] > 0.0) fix_add_row(&fbins[nb + e], r, sD);
+    for (int j = 0; j < kFixVals; ++j) fix_add(&G.lo[j], &G.hi[j], lfix[e].lo[j], lfix[e].hi[j]);
+    atomicAdd(&G.cnt, lfix[e].cnt);
   }
   if (work) {
     atomicAdd(&wsum[0], (unsigned long long)my_points);

@@ -82,27 +82,52 @@ def test_build_batch_vs_oracle(hg, batch, iters):
 
 
 def test_register_batch_vs_oracle(hg, batch):
+    """Every step of every pair's GPU trajectory against the oracle's step from
+    the same pose, and whole trajectories of the pairs that converge.
+
+    The update of Algorithm 1 is discontinuous where a point's most likely
+    child changes, so while a pair drifts away from the truth (an unstable
+    phase in which pose differences grow) rounding differences of 1e-6 rad
+    can move one point across a score gap of 1e-4 and the GPU and oracle
+    trajectories part, each still the method's own.  Step by step, from the
+    GPU's own poses, the two must agree on every iteration; end to end they
+    must agree on the pairs that converge."""
     pairs, src, tgt, soff, toff, levels = batch
     forest = hg.hgmm_build_batch(_cuda(src), soff, levels)
     R0, t0 = _starts(pairs)
-    r = hg.hgmm_register_batch(forest, _cuda(tgt), toff, R0=R0, t0=t0, max_iters=MAX_ITERS)
+    tg = _cuda(tgt)
+    # the GPU trajectory: registration is bitwise reproducible, so the call
+    # with max_iters = k gives the pose after k iterations
+    traj = [(R0, t0, np.zeros(len(pairs), np.int32))]
+    for k in range(1, MAX_ITERS + 1):
+        r = hg.hgmm_register_batch(forest, tg, toff, R0=R0, t0=t0, max_iters=k)
+        traj.append((r["R"], r["t"], r["iters"]))
     compared = 0
     for b, p in enumerate(pairs):
         host = forest.export(b)
-        o = oracle.register(to_oracle(oracle, host), p.tgt, R0=R0[b], t0=t0[b], max_iters=MAX_ITERS)
+        ot = to_oracle(oracle, host)
+        worst = 0.0
+        for k in range(r["iters"][b]):
+            Rk, tk = traj[k][0][b], traj[k][1][b]
+            o1 = oracle.register(ot, p.tgt, R0=Rk, t0=tk, max_iters=1)
+            da = math.radians(rotation_angle_deg(traj[k + 1][0][b], o1["R"]))
+            dt = np.linalg.norm(traj[k + 1][1][b] - o1["t"]) / host["extent"]
+            worst = max(worst, da, dt)
+            assert da < POSE_TOL and dt < POSE_TOL, (b, k, da, dt)
+        o = oracle.register(ot, p.tgt, R0=R0[b], t0=t0[b], max_iters=MAX_ITERS)
         dang = math.radians(rotation_angle_deg(r["R"][b], o["R"]))
         dt = np.linalg.norm(r["t"][b] - o["t"]) / host["extent"]
         log(f"[batch register] pair {b}: iters gpu {r['iters'][b]} oracle {o['iters']} status {r['status'][b]} "
-            f"{o['status']}  pose diff {dang:.2e} rad {dt:.2e} ext  err vs truth "
-            f"{rotation_angle_deg(r['R'][b], p.R_true):.4f} deg")
-        # the same trajectory, whether or not it converges (small clouds at
-        # lambda_c = 0.01 can drift away from the truth under the method itself)
+            f"{o['status']}  worst step difference {worst:.2e}; end to end {dang:.2e} rad {dt:.2e} ext; err vs "
+            f"truth {rotation_angle_deg(r['R'][b], p.R_true):.4f} deg")
         assert r["status"][b] == o["status"] == 0
-        assert dang < POSE_TOL and dt < POSE_TOL
-        assert abs(int(r["iters"][b]) - o["iters"]) <= 2
-        assert abs(r["loglik"][b] - o["loglik"]) <= 1e-4 * max(1.0, abs(o["loglik"]))
-        compared += o["iters"] < MAX_ITERS
-    log(f"[batch register] {compared} of {len(pairs)} pairs converged within {MAX_ITERS} iterations")
+        if o["iters"] < MAX_ITERS:
+            assert dang < POSE_TOL and dt < POSE_TOL
+            assert abs(int(r["iters"][b]) - o["iters"]) <= 2
+            assert abs(r["loglik"][b] - o["loglik"]) <= 1e-4 * max(1.0, abs(o["loglik"]))
+            compared += 1
+    log(f"[batch register] {compared} of {len(pairs)} pairs converged within {MAX_ITERS} iterations "
+        f"(compared end to end)")
 
 
 def test_register_batch_active_mask_and_estep(hg, batch):
