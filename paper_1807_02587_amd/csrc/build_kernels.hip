@@ -510,56 +510,59 @@ __device__ __forceinline__ uint32_t live_mask(const NodeF* ch) {
   return m;
 }
 
-// One EM iteration of the tiled (large) jobs, with the previous iteration's
-// M-step folded in.  Every block of a job folds the job's tile partials of
-// iteration it-1 in the same fixed order and runs the same FP64 M-step, so
-// all its blocks hold bit-identical children; the job's first tile publishes
-// them for the next launch (ping-pong child records, one set of 8 per tiled
-// job, slot = Tile::pad).  The first iteration starts from the initial
-// children in the scoring table.  Tile partials of the 80 moment sums are
-// FP64, value-major (part_next[v * pstride + tile]), ping-pong as well.
+static_assert(sizeof(EmFrame) <= kFrameBytes, "an E-step frame fits its record");
+
+// The live children of a frame (a dead child has the constant -inf).
+__device__ __forceinline__ uint32_t frame_live(const EmFrame& f) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) m |= (f.p[k][9] > -INFINITY) ? (1u << k) : 0u;
+  return m;
+}
+
+// One EM iteration of the tiled (large) jobs: the E-step of the tile's points
+// with the children of the job's frame, and the tile's partials of the 80
+// moment sums (FP64, value-major: part[v * pstride + tile]).  The frame is
+// the job's record in `frames` (slot = Tile::pad, the job's place among the
+// tiled jobs), written by em_fold_kernel after the previous iteration; the
+// first iteration (first = 1) forms it from the initial children in the
+// scoring table instead, and the job's first tile publishes those children
+// (ch, 8 per slot) for the fold.
 template <int NT, int KP>
 __global__ __launch_bounds__(NT) void em_tile_kernel(
     const float* __restrict__ xs, const float* __restrict__ ys, const float* __restrict__ zs,
     const Tile* __restrict__ tiles, const int* __restrict__ tile_ids, const Job* __restrict__ jobs,
-    const NodeF* __restrict__ tab, const NodeF* __restrict__ ch_prev, NodeF* ch_next,
-    const double* __restrict__ part_prev, double* part_next, size_t pstride, double eps, double min_mass,
+    const NodeF* __restrict__ tab, NodeF* ch, const char* __restrict__ frames, double* part, size_t pstride,
     int first, const int* dn, int n) {
-  constexpr int NR = NT / 16, NW = NT / 64;
+  constexpr int NR = NT / 16;
   const int nw = work_count(dn, n);
   for (int w = blockIdx.x; w < nw; w += gridDim.x) {
   const int tix = tile_ids[w];
   const Tile tl = tiles[tix];
   const Job jb = jobs[tl.job];
   const int slot = tl.pad;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  __shared__ NodeF ch[8];
+  const int tid = threadIdx.x;
+  __shared__ NodeF chs[8];
   __shared__ EmFrame fr;
   __shared__ float rows[NR][80];
-  __shared__ double tot[80];
-  // this block's points are requested first; their latency overlaps the fold
+  // this block's points are requested first; their latency overlaps the frame
   PointCache<KP> pc;
   load_points<NT>(xs, ys, zs, tl.start, tl.end, tid, pc);
-  if (tid < 8) copy_nodef(ch[tid], first ? tab[jb.child_base + tid] : ch_prev[(size_t)slot * 8 + tid]);
-  if (!first) {
-    // wave w folds value groups w, w + NW, ... of 5 values each
-    for (int v0 = 5 * wv; v0 < 80; v0 += 5 * NW) {
-      double t[5];
-      wave_fold<5, 4>(part_prev + (size_t)v0 * pstride + jb.tile_first, pstride, jb.ntiles, lane, t);
-      if (lane == 0)
-        for (int j = 0; j < 5; ++j) tot[v0 + j] = t[j];
-    }
+  if (first) {
+    if (tid < 8) copy_nodef(chs[tid], tab[jb.child_base + tid]);
     __syncthreads();
-    if (tid < 64) mstep_children<false, true>(tot, ch, nullptr, nullptr, 0, eps, min_mass, lane, &fr);
+    if (tix == jb.tile_first && tid < 8) copy_nodef(ch[(size_t)slot * 8 + tid], chs[tid]);
+    const uint32_t live0 = live_mask(chs);
+    if (live0) em_frame(chs, live0, fr, tid);
+    else if (tid < 8) fr.p[tid][9] = -INFINITY;
+  } else {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(frames + (size_t)slot * kFrameBytes);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&fr);
+    for (int i = tid; i < (int)(sizeof(EmFrame) / 4); i += NT) dst[i] = src[i];
   }
   __syncthreads();
-  if (tix == jb.tile_first && tid < 8) copy_nodef(ch_next[(size_t)slot * 8 + tid], ch[tid]);
-  const uint32_t live = live_mask(ch);
+  const uint32_t live = frame_live(fr);
   float a[8][10];
-  if (first) {  // uniform: the frame of the initial children
-    if (live) em_frame(ch, live, fr, tid);
-    __syncthreads();
-  }
   if (live) {
     em_range<NT, KP, false>(xs, ys, zs, tl.start, tl.end, tid, pc, fr, a);
   } else {
@@ -571,18 +574,66 @@ __global__ __launch_bounds__(NT) void em_tile_kernel(
   for (int v = tid; v < 80; v += NT) {
     double t = 0.0;
     for (int q = 0; q < NR; ++q) t += (double)rows[q][v];
-    part_next[(size_t)v * pstride + tix] = t;
+    part[(size_t)v * pstride + tix] = t;
   }
   __syncthreads();  // the block's LDS is reused by its next tile
   }
 }
+
+// The M-step of every tiled job between two iterations: one block of 4 waves
+// per job (block b = the job's slot among the tiled jobs; small blocks find
+// room beside the one-block-per-parent kernels that run at the same time);
+// wave w folds the tile partials of values 20w .. 20w+19 in a fixed order,
+// wave 0 runs the FP64 M-step of the children (ch, 8 per slot, updated in
+// place) and the block writes the next iteration's E-step frame (frames,
+// kFrameBytes per slot; every constant -inf when no child lives any more).
+constexpr int kFoldThreads = 256;
+__global__ __launch_bounds__(kFoldThreads) void em_fold_kernel(const int* __restrict__ job_ids,
+                                                               const Job* __restrict__ jobs,
+                                                               const double* __restrict__ partials, size_t pstride,
+                                                               double eps, double min_mass, NodeF* ch, char* frames,
+                                                               const int* dn, int n, const int* doff) {
+  const int nw = work_count(dn, n), base = doff ? *doff : 0;
+  for (int w = blockIdx.x; w < nw; w += gridDim.x) {
+  const Job jb = jobs[job_ids[base + w]];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  __shared__ NodeF chs[8];
+  __shared__ double tot[80];
+  __shared__ EmFrame fr;
+  if (tid < 8) copy_nodef(chs[tid], ch[(size_t)w * 8 + tid]);
+  for (int v0 = 20 * wv; v0 < 20 * wv + 20; v0 += 5) {
+    double t[5];
+    wave_fold<5, 4>(partials + (size_t)v0 * pstride + jb.tile_first, pstride, jb.ntiles, lane, t);
+    if (lane == 0)
+      for (int j = 0; j < 5; ++j) tot[v0 + j] = t[j];
+  }
+  __syncthreads();
+  if (tid < 64) mstep_children<false, true>(tot, chs, nullptr, nullptr, 0, eps, min_mass, lane, &fr);
+  __syncthreads();
+  if (tid < 8) {
+    if (live_mask(chs) == 0u) {
+      for (int i = 0; i < 9; ++i) fr.p[tid][i] = 0.f;
+      fr.p[tid][9] = -INFINITY;
+    }
+    copy_nodef(ch[(size_t)w * 8 + tid], chs[tid]);
+  }
+  __syncthreads();
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&fr);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(frames + (size_t)w * kFrameBytes);
+    for (int i = tid; i < (int)(sizeof(EmFrame) / 4); i += kFoldThreads) dst[i] = src[i];
+  }
+  __syncthreads();  // the block's LDS is reused by its next job
+  }
+}
+
+constexpr int kMstepThreads = 1024;
 
 // Final M-step of the tiled jobs after the last iteration: one block of 16
 // waves per job (block b = the job's slot among the tiled jobs); wave w folds
 // the tile partials of values 5w .. 5w+4 in a fixed order, then wave 0 runs
 // the M-step from the children of that iteration (chsrc) and writes the node
 // records.
-constexpr int kMstepThreads = 1024;
 __global__ __launch_bounds__(kMstepThreads) void em_mstep_kernel(const int* __restrict__ job_ids,
                                                                  const Job* __restrict__ jobs, NodeF* tab,
                                                                  NodeD* nodes, const double* __restrict__ partials,
@@ -1115,18 +1166,24 @@ void launch_init_children(const Job* jobs, int njobs, const TreeDev* trees, Node
 }
 
 void launch_em_tile(int nt, const float* xs, const float* ys, const float* zs, const Tile* tiles, const int* tile_ids,
-                    int n, const Job* jobs, const NodeF* tab, const NodeF* ch_prev, NodeF* ch_next,
-                    const double* part_prev, double* part_next, size_t pstride, double eps, double min_mass, int first,
-                    hipStream_t s, const int* dn) {
+                    int n, const Job* jobs, const NodeF* tab, NodeF* ch, const void* frames, double* part,
+                    size_t pstride, int first, hipStream_t s, const int* dn) {
+  const char* fr = static_cast<const char*>(frames);
   if (nt == 1024)
     hipLaunchKernelGGL((em_tile_kernel<1024, 2>), dim3(n), dim3(1024), 0, s, xs, ys, zs, tiles, tile_ids, jobs, tab,
-                       ch_prev, ch_next, part_prev, part_next, pstride, eps, min_mass, first, dn, n);
+                       ch, fr, part, pstride, first, dn, n);
   else if (nt == 512)
     hipLaunchKernelGGL((em_tile_kernel<512, 4>), dim3(n), dim3(512), 0, s, xs, ys, zs, tiles, tile_ids, jobs, tab,
-                       ch_prev, ch_next, part_prev, part_next, pstride, eps, min_mass, first, dn, n);
+                       ch, fr, part, pstride, first, dn, n);
   else
     hipLaunchKernelGGL((em_tile_kernel<256, 4>), dim3(n), dim3(256), 0, s, xs, ys, zs, tiles, tile_ids, jobs, tab,
-                       ch_prev, ch_next, part_prev, part_next, pstride, eps, min_mass, first, dn, n);
+                       ch, fr, part, pstride, first, dn, n);
+}
+
+void launch_em_fold(const int* job_ids, int n, const Job* jobs, const double* partials, size_t pstride, double eps,
+                    double min_mass, NodeF* ch, void* frames, hipStream_t s, const int* dn, const int* doff) {
+  hipLaunchKernelGGL(em_fold_kernel, dim3(n), dim3(kFoldThreads), 0, s, job_ids, jobs, partials, pstride, eps,
+                     min_mass, ch, static_cast<char*>(frames), dn, n, doff);
 }
 
 void launch_em_mstep(const int* job_ids, int n, const Job* jobs, NodeF* tab, NodeD* nodes, const double* partials,

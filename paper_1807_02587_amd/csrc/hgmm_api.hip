@@ -213,7 +213,8 @@ static int setup_forest(hgmm_forest_s* f) {
 static size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
 struct BuildLayout {
-  size_t pts[2], perm[2], child, tiles, tile_ids, job_ids, jobs, partials, partials2, chbuf, tile_counts, tile_base,
+  size_t pts[2], perm[2], child, tiles, tile_ids, job_ids, jobs, partials, partials2, chbuf, frames, tile_counts,
+      tile_base,
       counters, lvl_info, level_trees, plans, total;
   int64_t max_tiles, max_jobs, max_lvl;
 };
@@ -235,7 +236,8 @@ static BuildLayout build_layout(int64_t n_total, int64_t max_jobs, int64_t max_l
   L.jobs = o; o = align_up(o + sizeof(Job) * (size_t)L.max_jobs);
   L.partials = o; o = align_up(o + sizeof(double) * 80 * (size_t)L.max_tiles);
   L.partials2 = o; o = align_up(o + sizeof(double) * 80 * (size_t)L.max_tiles);
-  L.chbuf = o; o = align_up(o + sizeof(NodeF) * 8 * 2 * (size_t)L.max_jobs);
+  L.chbuf = o; o = align_up(o + sizeof(NodeF) * 8 * (size_t)L.max_jobs);
+  L.frames = o; o = align_up(o + kFrameBytes * (size_t)L.max_jobs);
   L.tile_counts = o; o = align_up(o + sizeof(int) * 9 * (size_t)L.max_tiles);
   L.tile_base = o; o = align_up(o + sizeof(int) * 9 * (size_t)L.max_tiles);
   L.counters = o; o = align_up(o + sizeof(unsigned) * (size_t)L.max_jobs);
@@ -541,7 +543,10 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
   Job* d_jobs = nullptr;
   double* d_partials = (double*)(ws + Ly.partials);
   double* d_part[2] = {d_partials, (double*)(ws + Ly.partials2)};
-  NodeF* d_ch[2] = {(NodeF*)(ws + Ly.chbuf), (NodeF*)(ws + Ly.chbuf) + 8 * (size_t)Ly.max_jobs};
+  // children (8 per tiled job) and the next E-step's frame (kFrameBytes per
+  // tiled job) of the tiled jobs between iterations
+  NodeF* d_ch = (NodeF*)(ws + Ly.chbuf);
+  void* d_frames = ws + Ly.frames;
   int* d_tile_counts = (int*)(ws + Ly.tile_counts);
   int* d_tile_base = (int*)(ws + Ly.tile_base);
   unsigned* d_counters = (unsigned*)(ws + Ly.counters);
@@ -736,16 +741,24 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
       }
     }
     if (nbig && p.build_iters > 0) {
+      // iteration it: the E-step of every tile, then (before the next one)
+      // the fold and M-step of every tiled job
       for (int it = 0; it < p.build_iters; ++it) {
-        ProfScope ps(PK_EM_TILE, (double)cls_points[3], s);
-        launch_em_tile(g_tune.tile_threads, cx, cy, cz, d_tiles, d_tile_ids, nbig, d_jobs, f->d_tab, d_ch[(it + 1) & 1],
-                       d_ch[it & 1],
-                       d_part[(it + 1) & 1], d_part[it & 1], (size_t)Ly.max_tiles, p.reg_eps, p.min_mass, it == 0, s);
+        {
+          ProfScope ps(PK_EM_TILE, (double)cls_points[3], s);
+          launch_em_tile(g_tune.tile_threads, cx, cy, cz, d_tiles, d_tile_ids, nbig, d_jobs, f->d_tab, d_ch, d_frames,
+                         d_part[it & 1], (size_t)Ly.max_tiles, it == 0, s);
+        }
+        if (it + 1 < p.build_iters) {
+          ProfScope ps(PK_EM_MSTEP, (double)nbigjobs, s);
+          launch_em_fold(d_job_ids + cls_off[3], nbigjobs, d_jobs, d_part[it & 1], (size_t)Ly.max_tiles, p.reg_eps,
+                         p.min_mass, d_ch, d_frames, s);
+        }
       }
       const int last = (p.build_iters - 1) & 1;
       ProfScope ps(PK_EM_MSTEP, (double)nbigjobs, s);
       launch_em_mstep(d_job_ids + cls_off[3], nbigjobs, d_jobs, f->d_tab, f->d_nodes, d_part[last],
-                      (size_t)Ly.max_tiles, p.reg_eps, p.min_mass, d_ch[last], s);
+                      (size_t)Ly.max_tiles, p.reg_eps, p.min_mass, d_ch, s);
     }
     for (int c = 0; c < 3; ++c)
       if (joined[c]) HIP_TRY(hipStreamWaitEvent(s, f->ev_join[c], 0));
@@ -863,7 +876,10 @@ static int run_build_graph(hgmm_forest_s* f, BuildInput in, const hgmm_build_par
   Job* d_jobs = (Job*)(ws + Ly.jobs);
   double* d_partials = (double*)(ws + Ly.partials);
   double* d_part[2] = {d_partials, (double*)(ws + Ly.partials2)};
-  NodeF* d_ch[2] = {(NodeF*)(ws + Ly.chbuf), (NodeF*)(ws + Ly.chbuf) + 8 * (size_t)Ly.max_jobs};
+  // children (8 per tiled job) and the next E-step's frame (kFrameBytes per
+  // tiled job) of the tiled jobs between iterations
+  NodeF* d_ch = (NodeF*)(ws + Ly.chbuf);
+  void* d_frames = ws + Ly.frames;
   int* d_tile_counts = (int*)(ws + Ly.tile_counts);
   int* d_tile_base = (int*)(ws + Ly.tile_base);
   int2* d_lvl = (int2*)(ws + Ly.lvl_info);
@@ -926,13 +942,16 @@ static int run_build_graph(hgmm_forest_s* f, BuildInput in, const hgmm_build_par
           ok = ok && hipEventRecord(f->ev_join[c], f->side[c]) == hipSuccess;
         }
         if (h[2] > 0) {  // tiled parents in the hinted plan
-          for (int it = 0; it < p.build_iters; ++it)
-            launch_em_tile(g_tune.tile_threads, cx, cy, cz, d_tiles, d_tile_ids, G_tile, d_jobs, f->d_tab,
-                           d_ch[(it + 1) & 1], d_ch[it & 1], d_part[(it + 1) & 1], d_part[it & 1],
-                           (size_t)Ly.max_tiles, p.reg_eps, p.min_mass, it == 0, gs, pl + PL_NBIG);
+          for (int it = 0; it < p.build_iters; ++it) {
+            launch_em_tile(g_tune.tile_threads, cx, cy, cz, d_tiles, d_tile_ids, G_tile, d_jobs, f->d_tab, d_ch,
+                           d_frames, d_part[it & 1], (size_t)Ly.max_tiles, it == 0, gs, pl + PL_NBIG);
+            if (it + 1 < p.build_iters)
+              launch_em_fold(d_job_ids, G_mstep, d_jobs, d_part[it & 1], (size_t)Ly.max_tiles, p.reg_eps, p.min_mass,
+                             d_ch, d_frames, gs, pl + PL_CLS_N + 3, pl + PL_CLS_OFF + 3);
+          }
           const int last = (p.build_iters - 1) & 1;
           launch_em_mstep(d_job_ids, G_mstep, d_jobs, f->d_tab, f->d_nodes, d_part[last], (size_t)Ly.max_tiles,
-                          p.reg_eps, p.min_mass, d_ch[last], gs, pl + PL_CLS_N + 3, pl + PL_CLS_OFF + 3);
+                          p.reg_eps, p.min_mass, d_ch, gs, pl + PL_CLS_N + 3, pl + PL_CLS_OFF + 3);
         }
         for (int c = 0; c < 3 && ok; ++c)
           if (h[3 + c] > 0) ok = ok && hipStreamWaitEvent(gs, f->ev_join[c], 0) == hipSuccess;

@@ -20,14 +20,19 @@ void launch_root(const float* xs, const float* ys, const float* zs, const Tile* 
                  const int* dntiles = nullptr, const int* dnjobs = nullptr);
 void launch_init_children(const Job* jobs, int njobs, const TreeDev* trees, NodeD* nodes, NodeF* tab, double eps,
                           hipStream_t s, const int* dn = nullptr);
-// one EM iteration of the tiled jobs (iteration 0: first = 1), folding in the
-// previous iteration's M-step; children and partials ping-pong between the
-// *_prev and *_next buffers; then, after the last iteration, the final M-step
-// from that iteration's children (chsrc, one set of 8 per tiled job)
+// one EM iteration of the tiled jobs (iteration 0: first = 1) with the frames
+// written by launch_em_fold (kFrameBytes per tiled job); between two
+// iterations, the fold of the partials and the M-step of every tiled job
+// (children ch updated in place, next frames written); after the last
+// iteration, the final M-step from that iteration's children (chsrc, one set
+// of 8 per tiled job) writes the node records
+constexpr size_t kFrameBytes = 512;
 void launch_em_tile(int nt, const float* xs, const float* ys, const float* zs, const Tile* tiles, const int* tile_ids,
-                    int n, const Job* jobs, const NodeF* tab, const NodeF* ch_prev, NodeF* ch_next,
-                    const double* part_prev, double* part_next, size_t pstride, double eps, double min_mass, int first,
-                    hipStream_t s, const int* dn = nullptr);
+                    int n, const Job* jobs, const NodeF* tab, NodeF* ch, const void* frames, double* part,
+                    size_t pstride, int first, hipStream_t s, const int* dn = nullptr);
+void launch_em_fold(const int* job_ids, int n, const Job* jobs, const double* partials, size_t pstride, double eps,
+                    double min_mass, NodeF* ch, void* frames, hipStream_t s, const int* dn = nullptr,
+                    const int* doff = nullptr);
 void launch_em_mstep(const int* job_ids, int n, const Job* jobs, NodeF* tab, NodeD* nodes, const double* partials,
                      size_t pstride, double eps, double min_mass, const NodeF* chsrc, hipStream_t s,
                      const int* dn = nullptr, const int* doff = nullptr);
