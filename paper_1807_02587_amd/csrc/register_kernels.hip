@@ -223,13 +223,35 @@ __device__ __forceinline__ void run_step(float (&v)[kFixVals], float take) {
   for (int j = 0; j < kFixVals; ++j) v[j] = fmaf(dpp_f<0x110 + SH>(v[j]), take, v[j]);
 }
 
-// A run of equal stop nodes staged for its adds: node (local id), number of
-// points and the sums {M0, D (3), Q}.
+// Block-shared fixed-point bins in LDS: bin k of the first kLdsNodes is node
+// k of levels 0-1; the others are keyed by node (open addressing with linear
+// probing; a bin's pad word holds its node + 1, 0 when free).  192 bins
+// (18 KB) keep the descent's LDS at 37 KB, four blocks per compute unit.
+constexpr int kHashSlots = 192;
+constexpr int kHashProbes = 16;
+
+// The keyed bin of `key` (a node below levels 0-1), claimed when free; -1
+// when the probes find none (the caller then adds to the node bin in HBM).
+__device__ __forceinline__ int hash_slot(FixBin* tab, int key) {
+  constexpr int kKeyed = kHashSlots - kLdsNodes;
+  const unsigned long long tag = (unsigned long long)key + 1ull;
+  int slot = kLdsNodes + (int)(((((unsigned)key * 0x9E3779B1u) >> 24) * (unsigned)kKeyed) >> 8);
+  for (int p = 0; p < kHashProbes; ++p) {
+    const unsigned long long prev = atomicCAS(&tab[slot].pad, 0ull, tag);
+    if (prev == 0ull || prev == tag) return slot;
+    slot = slot + 1 == kHashSlots ? kLdsNodes : slot + 1;
+  }
+  return -1;
+}
+
+// A run of equal stop nodes staged for its adds: its bin (-1: none, add to
+// the node bin in HBM), node (local id), number of points and the sums
+// {M0, D (3), Q}.
 struct WaveRun {
+  int slot;
   int key;
   unsigned n;
   float v[kFixVals];
-  int pad;
 };
 
 // Orders one wave's LDS writes before its later LDS reads of other lanes'
@@ -247,13 +269,14 @@ __device__ __forceinline__ void wave_lds_sync() {
 // descent, from the stop level's scores that each lane keeps.
 // Moments: neighbouring lanes of a wave with the same stop node form runs,
 // summed in FP32 by a fixed-order segmented scan inside each 16-lane row and
-// carried across row boundaries; the last lane of each run adds the run's
-// sums and count in fixed point (FixBin):
-// for the 72 nodes of levels 0-1 into block-shared LDS bins, which the block
-// adds to the node bins in HBM at its end, and for deeper nodes into the node
-// bins directly.  Fixed-point sums are integers, whose totals do not depend
-// on the order of the adds, so the moments, and the registration, are
-// bitwise reproducible.
+// carried across row boundaries; each run's sums and count are added in
+// fixed point (FixBin) to the block's bin of its node in LDS (one bin per
+// node of levels 0-1, deeper nodes in bins keyed by node), and at the end of
+// the block six neighbouring
+// lanes per node add each table bin to the node bin in HBM (when the table is
+// full a run goes to the node bin directly).  Fixed-point sums are integers,
+// whose totals do not depend on the order of the adds, so the moments, and
+// the registration, are bitwise reproducible.
 // NLEV: number of leading tree levels whose FP32 scoring records are staged
 // in LDS (2: the 72 nodes of levels 0-1; 3: also the 512 of level 2, 37 KB).
 // The FP64 scoring prefix is staged for levels 0-1.
@@ -288,7 +311,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
   constexpr int kStaged = NLEV >= 3 ? 584 : kLdsNodes;
   __shared__ NodeF lds[kStaged];
   __shared__ NodeS lds64[kLdsNodes];
-  __shared__ FixBin lfix[kLdsNodes];
+  __shared__ FixBin hbin[kHashSlots];
   __shared__ WaveRun wrun[4][64];
   __shared__ unsigned long long wsum[2];
   const int nl = T.levels >= 2 ? 72 : 8;
@@ -305,8 +328,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
     lds64[i].c = nd.c;
   }
   {
-    unsigned long long* z = &lfix[0].lo[0];
-    for (int i = threadIdx.x; i < kLdsNodes * (int)(sizeof(FixBin) / 8); i += blockDim.x) z[i] = 0ull;
+    unsigned long long* z = &hbin[0].lo[0];
+    for (int i = threadIdx.x; i < kHashSlots * (int)(sizeof(FixBin) / 8); i += blockDim.x) z[i] = 0ull;
     if (threadIdx.x < 2) wsum[threadIdx.x] = 0ull;
   }
   __syncthreads();
@@ -415,16 +438,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
         run_end = run_end && lane != bl;
       }
     }
-    // the runs' sums to the bins: the last lane of each run stages them in
-    // the wave's LDS rows, then six neighbouring lanes take one run (five
-    // sums and the count), so each atomic instruction adds to a few whole
-    // bins rather than to one word of many bins
+    // the runs' sums to their nodes' bins in the block's table: the last lane
+    // of each run claims the bin and stages the run in the wave's LDS rows,
+    // then six neighbouring lanes take one run each (five sums and the
+    // count), so the conversions to fixed point and the adds spread over
+    // the wave
     const bool emit = run_end && key >= 0;
     const unsigned long long ends = __ballot(emit);
     if (ends != 0ull) {
       wave_lds_sync();  // the previous points' reads of the rows are done
       if (emit) {
         WaveRun& w = wrun[wv][__popcll(ends & ((1ull << lane) - 1ull))];
+        w.slot = ATOMICS ? -1 : key < kLdsNodes ? key : hash_slot(hbin, key);
         w.key = key;
         w.n = (unsigned)(lane - rw + 1);
 #pragma unroll
@@ -436,31 +461,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
         const int r = r0 + lane / 6, col = lane - 6 * (lane / 6);
         if (lane >= 60 || r >= nruns) continue;
         const WaveRun& w = wrun[wv][r];
-        const int k = w.key;
+        const int k = w.key, sl = w.slot;
         if (ATOMICS) {
           // bins order {M0, D, count, Q}
           unsafeAtomicAdd(bins + (nb + k) * 6 + (col < 4 ? col : 9 - col), col == 5 ? (double)w.n : (double)w.v[col]);
         } else if (col == 5) {
-          if (k < nl) atomicAdd(&lfix[k].cnt, (unsigned long long)w.n);
+          if (sl >= 0) atomicAdd(&hbin[sl].cnt, (unsigned long long)w.n);
           else atomicAdd(&fbins[nb + k].cnt, (unsigned long long)w.n);
         } else {
           unsigned long long lo;
           long long hi;
           fix_split((double)w.v[col] * (col == 0 ? kFixScaleM0 : col < 4 ? sD : kFixScaleQ), lo, hi);
-          if (k < nl) fix_add(&lfix[k].lo[col], &lfix[k].hi[col], lo, hi);
+          if (sl >= 0) fix_add(&hbin[sl].lo[col], &hbin[sl].hi[col], lo, hi);
           else fix_add(&fbins[nb + k].lo[col], &fbins[nb + k].hi[col], lo, hi);
         }
       }
     }
   }
   __syncthreads();
-  // the block's level-0/1 bins into the node bins in HBM
-  for (int e = threadIdx.x; !ATOMICS && e < nl; e += blockDim.x) {
-    if (lfix[e].cnt == 0ull) continue;
-    FixBin& G = fbins[nb + e];
-#pragma unroll
-    for (int j = 0; j < kFixVals; ++j) fix_add(&G.lo[j], &G.hi[j], lfix[e].lo[j], lfix[e].hi[j]);
-    atomicAdd(&G.cnt, lfix[e].cnt);
+  // the table's bins into the node bins in HBM: six neighbouring lanes per
+  // bin (five sums and the count), so one atomic instruction adds to a few
+  // whole bins
+  for (int t = threadIdx.x; !ATOMICS && t < kHashSlots * 6; t += blockDim.x) {
+    const int slot = t / 6, col = t - 6 * slot;
+    if (hbin[slot].cnt == 0ull) continue;
+    FixBin& G = fbins[nb + (slot < kLdsNodes ? (int64_t)slot : (int64_t)(hbin[slot].pad - 1ull))];
+    if (col == 5) atomicAdd(&G.cnt, hbin[slot].cnt);
+    else fix_add(&G.lo[col], &G.hi[col], hbin[slot].lo[col], hbin[slot].hi[col]);
   }
   if (work) {
     atomicAdd(&wsum[0], (unsigned long long)my_points);
