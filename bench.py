@@ -359,9 +359,13 @@ class Batch:
         self.net = hg.MLP(seed=0)
         self.net.set_params(np.load(WEIGHTS))
         self.forest = None
+        self.wforest = None
 
     def warm(self):
-        return self.W.register_warm(self.net, self.src, self.tgt, self.off, self.off, self.lv, self.cfg, ws=self.ws)
+        r = self.W.register_warm(self.net, self.src, self.tgt, self.off, self.off, self.lv, self.cfg, ws=self.ws,
+                                 forest=self.wforest)
+        self.wforest = r["forest"]
+        return r
 
     def batched_plain(self):
         self.forest = self.hg.hgmm_build_batch(self.src, self.off, self.lv, ws=self.ws, forest=self.forest)

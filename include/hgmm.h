@@ -260,7 +260,8 @@ int hgmm_normal_equations(hgmm_tree tree, const double *d_bins, int64_t n, void 
  * tree is fitted by the same kernel launches; the forest handle holds B trees
  * (tree b built from cloud b with levels[b] levels; p->levels is ignored).
  * hgmm_register_batch registers target cloud b onto tree b of the forest
- * (same CSR layout, its own offsets), starting from R0[9 b..], t0[3 b..]
+ * for b < B (same CSR layout, its own offsets; the forest may hold more than
+ * B trees, and the others are not used), starting from R0[9 b..], t0[3 b..]
  * (host, nullable = identity); active (host, nullable) skips pairs whose
  * flag is 0 (their outputs are R0, t0 and 0 iterations).  Returns per pair R (B x 9), t (B x 3),
  * iters, loglik (nullable) and status (nullable; with status NULL a singular
@@ -276,7 +277,8 @@ int hgmm_register_batch(hgmm_tree forest, const float *d_xyz, const int64_t *off
 /* Mean log-likelihood of every target cloud at a fixed transform (R: B x 9,
  * t: B x 3, host): one E-step (Algorithm 1) per pair.  d_stop (nullable,
  * device, offsets[B] int32) receives each point's stop node (index inside its
- * pair's tree, -1 if unassigned). */
+ * pair's tree, -1 if unassigned).  As for hgmm_register_batch, cloud b goes
+ * with tree b and B may be below the forest size. */
 int hgmm_estep_batch(hgmm_tree forest, const float *d_xyz, const int64_t *offsets, int B, const double *R,
                      const double *t, double lambda_c, void *d_ws, size_t ws_bytes, void *stream, double *loglik,
                      int32_t *d_stop);

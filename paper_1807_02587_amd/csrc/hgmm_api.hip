@@ -1730,7 +1730,7 @@ size_t hgmm_build_batch_workspace_bytes(const int64_t* offsets, const int32_t* l
 }
 
 size_t hgmm_register_batch_workspace_bytes(hgmm_tree forest, const int64_t* offsets, int B) {
-  if (!forest || check_offsets(offsets, B) || B != (int)forest->trees.size()) return 0;
+  if (!forest || check_offsets(offsets, B) || B > (int)forest->trees.size()) return 0;
   return reg_layout(offsets[B], forest->total_nodes(), B).total;
 }
 
@@ -1786,8 +1786,8 @@ int hgmm_register_batch(hgmm_tree forest, const float* d_xyz, const int64_t* off
   int rc = check_offsets(offsets, B);
   if (rc) return rc;
   if (!forest || !d_xyz || !p || !d_ws || !R || !t || !iters) return fail(HGMM_EINVAL, "null pointer argument");
-  if (B != (int)forest->trees.size()) return fail(HGMM_EINVAL, "batch size %d != forest size %d", B,
-                                                   (int)forest->trees.size());
+  if (B > (int)forest->trees.size()) return fail(HGMM_EINVAL, "batch size %d > forest size %d", B,
+                                                  (int)forest->trees.size());
   if (p->max_iters < 1) return fail(HGMM_EINVAL, "max_iters must be >= 1");
   for (int b = 0; b < B; ++b)
     if (offsets[b + 1] - offsets[b] < 1) return fail(HGMM_ETOOFEW, "cloud %d to register is empty", b);
@@ -1817,7 +1817,7 @@ int hgmm_estep_batch(hgmm_tree forest, const float* d_xyz, const int64_t* offset
   int rc = check_offsets(offsets, B);
   if (rc) return rc;
   if (!forest || !d_xyz || !d_ws || !loglik) return fail(HGMM_EINVAL, "null pointer argument");
-  if (B != (int)forest->trees.size()) return fail(HGMM_EINVAL, "batch size != forest size");
+  if (B > (int)forest->trees.size()) return fail(HGMM_EINVAL, "batch size > forest size");
   for (int b = 0; b < B; ++b)
     if (offsets[b + 1] - offsets[b] < 1) return fail(HGMM_ETOOFEW, "cloud %d is empty", b);
   std::vector<int64_t> offs(offsets, offsets + B + 1);

@@ -3,7 +3,8 @@
 Pipeline per batch of pairs (every arithmetic step runs in the library's HIP
 kernels; this module only sequences calls and moves handles around):
 
-1. build the source forest (levels per pair) and a 2-level target forest;
+1. build the source trees (levels per pair) and the 2-level target trees,
+   as one forest (sources first) so that both share every launch;
 2. level-1 features of both trees in canonical frames (hgmm_warm_features);
 3. network forward (hgmm_mlp_forward) -> 6D rotation + translation;
 4. head -> initial transforms (hgmm_warm_head_pose);
@@ -50,9 +51,10 @@ def _eye_batch(B):
     return np.broadcast_to(np.eye(3), (B, 3, 3)).copy(), np.zeros((B, 3))
 
 
-def features_for(src_forest, tgt_forest, B, cfg: WarmConfig):
+def features_for(src_forest, tgt_forest, B, cfg: WarmConfig, tgt_first: int = 0):
+    """Features of source trees 0..B-1 and target trees tgt_first..tgt_first+B-1."""
     fs, frs = hg.hgmm_warm_features(src_forest, np.arange(B), cfg.reg_eps)
-    ft, frt = hg.hgmm_warm_features(tgt_forest, np.arange(B), cfg.reg_eps)
+    ft, frt = hg.hgmm_warm_features(tgt_forest, np.arange(tgt_first, tgt_first + B), cfg.reg_eps)
     return torch.cat([fs, ft], dim=1).contiguous(), frs, frt
 
 
@@ -125,18 +127,32 @@ def train(mlp, X, T, epochs: int = 20, batch: int = 512, lr: float = 1e-3, lr_mi
 
 
 def register_warm(mlp, src, tgt, src_off, tgt_off, src_levels, cfg: WarmConfig = WarmConfig(), ws=None,
-                  src_forest=None, fallback: str = "plain"):
+                  src_forest=None, fallback: str = "plain", forest=None):
     """Warm-started batched registration with the likelihood fallback
     (``fallback`` = "plain" or "identity", see the module docstring).
 
-    Returns dict(R (B,3,3), t, iters, loglik, fallback (B,) bool, R0, t0, forest)."""
+    Without ``src_forest`` the source and target trees are built as one
+    forest of 2B trees (source b is tree b, target b is tree B + b);
+    ``forest`` (optional) is a handle of an earlier call to rebuild in place.
+    With ``src_forest`` (B source trees) only the target forest is built.
+
+    Returns dict(R (B,3,3), t, iters, loglik, fallback (B,) bool, R0, t0,
+    forest) where forest holds the source trees 0..B-1."""
     ws = ws or hg.Workspace()
     B = len(src_levels)
     if src_forest is None:
-        src_forest = hg.hgmm_build_batch(src, src_off, src_levels, reg_eps=cfg.reg_eps, min_mass=cfg.min_mass, ws=ws)
-    tgt_forest = hg.hgmm_build_batch(tgt, tgt_off, [cfg.tgt_levels] * B, reg_eps=cfg.reg_eps, min_mass=cfg.min_mass,
-                                     ws=ws)
-    X, frs, frt = features_for(src_forest, tgt_forest, B, cfg)
+        both = torch.cat([src, tgt], dim=1).contiguous()
+        src_off = np.asarray(src_off, dtype=np.int64)
+        off = np.concatenate([src_off, np.asarray(tgt_off, dtype=np.int64)[1:] + src_off[-1]])
+        levels = [int(v) for v in np.atleast_1d(src_levels)] + [cfg.tgt_levels] * B
+        src_forest = hg.hgmm_build_batch(both, off, levels, reg_eps=cfg.reg_eps, min_mass=cfg.min_mass, ws=ws,
+                                         forest=forest)
+        tgt_forest, tgt_first = src_forest, B
+    else:
+        tgt_forest = hg.hgmm_build_batch(tgt, tgt_off, [cfg.tgt_levels] * B, reg_eps=cfg.reg_eps,
+                                         min_mass=cfg.min_mass, ws=ws)
+        tgt_first = 0
+    X, frs, frt = features_for(src_forest, tgt_forest, B, cfg, tgt_first)
     Y = mlp.forward(X)
     R0, t0 = hg.hgmm_warm_head_pose(Y, frs, frt)
     R0 = R0.cpu().numpy().reshape(B, 3, 3)

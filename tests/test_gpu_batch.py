@@ -166,14 +166,33 @@ def test_batch_argument_checks(hg, batch):
     from paper_1807_02587_amd import HgmmError
     pairs, src, tgt, soff, toff, levels = batch
     forest = hg.hgmm_build_batch(_cuda(src), soff, levels)
-    with pytest.raises(HgmmError):   # batch size differs from the forest's
-        hg.hgmm_register_batch(forest, _cuda(tgt[:, :toff[2]]), toff[:3])
+    more = np.concatenate([toff, [toff[-1] + 100]])
+    tgt_more = np.concatenate([tgt, tgt[:, :100]], axis=1)
+    with pytest.raises(HgmmError):   # more pairs than the forest has trees
+        hg.hgmm_register_batch(forest, _cuda(tgt_more), more)
     bad = soff.copy()
     bad[2] = bad[1] - 1
     with pytest.raises((HgmmError, AssertionError)):
         hg.hgmm_build_batch(_cuda(src), bad, levels)
     with pytest.raises(HgmmError):   # a cloud of fewer than 8 points
         hg.hgmm_build_batch(_cuda(src[:, :12]), np.array([0, 5, 12]), [1, 1])
+
+
+def test_register_onto_the_first_trees(hg, batch):
+    """A batch of B pairs registers onto the first B trees of a larger forest
+    (tree b with cloud b): the same results, bit for bit, as in the call with
+    every pair (a pair's registration depends only on its tree, points and
+    start)."""
+    pairs, src, tgt, soff, toff, levels = batch
+    forest = hg.hgmm_build_batch(_cuda(src), soff, levels)
+    R0, t0 = _starts(pairs)
+    full = hg.hgmm_register_batch(forest, _cuda(tgt), toff, R0=R0, t0=t0)
+    part = hg.hgmm_register_batch(forest, _cuda(tgt[:, :toff[3]]), toff[:4], R0=R0[:3], t0=t0[:3])
+    for k in ("R", "t", "iters", "loglik", "status"):
+        np.testing.assert_array_equal(part[k], full[k][:3])
+    ll = hg.hgmm_estep_batch(forest, _cuda(tgt[:, :toff[3]]), toff[:4], R0[:3], t0[:3])
+    ll_full = hg.hgmm_estep_batch(forest, _cuda(tgt), toff, R0, t0)
+    np.testing.assert_array_equal(ll, ll_full[:3])
 
 
 def test_tiled_and_block_paths_agree(hg, batch):

@@ -254,3 +254,37 @@ def test_trained_network_gain(hg):
     assert np.mean(ew <= 0.5) >= np.mean(ep <= 0.5) + 0.3
     ok = plain["status"] == 0
     assert np.all(warm["loglik"][ok] >= plain["loglik"][ok] - 1e-12)
+
+
+def test_warm_start_on_one_forest(hg):
+    """The warm start builds the source and target trees as one forest (target
+    b is tree B + b): its network inputs and initial poses agree with those
+    from separately built forests (the trees differ only in FP64 summation
+    order), the result never has a lower likelihood than the plain method on
+    the same trees, and the success rate matches the separate build's."""
+    import os
+    from paper_1807_02587_amd import warmstart as W
+    from synth.torch_scenes import cube_pairs
+    net = hg.MLP(seed=0)
+    net.set_params(np.load(os.path.join(os.path.dirname(hg.__file__), "weights", "warm_mlp.npy")))
+    cfg = W.WarmConfig()
+    B = 64
+    S = cube_pairs(3 * 10**6 + 5, B, n=10_000, max_angle_deg=90)
+    off = S.offsets.numpy()
+    Rt = S.R_true.cpu().numpy()
+    sep_forest = hg.hgmm_build_batch(S.src, off, [cfg.src_levels] * B)
+    sep = W.register_warm(net, S.src, S.tgt, off, off, [cfg.src_levels] * B, cfg, src_forest=sep_forest)
+    one = W.register_warm(net, S.src, S.tgt, off, off, [cfg.src_levels] * B, cfg)
+    assert one["forest"].ntrees == 2 * B
+    dR0 = float(np.abs(one["R0"] - sep["R0"]).max())
+    log(f"[one forest] initial poses differ by {dR0:.2e} at most")
+    assert dR0 < 1e-3
+    Ri = np.broadcast_to(np.eye(3), (B, 3, 3)).copy()
+    plain = hg.hgmm_register_batch(one["forest"], S.tgt, off, max_iters=cfg.max_iters, lambda_c=cfg.lambda_c, R0=Ri,
+                                   t0=np.zeros((B, 3)))
+    ok = plain["status"] == 0
+    assert np.all(one["loglik"][ok] >= plain["loglik"][ok])
+    e1 = W.rotation_errors_deg(one["R"], Rt)
+    e0 = W.rotation_errors_deg(sep["R"], Rt)
+    log(f"[one forest] within 0.5 deg: one forest {np.mean(e1 <= 0.5):.3f}, separate {np.mean(e0 <= 0.5):.3f}")
+    assert abs(np.mean(e1 <= 0.5) - np.mean(e0 <= 0.5)) <= 0.1
