@@ -361,6 +361,12 @@ class Batch:
         self.forest = None
         self.wforest = None
 
+    def release(self):
+        """Frees the forest handles (and their streams) kept between steps."""
+        import gc
+        self.forest = self.wforest = None
+        gc.collect()
+
     def warm(self):
         r = self.W.register_warm(self.net, self.src, self.tgt, self.off, self.off, self.lv, self.cfg, ws=self.ws,
                                  forest=self.wforest)
@@ -715,8 +721,13 @@ def main():
     if want("headline"):
         hg.hgmm_set_tuning(**batch_shapes)
         head, prof, bt = headline(args, hg)
+        # each forest handle owns streams; with a few hardware queues per
+        # process, streams of handles kept alive would share queues with the
+        # streams of the handles timed next
+        bt.release()
         if only is None:
             plain_forms(args, hg, bt, head)
+            bt.release()
         if only is None and not args.no_cpu_baseline:
             cpu = cpu_baseline(args, bt)
             progress("CPU baseline done")

@@ -383,8 +383,11 @@ void hgmm_tree_destroy(hgmm_tree tree);
  * at most block64_max points runs all its EM iterations in one 64-thread
  * block, at most block256_max in one 256-thread block, at most block512_max
  * in one 512-thread block; a larger parent is cut into tiles of tile_threads
- * threads and each EM iteration is one tile launch (which also runs the previous
- * iteration's M-step), plus one final M-step launch per level.  Points per
+ * threads and each EM iteration is one tile launch, plus one final M-step
+ * launch per level.  When a level's tile launch has at most fold_tiles tiles,
+ * every tile block also folds its parent's partials of the previous iteration
+ * and runs that M-step (no launch between iterations); with more tiles that
+ * fold runs once per parent in a launch of its own between iterations.  Points per
  * tile are level_points / target_tiles rounded up to a multiple of 64 and
  * clamped to [min_tile, max_tile].  Registration: reg_tile points per
  * 256-thread descent block (a multiple of 256); reg_chunk iterations are
@@ -408,12 +411,13 @@ void hgmm_tree_destroy(hgmm_tree tree);
  * capture, no graph launch; the host enqueues while the GPU runs).  Results
  * equal those of build_graph = 0.  Neither is used while hgmm_profile is on.
  * reg_atomics selects how the registration descent adds its moments: 0
- * (default) in 128-bit fixed point, whose integer sums do not depend on the
- * order of the additions, so moments and poses are bitwise reproducible from
- * run to run; 1 as FP64 atomic adds of each wave's FP32 sums into FP64 node
- * bins, whose order, and so the last bits of the moments of trees of 3 or
- * more levels, vary between runs (kept to compare against).
- * Defaults 256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0, 256, 2, 0, 0. */
+ * (default) in fixed point (two 64-bit integer words per value), whose
+ * integer sums do not depend on the order of the additions, so moments and
+ * poses are bitwise reproducible from run to run; 1 as FP64 atomic adds of
+ * the FP32 run sums into FP64 node bins, whose order, and so the last bits of
+ * the moments, vary between runs (kept to compare against).
+ * Defaults 256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0, 256, 2, 0, 0,
+ * 1024. */
 typedef struct hgmm_tuning {
   int32_t block64_max, block256_max, block512_max;
   int32_t min_tile, target_tiles, max_tile;
@@ -425,6 +429,7 @@ typedef struct hgmm_tuning {
   int32_t build_graph;    /* 1: construction planned on the device and run as one hipGraph; 2: the same
                              device-planned launches issued on the stream */
   int32_t reg_atomics;    /* 0: fixed-point moments (reproducible); 1: FP64 atomic moments */
+  int32_t fold_tiles;     /* largest tile launch whose blocks fold the previous iteration themselves */
 } hgmm_tuning;
 
 /* Constructions of a handle so far: those planned on the device (a replay of

@@ -20,7 +20,7 @@ class BuildParams(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [(k, C.c_int32) for k in ("block64_max", "block256_max", "block512_max", "min_tile", "target_tiles",
                                           "max_tile", "reg_tile", "reg_chunk", "reg_graph", "reg_sort", "tile_threads", "reg_lds_levels",
-                                          "build_graph", "reg_atomics")]
+                                          "build_graph", "reg_atomics", "fold_tiles")]
 
 
 class RegParams(C.Structure):

@@ -67,7 +67,8 @@ def hgmm_level_offset(level: int) -> int:
 
 
 TUNING_KEYS = ("block64_max", "block256_max", "block512_max", "min_tile", "target_tiles", "max_tile", "reg_tile",
-               "reg_chunk", "reg_graph", "reg_sort", "tile_threads", "reg_lds_levels", "build_graph", "reg_atomics")
+               "reg_chunk", "reg_graph", "reg_sort", "tile_threads", "reg_lds_levels", "build_graph", "reg_atomics",
+               "fold_tiles")
 
 
 def hgmm_get_tuning() -> dict:

@@ -521,40 +521,64 @@ __device__ __forceinline__ uint32_t frame_live(const EmFrame& f) {
 }
 
 // One EM iteration of the tiled (large) jobs: the E-step of the tile's points
-// with the children of the job's frame, and the tile's partials of the 80
-// moment sums (FP64, value-major: part[v * pstride + tile]).  The frame is
-// the job's record in `frames` (slot = Tile::pad, the job's place among the
-// tiled jobs), written by em_fold_kernel after the previous iteration; the
-// first iteration (first = 1) forms it from the initial children in the
-// scoring table instead, and the job's first tile publishes those children
-// (ch, 8 per slot) for the fold.
-template <int NT, int KP>
+// and the tile's partials of the 80 moment sums (FP64, value-major:
+// part_next[v * pstride + tile]).  The children of the job (one set of 8 per
+// tiled job, slot = Tile::pad, the job's place among the tiled jobs) come
+// from one of two places:
+//   INLINE: every block of the job folds the job's tile partials of the
+//   previous iteration (part_prev) in the same fixed order and runs the same
+//   FP64 M-step from ch_prev, so all its blocks hold bit-identical children,
+//   and the job's first tile publishes them in ch_next (ping-pong buffers);
+//   no launch between iterations, the fold repeated once per tile;
+//   otherwise: the block reads the job's E-step frame (frames, kFrameBytes
+//   per slot) that em_fold_kernel wrote after the previous iteration.
+// The first iteration (first = 1) starts from the initial children in the
+// scoring table, and the job's first tile publishes them in ch_next.
+template <int NT, int KP, bool INLINE>
 __global__ __launch_bounds__(NT) void em_tile_kernel(
     const float* __restrict__ xs, const float* __restrict__ ys, const float* __restrict__ zs,
     const Tile* __restrict__ tiles, const int* __restrict__ tile_ids, const Job* __restrict__ jobs,
-    const NodeF* __restrict__ tab, NodeF* ch, const char* __restrict__ frames, double* part, size_t pstride,
-    int first, const int* dn, int n) {
-  constexpr int NR = NT / 16;
+    const NodeF* __restrict__ tab, const NodeF* __restrict__ ch_prev, NodeF* ch_next,
+    const char* __restrict__ frames, const double* __restrict__ part_prev, double* part_next, size_t pstride,
+    double eps, double min_mass, int first, const int* dn, int n) {
+  constexpr int NR = NT / 16, NW = NT / 64;
   const int nw = work_count(dn, n);
   for (int w = blockIdx.x; w < nw; w += gridDim.x) {
   const int tix = tile_ids[w];
   const Tile tl = tiles[tix];
   const Job jb = jobs[tl.job];
   const int slot = tl.pad;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   __shared__ NodeF chs[8];
   __shared__ EmFrame fr;
   __shared__ float rows[NR][80];
-  // this block's points are requested first; their latency overlaps the frame
+  __shared__ double tot[INLINE ? 80 : 1];
+  // this block's points are requested first; their latency overlaps the
+  // fold or the frame
   PointCache<KP> pc;
   load_points<NT>(xs, ys, zs, tl.start, tl.end, tid, pc);
-  if (first) {
-    if (tid < 8) copy_nodef(chs[tid], tab[jb.child_base + tid]);
+  if (first || INLINE) {
+    if (tid < 8) copy_nodef(chs[tid], first ? tab[jb.child_base + tid] : ch_prev[(size_t)slot * 8 + tid]);
+    if (INLINE && !first) {
+      // wave w folds value groups w, w + NW, ... of 5 values each
+      for (int v0 = 5 * wv; v0 < 80; v0 += 5 * NW) {
+        double t[5];
+        wave_fold<5, 4>(part_prev + (size_t)v0 * pstride + jb.tile_first, pstride, jb.ntiles, lane, t);
+        if (lane == 0)
+          for (int j = 0; j < 5; ++j) tot[v0 + j] = t[j];
+      }
+      __syncthreads();
+      if (tid < 64) mstep_children<false, true>(tot, chs, nullptr, nullptr, 0, eps, min_mass, lane, &fr);
+    }
     __syncthreads();
-    if (tix == jb.tile_first && tid < 8) copy_nodef(ch[(size_t)slot * 8 + tid], chs[tid]);
+    if (tix == jb.tile_first && tid < 8) copy_nodef(ch_next[(size_t)slot * 8 + tid], chs[tid]);
     const uint32_t live0 = live_mask(chs);
-    if (live0) em_frame(chs, live0, fr, tid);
-    else if (tid < 8) fr.p[tid][9] = -INFINITY;
+    if (first) {
+      if (live0) em_frame(chs, live0, fr, tid);
+      else if (tid < 8) fr.p[tid][9] = -INFINITY;
+    } else if (live0 == 0u && tid < 8) {
+      fr.p[tid][9] = -INFINITY;  // the M-step left no live child
+    }
   } else {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(frames + (size_t)slot * kFrameBytes);
     uint32_t* dst = reinterpret_cast<uint32_t*>(&fr);
@@ -574,7 +598,7 @@ __global__ __launch_bounds__(NT) void em_tile_kernel(
   for (int v = tid; v < 80; v += NT) {
     double t = 0.0;
     for (int q = 0; q < NR; ++q) t += (double)rows[q][v];
-    part[(size_t)v * pstride + tix] = t;
+    part_next[(size_t)v * pstride + tix] = t;
   }
   __syncthreads();  // the block's LDS is reused by its next tile
   }
@@ -1166,18 +1190,21 @@ void launch_init_children(const Job* jobs, int njobs, const TreeDev* trees, Node
 }
 
 void launch_em_tile(int nt, const float* xs, const float* ys, const float* zs, const Tile* tiles, const int* tile_ids,
-                    int n, const Job* jobs, const NodeF* tab, NodeF* ch, const void* frames, double* part,
-                    size_t pstride, int first, hipStream_t s, const int* dn) {
+                    int n, const Job* jobs, const NodeF* tab, const NodeF* ch_prev, NodeF* ch_next, const void* frames,
+                    const double* part_prev, double* part_next, size_t pstride, double eps, double min_mass,
+                    int first, bool inline_fold, hipStream_t s, const int* dn) {
   const char* fr = static_cast<const char*>(frames);
-  if (nt == 1024)
-    hipLaunchKernelGGL((em_tile_kernel<1024, 2>), dim3(n), dim3(1024), 0, s, xs, ys, zs, tiles, tile_ids, jobs, tab,
-                       ch, fr, part, pstride, first, dn, n);
-  else if (nt == 512)
-    hipLaunchKernelGGL((em_tile_kernel<512, 4>), dim3(n), dim3(512), 0, s, xs, ys, zs, tiles, tile_ids, jobs, tab,
-                       ch, fr, part, pstride, first, dn, n);
-  else
-    hipLaunchKernelGGL((em_tile_kernel<256, 4>), dim3(n), dim3(256), 0, s, xs, ys, zs, tiles, tile_ids, jobs, tab,
-                       ch, fr, part, pstride, first, dn, n);
+#define HGMM_EM_TILE(NT_, KP_, IN_)                                                                               \
+  hipLaunchKernelGGL((em_tile_kernel<NT_, KP_, IN_>), dim3(n), dim3(NT_), 0, s, xs, ys, zs, tiles, tile_ids, jobs, \
+                     tab, ch_prev, ch_next, fr, part_prev, part_next, pstride, eps, min_mass, first, dn, n)
+  if (nt == 1024) {
+    if (inline_fold) HGMM_EM_TILE(1024, 2, true); else HGMM_EM_TILE(1024, 2, false);
+  } else if (nt == 512) {
+    if (inline_fold) HGMM_EM_TILE(512, 4, true); else HGMM_EM_TILE(512, 4, false);
+  } else {
+    if (inline_fold) HGMM_EM_TILE(256, 4, true); else HGMM_EM_TILE(256, 4, false);
+  }
+#undef HGMM_EM_TILE
 }
 
 void launch_em_fold(const int* job_ids, int n, const Job* jobs, const double* partials, size_t pstride, double eps,

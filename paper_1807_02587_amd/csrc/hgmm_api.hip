@@ -322,7 +322,7 @@ static int64_t max_lvl_for(const std::vector<TreeHost>& trees) {
 // launch shapes (process wide; see hgmm_tuning)
 // ---------------------------------------------------------------------------
 
-static hgmm_tuning g_tune = {256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0, 256, 2, 0, 0};
+static hgmm_tuning g_tune = {256, 2048, 8192, 1024, 1024, 4096, 512, 4, 0, 0, 256, 2, 0, 0, 1024};
 
 extern "C" int hgmm_set_tuning(const hgmm_tuning* t) {
   if (!t) return fail(HGMM_EINVAL, "null tuning");
@@ -341,6 +341,7 @@ extern "C" int hgmm_set_tuning(const hgmm_tuning* t) {
   if (t->reg_lds_levels != 2 && t->reg_lds_levels != 3) return fail(HGMM_EINVAL, "reg_lds_levels must be 2 or 3");
   if (t->build_graph < 0 || t->build_graph > 2) return fail(HGMM_EINVAL, "build_graph must be 0, 1 or 2");
   if (t->reg_atomics != 0 && t->reg_atomics != 1) return fail(HGMM_EINVAL, "reg_atomics must be 0 or 1");
+  if (t->fold_tiles < 0) return fail(HGMM_EINVAL, "fold_tiles must be >= 0");
   g_tune = *t;
   g_tune.min_tile = (t->min_tile + 63) / 64 * 64;
   g_tune.max_tile = (t->max_tile + 63) / 64 * 64;
@@ -544,7 +545,8 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
   double* d_partials = (double*)(ws + Ly.partials);
   double* d_part[2] = {d_partials, (double*)(ws + Ly.partials2)};
   // children (8 per tiled job) and the next E-step's frame (kFrameBytes per
-  // tiled job) of the tiled jobs between iterations
+  // tiled job) of the tiled jobs between iterations; with the fold inside
+  // the tile blocks the two regions are the children's ping-pong buffers
   NodeF* d_ch = (NodeF*)(ws + Ly.chbuf);
   void* d_frames = ws + Ly.frames;
   int* d_tile_counts = (int*)(ws + Ly.tile_counts);
@@ -741,15 +743,20 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
       }
     }
     if (nbig && p.build_iters > 0) {
-      // iteration it: the E-step of every tile, then (before the next one)
-      // the fold and M-step of every tiled job
+      // iteration it: the E-step of every tile; the previous iteration's fold
+      // and M-step either inside every tile block (few tiles: no launch in
+      // between) or once per tiled job in a launch of its own
+      const bool inl = nbig <= g_tune.fold_tiles;
+      NodeF* chb[2] = {d_ch, (NodeF*)d_frames};
       for (int it = 0; it < p.build_iters; ++it) {
         {
           ProfScope ps(PK_EM_TILE, (double)cls_points[3], s);
-          launch_em_tile(g_tune.tile_threads, cx, cy, cz, d_tiles, d_tile_ids, nbig, d_jobs, f->d_tab, d_ch, d_frames,
-                         d_part[it & 1], (size_t)Ly.max_tiles, it == 0, s);
+          launch_em_tile(g_tune.tile_threads, cx, cy, cz, d_tiles, d_tile_ids, nbig, d_jobs, f->d_tab,
+                         inl ? chb[(it + 1) & 1] : nullptr, inl ? chb[it & 1] : d_ch, inl ? nullptr : d_frames,
+                         d_part[(it + 1) & 1], d_part[it & 1], (size_t)Ly.max_tiles, p.reg_eps, p.min_mass, it == 0,
+                         inl, s);
         }
-        if (it + 1 < p.build_iters) {
+        if (!inl && it + 1 < p.build_iters) {
           ProfScope ps(PK_EM_MSTEP, (double)nbigjobs, s);
           launch_em_fold(d_job_ids + cls_off[3], nbigjobs, d_jobs, d_part[it & 1], (size_t)Ly.max_tiles, p.reg_eps,
                          p.min_mass, d_ch, d_frames, s);
@@ -758,7 +765,7 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
       const int last = (p.build_iters - 1) & 1;
       ProfScope ps(PK_EM_MSTEP, (double)nbigjobs, s);
       launch_em_mstep(d_job_ids + cls_off[3], nbigjobs, d_jobs, f->d_tab, f->d_nodes, d_part[last],
-                      (size_t)Ly.max_tiles, p.reg_eps, p.min_mass, d_ch, s);
+                      (size_t)Ly.max_tiles, p.reg_eps, p.min_mass, inl ? chb[last] : d_ch, s);
     }
     for (int c = 0; c < 3; ++c)
       if (joined[c]) HIP_TRY(hipStreamWaitEvent(s, f->ev_join[c], 0));
@@ -877,7 +884,8 @@ static int run_build_graph(hgmm_forest_s* f, BuildInput in, const hgmm_build_par
   double* d_partials = (double*)(ws + Ly.partials);
   double* d_part[2] = {d_partials, (double*)(ws + Ly.partials2)};
   // children (8 per tiled job) and the next E-step's frame (kFrameBytes per
-  // tiled job) of the tiled jobs between iterations
+  // tiled job) of the tiled jobs between iterations; with the fold inside
+  // the tile blocks the two regions are the children's ping-pong buffers
   NodeF* d_ch = (NodeF*)(ws + Ly.chbuf);
   void* d_frames = ws + Ly.frames;
   int* d_tile_counts = (int*)(ws + Ly.tile_counts);
@@ -942,16 +950,20 @@ static int run_build_graph(hgmm_forest_s* f, BuildInput in, const hgmm_build_par
           ok = ok && hipEventRecord(f->ev_join[c], f->side[c]) == hipSuccess;
         }
         if (h[2] > 0) {  // tiled parents in the hinted plan
+          const bool inl = h[2] <= g_tune.fold_tiles;
+          NodeF* chb[2] = {d_ch, (NodeF*)d_frames};
           for (int it = 0; it < p.build_iters; ++it) {
-            launch_em_tile(g_tune.tile_threads, cx, cy, cz, d_tiles, d_tile_ids, G_tile, d_jobs, f->d_tab, d_ch,
-                           d_frames, d_part[it & 1], (size_t)Ly.max_tiles, it == 0, gs, pl + PL_NBIG);
-            if (it + 1 < p.build_iters)
+            launch_em_tile(g_tune.tile_threads, cx, cy, cz, d_tiles, d_tile_ids, G_tile, d_jobs, f->d_tab,
+                           inl ? chb[(it + 1) & 1] : nullptr, inl ? chb[it & 1] : d_ch, inl ? nullptr : d_frames,
+                           d_part[(it + 1) & 1], d_part[it & 1], (size_t)Ly.max_tiles, p.reg_eps, p.min_mass,
+                           it == 0, inl, gs, pl + PL_NBIG);
+            if (!inl && it + 1 < p.build_iters)
               launch_em_fold(d_job_ids, G_mstep, d_jobs, d_part[it & 1], (size_t)Ly.max_tiles, p.reg_eps, p.min_mass,
                              d_ch, d_frames, gs, pl + PL_CLS_N + 3, pl + PL_CLS_OFF + 3);
           }
           const int last = (p.build_iters - 1) & 1;
           launch_em_mstep(d_job_ids, G_mstep, d_jobs, f->d_tab, f->d_nodes, d_part[last], (size_t)Ly.max_tiles,
-                          p.reg_eps, p.min_mass, d_ch, gs, pl + PL_CLS_N + 3, pl + PL_CLS_OFF + 3);
+                          p.reg_eps, p.min_mass, inl ? chb[last] : d_ch, gs, pl + PL_CLS_N + 3, pl + PL_CLS_OFF + 3);
         }
         for (int c = 0; c < 3 && ok; ++c)
           if (h[3 + c] > 0) ok = ok && hipStreamWaitEvent(gs, f->ev_join[c], 0) == hipSuccess;

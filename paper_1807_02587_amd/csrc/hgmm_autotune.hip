@@ -40,6 +40,7 @@ const std::vector<Knob>& knobs() {
       {&hgmm_tuning::reg_sort, {0, 1}},
       {&hgmm_tuning::reg_lds_levels, {2, 3}},
       {&hgmm_tuning::build_graph, {0, 1, 2}},
+      {&hgmm_tuning::fold_tiles, {0, 256, 1024, 4096, 1 << 30}},
   };
   return k;
 }

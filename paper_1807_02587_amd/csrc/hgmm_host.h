@@ -20,16 +20,20 @@ void launch_root(const float* xs, const float* ys, const float* zs, const Tile* 
                  const int* dntiles = nullptr, const int* dnjobs = nullptr);
 void launch_init_children(const Job* jobs, int njobs, const TreeDev* trees, NodeD* nodes, NodeF* tab, double eps,
                           hipStream_t s, const int* dn = nullptr);
-// one EM iteration of the tiled jobs (iteration 0: first = 1) with the frames
-// written by launch_em_fold (kFrameBytes per tiled job); between two
-// iterations, the fold of the partials and the M-step of every tiled job
-// (children ch updated in place, next frames written); after the last
+// one EM iteration of the tiled jobs (iteration 0: first = 1).  inline_fold:
+// every tile block folds the previous iteration's partials (part_prev) and
+// runs the M-step from ch_prev, the job's first tile publishing the children
+// in ch_next (ping-pong between iterations); otherwise the blocks read the
+// frames written by launch_em_fold (kFrameBytes per tiled job), which between
+// two iterations folds the partials and runs the M-step once per tiled job
+// (children ch updated in place, next frames written).  After the last
 // iteration, the final M-step from that iteration's children (chsrc, one set
-// of 8 per tiled job) writes the node records
+// of 8 per tiled job) writes the node records.
 constexpr size_t kFrameBytes = 512;
 void launch_em_tile(int nt, const float* xs, const float* ys, const float* zs, const Tile* tiles, const int* tile_ids,
-                    int n, const Job* jobs, const NodeF* tab, NodeF* ch, const void* frames, double* part,
-                    size_t pstride, int first, hipStream_t s, const int* dn = nullptr);
+                    int n, const Job* jobs, const NodeF* tab, const NodeF* ch_prev, NodeF* ch_next, const void* frames,
+                    const double* part_prev, double* part_next, size_t pstride, double eps, double min_mass,
+                    int first, bool inline_fold, hipStream_t s, const int* dn = nullptr);
 void launch_em_fold(const int* job_ids, int n, const Job* jobs, const double* partials, size_t pstride, double eps,
                     double min_mass, NodeF* ch, void* frames, hipStream_t s, const int* dn = nullptr,
                     const int* doff = nullptr);

@@ -195,6 +195,26 @@ def test_register_onto_the_first_trees(hg, batch):
     np.testing.assert_array_equal(ll, ll_full[:3])
 
 
+def test_fold_modes_agree(hg, batch):
+    """The previous iteration's fold and M-step inside every tile block
+    (fold_tiles large) and once per parent in a launch of its own
+    (fold_tiles = 0) sum the same partials in the same order: the trees are
+    identical bit for bit."""
+    pairs, src, _, soff, _, levels = batch
+    old = hg.hgmm_get_tuning()
+    out = []
+    try:
+        for ft in (0, 1 << 30):
+            hg.hgmm_set_tuning(block64_max=0, block256_max=0, block512_max=0, fold_tiles=ft)
+            f = hg.hgmm_build_batch(_cuda(src), soff, levels)
+            out.append([f.export(b) for b in range(len(levels))])
+    finally:
+        hg.hgmm_set_tuning(**old)
+    for a, b in zip(*out):
+        for k in ("live", "count", "pi", "mu", "cov", "kappa"):
+            np.testing.assert_array_equal(np.asarray(a[k]), np.asarray(b[k]))
+
+
 def test_tiled_and_block_paths_agree(hg, batch):
     """The same forest built with every parent tiled and with every parent in one
     block: one EM iteration from identical initial children agrees to the FP32
