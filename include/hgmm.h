@@ -360,6 +360,23 @@ int hgmm_warm_head_pose(const float *d_Y, const double *d_fr_src, const double *
                         double *d_t0, void *stream);
 int hgmm_warm_head_target(const double *d_R, const double *d_t, const double *d_fr_src, const double *d_fr_tgt, int P,
                           float *d_T, void *stream);
+/* Warm-started registration with the plain method as the fallback and the
+ * judge: pair b (target cloud b, CSR offsets, B pairs) onto tree b of the
+ * forest, starting from R0[9 b..], t0[3 b..] (host; the head's transforms).
+ * With coarse_levels > 0 and a tree deeper than that, the descent is first
+ * capped at coarse_levels levels (a wider basin; a pair whose capped run
+ * fails keeps R0, t0), then the registration runs over the whole tree.
+ * rule 0: every pair is also registered from the identity and keeps the
+ * result with the higher final log-likelihood (a failed warm run falls
+ * back); rule 1: one E-step at the identity, and a pair whose final
+ * log-likelihood is below the identity's (or whose warm run failed) is
+ * registered again from the identity.  Outputs as hgmm_register_batch, plus
+ * fallback[b] = 1 where the result is the plain method's.  The workspace is
+ * hgmm_register_batch_workspace_bytes.  Synchronises `stream`. */
+int hgmm_register_warm_batch(hgmm_tree forest, const float *d_xyz, const int64_t *offsets, int B,
+                             const hgmm_reg_params *p, int coarse_levels, int rule, const double *R0,
+                             const double *t0, void *d_ws, size_t ws_bytes, void *stream, double *R, double *t,
+                             int *iters, double *loglik, int *status, int32_t *fallback);
 /* C = op(A) op(B) on the MLP's bf16 MFMA GEMM (A, B raw bf16, C FP32). */
 int hgmm_gemm_bf16(int ta, int tb, int M, int N, int K, const uint16_t *d_A, int lda, const uint16_t *d_B, int ldb,
                    float *d_C, int ldc, void *stream);

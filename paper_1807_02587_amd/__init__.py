@@ -20,6 +20,7 @@ from .api import (  # noqa: F401
     hgmm_register_noalloc,
     hgmm_build_batch,
     hgmm_register_batch,
+    hgmm_register_warm_batch,
     hgmm_estep_batch,
     MLP,
     hgmm_warm_features,

@@ -67,6 +67,8 @@ SIGNATURES = {
     "hgmm_build_batch": (C.c_int, [P, P, P, C.c_int, P, P, C.c_size_t, P, P]),
     "hgmm_register_batch_workspace_bytes": (C.c_size_t, [P, P, C.c_int]),
     "hgmm_register_batch": (C.c_int, [P, P, P, C.c_int, P, P, P, P, P, C.c_size_t, P, P, P, P, P, P]),
+    "hgmm_register_warm_batch": (C.c_int, [P, P, P, C.c_int, P, C.c_int, C.c_int, P, P, P, C.c_size_t, P, P, P, P, P,
+                                           P, P]),
     "hgmm_odometry_workspace_bytes": (C.c_size_t, [P, C.c_int, C.c_int]),
     "hgmm_odometry": (C.c_int, [P, P, C.c_int, P, P, P, P, C.c_int, P, C.c_size_t, P, P, P, P, P, P, P, P]),
     "hgmm_estep_batch": (C.c_int, [P, P, P, C.c_int, P, P, D, P, C.c_size_t, P, P, P]),

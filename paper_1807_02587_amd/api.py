@@ -505,6 +505,34 @@ def hgmm_register_batch(forest: Tree, xyz: torch.Tensor, offsets, max_iters: int
     return dict(R=R.reshape(B, 3, 3), t=t, iters=iters, loglik=ll, status=st)
 
 
+def hgmm_register_warm_batch(forest: Tree, xyz: torch.Tensor, offsets, R0, t0, coarse_levels: int = 2,
+                             rule: str = "plain", max_iters: int = 30, lambda_c: float = 0.01, tol_rot: float = 1e-6,
+                             tol_trans_rel: float = 1e-6, ws: Workspace | None = None, stream=None) -> dict:
+    """Warm-started registration of B pairs (cloud b onto tree b) from R0, t0
+    with the plain method from the identity as fallback and judge (rule
+    "plain" or "identity"; see include/hgmm.h).  Returns dict(R (B,3,3), t,
+    iters, loglik, status, fallback (B,) bool)."""
+    xyz = _cloud(xyz)
+    lib = _lib.load()
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    B = len(off) - 1
+    if rule not in ("plain", "identity"):
+        raise ValueError(f"unknown fallback rule {rule!r}")
+    p = RegParams(max_iters, 0, lambda_c, tol_rot, tol_trans_rel)
+    R0a = np.ascontiguousarray(np.asarray(R0, dtype=np.float64).reshape(B, 9))
+    t0a = np.ascontiguousarray(np.asarray(t0, dtype=np.float64).reshape(B, 3))
+    ws = ws or Workspace(xyz.device)
+    wptr, wlen = ws.ptr(lib.hgmm_register_batch_workspace_bytes(forest.handle, off.ctypes.data_as(C.c_void_p), B))
+    R, t, ll = np.zeros((B, 9)), np.zeros((B, 3)), np.zeros(B)
+    iters, st, fb = np.zeros(B, np.int32), np.zeros(B, np.int32), np.zeros(B, np.int32)
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    check(lib.hgmm_register_warm_batch(forest.handle, C.c_void_p(xyz.data_ptr()), ptr(off), B, C.byref(p),
+                                       int(coarse_levels), 0 if rule == "plain" else 1, ptr(R0a), ptr(t0a), wptr, wlen,
+                                       _stream(stream), ptr(R), ptr(t), ptr(iters), ptr(ll), ptr(st), ptr(fb)),
+          "hgmm_register_warm_batch")
+    return dict(R=R.reshape(B, 3, 3), t=t, iters=iters, loglik=ll, status=st, fallback=fb.astype(bool))
+
+
 def hgmm_odometry(xyz: torch.Tensor, offsets, levels: int, build_iters: int = 30, reg_eps: float = 1e-6,
                   min_mass: float = 1.0, max_iters: int = 30, lambda_c: float = 0.01, tol_rot: float = 1e-6,
                   tol_trans_rel: float = 1e-6, R0=None, t0=None, prior_restart: bool = False,

@@ -1823,6 +1823,85 @@ int hgmm_register_batch(hgmm_tree forest, const float* d_xyz, const int64_t* off
   return HGMM_OK;
 }
 
+int hgmm_register_warm_batch(hgmm_tree forest, const float* d_xyz, const int64_t* offsets, int B,
+                             const hgmm_reg_params* p, int coarse_levels, int rule, const double* R0,
+                             const double* t0, void* d_ws, size_t ws_bytes, void* stream, double* R, double* t,
+                             int* iters, double* loglik, int* status, int32_t* fallback) {
+  int rc = check_offsets(offsets, B);
+  if (rc) return rc;
+  if (!forest || !d_xyz || !p || !R0 || !t0 || !d_ws || !R || !t || !iters || !loglik || !status || !fallback)
+    return fail(HGMM_EINVAL, "null pointer argument");
+  if (B > (int)forest->trees.size()) return fail(HGMM_EINVAL, "batch size %d > forest size %d", B,
+                                                  (int)forest->trees.size());
+  if (p->max_iters < 1) return fail(HGMM_EINVAL, "max_iters must be >= 1");
+  if (coarse_levels < 0) return fail(HGMM_EINVAL, "coarse_levels must be >= 0");
+  if (rule != 0 && rule != 1) return fail(HGMM_EINVAL, "rule must be 0 (plain) or 1 (identity)");
+  for (int b = 0; b < B; ++b)
+    if (offsets[b + 1] - offsets[b] < 1) return fail(HGMM_ETOOFEW, "cloud %d to register is empty", b);
+  std::vector<int64_t> offs(offsets, offsets + B + 1);
+  const int64_t n = offsets[B];
+  const float *xs = d_xyz, *ys = d_xyz + n, *zs = d_xyz + 2 * n;
+  hipStream_t s = (hipStream_t)stream;
+  const RegRun full{p->max_iters, p->lambda_c, p->tol_rot, p->tol_trans_rel, 0};
+  std::vector<PoseState> warm((size_t)B), plain((size_t)B);
+  // the start: the given transforms, refined with the capped descent
+  std::vector<double> Rs(R0, R0 + 9 * (size_t)B), ts(t0, t0 + 3 * (size_t)B);
+  int deepest = 0;
+  for (int b = 0; b < B; ++b) deepest = std::max(deepest, forest->trees[b].levels);
+  if (coarse_levels > 0 && deepest > coarse_levels) {
+    const RegRun capped{p->max_iters, p->lambda_c, p->tol_rot, p->tol_trans_rel, coarse_levels};
+    rc = run_register(forest, xs, ys, zs, offs, R0, t0, 1, capped, (char*)d_ws, ws_bytes, s, 0, nullptr, nullptr,
+                      nullptr, warm.data(), nullptr);
+    if (rc) return rc;
+    for (int b = 0; b < B; ++b) {
+      if (warm[b].status != 0) continue;
+      for (int i = 0; i < 9; ++i) Rs[9 * (size_t)b + i] = warm[b].R[i];
+      for (int i = 0; i < 3; ++i) ts[3 * (size_t)b + i] = warm[b].t[i];
+    }
+  }
+  rc = run_register(forest, xs, ys, zs, offs, Rs.data(), ts.data(), 1, full, (char*)d_ws, ws_bytes, s, 0, nullptr,
+                    nullptr, nullptr, warm.data(), nullptr);
+  if (rc) return rc;
+  std::vector<int32_t> fb((size_t)B, 0);
+  if (rule == 0) {
+    rc = run_register(forest, xs, ys, zs, offs, nullptr, nullptr, 1, full, (char*)d_ws, ws_bytes, s, 0, nullptr,
+                      nullptr, nullptr, plain.data(), nullptr);
+    if (rc) return rc;
+    for (int b = 0; b < B; ++b)
+      fb[b] = (warm[b].status != 0) || (plain[b].status == 0 && warm[b].loglik < plain[b].loglik);
+  } else {
+    std::vector<double> Ri(9 * (size_t)B, 0.0), ti(3 * (size_t)B, 0.0);
+    for (int b = 0; b < B; ++b) Ri[9 * (size_t)b] = Ri[9 * (size_t)b + 4] = Ri[9 * (size_t)b + 8] = 1.0;
+    std::vector<double> nrm(28 * (size_t)B);
+    const RegRun one{1, p->lambda_c, 0.0, 0.0, 0};
+    rc = run_register(forest, xs, ys, zs, offs, Ri.data(), ti.data(), 1, one, (char*)d_ws, ws_bytes, s, 1, nullptr,
+                      nullptr, nullptr, nullptr, nrm.data());
+    if (rc) return rc;
+    std::vector<int32_t> act((size_t)B, 0);
+    bool any = false;
+    for (int b = 0; b < B; ++b) {
+      fb[b] = (warm[b].status != 0) || (warm[b].loglik < nrm[28 * (size_t)b + 27]);
+      act[b] = fb[b];
+      any = any || fb[b];
+    }
+    if (any) {
+      rc = run_register(forest, xs, ys, zs, offs, nullptr, nullptr, 1, full, (char*)d_ws, ws_bytes, s, 0, nullptr,
+                        nullptr, nullptr, plain.data(), nullptr, act.data());
+      if (rc) return rc;
+    }
+  }
+  for (int b = 0; b < B; ++b) {
+    const PoseState& r = fb[b] ? plain[b] : warm[b];
+    for (int i = 0; i < 9; ++i) R[9 * (size_t)b + i] = r.R[i];
+    for (int i = 0; i < 3; ++i) t[3 * (size_t)b + i] = r.t[i];
+    iters[b] = r.iters;
+    loglik[b] = r.loglik;
+    status[b] = r.status;
+    fallback[b] = fb[b];
+  }
+  return HGMM_OK;
+}
+
 int hgmm_estep_batch(hgmm_tree forest, const float* d_xyz, const int64_t* offsets, int B, const double* R,
                      const double* t, double lambda_c, void* d_ws, size_t ws_bytes, void* stream, double* loglik,
                      int32_t* d_stop) {

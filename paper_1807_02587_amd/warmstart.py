@@ -11,11 +11,11 @@ kernels; this module only sequences calls and moves handles around):
 5. batched registration from those transforms, coarse to fine: first with
    the descent capped at cfg.coarse_levels levels, then with the whole tree;
 6. fallback: the plain method from the identity is the reference.  Rule "plain"
-   (default): every pair is also registered from the identity (one more
-   batched call) and keeps whichever result has the higher final
-   log-likelihood.  Rule "identity" (cheaper): a pair whose final
-   log-likelihood is below the log-likelihood of the identity transform (one
-   E-step, hgmm_estep_batch) is registered again from the identity.
+   (default): every pair is also registered from the identity and keeps
+   whichever result has the higher final log-likelihood.  Rule "identity"
+   (cheaper): a pair whose final log-likelihood is below the log-likelihood of
+   the identity transform (one E-step) is registered again from the identity.
+   Steps 5 and 6 are one library call (hgmm_register_warm_batch).
 
 Training data come from the batched GPU scene generator; the label of a pair
 is the plain method's converged pose when started at the ground truth.
@@ -45,10 +45,6 @@ class WarmConfig:
     # coarse-to-fine: from the network's pose, first register with the descent
     # capped at this many levels (wider basin), then with the whole tree; 0 off
     coarse_levels: int = 2
-
-
-def _eye_batch(B):
-    return np.broadcast_to(np.eye(3), (B, 3, 3)).copy(), np.zeros((B, 3))
 
 
 def features_for(src_forest, tgt_forest, B, cfg: WarmConfig, tgt_first: int = 0):
@@ -157,33 +153,11 @@ def register_warm(mlp, src, tgt, src_off, tgt_off, src_levels, cfg: WarmConfig =
     R0, t0 = hg.hgmm_warm_head_pose(Y, frs, frt)
     R0 = R0.cpu().numpy().reshape(B, 3, 3)
     t0 = t0.cpu().numpy()
-    Rs, ts = R0, t0
-    if cfg.coarse_levels and max(int(v) for v in np.atleast_1d(src_levels)) > cfg.coarse_levels:
-        rc = hg.hgmm_register_batch(src_forest, tgt, tgt_off, max_iters=cfg.max_iters, lambda_c=cfg.lambda_c,
-                                    R0=R0, t0=t0, ws=ws, max_levels=cfg.coarse_levels)
-        ok = (rc["status"] == 0).reshape(B, 1)
-        Rs = np.where(ok.reshape(B, 1, 1), rc["R"], R0)
-        ts = np.where(ok, rc["t"], t0)
-    r = hg.hgmm_register_batch(src_forest, tgt, tgt_off, max_iters=cfg.max_iters, lambda_c=cfg.lambda_c, R0=Rs,
-                               t0=ts, ws=ws)
-    Ri, ti = _eye_batch(B)
-    if fallback == "plain":
-        r2 = hg.hgmm_register_batch(src_forest, tgt, tgt_off, max_iters=cfg.max_iters, lambda_c=cfg.lambda_c,
-                                    R0=Ri, t0=ti, ws=ws)
-        fb = ((r["loglik"] < r2["loglik"]) & (r2["status"] == 0)) | (r["status"] != 0)
-    elif fallback == "identity":
-        ll_id = hg.hgmm_estep_batch(src_forest, tgt, tgt_off, Ri, ti, lambda_c=cfg.lambda_c, ws=ws)
-        fb = (r["loglik"] < ll_id) | (r["status"] != 0)
-        r2 = None
-        if fb.any():
-            r2 = hg.hgmm_register_batch(src_forest, tgt, tgt_off, max_iters=cfg.max_iters, lambda_c=cfg.lambda_c,
-                                        R0=Ri, t0=ti, active=fb.astype(np.int32), ws=ws)
-    else:
-        raise ValueError(f"unknown fallback rule {fallback!r}")
-    if r2 is not None:
-        for k in ("R", "t", "iters", "loglik", "status"):
-            r[k] = np.where(fb.reshape((B,) + (1,) * (r[k].ndim - 1)), r2[k], r[k])
-    r.update(fallback=fb, R0=R0, t0=t0, forest=src_forest)
+    # coarse to fine from the head's transforms, then the fallback rule (one
+    # library call)
+    r = hg.hgmm_register_warm_batch(src_forest, tgt, tgt_off, R0, t0, coarse_levels=cfg.coarse_levels, rule=fallback,
+                                    max_iters=cfg.max_iters, lambda_c=cfg.lambda_c, ws=ws)
+    r.update(R0=R0, t0=t0, forest=src_forest)
     return r
 
 

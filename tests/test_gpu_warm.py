@@ -288,3 +288,40 @@ def test_warm_start_on_one_forest(hg):
     e0 = W.rotation_errors_deg(sep["R"], Rt)
     log(f"[one forest] within 0.5 deg: one forest {np.mean(e1 <= 0.5):.3f}, separate {np.mean(e0 <= 0.5):.3f}")
     assert abs(np.mean(e1 <= 0.5) - np.mean(e0 <= 0.5)) <= 0.1
+
+
+@pytest.mark.parametrize("rule", ["plain", "identity"])
+def test_warm_entry_point_matches_the_call_sequence(hg, rule):
+    """hgmm_register_warm_batch (capped registration, full registration, the
+    fallback rule) gives the results of the same steps made as separate
+    batched calls, bit for bit."""
+    from synth.torch_scenes import cube_pairs
+    B = 32
+    S = cube_pairs(4 * 10**6 + 3, B, n=4000, max_angle_deg=60)
+    off = S.offsets.numpy()
+    forest = hg.hgmm_build_batch(S.src, off, [3] * B)
+    rng = np.random.default_rng(5)
+    Rt, tt = S.R_true.cpu().numpy(), S.t_true.cpu().numpy()
+    R0 = np.stack([rotation_from_axis_angle(rng.normal(size=3), math.radians(rng.uniform(0, 20))) @ Rt[b]
+                   for b in range(B)])
+    t0 = tt + rng.normal(scale=0.02, size=tt.shape)
+    kw = dict(max_iters=30, lambda_c=0.01)
+    rc = hg.hgmm_register_batch(forest, S.tgt, off, R0=R0, t0=t0, max_levels=2, **kw)
+    ok = rc["status"] == 0
+    Rs = np.where(ok[:, None, None], rc["R"], R0)
+    ts = np.where(ok[:, None], rc["t"], t0)
+    r = hg.hgmm_register_batch(forest, S.tgt, off, R0=Rs, t0=ts, **kw)
+    Ri, ti = np.broadcast_to(np.eye(3), (B, 3, 3)).copy(), np.zeros((B, 3))
+    if rule == "plain":
+        r2 = hg.hgmm_register_batch(forest, S.tgt, off, R0=Ri, t0=ti, **kw)
+        fb = ((r["loglik"] < r2["loglik"]) & (r2["status"] == 0)) | (r["status"] != 0)
+    else:
+        ll_id = hg.hgmm_estep_batch(forest, S.tgt, off, Ri, ti, lambda_c=0.01)
+        fb = (r["loglik"] < ll_id) | (r["status"] != 0)
+        r2 = hg.hgmm_register_batch(forest, S.tgt, off, R0=Ri, t0=ti, active=fb.astype(np.int32), **kw)
+    got = hg.hgmm_register_warm_batch(forest, S.tgt, off, R0, t0, coarse_levels=2, rule=rule, **kw)
+    log(f"[warm entry] rule {rule}: fallback {fb.mean():.2f}")
+    np.testing.assert_array_equal(got["fallback"], fb)
+    for k in ("R", "t", "iters", "loglik", "status"):
+        want = np.where(fb.reshape((B,) + (1,) * (r[k].ndim - 1)), r2[k], r[k])
+        np.testing.assert_array_equal(got[k], want)
