@@ -214,8 +214,7 @@ static size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
 struct BuildLayout {
   size_t pts[2], perm[2], child, tiles, tile_ids, job_ids, jobs, partials, partials2, chbuf, frames, tile_counts,
-      tile_base,
-      counters, lvl_info, level_trees, plans, total;
+      tile_base, lvl_info, level_trees, plans, total;
   int64_t max_tiles, max_jobs, max_lvl;
 };
 
@@ -240,7 +239,6 @@ static BuildLayout build_layout(int64_t n_total, int64_t max_jobs, int64_t max_l
   L.frames = o; o = align_up(o + kFrameBytes * (size_t)L.max_jobs);
   L.tile_counts = o; o = align_up(o + sizeof(int) * 9 * (size_t)L.max_tiles);
   L.tile_base = o; o = align_up(o + sizeof(int) * 9 * (size_t)L.max_tiles);
-  L.counters = o; o = align_up(o + sizeof(unsigned) * (size_t)L.max_jobs);
   L.lvl_info = o; o = align_up(o + sizeof(int2) * (size_t)L.max_lvl);
   // construction planned on the device: the trees of every level and the
   // level plans (PlanField ints)
@@ -251,9 +249,8 @@ static BuildLayout build_layout(int64_t n_total, int64_t max_jobs, int64_t max_l
 }
 
 struct RegLayout {
-  size_t bins, partials, counters, state, nmov, tiles, out, fbins, regf, dcount, ptiles, active, pose, keys, keys2,
-      vals,
-      perm, sxyz, sort_temp, flatf, flats, total;
+  size_t bins, state, nmov, tiles, out, fbins, regf, ptiles, active, pose, keys, keys2, vals, perm, sxyz, sort_temp,
+      flatf, flats, total;
   size_t sort_temp_bytes;
   int64_t max_tiles;
 };
@@ -263,11 +260,8 @@ static RegLayout reg_layout(int64_t n_total, int64_t nodes, int npairs) {
   L.max_tiles = n_total / 256 + npairs + 1;
   size_t o = 0;
   L.bins = o; o = align_up(o + sizeof(double) * 6 * (size_t)std::max<int64_t>(nodes, 1));
-  L.partials = o; o = align_up(o + sizeof(double) * 28 * (size_t)npairs);
-  L.counters = o; o = align_up(o + sizeof(unsigned) * (size_t)npairs);
   L.fbins = o; o = align_up(o + sizeof(FixBin) * (size_t)std::max<int64_t>(nodes, 1));  // fixed-point moments
   L.regf = o; o = align_up(o + sizeof(NodeF) * (size_t)std::max<int64_t>(nodes, 1));   // descent scoring records
-  L.dcount = o; o = align_up(o + sizeof(unsigned) * (size_t)npairs);
   // per-pair inputs uploaded together: tile ranges | point counts | start
   // poses (12 doubles: R row-major, t) | active flags
   L.ptiles = o; o = align_up(o + sizeof(int2) * (size_t)npairs);
@@ -551,7 +545,6 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
   void* d_frames = ws + Ly.frames;
   int* d_tile_counts = (int*)(ws + Ly.tile_counts);
   int* d_tile_base = (int*)(ws + Ly.tile_base);
-  unsigned* d_counters = (unsigned*)(ws + Ly.counters);
   int2* d_lvl = (int2*)(ws + Ly.lvl_info);
 
   // staging: trees | jobs | tiles | tile ids | job ids | level info
@@ -1071,8 +1064,6 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   RegLayout Ly = reg_layout(n_total, nodes_total, P);
   if (ws_bytes < Ly.total) return fail(HGMM_EINVAL, "register workspace too small: %zu < %zu", ws_bytes, Ly.total);
   double* d_bins = bins_ext ? bins_ext : (double*)(ws + Ly.bins);
-  double* d_partials = (double*)(ws + Ly.partials);
-  unsigned* d_counters = (unsigned*)(ws + Ly.counters);
   PoseState* d_state = (PoseState*)(ws + Ly.state);
   int64_t* d_nmov = (int64_t*)(ws + Ly.nmov);
   Tile* d_tiles = (Tile*)(ws + Ly.tiles);
@@ -1080,7 +1071,6 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   double* d_pose0 = (double*)(ws + Ly.pose);
   FixBin* d_fbins = (FixBin*)(ws + Ly.fbins);
   NodeF* d_regf = (NodeF*)(ws + Ly.regf);
-  unsigned* d_dcount = (unsigned*)(ws + Ly.dcount);
   int2* d_ptiles = (int2*)(ws + Ly.ptiles);
 
   // staging: tiles | per-pair inputs (the device layout from Ly.ptiles on) |

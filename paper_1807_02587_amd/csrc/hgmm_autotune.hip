@@ -121,7 +121,7 @@ extern "C" int hgmm_autotune(const float* d_src, const int64_t* src_offsets, con
   hgmm_get_tuning(&start);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-    if (e0) hipEventDestroy(e0);
+    if (e0) (void)hipEventDestroy(e0);
     return hgmm_fail(HGMM_EHIP, "event creation failed");
   }
   hgmm_tree forest = nullptr;
@@ -152,8 +152,8 @@ extern "C" int hgmm_autotune(const float* d_src, const int64_t* src_offsets, con
     }
     if (!moved) break;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (forest) hgmm_tree_destroy(forest);
   if (rc) {
     hgmm_set_tuning(&start);

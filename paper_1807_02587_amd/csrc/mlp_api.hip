@@ -52,11 +52,22 @@ static int dalloc(T*& p, int64_t n) {
   return HGMM_OK;
 }
 
+// (frees at teardown: their errors are not reported)
 static void mlp_free_acts(hgmm_mlp_s* m) {
-  hipFree(m->X);
-  for (int l = 0; l < 4; ++l) { hipFree(m->Z[l]); hipFree(m->H[l]); m->Z[l] = nullptr; m->H[l] = nullptr; }
-  hipFree(m->dH); hipFree(m->dZf); hipFree(m->dZb); hipFree(m->dY); hipFree(m->dYb); hipFree(m->rowloss);
-  if (m->h_loss) hipHostFree(m->h_loss);
+  (void)hipFree(m->X);
+  for (int l = 0; l < 4; ++l) {
+    (void)hipFree(m->Z[l]);
+    (void)hipFree(m->H[l]);
+    m->Z[l] = nullptr;
+    m->H[l] = nullptr;
+  }
+  (void)hipFree(m->dH);
+  (void)hipFree(m->dZf);
+  (void)hipFree(m->dZb);
+  (void)hipFree(m->dY);
+  (void)hipFree(m->dYb);
+  (void)hipFree(m->rowloss);
+  if (m->h_loss) (void)hipHostFree(m->h_loss);
   m->X = nullptr; m->dH = nullptr; m->dZf = nullptr; m->dZb = nullptr; m->dY = nullptr; m->dYb = nullptr;
   m->rowloss = nullptr; m->h_loss = nullptr;
   m->cap = 0;
@@ -129,8 +140,8 @@ void hgmm_mlp_destroy(hgmm_mlp m) {
   if (!m) return;
   mlp_free_acts(m);
   for (int l = 0; l < 4; ++l) {
-    hipFree(m->w[l]); hipFree(m->b[l]); hipFree(m->wb[l]); hipFree(m->mw[l]); hipFree(m->vw[l]);
-    hipFree(m->mb[l]); hipFree(m->vb[l]); hipFree(m->gw[l]); hipFree(m->gb[l]);
+    void* bufs[] = {m->w[l], m->b[l], m->wb[l], m->mw[l], m->vw[l], m->mb[l], m->vb[l], m->gw[l], m->gb[l]};
+    for (void* p : bufs) (void)hipFree(p);
   }
   delete m;
 }
@@ -185,8 +196,13 @@ int hgmm_mlp_create(uint64_t seed, hgmm_mlp* out) {
     for (int i = 0; i < kDims[l + 1]; ++i) host[o++] = 0.f;
   }
   for (int l = 0; l < 4; ++l) {
-    hipMemset(m->mw[l], 0, sizeof(float) * wsize(l)); hipMemset(m->vw[l], 0, sizeof(float) * wsize(l));
-    hipMemset(m->mb[l], 0, sizeof(float) * kDims[l + 1]); hipMemset(m->vb[l], 0, sizeof(float) * kDims[l + 1]);
+    if (hipMemset(m->mw[l], 0, sizeof(float) * wsize(l)) != hipSuccess ||
+        hipMemset(m->vw[l], 0, sizeof(float) * wsize(l)) != hipSuccess ||
+        hipMemset(m->mb[l], 0, sizeof(float) * kDims[l + 1]) != hipSuccess ||
+        hipMemset(m->vb[l], 0, sizeof(float) * kDims[l + 1]) != hipSuccess) {
+      hgmm_mlp_destroy(m);
+      return hgmm_fail(HGMM_EHIP, "clearing the optimiser state failed");
+    }
   }
   if ((rc = hgmm_mlp_set_params(m, host.data()))) { hgmm_mlp_destroy(m); return rc; }
   *out = m;
@@ -232,9 +248,11 @@ int hgmm_mlp_backward(hgmm_mlp m, const float* d_X, const float* d_T, int P, flo
     if (hipStreamSynchronize(s) != hipSuccess) return hgmm_fail(HGMM_EHIP, "sync failed");
     int64_t o = 0;
     for (int l = 0; l < 4; ++l) {
-      hipMemcpy(host_grads + o, m->gw[l], sizeof(float) * wsize(l), hipMemcpyDeviceToHost);
+      if (hipMemcpy(host_grads + o, m->gw[l], sizeof(float) * wsize(l), hipMemcpyDeviceToHost) != hipSuccess)
+        return hgmm_fail(HGMM_EHIP, "gradient copy failed");
       o += wsize(l);
-      hipMemcpy(host_grads + o, m->gb[l], sizeof(float) * kDims[l + 1], hipMemcpyDeviceToHost);
+      if (hipMemcpy(host_grads + o, m->gb[l], sizeof(float) * kDims[l + 1], hipMemcpyDeviceToHost) != hipSuccess)
+        return hgmm_fail(HGMM_EHIP, "gradient copy failed");
       o += kDims[l + 1];
     }
   }
@@ -270,10 +288,11 @@ int hgmm_warm_features(hgmm_tree forest, const int32_t* h_tree_ids, int n, doubl
   hipStream_t s = (hipStream_t)stream;
   int* d_ids = nullptr;
   if (hipMallocAsync((void**)&d_ids, sizeof(int) * n, s) != hipSuccess) return hgmm_fail(HGMM_ENOMEM, "alloc failed");
-  hipMemcpyAsync(d_ids, h_tree_ids, sizeof(int) * n, hipMemcpyHostToDevice, s);
-  launch_features(d_ids, n, hgmm_forest_trees(forest), hgmm_forest_nodes(forest), reg_eps, d_feat, d_frames, s);
-  hipFreeAsync(d_ids, s);
-  if (hipStreamSynchronize(s) != hipSuccess) return hgmm_fail(HGMM_EHIP, "features failed");
+  const bool copied = hipMemcpyAsync(d_ids, h_tree_ids, sizeof(int) * n, hipMemcpyHostToDevice, s) == hipSuccess;
+  if (copied)
+    launch_features(d_ids, n, hgmm_forest_trees(forest), hgmm_forest_nodes(forest), reg_eps, d_feat, d_frames, s);
+  const bool freed = hipFreeAsync(d_ids, s) == hipSuccess;
+  if (!copied || !freed || hipStreamSynchronize(s) != hipSuccess) return hgmm_fail(HGMM_EHIP, "features failed");
   return HGMM_OK;
 }
 

@@ -286,12 +286,13 @@ __device__ __forceinline__ void wave_lds_sync() {
 // stay in that XCD's L2.
 // work (nullable, profiling): adds the points processed and the levels they
 // scored to work[0] and work[1].  Held to 4 waves per SIMD (at most 128
-// VGPRs) for latency hiding.
+// VGPRs) for latency hiding; with level 2 staged (70 KB of LDS) two blocks
+// fit on a compute unit, two waves per SIMD.
 // rtab: the descent's copy of the scoring records (reg_table_kernel).
 // ATOMICS: the comparison mode, in which the run sums are added to FP64 node
 // bins (bins, 6 values per node, every level) with FP64 atomics instead.
 template <int NLEV, bool ATOMICS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void descend_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NLEV >= 3 ? 2 : 4))) void descend_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
                                                       const float* __restrict__ zs, const Tile* __restrict__ tiles,
                                                       int ntiles, int per_xcd, const TreeDev* __restrict__ trees,
                                                       const NodeF* __restrict__ rtab, const NodeD* __restrict__ nodes,
