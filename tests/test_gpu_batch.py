@@ -278,6 +278,32 @@ def test_register_graph_matches_stream(hg, batch):
         hg.hgmm_set_tuning(**old)
 
 
+def test_register_graph_follows_reg_tile(hg):
+    """The cached registration graph belongs to its launch shapes: changing
+    reg_tile between two graph registrations of one tree with the same number
+    of tiles (1500 points: two tiles at 768 and at 1024) builds a new graph,
+    so the single-level and soft E-steps still cover every point (their FP64
+    atomic moments allow only rounding-level differences from plain
+    launches)."""
+    p = small_pair(31, n=1500, max_angle_deg=5)
+    tree = hg.hgmm_build(_cuda(p.src), levels=2)
+    tg = _cuda(p.tgt)
+    old = hg.hgmm_get_tuning()
+    out = {}
+    try:
+        for graph in (0, 1):
+            for rt in (768, 1024):
+                hg.hgmm_set_tuning(reg_graph=graph, reg_tile=rt, reg_chunk=2)
+                out[graph, rt] = (hg.hgmm_register_flat(tree, tg, 1, max_iters=6),
+                                  hg.hgmm_register_soft(tree, tg, tau=0.01, max_iters=6))
+    finally:
+        hg.hgmm_set_tuning(**old)
+    for rt in (768, 1024):
+        for a, b in zip(out[1, rt], out[0, rt]):
+            np.testing.assert_allclose(a["R"], b["R"], rtol=0, atol=1e-9)
+            np.testing.assert_allclose(a["t"], b["t"], rtol=0, atol=1e-9 * p.extent)
+
+
 def test_morton_sorted_registration_matches(hg, batch):
     """reg_sort = 1 (moving points in Morton order inside each pair) changes only
     how points are grouped into wavefronts: per-point stop nodes and weights of
