@@ -261,7 +261,7 @@ static RegLayout reg_layout(int64_t n_total, int64_t nodes, int npairs) {
   size_t o = 0;
   L.bins = o; o = align_up(o + sizeof(double) * 6 * (size_t)std::max<int64_t>(nodes, 1));
   L.fbins = o; o = align_up(o + sizeof(FixBin) * (size_t)std::max<int64_t>(nodes, 1));  // fixed-point moments
-  L.regf = o; o = align_up(o + sizeof(NodeF) * (size_t)std::max<int64_t>(nodes, 1));   // descent scoring records
+  L.regf = o; o = align_up(o + sizeof(NodeR) * (size_t)std::max<int64_t>(nodes, 1));   // descent scoring records
   // per-pair inputs uploaded together: tile ranges | point counts | start
   // poses (12 doubles: R row-major, t) | active flags
   L.ptiles = o; o = align_up(o + sizeof(int2) * (size_t)npairs);
@@ -1070,7 +1070,7 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   double* d_out = (double*)(ws + Ly.out);
   double* d_pose0 = (double*)(ws + Ly.pose);
   FixBin* d_fbins = (FixBin*)(ws + Ly.fbins);
-  NodeF* d_regf = (NodeF*)(ws + Ly.regf);
+  NodeR* d_regf = (NodeR*)(ws + Ly.regf);
   int2* d_ptiles = (int2*)(ws + Ly.ptiles);
 
   // staging: tiles | per-pair inputs (the device layout from Ly.ptiles on) |
@@ -1168,7 +1168,7 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
       launch_flat_estep(xs, ys, zs, d_tiles, ntiles, rt, f->d_trees, d_flatf, d_flats, d_state, d_bins, so, go, pm,
                         rr.flat_level, q);
     else
-      launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, d_regf, f->d_nodes, d_state, d_fbins,
+      launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, d_regf, d_state, d_fbins,
                      fp64_atomics ? d_bins : nullptr, so, go, pm, g_tune.reg_lds_levels, rr.max_levels, wk, q);
   };
   auto mstep = [&](hipStream_t q) {

@@ -58,6 +58,19 @@ struct __align__(16) NodeF {
 };
 static_assert(sizeof(NodeF) == 64, "NodeF must be one 64-byte line");
 
+// FP64 scoring record of one node for the tree descent, 96 bytes:
+//   s = c - |W (p - mu)|^2,  W = sqrt(log2(e) / 2) * winv,  c = log2(e) * c_node,
+// the score of NodeF in FP64.  A dead node has mu = 0, W = 0 and c = -inf, so
+// it scores -inf for every point.
+struct __align__(16) NodeR {
+  double mu[3];
+  double w[6];
+  double c;
+  uint32_t flags;
+  uint32_t pad[3];
+};
+static_assert(sizeof(NodeR) == 96, "NodeR is six 16-byte words");
+
 // A contiguous range of sorted points that belongs to one parent (a "job").
 struct Tile {
   int32_t start, end, job, pad;
@@ -465,6 +478,16 @@ __device__ __forceinline__ double score64(const N& n, double p0, double p1, doub
   double w1 = n.winv[1] * d0 + n.winv[2] * d1;
   double w2 = n.winv[3] * d0 + n.winv[4] * d1 + n.winv[5] * d2;
   return kLog2e * (n.c - 0.5 * (w0 * w0 + w1 * w1 + w2 * w2));
+}
+
+// The squared whitened offset |W (p - mu)|^2 of a NodeR, which is
+// log2(e) / 2 times the squared Mahalanobis distance.
+__device__ __forceinline__ double quad_r(const NodeR& n, double p0, double p1, double p2) {
+  const double d0 = p0 - n.mu[0], d1 = p1 - n.mu[1], d2 = p2 - n.mu[2];
+  const double w0 = n.w[0] * d0;
+  const double w1 = fma(n.w[1], d0, n.w[2] * d1);
+  const double w2 = fma(n.w[3], d0, fma(n.w[4], d1, n.w[5] * d2));
+  return fma(w0, w0, fma(w1, w1, w2 * w2));
 }
 
 }  // namespace hgmm

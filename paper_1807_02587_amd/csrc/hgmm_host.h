@@ -75,9 +75,9 @@ void launch_init_pose(PoseState* st, int npairs, const double* R0, const double*
 // processed and levels scored
 // the descent's copy of the scoring records (dead nodes score -inf) with
 // this call's stop flags
-void launch_reg_table(const NodeF* tab, const NodeD* nodes, NodeF* rt, int64_t n, double lambda_c, hipStream_t s);
+void launch_reg_table(const NodeF* tab, const NodeD* nodes, NodeR* rt, int64_t n, double lambda_c, hipStream_t s);
 void launch_descend(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
-                    const TreeDev* trees, const NodeF* rtab, const NodeD* nodes, const PoseState* st, FixBin* fbins,
+                    const TreeDev* trees, const NodeR* rtab, const PoseState* st, FixBin* fbins,
                     double* atomic_bins, int32_t* stop_out, float* gamma_out, const int* perm, int lds_levels, int max_levels,
                     unsigned long long* work, hipStream_t s);
 void launch_flat_table(const NodeF* tab, const NodeD* nodes, NodeF* ft, NodeS* fs, int64_t n, hipStream_t s);

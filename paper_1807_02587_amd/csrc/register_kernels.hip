@@ -35,24 +35,28 @@ __global__ void set_stop_flags_kernel(NodeF* tab, const NodeD* __restrict__ node
   tab[g].flags = f;
 }
 
-// The descent's copy of the scoring records with this call's stop flags, in
-// which a dead node scores -inf with a zero rounding bound (c = -inf, W = 0,
-// errc = errg = 0), so that scoring 8 children needs no liveness test.
-__global__ void reg_table_kernel(const NodeF* __restrict__ tab, const NodeD* __restrict__ nodes, NodeF* rt, int64_t n,
+// The descent's FP64 scoring records (NodeR) with this call's stop flags.  A
+// dead node gets mu = 0, W = 0 and c = -inf, so that scoring 8 children
+// needs no liveness test.
+__global__ void reg_table_kernel(const NodeF* __restrict__ tab, const NodeD* __restrict__ nodes, NodeR* rt, int64_t n,
                                  double lambda_c) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
-  NodeF r = tab[g];
-  if (r.flags & F_LIVE) {
-    r.flags &= ~F_STOP;
-    if (nodes[g].kappa <= lambda_c) r.flags |= F_STOP;
+  const uint32_t f = tab[g].flags;
+  NodeR r;
+  if (f & F_LIVE) {
+    const NodeD& nd = nodes[g];
+    for (int i = 0; i < 3; ++i) r.mu[i] = nd.mu[i];
+    for (int i = 0; i < 6; ++i) r.w[i] = nd.winv[i] * kWScale;
+    r.c = nd.c * kLog2e;
+    r.flags = (f & ~F_STOP) | (nd.kappa <= lambda_c ? F_STOP : 0u);
   } else {
-    for (int i = 0; i < 6; ++i) r.w[i] = 0.f;
+    for (int i = 0; i < 3; ++i) r.mu[i] = 0.0;
+    for (int i = 0; i < 6; ++i) r.w[i] = 0.0;
     r.c = -INFINITY;
-    r.errc = 0.f;
-    r.errg = 0.f;
     r.flags = 0u;
   }
+  r.pad[0] = r.pad[1] = r.pad[2] = 0u;
   rt[g] = r;
 }
 
@@ -74,131 +78,25 @@ __global__ void init_pose_kernel(PoseState* st, int npairs, const double* __rest
   S.status = 0;
 }
 
-// Scores of the 8 children at C for p and the most likely live one; S holds
-// the children's FP64 scoring fields for the near-tie re-check.
-template <typename NodePtr, typename S64Ptr>
-__device__ __forceinline__ int choose_child(NodePtr C, S64Ptr S, double p0, double p1, double p2, float (&s)[8],
-                                            float (&q)[8], float (&m)[8], uint32_t& livemask) {
-  // branch-free over the children (every lane scores all 8; a dead child's
-  // record is read but its values are replaced), so the 8 independent
-  // chains interleave
-  livemask = 0u;
+// The most likely child among the 8 descent records at C, in FP64 (dead
+// children score -inf, so there is no liveness test; the lowest index wins
+// an exact tie).  Returns the child, -1 when none is live, and leaves every
+// child's score in s and the winner's in s1.
+template <typename RecPtr>
+__device__ __forceinline__ int choose_child64(RecPtr C, double p0, double p1, double p2, double (&s)[8],
+                                              double& s1) {
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const bool on = (C[k].flags & F_LIVE) != 0u;
-    livemask |= on ? (1u << k) : 0u;
-    float qk, mk;
-    const float sk = score32(C[k], p0, p1, p2, qk, mk);
-    s[k] = on ? sk : -INFINITY;
-    q[k] = on ? qk : 0.f;
-    m[k] = on ? mk : 0.f;
-  }
-  int k1 = -1;
-  float s1 = -INFINITY;
-#pragma unroll
-  for (int k = 0; k < 8; ++k)
-    if ((livemask >> k & 1u) && (k1 < 0 || s[k] > s1)) { s1 = s[k]; k1 = k; }
-  int k2 = -1;
-  float s2 = -INFINITY;
-#pragma unroll
-  for (int k = 0; k < 8; ++k)
-    if ((livemask >> k & 1u) && k != k1 && (k2 < 0 || s[k] > s2)) { s2 = s[k]; k2 = k; }
-  if (k2 >= 0) {
-    float e1 = 0.f, e2 = 0.f;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      if (k == k1) e1 = score_err(C[k], q[k], m[k]);
-      if (k == k2) e2 = score_err(C[k], q[k], m[k]);
-    }
-    if (s1 - s2 <= 2.f * (e1 + e2)) {
-      double best = -INFINITY;
-      int kb = k1;
-      bool first = true;
-      for (int k = 0; k < 8; ++k) {
-        if (!(livemask >> k & 1u)) continue;
-        double v = score64(S[k], p0, p1, p2);
-        if (first || v > best) { best = v; kb = k; first = false; }
-      }
-      k1 = kb;
-    }
-  }
-  return k1;
-}
-
-// The most likely child among the 8 descent records at C (dead ones score
-// -inf, so the FP32 pass has no liveness test).  When no child scores above
-// -inf, or the FP32 top-2 gap is inside the rounding bound, the live
-// children are compared in FP64 (lowest index on an exact tie).  Returns the
-// child (-1 when none is live), its FP32 score s1 and bound e1 (infinite
-// when the FP64 comparison picked another child than the FP32 pass); err
-// receives every child's FP32 rounding bound.
-template <typename RecPtr, typename S64Ptr>
-__device__ __forceinline__ int choose_child_reg(RecPtr C, S64Ptr S, double p0, double p1, double p2, float (&s)[8],
-                                                float (&err)[8], float& s1, float& e1) {
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    float q, m;
-    s[k] = score32(C[k], p0, p1, p2, q, m);
-    err[k] = score_err(C[k], q, m);
-  }
+  for (int k = 0; k < 8; ++k) s[k] = C[k].c - quad_r(C[k], p0, p1, p2);
   int k1 = -1;
   s1 = -INFINITY;
 #pragma unroll
   for (int k = 0; k < 8; ++k)
     if (s[k] > s1) { s1 = s[k]; k1 = k; }
-  int k2 = -1;
-  float s2 = -INFINITY;
-#pragma unroll
-  for (int k = 0; k < 8; ++k)
-    if (k != k1 && s[k] > s2) { s2 = s[k]; k2 = k; }
-  e1 = 0.f;
-  float e2 = 0.f;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    e1 = (k == k1) ? err[k] : e1;
-    e2 = (k == k2) ? err[k] : e2;
-  }
-  if (k1 < 0 || (k2 >= 0 && s1 - s2 <= 2.f * (e1 + e2))) {
-    double best = -INFINITY;
-    int kb = -1;
-    for (int k = 0; k < 8; ++k) {
-      if (!(C[k].flags & F_LIVE)) continue;
-      const double v = score64(S[k], p0, p1, p2);
-      if (kb < 0 || v > best) { best = v; kb = k; }
-    }
-    if (kb != k1 && kb >= 0) {
-      k1 = kb;
-      s1 = s[kb];
-      e1 = INFINITY;
-    }
-  }
   return k1;
 }
 
 constexpr int kLdsNodes = 72;    // levels 0 and 1 of one tree
-// gamma is recomputed from FP64 scores when its FP32 rounding bound exceeds
-// this (relative); the moments' tolerance against the oracle is 1e-5
-constexpr float kGammaTol = 4e-6f;
-
-// gamma of the stop child k among the live siblings.  Siblings whose FP32
-// weight t_j = 2^(s_j - s_k) contributes more than 1e-7 to gamma's rounding
-// bound (t_j (err_j + err_k) ln 2 gamma) take FP64 scores together with k;
-// the others keep their FP32 weights, so the recomputed gamma is within
-// 8e-7 relative of its FP64 value.
-template <typename S64Ptr>
-__device__ __forceinline__ float gamma_fp64(S64Ptr S, int k, const float (&s)[8], const float (&err)[8], float sk,
-                                            float ek, float gam32, double p0, double p1, double p2) {
-  const double skd = score64(S[k], p0, p1, p2);
-  float den = 1.0f;
-  for (int j = 0; j < 8; ++j) {
-    if (j == k) continue;
-    const float tj = __builtin_amdgcn_exp2f(s[j] - sk);
-    if (tj == 0.f) continue;  // a dead sibling, or one of weight below 2^-126
-    const bool exact = !(0.6931472f * tj * (err[j] + ek) * gam32 <= 1e-7f);
-    den += exact ? __builtin_amdgcn_exp2f((float)(score64(S[j], p0, p1, p2) - skd)) : tj;
-  }
-  return 1.0f / den;
-}
+constexpr double kTwoLn2 = 1.3862943611198906;  // 2 / log2(e)
 
 // Runs of equal keys inside the 16-lane rows of a wave.  A run starts at
 // the first lane of a row or where the key differs from the previous lane's.
@@ -277,25 +175,26 @@ __device__ __forceinline__ void wave_lds_sync() {
 // full a run goes to the node bin directly).  Fixed-point sums are integers,
 // whose totals do not depend on the order of the adds, so the moments, and
 // the registration, are bitwise reproducible.
-// NLEV: number of leading tree levels whose FP32 scoring records are staged
-// in LDS (2: the 72 nodes of levels 0-1; 3: also the 512 of level 2, 37 KB).
-// The FP64 scoring prefix is staged for levels 0-1.
+// Scores are FP64 (full rate on CDNA4, as FP32 without packing), so the
+// chosen child is the FP64 argmax and the weight needs no rounding bound.
+// NLEV: number of leading tree levels whose scoring records are staged in
+// LDS (2: the 72 nodes of levels 0-1, 7 KB; 3: also the 512 of level 2).
 // Grid: 8 * per_xcd blocks.  Consecutive blocks are dispatched to consecutive
 // XCDs, so block b takes tile (b % 8) * per_xcd + b / 8: every XCD works
 // through one contiguous range of tiles (of pairs), whose node records then
 // stay in that XCD's L2.
 // work (nullable, profiling): adds the points processed and the levels they
 // scored to work[0] and work[1].  Held to 4 waves per SIMD (at most 128
-// VGPRs) for latency hiding; with level 2 staged (70 KB of LDS) two blocks
-// fit on a compute unit, two waves per SIMD.
-// rtab: the descent's copy of the scoring records (reg_table_kernel).
+// VGPRs) for latency hiding; with level 2 staged (83 KB of LDS) one block
+// fits on a compute unit.
+// rtab: the descent's FP64 scoring records (reg_table_kernel).
 // ATOMICS: the comparison mode, in which the run sums are added to FP64 node
 // bins (bins, 6 values per node, every level) with FP64 atomics instead.
 template <int NLEV, bool ATOMICS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NLEV >= 3 ? 2 : 4))) void descend_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NLEV >= 3 ? 1 : 4))) void descend_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
                                                       const float* __restrict__ zs, const Tile* __restrict__ tiles,
                                                       int ntiles, int per_xcd, const TreeDev* __restrict__ trees,
-                                                      const NodeF* __restrict__ rtab, const NodeD* __restrict__ nodes,
+                                                      const NodeR* __restrict__ rtab,
                                                       const PoseState* __restrict__ st, FixBin* fbins,
                                                       double* bins, int32_t* stop_out, float* gamma_out,
                                                       const int* __restrict__ perm, int max_levels,
@@ -310,23 +209,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NLEV >= 3 ?
   const int L = (max_levels > 0 && max_levels < T.levels) ? max_levels : T.levels;
   const int64_t nb = T.node_base;
   constexpr int kStaged = NLEV >= 3 ? 584 : kLdsNodes;
-  __shared__ NodeF lds[kStaged];
-  __shared__ NodeS lds64[kLdsNodes];
+  __shared__ NodeR lds[kStaged];
   __shared__ FixBin hbin[kHashSlots];
   __shared__ WaveRun wrun[4][64];
   __shared__ unsigned long long wsum[2];
-  const int nl = T.levels >= 2 ? 72 : 8;
   const int nst = L >= NLEV ? kStaged : (L >= 2 ? 72 : 8);
-  for (int i = threadIdx.x; i < nst; i += blockDim.x) {
-    const float4* s = reinterpret_cast<const float4*>(&rtab[nb + i]);
-    float4* d = reinterpret_cast<float4*>(&lds[i]);
-    d[0] = s[0]; d[1] = s[1]; d[2] = s[2]; d[3] = s[3];
-  }
-  for (int i = threadIdx.x; i < nl; i += blockDim.x) {
-    const NodeD& nd = nodes[nb + i];
-    for (int k = 0; k < 3; ++k) lds64[i].mu[k] = nd.mu[k];
-    for (int k = 0; k < 6; ++k) lds64[i].winv[k] = nd.winv[k];
-    lds64[i].c = nd.c;
+  {
+    constexpr int kWords = (int)(sizeof(NodeR) / sizeof(float4));
+    const float4* src = reinterpret_cast<const float4*>(rtab + nb);
+    float4* dst = reinterpret_cast<float4*>(lds);
+    for (int i = threadIdx.x; i < nst * kWords; i += blockDim.x) dst[i] = src[i];
   }
   {
     unsigned long long* z = &hbin[0].lo[0];
@@ -353,57 +245,60 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NLEV >= 3 ?
       const double p2 = R6 * z0 + R7 * z1 + R8 * z2 + t2;
       int parent = 0;
       int l = 0;
-      // the stop level's child scores and bounds stay in these registers
-      // while other lanes of the wave descend further
-      float s[8], err[8], sk = 0.f, ek = 0.f;
+      // the stop level's child scores stay in these registers while other
+      // lanes of the wave descend further
+      double s[8], sk = 0.0;
       int kst = -1;
       int64_t lbst = 0;
-      for (; l < L; ++l) {
-        const int64_t lbase = lvl_off(l) + 8 * (int64_t)parent;
-        const bool in_lds = l < 2 || l < NLEV;
-        const NodeF* C = in_lds ? lds + lbase : rtab + nb + lbase;
-        const int k = (l < 2) ? choose_child_reg(C, lds64 + lbase, p0, p1, p2, s, err, sk, ek)
-                              : choose_child_reg(C, nodes + nb + lbase, p0, p1, p2, s, err, sk, ek);
-        if (k < 0) break;  // no live node here: the point is left unassigned
+      // one level: false when the descent ends here (no live child, or the
+      // chosen child is the stop node).  Called on the LDS copy for the
+      // staged levels and on the table in HBM below them, so that each
+      // call site reads through its own address space.
+      auto level = [&](const NodeR* C, int64_t lbase) -> bool {
+        const int k = choose_child64(C, p0, p1, p2, s, sk);
+        if (k < 0) return false;  // no live node here: the point is left unassigned
         const uint32_t flags = C[k].flags;
         if ((flags & F_STOP) || !(flags & F_HASCH) || (l == L - 1)) {
           kst = k;
           lbst = lbase;
-          break;
+          return false;
         }
         parent = 8 * parent + k;
+        return true;
+      };
+      bool go = true;
+      while (go && l < L && l < NLEV) {
+        const int64_t lbase = lvl_off(l) + 8 * (int64_t)parent;
+        go = level(lds + lbase, lbase);
+        if (go) ++l;
+      }
+      while (go && l < L) {
+        const int64_t lbase = lvl_off(l) + 8 * (int64_t)parent;
+        go = level(rtab + nb + lbase, lbase);
+        if (go) ++l;
       }
       my_points += 1u;
       my_levels += (unsigned)min(l + 1, L);
       if (kst >= 0) {
         // weight of the point at the chosen node: its posterior among the
         // live siblings, gamma = 1 / sum_j 2^(s_j - s_k) (dead siblings add
-        // 2^-inf = 0), with the FP32 rounding bound of that sum
-        float den = 1.f, bnd = 0.f;
+        // 2^-inf = 0).  The FP64 differences rounded to FP32 and the FP32
+        // exp2 and sum keep gamma within 1e-6 relative.
+        float den = 1.f;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const float tj = (j == kst) ? 0.f : __builtin_amdgcn_exp2f(s[j] - sk);
-          den += tj;
-          bnd = fmaf(tj, err[j] + ek, bnd);
-        }
+        for (int j = 0; j < 8; ++j) den += (j == kst) ? 0.f : __builtin_amdgcn_exp2f((float)(s[j] - sk));
         gam = 1.0f / den;
-        if (!(0.6931472f * bnd * gam <= kGammaTol))
-          gam = (lbst < kLdsNodes) ? gamma_fp64(lds64 + lbst, kst, s, err, sk, ek, gam, p0, p1, p2)
-                                   : gamma_fp64(nodes + nb + lbst, kst, s, err, sk, ek, gam, p0, p1, p2);
         g = nb + lbst + kst;
         // offset from the node mean (one FP32 rounding of an FP64 difference)
         // and the squared Mahalanobis distance in FP64
-        const int64_t lg = g - nb;
-        const double* mu = (lg < nl) ? lds64[lg].mu : nodes[g].mu;
-        const double* wi = (lg < nl) ? lds64[lg].winv : nodes[g].winv;
-        const double e0 = p0 - mu[0], e1 = p1 - mu[1], e2 = p2 - mu[2];
-        d0 = (float)e0;
-        d1 = (float)e1;
-        d2 = (float)e2;
-        const double w0 = wi[0] * e0;
-        const double w1 = wi[1] * e0 + wi[2] * e1;
-        const double w2 = wi[3] * e0 + wi[4] * e1 + wi[5] * e2;
-        dm2 = (float)(w0 * w0 + w1 * w1 + w2 * w2);
+        auto offset = [&](const NodeR& nr) {
+          d0 = (float)(p0 - nr.mu[0]);
+          d1 = (float)(p1 - nr.mu[1]);
+          d2 = (float)(p2 - nr.mu[2]);
+          dm2 = (float)(quad_r(nr, p0, p1, p2) * kTwoLn2);
+        };
+        if (g - nb < nst) offset(lds[g - nb]);
+        else offset(rtab[g]);
       }
       const int oi = perm ? perm[i] : i;
       if (stop_out) stop_out[oi] = g >= 0 ? (int32_t)(g - nb) : -1;
@@ -1014,13 +909,13 @@ void launch_import_nodes(NodeD* nodes, NodeF* tab, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(import_nodes_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nodes, tab, n);
 }
 
-void launch_reg_table(const NodeF* tab, const NodeD* nodes, NodeF* rt, int64_t n, double lambda_c, hipStream_t s) {
+void launch_reg_table(const NodeF* tab, const NodeD* nodes, NodeR* rt, int64_t n, double lambda_c, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(reg_table_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tab, nodes, rt, n, lambda_c);
 }
 
 void launch_descend(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
-                    const TreeDev* trees, const NodeF* rtab, const NodeD* nodes, const PoseState* st, FixBin* fbins,
+                    const TreeDev* trees, const NodeR* rtab, const PoseState* st, FixBin* fbins,
                     double* atomic_bins, int32_t* stop_out, float* gamma_out, const int* perm, int lds_levels,
                     int max_levels, unsigned long long* work, hipStream_t s) {
   if (ntiles <= 0) return;
@@ -1028,7 +923,7 @@ void launch_descend(const float* xs, const float* ys, const float* zs, const Til
   const dim3 grid((unsigned)(8 * per_xcd));
 #define HGMM_DESCEND(NL, AT)                                                                                          \
   hipLaunchKernelGGL((descend_kernel<NL, AT>), grid, dim3(256), 0, s, xs, ys, zs, tiles, ntiles, per_xcd, trees, rtab,\
-                     nodes, st, fbins, atomic_bins, stop_out, gamma_out, perm, max_levels, work)
+                     st, fbins, atomic_bins, stop_out, gamma_out, perm, max_levels, work)
   if (atomic_bins) {
     if (lds_levels >= 3) HGMM_DESCEND(3, true);
     else HGMM_DESCEND(2, true);
