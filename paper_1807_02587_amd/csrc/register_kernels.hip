@@ -2,15 +2,14 @@
 //
 // E-step (Sec. 4.1, Algorithm 1): every point of the moving cloud is
 // transformed in FP64, then descends the tree along the most likely child
-// (8 FP32 Mahalanobis scores per level, FP64 re-check of near ties) until the
-// chosen node is simple enough (complexity <= lambda_c), has no live children,
-// or is on the last level.  The point's weight at that node is its posterior
-// among the siblings of the last level visited.  Per-node moments are
-// aggregated across equal stop nodes inside a wavefront; the 72 nodes of the
-// first two levels are binned in FP64 LDS and written as per-block partials,
-// deeper nodes are added to FP64 bins in HBM.
-// M-step (Sec. 4.2, Eq. 8-16): one 1024-thread block per pair folds the block
-// partials in a fixed order, lets every node with mass contribute weighted
+// (8 FP64 Mahalanobis scores per level) until the chosen node is simple
+// enough (complexity <= lambda_c), has no live children, or is on the last
+// level.  The point's weight at that node is its posterior among the siblings
+// of the last level visited.  Per-node moments are summed over runs of equal
+// stop nodes inside a wavefront and added in fixed point, through a
+// block-shared table in LDS, to the node bins in HBM.
+// M-step (Sec. 4.2, Eq. 8-16): one 1024-thread block per pair reads and
+// clears the node bins, lets every node with mass contribute weighted
 // point-to-plane rows along its three eigen-directions to the 6x6 normal
 // equations, solves them by Cholesky and applies the exact rotation of the
 // solved angle vector.
@@ -123,9 +122,10 @@ __device__ __forceinline__ void run_step(float (&v)[kFixVals], float take) {
 
 // Block-shared fixed-point bins in LDS: bin k of the first kLdsNodes is node
 // k of levels 0-1; the others are keyed by node (open addressing with linear
-// probing; a bin's pad word holds its node + 1, 0 when free).  192 bins
-// (18 KB) keep the descent's LDS at 37 KB, four blocks per compute unit.
-constexpr int kHashSlots = 192;
+// probing; a bin's pad word holds its node + 1, 0 when free).  124 bins
+// (11.6 KB) keep the descent's LDS at 26.4 KB, six blocks of four waves per
+// compute unit.
+constexpr int kHashSlots = 124;
 constexpr int kHashProbes = 16;
 
 // The keyed bin of `key` (a node below levels 0-1), claimed when free; -1
@@ -184,14 +184,14 @@ __device__ __forceinline__ void wave_lds_sync() {
 // through one contiguous range of tiles (of pairs), whose node records then
 // stay in that XCD's L2.
 // work (nullable, profiling): adds the points processed and the levels they
-// scored to work[0] and work[1].  Held to 4 waves per SIMD (at most 128
-// VGPRs) for latency hiding; with level 2 staged (83 KB of LDS) one block
-// fits on a compute unit.
+// scored to work[0] and work[1].  Held to 6 waves per SIMD (at most 80
+// VGPRs), which the LDS allows, for latency hiding; with level 2 staged
+// (74 KB of LDS) two blocks fit on a compute unit.
 // rtab: the descent's FP64 scoring records (reg_table_kernel).
 // ATOMICS: the comparison mode, in which the run sums are added to FP64 node
 // bins (bins, 6 values per node, every level) with FP64 atomics instead.
 template <int NLEV, bool ATOMICS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NLEV >= 3 ? 1 : 4))) void descend_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NLEV >= 3 ? 2 : 6))) void descend_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
                                                       const float* __restrict__ zs, const Tile* __restrict__ tiles,
                                                       int ntiles, int per_xcd, const TreeDev* __restrict__ trees,
                                                       const NodeR* __restrict__ rtab,
