@@ -417,7 +417,7 @@ void hgmm_tree_destroy(hgmm_tree tree);
  * code of their position in the model tree's frame (one radix sort per call,
  * inside the workspace) so that neighbouring lanes stop at the same nodes;
  * the results change only by summation order.
- * reg_lds_levels = 3 also stages level 2 (512 nodes, 37 KB per block), which
+ * reg_lds_levels = 3 also stages level 2 (512 nodes, 48 KB per block), which
  * pays for large registration tiles.
  * build_graph = 1 plans every construction level on the device (the same
  * jobs, classes and tiles as the host planner) and runs all launches of a

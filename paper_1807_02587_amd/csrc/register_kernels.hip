@@ -251,9 +251,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NLEV >= 3 ?
       int kst = -1;
       int64_t lbst = 0;
       // one level: false when the descent ends here (no live child, or the
-      // chosen child is the stop node).  Called on the LDS copy for the
-      // staged levels and on the table in HBM below them, so that each
-      // call site reads through its own address space.
+      // chosen child is the stop node).  Each call site passes its own kind
+      // of pointer, so the records are read with scalar loads, LDS reads or
+      // vector loads as that site's address allows.
       auto level = [&](const NodeR* C, int64_t lbase) -> bool {
         const int k = choose_child64(C, p0, p1, p2, s, sk);
         if (k < 0) return false;  // no live node here: the point is left unassigned
@@ -267,14 +267,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NLEV >= 3 ?
         return true;
       };
       bool go = true;
-      while (go && l < L && l < NLEV) {
-        const int64_t lbase = lvl_off(l) + 8 * (int64_t)parent;
-        go = level(lds + lbase, lbase);
-        if (go) ++l;
-      }
       while (go && l < L) {
         const int64_t lbase = lvl_off(l) + 8 * (int64_t)parent;
-        go = level(rtab + nb + lbase, lbase);
+        // the lanes still descending are all at level l.  When they also
+        // share the parent (always at level 0, and mostly below it, as the
+        // points are in Morton order), its 8 records are read once for the
+        // wave with scalar loads and the FP64 arithmetic takes them from
+        // scalar registers; otherwise each lane reads them, from the LDS
+        // copy for the staged levels.
+        const int lu = __builtin_amdgcn_readfirstlane(l);
+        const int pu = __builtin_amdgcn_readfirstlane(parent);
+        if (__ballot(parent != pu) == 0ull) go = level(rtab + nb + lvl_off(lu) + 8 * (int64_t)pu, lbase);
+        else if (l < NLEV) go = level(lds + lbase, lbase);
+        else go = level(rtab + nb + lbase, lbase);
         if (go) ++l;
       }
       my_points += 1u;
