@@ -95,7 +95,10 @@ def _profile_kinds(hg):
 
 
 def roofline_of(prof, traffic=None):
-    """ALU roofline of the kernel family with the largest summed event time.
+    """ALU roofline of the kernel family with the largest summed event time
+    (the construction's one-block-per-parent EM and the registration descent
+    are within a few percent of each other on the headline step, so either
+    can lead; every family's fraction and average launch are reported).
     prof: hgmm_profile_read per kind (event ms, launches, host units, and for
     the descent the device-counted points and levels).  traffic: which
     committed counter summary ("batch" or "lidar") gives HBM bytes per launch."""
@@ -108,11 +111,12 @@ def roofline_of(prof, traffic=None):
     names = {"em_tile": "em_tile_kernel (construction EM iteration of large parents)",
              "em_block": "em_block_kernel (all construction EM iterations, one block per parent)",
              "descend": "descend_kernel (registration E-step)"}
-    fam = {}
+    fam, fam_us = {}, {}
     for k in flop:
         p = prof[k]
         if p["ms"] > 0 and p["launches"] > 0:
             fam[k] = round(flop[k](p) / (p["ms"] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4)
+            fam_us[k] = round(p["ms"] * 1e3 / p["launches"], 2)
     dom = max(flop, key=lambda k: prof[k]["ms"])
     p = prof[dom]
     ms, n = p["ms"], max(p["launches"], 1)
@@ -124,7 +128,7 @@ def roofline_of(prof, traffic=None):
            "flop_per_launch": round(f_launch), "algorithmic_bytes_per_launch": round(b_launch),
            "frac_of_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
            "achieved_hbm_GBs": round(b_launch / (us * 1e-6) / 1e9, 1) if us > 0 else 0.0,
-           "frac_by_family": fam}
+           "frac_by_family": fam, "avg_launch_us_by_family": fam_us}
     if traffic:
         out.update(_valu(dom, traffic))
     return out
