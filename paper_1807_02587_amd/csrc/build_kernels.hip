@@ -744,10 +744,27 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void em
 }
 
 // ---------------------------------------------------------------------------
-// hard partition: most likely live child of every point, with an FP64 re-check
-// whenever the FP32 top-2 gap is inside the rounding bound
+// hard partition: most likely live child of every point, in FP64
 // ---------------------------------------------------------------------------
 
+// The FP64 scoring fields of a node read through the constant address space:
+// the kernel never writes them, so reads at an address uniform over the block
+// become scalar loads.
+typedef const __attribute__((address_space(4))) NodeS ConstNodeS;
+
+__device__ __forceinline__ double score64_c(const ConstNodeS* n, double p0, double p1, double p2) {
+  const double d0 = p0 - n->mu[0], d1 = p1 - n->mu[1], d2 = p2 - n->mu[2];
+  const double w0 = n->winv[0] * d0;
+  const double w1 = n->winv[1] * d0 + n->winv[2] * d1;
+  const double w2 = n->winv[3] * d0 + n->winv[4] * d1 + n->winv[5] * d2;
+  return kLog2e * (n->c - 0.5 * (w0 * w0 + w1 * w1 + w2 * w2));
+}
+
+// Every point of a tile scores the 8 children of the tile's parent in FP64
+// (full rate on CDNA4, as FP32 without packing) and takes the most likely
+// live one (the lowest index on an exact tie; the first live child when no
+// score is a number).  The children are the same for the whole block, so
+// their records are read with scalar loads.
 __global__ __launch_bounds__(64) void partition_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
                                                        const float* __restrict__ zs, const Tile* __restrict__ tiles,
                                                        const Job* __restrict__ jobs, const NodeF* __restrict__ tab,
@@ -758,10 +775,12 @@ __global__ __launch_bounds__(64) void partition_kernel(const float* __restrict__
   const Tile tl = tiles[w];
   const Job jb = jobs[tl.job];
   const int lane = threadIdx.x;
-  __shared__ NodeF ch[8];
-  if (lane < 8) copy_nodef(ch[lane], tab[jb.child_base + lane]);
-  __syncthreads();
-  const uint32_t live = live_mask(ch);
+  uint32_t live = 0u;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) live |= (tab[jb.child_base + k].flags & F_LIVE) ? (1u << k) : 0u;
+  const ConstNodeS* S = (const ConstNodeS*)(nodes + jb.child_base);
+  static_assert(sizeof(NodeD) % 8 == 0 && __builtin_offsetof(NodeD, c) == __builtin_offsetof(NodeS, c),
+                "NodeS is the prefix of NodeD");
   int cnt[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int base = tl.start; base < tl.end; base += 64) {
     const int i = base + lane;
@@ -769,41 +788,17 @@ __global__ __launch_bounds__(64) void partition_kernel(const float* __restrict__
     int bucket = 8;
     if (valid && live) {
       const double p0 = xs[i], p1 = ys[i], p2 = zs[i];
-      float s[8], q[8], m[8];
+      double best = -INFINITY;
+      int kb = -1;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        if (live & (1u << k)) s[k] = score32(ch[k], p0, p1, p2, q[k], m[k]);
-        else { s[k] = -INFINITY; q[k] = 0.f; m[k] = 0.f; }
+        if (!(live & (1u << k))) continue;
+        const double v = score64_c((const ConstNodeS*)((const __attribute__((address_space(4))) char*)S +
+                                                       (size_t)k * sizeof(NodeD)),
+                                   p0, p1, p2);
+        if (kb < 0 || v > best) { best = v; kb = k; }
       }
-      int k1 = -1;
-      float s1 = -INFINITY;
-#pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if ((live & (1u << k)) && (k1 < 0 || s[k] > s1)) { s1 = s[k]; k1 = k; }
-      int k2 = -1;
-      float s2 = -INFINITY;
-#pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if ((live & (1u << k)) && k != k1 && (k2 < 0 || s[k] > s2)) { s2 = s[k]; k2 = k; }
-      bucket = k1;
-      if (k2 >= 0) {
-        float e1 = 0.f, e2 = 0.f;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          if (k == k1) e1 = score_err(ch[k], q[k], m[k]);
-          if (k == k2) e2 = score_err(ch[k], q[k], m[k]);
-        }
-        if (s1 - s2 <= 2.f * (e1 + e2)) {
-          double best = -INFINITY;
-          int kb = -1;
-          for (int k = 0; k < 8; ++k) {
-            if (!(live & (1u << k))) continue;
-            double v = score64(nodes[jb.child_base + k], p0, p1, p2);
-            if (kb < 0 || v > best) { best = v; kb = k; }
-          }
-          bucket = kb;
-        }
-      }
+      bucket = kb;
     }
     if (valid) child_out[i] = (uint8_t)bucket;
 #pragma unroll
@@ -815,7 +810,6 @@ __global__ __launch_bounds__(64) void partition_kernel(const float* __restrict__
     for (int b = 1; b < 9; ++b) v = (lane == b) ? cnt[b] : v;
     tile_counts[(size_t)w * 9 + lane] = v;
   }
-  __syncthreads();
   }
 }
 
