@@ -372,7 +372,10 @@ int hgmm_warm_head_target(const double *d_R, const double *d_t, const double *d_
  * log-likelihood is below the identity's (or whose warm run failed) is
  * registered again from the identity.  Outputs as hgmm_register_batch, plus
  * fallback[b] = 1 where the result is the plain method's.  The workspace is
- * hgmm_register_batch_workspace_bytes.  Synchronises `stream`. */
+ * hgmm_register_batch_workspace_bytes.  With reg_sort the moving points are
+ * put in Morton order once, by the first of these runs, and the later runs
+ * reuse that order (it depends on the points and the trees' frames, not on
+ * the poses).  Synchronises `stream`. */
 int hgmm_register_warm_batch(hgmm_tree forest, const float *d_xyz, const int64_t *offsets, int B,
                              const hgmm_reg_params *p, int coarse_levels, int rule, const double *R0,
                              const double *t0, void *d_ws, size_t ws_bytes, void *stream, double *R, double *t,

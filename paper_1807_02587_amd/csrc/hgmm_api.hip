@@ -1051,6 +1051,11 @@ struct RegRun {
   // nor the profiling events, so it allocates nothing
   char* stage = nullptr;
   size_t stage_bytes = 0;
+  // with reg_sort: the Morton order of the moving points is already in the
+  // workspace, left by an earlier run over the same points, forest and
+  // workspace (the keys depend on the points and the trees' frames, not on
+  // the poses), so the sort is skipped
+  bool sorted = false;
 };
 
 static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, const float* zs,
@@ -1136,9 +1141,10 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
     float* sx = (float*)(ws + Ly.sxyz);
     float* sy = sx + n_total;
     float* sz = sy + n_total;
-    HIP_TRY(launch_sort_points(xs, ys, zs, d_tiles, ntiles, f->d_trees, P, n_total, (uint64_t*)(ws + Ly.keys),
-                               (uint64_t*)(ws + Ly.keys2), (int*)(ws + Ly.vals), (int*)(ws + Ly.perm),
-                               ws + Ly.sort_temp, Ly.sort_temp_bytes, sx, sy, sz, s));
+    if (!rr.sorted)
+      HIP_TRY(launch_sort_points(xs, ys, zs, d_tiles, ntiles, f->d_trees, P, n_total, (uint64_t*)(ws + Ly.keys),
+                                 (uint64_t*)(ws + Ly.keys2), (int*)(ws + Ly.vals), (int*)(ws + Ly.perm),
+                                 ws + Ly.sort_temp, Ly.sort_temp_bytes, sx, sy, sz, s));
     xs = sx; ys = sy; zs = sz;
     d_perm = (const int*)(ws + Ly.perm);
   }
@@ -1832,7 +1838,10 @@ int hgmm_register_warm_batch(hgmm_tree forest, const float* d_xyz, const int64_t
   const int64_t n = offsets[B];
   const float *xs = d_xyz, *ys = d_xyz + n, *zs = d_xyz + 2 * n;
   hipStream_t s = (hipStream_t)stream;
-  const RegRun full{p->max_iters, p->lambda_c, p->tol_rot, p->tol_trans_rel, 0};
+  // every run below registers the same points onto the same trees with the
+  // same workspace, so the first one sorts them (reg_sort) and the others
+  // reuse its order
+  RegRun full{p->max_iters, p->lambda_c, p->tol_rot, p->tol_trans_rel, 0};
   std::vector<PoseState> warm((size_t)B), plain((size_t)B);
   // the start: the given transforms, refined with the capped descent
   std::vector<double> Rs(R0, R0 + 9 * (size_t)B), ts(t0, t0 + 3 * (size_t)B);
@@ -1843,6 +1852,7 @@ int hgmm_register_warm_batch(hgmm_tree forest, const float* d_xyz, const int64_t
     rc = run_register(forest, xs, ys, zs, offs, R0, t0, 1, capped, (char*)d_ws, ws_bytes, s, 0, nullptr, nullptr,
                       nullptr, warm.data(), nullptr);
     if (rc) return rc;
+    full.sorted = true;
     for (int b = 0; b < B; ++b) {
       if (warm[b].status != 0) continue;
       for (int i = 0; i < 9; ++i) Rs[9 * (size_t)b + i] = warm[b].R[i];
@@ -1852,6 +1862,7 @@ int hgmm_register_warm_batch(hgmm_tree forest, const float* d_xyz, const int64_t
   rc = run_register(forest, xs, ys, zs, offs, Rs.data(), ts.data(), 1, full, (char*)d_ws, ws_bytes, s, 0, nullptr,
                     nullptr, nullptr, warm.data(), nullptr);
   if (rc) return rc;
+  full.sorted = true;
   std::vector<int32_t> fb((size_t)B, 0);
   if (rule == 0) {
     rc = run_register(forest, xs, ys, zs, offs, nullptr, nullptr, 1, full, (char*)d_ws, ws_bytes, s, 0, nullptr,
@@ -1863,7 +1874,8 @@ int hgmm_register_warm_batch(hgmm_tree forest, const float* d_xyz, const int64_t
     std::vector<double> Ri(9 * (size_t)B, 0.0), ti(3 * (size_t)B, 0.0);
     for (int b = 0; b < B; ++b) Ri[9 * (size_t)b] = Ri[9 * (size_t)b + 4] = Ri[9 * (size_t)b + 8] = 1.0;
     std::vector<double> nrm(28 * (size_t)B);
-    const RegRun one{1, p->lambda_c, 0.0, 0.0, 0};
+    RegRun one{1, p->lambda_c, 0.0, 0.0, 0};
+    one.sorted = true;
     rc = run_register(forest, xs, ys, zs, offs, Ri.data(), ti.data(), 1, one, (char*)d_ws, ws_bytes, s, 1, nullptr,
                       nullptr, nullptr, nullptr, nrm.data());
     if (rc) return rc;
