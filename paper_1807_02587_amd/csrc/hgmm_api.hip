@@ -250,7 +250,7 @@ static BuildLayout build_layout(int64_t n_total, int64_t max_jobs, int64_t max_l
 
 struct RegLayout {
   size_t bins, state, nmov, tiles, out, fbins, regf, ptiles, active, pose, keys, keys2, vals, perm, sxyz, sort_temp,
-      flatf, flats, total;
+      flatf, total;
   size_t sort_temp_bytes;
   int64_t max_tiles;
 };
@@ -280,8 +280,7 @@ static RegLayout reg_layout(int64_t n_total, int64_t nodes, int npairs) {
   L.sort_temp_bytes = sort_temp_bytes(n_total, npairs);
   L.sort_temp = o; o = align_up(o + L.sort_temp_bytes);
   // scoring records with global weights (single-level E-step)
-  L.flatf = o; o = align_up(o + sizeof(NodeF) * (size_t)std::max<int64_t>(nodes, 1));
-  L.flats = o; o = align_up(o + sizeof(NodeS) * (size_t)std::max<int64_t>(nodes, 1));
+  L.flatf = o; o = align_up(o + sizeof(NodeR) * (size_t)std::max<int64_t>(nodes, 1));  // single-level records
   L.total = o;
   return L;
 }
@@ -1162,16 +1161,15 @@ static int run_register(hgmm_forest_s* f, const float* xs, const float* ys, cons
   int max_tree_levels = 1;
   for (auto& tr : f->trees) max_tree_levels = std::max(max_tree_levels, tr.levels);
   // one E-step launch (descent, or the single-level scan) and one M-step launch
-  NodeF* d_flatf = (NodeF*)(ws + Ly.flatf);
-  NodeS* d_flats = (NodeS*)(ws + Ly.flats);
-  if (flat) launch_flat_table(f->d_tab, f->d_nodes, d_flatf, d_flats, nodes_total, s);
+  NodeR* d_flatf = (NodeR*)(ws + Ly.flatf);
+  if (flat) launch_flat_table(f->d_tab, f->d_nodes, d_flatf, nodes_total, s);
   auto estep = [&](hipStream_t q, int32_t* so, float* go, const int* pm, unsigned long long* wk) {
     if (soft)
       launch_soft_estep(xs, ys, zs, d_tiles, ntiles, rt, max_tree_levels, f->d_trees, f->d_tab, f->d_nodes, d_state,
                         d_bins,
                         (float)rr.soft_tau, so, pm, q);
     else if (flat)
-      launch_flat_estep(xs, ys, zs, d_tiles, ntiles, rt, f->d_trees, d_flatf, d_flats, d_state, d_bins, so, go, pm,
+      launch_flat_estep(xs, ys, zs, d_tiles, ntiles, rt, f->d_trees, d_flatf, d_state, d_bins, so, go, pm,
                         rr.flat_level, q);
     else
       launch_descend(xs, ys, zs, d_tiles, ntiles, f->d_trees, d_regf, d_state, d_fbins,

@@ -480,9 +480,11 @@ __device__ __forceinline__ double score64(const N& n, double p0, double p1, doub
   return kLog2e * (n.c - 0.5 * (w0 * w0 + w1 * w1 + w2 * w2));
 }
 
-// The squared whitened offset |W (p - mu)|^2 of a NodeR, which is
+// The squared whitened offset |W (p - mu)|^2 of a NodeR (in any address
+// space), which is
 // log2(e) / 2 times the squared Mahalanobis distance.
-__device__ __forceinline__ double quad_r(const NodeR& n, double p0, double p1, double p2) {
+template <typename N>
+__device__ __forceinline__ double quad_r(const N& n, double p0, double p1, double p2) {
   const double d0 = p0 - n.mu[0], d1 = p1 - n.mu[1], d2 = p2 - n.mu[2];
   const double w0 = n.w[0] * d0;
   const double w1 = fma(n.w[1], d0, n.w[2] * d1);

@@ -80,11 +80,10 @@ void launch_descend(const float* xs, const float* ys, const float* zs, const Til
                     const TreeDev* trees, const NodeR* rtab, const PoseState* st, FixBin* fbins,
                     double* atomic_bins, int32_t* stop_out, float* gamma_out, const int* perm, int lds_levels, int max_levels,
                     unsigned long long* work, hipStream_t s);
-void launch_flat_table(const NodeF* tab, const NodeD* nodes, NodeF* ft, NodeS* fs, int64_t n, hipStream_t s);
+void launch_flat_table(const NodeF* tab, const NodeD* nodes, NodeR* fr, int64_t n, hipStream_t s);
 void launch_flat_estep(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
-                       int tile_points, const TreeDev* trees, const NodeF* tab, const NodeS* nodes,
-                       const PoseState* st, double* bins, int32_t* stop_out, float* gamma_out, const int* perm,
-                       int level, hipStream_t s);
+                       int tile_points, const TreeDev* trees, const NodeR* ftab, const PoseState* st, double* bins,
+                       int32_t* stop_out, float* gamma_out, const int* perm, int level, hipStream_t s);
 void launch_soft_estep(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
                        int tile_points, int max_levels, const TreeDev* trees, const NodeF* tab, const NodeD* nodes,
                        const PoseState* st, double* bins, float tau, int32_t* stops_out, const int* perm,

@@ -421,132 +421,101 @@ __global__ __launch_bounds__(256) void fold_bins_kernel(const TreeDev* __restric
 //
 // The live nodes of one tree level form a mixture of J = 8^(level+1)
 // components with their global weights.  Every point is scored against every
-// component (a linear scan instead of the tree's logarithmic descent): FP32
-// scores with their rounding bounds, a running maximum and a running
-// denominator sum_j 2^(s_j - s_max) rescaled whenever the maximum changes.
-// The FP32 winner is re-checked in FP64 over the whole level when another
-// component's score bound reaches it (lowest index wins exact FP64 ties), and
-// the posterior is recomputed in FP64 when its rounding bound exceeds
-// kFlatGammaTol (relative).  The moments go to the node bins with FP64
-// atomics after aggregation of equal components inside a wave.
-// The tree's scoring records carry the weight inside the sibling group; the
-// single-level mixture needs the global weight, so the E-step reads records
-// rebuilt with it (flat_table_kernel).
+// component (a linear scan instead of the tree's logarithmic descent), in
+// FP64, keeping the maximum (lowest index on exact ties) and the denominator
+// sum_j 2^(s_j - m) against a reference score m that moves only when a score
+// exceeds it by more than kFlatLag.  A move multiplies the old sum by less
+// than 2^-kFlatLag, so the FP32 exp2 of each term and of the rescale keep
+// the posterior within 1e-6 relative.  Every lane of a wave scores the same
+// component at a time, so the components' records are read with scalar
+// loads.  The moments go to the node bins with FP64 atomics after
+// aggregation of equal components inside a wave.  The tree's records carry
+// the weight inside the sibling group; the single-level mixture needs the
+// global weight, so the E-step reads records rebuilt with it
+// (flat_table_kernel).
 
-constexpr float kFlatGammaTol = 1e-5f;
-
-// Scoring records of every node with the global weight pi^g in the constant:
-// c = log pi^g - log|cov| / 2 (FP64), its FP32 log2 form and rounding bound.
-__global__ void flat_table_kernel(const NodeF* __restrict__ tab, const NodeD* __restrict__ nodes, NodeF* ft,
-                                  NodeS* fs, int64_t n) {
+// The FP64 scoring records of every node with the global weight pi^g in the
+// constant: c = log2(e) (log pi^g - log|cov| / 2), W = sqrt(log2(e) / 2) L^-1.
+// A dead component gets mu = 0, W = 0 and c = -inf, so it scores -inf for
+// every point and adds nothing to the running sums: the scan has no liveness
+// test.
+__global__ void flat_table_kernel(const NodeF* __restrict__ tab, const NodeD* __restrict__ nodes, NodeR* fr,
+                                  int64_t n) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   const NodeD& nd = nodes[g];
-  NodeF f = tab[g];
-  NodeS v;
-  for (int k = 0; k < 3; ++k) v.mu[k] = nd.mu[k];
-  for (int k = 0; k < 6; ++k) v.winv[k] = nd.winv[k];
-  v.c = 0.0;
-  if ((f.flags & F_LIVE) && nd.pig > 0.0) {
-    v.c = log(nd.pig) - 0.5 * nd.logdet;
-    f.c = (float)(v.c * kLog2e);
-    f.errc = 2.f * kU * fabsf(f.c) * 1.0001f;
+  NodeR r;
+  if ((tab[g].flags & F_LIVE) && nd.pig > 0.0) {
+    for (int k = 0; k < 3; ++k) r.mu[k] = nd.mu[k];
+    for (int k = 0; k < 6; ++k) r.w[k] = nd.winv[k] * kWScale;
+    r.c = (log(nd.pig) - 0.5 * nd.logdet) * kLog2e;
+    r.flags = F_LIVE;
   } else {
-    // a dead component scores -inf for every point (and adds nothing to the
-    // running sums), so the scan needs no liveness test
-    f = NodeF{};
-    f.c = -INFINITY;
+    for (int k = 0; k < 3; ++k) r.mu[k] = 0.0;
+    for (int k = 0; k < 6; ++k) r.w[k] = 0.0;
+    r.c = -INFINITY;
+    r.flags = 0u;
   }
-  ft[g] = f;
-  fs[g] = v;
+  r.pad[0] = r.pad[1] = r.pad[2] = 0u;
+  fr[g] = r;
 }
 
-template <typename NodePtr>
-__device__ double flat_argmax64(NodePtr S, const NodeF* __restrict__ F, int J, double p0, double p1, double p2,
-                                int& kb) {
-  double best = -INFINITY;
-  kb = -1;
-  for (int j = 0; j < J; ++j) {
-    if (!(F[j].flags & F_LIVE)) continue;
-    const double v = score64(S[j], p0, p1, p2);
-    if (kb < 0 || v > best) { best = v; kb = j; }
-  }
-  return best;
-}
+// a component record read through the constant address space: the kernel
+// never writes the table, so reads at a wave-uniform address are scalar loads
+typedef const __attribute__((address_space(4))) NodeR ConstNodeR;
 
-// posterior of component k among every live component, FP64 scores for the
-// components within 2^-40 of the FP32 maximum (the rest from FP32)
-template <typename NodePtr>
-__device__ float flat_gamma64(NodePtr S, const NodeF* __restrict__ F, int J, int k, double sk64, float s1,
-                              double p0, double p1, double p2) {
-  double den = 0.0;
-  for (int j = 0; j < J; ++j) {
-    if (!(F[j].flags & F_LIVE)) continue;
-    if (j == k) { den += 1.0; continue; }
-    float q, m;
-    const float dj = score32(F[j], p0, p1, p2, q, m) - s1;
-    den += dj > -40.f ? exp2(score64(S[j], p0, p1, p2) - sk64) : (double)__builtin_amdgcn_exp2f(dj);
-  }
-  return (float)(1.0 / den);
-}
+constexpr int kFlatSlices = 4;      // waves per block; wave w scans slice w of the components
+constexpr double kFlatLag = 8.0;    // the reference score moves when a score exceeds it by more
 
-constexpr int kFlatSlices = 4;  // waves per block; wave w scans slice w of the components
-constexpr int kFlatChunk = 64;  // records of a slice staged in LDS at a time (4 KB per wave)
-
-// Running state of a scan over components for one point: maximum s1 (index
-// k1, bound e1), den = sum_j 2^(s_j - s1), eb = sum_j 2^(s_j - s1) e_j, and
-// ub = the largest s_j + 2 e_j over the components other than k1.
+// Running state of a scan over components for one point: the maximum s1 and
+// its index k1, the reference m (s1 - kFlatLag <= m <= s1) and
+// den = sum_j 2^(s_j - m).
 struct FlatState {
-  float s1, e1, den, eb, ub;
+  double s1, m, den;
   int k1;
 };
 
 __device__ __forceinline__ void flat_init(FlatState& a) {
-  a.s1 = -__FLT_MAX__;
-  a.e1 = 0.f;
-  a.den = 0.f;
-  a.eb = 0.f;
-  a.ub = -INFINITY;
+  a.s1 = -INFINITY;
+  a.m = -INFINITY;
+  a.den = 0.0;
   a.k1 = -1;
 }
 
-__device__ __forceinline__ void flat_add(FlatState& a, float s, float e, int j) {
-  const bool up = s > a.s1;  // strict: the lower index stays on equal FP32 scores
-  const float r = __builtin_amdgcn_exp2f(up ? a.s1 - s : s - a.s1);
-  a.ub = fmaxf(a.ub, up ? fmaf(2.f, a.e1, a.s1) : fmaf(2.f, e, s));
-  a.den = up ? fmaf(a.den, r, 1.f) : a.den + r;
-  a.eb = up ? fmaf(a.eb, r, e) : fmaf(r, e, a.eb);
-  a.e1 = up ? e : a.e1;
+__device__ __forceinline__ void flat_add(FlatState& a, double s, int j) {
+  const bool up = s > a.s1;  // strict: the lower index stays on equal scores
   a.k1 = up ? j : a.k1;
   a.s1 = up ? s : a.s1;
+  const bool live = s > -INFINITY;
+  const double d = s - a.m;  // +inf before the first live component
+  const bool move = live && !(d <= kFlatLag);
+  const double e = (double)__builtin_amdgcn_exp2f((float)(move ? -d : d));
+  a.den = move ? fma(a.den, e, 1.0) : (live ? a.den + e : a.den);
+  a.m = move ? s : a.m;
 }
 
 // a <- a merged with b, where b holds components of higher index than a
 __device__ __forceinline__ void flat_merge(FlatState& a, const FlatState& b) {
   const bool up = b.s1 > a.s1;
-  const float ws = up ? b.s1 : a.s1, we = up ? b.e1 : a.e1, wd = up ? b.den : a.den, wb = up ? b.eb : a.eb;
-  const float ls = up ? a.s1 : b.s1, le = up ? a.e1 : b.e1, ld = up ? a.den : b.den, lb = up ? a.eb : b.eb;
-  const int wk = up ? b.k1 : a.k1;
-  const float r = __builtin_amdgcn_exp2f(ls - ws);
-  a.ub = fmaxf(fmaxf(a.ub, b.ub), fmaf(2.f, le, ls));
-  a.den = fmaf(ld, r, wd);
-  a.eb = fmaf(lb, r, wb);
-  a.s1 = ws;
-  a.e1 = we;
-  a.k1 = wk;
+  a.k1 = up ? b.k1 : a.k1;
+  a.s1 = up ? b.s1 : a.s1;
+  const double m = fmax(a.m, b.m);
+  const double ra = a.m > -INFINITY ? (double)__builtin_amdgcn_exp2f((float)(a.m - m)) : 0.0;
+  const double rb = b.m > -INFINITY ? (double)__builtin_amdgcn_exp2f((float)(b.m - m)) : 0.0;
+  a.den = fma(a.den, ra, b.den * rb);
+  a.m = m;
 }
 
 // Grid (tiles, sub-blocks): block (x, y) takes the 64 P points of tile x from
 // tl.start + 64 P y.  Its 4 waves each scan a quarter of the components for
-// all of those points (P per lane), the quarter staged through LDS and read
-// as broadcasts; the four partial states are merged in LDS in component
-// order, and the first 64 P threads finish one point each.
+// all of those points (P per lane), reading the records with scalar loads;
+// the four partial states are merged in LDS in component order, and the
+// first 64 P threads finish one point each.
 template <int P>
 __global__ __launch_bounds__(256) void flat_estep_kernel(const float* __restrict__ xs, const float* __restrict__ ys,
                                                          const float* __restrict__ zs, const Tile* __restrict__ tiles,
                                                          const TreeDev* __restrict__ trees,
-                                                         const NodeF* __restrict__ ftab,
-                                                         const NodeS* __restrict__ fs,
+                                                         const NodeR* __restrict__ ftab,
                                                          const PoseState* __restrict__ st, double* bins,
                                                          int32_t* stop_out, float* gamma_out,
                                                          const int* __restrict__ perm, int level) {
@@ -561,8 +530,7 @@ __global__ __launch_bounds__(256) void flat_estep_kernel(const float* __restrict
   const int64_t nb = T.node_base;
   const int64_t g0 = nb + lvl_off(level);
   const int J = 8 << (3 * level);
-  const NodeF* __restrict__ Fg = ftab + g0;
-  const NodeS* __restrict__ Sg = fs + g0;
+  const NodeR* __restrict__ Fg = ftab + g0;
   const double R0 = st[pair].R[0], R1 = st[pair].R[1], R2 = st[pair].R[2], R3 = st[pair].R[3],
                R4 = st[pair].R[4], R5 = st[pair].R[5], R6 = st[pair].R[6], R7 = st[pair].R[7],
                R8 = st[pair].R[8], t0 = st[pair].t[0], t1 = st[pair].t[1], t2 = st[pair].t[2];
@@ -582,55 +550,33 @@ __global__ __launch_bounds__(256) void flat_estep_kernel(const float* __restrict
   }
   const int per = J / kFlatSlices;
   const int jb = wv * per;
-  // each wave stages its slice through LDS in chunks of kFlatChunk records
-  // and reads them as broadcasts; dead components carry c = -inf
-  __shared__ NodeF lds[kFlatSlices][kFlatChunk];
-  for (int c0 = 0; c0 < per; c0 += kFlatChunk) {
-    const int nc = per - c0 < kFlatChunk ? per - c0 : kFlatChunk;
-    for (int r = lane; r < nc; r += 64) {
-      const float4* s = reinterpret_cast<const float4*>(&Fg[jb + c0 + r]);
-      float4* d = reinterpret_cast<float4*>(&lds[wv][r]);
-      d[0] = s[0]; d[1] = s[1]; d[2] = s[2]; d[3] = s[3];
-    }
-    __syncthreads();
+  const ConstNodeR* Cg = (const ConstNodeR*)(Fg + jb);
 #pragma unroll 2
-    for (int jj = 0; jj < nc; ++jj) {
-      const NodeF& C = lds[wv][jj];
+  for (int jj = 0; jj < per; ++jj) {
+    const ConstNodeR& C = Cg[jj];
 #pragma unroll
-      for (int q = 0; q < P; ++q) {
-        float qq, m;
-        const float s = score32(C, px[q], py[q], pz[q], qq, m);
-        flat_add(S[q], s, score_err(C, qq, m), jb + c0 + jj);
-      }
-    }
-    __syncthreads();
+    for (int q = 0; q < P; ++q) flat_add(S[q], C.c - quad_r(C, px[q], py[q], pz[q]), jb + jj);
   }
-  __shared__ float ms[kFlatSlices][5][NP];
+  __shared__ double ms[kFlatSlices][3][NP];
   __shared__ int mk[kFlatSlices][NP];
 #pragma unroll
   for (int q = 0; q < P; ++q) {
     const int r = lane + 64 * q;
     ms[wv][0][r] = S[q].s1;
-    ms[wv][1][r] = S[q].e1;
+    ms[wv][1][r] = S[q].m;
     ms[wv][2][r] = S[q].den;
-    ms[wv][3][r] = S[q].eb;
-    ms[wv][4][r] = S[q].ub;
     mk[wv][r] = S[q].k1;
   }
   __syncthreads();
   const int r = (int)threadIdx.x;
   if (r >= NP) return;  // whole waves leave; no barrier follows
   FlatState A;
-  {
-    A.s1 = ms[0][0][r]; A.e1 = ms[0][1][r]; A.den = ms[0][2][r]; A.eb = ms[0][3][r]; A.ub = ms[0][4][r];
-    A.k1 = mk[0][r];
+  A.s1 = ms[0][0][r]; A.m = ms[0][1][r]; A.den = ms[0][2][r]; A.k1 = mk[0][r];
 #pragma unroll
-    for (int w = 1; w < kFlatSlices; ++w) {
-      FlatState B;
-      B.s1 = ms[w][0][r]; B.e1 = ms[w][1][r]; B.den = ms[w][2][r]; B.eb = ms[w][3][r]; B.ub = ms[w][4][r];
-      B.k1 = mk[w][r];
-      flat_merge(A, B);
-    }
+  for (int w = 1; w < kFlatSlices; ++w) {
+    FlatState B;
+    B.s1 = ms[w][0][r]; B.m = ms[w][1][r]; B.den = ms[w][2][r]; B.k1 = mk[w][r];
+    flat_merge(A, B);
   }
   const int i = start + r;
   const bool valid = i < end;
@@ -641,38 +587,14 @@ __global__ __launch_bounds__(256) void flat_estep_kernel(const float* __restrict
     const double p0 = R0 * z0 + R1 * z1 + R2 * z2 + t0;
     const double p1 = R3 * z0 + R4 * z1 + R5 * z2 + t1;
     const double p2 = R6 * z0 + R7 * z1 + R8 * z2 + t2;
-    int k1 = A.k1;
-    float s1 = A.s1, eb = A.eb;
-    double sk64 = 0.0;
-    bool have64 = false;
-    if (A.ub >= s1 - 2.f * A.e1) {  // another component may win in exact arithmetic
-      int kb;
-      sk64 = flat_argmax64(Sg, Fg, J, p0, p1, p2, kb);
-      have64 = true;
-      if (kb != k1) {
-        k1 = kb;
-        float q, m;
-        s1 = score32(Fg[k1], p0, p1, p2, q, m);
-        eb = INFINITY;  // the FP32 sums refer to the old winner: recompute gamma in FP64
-      }
-    }
-    const float gbound = 0.6931472f * (eb + A.e1 * (A.den - 2.f)) / A.den;
-    if (gbound > kFlatGammaTol) {
-      if (!have64) sk64 = score64(Sg[k1], p0, p1, p2);
-      gam = flat_gamma64(Sg, Fg, J, k1, sk64, s1, p0, p1, p2);
-    } else {
-      gam = 1.0f / A.den;
-    }
-    g = g0 + k1;
-    const NodeS& nd = Sg[k1];
-    const double e0 = p0 - nd.mu[0], e1 = p1 - nd.mu[1], e2 = p2 - nd.mu[2];
-    d0 = (float)e0;
-    d1 = (float)e1;
-    d2 = (float)e2;
-    const double w0 = nd.winv[0] * e0;
-    const double w1 = nd.winv[1] * e0 + nd.winv[2] * e1;
-    const double w2 = nd.winv[3] * e0 + nd.winv[4] * e1 + nd.winv[5] * e2;
-    dm2 = (float)(w0 * w0 + w1 * w1 + w2 * w2);
+    // the winner's share: 2^(s1 - m) / den, 0 <= s1 - m <= kFlatLag
+    gam = (float)((double)__builtin_amdgcn_exp2f((float)(A.s1 - A.m)) / A.den);
+    g = g0 + A.k1;
+    const NodeR& nd = Fg[A.k1];
+    d0 = (float)(p0 - nd.mu[0]);
+    d1 = (float)(p1 - nd.mu[1]);
+    d2 = (float)(p2 - nd.mu[2]);
+    dm2 = (float)(quad_r(nd, p0, p1, p2) * kTwoLn2);
   }
   if (valid) {
     const int oi = perm ? perm[i] : i;
@@ -939,19 +861,18 @@ void launch_descend(const float* xs, const float* ys, const float* zs, const Til
 #undef HGMM_DESCEND
 }
 
-void launch_flat_table(const NodeF* tab, const NodeD* nodes, NodeF* ft, NodeS* fs, int64_t n, hipStream_t s) {
+void launch_flat_table(const NodeF* tab, const NodeD* nodes, NodeR* fr, int64_t n, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(flat_table_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tab, nodes, ft, fs, n);
+  hipLaunchKernelGGL(flat_table_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tab, nodes, fr, n);
 }
 
 void launch_flat_estep(const float* xs, const float* ys, const float* zs, const Tile* tiles, int ntiles,
-                       int tile_points, const TreeDev* trees, const NodeF* tab, const NodeS* nodes,
-                       const PoseState* st, double* bins, int32_t* stop_out, float* gamma_out, const int* perm,
-                       int level, hipStream_t s) {
+                       int tile_points, const TreeDev* trees, const NodeR* ftab, const PoseState* st, double* bins,
+                       int32_t* stop_out, float* gamma_out, const int* perm, int level, hipStream_t s) {
   constexpr int P = 1;
   const unsigned nsub = (unsigned)((tile_points + 64 * P - 1) / (64 * P));
-  hipLaunchKernelGGL((flat_estep_kernel<P>), dim3(ntiles, nsub), dim3(256), 0, s, xs, ys, zs, tiles, trees, tab,
-                     nodes, st, bins, stop_out, gamma_out, perm, level);
+  hipLaunchKernelGGL((flat_estep_kernel<P>), dim3(ntiles, nsub), dim3(256), 0, s, xs, ys, zs, tiles, trees, ftab, st,
+                     bins, stop_out, gamma_out, perm, level);
 }
 
 void launch_fold_bins(const TreeDev* trees, const FixBin* fbins, double* bins, int npairs, hipStream_t s) {
