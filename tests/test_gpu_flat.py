@@ -3,10 +3,11 @@ the FP64 oracle's single-level E-step and registration on the same tree.
 
 Tolerances as for the tree descent: the chosen component exact except points
 whose oracle top-2 gap is below 1e-6 (natural-log units), responsibilities
-within 2e-5 relative (the kernel recomputes a posterior in FP64 when its FP32
-rounding bound exceeds 1e-5), per-node moments within 1e-5, poses within
-1e-4 rad and 1e-4 * extent.  Levels 0-2 run the LDS-resident kernel (the whole
-level staged once per block), level 3 (4096 components) the chunked one.
+within 2e-5 relative (the kernel scores in FP64 and forms the posterior from
+FP32 exp2 of FP64 differences of at most 8 in log2 units, about 1e-6
+relative), per-node moments within 1e-5, poses within 1e-4 rad and
+1e-4 * extent.  Levels 0-2 and level 3 (4096 components, several scalar-load
+rounds per wave) are both covered.
 """
 
 import math
