@@ -77,6 +77,10 @@ struct TreeHost {
 struct hgmm_forest_s {
   int device = 0;
   std::vector<TreeHost> trees;
+  // host planner's scratch (jobs of a level, a tiled job's slot), kept with
+  // the handle so that a construction reuses their memory
+  std::vector<Job> plan_jobs;
+  std::vector<int> plan_slot;
   TreeDev* d_trees = nullptr;
   size_t cap_trees = 0;
   NodeD* d_nodes = nullptr;
@@ -594,8 +598,8 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
   const float* cz = in.zs;
   const int* cperm = nullptr;
   int ping = 0;
-  std::vector<Job> jobs;
-  jobs.reserve(1024);
+  std::vector<Job>& jobs = f->plan_jobs;
+  jobs.reserve((size_t)Ly.max_jobs);
 
   std::vector<std::array<int, 7>> hint((size_t)Lmax, std::array<int, 7>{0, 0, 0, 0, 0, 0, 0});
   for (int l = 0; l < Lmax; ++l) {
@@ -651,7 +655,8 @@ static int run_build(hgmm_forest_s* f, BuildInput in, const hgmm_build_params& p
     for (int c = 0; c < 4; ++c) cls_off[c + 1] = cls_off[c] + cls_n[c];
     // slot of each tiled job among the tiled jobs (its child records in the
     // ping-pong buffers and its block in the final M-step)
-    std::vector<int> slot_of((size_t)njobs, 0);
+    std::vector<int>& slot_of = f->plan_slot;
+    slot_of.assign((size_t)njobs, 0);
     {
       int fill[4] = {cls_off[0], cls_off[1], cls_off[2], cls_off[3]};
       for (int j = 0; j < njobs; ++j) {
