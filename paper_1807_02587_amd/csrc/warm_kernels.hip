@@ -103,7 +103,8 @@ __global__ void f32_to_bf16_kernel(const float* __restrict__ a, uint16_t* b, int
 // GEMM: C[M x N] (FP32) = op(A)[M x K] * op(B)[K x N], bf16 operands, FP32
 // accumulation on v_mfma_f32_16x16x32_bf16.  op(A)(i,k) = TA ? A[k*lda+i] :
 // A[i*lda+k]; op(B)(k,j) = TB ? B[j*ldb+k] : B[k*ldb+j].  beta != 0 adds
-// into C.  Block tile 64x64x32, 4 waves of 32x32.
+// into C.  Block tile 64x64x32, 4 waves of 32x32; the tiles are staged with
+// 16-byte loads along each operand's contiguous dimension.
 // ---------------------------------------------------------------------------
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
@@ -114,31 +115,64 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, con
                                                         const uint16_t* __restrict__ B, int ldb, float* C, int ldc,
                                                         float beta) {
   constexpr int BM = 64, BN = 64, BK = 32, PAD = 8;
+  static_assert(BM * BK == 8 * 256 && BN * BK == 8 * 256, "one 8-element chunk of each tile per thread");
   __shared__ __attribute__((aligned(16))) uint16_t As[BM][BK + PAD];   // row i, k
   __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][BK + PAD];   // column j, k (transposed)
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+  // 16-byte loads need 16-byte aligned rows of whole 8-element chunks
+  const bool vecA = (lda % 8) == 0 && ((uintptr_t)A & 15u) == 0u;
+  const bool vecB = (ldb % 8) == 0 && ((uintptr_t)B & 15u) == 0u;
   f32x4_t acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < K; k0 += BK) {
-    // stage the tiles (8 elements per thread for each operand)
-    for (int e = tid; e < BM * BK; e += 256) {
-      int i, k;
-      if (TA) { i = e % BM; k = e / BM; } else { i = e / BK; k = e % BK; }
-      const int gi = m0 + i, gk = k0 + k;
-      uint16_t v = 0;
-      if (gi < M && gk < K) v = TA ? A[(size_t)gk * lda + gi] : A[(size_t)gi * lda + gk];
-      As[i][k] = v;
-    }
-    for (int e = tid; e < BN * BK; e += 256) {
-      int j, k;
-      if (TB) { j = e / BK; k = e % BK; } else { j = e % BN; k = e / BN; }
-      const int gj = n0 + j, gk = k0 + k;
-      uint16_t v = 0;
-      if (gj < N && gk < K) v = TB ? B[(size_t)gj * ldb + gk] : B[(size_t)gk * ldb + gj];
-      Bs[j][k] = v;
+    // stage the tiles: each thread moves one chunk of 8 elements of each
+    // operand along its contiguous dimension, with one 16-byte load when the
+    // chunk is whole and aligned, element loads at the edges
+    {
+      union { uint4 q; uint16_t h[8]; } u;
+      if (!TA) {  // A row-major: 8 consecutive k of row i
+        const int i = tid >> 2, kc = (tid & 3) * 8, gi = m0 + i, gk = k0 + kc;
+        if (vecA && gi < M && gk + 8 <= K) {
+          u.q = *reinterpret_cast<const uint4*>(A + (size_t)gi * lda + gk);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) u.h[e] = (gi < M && gk + e < K) ? A[(size_t)gi * lda + gk + e] : (uint16_t)0;
+        }
+        *reinterpret_cast<uint4*>(&As[i][kc]) = u.q;
+      } else {  // A stored transposed: 8 consecutive i of column k
+        const int k = tid >> 3, ic = (tid & 7) * 8, gk = k0 + k, gi = m0 + ic;
+        if (vecA && gk < K && gi + 8 <= M) {
+          u.q = *reinterpret_cast<const uint4*>(A + (size_t)gk * lda + gi);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) u.h[e] = (gk < K && gi + e < M) ? A[(size_t)gk * lda + gi + e] : (uint16_t)0;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) As[ic + e][k] = u.h[e];
+      }
+      if (TB) {  // B stored transposed: 8 consecutive k of column j
+        const int j = tid >> 2, kc = (tid & 3) * 8, gj = n0 + j, gk = k0 + kc;
+        if (vecB && gj < N && gk + 8 <= K) {
+          u.q = *reinterpret_cast<const uint4*>(B + (size_t)gj * ldb + gk);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) u.h[e] = (gj < N && gk + e < K) ? B[(size_t)gj * ldb + gk + e] : (uint16_t)0;
+        }
+        *reinterpret_cast<uint4*>(&Bs[j][kc]) = u.q;
+      } else {  // B row-major: 8 consecutive j of row k
+        const int k = tid >> 3, jc = (tid & 7) * 8, gk = k0 + k, gj = n0 + jc;
+        if (vecB && gk < K && gj + 8 <= N) {
+          u.q = *reinterpret_cast<const uint4*>(B + (size_t)gk * ldb + gj);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) u.h[e] = (gk < K && gj + e < N) ? B[(size_t)gk * ldb + gj + e] : (uint16_t)0;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Bs[jc + e][k] = u.h[e];
+      }
     }
     __syncthreads();
     // A operand: row (lane % 16), k = 8*(lane/16) .. +7; B operand: column (lane % 16), same k
@@ -191,13 +225,27 @@ __global__ void gelu_back_kernel(const float* __restrict__ dH, const float* __re
   if (dZf) dZf[i] = g;
 }
 
-// db[j] = sum_i dZ[i, j] (fixed order per column)
-__global__ void colsum_kernel(const float* __restrict__ dZ, int M, int N, float* db) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
+// db[j] = sum_i dZ[i, j] in a fixed order: a block of kColsumThreads takes 64
+// columns; lane c of each wave reads column c of every 16th row (so a wave
+// reads 64 consecutive columns of a row, coalesced), starting at its row
+// group, and the 16 row-group sums of a column are added in group order.
+constexpr int kColsumThreads = 1024;
+constexpr int kColsumGroups = kColsumThreads / 64;
+__global__ __launch_bounds__(kColsumThreads) void colsum_kernel(const float* __restrict__ dZ, int M, int N,
+                                                                float* db) {
+  __shared__ float part[kColsumGroups][64];
+  const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + c;
   float s = 0.f;
-  for (int i = 0; i < M; ++i) s += dZ[(size_t)i * N + j];
-  db[j] = s;
+  if (j < N)
+    for (int i = rg; i < M; i += kColsumGroups) s += dZ[(size_t)i * N + j];
+  part[rg][c] = s;
+  __syncthreads();
+  if (rg == 0 && j < N) {
+    float t = part[0][c];
+    for (int g = 1; g < kColsumGroups; ++g) t += part[g][c];
+    db[j] = t;
+  }
 }
 
 // head loss: L = mean_p sum_c w_c (y - t)^2 / 2 (w = 1 for the 6D part, wt for
@@ -339,7 +387,8 @@ void launch_gelu_back(const float* dH, const float* Z, int64_t n, uint16_t* dZ, 
 }
 
 void launch_colsum(const float* dZ, int M, int N, float* db, hipStream_t s) {
-  hipLaunchKernelGGL(colsum_kernel, dim3(nblk(N, 256)), dim3(256), 0, s, dZ, M, N, db);
+  if (N <= 0) return;
+  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((N + 63) / 64)), dim3(kColsumThreads), 0, s, dZ, M, N, db);
 }
 
 void launch_head_loss(const float* Y, const float* T, int P, float wt, float* dY, uint16_t* dYb, float* rowloss,
