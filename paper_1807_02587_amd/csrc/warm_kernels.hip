@@ -225,17 +225,18 @@ __global__ void gelu_back_kernel(const float* __restrict__ dH, const float* __re
   if (dZf) dZf[i] = g;
 }
 
-// db[j] = sum_i dZ[i, j] in a fixed order: a block of kColsumThreads takes 64
-// columns; lane c of each wave reads column c of every 16th row (so a wave
-// reads 64 consecutive columns of a row, coalesced), starting at its row
-// group, and the 16 row-group sums of a column are added in group order.
+// db[j] = sum_i dZ[i, j] in a fixed order: a block of kColsumThreads takes
+// kColsumCols columns; thread (row group g, column c) sums column c over the
+// rows g, g + kColsumGroups, ... (a wave reads 4 rows of 16 consecutive
+// columns at a time), and the group sums of a column are added in group order.
 constexpr int kColsumThreads = 1024;
-constexpr int kColsumGroups = kColsumThreads / 64;
+constexpr int kColsumCols = 16;
+constexpr int kColsumGroups = kColsumThreads / kColsumCols;
 __global__ __launch_bounds__(kColsumThreads) void colsum_kernel(const float* __restrict__ dZ, int M, int N,
                                                                 float* db) {
-  __shared__ float part[kColsumGroups][64];
-  const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
-  const int j = blockIdx.x * 64 + c;
+  __shared__ float part[kColsumGroups][kColsumCols];
+  const int c = threadIdx.x % kColsumCols, rg = threadIdx.x / kColsumCols;
+  const int j = blockIdx.x * kColsumCols + c;
   float s = 0.f;
   if (j < N)
     for (int i = rg; i < M; i += kColsumGroups) s += dZ[(size_t)i * N + j];
@@ -388,7 +389,8 @@ void launch_gelu_back(const float* dH, const float* Z, int64_t n, uint16_t* dZ, 
 
 void launch_colsum(const float* dZ, int M, int N, float* db, hipStream_t s) {
   if (N <= 0) return;
-  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((N + 63) / 64)), dim3(kColsumThreads), 0, s, dZ, M, N, db);
+  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((N + kColsumCols - 1) / kColsumCols)), dim3(kColsumThreads), 0, s,
+                     dZ, M, N, db);
 }
 
 void launch_head_loss(const float* Y, const float* T, int P, float wt, float* dY, uint16_t* dYb, float* rowloss,
