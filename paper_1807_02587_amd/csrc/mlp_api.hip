@@ -18,6 +18,7 @@
 using namespace hgmm;
 
 static const int kDims[5] = {1280, 512, 512, 512, 9};
+constexpr int kGradSlices = 8;  // most slices of the weight gradients' reduction
 
 struct hgmm_mlp_s {
   float* w[4] = {};     // FP32 master weights [in x out]
@@ -39,6 +40,7 @@ struct hgmm_mlp_s {
   uint16_t* dZb = nullptr;
   float* dY = nullptr;
   uint16_t* dYb = nullptr;
+  float* gpart = nullptr;   // partial weight gradients of the reduction slices
   float* rowloss = nullptr;
   float* h_loss = nullptr;  // pinned
 };
@@ -67,9 +69,10 @@ static void mlp_free_acts(hgmm_mlp_s* m) {
   (void)hipFree(m->dY);
   (void)hipFree(m->dYb);
   (void)hipFree(m->rowloss);
+  (void)hipFree(m->gpart);
   if (m->h_loss) (void)hipHostFree(m->h_loss);
   m->X = nullptr; m->dH = nullptr; m->dZf = nullptr; m->dZb = nullptr; m->dY = nullptr; m->dYb = nullptr;
-  m->rowloss = nullptr; m->h_loss = nullptr;
+  m->rowloss = nullptr; m->h_loss = nullptr; m->gpart = nullptr;
   m->cap = 0;
 }
 
@@ -90,6 +93,7 @@ static int mlp_reserve(hgmm_mlp_s* m, int P) {
   rc |= dalloc(m->dY, (int64_t)P * 9);
   rc |= dalloc(m->dYb, (int64_t)P * 9);
   rc |= dalloc(m->rowloss, P);
+  rc |= dalloc(m->gpart, (int64_t)kGradSlices * 1280 * 512);
   if (hipHostMalloc((void**)&m->h_loss, sizeof(float) * (size_t)P, hipHostMallocDefault) != hipSuccess) rc = 1;
   if (rc) { mlp_free_acts(m); return hgmm_fail(HGMM_ENOMEM, "activation allocation failed"); }
   m->cap = P;
@@ -116,8 +120,16 @@ static void mlp_backward_core(hgmm_mlp_s* m, const float* T, int P, float wt, hi
   for (int l = 3; l >= 0; --l) {
     const int K = kDims[l], N = kDims[l + 1];
     const uint16_t* Hin = (l == 0) ? m->X : m->H[l];
-    // gW = Hin^T dZ  [K x N]
-    launch_gemm(true, false, K, N, P, Hin, K, dZ, N, m->gw[l], N, 0.f, s);
+    // gW = Hin^T dZ  [K x N]: a reduction over the P rows, split into up
+    // to kGradSlices parts of at least 512 rows whose partial products are
+    // added in slice order
+    const int slices = std::min(kGradSlices, std::max(1, P / 512));
+    if (slices > 1) {
+      launch_gemm_slices(true, false, K, N, P, Hin, K, dZ, N, m->gpart, N, 0.f, slices, s);
+      launch_sum_slices(m->gpart, gemm_slices_used(P, slices), (int64_t)K * N, m->gw[l], s);
+    } else {
+      launch_gemm(true, false, K, N, P, Hin, K, dZ, N, m->gw[l], N, 0.f, s);
+    }
     launch_colsum(dZf, P, N, m->gb[l], s);
     if (l == 0) break;
     // dH = dZ W^T [P x K], then through GELU of layer l-1

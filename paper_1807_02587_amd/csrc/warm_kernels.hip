@@ -113,13 +113,17 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, const uint16_t* __restrict__ A, int lda,
                                                         const uint16_t* __restrict__ B, int ldb, float* C, int ldc,
-                                                        float beta) {
+                                                        float beta, int kslice, size_t cslice) {
   constexpr int BM = 64, BN = 64, BK = 32, PAD = 8;
   static_assert(BM * BK == 8 * 256 && BN * BK == 8 * 256, "one 8-element chunk of each tile per thread");
   __shared__ __attribute__((aligned(16))) uint16_t As[BM][BK + PAD];   // row i, k
   __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][BK + PAD];   // column j, k (transposed)
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  // slice z of the reduction: k in [kb, ke), written to C + z * cslice
+  const int kb = (int)blockIdx.z * kslice;
+  const int ke = K - kb < kslice ? K : kb + kslice;
+  C += (size_t)blockIdx.z * cslice;
   const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
   // 16-byte loads need 16-byte aligned rows of whole 8-element chunks
   const bool vecA = (lda % 8) == 0 && ((uintptr_t)A & 15u) == 0u;
@@ -127,7 +131,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, con
   f32x4_t acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  for (int k0 = kb; k0 < ke; k0 += BK) {
     // stage the tiles: each thread moves one chunk of 8 elements of each
     // operand along its contiguous dimension, with one 16-byte load when the
     // chunk is whole and aligned, element loads at the edges
@@ -135,40 +139,40 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, con
       union { uint4 q; uint16_t h[8]; } u;
       if (!TA) {  // A row-major: 8 consecutive k of row i
         const int i = tid >> 2, kc = (tid & 3) * 8, gi = m0 + i, gk = k0 + kc;
-        if (vecA && gi < M && gk + 8 <= K) {
+        if (vecA && gi < M && gk + 8 <= ke) {
           u.q = *reinterpret_cast<const uint4*>(A + (size_t)gi * lda + gk);
         } else {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) u.h[e] = (gi < M && gk + e < K) ? A[(size_t)gi * lda + gk + e] : (uint16_t)0;
+          for (int e = 0; e < 8; ++e) u.h[e] = (gi < M && gk + e < ke) ? A[(size_t)gi * lda + gk + e] : (uint16_t)0;
         }
         *reinterpret_cast<uint4*>(&As[i][kc]) = u.q;
       } else {  // A stored transposed: 8 consecutive i of column k
         const int k = tid >> 3, ic = (tid & 7) * 8, gk = k0 + k, gi = m0 + ic;
-        if (vecA && gk < K && gi + 8 <= M) {
+        if (vecA && gk < ke && gi + 8 <= M) {
           u.q = *reinterpret_cast<const uint4*>(A + (size_t)gk * lda + gi);
         } else {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) u.h[e] = (gk < K && gi + e < M) ? A[(size_t)gk * lda + gi + e] : (uint16_t)0;
+          for (int e = 0; e < 8; ++e) u.h[e] = (gk < ke && gi + e < M) ? A[(size_t)gk * lda + gi + e] : (uint16_t)0;
         }
 #pragma unroll
         for (int e = 0; e < 8; ++e) As[ic + e][k] = u.h[e];
       }
       if (TB) {  // B stored transposed: 8 consecutive k of column j
         const int j = tid >> 2, kc = (tid & 3) * 8, gj = n0 + j, gk = k0 + kc;
-        if (vecB && gj < N && gk + 8 <= K) {
+        if (vecB && gj < N && gk + 8 <= ke) {
           u.q = *reinterpret_cast<const uint4*>(B + (size_t)gj * ldb + gk);
         } else {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) u.h[e] = (gj < N && gk + e < K) ? B[(size_t)gj * ldb + gk + e] : (uint16_t)0;
+          for (int e = 0; e < 8; ++e) u.h[e] = (gj < N && gk + e < ke) ? B[(size_t)gj * ldb + gk + e] : (uint16_t)0;
         }
         *reinterpret_cast<uint4*>(&Bs[j][kc]) = u.q;
       } else {  // B row-major: 8 consecutive j of row k
         const int k = tid >> 3, jc = (tid & 7) * 8, gk = k0 + k, gj = n0 + jc;
-        if (vecB && gk < K && gj + 8 <= N) {
+        if (vecB && gk < ke && gj + 8 <= N) {
           u.q = *reinterpret_cast<const uint4*>(B + (size_t)gk * ldb + gj);
         } else {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) u.h[e] = (gk < K && gj + e < N) ? B[(size_t)gk * ldb + gj + e] : (uint16_t)0;
+          for (int e = 0; e < 8; ++e) u.h[e] = (gk < ke && gj + e < N) ? B[(size_t)gk * ldb + gj + e] : (uint16_t)0;
         }
 #pragma unroll
         for (int e = 0; e < 8; ++e) Bs[jc + e][k] = u.h[e];
@@ -372,11 +376,37 @@ void launch_f32_to_bf16(const float* a, uint16_t* b, int64_t n, hipStream_t s) {
 
 void launch_gemm(bool ta, bool tb, int M, int N, int K, const uint16_t* A, int lda, const uint16_t* B, int ldb,
                  float* C, int ldc, float beta, hipStream_t s) {
-  dim3 grid((N + 63) / 64, (M + 63) / 64);
-  if (!ta && !tb) hipLaunchKernelGGL((gemm_bf16_kernel<false, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, beta);
-  else if (!ta && tb) hipLaunchKernelGGL((gemm_bf16_kernel<false, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, beta);
-  else if (ta && !tb) hipLaunchKernelGGL((gemm_bf16_kernel<true, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, beta);
-  else hipLaunchKernelGGL((gemm_bf16_kernel<true, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, beta);
+  launch_gemm_slices(ta, tb, M, N, K, A, lda, B, ldb, C, ldc, beta, 1, s);
+}
+
+void launch_gemm_slices(bool ta, bool tb, int M, int N, int K, const uint16_t* A, int lda, const uint16_t* B, int ldb,
+                        float* C, int ldc, float beta, int slices, hipStream_t s) {
+  // slices of the reduction in whole 32-element K steps (16-byte loads stay
+  // aligned); slice z writes C + z * M * ldc
+  const int steps = (K + 31) / 32;
+  const int per = slices > 1 ? (steps + slices - 1) / slices : steps;
+  const int nz = slices > 1 ? (steps + per - 1) / per : 1;
+  const int kslice = slices > 1 ? 32 * per : K;
+  const size_t cslice = (size_t)M * (size_t)ldc;
+  dim3 grid((N + 63) / 64, (M + 63) / 64, (unsigned)(nz > 0 ? nz : 1));
+  if (!ta && !tb) hipLaunchKernelGGL((gemm_bf16_kernel<false, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, beta, kslice, cslice);
+  else if (!ta && tb) hipLaunchKernelGGL((gemm_bf16_kernel<false, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, beta, kslice, cslice);
+  else if (ta && !tb) hipLaunchKernelGGL((gemm_bf16_kernel<true, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, beta, kslice, cslice);
+  else hipLaunchKernelGGL((gemm_bf16_kernel<true, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, beta, kslice, cslice);
+}
+
+// out[e] = sum over the slices of part[z * n + e], in slice order
+__global__ void sum_slices_kernel(const float* __restrict__ part, int slices, int64_t n, float* out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  float t = part[e];
+  for (int z = 1; z < slices; ++z) t += part[(size_t)z * (size_t)n + (size_t)e];
+  out[e] = t;
+}
+
+void launch_sum_slices(const float* part, int slices, int64_t n, float* out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(sum_slices_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, part, slices, n, out);
 }
 
 void launch_bias_act(float* Z, const float* bias, int M, int N, uint16_t* H, int act, hipStream_t s) {

@@ -62,9 +62,13 @@ def _params(seed):
     return np.concatenate(p).astype(np.float32)
 
 
-def test_mlp_forward_and_gradients_vs_oracle(hg):
+@pytest.mark.parametrize("P", [33, 1100, 4100])
+def test_mlp_forward_and_gradients_vs_oracle(hg, P):
+    """Forward and every gradient element against the FP64 oracle.  From 1024
+    rows the weight gradients' reduction over the rows is split into slices of
+    at least 512 rows (2 slices at 1100 rows, 8 at 4100, both with a shorter
+    last slice) whose partial products are added in slice order."""
     rng = np.random.default_rng(3)
-    P = 33
     params = _params(4)
     net = hg.MLP(seed=1)
     net.set_params(params)
@@ -75,7 +79,7 @@ def test_mlp_forward_and_gradients_vs_oracle(hg):
     Y = net.forward(Xg).cpu().numpy()
     Yo, _ = omlp.forward(params.astype(np.float64), X.astype(np.float64), bf16=True)
     ey = np.abs(Y - Yo).max() / np.abs(Yo).max()
-    log(f"[mlp] forward rel err {ey:.2e}")
+    log(f"[mlp] P={P} forward rel err {ey:.2e}")
     assert ey < 1e-2
     g, loss = net.backward(Xg, Tg, trans_weight=0.5)
     lo, go = omlp.loss_and_grad(params.astype(np.float64), X.astype(np.float64), T.astype(np.float64),
