@@ -48,7 +48,12 @@ class WarmConfig:
 
 
 def features_for(src_forest, tgt_forest, B, cfg: WarmConfig, tgt_first: int = 0):
-    """Features of source trees 0..B-1 and target trees tgt_first..tgt_first+B-1."""
+    """Features of source trees 0..B-1 and target trees tgt_first..tgt_first+B-1
+    (one library call when both are in one forest)."""
+    if src_forest is tgt_forest:
+        ids = np.concatenate([np.arange(B), np.arange(tgt_first, tgt_first + B)])
+        f, fr = hg.hgmm_warm_features(src_forest, ids, cfg.reg_eps)
+        return torch.cat([f[:B], f[B:]], dim=1).contiguous(), fr[:B], fr[B:]
     fs, frs = hg.hgmm_warm_features(src_forest, np.arange(B), cfg.reg_eps)
     ft, frt = hg.hgmm_warm_features(tgt_forest, np.arange(tgt_first, tgt_first + B), cfg.reg_eps)
     return torch.cat([fs, ft], dim=1).contiguous(), frs, frt
