@@ -6,7 +6,7 @@ ceil(log8(N / 50))) registered in one batch with the learned warm start and
 the plain-likelihood fallback: the source forest, the 2-level target forest,
 the level-1 features, the network and its head, the registration capped at
 two levels and then over the whole tree, the plain method from the identity
-as the judge, and the choice per pair.  Inputs are resident in HBM.
+as the arbiter, and the choice per pair.  Inputs are resident in HBM.
 
 Prints one JSON line: pairs/s of that step and, beside it, the plain GPU form
 (one pair at a time: build + register from the identity) and the batched

@@ -361,7 +361,7 @@ int hgmm_warm_head_pose(const float *d_Y, const double *d_fr_src, const double *
 int hgmm_warm_head_target(const double *d_R, const double *d_t, const double *d_fr_src, const double *d_fr_tgt, int P,
                           float *d_T, void *stream);
 /* Warm-started registration with the plain method as the fallback and the
- * judge: pair b (target cloud b, CSR offsets, B pairs) onto tree b of the
+ * arbiter: pair b (target cloud b, CSR offsets, B pairs) onto tree b of the
  * forest, starting from R0[9 b..], t0[3 b..] (host; the head's transforms).
  * With coarse_levels > 0 and a tree deeper than that, the descent is first
  * capped at coarse_levels levels (a wider basin; a pair whose capped run

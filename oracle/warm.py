@@ -14,7 +14,7 @@ Its steps, in the order the GPU path takes them:
 * ``register_warm``: network forward (oracle.mlp), the head's pose, a
   registration of the target capped at two levels of the source tree when it
   is deeper, then the whole tree, and the plain method from the identity as
-  the judge: the result with the higher final log-likelihood is kept.
+  the arbiter: the result with the higher final log-likelihood is kept.
 """
 
 from __future__ import annotations
@@ -81,7 +81,7 @@ def initial_pose(params, src_tree: OracleTree, tgt_tree: OracleTree, reg_eps: fl
 def register_warm(params, src_tree: OracleTree, tgt_tree: OracleTree, tgt_xyz, reg_eps: float, lambda_c=0.01,
                   max_iters=30, coarse_levels=2):
     """Warm-started registration of tgt_xyz onto src_tree with the plain
-    method from the identity as the judge.  Returns the registration dict of
+    method from the identity as the arbiter.  Returns the registration dict of
     the kept run plus ``fallback`` (True when the identity start won) and the
     network's start (R0, t0)."""
     R0, t0 = initial_pose(params, src_tree, tgt_tree, reg_eps)

@@ -509,7 +509,7 @@ def hgmm_register_warm_batch(forest: Tree, xyz: torch.Tensor, offsets, R0, t0, c
                              rule: str = "plain", max_iters: int = 30, lambda_c: float = 0.01, tol_rot: float = 1e-6,
                              tol_trans_rel: float = 1e-6, ws: Workspace | None = None, stream=None) -> dict:
     """Warm-started registration of B pairs (cloud b onto tree b) from R0, t0
-    with the plain method from the identity as fallback and judge (rule
+    with the plain method from the identity as fallback and arbiter (rule
     "plain" or "identity"; see include/hgmm.h).  Returns dict(R (B,3,3), t,
     iters, loglik, status, fallback (B,) bool)."""
     xyz = _cloud(xyz)
