@@ -18,7 +18,7 @@
 using namespace hgmm;
 
 static const int kDims[5] = {1280, 512, 512, 512, 9};
-constexpr int kGradSlices = 8;  // most slices of the weight gradients' reduction
+constexpr int kGradSlices = 8;  // most slices of a GEMM reduction (weight gradients; forward of small batches)
 
 struct hgmm_mlp_s {
   float* w[4] = {};     // FP32 master weights [in x out]
@@ -100,12 +100,23 @@ static int mlp_reserve(hgmm_mlp_s* m, int P) {
   return HGMM_OK;
 }
 
-// forward from m->X (bf16, P rows); Z[3] holds the 9 outputs
+// forward from m->X (bf16, P rows); Z[3] holds the 9 outputs.  A small
+// batch gives a layer few 64 x 64 output tiles, so its reduction over the
+// inputs is split into slices (at least 4 steps of 32 each) until the grid has
+// about 128 blocks; the slices' partial products are added in slice order.
 static void mlp_forward_core(hgmm_mlp_s* m, int P, hipStream_t s) {
   const uint16_t* in = m->X;
   for (int l = 0; l < 4; ++l) {
     const int K = kDims[l], N = kDims[l + 1];
-    launch_gemm(false, false, P, N, K, in, K, m->wb[l], N, m->Z[l], N, 0.f, s);
+    const int tiles = ((P + 63) / 64) * ((N + 63) / 64);
+    int slices = std::min(kGradSlices, std::max(1, std::min(128 / std::max(tiles, 1), K / 128)));
+    while (slices > 1 && (int64_t)slices * P * N > (int64_t)kGradSlices * 1280 * 512) --slices;
+    if (slices > 1) {
+      launch_gemm_slices(false, false, P, N, K, in, K, m->wb[l], N, m->gpart, N, 0.f, slices, s);
+      launch_sum_slices(m->gpart, gemm_slices_used(K, slices), (int64_t)P * N, m->Z[l], s);
+    } else {
+      launch_gemm(false, false, P, N, K, in, K, m->wb[l], N, m->Z[l], N, 0.f, s);
+    }
     launch_bias_act(m->Z[l], m->b[l], P, N, l < 3 ? m->H[l + 1] : nullptr, l < 3 ? 1 : 0, s);
     in = m->H[l + 1];
   }
